@@ -1,0 +1,241 @@
+"""CPU oracle for the CHR hot path (test infrastructure only).
+
+This package wraps ``chr_oracle.c``, the plain CPU reference that the GPU
+library is checked against.  Only the test suite, ``__graft_entry__.smoke()``
+and the CPU-baseline leg of ``bench.py`` may import it.  It shares no code with
+the GPU library and never imports it.
+
+Paper: "Accelerating In-transit Isosurface Generation With Topology Preserving
+Compression" (arXiv 2408.05462), Sec. II.B (topology preservation, the edge
+condition on d0/d1 and the error translation over D).  The hierarchy,
+predictor, quantizer, stream format and triangle table are unspecified by the
+paper; the readings implemented are documented in ``chr_oracle.c``.
+
+Parity unpinned: compression ratio (the paper prints none).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "chr_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+OK, E_INVAL, E_ACCURACY, E_LEVEL, E_CORRUPT, E_CAPACITY, E_NOMEM = 0, -1, -2, -3, -4, -5, -6
+MC_MAXTRI = 12
+
+
+class OracleError(RuntimeError):
+    def __init__(self, rc, what):
+        super().__init__(f"{what}: oracle status {rc}")
+        self.rc = rc
+
+
+def build() -> str:
+    """Compile the oracle (gcc, -O2 -ffp-contract=off, OpenMP)."""
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
+           "-shared", "-std=c11", "-Wall", "-Wextra", _SRC, "-o", _LIB + ".tmp", "-lm"]
+    subprocess.check_call(cmd, cwd=_HERE)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = C.CDLL(_LIB)
+        i64p = C.POINTER(C.c_int64)
+        L.orc_level_of.argtypes = [C.c_int64, C.c_int64, C.c_int64, C.c_int]
+        L.orc_level_of.restype = C.c_int
+        L.orc_predict.argtypes = [C.c_void_p, i64p, C.c_int64, C.c_int64, C.c_int64, C.c_int, C.c_int]
+        L.orc_predict.restype = C.c_float
+        L.orc_quantize.argtypes = [C.c_float, C.c_float, C.c_double, C.c_int, C.POINTER(C.c_int32),
+                                   C.POINTER(C.c_int), C.POINTER(C.c_float)]
+        L.orc_rank.argtypes = [C.c_float, C.c_void_p, C.c_int]
+        L.orc_rank.restype = C.c_int
+        L.orc_compress_bound.argtypes = [i64p, C.c_int, C.c_int]
+        L.orc_compress_bound.restype = C.c_size_t
+        L.orc_compress.argtypes = [C.c_void_p, i64p, C.c_double, C.c_void_p, C.c_int, C.c_int, C.c_int,
+                                   C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+                                   C.POINTER(C.c_size_t)]
+        L.orc_compress.restype = C.c_int
+        L.orc_stream_verify.argtypes = [C.c_void_p, C.c_size_t]
+        L.orc_stream_codes.argtypes = [C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]
+        L.orc_decompress.argtypes = [C.c_void_p, C.c_size_t, C.c_int, C.c_double, C.c_void_p]
+        L.orc_block_index.argtypes = [C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]
+        L.orc_mc_table.argtypes = [C.c_void_p, C.c_void_p]
+        L.orc_mc_table.restype = None
+        L.orc_mc_cases.argtypes = [C.c_void_p, i64p, C.c_float, C.c_void_p]
+        L.orc_mc_cases.restype = None
+        L.orc_mc.argtypes = [C.c_void_p, i64p, C.c_float, C.c_float, C.c_void_p, C.c_int64, C.c_void_p,
+                             C.c_int64, i64p]
+        L.orc_topology_error_bound.argtypes = [C.c_void_p, i64p, C.c_void_p, C.c_int, C.c_int64, i64p]
+        L.orc_topology_error_bound.restype = C.c_double
+        L.orc_stream_info.argtypes = [C.c_void_p, C.c_size_t, C.c_void_p]
+        _lib = L
+    return _lib
+
+
+def _dims(shape):
+    return (C.c_int64 * 3)(*[int(s) for s in shape])
+
+
+def _f32(a):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    return a, a.ctypes.data
+
+
+def level_of(x, y, z, nL):
+    return lib().orc_level_of(x, y, z, nL)
+
+
+def predict(xr, x, y, z, level, nL):
+    xr, p = _f32(xr)
+    return float(lib().orc_predict(p, _dims(xr.shape), x, y, z, level, nL))
+
+
+def quantize(x, p, e, qmax=32767):
+    q, o, r = C.c_int32(), C.c_int(), C.c_float()
+    lib().orc_quantize(x, p, e, qmax, C.byref(q), C.byref(o), C.byref(r))
+    return q.value, o.value, np.float32(r.value)
+
+
+def rank(v, iso):
+    iso = np.ascontiguousarray(np.sort(np.asarray(iso, np.float32)))
+    return lib().orc_rank(v, iso.ctypes.data, len(iso))
+
+
+def compress_bound(shape, nL, block):
+    return lib().orc_compress_bound(_dims(shape), nL, block)
+
+
+def compress(x, error_bound, isovalues=(), levels=3, block=64, qmax=32767):
+    """Returns dict(stream=bytes(np.uint8), q, flags, xr)."""
+    x, px = _f32(x)
+    iso = np.ascontiguousarray(np.asarray(isovalues, np.float32).reshape(-1))
+    cap = compress_bound(x.shape, levels, block)
+    stream = np.zeros(cap, np.uint8)
+    q = np.zeros(x.shape, np.int32)
+    fl = np.zeros(x.shape, np.uint8)
+    xr = np.zeros(x.shape, np.float32)
+    nbytes = C.c_size_t()
+    rc = lib().orc_compress(px, _dims(x.shape), float(error_bound), iso.ctypes.data, len(iso), levels,
+                            block, qmax, q.ctypes.data, fl.ctypes.data, xr.ctypes.data,
+                            stream.ctypes.data, cap, C.byref(nbytes))
+    if rc != OK:
+        raise OracleError(rc, "orc_compress")
+    return dict(stream=stream[: nbytes.value].copy(), q=q, flags=fl, xr=xr)
+
+
+class Info(C.Structure):
+    _fields_ = [("dims", C.c_int64 * 3), ("levels", C.c_int), ("block", C.c_int), ("qmax", C.c_int),
+                ("n_iso", C.c_int), ("error_bound", C.c_double), ("inv", C.c_float), ("step", C.c_float),
+                ("iso", C.c_float * 16), ("vmin", C.c_float), ("vmax", C.c_float), ("nblocks", C.c_int64),
+                ("nb", C.c_int * 3), ("flags", C.c_uint32), ("total_bytes", C.c_uint64),
+                ("n_outlier", C.c_uint64), ("n_corrected", C.c_uint64), ("payload_offset", C.c_uint64)]
+
+
+def stream_info(stream):
+    s = np.ascontiguousarray(stream, np.uint8)
+    info = Info()
+    rc = lib().orc_stream_info(s.ctypes.data, s.size, C.byref(info))
+    if rc != OK:
+        raise OracleError(rc, "orc_stream_info")
+    return info
+
+
+def stream_verify(stream):
+    s = np.ascontiguousarray(stream, np.uint8)
+    return lib().orc_stream_verify(s.ctypes.data, s.size)
+
+
+def stream_codes(stream):
+    s = np.ascontiguousarray(stream, np.uint8)
+    info = stream_info(s)
+    shape = tuple(info.dims)
+    q = np.zeros(shape, np.int32)
+    e = np.zeros(shape, np.uint8)
+    rc = lib().orc_stream_codes(s.ctypes.data, s.size, q.ctypes.data, e.ctypes.data)
+    if rc != OK:
+        raise OracleError(rc, "orc_stream_codes")
+    return q, e
+
+
+def decompress(stream, level=0, error_bound=None):
+    s = np.ascontiguousarray(stream, np.uint8)
+    info = stream_info(s)
+    eb = info.error_bound if error_bound is None else error_bound
+    shape = tuple(((int(n) - 1) >> level) + 1 for n in info.dims)
+    out = np.zeros(shape, np.float32)
+    rc = lib().orc_decompress(s.ctypes.data, s.size, level, float(eb), out.ctypes.data)
+    if rc != OK:
+        raise OracleError(rc, "orc_decompress")
+    return out
+
+
+def decompress_rc(stream, level, error_bound):
+    s = np.ascontiguousarray(stream, np.uint8)
+    info = stream_info(s)
+    shape = tuple(((int(n) - 1) >> max(level, 0)) + 1 for n in info.dims)
+    out = np.zeros(shape, np.float32)
+    return lib().orc_decompress(s.ctypes.data, s.size, level, float(error_bound), out.ctypes.data)
+
+
+def block_index(stream):
+    s = np.ascontiguousarray(stream, np.uint8)
+    info = stream_info(s)
+    mins = np.zeros(info.nblocks, np.float32)
+    maxs = np.zeros(info.nblocks, np.float32)
+    rc = lib().orc_block_index(s.ctypes.data, s.size, mins.ctypes.data, maxs.ctypes.data)
+    if rc != OK:
+        raise OracleError(rc, "orc_block_index")
+    return mins, maxs
+
+
+def mc_table():
+    ntri = np.zeros(256, np.uint8)
+    tri = np.zeros((256, 3 * MC_MAXTRI), np.int8)
+    lib().orc_mc_table(ntri.ctypes.data, tri.ctypes.data)
+    return ntri, tri
+
+
+def mc_cases(f, k):
+    f, pf = _f32(f)
+    cd = tuple(max(int(n) - 1, 0) for n in f.shape)
+    cases = np.zeros(cd, np.uint8)
+    if min(cd) > 0:
+        lib().orc_mc_cases(pf, _dims(f.shape), float(np.float32(k)), cases.ctypes.data)
+    return cases
+
+
+def mc(f, k, spacing=1.0, cap_v=None, cap_t=None):
+    """Returns (verts [V,3] float32 xyz, tris [T,3] int32)."""
+    f, pf = _f32(f)
+    counts = (C.c_int64 * 2)()
+    if cap_v is None or cap_t is None:
+        rc = lib().orc_mc(pf, _dims(f.shape), float(np.float32(k)), float(spacing), None, 0, None, 0, counts)
+        cap_v, cap_t = counts[0], counts[1]
+    verts = np.zeros((max(cap_v, 1), 3), np.float32)
+    tris = np.zeros((max(cap_t, 1), 3), np.int32)
+    rc = lib().orc_mc(pf, _dims(f.shape), float(np.float32(k)), float(spacing), verts.ctypes.data, cap_v,
+                      tris.ctypes.data, cap_t, counts)
+    if rc not in (OK, E_CAPACITY):
+        raise OracleError(rc, "orc_mc")
+    return verts[: min(counts[0], cap_v)], tris[: min(counts[1], cap_t)], (counts[0], counts[1]), rc
+
+
+def topology_error_bound(f, isovalues, nth=1):
+    f, pf = _f32(f)
+    iso = np.ascontiguousarray(np.asarray(isovalues, np.float32).reshape(-1))
+    nd = C.c_int64()
+    r = lib().orc_topology_error_bound(pf, _dims(f.shape), iso.ctypes.data, len(iso), nth, C.byref(nd))
+    return r, nd.value
