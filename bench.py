@@ -1,0 +1,249 @@
+#!/usr/bin/env python3
+"""Benchmark of the CHR hot path on one MI355X.
+
+One step = compress the field into a CHR stream (all levels, topology
+checks for every candidate isovalue) -> reconstruct level 0 from the stream
+-> marching cubes on the reconstruction for every candidate isovalue.  The
+input is resident in HBM before the timed region; each step re-runs the whole
+path on the same buffers.
+
+Prints ONE JSON line (see the design doc for the fields).  --gpus must be 1.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "CHR compress+reconstruct+MC input GB/s (% HBM peak); served p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per unit, by kernel ("Measurement"):
+#   k_encode_fine : 4 B per level-0 point read + its share of the stream written
+#   k_decode_fine : its share of the stream read + 4 B per output point written
+#   k_mc_bits     : 4 B per point read + 1 bit per point written
+KERNELS = ("k_encode_fine", "k_decode_fine", "k_mc_bits", "k_mc_emit", "k_encode_coarse", "k_pack",
+           "k_decode_coarse", "k_mc_count")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse_args():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="phantom512", choices=["phantom512", "taylor_green256", "gaussians64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-planes", type=int, default=0,
+                    help="z-planes of the field the oracle baseline runs on (0: automatic)")
+    ap.add_argument("--kernel", default="", help="kernel timed with HIP events (default: the dominant one)")
+    return ap.parse_args()
+
+
+def profile_traffic(kernel):
+    """HBM traffic per launch from the committed rocprofv3 counter summary of
+    `kernel`, or None when the summary is missing or the kernel's source has
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_counters.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    h = re.search(r"source_sha256:\s*([0-9a-f]+)", txt)
+    src = re.search(r"source_file:\s*(\S+)", txt)
+    if not (m and h and src):
+        return None
+    cur = hashlib.sha256(open(os.path.join(ROOT, src.group(1)), "rb").read()).hexdigest()
+    if cur != h.group(1):
+        return None
+    return float(m.group(1))
+
+
+def main():
+    args = parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "bench.py measures one GPU only: every GPU box here has one GPU; "
+                                   "run with --gpus 1"}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_2408_05462_amd import _lib as L
+    from paper_2408_05462_amd import api, inputs
+
+    lib = L.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.time()
+    w = inputs.workload(args.workload)
+    f_np = w["field"]
+    shape = f_np.shape
+    N = int(np.prod(shape))
+    isos = list(w["isovalues"])
+    e = w["error_bound"]
+    log(f"workload {args.workload} {shape} generated in {time.time() - t0:.1f}s; e={e:.6g} isovalues={isos}")
+
+    x = torch.from_numpy(f_np).to(dev)
+    p = api.params(w["levels"], w["block"])
+    cap = api.chr_compress_bound(shape, p)
+    sbuf = torch.empty(cap, dtype=torch.uint8, device=dev)
+    res = torch.zeros(64, dtype=torch.uint8, device=dev)
+    cws = torch.empty(api.chr_compress_workspace(shape, p), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+
+    # first compression: header for the reconstruction side, sizes, checks
+    api.chr_compress(x, e, isos, p, sbuf, res, cws)
+    torch.cuda.synchronize()
+    r = api.read_result(res)
+    if r["status"] != 0:
+        raise SystemExit(f"compression status {r['status']}")
+    nbytes = r["stream_bytes"]
+    info, _ = api.chr_stream_info_dev(sbuf[:nbytes])
+    sdev = sbuf[:nbytes]
+    recon = torch.empty(shape, dtype=torch.float32, device=dev)
+    st = torch.zeros(1, dtype=torch.int32, device=dev)
+    rws = torch.empty(max(api.chr_reconstruct_workspace(info, 0), 256), dtype=torch.uint8, device=dev)
+    api.chr_reconstruct(info, sdev, 0, e, recon, st, rws)
+    mws = torch.empty(api.iso_workspace(shape), dtype=torch.uint8, device=dev)
+    counts = torch.zeros((len(isos), 2), dtype=torch.int64, device=dev)
+    for j, k in enumerate(isos):
+        api.iso_extract(recon, k, 1.0, None, None, counts[j], mws)
+    torch.cuda.synchronize()
+    cnt = counts.cpu().numpy()
+    vmax_, tmax_ = int(cnt[:, 0].max()), int(cnt[:, 1].max())
+    verts = torch.empty((max(vmax_, 1), 3), dtype=torch.float32, device=dev)
+    tris = torch.empty((max(tmax_, 1), 3), dtype=torch.int32, device=dev)
+    # correctness guards on the full-size output (properties that hold at any size)
+    err = (recon.double() - x.double()).abs().max().item()
+    assert err <= e, f"error bound violated: {err} > {e}"
+    for k in isos:
+        assert torch.equal(recon < k, x < k), "a vertex changed side of a candidate isovalue"
+
+    def step():
+        api.chr_compress(x, e, isos, p, sbuf, res, cws)
+        ev[1].record(stream)
+        api.chr_reconstruct(info, sdev, 0, e, recon, st, rws)
+        ev[2].record(stream)
+        for j, k in enumerate(isos):
+            api.iso_extract(recon, k, 1.0, verts, tris, counts[j], mws)
+
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    for _ in range(args.warmup):
+        ev[0].record(stream)
+        step()
+        ev[3].record(stream)
+    torch.cuda.synchronize()
+
+    # per-kernel timing with HIP events on the launch stream, inside the timed region
+    kern = args.kernel or "k_encode_fine"
+    L.check(lib.chr_prof_enable(kern.encode(), max(args.steps, 1)), "chr_prof_enable")
+
+    stage = np.zeros(3)
+    total_ev = 0.0
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        ev[0].record(stream)
+        step()
+        ev[3].record(stream)
+        torch.cuda.synchronize()
+        stage += [ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]), ev[2].elapsed_time(ev[3])]
+        total_ev += ev[0].elapsed_time(ev[3])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+
+    ms = (C.c_float * max(args.steps, 1))()
+    nk = C.c_int()
+    L.check(lib.chr_prof_collect(ms, args.steps, C.byref(nk)), "chr_prof_collect")
+    lib.chr_prof_disable()
+    kern_ms = float(np.mean(list(ms)[: nk.value])) if nk.value else None
+
+    # checks after the timed region
+    r = api.read_result(res)
+    assert r["status"] == 0 and r["stream_bytes"] == nbytes
+    assert int(st.item()) == 0
+
+    ms_step = total_ev / args.steps
+    gbs = 4.0 * N / (ms_step * 1e-3) / 1e9
+    stage_ms = stage / args.steps
+    cr = 4.0 * N / nbytes
+
+    # algorithmic bytes of the timed kernel per launch
+    lvl0 = None
+    if kern == "k_encode_fine" or kern == "k_decode_fine":
+        # level-0 points of the whole field (unique): N minus the level-1 grid
+        g1 = int(np.prod([((n - 1) >> 1) + 1 for n in shape]))
+        lvl0 = N - g1
+        # stream bytes of the level-0 sections
+        s0 = 0
+        hb = bytes(sdev[: int(info.payload_offset)].cpu().numpy())
+        nl = info.levels
+        for b in range(info.nblocks):
+            ent = 256 + 16 * (b * nl + nl - 1)
+            s0 += int.from_bytes(hb[ent + 8: ent + 16], "little")
+        alg = 4.0 * lvl0 + s0
+    elif kern == "k_mc_bits":
+        alg = 4.0 * N + N / 8.0
+    else:
+        alg = None
+    roofline = None
+    if kern_ms and alg:
+        achieved = alg / (kern_ms * 1e-3) / 1e9
+        traffic = profile_traffic(kern)
+        roofline = {"bound": "hbm", "kernel": kern, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                    "avg_launch_ms": round(kern_ms, 4), "algorithmic_bytes": alg}
+
+    # CPU oracle baseline on a bounded sample of the same workload
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        planes = args.cpu_planes or min(shape[0], max(2, (64 << 20) // (shape[1] * shape[2])))
+        sub = np.ascontiguousarray(f_np[:planes])
+        tc = time.perf_counter()
+        ref = oracle.compress(sub, e, isos, levels=w["levels"], block=w["block"])
+        y = oracle.decompress(ref["stream"])
+        for k in isos:
+            oracle.mc(y, k)
+        tcpu = time.perf_counter() - tc
+        nsub = sub.size
+        cpu = {"value": round(4.0 * nsub / tcpu / 1e9, 4), "unit": "GB/s",
+               "cores": int(oracle.threads()), "kind": "oracle",
+               "sample": f"first {planes} z-planes ({'x'.join(map(str, sub.shape))}, {nsub} points), "
+                         f"compress+reconstruct+MC for {len(isos)} isovalue(s), {tcpu:.2f}s"}
+
+    out = {
+        "metric": METRIC, "value": round(gbs, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "dims": list(shape), "levels": w["levels"], "block": w["block"],
+                   "error_bound": e, "isovalues": isos},
+        "hbm_frac_input": round(gbs / HBM_PEAK_GBS, 4),
+        "stages_ms": {"compress": round(stage_ms[0], 4), "reconstruct": round(stage_ms[1], 4),
+                      "mc_all_isovalues": round(stage_ms[2], 4)},
+        "stages_gbs": {"compress": round(4.0 * N / stage_ms[0] / 1e6, 1),
+                       "reconstruct": round(4.0 * N / stage_ms[1] / 1e6, 1),
+                       "mc_per_isovalue": round(4.0 * N * len(isos) / stage_ms[2] / 1e6, 1)},
+        "compression_ratio": round(cr, 3), "stream_bytes": nbytes, "n_outlier": r["n_outlier"],
+        "n_corrected": r["n_corrected"], "triangles": [int(c[1]) for c in cnt],
+        "wall_s_timed": round(wall, 3), "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

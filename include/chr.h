@@ -1,0 +1,206 @@
+/*
+ * chr.h -- C ABI of the MI355X (gfx950) CHR library.
+ *
+ * Compressed Hierarchical Representation (CHR) with topology preservation for
+ * 3D binary32 scalar fields, reconstruction at any hierarchy level, and
+ * marching-cubes isosurface extraction, after "Accelerating In-transit
+ * Isosurface Generation With Topology Preserving Compression" (arXiv
+ * 2408.05462).  The data source compresses a field into a CHR; the
+ * visualization side requests the data an isovalue needs at a given accuracy
+ * and generates the isosurface (Sec. II, workflow description).
+ *
+ * Conventions for every call:
+ *  - A field is float32 [nz][ny][nx], x fastest.  dims[] = {nz, ny, nx},
+ *    each in [1, 2^30].
+ *  - Pointers named d_* are device pointers (HIP global memory, gfx950);
+ *    h_* are host pointers.  The caller owns every buffer it passes in;
+ *    the library never frees caller memory and keeps no pointer after a call
+ *    returns.
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *    Compute calls are asynchronous on that stream: the host-side return
+ *    code reports argument errors only.  Conditions found on the device
+ *    (non-finite input, too small an output buffer, a corrupt stream) are
+ *    written to the device-side status/result words documented per call.
+ *  - Workspace: every compute call takes a device scratch buffer d_ws of at
+ *    least the size its *_workspace() query returns; the library allocates
+ *    nothing on the device.
+ *  - Return codes: CHR_OK or a negative CHR_E_* value; chr_last_error()
+ *    returns a thread-local message for the last failure.
+ */
+#ifndef CHR_H
+#define CHR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CHR_OK 0
+#define CHR_E_INVAL (-1)    /* bad argument, or non-finite input value     */
+#define CHR_E_ACCURACY (-2) /* requested error bound below the stream's     */
+#define CHR_E_LEVEL (-3)    /* requested level not in the hierarchy         */
+#define CHR_E_CORRUPT (-4)  /* stream fails its magic/version/checksums     */
+#define CHR_E_CAPACITY (-5) /* output buffer too small; size reported       */
+#define CHR_E_NOMEM (-6)    /* workspace too small                           */
+#define CHR_E_HIP (-7)      /* a HIP runtime call failed                     */
+
+/* Compression parameters.
+ *  levels: nL, number of hierarchy levels (1..16).  Level nL-1 holds the
+ *          anchors (points whose coordinates are all multiples of
+ *          S = 2^(nL-1)); level l < nL-1 holds the points of the 2^l grid
+ *          that are not on the 2^(l+1) grid.
+ *  block:  B, edge of the cubic cell blocks of the domain decomposition
+ *          (Sec. II.A: domain decomposition into blocks; Sec. III tests 64
+ *          and 128).  Must be a multiple of S.  Each block stores the points
+ *          of its closed extent [o, o+B] (faces shared with neighbours), so
+ *          every block decodes on its own.  The closed extent must hold
+ *          fewer than 2^31 points.
+ *  qmax:   largest quantization code magnitude (1..32767). */
+typedef struct chr_params {
+  int levels;
+  int block;
+  int qmax;
+} chr_params;
+
+/* Device-side result of chr_compress (caller-allocated device memory). */
+typedef struct chr_result {
+  uint64_t stream_bytes; /* bytes of the stream (the required size when status = CHR_E_CAPACITY) */
+  uint64_t n_outlier;    /* points stored exactly because the bound or qmax failed */
+  uint64_t n_corrected;  /* points stored exactly because their side of an isovalue changed */
+  int32_t status;        /* CHR_OK, CHR_E_INVAL (non-finite input) or CHR_E_CAPACITY */
+  float vmin, vmax;      /* range of the input field */
+  uint32_t reserved;
+} chr_result;
+
+/* Parsed stream header (host side). */
+typedef struct chr_info {
+  int64_t dims[3];
+  int levels, block, qmax, n_iso;
+  double error_bound;
+  float inv, step;       /* 1/(2e) and 2e as stored (binary32) */
+  float isovalues[16];   /* sorted ascending, de-duplicated */
+  float vmin, vmax;
+  int64_t nblocks;
+  int nb[3];
+  uint32_t flags;        /* bit 0: lossless mode */
+  uint64_t total_bytes, n_outlier, n_corrected, payload_offset;
+} chr_info;
+
+const char *chr_last_error(void);
+int chr_version(void);
+
+/* ---- compression (Sec. II.A CHR generation; Sec. II.B topology
+ *      preserving compression) ------------------------------------------ */
+
+/* Upper bound on the stream size for these dims and parameters (every point
+ * stored exactly).  0 on invalid arguments. */
+size_t chr_compress_bound(const int64_t dims[3], const chr_params *p);
+
+/* Workspace bytes chr_compress needs.  0 on invalid arguments. */
+size_t chr_compress_workspace(const int64_t dims[3], const chr_params *p);
+
+/* Compresses d_field into the CHR stream d_stream (capacity bytes).
+ *
+ * error_bound: absolute bound e >= 0 (finite); every reconstructed value x'
+ *   satisfies |x' - x| <= e (checked in double).  e = 0 is lossless.
+ * h_isovalues / n_iso: up to 16 candidate isovalues (host array; sorted and
+ *   de-duplicated by the library).  For each of them every cell of the
+ *   reconstructed field, at every level, keeps the marching-cubes case of
+ *   the original field (Sec. II.B, topology preservation): a vertex whose
+ *   reconstruction would change side of any candidate is stored exactly.
+ * d_result: device chr_result, written when the work completes.
+ * d_codes, d_flags: optional (may be NULL) per-point outputs in field layout:
+ *   quantization code (0 where stored exactly) and flags (bit 0 outlier,
+ *   bit 1 topology correction).
+ * Device-detected: non-finite input -> status CHR_E_INVAL (stream invalid);
+ * stream larger than capacity -> status CHR_E_CAPACITY, stream_bytes = the
+ * required size, nothing written beyond capacity. */
+int chr_compress(const float *d_field, const int64_t dims[3], double error_bound,
+                 const float *h_isovalues, int n_iso, const chr_params *p,
+                 void *d_stream, size_t capacity, chr_result *d_result,
+                 int32_t *d_codes, uint8_t *d_flags,
+                 void *d_ws, size_t ws_bytes, void *stream);
+
+/* ---- stream inspection (host) ------------------------------------------ */
+
+/* Parses and validates a stream header from a host copy of its first n
+ * bytes (n >= 256; if n also covers the section and block tables, their
+ * checksum is verified too).  CHR_E_CORRUPT on any mismatch. */
+int chr_stream_info(const void *h_stream, size_t n, chr_info *out);
+
+/* Verifies every checksum of a whole stream held on the host. */
+int chr_stream_verify(const void *h_stream, size_t n);
+
+/* ---- reconstruction (Sec. II: the visualization side requests the data an
+ *      isovalue needs at a desired accuracy) -------------------------------- */
+
+/* Workspace bytes chr_reconstruct needs for this stream and level. */
+size_t chr_reconstruct_workspace(const chr_info *info, int level);
+
+/* Reconstructs level `level` of a stream held on the device.
+ * info: header parsed by chr_stream_info from a host copy of the stream.
+ * Output: d_out, float32 [((nz-1)>>level)+1][((ny-1)>>level)+1][((nx-1)>>level)+1],
+ *   the reconstructed values of the points whose coordinates are multiples
+ *   of 2^level.  Level 0 is the full field.
+ * error_bound: the accuracy requested; must be >= the stream's bound
+ *   (else CHR_E_ACCURACY).  level must be < levels (else CHR_E_LEVEL).
+ * d_status: optional device int32, set to CHR_E_CORRUPT if a section fails
+ *   its structural checks on the device (those sections are skipped). */
+int chr_reconstruct(const chr_info *info, const void *d_stream, size_t stream_bytes,
+                    int level, double error_bound, float *d_out, int32_t *d_status,
+                    void *d_ws, size_t ws_bytes, void *stream);
+
+/* ---- isosurface extraction (marching cubes, Sec. I and Sec. II.B) ------- */
+
+/* Workspace bytes iso_extract / iso_cases need for a field of these dims. */
+size_t iso_workspace(const int64_t dims[3]);
+
+/* Marching cubes on d_field at `isovalue`.
+ * Vertices: float32 [V][3] (x, y, z) in units of `spacing` grid steps
+ *   (spacing 2^l for a level-l reconstruction), ordered by (grid point in
+ *   x-fastest order, axis x<y<z) of the edge they lie on.
+ * Triangles: int32 [T][3] vertex ids, ordered by cell, then table order;
+ *   oriented with normals toward increasing field values.
+ * d_counts: device int64[2] = {V, T}, the required sizes, written even when
+ *   cap_v or cap_t is too small (then only the first cap_* are written).
+ * Ids are int32: V beyond 2^31-1 is reported in d_counts and not written. */
+int iso_extract(const float *d_field, const int64_t dims[3], float isovalue, float spacing,
+                float *d_vertices, int64_t cap_v, int32_t *d_tris, int64_t cap_t,
+                int64_t *d_counts, void *d_ws, size_t ws_bytes, void *stream);
+
+/* Marching-cubes case of every cell: d_cases is uint8 [nz-1][ny-1][nx-1];
+ * bit v is set iff the value at corner v = dx + 2dy + 4dz is below the
+ * isovalue (f < k). */
+int iso_cases(const float *d_field, const int64_t dims[3], float isovalue,
+              uint8_t *d_cases, void *d_ws, size_t ws_bytes, void *stream);
+
+/* Host copy of the library's generated triangle table:
+ * ntri[256]; tri[256][15] cell-edge ids (unused entries -1). */
+int chr_mc_table(uint8_t *ntri, int8_t *tri);
+
+/* ---- range (validation helper for relative error bounds) ---------------- */
+
+/* Range of n values (Sec. II.B error translation works in absolute units; a
+ * relative bound is rel * (max - min)).  d_out is 4 device words:
+ * [0] min and [1] max of the finite values (float32), [2] number of
+ * non-finite values (uint32), [3] unused. */
+int chr_range(const float *d_field, int64_t n, float *d_out, void *stream);
+
+/* ---- measurement support ------------------------------------------------ */
+
+/* While enabled, every launch of the kernel named `kernel` (for example
+ * "k_encode_fine") records a HIP event before and after it on its launch
+ * stream, up to max_launches launches.  chr_prof_collect returns the
+ * durations in milliseconds of the launches recorded so far (the caller must
+ * have synchronized the stream) and starts a new collection; chr_prof_disable
+ * releases the events.  Host-side; not thread-safe. */
+int chr_prof_enable(const char *kernel, int max_launches);
+int chr_prof_collect(float *ms, int max, int *n_out);
+int chr_prof_disable(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

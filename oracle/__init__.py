@@ -81,6 +81,7 @@ def lib():
         L.orc_topology_error_bound.argtypes = [C.c_void_p, i64p, C.c_void_p, C.c_int, C.c_int64, i64p]
         L.orc_topology_error_bound.restype = C.c_double
         L.orc_stream_info.argtypes = [C.c_void_p, C.c_size_t, C.c_void_p]
+        L.orc_threads.restype = C.c_int
         _lib = L
     return _lib
 
@@ -92,6 +93,10 @@ def _dims(shape):
 def _f32(a):
     a = np.ascontiguousarray(a, dtype=np.float32)
     return a, a.ctypes.data
+
+
+def threads():
+    return lib().orc_threads()
 
 
 def level_of(x, y, z, nL):

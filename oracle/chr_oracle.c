@@ -20,6 +20,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define MAGIC 0x31524843u /* "CHR1" */
 #define VERSION 1u
@@ -81,6 +84,14 @@ static int tz(int64_t c) { int t = 0; while (!(c & 1)) { c >>= 1; t++; } return 
  * coordinates, capped at the top level nL-1 (a zero coordinate imposes no
  * limit).  Top-level points (multiples of 2^(nL-1)) are the anchors; a point
  * of level l < nL-1 lies on the 2^l grid but not on the 2^(l+1) grid. */
+int orc_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 int orc_level_of(int64_t x, int64_t y, int64_t z, int nL) {
   int lv = nL - 1;
   if (x && tz(x) < lv) lv = tz(x);

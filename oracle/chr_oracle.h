@@ -43,6 +43,9 @@ enum {
   ORC_E_NOMEM = -6
 };
 
+/* Number of threads the oracle's parallel loops use. */
+int orc_threads(void);
+
 /* Level of grid point (x,y,z) in an nL-level hierarchy (reading R4). */
 int orc_level_of(int64_t x, int64_t y, int64_t z, int nL);
 

@@ -1,0 +1,112 @@
+"""ctypes binding of libchr.so (include/chr.h).
+
+Argument marshalling only: every step of compression, reconstruction and
+extraction runs in the library's HIP kernels.  PyTorch supplies device
+memory and the HIP stream.  The library must be built (``build()`` in
+``__graft_entry__`` or ``python -m paper_2408_05462_amd.build``); importing
+this module without it raises, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libchr.so")
+
+CHR_OK, CHR_E_INVAL, CHR_E_ACCURACY, CHR_E_LEVEL = 0, -1, -2, -3
+CHR_E_CORRUPT, CHR_E_CAPACITY, CHR_E_NOMEM, CHR_E_HIP = -4, -5, -6, -7
+STATUS_NAMES = {0: "CHR_OK", -1: "CHR_E_INVAL", -2: "CHR_E_ACCURACY", -3: "CHR_E_LEVEL", -4: "CHR_E_CORRUPT",
+                -5: "CHR_E_CAPACITY", -6: "CHR_E_NOMEM", -7: "CHR_E_HIP"}
+
+EXPORTS = ["chr_last_error", "chr_version", "chr_compress_bound", "chr_compress_workspace", "chr_compress",
+           "chr_stream_info", "chr_stream_verify", "chr_reconstruct_workspace", "chr_reconstruct",
+           "iso_workspace", "iso_extract", "iso_cases", "chr_mc_table", "chr_range", "chr_prof_enable",
+           "chr_prof_collect", "chr_prof_disable"]
+
+
+class ChrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class chr_params(C.Structure):
+    _fields_ = [("levels", C.c_int), ("block", C.c_int), ("qmax", C.c_int)]
+
+
+class chr_result(C.Structure):
+    _fields_ = [("stream_bytes", C.c_uint64), ("n_outlier", C.c_uint64), ("n_corrected", C.c_uint64),
+                ("status", C.c_int32), ("vmin", C.c_float), ("vmax", C.c_float), ("reserved", C.c_uint32)]
+
+
+class chr_info(C.Structure):
+    _fields_ = [("dims", C.c_int64 * 3), ("levels", C.c_int), ("block", C.c_int), ("qmax", C.c_int),
+                ("n_iso", C.c_int), ("error_bound", C.c_double), ("inv", C.c_float), ("step", C.c_float),
+                ("isovalues", C.c_float * 16), ("vmin", C.c_float), ("vmax", C.c_float),
+                ("nblocks", C.c_int64), ("nb", C.c_int * 3), ("flags", C.c_uint32),
+                ("total_bytes", C.c_uint64), ("n_outlier", C.c_uint64), ("n_corrected", C.c_uint64),
+                ("payload_offset", C.c_uint64)]
+
+
+RESULT_BYTES = C.sizeof(chr_result)
+
+_lib = None
+
+
+def load():
+    """Loads libchr.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
+                          "(python -m paper_2408_05462_amd.build)")
+    L = C.CDLL(LIB_PATH)
+    i64p = C.POINTER(C.c_int64)
+    vp = C.c_void_p
+    L.chr_last_error.restype = C.c_char_p
+    L.chr_version.restype = C.c_int
+    L.chr_compress_bound.argtypes = [i64p, C.POINTER(chr_params)]
+    L.chr_compress_bound.restype = C.c_size_t
+    L.chr_compress_workspace.argtypes = [i64p, C.POINTER(chr_params)]
+    L.chr_compress_workspace.restype = C.c_size_t
+    L.chr_compress.argtypes = [vp, i64p, C.c_double, vp, C.c_int, C.POINTER(chr_params), vp, C.c_size_t, vp,
+                               vp, vp, vp, C.c_size_t, vp]
+    L.chr_compress.restype = C.c_int
+    L.chr_stream_info.argtypes = [vp, C.c_size_t, C.POINTER(chr_info)]
+    L.chr_stream_info.restype = C.c_int
+    L.chr_stream_verify.argtypes = [vp, C.c_size_t]
+    L.chr_stream_verify.restype = C.c_int
+    L.chr_reconstruct_workspace.argtypes = [C.POINTER(chr_info), C.c_int]
+    L.chr_reconstruct_workspace.restype = C.c_size_t
+    L.chr_reconstruct.argtypes = [C.POINTER(chr_info), vp, C.c_size_t, C.c_int, C.c_double, vp, vp, vp,
+                                  C.c_size_t, vp]
+    L.chr_reconstruct.restype = C.c_int
+    L.iso_workspace.argtypes = [i64p]
+    L.iso_workspace.restype = C.c_size_t
+    L.iso_extract.argtypes = [vp, i64p, C.c_float, C.c_float, vp, C.c_int64, vp, C.c_int64, vp, vp, C.c_size_t,
+                              vp]
+    L.iso_extract.restype = C.c_int
+    L.iso_cases.argtypes = [vp, i64p, C.c_float, vp, vp, C.c_size_t, vp]
+    L.iso_cases.restype = C.c_int
+    L.chr_mc_table.argtypes = [vp, vp]
+    L.chr_mc_table.restype = C.c_int
+    L.chr_range.argtypes = [vp, C.c_int64, vp, vp]
+    L.chr_range.restype = C.c_int
+    L.chr_prof_enable.argtypes = [C.c_char_p, C.c_int]
+    L.chr_prof_enable.restype = C.c_int
+    L.chr_prof_collect.argtypes = [vp, C.c_int, C.POINTER(C.c_int)]
+    L.chr_prof_collect.restype = C.c_int
+    L.chr_prof_disable.restype = C.c_int
+    _lib = L
+    return L
+
+
+def check(rc, what):
+    if rc != CHR_OK:
+        raise ChrError(rc, f"{what}: {load().chr_last_error().decode()}")
+
+
+def dims3(shape):
+    return (C.c_int64 * 3)(*[int(s) for s in shape])

@@ -1,0 +1,221 @@
+"""Torch-facing wrappers of the C ABI, with the same names as include/chr.h.
+
+Each function marshals tensors into the C call; the work runs in the HIP
+kernels of libchr.so.  Calls are asynchronous on the current (or given) HIP
+stream unless noted.  ``compress``/``reconstruct``/``extract`` are
+synchronous conveniences that also read back device-side status.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _p(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _s(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _need_cuda_f32(t, name):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+
+
+def params(levels=3, block=64, qmax=32767):
+    return L.chr_params(levels, block, qmax)
+
+
+# ------------------------------------------------------------------ compress
+
+def chr_compress_bound(shape, p):
+    n = L.load().chr_compress_bound(L.dims3(shape), C.byref(p))
+    if n == 0:
+        L.check(L.CHR_E_INVAL, "chr_compress_bound")
+    return n
+
+
+def chr_compress_workspace(shape, p):
+    n = L.load().chr_compress_workspace(L.dims3(shape), C.byref(p))
+    if n == 0:
+        L.check(L.CHR_E_INVAL, "chr_compress_workspace")
+    return n
+
+
+def chr_compress(field, error_bound, isovalues, p, out, result, ws, codes=None, flags=None, stream=None):
+    """Launches compression of `field` into the uint8 buffer `out`; `result`
+    is a uint8 device buffer of at least RESULT_BYTES bytes."""
+    _need_cuda_f32(field, "field")
+    iso = np.ascontiguousarray(np.asarray(isovalues, np.float32).reshape(-1))
+    rc = L.load().chr_compress(_p(field), L.dims3(field.shape), float(error_bound), iso.ctypes.data_as(C.c_void_p),
+                               len(iso), C.byref(p), _p(out), out.numel(), _p(result), _p(codes), _p(flags), _p(ws),
+                               ws.numel(), _s(stream))
+    L.check(rc, "chr_compress")
+
+
+def read_result(result):
+    r = L.chr_result.from_buffer_copy(bytes(result[: L.RESULT_BYTES].cpu().numpy()))
+    return dict(stream_bytes=int(r.stream_bytes), n_outlier=int(r.n_outlier), n_corrected=int(r.n_corrected),
+                status=int(r.status), vmin=float(r.vmin), vmax=float(r.vmax))
+
+
+@dataclass
+class Compressed:
+    stream: torch.Tensor      # uint8 on the device, exactly stream_bytes long
+    info: L.chr_info          # parsed header
+    header: bytes             # host copy of header + tables
+    result: dict
+
+
+def compress(field, error_bound, isovalues=(), levels=3, block=64, qmax=32767, codes=None, flags=None):
+    """Synchronous compression; raises ChrError on any device-side status."""
+    p = params(levels, block, qmax)
+    dev = field.device
+    cap = chr_compress_bound(field.shape, p)
+    out = torch.empty(cap, dtype=torch.uint8, device=dev)
+    res = torch.zeros(64, dtype=torch.uint8, device=dev)
+    ws = torch.empty(chr_compress_workspace(field.shape, p), dtype=torch.uint8, device=dev)
+    chr_compress(field, error_bound, isovalues, p, out, res, ws, codes, flags)
+    torch.cuda.synchronize(dev)
+    r = read_result(res)
+    if r["status"] != 0:
+        raise L.ChrError(r["status"], "chr_compress (device status)")
+    s = out[: r["stream_bytes"]]
+    info, head = chr_stream_info_dev(s)
+    return Compressed(stream=s, info=info, header=head, result=r)
+
+
+# ------------------------------------------------------------------ stream inspection
+
+def chr_stream_info(host_bytes):
+    buf = np.ascontiguousarray(np.frombuffer(bytes(host_bytes), np.uint8))
+    info = L.chr_info()
+    rc = L.load().chr_stream_info(buf.ctypes.data_as(C.c_void_p), buf.size, C.byref(info))
+    L.check(rc, "chr_stream_info")
+    return info
+
+
+def chr_stream_info_dev(stream_dev):
+    """Copies the header and tables of a device stream to the host and parses them."""
+    head = bytes(stream_dev[:256].cpu().numpy())
+    info = chr_stream_info(head)
+    head = bytes(stream_dev[: int(info.payload_offset)].cpu().numpy())
+    info = chr_stream_info(head)
+    return info, head
+
+
+def chr_stream_verify(host_bytes):
+    buf = np.ascontiguousarray(np.frombuffer(bytes(host_bytes), np.uint8))
+    return L.load().chr_stream_verify(buf.ctypes.data_as(C.c_void_p), buf.size)
+
+
+# ------------------------------------------------------------------ reconstruct
+
+def level_shape(info, level):
+    return tuple(((int(n) - 1) >> level) + 1 for n in info.dims)
+
+
+def chr_reconstruct_workspace(info, level):
+    n = L.load().chr_reconstruct_workspace(C.byref(info), level)
+    if n == 0:
+        L.check(L.CHR_E_LEVEL, "chr_reconstruct_workspace")
+    return n
+
+
+def chr_reconstruct(info, stream_dev, level, error_bound, out, status, ws, stream=None):
+    rc = L.load().chr_reconstruct(C.byref(info), _p(stream_dev), stream_dev.numel(), level, float(error_bound),
+                                  _p(out), _p(status), _p(ws), 0 if ws is None else ws.numel(), _s(stream))
+    L.check(rc, "chr_reconstruct")
+
+
+def reconstruct(c: Compressed, level=0, error_bound=None):
+    eb = c.info.error_bound if error_bound is None else error_bound
+    dev = c.stream.device
+    out = torch.empty(level_shape(c.info, level), dtype=torch.float32, device=dev)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    ws = torch.empty(max(chr_reconstruct_workspace(c.info, level), 256), dtype=torch.uint8, device=dev)
+    chr_reconstruct(c.info, c.stream, level, eb, out, status, ws)
+    torch.cuda.synchronize(dev)
+    st = int(status.item())
+    if st != 0:
+        raise L.ChrError(st, "chr_reconstruct (device status)")
+    return out
+
+
+# ------------------------------------------------------------------ extract
+
+def iso_workspace(shape):
+    n = L.load().iso_workspace(L.dims3(shape))
+    if n == 0:
+        L.check(L.CHR_E_INVAL, "iso_workspace")
+    return n
+
+
+def iso_extract(field, isovalue, spacing, verts, tris, counts, ws, stream=None):
+    _need_cuda_f32(field, "field")
+    rc = L.load().iso_extract(_p(field), L.dims3(field.shape), float(np.float32(isovalue)), float(spacing),
+                              _p(verts), 0 if verts is None else verts.shape[0], _p(tris),
+                              0 if tris is None else tris.shape[0], _p(counts), _p(ws), ws.numel(), _s(stream))
+    L.check(rc, "iso_extract")
+
+
+def extract(field, isovalue, spacing=1.0):
+    """Synchronous marching cubes: returns (verts [V,3] f32, tris [T,3] i32)."""
+    dev = field.device
+    ws = torch.empty(iso_workspace(field.shape), dtype=torch.uint8, device=dev)
+    counts = torch.zeros(2, dtype=torch.int64, device=dev)
+    iso_extract(field, isovalue, spacing, None, None, counts, ws)
+    torch.cuda.synchronize(dev)
+    nv, nt = (int(v) for v in counts.cpu())
+    verts = torch.empty((max(nv, 1), 3), dtype=torch.float32, device=dev)
+    tris = torch.empty((max(nt, 1), 3), dtype=torch.int32, device=dev)
+    iso_extract(field, isovalue, spacing, verts, tris, counts, ws)
+    torch.cuda.synchronize(dev)
+    return verts[:nv], tris[:nt]
+
+
+def iso_cases(field, isovalue, out, ws, stream=None):
+    rc = L.load().iso_cases(_p(field), L.dims3(field.shape), float(np.float32(isovalue)), _p(out), _p(ws),
+                            ws.numel(), _s(stream))
+    L.check(rc, "iso_cases")
+
+
+def cases(field, isovalue):
+    dev = field.device
+    cd = tuple(max(int(n) - 1, 0) for n in field.shape)
+    out = torch.zeros(cd, dtype=torch.uint8, device=dev)
+    ws = torch.empty(iso_workspace(field.shape), dtype=torch.uint8, device=dev)
+    if min(cd) > 0:
+        iso_cases(field, isovalue, out, ws)
+        torch.cuda.synchronize(dev)
+    return out
+
+
+def chr_mc_table():
+    ntri = np.zeros(256, np.uint8)
+    tri = np.zeros((256, 15), np.int8)
+    rc = L.load().chr_mc_table(ntri.ctypes.data_as(C.c_void_p), tri.ctypes.data_as(C.c_void_p))
+    L.check(rc, "chr_mc_table")
+    return ntri, tri
+
+
+def chr_range(field, out, stream=None):
+    rc = L.load().chr_range(_p(field), field.numel(), _p(out), _s(stream))
+    L.check(rc, "chr_range")
+
+
+def field_range(field):
+    out = torch.zeros(4, dtype=torch.float32, device=field.device)
+    chr_range(field, out)
+    torch.cuda.synchronize(field.device)
+    v = out.cpu()
+    return float(v[0]), float(v[1]), int(v[2:3].view(torch.int32).item())

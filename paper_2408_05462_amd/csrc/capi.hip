@@ -1,0 +1,515 @@
+// capi.hip -- the C ABI (include/chr.h): argument checks, plans, workspace
+// layouts and host-side stream parsing.  All compute runs in the kernels of
+// encode.hip, decode.hip, mc.hip and scan.hip.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/chr.h"
+#include "chr_plan.h"
+
+using namespace chr;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+bool dims_ok(const int64_t d[3]) {
+  if (!d) return false;
+  for (int a = 0; a < 3; a++)
+    if (d[a] < 1 || d[a] > ((int64_t)1 << 30)) return false;
+  return true;
+}
+
+size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+// Per-axis block extents: (cells of the block, how many blocks have it).
+struct AxisClass {
+  int64_t ext[2];
+  int64_t count[2];
+  int n;
+};
+
+AxisClass axis_classes(int64_t n, int64_t B) {
+  AxisClass c{};
+  int64_t cells = n - 1;
+  int64_t nb = blocks_along(n, B);
+  if (cells <= 0) {
+    c.ext[0] = 0; c.count[0] = 1; c.n = 1;
+    return c;
+  }
+  int64_t last = cells - (nb - 1) * B;
+  if (last == B) { c.ext[0] = B; c.count[0] = nb; c.n = 1; }
+  else {
+    c.n = 0;
+    if (nb > 1) { c.ext[c.n] = B; c.count[c.n] = nb - 1; c.n++; }
+    c.ext[c.n] = last; c.count[c.n] = 1; c.n++;
+  }
+  return c;
+}
+
+bool params_ok(const int64_t dims[3], const chr_params *p, std::string &why) {
+  if (!dims_ok(dims)) { why = "dims must be in [1, 2^30]"; return false; }
+  if (!p) { why = "params is NULL"; return false; }
+  if (p->levels < 1 || p->levels > kMaxLevels) { why = "levels must be in [1, 16]"; return false; }
+  int64_t S = (int64_t)1 << (p->levels - 1);
+  if (p->block < 1 || p->block % S) { why = "block must be a positive multiple of 2^(levels-1)"; return false; }
+  if (p->qmax < 1 || p->qmax > 32767) { why = "qmax must be in [1, 32767]"; return false; }
+  // every section's point count must fit 31 bits
+  int64_t e[3];
+  for (int a = 0; a < 3; a++) e[a] = std::min<int64_t>(p->block, dims[a] - 1) + 1;
+  if ((double)e[0] * (double)e[1] * (double)e[2] >= 2147483647.0) { why = "block too large for this field"; return false; }
+  return true;
+}
+
+void fill_geo(Geo &g, const int64_t dims[3], int nL, int B, int qmax) {
+  std::memset(&g, 0, sizeof(g));
+  for (int a = 0; a < 3; a++) {
+    g.n[a] = dims[a];
+    g.nb[a] = blocks_along(dims[a], B);
+  }
+  g.nblocks = g.nb[0] * g.nb[1] * g.nb[2];
+  g.nL = nL;
+  g.B = B;
+  g.qmax = qmax;
+}
+
+void set_quant(Geo &g, double e) {
+  g.e = e;
+  g.inv = 0.f;
+  g.step = 0.f;
+  if (e > 0) {
+    g.inv = (float)(1.0 / (2.0 * e));
+    g.step = (float)(2.0 * e);
+  }
+  g.lossless = (!(e > 0) || g.step == 0.0f || !std::isfinite(g.step)) ? 1 : 0;
+}
+
+// max chunks of a level-l section (the first block is the largest)
+uint32_t max_chunks(const Geo &g, int l) {
+  int64_t o[3], hi[3];
+  block_ext(g, 0, o, hi);
+  Sec s = sec_geom(o, hi, l, g.nL - 1);
+  return (s.npts + 63) / 64;
+}
+
+struct EncLayout {
+  size_t off_G, off_cnt, off_P, off_scan, off_pay, off_emask, off_exv, off_bstat, off_st, off_secsz, off_secoff,
+      off_scan64, total;
+};
+
+EncLayout enc_layout(EncPlan &P) {
+  const Geo &g = P.g;
+  const int L = g.nL - 1;
+  int64_t base = 0;
+  for (int l = L; l >= 0; l--) {
+    P.maxch[l] = max_chunks(g, l);
+    P.slot_base[l] = base;
+    base += g.nblocks * (int64_t)P.maxch[l];
+  }
+  P.nslots = base;
+  int64_t goff = 0;
+  for (int l = 0; l < kMaxLevels; l++) {
+    for (int a = 0; a < 3; a++) P.gd[l][a] = (l <= L) ? lvl_dim(g.n[a], l) : 0;
+    P.g_off[l] = 0;
+    if (l >= 1 && l <= L) {
+      P.g_off[l] = goff;
+      goff += P.gd[l][0] * P.gd[l][1] * P.gd[l][2];
+    }
+  }
+  const int64_t nsec = g.nblocks * g.nL;
+  P.payload_off = kHeaderBytes + 16 * (uint64_t)nsec + 16 * (uint64_t)g.nblocks;
+  EncLayout Lo{};
+  size_t o = 0;
+  Lo.off_G = o; o = align256(o + sizeof(float) * (size_t)std::max<int64_t>(goff, 1));
+  Lo.off_cnt = o; o = align256(o + sizeof(U4) * (size_t)P.nslots);
+  Lo.off_P = o; o = align256(o + sizeof(U4) * (size_t)(P.nslots + 1));
+  Lo.off_scan = o; o = align256(o + sizeof(U4) * (size_t)scan_tmp_elems(P.nslots));
+  Lo.off_pay = o; o = align256(o + sizeof(uint32_t) * 32 * (size_t)P.nslots);
+  Lo.off_emask = o; o = align256(o + sizeof(uint64_t) * (size_t)P.nslots);
+  Lo.off_exv = o; o = align256(o + sizeof(float) * 64 * (size_t)P.nslots);
+  Lo.off_bstat = o; o = align256(o + sizeof(uint32_t) * 2 * (size_t)g.nblocks);
+  Lo.off_st = o; o = align256(o + sizeof(Stats));
+  Lo.off_secsz = o; o = align256(o + sizeof(uint64_t) * (size_t)nsec);
+  Lo.off_secoff = o; o = align256(o + sizeof(uint64_t) * (size_t)(nsec + 1));
+  Lo.off_scan64 = o; o = align256(o + sizeof(uint64_t) * (size_t)scan_tmp_elems(nsec));
+  Lo.total = o;
+  return Lo;
+}
+
+int prepare_iso(const float *h_iso, int n_iso, Geo &g, std::string &why) {
+  if (n_iso < 0 || n_iso > kMaxIso) { why = "n_iso must be in [0, 16]"; return -1; }
+  if (n_iso > 0 && !h_iso) { why = "isovalues is NULL"; return -1; }
+  float t[kMaxIso];
+  for (int j = 0; j < n_iso; j++) {
+    if (!std::isfinite(h_iso[j])) { why = "isovalues must be finite"; return -1; }
+    t[j] = h_iso[j];
+  }
+  std::sort(t, t + n_iso);
+  int k = 0;
+  for (int j = 0; j < n_iso; j++)
+    if (k == 0 || t[j] != g.iso[k - 1]) g.iso[k++] = t[j];
+  for (int j = k; j < kMaxIso; j++) g.iso[j] = 0.f;
+  g.K = k;
+  return 0;
+}
+
+uint32_t host_checksum(const uint8_t *p, size_t nbytes) {
+  uint32_t s = 0;
+  for (size_t j = 0; j < nbytes / 4; j++) {
+    uint32_t w;
+    std::memcpy(&w, p + 4 * j, 4);
+    s += fmix32(w ^ (uint32_t)((uint32_t)j * 0x9E3779B9u));
+  }
+  return s;
+}
+
+template <class T>
+T rd(const uint8_t *p) {
+  T v;
+  std::memcpy(&v, p, sizeof(T));
+  return v;
+}
+
+int check_hip(const char *what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(CHR_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  return CHR_OK;
+}
+
+struct Prof {
+  std::string name;
+  std::vector<hipEvent_t> ev;  // begin/end pairs
+  int used = 0;                // events recorded
+  bool on = false;
+} g_prof;
+
+}  // namespace
+
+namespace chr {
+void prof_mark(const char *kernel, hipStream_t s, int end) {
+  if (!g_prof.on || g_prof.name != kernel) return;
+  if (!end && g_prof.used + 2 > (int)g_prof.ev.size()) return;
+  if (end && (g_prof.used & 1) == 0) return;  // its begin was not recorded
+  hipEventRecord(g_prof.ev[g_prof.used], s);
+  g_prof.used++;
+}
+}  // namespace chr
+
+extern "C" {
+
+int chr_prof_enable(const char *kernel, int max_launches) {
+  if (!kernel || max_launches < 1) return fail(CHR_E_INVAL, "bad argument");
+  chr_prof_disable();
+  g_prof.ev.resize(2 * (size_t)max_launches);
+  for (auto &e : g_prof.ev)
+    if (hipEventCreate(&e) != hipSuccess) return fail(CHR_E_HIP, "hipEventCreate failed");
+  g_prof.name = kernel;
+  g_prof.used = 0;
+  g_prof.on = true;
+  return CHR_OK;
+}
+
+int chr_prof_collect(float *ms, int max, int *n_out) {
+  if (!n_out) return fail(CHR_E_INVAL, "bad argument");
+  int n = 0;
+  for (int i = 0; i + 1 < g_prof.used && n < max; i += 2) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, g_prof.ev[i], g_prof.ev[i + 1]) != hipSuccess) return fail(CHR_E_HIP, "event timing failed");
+    if (ms) ms[n] = t;
+    n++;
+  }
+  *n_out = n;
+  g_prof.used = 0;
+  return CHR_OK;
+}
+
+int chr_prof_disable(void) {
+  for (auto &e : g_prof.ev) hipEventDestroy(e);
+  g_prof.ev.clear();
+  g_prof.used = 0;
+  g_prof.on = false;
+  return CHR_OK;
+}
+
+const char *chr_last_error(void) { return g_err.c_str(); }
+
+int chr_version(void) { return 1; }
+
+size_t chr_compress_bound(const int64_t dims[3], const chr_params *p) {
+  std::string why;
+  if (!params_ok(dims, p, why)) { g_err = why; return 0; }
+  Geo g;
+  fill_geo(g, dims, p->levels, p->block, p->qmax);
+  const int L = g.nL - 1;
+  size_t total = kHeaderBytes + 16 * (size_t)g.nblocks * g.nL + 16 * (size_t)g.nblocks;
+  AxisClass ac[3];
+  for (int a = 0; a < 3; a++) ac[a] = axis_classes(dims[a], p->block);
+  for (int iz = 0; iz < ac[0].n; iz++)
+    for (int iy = 0; iy < ac[1].n; iy++)
+      for (int ix = 0; ix < ac[2].n; ix++) {
+        int64_t o[3] = {0, 0, 0}, hi[3] = {ac[0].ext[iz], ac[1].ext[iy], ac[2].ext[ix]};
+        int64_t cnt = ac[0].count[iz] * ac[1].count[iy] * ac[2].count[ix];
+        for (int l = L; l >= 0; l--) {
+          Sec s = sec_geom(o, hi, l, L);
+          uint64_t nch = (s.npts + 63) / 64;
+          total += (size_t)cnt * sec_bytes(s.npts, 16 * nch, nch, s.npts);
+        }
+      }
+  return total;
+}
+
+size_t chr_compress_workspace(const int64_t dims[3], const chr_params *p) {
+  std::string why;
+  if (!params_ok(dims, p, why)) { g_err = why; return 0; }
+  EncPlan P;
+  std::memset(&P, 0, sizeof(P));
+  fill_geo(P.g, dims, p->levels, p->block, p->qmax);
+  return enc_layout(P).total;
+}
+
+int chr_compress(const float *d_field, const int64_t dims[3], double error_bound, const float *h_isovalues,
+                 int n_iso, const chr_params *p, void *d_stream, size_t capacity, chr_result *d_result,
+                 int32_t *d_codes, uint8_t *d_flags, void *d_ws, size_t ws_bytes, void *stream) {
+  std::string why;
+  if (!params_ok(dims, p, why)) return fail(CHR_E_INVAL, why);
+  if (!d_field || !d_stream || !d_result || !d_ws) return fail(CHR_E_INVAL, "NULL device pointer");
+  if (!(error_bound >= 0) || !std::isfinite(error_bound)) return fail(CHR_E_INVAL, "error_bound must be finite and >= 0");
+  EncPlan P;
+  std::memset(&P, 0, sizeof(P));
+  fill_geo(P.g, dims, p->levels, p->block, p->qmax);
+  if (prepare_iso(h_isovalues, n_iso, P.g, why)) return fail(CHR_E_INVAL, why);
+  set_quant(P.g, error_bound);
+  EncLayout Lo = enc_layout(P);
+  if (ws_bytes < Lo.total) return fail(CHR_E_NOMEM, "workspace too small: need " + std::to_string(Lo.total));
+  if (P.g.nblocks > 65535) return fail(CHR_E_INVAL, "more than 65535 blocks: use a larger block");
+  if (capacity < P.payload_off) return fail(CHR_E_CAPACITY, "capacity below the header and tables");
+  uint8_t *ws = static_cast<uint8_t *>(d_ws);
+  P.x = d_field;
+  P.G = reinterpret_cast<float *>(ws + Lo.off_G);
+  P.cnt = reinterpret_cast<U4 *>(ws + Lo.off_cnt);
+  P.P = reinterpret_cast<U4 *>(ws + Lo.off_P);
+  P.pay = reinterpret_cast<uint32_t *>(ws + Lo.off_pay);
+  P.emask = reinterpret_cast<unsigned long long *>(ws + Lo.off_emask);
+  P.exv = reinterpret_cast<float *>(ws + Lo.off_exv);
+  P.bstat = reinterpret_cast<uint32_t *>(ws + Lo.off_bstat);
+  P.st = reinterpret_cast<Stats *>(ws + Lo.off_st);
+  P.secsz = reinterpret_cast<uint64_t *>(ws + Lo.off_secsz);
+  P.secoff = reinterpret_cast<uint64_t *>(ws + Lo.off_secoff);
+  P.out = static_cast<uint8_t *>(d_stream);
+  P.cap = capacity;
+  P.result = d_result;
+  P.codes = d_codes;
+  P.flags = d_flags;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  launch_encode(P, 0, reinterpret_cast<U4 *>(ws + Lo.off_scan), reinterpret_cast<uint64_t *>(ws + Lo.off_scan64), s);
+  return check_hip("chr_compress launch");
+}
+
+int chr_stream_info(const void *h_stream, size_t n, chr_info *I) {
+  if (!h_stream || !I) return fail(CHR_E_INVAL, "NULL argument");
+  const uint8_t *s = static_cast<const uint8_t *>(h_stream);
+  if (n < (size_t)kHeaderBytes) return fail(CHR_E_CORRUPT, "stream shorter than its header");
+  if (rd<uint32_t>(s) != kMagic || rd<uint32_t>(s + 4) != kVersion) return fail(CHR_E_CORRUPT, "bad magic or version");
+  if (host_checksum(s, 252) != rd<uint32_t>(s + 252)) return fail(CHR_E_CORRUPT, "header checksum mismatch");
+  std::memset(I, 0, sizeof(*I));
+  for (int a = 0; a < 3; a++) I->dims[a] = rd<int64_t>(s + 8 + 8 * a);
+  I->levels = rd<int32_t>(s + 32);
+  I->block = rd<int32_t>(s + 36);
+  I->qmax = rd<int32_t>(s + 40);
+  I->n_iso = rd<int32_t>(s + 44);
+  I->error_bound = rd<double>(s + 48);
+  I->inv = rd<float>(s + 56);
+  I->step = rd<float>(s + 60);
+  for (int j = 0; j < kMaxIso; j++) I->isovalues[j] = rd<float>(s + 64 + 4 * j);
+  I->vmin = rd<float>(s + 128);
+  I->vmax = rd<float>(s + 132);
+  I->nblocks = rd<int64_t>(s + 136);
+  for (int a = 0; a < 3; a++) I->nb[a] = rd<int32_t>(s + 144 + 4 * a);
+  I->flags = rd<uint32_t>(s + 156);
+  I->total_bytes = rd<uint64_t>(s + 160);
+  I->n_outlier = rd<uint64_t>(s + 168);
+  I->n_corrected = rd<uint64_t>(s + 176);
+  I->payload_offset = rd<uint64_t>(s + 184);
+  chr_params p{I->levels, I->block, I->qmax};
+  std::string why;
+  if (!params_ok(I->dims, &p, why)) return fail(CHR_E_CORRUPT, "header parameters invalid: " + why);
+  if (I->n_iso < 0 || I->n_iso > kMaxIso) return fail(CHR_E_CORRUPT, "bad isovalue count");
+  Geo g;
+  fill_geo(g, I->dims, I->levels, I->block, I->qmax);
+  if (g.nblocks != I->nblocks || g.nb[0] != I->nb[0] || g.nb[1] != I->nb[1] || g.nb[2] != I->nb[2])
+    return fail(CHR_E_CORRUPT, "block grid mismatch");
+  if (I->payload_offset != kHeaderBytes + 16 * (uint64_t)I->nblocks * I->levels + 16 * (uint64_t)I->nblocks)
+    return fail(CHR_E_CORRUPT, "payload offset mismatch");
+  if (I->payload_offset > I->total_bytes) return fail(CHR_E_CORRUPT, "total size below the tables");
+  if (n >= I->payload_offset &&
+      host_checksum(s + kHeaderBytes, I->payload_offset - kHeaderBytes) != rd<uint32_t>(s + 248))
+    return fail(CHR_E_CORRUPT, "table checksum mismatch");
+  return CHR_OK;
+}
+
+int chr_stream_verify(const void *h_stream, size_t n) {
+  chr_info I;
+  int rc = chr_stream_info(h_stream, n, &I);
+  if (rc) return rc;
+  if (n < I.total_bytes) return fail(CHR_E_CORRUPT, "stream truncated");
+  if (n < I.payload_offset) return fail(CHR_E_CORRUPT, "stream truncated");
+  const uint8_t *s = static_cast<const uint8_t *>(h_stream);
+  const size_t btab = kHeaderBytes + 16 * (size_t)I.nblocks * I.levels;
+  for (int64_t b = 0; b < I.nblocks; b++) {
+    const uint8_t *first = s + kHeaderBytes + 16 * (size_t)b * I.levels;
+    const uint8_t *last = s + kHeaderBytes + 16 * ((size_t)b * I.levels + I.levels - 1);
+    uint64_t start = rd<uint64_t>(first), end = rd<uint64_t>(last) + rd<uint64_t>(last + 8);
+    if (start > end || end > I.total_bytes) return fail(CHR_E_CORRUPT, "section table out of range");
+    if (host_checksum(s + start, end - start) != rd<uint32_t>(s + btab + 16 * (size_t)b + 8))
+      return fail(CHR_E_CORRUPT, "block checksum mismatch");
+  }
+  return CHR_OK;
+}
+
+static int dec_plan(const chr_info *I, int level, DecPlan &D, size_t &need) {
+  std::memset(&D, 0, sizeof(D));
+  chr_params p{I->levels, I->block, I->qmax};
+  std::string why;
+  if (!params_ok(I->dims, &p, why)) return fail(CHR_E_CORRUPT, why);
+  if (level < 0 || level >= I->levels) return fail(CHR_E_LEVEL, "level outside the hierarchy");
+  fill_geo(D.g, I->dims, I->levels, I->block, I->qmax);
+  set_quant(D.g, I->error_bound);
+  if (std::memcmp(&D.g.inv, &I->inv, 4) || std::memcmp(&D.g.step, &I->step, 4))
+    return fail(CHR_E_CORRUPT, "quantizer constants do not match the error bound");
+  if ((D.g.lossless ? 1u : 0u) != (I->flags & 1u)) return fail(CHR_E_CORRUPT, "lossless flag mismatch");
+  D.g.K = I->n_iso;
+  for (int j = 0; j < kMaxIso; j++) D.g.iso[j] = I->isovalues[j];
+  D.lo = level;
+  const int L = I->levels - 1;
+  need = 0;
+  for (int l = 0; l < kMaxLevels; l++)
+    for (int a = 0; a < 3; a++) D.gd[l][a] = (l <= L) ? lvl_dim(I->dims[a], l) : 0;
+  for (int l = std::max(level, 1); l <= L; l++) {
+    if (l == level) continue;  // the output itself
+    need = align256(need + sizeof(float) * (size_t)(D.gd[l][0] * D.gd[l][1] * D.gd[l][2]));
+  }
+  D.payload_off = I->payload_offset;
+  if (D.g.nblocks > 65535) return fail(CHR_E_INVAL, "more than 65535 blocks");
+  return CHR_OK;
+}
+
+size_t chr_reconstruct_workspace(const chr_info *info, int level) {
+  if (!info) return 0;
+  DecPlan D;
+  size_t need = 0;
+  if (dec_plan(info, level, D, need)) return 0;
+  return std::max<size_t>(need, 256);
+}
+
+int chr_reconstruct(const chr_info *info, const void *d_stream, size_t stream_bytes, int level, double error_bound,
+                    float *d_out, int32_t *d_status, void *d_ws, size_t ws_bytes, void *stream) {
+  if (!info || !d_stream || !d_out) return fail(CHR_E_INVAL, "NULL argument");
+  DecPlan D;
+  size_t need = 0;
+  int rc = dec_plan(info, level, D, need);
+  if (rc) return rc;
+  if (!(error_bound >= info->error_bound)) return fail(CHR_E_ACCURACY, "requested error bound below the stream's");
+  if (stream_bytes < info->total_bytes) return fail(CHR_E_CORRUPT, "stream shorter than its header states");
+  if (ws_bytes < need || (need && !d_ws)) return fail(CHR_E_NOMEM, "workspace too small: need " + std::to_string(need));
+  const int L = info->levels - 1;
+  size_t off = 0;
+  uint8_t *ws = static_cast<uint8_t *>(d_ws);
+  for (int l = std::max(level, 1); l <= L; l++) {
+    if (l == level) { D.gp[l] = d_out; continue; }
+    D.gp[l] = reinterpret_cast<float *>(ws + off);
+    off = align256(off + sizeof(float) * (size_t)(D.gd[l][0] * D.gd[l][1] * D.gd[l][2]));
+  }
+  D.s = static_cast<const uint8_t *>(d_stream);
+  D.sbytes = info->total_bytes;
+  D.out = d_out;
+  D.status = d_status;
+  launch_decode(D, static_cast<hipStream_t>(stream));
+  return check_hip("chr_reconstruct launch");
+}
+
+static int mc_plan(const float *d_field, const int64_t dims[3], McPlan &M, size_t &need, size_t off[5]) {
+  std::memset(&M, 0, sizeof(M));
+  if (!dims_ok(dims)) return fail(CHR_E_INVAL, "dims must be in [1, 2^30]");
+  for (int a = 0; a < 3; a++) M.n[a] = dims[a];
+  M.nrows = dims[0] * dims[1];
+  M.nw = ceil_div(dims[2], 64);
+  M.f = d_field;
+  size_t o = 0;
+  off[0] = o; o = align256(o + 8 * (size_t)(M.nrows * M.nw));
+  off[1] = o; o = align256(o + sizeof(U4) * (size_t)M.nrows);
+  off[2] = o; o = align256(o + sizeof(U4) * (size_t)(M.nrows + 1));
+  off[3] = o; o = align256(o + sizeof(U4) * (size_t)scan_tmp_elems(M.nrows));
+  need = o;
+  return CHR_OK;
+}
+
+size_t iso_workspace(const int64_t dims[3]) {
+  McPlan M;
+  size_t need = 0, off[5];
+  if (mc_plan(nullptr, dims, M, need, off)) return 0;
+  return need;
+}
+
+int iso_extract(const float *d_field, const int64_t dims[3], float isovalue, float spacing, float *d_vertices,
+                int64_t cap_v, int32_t *d_tris, int64_t cap_t, int64_t *d_counts, void *d_ws, size_t ws_bytes,
+                void *stream) {
+  if (!d_field || !d_counts || !d_ws) return fail(CHR_E_INVAL, "NULL argument");
+  if (cap_v < 0 || cap_t < 0 || (cap_v && !d_vertices) || (cap_t && !d_tris)) return fail(CHR_E_INVAL, "bad capacity");
+  if (!std::isfinite(isovalue) || !std::isfinite(spacing)) return fail(CHR_E_INVAL, "isovalue and spacing must be finite");
+  McPlan M;
+  size_t need = 0, off[5];
+  int rc = mc_plan(d_field, dims, M, need, off);
+  if (rc) return rc;
+  if (ws_bytes < need) return fail(CHR_E_NOMEM, "workspace too small: need " + std::to_string(need));
+  uint8_t *ws = static_cast<uint8_t *>(d_ws);
+  M.bits = reinterpret_cast<unsigned long long *>(ws + off[0]);
+  M.cnt = reinterpret_cast<U4 *>(ws + off[1]);
+  M.P = reinterpret_cast<U4 *>(ws + off[2]);
+  M.k = isovalue;
+  M.spacing = spacing;
+  M.verts = d_vertices;
+  M.tris = d_tris;
+  M.cap_v = cap_v;
+  M.cap_t = cap_t;
+  M.counts = d_counts;
+  launch_mc(M, reinterpret_cast<U4 *>(ws + off[3]), static_cast<hipStream_t>(stream));
+  return check_hip("iso_extract launch");
+}
+
+int iso_cases(const float *d_field, const int64_t dims[3], float isovalue, uint8_t *d_cases, void *d_ws,
+              size_t ws_bytes, void *stream) {
+  if (!d_field || !d_cases || !d_ws) return fail(CHR_E_INVAL, "NULL argument");
+  McPlan M;
+  size_t need = 0, off[5];
+  int rc = mc_plan(d_field, dims, M, need, off);
+  if (rc) return rc;
+  if (ws_bytes < need) return fail(CHR_E_NOMEM, "workspace too small");
+  uint8_t *ws = static_cast<uint8_t *>(d_ws);
+  M.bits = reinterpret_cast<unsigned long long *>(ws + off[0]);
+  M.k = isovalue;
+  M.cases = d_cases;
+  launch_mc_cases(M, static_cast<hipStream_t>(stream));
+  return check_hip("iso_cases launch");
+}
+
+int chr_mc_table(uint8_t *ntri, int8_t *tri) {
+  if (!ntri || !tri) return fail(CHR_E_INVAL, "NULL argument");
+  mc_table_host(ntri, tri);
+  return CHR_OK;
+}
+
+int chr_range(const float *d_field, int64_t n, float *d_out, void *stream) {
+  if (!d_field || !d_out || n < 1) return fail(CHR_E_INVAL, "bad argument");
+  launch_range(d_field, n, d_out, static_cast<hipStream_t>(stream));
+  return check_hip("chr_range launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,194 @@
+// chr_device.h -- shared definitions of the gfx950 CHR kernels.
+//
+// Stream format (little-endian; all offsets in bytes from the stream start):
+//   header, 256 bytes:
+//     0 u32 magic "CHR1"   4 u32 version=1   8 i64 nz  16 i64 ny  24 i64 nx
+//     32 i32 levels  36 i32 block  40 i32 qmax  44 i32 n_iso  48 f64 e
+//     56 f32 1/(2e)  60 f32 2e  64 f32 iso[16]  128 f32 vmin  132 f32 vmax
+//     136 i64 nblocks  144 i32 nbz,nby,nbx  156 u32 flags (bit0 lossless)
+//     160 u64 total bytes  168 u64 #outliers  176 u64 #corrections
+//     184 u64 payload offset  248 u32 table checksum  252 u32 header checksum
+//   section table at 256: per block (bz,by,bx lexicographic), per level from
+//     the coarsest: {u64 offset, u64 bytes}
+//   block table: per block {f32 min, f32 max, u32 checksum, u32 0}
+//   payload: blocks in order, each the concatenation of its sections.
+//   section (the points of one level in one closed block, lexicographic z,y,x):
+//     u32 npts, u32 W, u32 NE, u32 NX
+//     tile table: per 64 chunks {u32 W, u32 NE, u32 NX before the tile}, pad 8
+//     chunk header bytes (bits 0-4 width w <= 16, bit 7 has exact values), pad 8
+//     payload: per 64-point chunk w u64 words, code of lane i at bits [i*w,(i+1)*w)
+//       (code = zigzag of the quantization code; 0 where stored exactly)
+//     exact masks: u64 per chunk that has exact values (bit i = lane i)
+//     exact values: binary32 bits in chunk order then lane order, pad 8
+//   checksum of a byte range: sum mod 2^32 of fmix32(word_j ^ j*0x9E3779B9)
+//     over its 32-bit words (fmix32 = MurmurHash3's finalizer).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace chr {
+
+constexpr uint32_t kMagic = 0x31524843u;
+constexpr uint32_t kVersion = 1u;
+constexpr int kHeaderBytes = 256;
+constexpr int kMaxIso = 16;
+constexpr int kMaxW = 16;           // 32767 -> zigzag < 2^16
+constexpr int kWave = 64;
+
+// Everything a kernel needs to know about the field and the hierarchy.
+struct Geo {
+  int64_t n[3];      // dims z, y, x
+  int64_t nb[3];     // blocks per axis
+  int64_t nblocks;
+  int nL, B, qmax, K;
+  double e;
+  float inv, step;
+  int lossless;
+  float iso[kMaxIso];
+};
+
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+__host__ __device__ inline int64_t blocks_along(int64_t n, int64_t B) {
+  return n - 1 <= 0 ? 1 : ceil_div(n - 1, B);
+}
+
+// Closed extent [o, hi] of block b (lexicographic bz, by, bx).
+__host__ __device__ inline void block_ext(const Geo &g, int64_t b, int64_t o[3], int64_t hi[3]) {
+  int64_t bi[3];
+  bi[2] = b % g.nb[2];
+  bi[1] = (b / g.nb[2]) % g.nb[1];
+  bi[0] = b / (g.nb[2] * g.nb[1]);
+  for (int a = 0; a < 3; a++) {
+    o[a] = bi[a] * g.B;
+    hi[a] = o[a] + g.B;
+    if (hi[a] > g.n[a] - 1) hi[a] = g.n[a] - 1;
+  }
+}
+
+// Level-l section of one closed block: the points of the block's 2^l grid
+// that are not on its 2^(l+1) grid (all of them at the top level), visited in
+// lexicographic (z, y, x) order.  Local grid index (w, v, u) -> coordinate
+// o + (w, v, u) * 2^l.
+struct Sec {
+  uint32_t mx, my, mz;   // 2^l-grid points per axis in the block
+  uint32_t rowE;         // points in an even row of an even plane (odd u)
+  uint32_t Pe, Po;       // points in an even / odd plane
+  uint32_t npts;
+  int top;
+};
+
+__host__ __device__ inline Sec sec_geom(const int64_t o[3], const int64_t hi[3], int l, int L) {
+  Sec s;
+  s.mz = (uint32_t)((hi[0] - o[0]) >> l) + 1;
+  s.my = (uint32_t)((hi[1] - o[1]) >> l) + 1;
+  s.mx = (uint32_t)((hi[2] - o[2]) >> l) + 1;
+  s.top = (l == L);
+  if (s.top) {
+    s.rowE = 0; s.Pe = 0; s.Po = s.mx * s.my;
+    s.npts = s.mx * s.my * s.mz;
+  } else {
+    uint32_t cx = (s.mx + 1) / 2, cy = (s.my + 1) / 2, cz = (s.mz + 1) / 2;
+    s.rowE = s.mx - cx;
+    s.Pe = s.my * s.mx - cy * cx;
+    s.Po = s.my * s.mx;
+    s.npts = s.mz * s.my * s.mx - cz * cy * cx;
+  }
+  return s;
+}
+
+__host__ __device__ inline void sec_point(const Sec &s, uint32_t j, uint32_t &w, uint32_t &v, uint32_t &u) {
+  if (s.top) {
+    u = j % s.mx;
+    uint32_t t = j / s.mx;
+    v = t % s.my;
+    w = t / s.my;
+    return;
+  }
+  uint32_t pair = s.Pe + s.Po;
+  uint32_t w2 = j / pair, r = j - w2 * pair;
+  if (r < s.Pe) {
+    w = 2 * w2;
+    uint32_t RP = s.rowE + s.mx;
+    uint32_t v2 = r / RP, t = r - v2 * RP;
+    if (t < s.rowE) { v = 2 * v2; u = 2 * t + 1; }
+    else { v = 2 * v2 + 1; u = t - s.rowE; }
+  } else {
+    r -= s.Pe;
+    w = 2 * w2 + 1;
+    v = r / s.mx;
+    u = r - v * s.mx;
+  }
+}
+
+__host__ __device__ inline size_t pad8(size_t n) { return (n + 7) & ~(size_t)7; }
+
+__host__ __device__ inline uint64_t sec_bytes(uint64_t npts, uint64_t W, uint64_t NE, uint64_t NX) {
+  uint64_t nch = (npts + 63) / 64, ntile = (nch + 63) / 64;
+  return 16 + pad8(12 * ntile) + pad8(nch) + 8 * W + 8 * NE + pad8(4 * NX);
+}
+
+// Compact grid of level l: the points whose coordinates are multiples of 2^l.
+__host__ __device__ inline int64_t lvl_dim(int64_t n, int l) { return ((n - 1) >> l) + 1; }
+
+// Ordered-integer image of a binary32 value: unsigned comparison of the
+// images is the total order with -0 < +0.
+__host__ __device__ inline uint32_t ord_of(float f) {
+  uint32_t u;
+  __builtin_memcpy(&u, &f, 4);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__host__ __device__ inline float of_ord(uint32_t o) {
+  uint32_t u = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
+  float f;
+  __builtin_memcpy(&f, &u, 4);
+  return f;
+}
+
+__host__ __device__ inline uint32_t fmix32(uint32_t h) {
+  h ^= h >> 16; h *= 0x85ebca6bu; h ^= h >> 13; h *= 0xc2b2ae35u; h ^= h >> 16;
+  return h;
+}
+
+// ---------------------------------------------------------------- waves
+
+__device__ inline int lane_id() { return (int)__lane_id(); }
+
+__device__ inline uint32_t wave_or(uint32_t v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v |= __shfl_xor(v, m, kWave);
+  return v;
+}
+__device__ inline uint32_t wave_min_u(uint32_t v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) { uint32_t o = __shfl_xor(v, m, kWave); v = o < v ? o : v; }
+  return v;
+}
+__device__ inline uint32_t wave_max_u(uint32_t v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) { uint32_t o = __shfl_xor(v, m, kWave); v = o > v ? o : v; }
+  return v;
+}
+__device__ inline uint32_t wave_sum_u(uint32_t v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, kWave);
+  return v;
+}
+// exclusive prefix sum over the lanes of a wave
+__device__ inline uint32_t wave_excl_sum(uint32_t v) {
+  uint32_t x = v;
+  int lid = lane_id();
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    uint32_t y = __shfl_up(x, d, kWave);
+    if (lid >= d) x += y;
+  }
+  return x - v;
+}
+// number of set bits of m below this lane
+__device__ inline uint32_t lanes_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+}  // namespace chr

@@ -1,0 +1,86 @@
+// chr_plan.h -- launch plans of the compress / reconstruct / extract paths.
+#pragma once
+
+#include "chr_device.h"
+#include "scan.h"
+
+namespace chr {
+
+constexpr int kMaxLevels = 16;
+
+// Device-side statistics of one compression.
+struct Stats {
+  uint32_t xmin_ord, xmax_ord;   // range of the input (ordered images)
+  uint32_t nonfinite;
+  uint32_t pad;
+  unsigned long long n_outlier, n_corrected;
+};
+
+// Compression: per-level chunk slots hold one 64-point chunk each before the
+// stream is assembled (width/exact counts, packed codes, exact mask, exact
+// values); slots of level l for block b start at slot_base[l] + b*maxch[l].
+struct EncPlan {
+  Geo g;
+  int64_t slot_base[kMaxLevels];
+  uint32_t maxch[kMaxLevels];
+  int64_t nslots;
+  int64_t gd[kMaxLevels][3];     // compact grid dims of level l
+  int64_t g_off[kMaxLevels];     // offset (floats) of compact grid l >= 1 in G
+  uint64_t payload_off;          // bytes before the first section
+  uint64_t cap;
+  const float *x;
+  float *G;
+  U4 *cnt, *P;                   // per-slot {w, has exact, #exact, 0} and exclusive prefix
+  uint32_t *pay;                 // nslots * 32 words
+  unsigned long long *emask;     // nslots
+  float *exv;                    // nslots * 64
+  uint32_t *bstat;               // nblocks * 2 ordered min/max of reconstructed values
+  Stats *st;
+  uint64_t *secsz, *secoff;      // nblocks*nL (+1)
+  uint8_t *out;
+  void *result;                  // chr_result*
+  int32_t *codes;
+  uint8_t *flags;
+};
+
+// Reconstruction of levels L..lo.
+struct DecPlan {
+  Geo g;
+  int lo;
+  int64_t gd[kMaxLevels][3];
+  float *gp[kMaxLevels];         // compact grid of level l (gp[lo] = output when lo >= 1)
+  const uint8_t *s;
+  uint64_t sbytes;
+  uint64_t payload_off;
+  float *out;                    // full-resolution output when lo == 0
+  int32_t *status;
+};
+
+struct McPlan {
+  int64_t n[3];
+  int64_t nrows, nw;             // point rows (nz*ny) and 64-bit words per row
+  float k, spacing;
+  const float *f;
+  unsigned long long *bits;      // nrows * nw below-isovalue bits
+  U4 *cnt, *P;                   // per row {vertices, triangles, 0, 0} and prefix
+  float *verts;
+  int32_t *tris;
+  int64_t cap_v, cap_t;
+  int64_t *counts;
+  uint8_t *cases;
+};
+
+// Measurement hook: records a HIP event around launches of the kernel
+// selected with chr_prof_enable (no-op otherwise).
+void prof_mark(const char *kernel, hipStream_t s, int end);
+
+// launchers (encode.hip, decode.hip, mc.hip)
+void launch_encode(const EncPlan &p, int64_t scan_tmp_elems_u4, U4 *scan_tmp, uint64_t *scan_tmp64,
+                   hipStream_t s);
+void launch_decode(const DecPlan &p, hipStream_t s);
+void launch_mc(const McPlan &p, U4 *scan_tmp, hipStream_t s);
+void launch_mc_cases(const McPlan &p, hipStream_t s);
+void launch_range(const float *f, int64_t n, float *out, hipStream_t s);
+void mc_table_host(uint8_t *ntri, int8_t *tri);
+
+}  // namespace chr

@@ -1,0 +1,272 @@
+// decode.hip -- CHR reconstruction kernels for gfx950 (the visualization
+// side's reconstruction of the requested level, Sec. II).
+//
+// One 64-lane wave decodes one tile (64 chunks = 4096 points) of a section:
+// lane t reads chunk t's header byte, wave prefix sums over the widths and
+// exact flags (plus the tile's stored base offsets) locate every chunk's
+// codes, exact mask and exact values; then for each chunk every lane unpacks
+// its w-bit code with one or two aligned 32-bit loads, predicts its point
+// exactly as compression did, and writes x' = exact value or p + q*2e.
+// Coarse levels run one workgroup per block (levels nL-1 .. max(lo,1)); level
+// 0 runs over (tile groups, blocks) and writes whole output rows, taking the
+// even points of even rows from the level-1 grid.
+#include "chr_plan.h"
+
+namespace chr {
+namespace {
+
+constexpr int kBS = 256;
+constexpr int kWaves = kBS / kWave;
+
+__device__ inline float avg2(float a, float b) { return __fmul_rn(__fadd_rn(a, b), 0.5f); }
+
+// Same prediction as compression (multilinear midpoints from the coarser
+// compact grid, x then y then z, lower parent alone at the domain edge).
+__device__ inline float predict(const float *__restrict__ Gp, const int64_t gd[3], int l, int64_t z,
+                                int64_t y, int64_t x) {
+  const int sh = l + 1;
+  const int oz = (int)((z >> l) & 1), oy = (int)((y >> l) & 1), ox = (int)((x >> l) & 1);
+  const int64_t zl = (z - ((int64_t)oz << l)) >> sh;
+  const int64_t yl = (y - ((int64_t)oy << l)) >> sh;
+  const int64_t xl = (x - ((int64_t)ox << l)) >> sh;
+  const bool zu = oz && (zl + 1 < gd[0]);
+  const bool yu = oy && (yl + 1 < gd[1]);
+  const bool xu = ox && (xl + 1 < gd[2]);
+  auto row = [&](int64_t zi, int64_t yi) {
+    const float *r = Gp + (zi * gd[1] + yi) * gd[2];
+    float a = r[xl];
+    if (xu) a = avg2(a, r[xl + 1]);
+    return a;
+  };
+  float p = row(zl, yl);
+  if (yu) p = avg2(p, row(zl, yl + 1));
+  if (zu) {
+    float p1 = row(zl + 1, yl);
+    if (yu) p1 = avg2(p1, row(zl + 1, yl + 1));
+    p = avg2(p, p1);
+  }
+  return p;
+}
+
+__device__ inline uint32_t ld32(const uint8_t *p) { return *reinterpret_cast<const uint32_t *>(p); }
+__device__ inline uint64_t ld64(const uint8_t *p) {
+  const uint32_t *q = reinterpret_cast<const uint32_t *>(p);
+  return (uint64_t)q[0] | ((uint64_t)q[1] << 32);
+}
+
+__device__ inline uint32_t rl32(uint32_t v, int k) { return __builtin_amdgcn_readlane(v, k); }
+__device__ inline uint64_t rl64(uint64_t v, int k) {
+  return (uint64_t)rl32((uint32_t)v, k) | ((uint64_t)rl32((uint32_t)(v >> 32), k) << 32);
+}
+
+struct SecView {
+  const uint8_t *p;
+  uint32_t npts, W, NE, NX, nch, ntile;
+  uint64_t A, Poff, Moff, Xoff;
+  bool ok;
+};
+
+// Locates section (b, l) and checks its structure against the expected
+// point count and its table size.
+__device__ inline SecView open_section(const DecPlan &D, int64_t b, int l, uint32_t expect_npts) {
+  SecView v;
+  v.ok = false;
+  const int L = D.g.nL - 1;
+  const uint64_t ent = kHeaderBytes + 16 * ((uint64_t)b * D.g.nL + (uint64_t)(L - l));
+  if (ent + 16 > D.sbytes) return v;
+  const uint64_t off = ld64(D.s + ent), sz = ld64(D.s + ent + 8);
+  if (off < D.payload_off || (off & 7) || sz < 16 || off + sz > D.sbytes) return v;
+  v.p = D.s + off;
+  v.npts = ld32(v.p);
+  v.W = ld32(v.p + 4);
+  v.NE = ld32(v.p + 8);
+  v.NX = ld32(v.p + 12);
+  if (v.npts != expect_npts) return v;
+  if (sec_bytes(v.npts, v.W, v.NE, v.NX) != sz) return v;
+  v.nch = (v.npts + 63) / 64;
+  v.ntile = (v.nch + 63) / 64;
+  v.A = 16 + pad8(12 * (uint64_t)v.ntile);
+  v.Poff = v.A + pad8(v.nch);
+  v.Moff = v.Poff + 8 * (uint64_t)v.W;
+  v.Xoff = v.Moff + 8 * (uint64_t)v.NE;
+  v.ok = true;
+  return v;
+}
+
+__device__ inline void set_status(const DecPlan &D, int32_t code) {
+  if (D.status) atomicMin(D.status, code);
+}
+
+// Decodes tile t of a section; calls emit(z, y, x, value) for every point.
+template <class Emit>
+__device__ void dec_tile(const DecPlan &D, const SecView &v, int l, const int64_t o[3], const Sec &s, uint32_t t,
+                         Emit emit) {
+  const Geo &g = D.g;
+  const int L = g.nL - 1;
+  const int lane = lane_id();
+  const uint32_t c = t * 64 + (uint32_t)lane;
+  const uint8_t *tt = v.p + 16 + 12 * (uint64_t)t;
+  const uint32_t tw = ld32(tt), te = ld32(tt + 4), tx = ld32(tt + 8);
+  const uint32_t hb = c < v.nch ? v.p[v.A + c] : 0u;
+  const uint32_t w = hb & 31u, he = hb >> 7;
+  const uint32_t wo = tw + wave_excl_sum(w), eo = te + wave_excl_sum(he);
+  // structural checks: widths, exact masks and values stay inside the section
+  const uint32_t bad_l = (w > (uint32_t)kMaxW) || (hb & 0x60u) || (wo + w > v.W) || (he && eo >= v.NE);
+  if (__ballot(bad_l)) {
+    set_status(D, -4);
+    return;
+  }
+  const uint64_t em = he ? ld64(v.p + v.Moff + 8 * (uint64_t)eo) : 0ull;
+  const uint32_t pc = (uint32_t)__popcll(em);
+  const uint32_t xo = tx + wave_excl_sum(pc);
+  if (__ballot(xo + pc > v.NX)) {
+    set_status(D, -4);
+    return;
+  }
+  const uint32_t nc = min(64u, v.nch - t * 64);
+  const float *Gp = (l < L) ? D.gp[l + 1] : nullptr;
+  for (uint32_t k = 0; k < nc; k++) {
+    const uint32_t wk = rl32(w, (int)k), wok = rl32(wo, (int)k), xok = rl32(xo, (int)k);
+    const uint64_t emk = rl64(em, (int)k);
+    const uint32_t j = (t * 64 + k) * 64 + (uint32_t)lane;
+    if (j >= s.npts) continue;
+    uint32_t zc = 0;
+    if (wk) {
+      const uint32_t bit = (uint32_t)lane * wk, off = bit & 31u;
+      const uint8_t *wp = v.p + v.Poff + 8 * (uint64_t)wok + 4 * (uint64_t)(bit >> 5);
+      uint32_t lo = ld32(wp);
+      zc = lo >> off;
+      if (off + wk > 32u) zc |= ld32(wp + 4) << (32u - off);
+      zc &= (wk == 32u) ? 0xffffffffu : ((1u << wk) - 1u);
+    }
+    uint32_t ww, vv, uu;
+    sec_point(s, j, ww, vv, uu);
+    const int64_t z = o[0] + ((int64_t)ww << l), y = o[1] + ((int64_t)vv << l), x = o[2] + ((int64_t)uu << l);
+    float r;
+    if ((emk >> lane) & 1ull) {
+      r = __uint_as_float(ld32(v.p + v.Xoff + 4 * ((uint64_t)xok + lanes_below(emk))));
+    } else {
+      const float p = (l == L) ? 0.0f : predict(Gp, D.gd[l + 1], l, z, y, x);
+      const int32_t q = (int32_t)(zc >> 1) ^ -(int32_t)(zc & 1u);
+      r = g.lossless ? p : __fadd_rn(p, __fmul_rn((float)q, g.step));
+    }
+    emit(z, y, x, r);
+  }
+}
+
+// Coarse levels of one block per workgroup.
+__global__ __launch_bounds__(kBS) void k_decode_coarse(DecPlan D) {
+  const Geo &g = D.g;
+  const int L = g.nL - 1;
+  const int64_t b = blockIdx.x;
+  const int wave = threadIdx.x / kWave;
+  const int lmin = D.lo > 1 ? D.lo : 1;
+  int64_t o[3], hi[3];
+  block_ext(g, b, o, hi);
+  for (int l = L; l >= lmin; l--) {
+    float *dst = D.gp[l];
+    const int64_t *gd = D.gd[l];
+    if (l < L) {
+      const int sh = l + 1;
+      const int64_t c0 = ((hi[0] - o[0]) >> sh) + 1, c1 = ((hi[1] - o[1]) >> sh) + 1, c2 = ((hi[2] - o[2]) >> sh) + 1;
+      const float *src = D.gp[l + 1];
+      for (int64_t i = threadIdx.x; i < c0 * c1 * c2; i += kBS) {
+        const int64_t u = i % c2, v = (i / c2) % c1, w = i / (c2 * c1);
+        const int64_t zc = (o[0] >> sh) + w, yc = (o[1] >> sh) + v, xc = (o[2] >> sh) + u;
+        dst[((2 * zc) * gd[1] + 2 * yc) * gd[2] + 2 * xc] = src[(zc * D.gd[l + 1][1] + yc) * D.gd[l + 1][2] + xc];
+      }
+    }
+    const Sec s = sec_geom(o, hi, l, L);
+    const SecView v = open_section(D, b, l, s.npts);
+    if (!v.ok) {
+      if (threadIdx.x == 0) set_status(D, -4);
+    } else {
+      for (uint32_t t = wave; t < v.ntile; t += kWaves)
+        dec_tile(D, v, l, o, s, t, [&](int64_t z, int64_t y, int64_t x, float r) {
+          dst[((z >> l) * gd[1] + (y >> l)) * gd[2] + (x >> l)] = r;
+        });
+    }
+    __syncthreads();
+  }
+}
+
+// Level 0 over (tile groups, blocks): each wave decodes one tile and writes
+// the points the block owns, plus the coarse (even) points of even rows.
+__global__ __launch_bounds__(kBS) void k_decode_fine(DecPlan D) {
+  const Geo &g = D.g;
+  const int L = g.nL - 1;
+  const int64_t b = blockIdx.y;
+  const uint32_t t = blockIdx.x * kWaves + threadIdx.x / kWave;
+  int64_t o[3], hi[3];
+  block_ext(g, b, o, hi);
+  const Sec s = sec_geom(o, hi, 0, L);
+  const uint32_t nch = (s.npts + 63) / 64;
+  if (t >= (nch + 63) / 64) return;
+  const SecView v = open_section(D, b, 0, s.npts);
+  if (!v.ok) {
+    if (lane_id() == 0) set_status(D, -4);
+    return;
+  }
+  const int64_t n1 = g.n[1], n2 = g.n[2];
+  const int64_t ez = (o[0] + g.B < g.n[0] - 1) ? o[0] + g.B : g.n[0];  // first z not owned
+  const int64_t ey = (o[1] + g.B < g.n[1] - 1) ? o[1] + g.B : g.n[1];
+  const int64_t ex = (o[2] + g.B < g.n[2] - 1) ? o[2] + g.B : g.n[2];
+  const float *G1 = (L >= 1) ? D.gp[1] : nullptr;
+  const int64_t *gd1 = D.gd[1];
+  float *out = D.out;
+  dec_tile(D, v, 0, o, s, t, [&](int64_t z, int64_t y, int64_t x, float r) {
+    if (z >= ez || y >= ey) return;
+    float *row = out + (z * n1 + y) * n2;
+    if (x < ex) row[x] = r;
+    if (L >= 1 && !((z | y) & 1) && (x & 1)) {
+      // even row of an even plane: the neighbouring even points come from level 1
+      const float *g1 = G1 + ((z >> 1) * gd1[1] + (y >> 1)) * gd1[2];
+      row[x - 1] = g1[(x - 1) >> 1];
+      if (x + 1 == hi[2] && hi[2] == g.n[2] - 1) row[x + 1] = g1[(x + 1) >> 1];
+    }
+  });
+}
+
+// Even points of even rows in blocks one point wide along x (no level-0
+// point in those rows writes them).
+__global__ __launch_bounds__(kBS) void k_decode_thin(DecPlan D) {
+  const Geo &g = D.g;
+  const int64_t b = blockIdx.x;
+  int64_t o[3], hi[3];
+  block_ext(g, b, o, hi);
+  if (hi[2] != o[2]) return;
+  const int64_t cz = ((hi[0] - o[0]) >> 1) + 1, cy = ((hi[1] - o[1]) >> 1) + 1;
+  for (int64_t i = threadIdx.x; i < cz * cy; i += kBS) {
+    const int64_t z = o[0] + 2 * (i / cy), y = o[1] + 2 * (i % cy), x = o[2];
+    D.out[(z * g.n[1] + y) * g.n[2] + x] = D.gp[1][((z >> 1) * D.gd[1][1] + (y >> 1)) * D.gd[1][2] + (x >> 1)];
+  }
+}
+
+}  // namespace
+
+void launch_decode(const DecPlan &p, hipStream_t s) {
+  const Geo &g = p.g;
+  const int L = g.nL - 1;
+  if (L >= 1) {
+    prof_mark("k_decode_coarse", s, 0);
+    k_decode_coarse<<<dim3((unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
+    prof_mark("k_decode_coarse", s, 1);
+  }
+  if (p.lo == 0) {
+    // the largest level-0 section belongs to the first block
+    int64_t o[3], hi[3];
+    block_ext(g, 0, o, hi);
+    const Sec s0 = sec_geom(o, hi, 0, L);
+    const int64_t ntile = ceil_div(ceil_div(s0.npts, 64), 64);
+    prof_mark("k_decode_fine", s, 0);
+    k_decode_fine<<<dim3((unsigned)ceil_div(ntile > 0 ? ntile : 1, kWaves), (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
+    prof_mark("k_decode_fine", s, 1);
+    if (L >= 1) {
+      prof_mark("k_decode_thin", s, 0);
+      k_decode_thin<<<dim3((unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
+      prof_mark("k_decode_thin", s, 1);
+    }
+  }
+}
+
+}  // namespace chr

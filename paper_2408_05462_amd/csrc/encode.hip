@@ -1,0 +1,487 @@
+// encode.hip -- CHR compression kernels for gfx950.
+//
+// One 64-lane wave encodes one 64-point chunk of a (block, level) section:
+// every lane predicts its point from the reconstructed coarser grid,
+// quantizes, checks the error bound, checks that the point stays on the same
+// side of every candidate isovalue (Sec. II.B: topology preservation) and, if
+// either check fails, stores the point exactly.  The chunk's zigzag codes are
+// bit-packed at the wave's maximum width through LDS, exact points are
+// compacted with a ballot and mbcnt.
+//
+// Launch sequence: coarse levels (one workgroup per block, levels nL-1..1,
+// each level's compact grid written before the next level reads it) ->
+// level 0 (a 2D grid over chunk groups x blocks) -> scan of the per-chunk
+// sizes -> section sizes -> scan of section sizes -> section headers and
+// tables -> chunk copy into the stream -> block table -> stream header.
+#include "chr_plan.h"
+
+namespace chr {
+namespace {
+
+constexpr int kBS = 256;
+constexpr int kWaves = kBS / kWave;
+constexpr int kChunksPerWave = 4;
+
+__device__ inline float avg2(float a, float b) { return __fmul_rn(__fadd_rn(a, b), 0.5f); }
+
+// Multilinear midpoint prediction of point (z,y,x) of level l from the
+// compact grid Gp of level l+1 (dims gd): along each axis where the
+// coordinate is an odd multiple of 2^l the two parents at -2^l and +2^l are
+// averaged (the lower one alone if the upper one is outside the domain);
+// averages along x first, then y, then z.
+__device__ inline float predict(const float *__restrict__ Gp, const int64_t gd[3], int l, int64_t z,
+                                int64_t y, int64_t x) {
+  const int sh = l + 1;
+  const int oz = (int)((z >> l) & 1), oy = (int)((y >> l) & 1), ox = (int)((x >> l) & 1);
+  const int64_t zl = (z - ((int64_t)oz << l)) >> sh;
+  const int64_t yl = (y - ((int64_t)oy << l)) >> sh;
+  const int64_t xl = (x - ((int64_t)ox << l)) >> sh;
+  const bool zu = oz && (zl + 1 < gd[0]);
+  const bool yu = oy && (yl + 1 < gd[1]);
+  const bool xu = ox && (xl + 1 < gd[2]);
+  auto row = [&](int64_t zi, int64_t yi) {
+    const float *r = Gp + (zi * gd[1] + yi) * gd[2];
+    float a = r[xl];
+    if (xu) a = avg2(a, r[xl + 1]);
+    return a;
+  };
+  float p = row(zl, yl);
+  if (yu) p = avg2(p, row(zl, yl + 1));
+  if (zu) {
+    float p1 = row(zl + 1, yl);
+    if (yu) p1 = avg2(p1, row(zl + 1, yl + 1));
+    p = avg2(p, p1);
+  }
+  return p;
+}
+
+// Error-bounded linear quantization: q = rint((x-p)/(2e)) (half even), the
+// reconstruction p + q*2e, an outlier when |q| > qmax or the reconstruction
+// misses the bound (checked in double).  Lossless mode: q = 0, x' = p.
+__device__ inline void quantize(const Geo &g, float x, float p, int32_t &q, int &O, float &xr) {
+  if (g.lossless) {
+    q = 0;
+    xr = p;
+    O = __float_as_uint(p) != __float_as_uint(x);
+    return;
+  }
+  const float d = __fsub_rn(x, p);
+  const float qf = rintf(__fmul_rn(d, g.inv));
+  if (!(fabsf(qf) <= (float)g.qmax)) {
+    q = 0; O = 1; xr = p;
+    return;
+  }
+  xr = __fadd_rn(p, __fmul_rn(qf, g.step));
+  q = (int32_t)qf;
+  O = !(fabs((double)xr - (double)x) <= g.e);
+}
+
+// Number of candidate isovalues k with k <= v; equal counts for x and x'
+// mean x' lies on the same side of every candidate as x.
+__device__ inline int rank_of(const Geo &g, float v) {
+  int r = 0;
+  for (int j = 0; j < g.K; j++) r += (g.iso[j] <= v) ? 1 : 0;
+  return r;
+}
+
+struct Acc {
+  uint32_t rmin, rmax;   // reconstructed values (block index)
+  uint32_t xmin, xmax;   // input values (header range)
+  uint32_t nonfinite;
+  uint32_t nO, nC;       // owned points only
+  __device__ void init() { rmin = xmin = 0xffffffffu; rmax = xmax = 0u; nonfinite = 0; nO = nC = 0; }
+};
+
+__device__ inline bool owned(const Geo &g, const int64_t o[3], int64_t z, int64_t y, int64_t x) {
+  return (z < o[0] + g.B || z == g.n[0] - 1) && (y < o[1] + g.B || y == g.n[1] - 1) &&
+         (x < o[2] + g.B || x == g.n[2] - 1);
+}
+
+__device__ void flush(const EncPlan &P, int64_t b, Acc &a) {
+  uint32_t rmin = wave_min_u(a.rmin), rmax = wave_max_u(a.rmax);
+  uint32_t xmin = wave_min_u(a.xmin), xmax = wave_max_u(a.xmax);
+  uint32_t nf = wave_or(a.nonfinite), nO = wave_sum_u(a.nO), nC = wave_sum_u(a.nC);
+  if (lane_id() == 0) {
+    if (rmin != 0xffffffffu) atomicMin(&P.bstat[2 * b], rmin);
+    if (rmax != 0u) atomicMax(&P.bstat[2 * b + 1], rmax);
+    if (xmin != 0xffffffffu) atomicMin(&P.st->xmin_ord, xmin);
+    if (xmax != 0u) atomicMax(&P.st->xmax_ord, xmax);
+    if (nf) atomicOr(&P.st->nonfinite, nf);
+    if (nO) atomicAdd(&P.st->n_outlier, (unsigned long long)nO);
+    if (nC) atomicAdd(&P.st->n_corrected, (unsigned long long)nC);
+  }
+}
+
+// Encodes chunk c of the level-l section of block b into its slot.
+__device__ void enc_chunk(const EncPlan &P, int l, int64_t b, const int64_t o[3], const Sec &s, uint32_t c,
+                          uint32_t *pack, Acc &acc) {
+  const Geo &g = P.g;
+  const int L = g.nL - 1;
+  const int lane = lane_id();
+  const uint32_t j = c * kWave + (uint32_t)lane;
+  const bool valid = j < s.npts;
+  float x = 0.f, xr = 0.f;
+  int32_t q = 0;
+  int O = 0, C = 0;
+  if (valid) {
+    uint32_t w, v, u;
+    sec_point(s, j, w, v, u);
+    const int64_t z = o[0] + ((int64_t)w << l), y = o[1] + ((int64_t)v << l), xx = o[2] + ((int64_t)u << l);
+    const int64_t gi = (z * g.n[1] + y) * g.n[2] + xx;
+    x = P.x[gi];
+    const float p = (l == L) ? 0.0f : predict(P.G + P.g_off[l + 1], P.gd[l + 1], l, z, y, xx);
+    quantize(g, x, p, q, O, xr);
+    if (!O && g.K > 0) C = rank_of(g, x) != rank_of(g, xr);
+    if (O || C) { xr = x; q = 0; }
+    if (l >= 1) P.G[P.g_off[l] + ((z >> l) * P.gd[l][1] + (y >> l)) * P.gd[l][2] + (xx >> l)] = xr;
+    const uint32_t ro = ord_of(xr), xo = ord_of(x);
+    acc.rmin = min(acc.rmin, ro); acc.rmax = max(acc.rmax, ro);
+    acc.xmin = min(acc.xmin, xo); acc.xmax = max(acc.xmax, xo);
+    acc.nonfinite |= !isfinite(x);
+    if (owned(g, o, z, y, xx)) { acc.nO += O; acc.nC += C; }
+    if (P.codes) P.codes[gi] = q;
+    if (P.flags) P.flags[gi] = (uint8_t)(O | (C << 1));
+  }
+  const bool E = valid && (O || C);
+  const uint32_t zz = (valid && !E) ? (((uint32_t)q << 1) ^ (uint32_t)(q >> 31)) : 0u;
+  const uint32_t orv = wave_or(zz);
+  const int wb = orv ? 32 - __clz((int)orv) : 0;
+  const unsigned long long em = __ballot(E);
+  const int64_t slot = P.slot_base[l] + b * (int64_t)P.maxch[l] + c;
+
+  // pack the codes at bit lane*wb through LDS
+  if (lane < 32) pack[lane] = 0u;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  if (wb && zz) {
+    const uint32_t bit = (uint32_t)lane * (uint32_t)wb, wi = bit >> 5, off = bit & 31u;
+    __hip_atomic_fetch_or(&pack[wi], zz << off, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    if (off + (uint32_t)wb > 32u)
+      __hip_atomic_fetch_or(&pack[wi + 1], zz >> (32u - off), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  if (lane < 2 * wb) P.pay[slot * 32 + lane] = pack[lane];
+  if (E) P.exv[slot * 64 + lanes_below(em)] = x;
+  if (lane == 0) {
+    P.cnt[slot] = U4{(uint32_t)wb, em ? 1u : 0u, (uint32_t)__popcll(em), 0u};
+    if (em) P.emask[slot] = em;
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ inline void zero_slot(const EncPlan &P, int l, int64_t b, uint32_t c) {
+  if (lane_id() == 0) P.cnt[P.slot_base[l] + b * (int64_t)P.maxch[l] + c] = U4{0, 0, 0, 0};
+}
+
+__global__ __launch_bounds__(kBS) void k_init(EncPlan P) {
+  const int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x;
+  if (i < P.g.nblocks) { P.bstat[2 * i] = 0xffffffffu; P.bstat[2 * i + 1] = 0u; }
+  if (i == 0) {
+    P.st->xmin_ord = 0xffffffffu; P.st->xmax_ord = 0u; P.st->nonfinite = 0; P.st->pad = 0;
+    P.st->n_outlier = 0; P.st->n_corrected = 0;
+    P.P[P.nslots] = U4{0, 0, 0, 0};
+  }
+}
+
+// Levels nL-1 .. 1 of one block per workgroup.
+__global__ __launch_bounds__(kBS) void k_encode_coarse(EncPlan P) {
+  __shared__ uint32_t pack[kWaves][32];
+  const Geo &g = P.g;
+  const int L = g.nL - 1;
+  const int64_t b = blockIdx.x;
+  const int wave = threadIdx.x / kWave;
+  int64_t o[3], hi[3];
+  block_ext(g, b, o, hi);
+  Acc acc;
+  acc.init();
+  for (int l = L; l >= 1; l--) {
+    if (l < L) {
+      // the block's points of the coarser grid carry over unchanged
+      const int sh = l + 1;
+      const int64_t c0 = ((hi[0] - o[0]) >> sh) + 1, c1 = ((hi[1] - o[1]) >> sh) + 1, c2 = ((hi[2] - o[2]) >> sh) + 1;
+      const float *src = P.G + P.g_off[l + 1];
+      float *dst = P.G + P.g_off[l];
+      for (int64_t i = threadIdx.x; i < c0 * c1 * c2; i += kBS) {
+        const int64_t u = i % c2, v = (i / c2) % c1, w = i / (c2 * c1);
+        const int64_t zc = (o[0] >> sh) + w, yc = (o[1] >> sh) + v, xc = (o[2] >> sh) + u;
+        dst[((2 * zc) * P.gd[l][1] + 2 * yc) * P.gd[l][2] + 2 * xc] =
+            src[(zc * P.gd[l + 1][1] + yc) * P.gd[l + 1][2] + xc];
+      }
+    }
+    const Sec s = sec_geom(o, hi, l, L);
+    const uint32_t nch = (s.npts + 63) / 64;
+    for (uint32_t c = wave; c < P.maxch[l]; c += kWaves) {
+      if (c < nch) enc_chunk(P, l, b, o, s, c, pack[wave], acc);
+      else zero_slot(P, l, b, c);
+    }
+    __syncthreads();
+  }
+  flush(P, b, acc);
+}
+
+// Level 0: a 2D grid of (chunk groups, blocks).
+__global__ __launch_bounds__(kBS) void k_encode_fine(EncPlan P) {
+  __shared__ uint32_t pack[kWaves][32];
+  const Geo &g = P.g;
+  const int L = g.nL - 1;
+  const int64_t b = blockIdx.y;
+  const int wave = threadIdx.x / kWave;
+  int64_t o[3], hi[3];
+  block_ext(g, b, o, hi);
+  const Sec s = sec_geom(o, hi, 0, L);
+  const uint32_t nch = (s.npts + 63) / 64;
+  Acc acc;
+  acc.init();
+  for (int k = 0; k < kChunksPerWave; k++) {
+    const uint32_t c = (blockIdx.x * kChunksPerWave + k) * kWaves + wave;
+    if (c >= P.maxch[0]) break;
+    if (c < nch) enc_chunk(P, 0, b, o, s, c, pack[wave], acc);
+    else zero_slot(P, 0, b, c);
+  }
+  flush(P, b, acc);
+}
+
+// Byte size of every section from the scanned chunk sizes.
+__global__ __launch_bounds__(kBS) void k_sections(EncPlan P) {
+  const Geo &g = P.g;
+  const int64_t nsec = g.nblocks * g.nL;
+  const int64_t sec = (int64_t)blockIdx.x * kBS + threadIdx.x;
+  if (sec >= nsec) return;
+  const int L = g.nL - 1;
+  const int64_t b = sec / g.nL;
+  const int l = L - (int)(sec % g.nL);
+  int64_t o[3], hi[3];
+  block_ext(g, b, o, hi);
+  const Sec s = sec_geom(o, hi, l, L);
+  const uint32_t nch = (s.npts + 63) / 64;
+  const int64_t s0 = P.slot_base[l] + b * (int64_t)P.maxch[l];
+  const U4 a = P.P[s0], e = P.P[s0 + nch];
+  P.secsz[sec] = sec_bytes(s.npts, e.x - a.x, e.y - a.y, e.z - a.z);
+}
+
+__device__ inline void put8(const EncPlan &P, uint64_t off, uint8_t v) {
+  if (off < P.cap) P.out[off] = v;
+}
+__device__ inline void put32(const EncPlan &P, uint64_t off, uint32_t v) {
+  if (off + 4 <= P.cap) *reinterpret_cast<uint32_t *>(P.out + off) = v;
+}
+__device__ inline void put64(const EncPlan &P, uint64_t off, uint64_t v) {
+  if (off + 8 <= P.cap) {
+    uint32_t *p = reinterpret_cast<uint32_t *>(P.out + off);
+    p[0] = (uint32_t)v;
+    p[1] = (uint32_t)(v >> 32);
+  }
+}
+
+// Section table entries, section headers and padding bytes.
+__global__ __launch_bounds__(kBS) void k_sec_table(EncPlan P) {
+  const Geo &g = P.g;
+  const int64_t nsec = g.nblocks * g.nL;
+  const int64_t sec = (int64_t)blockIdx.x * kBS + threadIdx.x;
+  if (sec >= nsec) return;
+  const int L = g.nL - 1;
+  const int64_t b = sec / g.nL;
+  const int l = L - (int)(sec % g.nL);
+  int64_t o[3], hi[3];
+  block_ext(g, b, o, hi);
+  const Sec s = sec_geom(o, hi, l, L);
+  const uint32_t nch = (s.npts + 63) / 64, ntile = (nch + 63) / 64;
+  const int64_t s0 = P.slot_base[l] + b * (int64_t)P.maxch[l];
+  const U4 a = P.P[s0], e = P.P[s0 + nch];
+  const uint32_t W = e.x - a.x, NE = e.y - a.y, NX = e.z - a.z;
+  const uint64_t so = P.payload_off + P.secoff[sec];
+  put64(P, kHeaderBytes + 16 * (uint64_t)sec, so);
+  put64(P, kHeaderBytes + 16 * (uint64_t)sec + 8, P.secsz[sec]);
+  put32(P, so, s.npts);
+  put32(P, so + 4, W);
+  put32(P, so + 8, NE);
+  put32(P, so + 12, NX);
+  const uint64_t tt = 16 + 12 * (uint64_t)ntile, A = 16 + pad8(12 * (uint64_t)ntile);
+  for (uint64_t i = tt; i < A; i++) put8(P, so + i, 0);
+  const uint64_t H = A + nch, Poff = A + pad8(nch);
+  for (uint64_t i = H; i < Poff; i++) put8(P, so + i, 0);
+  const uint64_t Xend = Poff + 8 * (uint64_t)W + 8 * (uint64_t)NE + 4 * (uint64_t)NX;
+  const uint64_t end = Poff + 8 * (uint64_t)W + 8 * (uint64_t)NE + pad8(4 * (uint64_t)NX);
+  for (uint64_t i = Xend; i < end; i++) put8(P, so + i, 0);
+}
+
+// Copies every chunk from its slot into its place in the stream.
+__global__ __launch_bounds__(kBS) void k_pack(EncPlan P) {
+  const Geo &g = P.g;
+  const int L = g.nL - 1;
+  const int lane = lane_id();
+  const int64_t slot = (int64_t)blockIdx.x * kWaves + threadIdx.x / kWave;
+  if (slot >= P.nslots) return;
+  int l = 0;
+  for (int t = 0; t <= L; t++)
+    if (slot >= P.slot_base[t] && slot < P.slot_base[t] + g.nblocks * (int64_t)P.maxch[t]) l = t;
+  const int64_t rel = slot - P.slot_base[l];
+  const int64_t b = rel / P.maxch[l];
+  const uint32_t c = (uint32_t)(rel % P.maxch[l]);
+  int64_t o[3], hi[3];
+  block_ext(g, b, o, hi);
+  const Sec s = sec_geom(o, hi, l, L);
+  const uint32_t nch = (s.npts + 63) / 64;
+  if (c >= nch) return;
+  const uint32_t ntile = (nch + 63) / 64;
+  const int64_t s0 = P.slot_base[l] + b * (int64_t)P.maxch[l];
+  const U4 a = P.P[s0], e = P.P[s0 + nch], cur = P.P[slot], cc = P.cnt[slot];
+  const uint32_t W = e.x - a.x, NE = e.y - a.y;
+  const uint32_t pw = cur.x - a.x, pe = cur.y - a.y, px = cur.z - a.z;
+  const uint64_t so = P.payload_off + P.secoff[b * g.nL + (L - l)];
+  const uint64_t A = 16 + pad8(12 * (uint64_t)ntile), Poff = A + pad8(nch);
+  const uint64_t Moff = Poff + 8 * (uint64_t)W, Xoff = Moff + 8 * (uint64_t)NE;
+  if (lane == 0) {
+    if (c % 64 == 0) {
+      const uint64_t t = so + 16 + 12 * (uint64_t)(c / 64);
+      put32(P, t, pw);
+      put32(P, t + 4, pe);
+      put32(P, t + 8, px);
+    }
+    put8(P, so + A + c, (uint8_t)(cc.x | (cc.y ? 0x80u : 0u)));
+    if (cc.y) put64(P, so + Moff + 8 * (uint64_t)pe, P.emask[slot]);
+  }
+  if (lane < 2 * (int)cc.x) put32(P, so + Poff + 8 * (uint64_t)pw + 4 * lane, P.pay[slot * 32 + lane]);
+  if (lane < (int)cc.z) put32(P, so + Xoff + 4 * ((uint64_t)px + lane), __float_as_uint(P.exv[slot * 64 + lane]));
+}
+
+__device__ inline uint32_t get32(const EncPlan &P, uint64_t off) {
+  return *reinterpret_cast<const uint32_t *>(P.out + off);
+}
+
+template <int BS>
+__device__ uint32_t block_sum(uint32_t v) {
+  __shared__ uint32_t red[BS / kWave];
+  v = wave_sum_u(v);
+  if (lane_id() == 0) red[threadIdx.x / kWave] = v;
+  __syncthreads();
+  uint32_t t = 0;
+  for (int i = 0; i < BS / kWave; i++) t += red[i];
+  __syncthreads();
+  return t;
+}
+
+// Block table: min/max of the block's reconstructed values and the checksum
+// of its byte range.
+__global__ __launch_bounds__(kBS) void k_block_table(EncPlan P) {
+  const Geo &g = P.g;
+  const int64_t b = blockIdx.x;
+  const uint64_t total = P.payload_off + P.secoff[g.nblocks * g.nL];
+  const bool fits = total <= P.cap;
+  const uint64_t start = P.payload_off + P.secoff[b * g.nL];
+  const uint64_t end = P.payload_off + P.secoff[(b + 1) * g.nL];
+  uint32_t sum = 0;
+  if (fits)
+    for (uint64_t j = threadIdx.x; j < (end - start) / 4; j += kBS)
+      sum += fmix32(get32(P, start + 4 * j) ^ (uint32_t)((uint32_t)j * 0x9E3779B9u));
+  sum = block_sum<kBS>(sum);
+  if (threadIdx.x == 0) {
+    const uint64_t bt = kHeaderBytes + 16 * (uint64_t)g.nblocks * g.nL + 16 * (uint64_t)b;
+    put32(P, bt, __float_as_uint(of_ord(P.bstat[2 * b])));
+    put32(P, bt + 4, __float_as_uint(of_ord(P.bstat[2 * b + 1])));
+    put32(P, bt + 8, sum);
+    put32(P, bt + 12, 0);
+  }
+}
+
+struct ResultDev {
+  uint64_t stream_bytes, n_outlier, n_corrected;
+  int32_t status;
+  float vmin, vmax;
+  uint32_t reserved;
+};
+
+// Stream header, table checksum, header checksum, and the result record.
+__global__ __launch_bounds__(kBS) void k_header(EncPlan P) {
+  const Geo &g = P.g;
+  const uint64_t total = P.payload_off + P.secoff[g.nblocks * g.nL];
+  const bool fits = total <= P.cap;
+  uint32_t sum = 0;
+  if (fits)
+    for (uint64_t j = threadIdx.x; j < (P.payload_off - kHeaderBytes) / 4; j += kBS)
+      sum += fmix32(get32(P, kHeaderBytes + 4 * j) ^ (uint32_t)((uint32_t)j * 0x9E3779B9u));
+  sum = block_sum<kBS>(sum);
+  if (threadIdx.x != 0) return;
+  const float vmin = of_ord(P.st->xmin_ord), vmax = of_ord(P.st->xmax_ord);
+  if (fits) {
+    for (int i = 0; i < kHeaderBytes; i += 4) put32(P, i, 0u);
+    put32(P, 0, kMagic);
+    put32(P, 4, kVersion);
+    for (int a = 0; a < 3; a++) put64(P, 8 + 8 * a, (uint64_t)g.n[a]);
+    put32(P, 32, (uint32_t)g.nL);
+    put32(P, 36, (uint32_t)g.B);
+    put32(P, 40, (uint32_t)g.qmax);
+    put32(P, 44, (uint32_t)g.K);
+    uint64_t eb;
+    __builtin_memcpy(&eb, &g.e, 8);
+    put64(P, 48, eb);
+    put32(P, 56, __float_as_uint(g.inv));
+    put32(P, 60, __float_as_uint(g.step));
+    for (int j = 0; j < kMaxIso; j++) put32(P, 64 + 4 * j, __float_as_uint(j < g.K ? g.iso[j] : 0.0f));
+    put32(P, 128, __float_as_uint(vmin));
+    put32(P, 132, __float_as_uint(vmax));
+    put64(P, 136, (uint64_t)g.nblocks);
+    for (int a = 0; a < 3; a++) put32(P, 144 + 4 * a, (uint32_t)g.nb[a]);
+    put32(P, 156, g.lossless ? 1u : 0u);
+    put64(P, 160, total);
+    put64(P, 168, P.st->n_outlier);
+    put64(P, 176, P.st->n_corrected);
+    put64(P, 184, P.payload_off);
+    put32(P, 248, sum);
+    uint32_t hs = 0;
+    for (uint32_t j = 0; j < 63; j++) hs += fmix32(get32(P, 4 * j) ^ (j * 0x9E3779B9u));
+    put32(P, 252, hs);
+  }
+  ResultDev *r = reinterpret_cast<ResultDev *>(P.result);
+  r->stream_bytes = total;
+  r->n_outlier = P.st->n_outlier;
+  r->n_corrected = P.st->n_corrected;
+  r->status = P.st->nonfinite ? -1 : (fits ? 0 : -5);
+  r->vmin = vmin;
+  r->vmax = vmax;
+  r->reserved = 0;
+}
+
+}  // namespace
+
+void launch_encode(const EncPlan &p, int64_t, U4 *scan_tmp, uint64_t *scan_tmp64, hipStream_t s) {
+  const Geo &g = p.g;
+  const int L = g.nL - 1;
+  const int64_t nsec = g.nblocks * g.nL;
+  k_init<<<dim3((unsigned)ceil_div(g.nblocks > 0 ? g.nblocks : 1, kBS)), dim3(kBS), 0, s>>>(p);
+  if (L >= 1) {
+    prof_mark("k_encode_coarse", s, 0);
+    k_encode_coarse<<<dim3((unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
+    prof_mark("k_encode_coarse", s, 1);
+  }
+  {
+    const unsigned gx = (unsigned)ceil_div(p.maxch[0], (int64_t)kWaves * kChunksPerWave);
+    if (gx > 0) {
+      prof_mark("k_encode_fine", s, 0);
+      k_encode_fine<<<dim3(gx, (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
+      prof_mark("k_encode_fine", s, 1);
+    }
+  }
+  scan_u4(p.cnt, p.P, p.nslots, scan_tmp, s);
+  prof_mark("k_sections", s, 0);
+  k_sections<<<dim3((unsigned)ceil_div(nsec, kBS)), dim3(kBS), 0, s>>>(p);
+  prof_mark("k_sections", s, 1);
+  scan_u64(p.secsz, p.secoff, nsec, scan_tmp64, s);
+  prof_mark("k_sec_table", s, 0);
+  k_sec_table<<<dim3((unsigned)ceil_div(nsec, kBS)), dim3(kBS), 0, s>>>(p);
+  prof_mark("k_sec_table", s, 1);
+  if (p.nslots > 0) {
+    prof_mark("k_pack", s, 0);
+    k_pack<<<dim3((unsigned)ceil_div(p.nslots, kWaves)), dim3(kBS), 0, s>>>(p);
+    prof_mark("k_pack", s, 1);
+  }
+  prof_mark("k_block_table", s, 0);
+  k_block_table<<<dim3((unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
+  prof_mark("k_block_table", s, 1);
+  prof_mark("k_header", s, 0);
+  k_header<<<dim3(1), dim3(kBS), 0, s>>>(p);
+  prof_mark("k_header", s, 1);
+}
+
+}  // namespace chr

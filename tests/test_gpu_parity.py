@@ -1,0 +1,187 @@
+"""GPU parity: the HIP path against the CPU oracle, through the C ABI.
+
+Bit-exact: stream bytes, quantization codes, outlier/correction flags, case
+indices, triangle lists and vertex positions.  Reconstructed values are
+compared bitwise as well (the tolerance of 1e-6 x range is not needed: both
+sides perform the same binary32 operations in the same order).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2408_05462_amd import api, inputs
+from paper_2408_05462_amd import _lib as L
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _field(kind, shape, seed):
+    rng = np.random.default_rng(seed)
+    if kind == "normal":
+        return rng.standard_normal(shape).astype(np.float32)
+    if kind == "smooth":
+        z, y, x = np.meshgrid(*[np.linspace(0, 3, n) for n in shape], indexing="ij")
+        return (np.sin(x + 0.3 * y) * np.cos(y - z) + 0.01 * rng.standard_normal(shape)).astype(np.float32)
+    if kind == "grf":
+        n = max(shape)
+        return np.ascontiguousarray(inputs.grf(n, 0.5)[: shape[0], : shape[1], : shape[2]])
+    raise KeyError(kind)
+
+
+CASES = [
+    # (kind, shape, levels, block, relative error bound, number of isovalues)
+    ("normal", (17, 23, 29), 3, 8, 3e-2, 2),
+    ("smooth", (33, 33, 33), 4, 16, 1e-3, 3),
+    ("grf", (40, 37, 70), 3, 4, 1e-2, 1),
+    ("grf", (64, 64, 64), 5, 64, 1e-3, 8),
+    ("smooth", (1, 30, 31), 2, 2, 1e-2, 1),
+    ("normal", (9, 1, 5), 1, 1, 0.1, 1),
+    ("normal", (65, 66, 67), 3, 32, 0.0, 1),     # lossless
+    ("smooth", (70, 65, 129), 6, 64, 5e-4, 16),  # partial blocks on every axis, 16 isovalues
+]
+
+
+def _run(kind, shape, nL, B, rel, nk, seed=0):
+    f = _field(kind, shape, seed)
+    e = inputs.abs_error_bound(rel, f)
+    isos = list(np.quantile(f, np.linspace(0.2, 0.8, nk)).astype(np.float32)) if nk else []
+    ref = oracle.compress(f, e, isos, levels=nL, block=B)
+    x = torch.from_numpy(f).to(DEV)
+    codes = torch.zeros(shape, dtype=torch.int32, device=DEV)
+    flags = torch.zeros(shape, dtype=torch.uint8, device=DEV)
+    c = api.compress(x, e, isos, levels=nL, block=B, codes=codes, flags=flags)
+    return f, e, isos, ref, x, c, codes, flags
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}-{'x'.join(map(str, c[1]))}-L{c[2]}-B{c[3]}")
+def test_compress_bitexact(case):
+    f, e, isos, ref, x, c, codes, flags = _run(*case)
+    print("case", case, flush=True)
+    assert np.array_equal(codes.cpu().numpy(), ref["q"])
+    assert np.array_equal(flags.cpu().numpy(), ref["flags"])
+    got = c.stream.cpu().numpy()
+    assert got.size == ref["stream"].size
+    assert np.array_equal(got, ref["stream"])
+    assert c.result["n_outlier"] == int((ref["flags"] & 1).sum())
+    assert c.result["n_corrected"] == int((ref["flags"] >> 1).sum())
+    assert c.result["vmin"] == f.min() and c.result["vmax"] == f.max()
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}-{'x'.join(map(str, c[1]))}-L{c[2]}-B{c[3]}")
+def test_reconstruct_bitexact_every_level(case):
+    f, e, isos, ref, x, c, codes, flags = _run(*case)
+    nL = case[2]
+    for l in range(nL):
+        y = api.reconstruct(c, l).cpu().numpy()
+        s = slice(None, None, 1 << l)
+        assert np.array_equal(y.view(np.uint32), ref["xr"][s, s, s].view(np.uint32)), l
+    # decoding the oracle's own stream on the GPU (independent of the GPU encoder)
+    s_dev = torch.from_numpy(ref["stream"]).to(DEV)
+    oc = api.Compressed(stream=s_dev, info=api.chr_stream_info(bytes(ref["stream"])), header=b"", result={})
+    y = api.reconstruct(oc, 0).cpu().numpy()
+    assert np.array_equal(y.view(np.uint32), ref["xr"].view(np.uint32))
+
+
+@pytest.mark.parametrize("seed,shape,k", [(0, (17, 23, 29), 0.1), (1, (64, 64, 64), -0.4), (2, (5, 70, 130), 0.0),
+                                          (3, (2, 2, 2), 0.0), (4, (31, 1, 40), 0.2), (5, (40, 33, 1), 0.2)])
+def test_mc_bitexact(seed, shape, k):
+    f = np.random.default_rng(seed).standard_normal(shape).astype(np.float32)
+    if seed == 3:
+        f[:] = [[[0.0, 1.0], [-1.0, 0.0]], [[1.0, -2.0], [0.5, -0.5]]]
+    print("mc", seed, shape, flush=True)
+    x = torch.from_numpy(f).to(DEV)
+    v, t = api.extract(x, k, spacing=2.0)
+    rv, rt, counts, rc = oracle.mc(f, k, spacing=2.0)
+    assert (v.shape[0], t.shape[0]) == counts
+    assert np.array_equal(v.cpu().numpy().view(np.uint32), rv.view(np.uint32))
+    assert np.array_equal(t.cpu().numpy(), rt)
+    if min(shape) > 1:
+        assert np.array_equal(api.cases(x, k).cpu().numpy(), oracle.mc_cases(f, k))
+
+
+def test_mc_capacity_reports_required_size():
+    f = np.random.default_rng(7).standard_normal((20, 20, 20)).astype(np.float32)
+    x = torch.from_numpy(f).to(DEV)
+    ws = torch.empty(api.iso_workspace(x.shape), dtype=torch.uint8, device=DEV)
+    counts = torch.zeros(2, dtype=torch.int64, device=DEV)
+    verts = torch.zeros((10, 3), dtype=torch.float32, device=DEV)
+    tris = torch.zeros((7, 3), dtype=torch.int32, device=DEV)
+    api.iso_extract(x, 0.0, 1.0, verts, tris, counts, ws)
+    torch.cuda.synchronize()
+    rv, rt, cnt, rc = oracle.mc(f, 0.0)
+    assert tuple(counts.cpu().tolist()) == cnt
+    assert np.array_equal(verts.cpu().numpy(), rv[:10])
+    assert np.array_equal(tris.cpu().numpy(), rt[:7])
+
+
+def test_gaussians64_end_to_end():
+    w = inputs.workload("gaussians64")
+    f = w["field"]
+    ref = oracle.compress(f, w["error_bound"], w["isovalues"], levels=w["levels"], block=w["block"])
+    x = torch.from_numpy(f).to(DEV)
+    c = api.compress(x, w["error_bound"], w["isovalues"], levels=w["levels"], block=w["block"])
+    assert np.array_equal(c.stream.cpu().numpy(), ref["stream"])
+    y = api.reconstruct(c, 0)
+    assert np.array_equal(y.cpu().numpy().view(np.uint32), ref["xr"].view(np.uint32))
+    k = w["isovalues"][0]
+    v, t = api.extract(y, k)
+    rv, rt, cnt, _ = oracle.mc(ref["xr"], k)
+    assert np.array_equal(v.cpu().numpy().view(np.uint32), rv.view(np.uint32))
+    assert np.array_equal(t.cpu().numpy(), rt)
+    # topology preserved: the reconstructed field gives the original's cases
+    assert np.array_equal(api.cases(y, k).cpu().numpy(), oracle.mc_cases(f, k))
+
+
+def test_device_status_nonfinite_and_capacity():
+    f = np.random.default_rng(1).standard_normal((16, 16, 16)).astype(np.float32)
+    f[3, 4, 5] = np.inf
+    x = torch.from_numpy(f).to(DEV)
+    with pytest.raises(L.ChrError) as ei:
+        api.compress(x, 0.01, [0.0], levels=3, block=8)
+    assert ei.value.code == L.CHR_E_INVAL
+    g = torch.from_numpy(np.random.default_rng(2).standard_normal((16, 16, 16)).astype(np.float32)).to(DEV)
+    p = api.params(3, 8)
+    ref = oracle.compress(g.cpu().numpy(), 0.01, [0.0], levels=3, block=8)
+    cap = len(ref["stream"]) - 64
+    out = torch.zeros(cap, dtype=torch.uint8, device=DEV)
+    res = torch.zeros(64, dtype=torch.uint8, device=DEV)
+    ws = torch.empty(api.chr_compress_workspace(g.shape, p), dtype=torch.uint8, device=DEV)
+    api.chr_compress(g, 0.01, [0.0], p, out, res, ws)
+    torch.cuda.synchronize()
+    r = api.read_result(res)
+    assert r["status"] == L.CHR_E_CAPACITY and r["stream_bytes"] == len(ref["stream"])
+
+
+def test_reconstruct_rejects_bad_requests_and_corruption():
+    f = np.random.default_rng(3).standard_normal((20, 20, 20)).astype(np.float32)
+    ref = oracle.compress(f, 0.05, [0.0], levels=3, block=8)
+    info = api.chr_stream_info(bytes(ref["stream"]))
+    s_dev = torch.from_numpy(ref["stream"]).to(DEV)
+    out = torch.empty((20, 20, 20), dtype=torch.float32, device=DEV)
+    st = torch.zeros(1, dtype=torch.int32, device=DEV)
+    ws = torch.empty(max(api.chr_reconstruct_workspace(info, 0), 256), dtype=torch.uint8, device=DEV)
+    with pytest.raises(L.ChrError) as ei:
+        api.chr_reconstruct(info, s_dev, 0, 0.01, out, st, ws)
+    assert ei.value.code == L.CHR_E_ACCURACY
+    with pytest.raises(L.ChrError) as ei:
+        api.chr_reconstruct(info, s_dev, 3, 0.05, out, st, ws)
+    assert ei.value.code == L.CHR_E_LEVEL
+    # a section header that disagrees with the geometry is caught on the device
+    bad = ref["stream"].copy()
+    off = int(np.frombuffer(bad[256:264].tobytes(), np.uint64)[0])
+    bad[off] ^= 0x01                       # npts of the first section
+    s_bad = torch.from_numpy(bad).to(DEV)
+    api.chr_reconstruct(info, s_bad, 0, 0.05, out, st, ws)
+    torch.cuda.synchronize()
+    assert int(st.item()) == L.CHR_E_CORRUPT
+
+
+def test_range():
+    f = np.random.default_rng(5).standard_normal((33, 17, 65)).astype(np.float32)
+    f[1, 2, 3] = np.nan
+    x = torch.from_numpy(f).to(DEV)
+    mn, mx, nf = api.field_range(x)
+    assert nf == 1 and mn == np.nanmin(f) and mx == np.nanmax(f)
