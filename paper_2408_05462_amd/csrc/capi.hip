@@ -101,7 +101,7 @@ uint32_t max_chunks(const Geo &g, int l) {
 }
 
 struct EncLayout {
-  size_t off_G, off_cnt, off_P, off_scan, off_pay, off_emask, off_exv, off_bstat, off_st, off_secsz, off_secoff,
+  size_t off_G, off_cnt, off_P, off_scan, off_pay, off_emask, off_exv, off_part, off_bst, off_secsz, off_secoff,
       off_scan64, total;
 };
 
@@ -135,8 +135,10 @@ EncLayout enc_layout(EncPlan &P) {
   Lo.off_pay = o; o = align256(o + sizeof(uint32_t) * 32 * (size_t)P.nslots);
   Lo.off_emask = o; o = align256(o + sizeof(uint64_t) * (size_t)P.nslots);
   Lo.off_exv = o; o = align256(o + sizeof(float) * 64 * (size_t)P.nslots);
-  Lo.off_bstat = o; o = align256(o + sizeof(uint32_t) * 2 * (size_t)g.nblocks);
-  Lo.off_st = o; o = align256(o + sizeof(Stats));
+  P.part_per_block = encode_fine_groups(P) + 1;
+  encode_pack_layout(P);
+  Lo.off_part = o; o = align256(o + sizeof(Part) * (size_t)(g.nblocks * P.part_per_block));
+  Lo.off_bst = o; o = align256(o + sizeof(Part) * (size_t)g.nblocks);
   Lo.off_secsz = o; o = align256(o + sizeof(uint64_t) * (size_t)nsec);
   Lo.off_secoff = o; o = align256(o + sizeof(uint64_t) * (size_t)(nsec + 1));
   Lo.off_scan64 = o; o = align256(o + sizeof(uint64_t) * (size_t)scan_tmp_elems(nsec));
@@ -299,8 +301,8 @@ int chr_compress(const float *d_field, const int64_t dims[3], double error_bound
   P.pay = reinterpret_cast<uint32_t *>(ws + Lo.off_pay);
   P.emask = reinterpret_cast<unsigned long long *>(ws + Lo.off_emask);
   P.exv = reinterpret_cast<float *>(ws + Lo.off_exv);
-  P.bstat = reinterpret_cast<uint32_t *>(ws + Lo.off_bstat);
-  P.st = reinterpret_cast<Stats *>(ws + Lo.off_st);
+  P.part = reinterpret_cast<Part *>(ws + Lo.off_part);
+  P.bst = reinterpret_cast<Part *>(ws + Lo.off_bst);
   P.secsz = reinterpret_cast<uint64_t *>(ws + Lo.off_secsz);
   P.secoff = reinterpret_cast<uint64_t *>(ws + Lo.off_secoff);
   P.out = static_cast<uint8_t *>(d_stream);

@@ -67,6 +67,38 @@ __host__ __device__ inline void block_ext(const Geo &g, int64_t b, int64_t o[3],
   }
 }
 
+// Division by a runtime constant d for dividends below 2^31: with
+// l = ceil(log2 d) and m = floor(2^(31+l)/d) + 1 (< 2^32), n/d equals
+// mulhi(n, m) >> (l-1) for every n < 2^31 (Granlund-Montgomery).
+struct FastDiv {
+  uint32_t d, m;
+  int sh;   // l - 1, or -1 when d == 1
+};
+
+__host__ __device__ inline FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f;
+  f.d = d;
+  int l = 0;
+  while (((uint64_t)1 << l) < (uint64_t)d) l++;
+  if (l == 0) {
+    f.m = 0;
+    f.sh = -1;
+  } else {
+    f.m = (uint32_t)((((uint64_t)1) << (31 + l)) / d + 1);
+    f.sh = l - 1;
+  }
+  return f;
+}
+
+__host__ __device__ inline uint32_t fdiv(uint32_t n, const FastDiv &f) {
+  if (f.sh < 0) return n;
+#ifdef __HIP_DEVICE_COMPILE__
+  return __umulhi(n, f.m) >> f.sh;
+#else
+  return (uint32_t)(((uint64_t)n * f.m) >> 32) >> f.sh;
+#endif
+}
+
 // Level-l section of one closed block: the points of the block's 2^l grid
 // that are not on its 2^(l+1) grid (all of them at the top level), visited in
 // lexicographic (z, y, x) order.  Local grid index (w, v, u) -> coordinate
@@ -77,6 +109,7 @@ struct Sec {
   uint32_t Pe, Po;       // points in an even / odd plane
   uint32_t npts;
   int top;
+  FastDiv d_pair, d_rp, d_mx, d_my;
 };
 
 __host__ __device__ inline Sec sec_geom(const int64_t o[3], const int64_t hi[3], int l, int L) {
@@ -95,29 +128,34 @@ __host__ __device__ inline Sec sec_geom(const int64_t o[3], const int64_t hi[3],
     s.Po = s.my * s.mx;
     s.npts = s.mz * s.my * s.mx - cz * cy * cx;
   }
+  s.d_pair = make_fastdiv(s.Pe + s.Po);
+  s.d_rp = make_fastdiv(s.rowE + s.mx);
+  s.d_mx = make_fastdiv(s.mx);
+  s.d_my = make_fastdiv(s.my);
   return s;
 }
 
 __host__ __device__ inline void sec_point(const Sec &s, uint32_t j, uint32_t &w, uint32_t &v, uint32_t &u) {
   if (s.top) {
-    u = j % s.mx;
-    uint32_t t = j / s.mx;
-    v = t % s.my;
-    w = t / s.my;
+    const uint32_t t = fdiv(j, s.d_mx);
+    u = j - t * s.mx;
+    w = fdiv(t, s.d_my);
+    v = t - w * s.my;
     return;
   }
-  uint32_t pair = s.Pe + s.Po;
-  uint32_t w2 = j / pair, r = j - w2 * pair;
+  const uint32_t pair = s.Pe + s.Po;
+  const uint32_t w2 = fdiv(j, s.d_pair);
+  uint32_t r = j - w2 * pair;
   if (r < s.Pe) {
     w = 2 * w2;
-    uint32_t RP = s.rowE + s.mx;
-    uint32_t v2 = r / RP, t = r - v2 * RP;
+    const uint32_t RP = s.rowE + s.mx;
+    const uint32_t v2 = fdiv(r, s.d_rp), t = r - v2 * RP;
     if (t < s.rowE) { v = 2 * v2; u = 2 * t + 1; }
     else { v = 2 * v2 + 1; u = t - s.rowE; }
   } else {
     r -= s.Pe;
     w = 2 * w2 + 1;
-    v = r / s.mx;
+    v = fdiv(r, s.d_mx);
     u = r - v * s.mx;
   }
 }

@@ -8,12 +8,12 @@ namespace chr {
 
 constexpr int kMaxLevels = 16;
 
-// Device-side statistics of one compression.
-struct Stats {
-  uint32_t xmin_ord, xmax_ord;   // range of the input (ordered images)
-  uint32_t nonfinite;
-  uint32_t pad;
-  unsigned long long n_outlier, n_corrected;
+// Statistics of the points one workgroup encoded (ordered images of
+// binary32 values; counts cover the points the block owns).
+struct Part {
+  uint32_t rmin, rmax;   // reconstructed values (block index)
+  uint32_t xmin, xmax;   // input values (header range)
+  uint32_t nonfinite, nO, nC, pad;
 };
 
 // Compression: per-level chunk slots hold one 64-point chunk each before the
@@ -34,8 +34,11 @@ struct EncPlan {
   uint32_t *pay;                 // nslots * 32 words
   unsigned long long *emask;     // nslots
   float *exv;                    // nslots * 64
-  uint32_t *bstat;               // nblocks * 2 ordered min/max of reconstructed values
-  Stats *st;
+  Part *part;                    // per block: part_per_block workgroup records
+  int64_t part_per_block;        // level-0 workgroups per block + 1 (coarse levels)
+  Part *bst;                     // per block reduction of its records
+  int64_t pack_base[kMaxLevels]; // first packing workgroup of each level
+  int64_t pack_gpb[kMaxLevels];  // packing workgroups per block and level
   uint64_t *secsz, *secoff;      // nblocks*nL (+1)
   uint8_t *out;
   void *result;                  // chr_result*
@@ -77,6 +80,8 @@ void prof_mark(const char *kernel, hipStream_t s, int end);
 // launchers (encode.hip, decode.hip, mc.hip)
 void launch_encode(const EncPlan &p, int64_t scan_tmp_elems_u4, U4 *scan_tmp, uint64_t *scan_tmp64,
                    hipStream_t s);
+int64_t encode_fine_groups(const EncPlan &p);   // level-0 workgroups per block
+void encode_pack_layout(EncPlan &p);            // fills pack_base / pack_gpb
 void launch_decode(const DecPlan &p, hipStream_t s);
 void launch_mc(const McPlan &p, U4 *scan_tmp, hipStream_t s);
 void launch_mc_cases(const McPlan &p, hipStream_t s);

@@ -21,19 +21,20 @@ constexpr int kWaves = kBS / kWave;
 __device__ inline float avg2(float a, float b) { return __fmul_rn(__fadd_rn(a, b), 0.5f); }
 
 // Same prediction as compression (multilinear midpoints from the coarser
-// compact grid, x then y then z, lower parent alone at the domain edge).
-__device__ inline float predict(const float *__restrict__ Gp, const int64_t gd[3], int l, int64_t z,
-                                int64_t y, int64_t x) {
+// compact grid of dims g0 x g1 x g2, x then y then z, lower parent alone at
+// the domain edge).
+__device__ inline float predict(const float *__restrict__ Gp, uint32_t g0, uint32_t g1, uint32_t g2, int l,
+                                uint32_t z, uint32_t y, uint32_t x) {
   const int sh = l + 1;
-  const int oz = (int)((z >> l) & 1), oy = (int)((y >> l) & 1), ox = (int)((x >> l) & 1);
-  const int64_t zl = (z - ((int64_t)oz << l)) >> sh;
-  const int64_t yl = (y - ((int64_t)oy << l)) >> sh;
-  const int64_t xl = (x - ((int64_t)ox << l)) >> sh;
-  const bool zu = oz && (zl + 1 < gd[0]);
-  const bool yu = oy && (yl + 1 < gd[1]);
-  const bool xu = ox && (xl + 1 < gd[2]);
-  auto row = [&](int64_t zi, int64_t yi) {
-    const float *r = Gp + (zi * gd[1] + yi) * gd[2];
+  const uint32_t oz = (z >> l) & 1u, oy = (y >> l) & 1u, ox = (x >> l) & 1u;
+  const uint32_t zl = (z - (oz << l)) >> sh;
+  const uint32_t yl = (y - (oy << l)) >> sh;
+  const uint32_t xl = (x - (ox << l)) >> sh;
+  const bool zu = oz && (zl + 1 < g0);
+  const bool yu = oy && (yl + 1 < g1);
+  const bool xu = ox && (xl + 1 < g2);
+  auto row = [&](uint32_t zi, uint32_t yi) {
+    const float *r = Gp + ((size_t)zi * g1 + yi) * g2;
     float a = r[xl];
     if (xu) a = avg2(a, r[xl + 1]);
     return a;
@@ -125,6 +126,7 @@ __device__ void dec_tile(const DecPlan &D, const SecView &v, int l, const int64_
   }
   const uint32_t nc = min(64u, v.nch - t * 64);
   const float *Gp = (l < L) ? D.gp[l + 1] : nullptr;
+  const uint32_t g0 = (uint32_t)D.gd[l + 1][0], g1 = (uint32_t)D.gd[l + 1][1], g2 = (uint32_t)D.gd[l + 1][2];
   for (uint32_t k = 0; k < nc; k++) {
     const uint32_t wk = rl32(w, (int)k), wok = rl32(wo, (int)k), xok = rl32(xo, (int)k);
     const uint64_t emk = rl64(em, (int)k);
@@ -141,12 +143,12 @@ __device__ void dec_tile(const DecPlan &D, const SecView &v, int l, const int64_
     }
     uint32_t ww, vv, uu;
     sec_point(s, j, ww, vv, uu);
-    const int64_t z = o[0] + ((int64_t)ww << l), y = o[1] + ((int64_t)vv << l), x = o[2] + ((int64_t)uu << l);
+    const uint32_t z = (uint32_t)o[0] + (ww << l), y = (uint32_t)o[1] + (vv << l), x = (uint32_t)o[2] + (uu << l);
     float r;
     if ((emk >> lane) & 1ull) {
       r = __uint_as_float(ld32(v.p + v.Xoff + 4 * ((uint64_t)xok + lanes_below(emk))));
     } else {
-      const float p = (l == L) ? 0.0f : predict(Gp, D.gd[l + 1], l, z, y, x);
+      const float p = (l == L) ? 0.0f : predict(Gp, g0, g1, g2, l, z, y, x);
       const int32_t q = (int32_t)(zc >> 1) ^ -(int32_t)(zc & 1u);
       r = g.lossless ? p : __fadd_rn(p, __fmul_rn((float)q, g.step));
     }
@@ -182,8 +184,8 @@ __global__ __launch_bounds__(kBS) void k_decode_coarse(DecPlan D) {
       if (threadIdx.x == 0) set_status(D, -4);
     } else {
       for (uint32_t t = wave; t < v.ntile; t += kWaves)
-        dec_tile(D, v, l, o, s, t, [&](int64_t z, int64_t y, int64_t x, float r) {
-          dst[((z >> l) * gd[1] + (y >> l)) * gd[2] + (x >> l)] = r;
+        dec_tile(D, v, l, o, s, t, [&](uint32_t z, uint32_t y, uint32_t x, float r) {
+          dst[((size_t)(z >> l) * (uint32_t)gd[1] + (y >> l)) * (uint32_t)gd[2] + (x >> l)] = r;
         });
     }
     __syncthreads();
@@ -214,13 +216,13 @@ __global__ __launch_bounds__(kBS) void k_decode_fine(DecPlan D) {
   const float *G1 = (L >= 1) ? D.gp[1] : nullptr;
   const int64_t *gd1 = D.gd[1];
   float *out = D.out;
-  dec_tile(D, v, 0, o, s, t, [&](int64_t z, int64_t y, int64_t x, float r) {
+  dec_tile(D, v, 0, o, s, t, [&](uint32_t z, uint32_t y, uint32_t x, float r) {
     if (z >= ez || y >= ey) return;
-    float *row = out + (z * n1 + y) * n2;
+    float *row = out + ((size_t)z * (uint32_t)n1 + y) * (uint32_t)n2;
     if (x < ex) row[x] = r;
-    if (L >= 1 && !((z | y) & 1) && (x & 1)) {
+    if (L >= 1 && !((z | y) & 1u) && (x & 1u)) {
       // even row of an even plane: the neighbouring even points come from level 1
-      const float *g1 = G1 + ((z >> 1) * gd1[1] + (y >> 1)) * gd1[2];
+      const float *g1 = G1 + ((size_t)(z >> 1) * (uint32_t)gd1[1] + (y >> 1)) * (uint32_t)gd1[2];
       row[x - 1] = g1[(x - 1) >> 1];
       if (x + 1 == hi[2] && hi[2] == g.n[2] - 1) row[x + 1] = g1[(x + 1) >> 1];
     }

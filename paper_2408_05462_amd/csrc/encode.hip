@@ -6,7 +6,9 @@
 // side of every candidate isovalue (Sec. II.B: topology preservation) and, if
 // either check fails, stores the point exactly.  The chunk's zigzag codes are
 // bit-packed at the wave's maximum width through LDS, exact points are
-// compacted with a ballot and mbcnt.
+// compacted with a ballot and mbcnt.  Statistics (block min/max, counts) are
+// reduced per workgroup into a record of their own -- no atomics -- and
+// folded per block and per stream by the table and header kernels.
 //
 // Launch sequence: coarse levels (one workgroup per block, levels nL-1..1,
 // each level's compact grid written before the next level reads it) ->
@@ -21,26 +23,27 @@ namespace {
 constexpr int kBS = 256;
 constexpr int kWaves = kBS / kWave;
 constexpr int kChunksPerWave = 4;
+constexpr int kChunksPerWG = kWaves * kChunksPerWave;
 
 __device__ inline float avg2(float a, float b) { return __fmul_rn(__fadd_rn(a, b), 0.5f); }
 
 // Multilinear midpoint prediction of point (z,y,x) of level l from the
-// compact grid Gp of level l+1 (dims gd): along each axis where the
+// compact grid Gp of level l+1 (dims g0 x g1 x g2): along each axis where the
 // coordinate is an odd multiple of 2^l the two parents at -2^l and +2^l are
 // averaged (the lower one alone if the upper one is outside the domain);
 // averages along x first, then y, then z.
-__device__ inline float predict(const float *__restrict__ Gp, const int64_t gd[3], int l, int64_t z,
-                                int64_t y, int64_t x) {
+__device__ inline float predict(const float *__restrict__ Gp, uint32_t g0, uint32_t g1, uint32_t g2, int l,
+                                uint32_t z, uint32_t y, uint32_t x) {
   const int sh = l + 1;
-  const int oz = (int)((z >> l) & 1), oy = (int)((y >> l) & 1), ox = (int)((x >> l) & 1);
-  const int64_t zl = (z - ((int64_t)oz << l)) >> sh;
-  const int64_t yl = (y - ((int64_t)oy << l)) >> sh;
-  const int64_t xl = (x - ((int64_t)ox << l)) >> sh;
-  const bool zu = oz && (zl + 1 < gd[0]);
-  const bool yu = oy && (yl + 1 < gd[1]);
-  const bool xu = ox && (xl + 1 < gd[2]);
-  auto row = [&](int64_t zi, int64_t yi) {
-    const float *r = Gp + (zi * gd[1] + yi) * gd[2];
+  const uint32_t oz = (z >> l) & 1u, oy = (y >> l) & 1u, ox = (x >> l) & 1u;
+  const uint32_t zl = (z - (oz << l)) >> sh;
+  const uint32_t yl = (y - (oy << l)) >> sh;
+  const uint32_t xl = (x - (ox << l)) >> sh;
+  const bool zu = oz && (zl + 1 < g0);
+  const bool yu = oy && (yl + 1 < g1);
+  const bool xu = ox && (xl + 1 < g2);
+  auto row = [&](uint32_t zi, uint32_t yi) {
+    const float *r = Gp + ((size_t)zi * g1 + yi) * g2;
     float a = r[xl];
     if (xu) a = avg2(a, r[xl + 1]);
     return a;
@@ -84,37 +87,36 @@ __device__ inline int rank_of(const Geo &g, float v) {
   return r;
 }
 
-struct Acc {
-  uint32_t rmin, rmax;   // reconstructed values (block index)
-  uint32_t xmin, xmax;   // input values (header range)
-  uint32_t nonfinite;
-  uint32_t nO, nC;       // owned points only
-  __device__ void init() { rmin = xmin = 0xffffffffu; rmax = xmax = 0u; nonfinite = 0; nO = nC = 0; }
-};
-
-__device__ inline bool owned(const Geo &g, const int64_t o[3], int64_t z, int64_t y, int64_t x) {
-  return (z < o[0] + g.B || z == g.n[0] - 1) && (y < o[1] + g.B || y == g.n[1] - 1) &&
-         (x < o[2] + g.B || x == g.n[2] - 1);
+__device__ inline void part_init(Part &a) {
+  a.rmin = a.xmin = 0xffffffffu;
+  a.rmax = a.xmax = 0u;
+  a.nonfinite = a.nO = a.nC = a.pad = 0;
 }
 
-__device__ void flush(const EncPlan &P, int64_t b, Acc &a) {
-  uint32_t rmin = wave_min_u(a.rmin), rmax = wave_max_u(a.rmax);
-  uint32_t xmin = wave_min_u(a.xmin), xmax = wave_max_u(a.xmax);
-  uint32_t nf = wave_or(a.nonfinite), nO = wave_sum_u(a.nO), nC = wave_sum_u(a.nC);
-  if (lane_id() == 0) {
-    if (rmin != 0xffffffffu) atomicMin(&P.bstat[2 * b], rmin);
-    if (rmax != 0u) atomicMax(&P.bstat[2 * b + 1], rmax);
-    if (xmin != 0xffffffffu) atomicMin(&P.st->xmin_ord, xmin);
-    if (xmax != 0u) atomicMax(&P.st->xmax_ord, xmax);
-    if (nf) atomicOr(&P.st->nonfinite, nf);
-    if (nO) atomicAdd(&P.st->n_outlier, (unsigned long long)nO);
-    if (nC) atomicAdd(&P.st->n_corrected, (unsigned long long)nC);
+// Reduces the threads' records of one workgroup and stores it at *dst.
+__device__ void part_store(const Part &a, Part *dst) {
+  __shared__ Part red[kWaves];
+  Part r;
+  r.rmin = wave_min_u(a.rmin); r.rmax = wave_max_u(a.rmax);
+  r.xmin = wave_min_u(a.xmin); r.xmax = wave_max_u(a.xmax);
+  r.nonfinite = wave_or(a.nonfinite); r.nO = wave_sum_u(a.nO); r.nC = wave_sum_u(a.nC);
+  r.pad = 0;
+  if (lane_id() == 0) red[threadIdx.x / kWave] = r;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Part t = red[0];
+    for (int i = 1; i < kWaves; i++) {
+      t.rmin = min(t.rmin, red[i].rmin); t.rmax = max(t.rmax, red[i].rmax);
+      t.xmin = min(t.xmin, red[i].xmin); t.xmax = max(t.xmax, red[i].xmax);
+      t.nonfinite |= red[i].nonfinite; t.nO += red[i].nO; t.nC += red[i].nC;
+    }
+    *dst = t;
   }
 }
 
 // Encodes chunk c of the level-l section of block b into its slot.
-__device__ void enc_chunk(const EncPlan &P, int l, int64_t b, const int64_t o[3], const Sec &s, uint32_t c,
-                          uint32_t *pack, Acc &acc) {
+__device__ void enc_chunk(const EncPlan &P, int l, int64_t b, const int64_t o[3], const int64_t own[3],
+                          const Sec &s, uint32_t c, uint32_t *pack, Part &acc) {
   const Geo &g = P.g;
   const int L = g.nL - 1;
   const int lane = lane_id();
@@ -126,19 +128,26 @@ __device__ void enc_chunk(const EncPlan &P, int l, int64_t b, const int64_t o[3]
   if (valid) {
     uint32_t w, v, u;
     sec_point(s, j, w, v, u);
-    const int64_t z = o[0] + ((int64_t)w << l), y = o[1] + ((int64_t)v << l), xx = o[2] + ((int64_t)u << l);
-    const int64_t gi = (z * g.n[1] + y) * g.n[2] + xx;
+    const uint32_t z = (uint32_t)o[0] + (w << l), y = (uint32_t)o[1] + (v << l), xx = (uint32_t)o[2] + (u << l);
+    const size_t gi = ((size_t)z * (uint32_t)g.n[1] + y) * (uint32_t)g.n[2] + xx;
     x = P.x[gi];
-    const float p = (l == L) ? 0.0f : predict(P.G + P.g_off[l + 1], P.gd[l + 1], l, z, y, xx);
+    float p = 0.0f;
+    if (l < L) {
+      const int64_t *gd = P.gd[l + 1];
+      p = predict(P.G + P.g_off[l + 1], (uint32_t)gd[0], (uint32_t)gd[1], (uint32_t)gd[2], l, z, y, xx);
+    }
     quantize(g, x, p, q, O, xr);
     if (!O && g.K > 0) C = rank_of(g, x) != rank_of(g, xr);
     if (O || C) { xr = x; q = 0; }
-    if (l >= 1) P.G[P.g_off[l] + ((z >> l) * P.gd[l][1] + (y >> l)) * P.gd[l][2] + (xx >> l)] = xr;
+    if (l >= 1) {
+      const int64_t *gd = P.gd[l];
+      P.G[P.g_off[l] + ((size_t)(z >> l) * (uint32_t)gd[1] + (y >> l)) * (uint32_t)gd[2] + (xx >> l)] = xr;
+    }
     const uint32_t ro = ord_of(xr), xo = ord_of(x);
     acc.rmin = min(acc.rmin, ro); acc.rmax = max(acc.rmax, ro);
     acc.xmin = min(acc.xmin, xo); acc.xmax = max(acc.xmax, xo);
     acc.nonfinite |= !isfinite(x);
-    if (owned(g, o, z, y, xx)) { acc.nO += O; acc.nC += C; }
+    if (z < own[0] && y < own[1] && xx < own[2]) { acc.nO += O; acc.nC += C; }
     if (P.codes) P.codes[gi] = q;
     if (P.flags) P.flags[gi] = (uint8_t)(O | (C << 1));
   }
@@ -174,14 +183,10 @@ __device__ inline void zero_slot(const EncPlan &P, int l, int64_t b, uint32_t c)
   if (lane_id() == 0) P.cnt[P.slot_base[l] + b * (int64_t)P.maxch[l] + c] = U4{0, 0, 0, 0};
 }
 
-__global__ __launch_bounds__(kBS) void k_init(EncPlan P) {
-  const int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x;
-  if (i < P.g.nblocks) { P.bstat[2 * i] = 0xffffffffu; P.bstat[2 * i + 1] = 0u; }
-  if (i == 0) {
-    P.st->xmin_ord = 0xffffffffu; P.st->xmax_ord = 0u; P.st->nonfinite = 0; P.st->pad = 0;
-    P.st->n_outlier = 0; P.st->n_corrected = 0;
-    P.P[P.nslots] = U4{0, 0, 0, 0};
-  }
+// First coordinate past the points block b owns along each axis: the upper
+// face belongs to the next block unless it is the domain's last plane.
+__device__ inline void owned_end(const Geo &g, const int64_t o[3], int64_t own[3]) {
+  for (int a = 0; a < 3; a++) own[a] = (o[a] + g.B < g.n[a] - 1) ? o[a] + g.B : g.n[a];
 }
 
 // Levels nL-1 .. 1 of one block per workgroup.
@@ -191,10 +196,11 @@ __global__ __launch_bounds__(kBS) void k_encode_coarse(EncPlan P) {
   const int L = g.nL - 1;
   const int64_t b = blockIdx.x;
   const int wave = threadIdx.x / kWave;
-  int64_t o[3], hi[3];
+  int64_t o[3], hi[3], own[3];
   block_ext(g, b, o, hi);
-  Acc acc;
-  acc.init();
+  owned_end(g, o, own);
+  Part acc;
+  part_init(acc);
   for (int l = L; l >= 1; l--) {
     if (l < L) {
       // the block's points of the coarser grid carry over unchanged
@@ -212,12 +218,12 @@ __global__ __launch_bounds__(kBS) void k_encode_coarse(EncPlan P) {
     const Sec s = sec_geom(o, hi, l, L);
     const uint32_t nch = (s.npts + 63) / 64;
     for (uint32_t c = wave; c < P.maxch[l]; c += kWaves) {
-      if (c < nch) enc_chunk(P, l, b, o, s, c, pack[wave], acc);
+      if (c < nch) enc_chunk(P, l, b, o, own, s, c, pack[wave], acc);
       else zero_slot(P, l, b, c);
     }
     __syncthreads();
   }
-  flush(P, b, acc);
+  part_store(acc, &P.part[b * P.part_per_block + (P.part_per_block - 1)]);
 }
 
 // Level 0: a 2D grid of (chunk groups, blocks).
@@ -227,19 +233,20 @@ __global__ __launch_bounds__(kBS) void k_encode_fine(EncPlan P) {
   const int L = g.nL - 1;
   const int64_t b = blockIdx.y;
   const int wave = threadIdx.x / kWave;
-  int64_t o[3], hi[3];
+  int64_t o[3], hi[3], own[3];
   block_ext(g, b, o, hi);
+  owned_end(g, o, own);
   const Sec s = sec_geom(o, hi, 0, L);
   const uint32_t nch = (s.npts + 63) / 64;
-  Acc acc;
-  acc.init();
+  Part acc;
+  part_init(acc);
   for (int k = 0; k < kChunksPerWave; k++) {
     const uint32_t c = (blockIdx.x * kChunksPerWave + k) * kWaves + wave;
     if (c >= P.maxch[0]) break;
-    if (c < nch) enc_chunk(P, 0, b, o, s, c, pack[wave], acc);
+    if (c < nch) enc_chunk(P, 0, b, o, own, s, c, pack[wave], acc);
     else zero_slot(P, 0, b, c);
   }
-  flush(P, b, acc);
+  part_store(acc, &P.part[b * P.part_per_block + blockIdx.x]);
 }
 
 // Byte size of every section from the scanned chunk sizes.
@@ -306,44 +313,52 @@ __global__ __launch_bounds__(kBS) void k_sec_table(EncPlan P) {
   for (uint64_t i = Xend; i < end; i++) put8(P, so + i, 0);
 }
 
-// Copies every chunk from its slot into its place in the stream.
+// Copies chunks from their slots into the stream; one workgroup per
+// (level, block, group of kChunksPerWG chunks).  Levels are laid out from the
+// coarsest (first workgroups) to level 0.
 __global__ __launch_bounds__(kBS) void k_pack(EncPlan P) {
   const Geo &g = P.g;
   const int L = g.nL - 1;
   const int lane = lane_id();
-  const int64_t slot = (int64_t)blockIdx.x * kWaves + threadIdx.x / kWave;
-  if (slot >= P.nslots) return;
-  int l = 0;
-  for (int t = 0; t <= L; t++)
-    if (slot >= P.slot_base[t] && slot < P.slot_base[t] + g.nblocks * (int64_t)P.maxch[t]) l = t;
-  const int64_t rel = slot - P.slot_base[l];
-  const int64_t b = rel / P.maxch[l];
-  const uint32_t c = (uint32_t)(rel % P.maxch[l]);
+  const int wave = threadIdx.x / kWave;
+  const int64_t wg = blockIdx.x;
+  int l = L;
+  for (int t = L - 1; t >= 0; t--)
+    if (wg >= P.pack_base[t]) l = t;
+  const int64_t rel = wg - P.pack_base[l];
+  const int64_t b = rel / P.pack_gpb[l];
+  const uint32_t grp = (uint32_t)(rel % P.pack_gpb[l]);
   int64_t o[3], hi[3];
   block_ext(g, b, o, hi);
   const Sec s = sec_geom(o, hi, l, L);
   const uint32_t nch = (s.npts + 63) / 64;
-  if (c >= nch) return;
   const uint32_t ntile = (nch + 63) / 64;
   const int64_t s0 = P.slot_base[l] + b * (int64_t)P.maxch[l];
-  const U4 a = P.P[s0], e = P.P[s0 + nch], cur = P.P[slot], cc = P.cnt[slot];
+  const U4 a = P.P[s0], e = P.P[s0 + nch];
   const uint32_t W = e.x - a.x, NE = e.y - a.y;
-  const uint32_t pw = cur.x - a.x, pe = cur.y - a.y, px = cur.z - a.z;
   const uint64_t so = P.payload_off + P.secoff[b * g.nL + (L - l)];
   const uint64_t A = 16 + pad8(12 * (uint64_t)ntile), Poff = A + pad8(nch);
   const uint64_t Moff = Poff + 8 * (uint64_t)W, Xoff = Moff + 8 * (uint64_t)NE;
-  if (lane == 0) {
-    if (c % 64 == 0) {
-      const uint64_t t = so + 16 + 12 * (uint64_t)(c / 64);
-      put32(P, t, pw);
-      put32(P, t + 4, pe);
-      put32(P, t + 8, px);
+  for (int k = 0; k < kChunksPerWave; k++) {
+    const uint32_t c = grp * kChunksPerWG + k * kWaves + wave;
+    if (c >= nch) break;
+    const int64_t slot = s0 + c;
+    const U4 cur = P.P[slot], cc = P.cnt[slot];
+    const uint32_t pw = cur.x - a.x, pe = cur.y - a.y, px = cur.z - a.z;
+    if (lane == 0) {
+      if (c % 64 == 0) {
+        const uint64_t t = so + 16 + 12 * (uint64_t)(c / 64);
+        put32(P, t, pw);
+        put32(P, t + 4, pe);
+        put32(P, t + 8, px);
+      }
+      put8(P, so + A + c, (uint8_t)(cc.x | (cc.y ? 0x80u : 0u)));
+      if (cc.y) put64(P, so + Moff + 8 * (uint64_t)pe, P.emask[slot]);
     }
-    put8(P, so + A + c, (uint8_t)(cc.x | (cc.y ? 0x80u : 0u)));
-    if (cc.y) put64(P, so + Moff + 8 * (uint64_t)pe, P.emask[slot]);
+    if (lane < 2 * (int)cc.x) put32(P, so + Poff + 8 * (uint64_t)pw + 4 * lane, P.pay[slot * 32 + lane]);
+    if (lane < (int)cc.z)
+      put32(P, so + Xoff + 4 * ((uint64_t)px + lane), __float_as_uint(P.exv[slot * 64 + lane]));
   }
-  if (lane < 2 * (int)cc.x) put32(P, so + Poff + 8 * (uint64_t)pw + 4 * lane, P.pay[slot * 32 + lane]);
-  if (lane < (int)cc.z) put32(P, so + Xoff + 4 * ((uint64_t)px + lane), __float_as_uint(P.exv[slot * 64 + lane]));
 }
 
 __device__ inline uint32_t get32(const EncPlan &P, uint64_t off) {
@@ -362,9 +377,9 @@ __device__ uint32_t block_sum(uint32_t v) {
   return t;
 }
 
-// Block table: min/max of the block's reconstructed values and the checksum
-// of its byte range.
-__global__ __launch_bounds__(kBS) void k_block_table(EncPlan P) {
+// Block table: folds the block's workgroup records (min/max of the
+// reconstructed values, input range, counts) and checksums its byte range.
+__global__ __launch_bounds__(kBS) void k_block_table(EncPlan P, int64_t nfine, int has_coarse) {
   const Geo &g = P.g;
   const int64_t b = blockIdx.x;
   const uint64_t total = P.payload_off + P.secoff[g.nblocks * g.nL];
@@ -376,10 +391,22 @@ __global__ __launch_bounds__(kBS) void k_block_table(EncPlan P) {
     for (uint64_t j = threadIdx.x; j < (end - start) / 4; j += kBS)
       sum += fmix32(get32(P, start + 4 * j) ^ (uint32_t)((uint32_t)j * 0x9E3779B9u));
   sum = block_sum<kBS>(sum);
+  Part acc;
+  part_init(acc);
+  const Part *rec = P.part + b * P.part_per_block;
+  for (int64_t i = threadIdx.x; i < nfine + (has_coarse ? 1 : 0); i += kBS) {
+    const Part r = rec[i < nfine ? i : P.part_per_block - 1];
+    acc.rmin = min(acc.rmin, r.rmin); acc.rmax = max(acc.rmax, r.rmax);
+    acc.xmin = min(acc.xmin, r.xmin); acc.xmax = max(acc.xmax, r.xmax);
+    acc.nonfinite |= r.nonfinite; acc.nO += r.nO; acc.nC += r.nC;
+  }
+  part_store(acc, &P.bst[b]);
+  __syncthreads();
   if (threadIdx.x == 0) {
+    const Part t = P.bst[b];
     const uint64_t bt = kHeaderBytes + 16 * (uint64_t)g.nblocks * g.nL + 16 * (uint64_t)b;
-    put32(P, bt, __float_as_uint(of_ord(P.bstat[2 * b])));
-    put32(P, bt + 4, __float_as_uint(of_ord(P.bstat[2 * b + 1])));
+    put32(P, bt, __float_as_uint(of_ord(t.rmin)));
+    put32(P, bt + 4, __float_as_uint(of_ord(t.rmax)));
     put32(P, bt + 8, sum);
     put32(P, bt + 12, 0);
   }
@@ -394,16 +421,36 @@ struct ResultDev {
 
 // Stream header, table checksum, header checksum, and the result record.
 __global__ __launch_bounds__(kBS) void k_header(EncPlan P) {
+  __shared__ uint32_t red[kWaves][3];
+  __shared__ unsigned long long redc[kWaves][2];
   const Geo &g = P.g;
   const uint64_t total = P.payload_off + P.secoff[g.nblocks * g.nL];
   const bool fits = total <= P.cap;
+  uint32_t xmin = 0xffffffffu, xmax = 0u, nf = 0u;
+  unsigned long long nO = 0, nC = 0;
+  for (int64_t b = threadIdx.x; b < g.nblocks; b += kBS) {
+    const Part t = P.bst[b];
+    xmin = min(xmin, t.xmin); xmax = max(xmax, t.xmax); nf |= t.nonfinite;
+    nO += t.nO; nC += t.nC;
+  }
+  xmin = wave_min_u(xmin); xmax = wave_max_u(xmax); nf = wave_or(nf);
+  for (int m = 32; m >= 1; m >>= 1) { nO += __shfl_xor(nO, m, kWave); nC += __shfl_xor(nC, m, kWave); }
+  if (lane_id() == 0) {
+    red[threadIdx.x / kWave][0] = xmin; red[threadIdx.x / kWave][1] = xmax; red[threadIdx.x / kWave][2] = nf;
+    redc[threadIdx.x / kWave][0] = nO; redc[threadIdx.x / kWave][1] = nC;
+  }
+  __syncthreads();
   uint32_t sum = 0;
   if (fits)
     for (uint64_t j = threadIdx.x; j < (P.payload_off - kHeaderBytes) / 4; j += kBS)
       sum += fmix32(get32(P, kHeaderBytes + 4 * j) ^ (uint32_t)((uint32_t)j * 0x9E3779B9u));
   sum = block_sum<kBS>(sum);
   if (threadIdx.x != 0) return;
-  const float vmin = of_ord(P.st->xmin_ord), vmax = of_ord(P.st->xmax_ord);
+  for (int i = 1; i < kWaves; i++) {
+    red[0][0] = min(red[0][0], red[i][0]); red[0][1] = max(red[0][1], red[i][1]); red[0][2] |= red[i][2];
+    redc[0][0] += redc[i][0]; redc[0][1] += redc[i][1];
+  }
+  const float vmin = of_ord(red[0][0]), vmax = of_ord(red[0][1]);
   if (fits) {
     for (int i = 0; i < kHeaderBytes; i += 4) put32(P, i, 0u);
     put32(P, 0, kMagic);
@@ -425,8 +472,8 @@ __global__ __launch_bounds__(kBS) void k_header(EncPlan P) {
     for (int a = 0; a < 3; a++) put32(P, 144 + 4 * a, (uint32_t)g.nb[a]);
     put32(P, 156, g.lossless ? 1u : 0u);
     put64(P, 160, total);
-    put64(P, 168, P.st->n_outlier);
-    put64(P, 176, P.st->n_corrected);
+    put64(P, 168, redc[0][0]);
+    put64(P, 176, redc[0][1]);
     put64(P, 184, P.payload_off);
     put32(P, 248, sum);
     uint32_t hs = 0;
@@ -435,9 +482,9 @@ __global__ __launch_bounds__(kBS) void k_header(EncPlan P) {
   }
   ResultDev *r = reinterpret_cast<ResultDev *>(P.result);
   r->stream_bytes = total;
-  r->n_outlier = P.st->n_outlier;
-  r->n_corrected = P.st->n_corrected;
-  r->status = P.st->nonfinite ? -1 : (fits ? 0 : -5);
+  r->n_outlier = redc[0][0];
+  r->n_corrected = redc[0][1];
+  r->status = red[0][2] ? -1 : (fits ? 0 : -5);
   r->vmin = vmin;
   r->vmax = vmax;
   r->reserved = 0;
@@ -445,23 +492,33 @@ __global__ __launch_bounds__(kBS) void k_header(EncPlan P) {
 
 }  // namespace
 
+int64_t encode_fine_groups(const EncPlan &p) { return ceil_div(p.maxch[0], (int64_t)kChunksPerWG); }
+
+void encode_pack_layout(EncPlan &p) {
+  const int L = p.g.nL - 1;
+  int64_t base = 0;
+  for (int l = L; l >= 0; l--) {
+    p.pack_base[l] = base;
+    p.pack_gpb[l] = ceil_div(p.maxch[l] > 0 ? p.maxch[l] : 1, (int64_t)kChunksPerWG);
+    base += p.g.nblocks * p.pack_gpb[l];
+  }
+  for (int l = L + 1; l < kMaxLevels; l++) { p.pack_base[l] = base; p.pack_gpb[l] = 1; }
+}
+
 void launch_encode(const EncPlan &p, int64_t, U4 *scan_tmp, uint64_t *scan_tmp64, hipStream_t s) {
   const Geo &g = p.g;
   const int L = g.nL - 1;
   const int64_t nsec = g.nblocks * g.nL;
-  k_init<<<dim3((unsigned)ceil_div(g.nblocks > 0 ? g.nblocks : 1, kBS)), dim3(kBS), 0, s>>>(p);
+  const int64_t gx = encode_fine_groups(p);
   if (L >= 1) {
     prof_mark("k_encode_coarse", s, 0);
     k_encode_coarse<<<dim3((unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
     prof_mark("k_encode_coarse", s, 1);
   }
-  {
-    const unsigned gx = (unsigned)ceil_div(p.maxch[0], (int64_t)kWaves * kChunksPerWave);
-    if (gx > 0) {
-      prof_mark("k_encode_fine", s, 0);
-      k_encode_fine<<<dim3(gx, (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
-      prof_mark("k_encode_fine", s, 1);
-    }
+  if (gx > 0) {
+    prof_mark("k_encode_fine", s, 0);
+    k_encode_fine<<<dim3((unsigned)gx, (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
+    prof_mark("k_encode_fine", s, 1);
   }
   scan_u4(p.cnt, p.P, p.nslots, scan_tmp, s);
   prof_mark("k_sections", s, 0);
@@ -471,13 +528,14 @@ void launch_encode(const EncPlan &p, int64_t, U4 *scan_tmp, uint64_t *scan_tmp64
   prof_mark("k_sec_table", s, 0);
   k_sec_table<<<dim3((unsigned)ceil_div(nsec, kBS)), dim3(kBS), 0, s>>>(p);
   prof_mark("k_sec_table", s, 1);
-  if (p.nslots > 0) {
+  const int64_t npack = p.pack_base[0] + g.nblocks * p.pack_gpb[0];
+  if (p.nslots > 0 && npack > 0) {
     prof_mark("k_pack", s, 0);
-    k_pack<<<dim3((unsigned)ceil_div(p.nslots, kWaves)), dim3(kBS), 0, s>>>(p);
+    k_pack<<<dim3((unsigned)npack), dim3(kBS), 0, s>>>(p);
     prof_mark("k_pack", s, 1);
   }
   prof_mark("k_block_table", s, 0);
-  k_block_table<<<dim3((unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
+  k_block_table<<<dim3((unsigned)g.nblocks), dim3(kBS), 0, s>>>(p, gx, L >= 1 ? 1 : 0);
   prof_mark("k_block_table", s, 1);
   prof_mark("k_header", s, 0);
   k_header<<<dim3(1), dim3(kBS), 0, s>>>(p);
