@@ -446,9 +446,10 @@ static int mc_plan(const float *d_field, const int64_t dims[3], McPlan &M, size_
   M.f = d_field;
   size_t o = 0;
   off[0] = o; o = align256(o + 8 * (size_t)(M.nrows * M.nw));
-  off[1] = o; o = align256(o + sizeof(U4) * (size_t)M.nrows);
-  off[2] = o; o = align256(o + sizeof(U4) * (size_t)(M.nrows + 1));
-  off[3] = o; o = align256(o + sizeof(U4) * (size_t)scan_tmp_elems(M.nrows));
+  const int64_t nwords = M.nrows * M.nw;
+  off[1] = o; o = align256(o + sizeof(U4) * (size_t)nwords);
+  off[2] = o; o = align256(o + sizeof(U4) * (size_t)(nwords + 1));
+  off[3] = o; o = align256(o + sizeof(U4) * (size_t)scan_tmp_elems(nwords));
   need = o;
   return CHR_OK;
 }

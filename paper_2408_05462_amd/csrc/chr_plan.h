@@ -65,7 +65,7 @@ struct McPlan {
   float k, spacing;
   const float *f;
   unsigned long long *bits;      // nrows * nw below-isovalue bits
-  U4 *cnt, *P;                   // per row {vertices, triangles, 0, 0} and prefix
+  U4 *cnt, *P;                   // per word {vertices, triangles, 0, 0} and prefix
   float *verts;
   int32_t *tris;
   int64_t cap_v, cap_t;

@@ -1,17 +1,18 @@
 // mc.hip -- marching cubes on gfx950 (Sec. I: isosurface generation;
 // Sec. II.B: the per-cell case that topology preservation keeps).
 //
-//  1. k_mc_bits:  one coalesced pass over the field; a wave ballots f < k for
-//     64 consecutive points of a row and stores the 64-bit word (1 bit/point).
-//  2. k_mc_count: one wave per row of points; from the bit rows (y,z),
-//     (y+1,z), (y,z+1), (y+1,z+1) it counts the row's crossing owned edges
-//     (+x,+y,+z of each point) with popcounts on wave-uniform words, and the
-//     triangles of the cell row (case per lane, table lookup, wave sum).
-//  3. scan of the per-row counts (vertex and triangle offsets).
-//  4. k_mc_emit:  one wave per active row; vertex ids come from the row
-//     offsets plus popcounts of the crossing masks below a point, so every
-//     triangle finds its three vertex ids without any per-point id array.
-//     Vertices are interpolated at t = (k - fa) / (fb - fa).
+// The field is reduced once to one bit per point (f < k) in 64-bit words
+// along x; everything after that works on words:
+//  1. k_mc_bits:  coalesced streaming pass, a ballot per 64 points.
+//  2. k_mc_count: one lane per word: the word's crossing +x/+y/+z edges
+//     (XORs of neighbouring words, popcount) and the triangles of the word's
+//     active cells (cells whose 8 corners disagree, iterated as set bits;
+//     triangle count from the generated table in LDS).
+//  3. scan of the per-word {vertices, triangles}.
+//  4. k_mc_emit:  one lane per word: vertices in (point, axis) order, then
+//     triangles in (cell, table order) order; the id of the vertex on an edge
+//     owned by point x' of word W is W's vertex base plus the popcount of W's
+//     crossing masks below x' -- no per-point id array.
 #include "chr_plan.h"
 #include "mc_table.h"
 
@@ -20,198 +21,256 @@ namespace {
 
 constexpr int kBS = 256;
 constexpr int kWaves = kBS / kWave;
+constexpr int kWordsPerWave = 16;
 
 constexpr mct::Table kTable = mct::make_table();
 __constant__ mct::Table c_table = kTable;
 
+typedef unsigned long long u64;
+
+// f < k for 64 consecutive points per word; a wave covers kWordsPerWave
+// words with all loads issued before the ballots.
 __global__ __launch_bounds__(kBS) void k_mc_bits(McPlan M) {
   const int64_t nwords = M.nrows * M.nw;
-  const int64_t wid = (int64_t)blockIdx.x * kWaves + threadIdx.x / kWave;
-  if (wid >= nwords) return;
-  const int64_t row = wid / M.nw, w = wid % M.nw;
-  const int64_t x = w * 64 + lane_id();
-  bool below = false;
-  if (x < M.n[2]) below = M.f[row * M.n[2] + x] < M.k;
-  const unsigned long long m = __ballot(below);
-  if (lane_id() == 0) M.bits[wid] = m;
+  const int64_t w0 = ((int64_t)blockIdx.x * kWaves + threadIdx.x / kWave) * kWordsPerWave;
+  if (w0 >= nwords) return;
+  const int lane = lane_id();
+  const int64_t nx = M.n[2];
+  float v[kWordsPerWave];
+#pragma unroll
+  for (int k = 0; k < kWordsPerWave; k++) {
+    const int64_t wi = w0 + k;
+    v[k] = 0.f;
+    if (wi < nwords) {
+      const int64_t row = wi / M.nw, x = (wi - row * M.nw) * 64 + lane;
+      if (x < nx) v[k] = M.f[row * nx + x];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kWordsPerWave; k++) {
+    const int64_t wi = w0 + k;
+    bool below = false;
+    if (wi < nwords) {
+      const int64_t row = wi / M.nw, x = (wi - row * M.nw) * 64 + lane;
+      below = (x < nx) && (v[k] < M.k);
+    }
+    const u64 m = __ballot(below);
+    if (lane == 0 && wi < nwords) M.bits[wi] = m;
+  }
 }
 
-// Crossing masks of the owned +x/+y/+z edges of word w of point row (y, z).
-struct Cross {
-  unsigned long long cx, cy, cz;
+struct WordCtx {
+  int64_t row, w, z, y;
+  u64 valid, validx;   // points of the word / points with a +x neighbour
 };
 
-__device__ inline Cross cross_masks(const McPlan &M, int64_t z, int64_t y, int64_t w) {
-  Cross c{0, 0, 0};
-  if (w < 0 || w >= M.nw || y >= M.n[1] || z >= M.n[0]) return c;
-  const int64_t r = z * M.n[1] + y;
-  const unsigned long long *B = M.bits;
-  const unsigned long long m = B[r * M.nw + w];
-  const unsigned long long nx = (w + 1 < M.nw) ? B[r * M.nw + w + 1] : 0ull;
-  const int64_t nxp = M.n[2];
-  const int64_t rem = nxp - w * 64;  // valid points in this word
-  const unsigned long long valid = rem >= 64 ? ~0ull : ((1ull << rem) - 1ull);
-  // +x edges exist for points x + 1 < nx
+__device__ inline WordCtx word_ctx(const McPlan &M, int64_t gw) {
+  WordCtx c;
+  c.row = gw / M.nw;
+  c.w = gw - c.row * M.nw;
+  c.z = c.row / M.n[1];
+  c.y = c.row - c.z * M.n[1];
+  const int64_t rem = M.n[2] - c.w * 64;
+  c.valid = rem >= 64 ? ~0ull : ((1ull << rem) - 1ull);
   const int64_t remx = rem - 1;
-  const unsigned long long validx = remx >= 64 ? ~0ull : (remx <= 0 ? 0ull : ((1ull << remx) - 1ull));
-  c.cx = (m ^ ((m >> 1) | (nx << 63))) & validx;
-  if (y + 1 < M.n[1]) c.cy = (m ^ B[(r + 1) * M.nw + w]) & valid;
-  if (z + 1 < M.n[0]) c.cz = (m ^ B[(r + M.n[1]) * M.nw + w]) & valid;
+  c.validx = remx >= 64 ? ~0ull : (remx <= 0 ? 0ull : ((1ull << remx) - 1ull));
   return c;
 }
 
-__device__ inline unsigned long long shifted(const unsigned long long *B, int64_t base, int64_t w, int64_t nw) {
-  const unsigned long long m = B[base + w];
-  const unsigned long long nx = (w + 1 < nw) ? B[base + w + 1] : 0ull;
-  return (m >> 1) | (nx << 63);
+__device__ inline u64 bitsw(const McPlan &M, int64_t row, int64_t w) {
+  return (w < M.nw) ? M.bits[row * M.nw + w] : 0ull;
 }
 
-// Case of the cell at this lane from the four bit rows of the cell row.
-__device__ inline uint32_t cell_case(unsigned long long m00, unsigned long long s00, unsigned long long m10,
-                                     unsigned long long s10, unsigned long long m01, unsigned long long s01,
-                                     unsigned long long m11, unsigned long long s11, int lane) {
-  return (uint32_t)(((m00 >> lane) & 1) | (((s00 >> lane) & 1) << 1) | (((m10 >> lane) & 1) << 2) |
-                    (((s10 >> lane) & 1) << 3) | (((m01 >> lane) & 1) << 4) | (((s01 >> lane) & 1) << 5) |
-                    (((m11 >> lane) & 1) << 6) | (((s11 >> lane) & 1) << 7));
+struct Cross {
+  u64 cx, cy, cz;
+};
+
+// Crossing masks of the owned +x/+y/+z edges of word w of point row (z, y).
+__device__ inline Cross cross_of(const McPlan &M, int64_t z, int64_t y, int64_t w) {
+  Cross c{0, 0, 0};
+  if (w >= M.nw) return c;
+  const int64_t row = z * M.n[1] + y;
+  const int64_t rem = M.n[2] - w * 64;
+  const u64 valid = rem >= 64 ? ~0ull : ((1ull << rem) - 1ull);
+  const int64_t remx = rem - 1;
+  const u64 validx = remx >= 64 ? ~0ull : (remx <= 0 ? 0ull : ((1ull << remx) - 1ull));
+  const u64 m = bitsw(M, row, w);
+  c.cx = (m ^ ((m >> 1) | (bitsw(M, row, w + 1) << 63))) & validx;
+  if (y + 1 < M.n[1]) c.cy = (m ^ bitsw(M, row + 1, w)) & valid;
+  if (z + 1 < M.n[0]) c.cz = (m ^ bitsw(M, row + M.n[1], w)) & valid;
+  return c;
+}
+
+__device__ inline u64 shr1(u64 m, u64 next) { return (m >> 1) | (next << 63); }
+
+// The 8 corner masks of the cells of word w of cell row `row`.
+struct Corners {
+  u64 m[8];
+};
+
+__device__ inline Corners corners_of(const McPlan &M, int64_t row, int64_t w) {
+  Corners C;
+  const int64_t r[4] = {row, row + 1, row + M.n[1], row + M.n[1] + 1};  // (dy,dz) = 00, 10, 01, 11
+  for (int i = 0; i < 4; i++) {
+    const u64 a = bitsw(M, r[i], w), b = bitsw(M, r[i], w + 1);
+    C.m[2 * i] = a;               // corner dx = 0
+    C.m[2 * i + 1] = shr1(a, b);  // corner dx = 1
+  }
+  return C;
+}
+
+__device__ inline uint32_t case_at(const Corners &C, int i) {
+  uint32_t cs = 0;
+#pragma unroll
+  for (int v = 0; v < 8; v++) cs |= (uint32_t)((C.m[v] >> i) & 1ull) << v;
+  return cs;
+}
+
+__device__ inline u64 active_cells(const Corners &C, u64 validx) {
+  u64 any = 0, all = ~0ull;
+#pragma unroll
+  for (int v = 0; v < 8; v++) { any |= C.m[v]; all &= C.m[v]; }
+  return any & ~all & validx;
 }
 
 __global__ __launch_bounds__(kBS) void k_mc_count(McPlan M) {
-  const int64_t row = (int64_t)blockIdx.x * kWaves + threadIdx.x / kWave;
-  if (row >= M.nrows) return;
-  const int lane = lane_id();
-  const int64_t z = row / M.n[1], y = row % M.n[1];
-  const bool cells = (y + 1 < M.n[1]) && (z + 1 < M.n[0]);
-  uint32_t nv = 0, nt = 0;
-  const unsigned long long *B = M.bits;
-  for (int64_t w = 0; w < M.nw; w++) {
-    const Cross c = cross_masks(M, z, y, w);
-    nv += (uint32_t)(__popcll(c.cx) + __popcll(c.cy) + __popcll(c.cz));
-    if (cells) {
-      const int64_t r00 = row * M.nw, r10 = (row + 1) * M.nw, r01 = (row + M.n[1]) * M.nw,
-                    r11 = (row + M.n[1] + 1) * M.nw;
-      const uint32_t cs = cell_case(B[r00 + w], shifted(B, r00, w, M.nw), B[r10 + w], shifted(B, r10, w, M.nw),
-                                    B[r01 + w], shifted(B, r01, w, M.nw), B[r11 + w], shifted(B, r11, w, M.nw), lane);
-      const int64_t x = w * 64 + lane;
-      nt += (x + 1 < M.n[2]) ? c_table.ntri[cs] : 0u;
+  __shared__ uint8_t ntri[256];
+  for (int i = threadIdx.x; i < 256; i += kBS) ntri[i] = c_table.ntri[i];
+  __syncthreads();
+  const int64_t gw = (int64_t)blockIdx.x * kBS + threadIdx.x;
+  if (gw >= M.nrows * M.nw) return;
+  const WordCtx c = word_ctx(M, gw);
+  const Cross x = cross_of(M, c.z, c.y, c.w);
+  const uint32_t nv = (uint32_t)(__popcll(x.cx) + __popcll(x.cy) + __popcll(x.cz));
+  uint32_t nt = 0;
+  if (c.y + 1 < M.n[1] && c.z + 1 < M.n[0]) {
+    const Corners C = corners_of(M, c.row, c.w);
+    u64 act = active_cells(C, c.validx);
+    while (act) {
+      const int i = __ffsll((long long)act) - 1;
+      act &= act - 1;
+      nt += ntri[case_at(C, i)];
     }
   }
-  nt = wave_sum_u(nt);
-  if (lane == 0) M.cnt[row] = U4{nv, nt, 0u, 0u};
+  M.cnt[gw] = U4{nv, nt, 0u, 0u};
 }
 
 __device__ inline float interp(float fa, float fb, float k) {
   return __fdiv_rn(__fsub_rn(k, fa), __fsub_rn(fb, fa));
 }
 
+// Vertex-id context of one owner row for word w: crossing masks of words w
+// and w+1 and their vertex bases.
+struct Owner {
+  Cross c0, c1;
+  uint64_t v0, v1;
+};
+
+__device__ inline int popc3_below(const Cross &c, int x) {
+  const u64 bm = (x >= 64) ? ~0ull : ((1ull << x) - 1ull);
+  return __popcll(c.cx & bm) + __popcll(c.cy & bm) + __popcll(c.cz & bm);
+}
+
 __global__ __launch_bounds__(kBS) void k_mc_emit(McPlan M) {
-  const int64_t row = (int64_t)blockIdx.x * kWaves + threadIdx.x / kWave;
-  if (row >= M.nrows) return;
-  const U4 p0 = M.P[row], p1 = M.P[row + 1];
-  const uint32_t nv_row = p1.x - p0.x, nt_row = p1.y - p0.y;
-  if (nv_row == 0 && nt_row == 0) return;
-  const int lane = lane_id();
-  const unsigned long long below_lane = (1ull << lane) - 1ull;
-  const int64_t z = row / M.n[1], y = row % M.n[1];
+  __shared__ mct::Table tab;
+  {
+    const uint8_t *src = reinterpret_cast<const uint8_t *>(&c_table);
+    uint8_t *dst = reinterpret_cast<uint8_t *>(&tab);
+    for (int i = threadIdx.x; i < (int)sizeof(mct::Table); i += kBS) dst[i] = src[i];
+  }
+  __syncthreads();
+  const int64_t gw = (int64_t)blockIdx.x * kBS + threadIdx.x;
+  if (gw >= M.nrows * M.nw) return;
+  const U4 p0 = M.P[gw], p1 = M.P[gw + 1];
+  if (p0.x == p1.x && p0.y == p1.y) return;
+  const WordCtx c = word_ctx(M, gw);
   const int64_t n1 = M.n[1], n2 = M.n[2];
   const float *f = M.f;
   const float k = M.k, sp = M.spacing;
 
-  // vertices of this point row
-  if (nv_row) {
-    uint64_t run = p0.x;
-    for (int64_t w = 0; w < M.nw; w++) {
-      const Cross c = cross_masks(M, z, y, w);
-      const uint32_t tot = (uint32_t)(__popcll(c.cx) + __popcll(c.cy) + __popcll(c.cz));
-      if (tot) {
-        const int64_t x = w * 64 + lane;
-        uint64_t id = run + (uint64_t)(__popcll(c.cx & below_lane) + __popcll(c.cy & below_lane) +
-                                       __popcll(c.cz & below_lane));
-        const bool ex = (c.cx >> lane) & 1, ey = (c.cy >> lane) & 1, ez = (c.cz >> lane) & 1;
-        if (ex || ey || ez) {
-          const float fa = f[(z * n1 + y) * n2 + x];
-          const float px = (float)x, py = (float)y, pz = (float)z;
-          if (ex) {
-            if ((int64_t)id < M.cap_v) {
-              const float t = interp(fa, f[(z * n1 + y) * n2 + x + 1], k);
-              float *v = M.verts + 3 * id;
-              v[0] = __fmul_rn(__fadd_rn(px, t), sp); v[1] = __fmul_rn(py, sp); v[2] = __fmul_rn(pz, sp);
-            }
-            id++;
-          }
-          if (ey) {
-            if ((int64_t)id < M.cap_v) {
-              const float t = interp(fa, f[(z * n1 + y + 1) * n2 + x], k);
-              float *v = M.verts + 3 * id;
-              v[0] = __fmul_rn(px, sp); v[1] = __fmul_rn(__fadd_rn(py, t), sp); v[2] = __fmul_rn(pz, sp);
-            }
-            id++;
-          }
-          if (ez) {
-            if ((int64_t)id < M.cap_v) {
-              const float t = interp(fa, f[((z + 1) * n1 + y) * n2 + x], k);
-              float *v = M.verts + 3 * id;
-              v[0] = __fmul_rn(px, sp); v[1] = __fmul_rn(py, sp); v[2] = __fmul_rn(__fadd_rn(pz, t), sp);
-            }
-            id++;
-          }
+  // vertices of this word's points, in (point, axis) order
+  if (p1.x != p0.x) {
+    const Cross x = cross_of(M, c.z, c.y, c.w);
+    uint64_t id = p0.x;
+    u64 pts = x.cx | x.cy | x.cz;
+    const float py = (float)c.y, pz = (float)c.z;
+    while (pts) {
+      const int i = __ffsll((long long)pts) - 1;
+      pts &= pts - 1;
+      const int64_t xx = c.w * 64 + i;
+      const size_t gi = ((size_t)c.z * n1 + c.y) * n2 + xx;
+      const float fa = f[gi];
+      const float px = (float)xx;
+      if ((x.cx >> i) & 1ull) {
+        if ((int64_t)id < M.cap_v) {
+          const float t = interp(fa, f[gi + 1], k);
+          float *v = M.verts + 3 * id;
+          v[0] = __fmul_rn(__fadd_rn(px, t), sp); v[1] = __fmul_rn(py, sp); v[2] = __fmul_rn(pz, sp);
         }
+        id++;
       }
-      run += tot;
+      if ((x.cy >> i) & 1ull) {
+        if ((int64_t)id < M.cap_v) {
+          const float t = interp(fa, f[gi + n2], k);
+          float *v = M.verts + 3 * id;
+          v[0] = __fmul_rn(px, sp); v[1] = __fmul_rn(__fadd_rn(py, t), sp); v[2] = __fmul_rn(pz, sp);
+        }
+        id++;
+      }
+      if ((x.cz >> i) & 1ull) {
+        if ((int64_t)id < M.cap_v) {
+          const float t = interp(fa, f[gi + (size_t)n1 * n2], k);
+          float *v = M.verts + 3 * id;
+          v[0] = __fmul_rn(px, sp); v[1] = __fmul_rn(py, sp); v[2] = __fmul_rn(__fadd_rn(pz, t), sp);
+        }
+        id++;
+      }
     }
   }
 
-  // triangles of this cell row
-  if (nt_row) {
-    const unsigned long long *B = M.bits;
-    const int64_t rows[4] = {row, row + 1, row + n1, row + n1 + 1};   // owner rows (dy,dz) = 00,10,01,11
-    const int64_t ry[4] = {y, y + 1, y, y + 1}, rz[4] = {z, z, z + 1, z + 1};
-    uint64_t vbase[4];
-    for (int i = 0; i < 4; i++) vbase[i] = M.P[rows[i]].x;
-    uint64_t trun = p0.y;
-    Cross cur[4], nxt[4];
-    for (int i = 0; i < 4; i++) cur[i] = cross_masks(M, rz[i], ry[i], 0);
-    for (int64_t w = 0; w < M.nw; w++) {
-      for (int i = 0; i < 4; i++) nxt[i] = cross_masks(M, rz[i], ry[i], w + 1);
-      const int64_t r00 = row * M.nw, r10 = (row + 1) * M.nw, r01 = (row + n1) * M.nw, r11 = (row + n1 + 1) * M.nw;
-      const uint32_t cs = cell_case(B[r00 + w], shifted(B, r00, w, M.nw), B[r10 + w], shifted(B, r10, w, M.nw),
-                                    B[r01 + w], shifted(B, r01, w, M.nw), B[r11 + w], shifted(B, r11, w, M.nw), lane);
-      const int64_t x = w * 64 + lane;
-      const uint32_t ntr = (x + 1 < n2) ? c_table.ntri[cs] : 0u;
-      const uint32_t toff = wave_excl_sum(ntr);
-      for (uint32_t t = 0; t < ntr; t++) {
-        const uint64_t tid = trun + toff + t;
+  // triangles of this word's cells, in (cell, table order) order
+  if (p1.y != p0.y) {
+    const int64_t rows[4] = {c.row, c.row + 1, c.row + n1, c.row + n1 + 1};
+    const int64_t ry[4] = {c.y, c.y + 1, c.y, c.y + 1}, rz[4] = {c.z, c.z, c.z + 1, c.z + 1};
+    Owner own[4];
+    for (int r = 0; r < 4; r++) {
+      own[r].c0 = cross_of(M, rz[r], ry[r], c.w);
+      own[r].c1 = cross_of(M, rz[r], ry[r], c.w + 1);
+      own[r].v0 = M.P[rows[r] * M.nw + c.w].x;
+      own[r].v1 = (c.w + 1 < M.nw) ? M.P[rows[r] * M.nw + c.w + 1].x : 0;
+    }
+    const Corners C = corners_of(M, c.row, c.w);
+    u64 act = active_cells(C, c.validx);
+    uint64_t tid = p0.y;
+    while (act) {
+      const int i = __ffsll((long long)act) - 1;
+      act &= act - 1;
+      const uint32_t cs = case_at(C, i);
+      const int nt = tab.ntri[cs];
+      for (int t = 0; t < nt; t++, tid++) {
         int32_t ids[3];
         for (int q = 0; q < 3; q++) {
-          const int e = c_table.tri[cs][3 * t + q];
+          const int e = tab.tri[cs][3 * t + q];
           const int axis = e >> 2, i2 = e & 3;
-          // owner point of the edge: cell origin + the edge's lower corner
           int dx = 0, dy = 0, dz = 0;
           if (axis == 0) { dy = i2 & 1; dz = i2 >> 1; }
           if (axis == 1) { dx = i2 & 1; dz = i2 >> 1; }
           if (axis == 2) { dx = i2 & 1; dy = i2 >> 1; }
-          const int R = dy + 2 * dz;
-          const int xi = lane + dx;  // 0..64 within this word
-          Cross cw;
-          unsigned long long bm;
+          const Owner &o = own[dy + 2 * dz];
+          const int xo = i + dx;
+          uint64_t id;
+          u64 mx, my;
           int bit;
-          if (xi < 64) { cw = cur[R]; bm = (1ull << xi) - 1ull; bit = xi; }
-          else { cw = nxt[R]; bm = 0ull; bit = 0; }
-          uint64_t before = (xi < 64) ? (uint64_t)(__popcll(cw.cx & bm) + __popcll(cw.cy & bm) + __popcll(cw.cz & bm))
-                                      : (uint64_t)(__popcll(cur[R].cx) + __popcll(cur[R].cy) + __popcll(cur[R].cz));
-          uint64_t within = 0;
-          if (axis >= 1) within += (cw.cx >> bit) & 1;
-          if (axis >= 2) within += (cw.cy >> bit) & 1;
-          ids[q] = (int32_t)(vbase[R] + before + within);
+          if (xo < 64) { id = o.v0 + popc3_below(o.c0, xo); mx = o.c0.cx; my = o.c0.cy; bit = xo; }
+          else { id = o.v1; mx = o.c1.cx; my = o.c1.cy; bit = 0; }
+          if (axis >= 1) id += (mx >> bit) & 1ull;
+          if (axis >= 2) id += (my >> bit) & 1ull;
+          ids[q] = (int32_t)id;
         }
         if ((int64_t)tid < M.cap_t) {
           int32_t *o = M.tris + 3 * tid;
           o[0] = ids[0]; o[1] = ids[1]; o[2] = ids[2];
         }
-      }
-      trun += wave_sum_u(ntr);
-      for (int i = 0; i < 4; i++) {
-        vbase[i] += (uint64_t)(__popcll(cur[i].cx) + __popcll(cur[i].cy) + __popcll(cur[i].cz));
-        cur[i] = nxt[i];
       }
     }
   }
@@ -219,26 +278,24 @@ __global__ __launch_bounds__(kBS) void k_mc_emit(McPlan M) {
 
 __global__ void k_mc_counts(McPlan M) {
   if (threadIdx.x == 0) {
-    M.counts[0] = (int64_t)M.P[M.nrows].x;
-    M.counts[1] = (int64_t)M.P[M.nrows].y;
+    const int64_t n = M.nrows * M.nw;
+    M.counts[0] = (int64_t)M.P[n].x;
+    M.counts[1] = (int64_t)M.P[n].y;
   }
 }
 
+// Case of every cell (one lane per word of cells).
 __global__ __launch_bounds__(kBS) void k_mc_cases(McPlan M) {
-  const int64_t cz = M.n[0] - 1, cy = M.n[1] - 1, cx = M.n[2] - 1;
-  const int64_t row = (int64_t)blockIdx.x * kWaves + threadIdx.x / kWave;
-  if (row >= cz * cy) return;
-  const int lane = lane_id();
-  const int64_t z = row / cy, y = row % cy;
-  const int64_t prow = z * M.n[1] + y;
-  const unsigned long long *B = M.bits;
-  for (int64_t w = 0; w < M.nw; w++) {
-    const int64_t r00 = prow * M.nw, r10 = (prow + 1) * M.nw, r01 = (prow + M.n[1]) * M.nw,
-                  r11 = (prow + M.n[1] + 1) * M.nw;
-    const uint32_t cs = cell_case(B[r00 + w], shifted(B, r00, w, M.nw), B[r10 + w], shifted(B, r10, w, M.nw),
-                                  B[r01 + w], shifted(B, r01, w, M.nw), B[r11 + w], shifted(B, r11, w, M.nw), lane);
-    const int64_t x = w * 64 + lane;
-    if (x < cx) M.cases[(z * cy + y) * cx + x] = (uint8_t)cs;
+  const int64_t gw = (int64_t)blockIdx.x * kBS + threadIdx.x;
+  if (gw >= M.nrows * M.nw) return;
+  const WordCtx c = word_ctx(M, gw);
+  if (c.y + 1 >= M.n[1] || c.z + 1 >= M.n[0]) return;
+  const int64_t cy = M.n[1] - 1, cx = M.n[2] - 1;
+  const Corners C = corners_of(M, c.row, c.w);
+  for (int i = 0; i < 64; i++) {
+    const int64_t x = c.w * 64 + i;
+    if (x >= cx) break;
+    M.cases[(c.z * cy + c.y) * cx + x] = (uint8_t)case_at(C, i);
   }
 }
 
@@ -278,25 +335,23 @@ __global__ void k_range_fin(uint32_t *acc) {
 void launch_mc(const McPlan &p, U4 *scan_tmp, hipStream_t s) {
   const int64_t nwords = p.nrows * p.nw;
   prof_mark("k_mc_bits", s, 0);
-  k_mc_bits<<<dim3((unsigned)ceil_div(nwords, kWaves)), dim3(kBS), 0, s>>>(p);
+  k_mc_bits<<<dim3((unsigned)ceil_div(nwords, (int64_t)kWaves * kWordsPerWave)), dim3(kBS), 0, s>>>(p);
   prof_mark("k_mc_bits", s, 1);
   prof_mark("k_mc_count", s, 0);
-  k_mc_count<<<dim3((unsigned)ceil_div(p.nrows, kWaves)), dim3(kBS), 0, s>>>(p);
+  k_mc_count<<<dim3((unsigned)ceil_div(nwords, kBS)), dim3(kBS), 0, s>>>(p);
   prof_mark("k_mc_count", s, 1);
-  scan_u4(p.cnt, p.P, p.nrows, scan_tmp, s);
+  scan_u4(p.cnt, p.P, nwords, scan_tmp, s);
   prof_mark("k_mc_emit", s, 0);
-  k_mc_emit<<<dim3((unsigned)ceil_div(p.nrows, kWaves)), dim3(kBS), 0, s>>>(p);
+  k_mc_emit<<<dim3((unsigned)ceil_div(nwords, kBS)), dim3(kBS), 0, s>>>(p);
   prof_mark("k_mc_emit", s, 1);
   k_mc_counts<<<dim3(1), dim3(64), 0, s>>>(p);
 }
 
 void launch_mc_cases(const McPlan &p, hipStream_t s) {
   const int64_t nwords = p.nrows * p.nw;
-  prof_mark("k_mc_bits", s, 0);
-  k_mc_bits<<<dim3((unsigned)ceil_div(nwords, kWaves)), dim3(kBS), 0, s>>>(p);
-  prof_mark("k_mc_bits", s, 1);
-  const int64_t crow = (p.n[0] - 1) * (p.n[1] - 1);
-  if (crow > 0 && p.n[2] > 1) k_mc_cases<<<dim3((unsigned)ceil_div(crow, kWaves)), dim3(kBS), 0, s>>>(p);
+  k_mc_bits<<<dim3((unsigned)ceil_div(nwords, (int64_t)kWaves * kWordsPerWave)), dim3(kBS), 0, s>>>(p);
+  if (p.n[0] > 1 && p.n[1] > 1 && p.n[2] > 1)
+    k_mc_cases<<<dim3((unsigned)ceil_div(nwords, kBS)), dim3(kBS), 0, s>>>(p);
 }
 
 void launch_range(const float *f, int64_t n, float *out, hipStream_t s) {
