@@ -289,6 +289,7 @@ int chr_compress(const float *d_field, const int64_t dims[3], double error_bound
   fill_geo(P.g, dims, p->levels, p->block, p->qmax);
   if (prepare_iso(h_isovalues, n_iso, P.g, why)) return fail(CHR_E_INVAL, why);
   set_quant(P.g, error_bound);
+  make_l0geo(P.g, P.l0);
   EncLayout Lo = enc_layout(P);
   if (ws_bytes < Lo.total) return fail(CHR_E_NOMEM, "workspace too small: need " + std::to_string(Lo.total));
   if (P.g.nblocks > 65535) return fail(CHR_E_INVAL, "more than 65535 blocks: use a larger block");
@@ -389,6 +390,7 @@ static int dec_plan(const chr_info *I, int level, DecPlan &D, size_t &need) {
   if ((D.g.lossless ? 1u : 0u) != (I->flags & 1u)) return fail(CHR_E_CORRUPT, "lossless flag mismatch");
   D.g.K = I->n_iso;
   for (int j = 0; j < kMaxIso; j++) D.g.iso[j] = I->isovalues[j];
+  make_l0geo(D.g, D.l0);
   D.lo = level;
   const int L = I->levels - 1;
   need = 0;

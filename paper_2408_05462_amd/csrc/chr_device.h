@@ -160,6 +160,52 @@ __host__ __device__ inline void sec_point(const Sec &s, uint32_t j, uint32_t &w,
   }
 }
 
+// Level-0 section geometry of the (at most 8) block shapes -- interior or
+// last block along each axis -- plus divisors that split a block index into
+// (bz, by, bx); filled on the host so kernels skip the 64-bit arithmetic.
+struct L0Geo {
+  Sec sec[8];
+  FastDiv d_nb2, d_nb1;
+  uint32_t nb[3];
+};
+
+__host__ inline void make_l0geo(const Geo &g, L0Geo &G) {
+  for (int a = 0; a < 3; a++) G.nb[a] = (uint32_t)g.nb[a];
+  G.d_nb2 = make_fastdiv(G.nb[2]);
+  G.d_nb1 = make_fastdiv(G.nb[1]);
+  for (int cls = 0; cls < 8; cls++) {
+    const int64_t bz = (cls & 4) ? g.nb[0] - 1 : 0, by = (cls & 2) ? g.nb[1] - 1 : 0, bx = (cls & 1) ? g.nb[2] - 1 : 0;
+    int64_t o[3], hi[3];
+    block_ext(g, (bz * g.nb[1] + by) * g.nb[2] + bx, o, hi);
+    G.sec[cls] = sec_geom(o, hi, 0, g.nL - 1);
+  }
+}
+
+// Block b's origin, closed-extent end, first non-owned coordinate and shape class.
+struct BlockPos {
+  uint32_t o[3], hi[3], own[3];
+  int cls;
+};
+
+__device__ inline BlockPos block_pos(const Geo &g, const L0Geo &G, uint32_t b) {
+  BlockPos p;
+  const uint32_t t = fdiv(b, G.d_nb2);
+  const uint32_t bx = b - t * G.nb[2];
+  const uint32_t bz = fdiv(t, G.d_nb1);
+  const uint32_t by = t - bz * G.nb[1];
+  const uint32_t bi[3] = {bz, by, bx};
+  p.cls = 0;
+  for (int a = 0; a < 3; a++) {
+    const uint32_t n = (uint32_t)g.n[a];
+    p.o[a] = bi[a] * (uint32_t)g.B;
+    const uint32_t e = p.o[a] + (uint32_t)g.B;
+    p.hi[a] = e < n - 1 ? e : n - 1;
+    p.own[a] = e < n - 1 ? e : n;
+    if (bi[a] == G.nb[a] - 1) p.cls |= 4 >> a;
+  }
+  return p;
+}
+
 __host__ __device__ inline size_t pad8(size_t n) { return (n + 7) & ~(size_t)7; }
 
 __host__ __device__ inline uint64_t sec_bytes(uint64_t npts, uint64_t W, uint64_t NE, uint64_t NX) {
@@ -224,6 +270,28 @@ __device__ inline uint32_t wave_excl_sum(uint32_t v) {
   }
   return x - v;
 }
+// Wave-wide reductions through DPP: within each 16-lane row (xor 1, xor 2,
+// half mirror, mirror), then across rows (broadcast of lanes 15 and 31);
+// lane 63 ends with the result, which is read back as a wave-uniform value.
+template <class Op>
+__device__ inline uint32_t wave_reduce_dpp(uint32_t v, Op op, uint32_t ident) {
+  v = op(v, (uint32_t)__builtin_amdgcn_update_dpp((int)ident, (int)v, 0xb1, 0xf, 0xf, false));   // quad_perm 1,0,3,2
+  v = op(v, (uint32_t)__builtin_amdgcn_update_dpp((int)ident, (int)v, 0x4e, 0xf, 0xf, false));   // quad_perm 2,3,0,1
+  v = op(v, (uint32_t)__builtin_amdgcn_update_dpp((int)ident, (int)v, 0x141, 0xf, 0xf, false));  // row_half_mirror
+  v = op(v, (uint32_t)__builtin_amdgcn_update_dpp((int)ident, (int)v, 0x140, 0xf, 0xf, false));  // row_mirror
+  v = op(v, (uint32_t)__builtin_amdgcn_update_dpp((int)ident, (int)v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+  v = op(v, (uint32_t)__builtin_amdgcn_update_dpp((int)ident, (int)v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+struct OpOr { __device__ uint32_t operator()(uint32_t a, uint32_t b) const { return a | b; } };
+struct OpMin { __device__ uint32_t operator()(uint32_t a, uint32_t b) const { return a < b ? a : b; } };
+struct OpMax { __device__ uint32_t operator()(uint32_t a, uint32_t b) const { return a > b ? a : b; } };
+struct OpAdd { __device__ uint32_t operator()(uint32_t a, uint32_t b) const { return a + b; } };
+__device__ inline uint32_t wave_or_dpp(uint32_t v) { return wave_reduce_dpp(v, OpOr(), 0u); }
+__device__ inline uint32_t wave_min_dpp(uint32_t v) { return wave_reduce_dpp(v, OpMin(), 0xffffffffu); }
+__device__ inline uint32_t wave_max_dpp(uint32_t v) { return wave_reduce_dpp(v, OpMax(), 0u); }
+__device__ inline uint32_t wave_sum_dpp(uint32_t v) { return wave_reduce_dpp(v, OpAdd(), 0u); }
+
 // number of set bits of m below this lane
 __device__ inline uint32_t lanes_below(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));

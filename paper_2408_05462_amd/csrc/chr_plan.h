@@ -21,6 +21,7 @@ struct Part {
 // values); slots of level l for block b start at slot_base[l] + b*maxch[l].
 struct EncPlan {
   Geo g;
+  L0Geo l0;
   int64_t slot_base[kMaxLevels];
   uint32_t maxch[kMaxLevels];
   int64_t nslots;
@@ -49,6 +50,7 @@ struct EncPlan {
 // Reconstruction of levels L..lo.
 struct DecPlan {
   Geo g;
+  L0Geo l0;
   int lo;
   int64_t gd[kMaxLevels][3];
   float *gp[kMaxLevels];         // compact grid of level l (gp[lo] = output when lo >= 1)

@@ -229,6 +229,110 @@ __global__ __launch_bounds__(kBS) void k_decode_fine(DecPlan D) {
   });
 }
 
+// Level 0 below a coarser level (nL >= 2) over (tile groups, blocks): one
+// wave per tile, block geometry from the host-filled shape table, and
+// block-relative 32-bit offsets from uniform base pointers (the block's first
+// plane of the output and of the level-1 grid).  Writes the points the block
+// owns, plus the even points of even rows taken from level 1.
+__global__ __launch_bounds__(kBS) void k_decode_l0(DecPlan D) {
+  const Geo &g = D.g;
+  const uint32_t b = blockIdx.y;
+  const uint32_t t = blockIdx.x * kWaves + threadIdx.x / kWave;
+  const int lane = lane_id();
+  const BlockPos bp = block_pos(g, D.l0, b);
+  const Sec &s = D.l0.sec[bp.cls];
+  const uint32_t nch = (s.npts + 63) / 64;
+  if (t >= (nch + 63) / 64) return;
+  const SecView v = open_section(D, b, 0, s.npts);
+  if (!v.ok) {
+    if (lane == 0) set_status(D, -4);
+    return;
+  }
+  const uint32_t n1 = (uint32_t)g.n[1], n2 = (uint32_t)g.n[2];
+  const uint32_t oy = bp.o[1], ox = bp.o[2];
+  const uint32_t ownz = bp.own[0] - bp.o[0], owny = bp.own[1], ownx = bp.own[2];
+  const bool lastx = (bp.hi[2] == (uint32_t)g.n[2] - 1);
+  float *__restrict__ ob = D.out + (size_t)bp.o[0] * n1 * n2;
+  const uint32_t g0 = (uint32_t)D.gd[1][0], g1 = (uint32_t)D.gd[1][1], g2 = (uint32_t)D.gd[1][2];
+  const uint32_t zg = bp.o[0] >> 1;
+  const float *__restrict__ G1 = D.gp[1] + (size_t)zg * g1 * g2;
+  const float step = g.step;
+  const int lossless = g.lossless;
+
+  const uint32_t c = t * 64 + (uint32_t)lane;
+  const uint8_t *tt = v.p + 16 + 12 * (uint64_t)t;
+  const uint32_t tw = ld32(tt), te = ld32(tt + 4), tx = ld32(tt + 8);
+  const uint32_t hb = c < v.nch ? v.p[v.A + c] : 0u;
+  const uint32_t w = hb & 31u, he = hb >> 7;
+  const uint32_t wo = tw + wave_excl_sum(w), eo = te + wave_excl_sum(he);
+  const uint32_t bad_l = (w > (uint32_t)kMaxW) || (hb & 0x60u) || (wo + w > v.W) || (he && eo >= v.NE);
+  if (__ballot(bad_l)) {
+    set_status(D, -4);
+    return;
+  }
+  const uint64_t em = he ? ld64(v.p + v.Moff + 8 * (uint64_t)eo) : 0ull;
+  const uint32_t pc = (uint32_t)__popcll(em);
+  const uint32_t xo = tx + wave_excl_sum(pc);
+  if (__ballot(xo + pc > v.NX)) {
+    set_status(D, -4);
+    return;
+  }
+  const uint32_t nc = min(64u, v.nch - t * 64);
+  const uint8_t *pay = v.p + v.Poff;
+  const uint32_t *exv = reinterpret_cast<const uint32_t *>(v.p + v.Xoff);
+#pragma unroll 1
+  for (uint32_t k = 0; k < nc; k++) {
+    const uint32_t wk = rl32(w, (int)k), wok = rl32(wo, (int)k), xok = rl32(xo, (int)k);
+    const uint64_t emk = rl64(em, (int)k);
+    const uint32_t j = (t * 64 + k) * 64 + (uint32_t)lane;
+    if (j >= s.npts) continue;
+    uint32_t zc = 0;
+    if (wk) {
+      const uint32_t bit = (uint32_t)lane * wk, off = bit & 31u;
+      const uint32_t *wp = reinterpret_cast<const uint32_t *>(pay + 8 * (uint64_t)wok) + (bit >> 5);
+      zc = wp[0] >> off;
+      if (off + wk > 32u) zc |= wp[1] << (32u - off);
+      zc &= (1u << wk) - 1u;
+    }
+    uint32_t zz_, vv, uu;
+    sec_point(s, j, zz_, vv, uu);
+    const uint32_t y = oy + vv, x = ox + uu;
+    const uint32_t zl = zz_ >> 1, yl = y >> 1, xl = x >> 1;
+    float r;
+    if ((emk >> lane) & 1ull) {
+      r = __uint_as_float(exv[xok + lanes_below(emk)]);
+    } else {
+      const uint32_t pz = zz_ & 1u, py = y & 1u, px = x & 1u;
+      const bool zu = pz && (zg + zl + 1 < g0), yu = py && (yl + 1 < g1), xu = px && (xl + 1 < g2);
+      auto row = [&](uint32_t zi, uint32_t yi) {
+        const float *rr = G1 + (zi * g1 + yi) * g2;
+        float a = rr[xl];
+        if (xu) a = avg2(a, rr[xl + 1]);
+        return a;
+      };
+      float p = row(zl, yl);
+      if (yu) p = avg2(p, row(zl, yl + 1));
+      if (zu) {
+        float p1 = row(zl + 1, yl);
+        if (yu) p1 = avg2(p1, row(zl + 1, yl + 1));
+        p = avg2(p, p1);
+      }
+      const int32_t q = (int32_t)(zc >> 1) ^ -(int32_t)(zc & 1u);
+      r = lossless ? p : __fadd_rn(p, __fmul_rn((float)q, step));
+    }
+    if (zz_ < ownz && y < owny) {
+      float *orow = ob + (zz_ * n1 + y) * n2;
+      if (x < ownx) orow[x] = r;
+      if (!((zz_ | y) & 1u) && (x & 1u)) {
+        // even row of an even plane: the neighbouring even points come from level 1
+        const float *grow = G1 + (zl * g1 + yl) * g2;
+        orow[x - 1] = grow[xl];
+        if (x + 1 == bp.hi[2] && lastx) orow[x + 1] = grow[xl + 1];
+      }
+    }
+  }
+}
+
 // Even points of even rows in blocks one point wide along x (no level-0
 // point in those rows writes them).
 __global__ __launch_bounds__(kBS) void k_decode_thin(DecPlan D) {
@@ -260,8 +364,11 @@ void launch_decode(const DecPlan &p, hipStream_t s) {
     block_ext(g, 0, o, hi);
     const Sec s0 = sec_geom(o, hi, 0, L);
     const int64_t ntile = ceil_div(ceil_div(s0.npts, 64), 64);
+    const bool slab32 = (double)(hi[0] - o[0] + 1) * (double)g.n[1] * (double)g.n[2] < 4294967296.0;
+    const dim3 grid((unsigned)ceil_div(ntile > 0 ? ntile : 1, kWaves), (unsigned)g.nblocks);
     prof_mark("k_decode_fine", s, 0);
-    k_decode_fine<<<dim3((unsigned)ceil_div(ntile > 0 ? ntile : 1, kWaves), (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
+    if (L >= 1 && slab32) k_decode_l0<<<grid, dim3(kBS), 0, s>>>(p);
+    else k_decode_fine<<<grid, dim3(kBS), 0, s>>>(p);
     prof_mark("k_decode_fine", s, 1);
     if (L >= 1) {
       prof_mark("k_decode_thin", s, 0);

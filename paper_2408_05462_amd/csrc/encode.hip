@@ -97,9 +97,9 @@ __device__ inline void part_init(Part &a) {
 __device__ void part_store(const Part &a, Part *dst) {
   __shared__ Part red[kWaves];
   Part r;
-  r.rmin = wave_min_u(a.rmin); r.rmax = wave_max_u(a.rmax);
-  r.xmin = wave_min_u(a.xmin); r.xmax = wave_max_u(a.xmax);
-  r.nonfinite = wave_or(a.nonfinite); r.nO = wave_sum_u(a.nO); r.nC = wave_sum_u(a.nC);
+  r.rmin = wave_min_dpp(a.rmin); r.rmax = wave_max_dpp(a.rmax);
+  r.xmin = wave_min_dpp(a.xmin); r.xmax = wave_max_dpp(a.xmax);
+  r.nonfinite = wave_or_dpp(a.nonfinite); r.nO = wave_sum_dpp(a.nO); r.nC = wave_sum_dpp(a.nC);
   r.pad = 0;
   if (lane_id() == 0) red[threadIdx.x / kWave] = r;
   __syncthreads();
@@ -153,7 +153,7 @@ __device__ void enc_chunk(const EncPlan &P, int l, int64_t b, const int64_t o[3]
   }
   const bool E = valid && (O || C);
   const uint32_t zz = (valid && !E) ? (((uint32_t)q << 1) ^ (uint32_t)(q >> 31)) : 0u;
-  const uint32_t orv = wave_or(zz);
+  const uint32_t orv = wave_or_dpp(zz);
   const int wb = orv ? 32 - __clz((int)orv) : 0;
   const unsigned long long em = __ballot(E);
   const int64_t slot = P.slot_base[l] + b * (int64_t)P.maxch[l] + c;
@@ -245,6 +245,115 @@ __global__ __launch_bounds__(kBS) void k_encode_fine(EncPlan P) {
     if (c >= P.maxch[0]) break;
     if (c < nch) enc_chunk(P, 0, b, o, own, s, c, pack[wave], acc);
     else zero_slot(P, 0, b, c);
+  }
+  part_store(acc, &P.part[b * P.part_per_block + blockIdx.x]);
+}
+
+// Packs the chunk of this wave (codes zz, exact flags E, exact values x) into
+// slot `slot`.
+__device__ inline void pack_chunk(const EncPlan &P, int64_t slot, uint32_t zz, bool E, float x, uint32_t *pack) {
+  const int lane = lane_id();
+  const uint32_t orv = wave_or_dpp(zz);
+  const int wb = orv ? 32 - __clz((int)orv) : 0;
+  const unsigned long long em = __ballot(E);
+  if (lane < 32) pack[lane] = 0u;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  if (zz) {
+    const uint32_t bit = (uint32_t)lane * (uint32_t)wb, wi = bit >> 5, off = bit & 31u;
+    __hip_atomic_fetch_or(&pack[wi], zz << off, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    if (off + (uint32_t)wb > 32u)
+      __hip_atomic_fetch_or(&pack[wi + 1], zz >> (32u - off), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  if (lane < 2 * wb) P.pay[slot * 32 + lane] = pack[lane];
+  if (E) P.exv[slot * 64 + lanes_below(em)] = x;
+  if (lane == 0) {
+    P.cnt[slot] = U4{(uint32_t)wb, em ? 1u : 0u, (uint32_t)__popcll(em), 0u};
+    if (em) P.emask[slot] = em;
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Level 0 below a coarser level (nL >= 2): the same arithmetic as
+// enc_chunk with the level fixed at 0, block-relative 32-bit offsets from
+// uniform base pointers (the block's first plane of the field and of the
+// level-1 grid), and the optional per-point outputs compiled in only when
+// requested.
+template <bool AUX>
+__global__ __launch_bounds__(kBS) void k_encode_l0(EncPlan P) {
+  __shared__ uint32_t pack[kWaves][32];
+  const Geo &g = P.g;
+  const uint32_t b = blockIdx.y;
+  const int wave = threadIdx.x / kWave;
+  const int lane = lane_id();
+  const BlockPos bp = block_pos(g, P.l0, b);
+  const Sec &s = P.l0.sec[bp.cls];
+  const uint32_t nch = (s.npts + 63) / 64;
+  const uint32_t n1 = (uint32_t)g.n[1], n2 = (uint32_t)g.n[2];
+  const uint32_t oy = bp.o[1], ox = bp.o[2];
+  const float *__restrict__ xb = P.x + (size_t)bp.o[0] * n1 * n2;
+  const uint32_t g0 = (uint32_t)P.gd[1][0], g1 = (uint32_t)P.gd[1][1], g2 = (uint32_t)P.gd[1][2];
+  const uint32_t zg = bp.o[0] >> 1;
+  const float *__restrict__ G1 = P.G + P.g_off[1] + (size_t)zg * g1 * g2;
+  const uint32_t ownz = bp.own[0] - bp.o[0], owny = bp.own[1], ownx = bp.own[2];
+  const int64_t slot0 = P.slot_base[0] + (int64_t)b * P.maxch[0];
+  Part acc;
+  part_init(acc);
+#pragma unroll 1
+  for (int k = 0; k < kChunksPerWave; k++) {
+    const uint32_t c = (blockIdx.x * kChunksPerWave + k) * kWaves + wave;
+    if (c >= P.maxch[0]) break;
+    if (c >= nch) {
+      if (lane == 0) P.cnt[slot0 + c] = U4{0, 0, 0, 0};
+      continue;
+    }
+    const uint32_t j = c * kWave + (uint32_t)lane;
+    float x = 0.f;
+    uint32_t zz = 0;
+    bool E = false;
+    if (j < s.npts) {
+      uint32_t w, v, u;
+      sec_point(s, j, w, v, u);
+      const uint32_t y = oy + v, xx = ox + u;
+      x = xb[(w * n1 + y) * n2 + xx];
+      const uint32_t pz = w & 1u, py = y & 1u, px = xx & 1u;
+      const uint32_t zl = w >> 1, yl = y >> 1, xl = xx >> 1;
+      const bool zu = pz && (zg + zl + 1 < g0), yu = py && (yl + 1 < g1), xu = px && (xl + 1 < g2);
+      auto row = [&](uint32_t zi, uint32_t yi) {
+        const float *r = G1 + (zi * g1 + yi) * g2;
+        float a = r[xl];
+        if (xu) a = avg2(a, r[xl + 1]);
+        return a;
+      };
+      float p = row(zl, yl);
+      if (yu) p = avg2(p, row(zl, yl + 1));
+      if (zu) {
+        float p1 = row(zl + 1, yl);
+        if (yu) p1 = avg2(p1, row(zl + 1, yl + 1));
+        p = avg2(p, p1);
+      }
+      int32_t q;
+      int O, C = 0;
+      float xr;
+      quantize(g, x, p, q, O, xr);
+      if (!O && g.K > 0) C = rank_of(g, x) != rank_of(g, xr);
+      if (O || C) { xr = x; q = 0; }
+      E = O || C;
+      zz = ((uint32_t)q << 1) ^ (uint32_t)(q >> 31);
+      const uint32_t ro = ord_of(xr), xo = ord_of(x);
+      acc.rmin = min(acc.rmin, ro); acc.rmax = max(acc.rmax, ro);
+      acc.xmin = min(acc.xmin, xo); acc.xmax = max(acc.xmax, xo);
+      acc.nonfinite |= !isfinite(x);
+      if (w < ownz && y < owny && xx < ownx) { acc.nO += O; acc.nC += C; }
+      if (AUX) {
+        const size_t gi = ((size_t)(bp.o[0] + w) * n1 + y) * n2 + xx;
+        if (P.codes) P.codes[gi] = q;
+        if (P.flags) P.flags[gi] = (uint8_t)(O | (C << 1));
+      }
+    }
+    pack_chunk(P, slot0 + c, zz, E, x, pack[wave]);
   }
   part_store(acc, &P.part[b * P.part_per_block + blockIdx.x]);
 }
@@ -516,8 +625,17 @@ void launch_encode(const EncPlan &p, int64_t, U4 *scan_tmp, uint64_t *scan_tmp64
     prof_mark("k_encode_coarse", s, 1);
   }
   if (gx > 0) {
+    // the level-0 kernel addresses a block's slab of planes with 32-bit offsets
+    int64_t o[3], hi[3];
+    block_ext(g, 0, o, hi);
+    const bool slab32 = (double)(hi[0] - o[0] + 1) * (double)g.n[1] * (double)g.n[2] < 4294967296.0;
     prof_mark("k_encode_fine", s, 0);
-    k_encode_fine<<<dim3((unsigned)gx, (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
+    if (L >= 1 && slab32 && !p.codes && !p.flags)
+      k_encode_l0<false><<<dim3((unsigned)gx, (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
+    else if (L >= 1 && slab32)
+      k_encode_l0<true><<<dim3((unsigned)gx, (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
+    else
+      k_encode_fine<<<dim3((unsigned)gx, (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
     prof_mark("k_encode_fine", s, 1);
   }
   scan_u4(p.cnt, p.P, p.nslots, scan_tmp, s);
