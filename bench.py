@@ -50,6 +50,9 @@ def parse_args():
     ap.add_argument("--cpu-planes", type=int, default=0,
                     help="z-planes of the field the oracle baseline runs on (0: automatic)")
     ap.add_argument("--kernel", default="", help="kernel timed with HIP events (default: the dominant one)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one plain device copy of the field (4N bytes read, 4N written) before the timed "
+                         "region, as the reference for scaling hardware traffic counters")
     return ap.parse_args()
 
 
@@ -139,6 +142,12 @@ def main():
         ev[2].record(stream)
         for j, k in enumerate(isos):
             api.iso_extract(recon, k, 1.0, verts, tris, counts[j], mws)
+
+    if args.calib_copy:
+        scratch = torch.empty_like(x)
+        scratch.copy_(x)
+        torch.cuda.synchronize()
+        del scratch
 
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     for _ in range(args.warmup):

@@ -135,7 +135,8 @@ EncLayout enc_layout(EncPlan &P) {
   Lo.off_pay = o; o = align256(o + sizeof(uint32_t) * 32 * (size_t)P.nslots);
   Lo.off_emask = o; o = align256(o + sizeof(uint64_t) * (size_t)P.nslots);
   Lo.off_exv = o; o = align256(o + sizeof(float) * 64 * (size_t)P.nslots);
-  P.part_per_block = encode_fine_groups(P) + 1;
+  P.part_l1 = encode_fine_groups(P);
+  P.part_per_block = P.part_l1 + encode_l1_groups(P) + 1;
   encode_pack_layout(P);
   Lo.off_part = o; o = align256(o + sizeof(Part) * (size_t)(g.nblocks * P.part_per_block));
   Lo.off_bst = o; o = align256(o + sizeof(Part) * (size_t)g.nblocks);
@@ -439,12 +440,14 @@ int chr_reconstruct(const chr_info *info, const void *d_stream, size_t stream_by
   return check_hip("chr_reconstruct launch");
 }
 
-static int mc_plan(const float *d_field, const int64_t dims[3], McPlan &M, size_t &need, size_t off[5]) {
+static int mc_plan(const float *d_field, const int64_t dims[3], McPlan &M, size_t &need, size_t off[6]) {
   std::memset(&M, 0, sizeof(M));
   if (!dims_ok(dims)) return fail(CHR_E_INVAL, "dims must be in [1, 2^30]");
   for (int a = 0; a < 3; a++) M.n[a] = dims[a];
   M.nrows = dims[0] * dims[1];
   M.nw = ceil_div(dims[2], 64);
+  if ((double)M.nrows * (double)M.nw * 64.0 >= 4294967296.0)
+    return fail(CHR_E_INVAL, "field too large for marching cubes (2^32 padded points)");
   M.f = d_field;
   size_t o = 0;
   off[0] = o; o = align256(o + 8 * (size_t)(M.nrows * M.nw));
@@ -452,13 +455,15 @@ static int mc_plan(const float *d_field, const int64_t dims[3], McPlan &M, size_
   off[1] = o; o = align256(o + sizeof(U4) * (size_t)nwords);
   off[2] = o; o = align256(o + sizeof(U4) * (size_t)(nwords + 1));
   off[3] = o; o = align256(o + sizeof(U4) * (size_t)scan_tmp_elems(nwords));
+  off[4] = o; o = align256(o + sizeof(uint32_t) * (size_t)(nwords * 64));
+  off[5] = o; o = align256(o + sizeof(uint2) * (size_t)(nwords * 64));
   need = o;
   return CHR_OK;
 }
 
 size_t iso_workspace(const int64_t dims[3]) {
   McPlan M;
-  size_t need = 0, off[5];
+  size_t need = 0, off[6];
   if (mc_plan(nullptr, dims, M, need, off)) return 0;
   return need;
 }
@@ -470,7 +475,7 @@ int iso_extract(const float *d_field, const int64_t dims[3], float isovalue, flo
   if (cap_v < 0 || cap_t < 0 || (cap_v && !d_vertices) || (cap_t && !d_tris)) return fail(CHR_E_INVAL, "bad capacity");
   if (!std::isfinite(isovalue) || !std::isfinite(spacing)) return fail(CHR_E_INVAL, "isovalue and spacing must be finite");
   McPlan M;
-  size_t need = 0, off[5];
+  size_t need = 0, off[6];
   int rc = mc_plan(d_field, dims, M, need, off);
   if (rc) return rc;
   if (ws_bytes < need) return fail(CHR_E_NOMEM, "workspace too small: need " + std::to_string(need));
@@ -478,6 +483,8 @@ int iso_extract(const float *d_field, const int64_t dims[3], float isovalue, flo
   M.bits = reinterpret_cast<unsigned long long *>(ws + off[0]);
   M.cnt = reinterpret_cast<U4 *>(ws + off[1]);
   M.P = reinterpret_cast<U4 *>(ws + off[2]);
+  M.vlist = reinterpret_cast<uint32_t *>(ws + off[4]);
+  M.clist = reinterpret_cast<uint2 *>(ws + off[5]);
   M.k = isovalue;
   M.spacing = spacing;
   M.verts = d_vertices;
@@ -493,7 +500,7 @@ int iso_cases(const float *d_field, const int64_t dims[3], float isovalue, uint8
               size_t ws_bytes, void *stream) {
   if (!d_field || !d_cases || !d_ws) return fail(CHR_E_INVAL, "NULL argument");
   McPlan M;
-  size_t need = 0, off[5];
+  size_t need = 0, off[6];
   int rc = mc_plan(d_field, dims, M, need, off);
   if (rc) return rc;
   if (ws_bytes < need) return fail(CHR_E_NOMEM, "workspace too small");

@@ -206,6 +206,18 @@ __device__ inline BlockPos block_pos(const Geo &g, const L0Geo &G, uint32_t b) {
   return p;
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin by linear id.  This
+// maps linear id i of a 2D grid to logical work so that each XCD receives a
+// contiguous eighth of the work (its L2 then sees neighbouring data).
+__device__ inline void xcd_remap(uint32_t &bx, uint32_t &by) {
+  const uint32_t gx = gridDim.x, n = gridDim.x * gridDim.y;
+  const uint32_t i = blockIdx.y * gx + blockIdx.x;
+  const uint32_t n8 = n >> 3;
+  const uint32_t l = (i < (n8 << 3)) ? (i & 7u) * n8 + (i >> 3) : i;
+  by = l / gx;
+  bx = l - by * gx;
+}
+
 __host__ __device__ inline size_t pad8(size_t n) { return (n + 7) & ~(size_t)7; }
 
 __host__ __device__ inline uint64_t sec_bytes(uint64_t npts, uint64_t W, uint64_t NE, uint64_t NX) {

@@ -36,7 +36,8 @@ struct EncPlan {
   unsigned long long *emask;     // nslots
   float *exv;                    // nslots * 64
   Part *part;                    // per block: part_per_block workgroup records
-  int64_t part_per_block;        // level-0 workgroups per block + 1 (coarse levels)
+  int64_t part_per_block;        // records per block: level-0 workgroups, level-1 workgroups, coarse levels
+  int64_t part_l1;               // first level-1 record of a block
   Part *bst;                     // per block reduction of its records
   int64_t pack_base[kMaxLevels]; // first packing workgroup of each level
   int64_t pack_gpb[kMaxLevels];  // packing workgroups per block and level
@@ -67,7 +68,9 @@ struct McPlan {
   float k, spacing;
   const float *f;
   unsigned long long *bits;      // nrows * nw below-isovalue bits
-  U4 *cnt, *P;                   // per word {vertices, triangles, 0, 0} and prefix
+  U4 *cnt, *P;                   // per word {vertices, triangles, crossing points, active cells} and prefix
+  uint32_t *vlist;               // crossing points (word*64 + bit)
+  uint2 *clist;                  // active cells (word*64 + bit, first triangle id)
   float *verts;
   int32_t *tris;
   int64_t cap_v, cap_t;
@@ -83,6 +86,7 @@ void prof_mark(const char *kernel, hipStream_t s, int end);
 void launch_encode(const EncPlan &p, int64_t scan_tmp_elems_u4, U4 *scan_tmp, uint64_t *scan_tmp64,
                    hipStream_t s);
 int64_t encode_fine_groups(const EncPlan &p);   // level-0 workgroups per block
+int64_t encode_l1_groups(const EncPlan &p);     // level-1 workgroups per block
 void encode_pack_layout(EncPlan &p);            // fills pack_base / pack_gpb
 void launch_decode(const DecPlan &p, hipStream_t s);
 void launch_mc(const McPlan &p, U4 *scan_tmp, hipStream_t s);

@@ -98,10 +98,12 @@ __device__ inline void set_status(const DecPlan &D, int32_t code) {
   if (D.status) atomicMin(D.status, code);
 }
 
-// Decodes tile t of a section; calls emit(z, y, x, value) for every point.
+// Decodes chunks [kbeg, kend) of tile t of a section (every lane of the
+// wave takes part in the tile's offset scan); calls emit(z, y, x, value) for
+// every point.
 template <class Emit>
 __device__ void dec_tile(const DecPlan &D, const SecView &v, int l, const int64_t o[3], const Sec &s, uint32_t t,
-                         Emit emit) {
+                         uint32_t kbeg, uint32_t kend, Emit emit) {
   const Geo &g = D.g;
   const int L = g.nL - 1;
   const int lane = lane_id();
@@ -124,10 +126,10 @@ __device__ void dec_tile(const DecPlan &D, const SecView &v, int l, const int64_
     set_status(D, -4);
     return;
   }
-  const uint32_t nc = min(64u, v.nch - t * 64);
+  const uint32_t nc = min(min(64u, v.nch - t * 64), kend);
   const float *Gp = (l < L) ? D.gp[l + 1] : nullptr;
   const uint32_t g0 = (uint32_t)D.gd[l + 1][0], g1 = (uint32_t)D.gd[l + 1][1], g2 = (uint32_t)D.gd[l + 1][2];
-  for (uint32_t k = 0; k < nc; k++) {
+  for (uint32_t k = kbeg; k < nc; k++) {
     const uint32_t wk = rl32(w, (int)k), wok = rl32(wo, (int)k), xok = rl32(xo, (int)k);
     const uint64_t emk = rl64(em, (int)k);
     const uint32_t j = (t * 64 + k) * 64 + (uint32_t)lane;
@@ -162,7 +164,7 @@ __global__ __launch_bounds__(kBS) void k_decode_coarse(DecPlan D) {
   const int L = g.nL - 1;
   const int64_t b = blockIdx.x;
   const int wave = threadIdx.x / kWave;
-  const int lmin = D.lo > 1 ? D.lo : 1;
+  const int lmin = D.lo > 2 ? D.lo : 2;
   int64_t o[3], hi[3];
   block_ext(g, b, o, hi);
   for (int l = L; l >= lmin; l--) {
@@ -184,7 +186,7 @@ __global__ __launch_bounds__(kBS) void k_decode_coarse(DecPlan D) {
       if (threadIdx.x == 0) set_status(D, -4);
     } else {
       for (uint32_t t = wave; t < v.ntile; t += kWaves)
-        dec_tile(D, v, l, o, s, t, [&](uint32_t z, uint32_t y, uint32_t x, float r) {
+        dec_tile(D, v, l, o, s, t, 0u, 64u, [&](uint32_t z, uint32_t y, uint32_t x, float r) {
           dst[((size_t)(z >> l) * (uint32_t)gd[1] + (y >> l)) * (uint32_t)gd[2] + (x >> l)] = r;
         });
     }
@@ -216,7 +218,7 @@ __global__ __launch_bounds__(kBS) void k_decode_fine(DecPlan D) {
   const float *G1 = (L >= 1) ? D.gp[1] : nullptr;
   const int64_t *gd1 = D.gd[1];
   float *out = D.out;
-  dec_tile(D, v, 0, o, s, t, [&](uint32_t z, uint32_t y, uint32_t x, float r) {
+  dec_tile(D, v, 0, o, s, t, 0u, 64u, [&](uint32_t z, uint32_t y, uint32_t x, float r) {
     if (z >= ez || y >= ey) return;
     float *row = out + ((size_t)z * (uint32_t)n1 + y) * (uint32_t)n2;
     if (x < ex) row[x] = r;
@@ -229,6 +231,42 @@ __global__ __launch_bounds__(kBS) void k_decode_fine(DecPlan D) {
   });
 }
 
+// Level 1 (nL >= 2) over (tiles, blocks): one workgroup per tile, each wave
+// 16 of its chunks; the block's level-2 points are copied into the level-1
+// grid (the output when level 1 is requested) by the same workgroups.
+__global__ __launch_bounds__(kBS) void k_decode_l1(DecPlan D) {
+  const Geo &g = D.g;
+  const int L = g.nL - 1;
+  uint32_t t, b;
+  xcd_remap(t, b);
+  const int wave = threadIdx.x / kWave;
+  int64_t o[3], hi[3];
+  block_ext(g, b, o, hi);
+  float *dst = D.gp[1];
+  const int64_t *gd = D.gd[1];
+  if (L >= 2) {
+    const int sh = 2;
+    const int64_t c0 = ((hi[0] - o[0]) >> sh) + 1, c1 = ((hi[1] - o[1]) >> sh) + 1, c2 = ((hi[2] - o[2]) >> sh) + 1;
+    const float *src = D.gp[2];
+    for (int64_t i = (int64_t)t * kBS + threadIdx.x; i < c0 * c1 * c2; i += (int64_t)gridDim.x * kBS) {
+      const int64_t u = i % c2, v = (i / c2) % c1, w = i / (c2 * c1);
+      const int64_t zc = (o[0] >> sh) + w, yc = (o[1] >> sh) + v, xc = (o[2] >> sh) + u;
+      dst[((2 * zc) * gd[1] + 2 * yc) * gd[2] + 2 * xc] = src[(zc * D.gd[2][1] + yc) * D.gd[2][2] + xc];
+    }
+  }
+  const Sec s = sec_geom(o, hi, 1, L);
+  const uint32_t nch = (s.npts + 63) / 64;
+  if (t >= (nch + 63) / 64) return;
+  const SecView v = open_section(D, b, 1, s.npts);
+  if (!v.ok) {
+    if (threadIdx.x == 0) set_status(D, -4);
+    return;
+  }
+  dec_tile(D, v, 1, o, s, t, wave * 16u, wave * 16u + 16u, [&](uint32_t z, uint32_t y, uint32_t x, float r) {
+    dst[((size_t)(z >> 1) * (uint32_t)gd[1] + (y >> 1)) * (uint32_t)gd[2] + (x >> 1)] = r;
+  });
+}
+
 // Level 0 below a coarser level (nL >= 2) over (tile groups, blocks): one
 // wave per tile, block geometry from the host-filled shape table, and
 // block-relative 32-bit offsets from uniform base pointers (the block's first
@@ -236,8 +274,9 @@ __global__ __launch_bounds__(kBS) void k_decode_fine(DecPlan D) {
 // owns, plus the even points of even rows taken from level 1.
 __global__ __launch_bounds__(kBS) void k_decode_l0(DecPlan D) {
   const Geo &g = D.g;
-  const uint32_t b = blockIdx.y;
-  const uint32_t t = blockIdx.x * kWaves + threadIdx.x / kWave;
+  uint32_t t, b;
+  xcd_remap(t, b);
+  const uint32_t kbeg = (threadIdx.x / kWave) * 16u;
   const int lane = lane_id();
   const BlockPos bp = block_pos(g, D.l0, b);
   const Sec &s = D.l0.sec[bp.cls];
@@ -277,11 +316,11 @@ __global__ __launch_bounds__(kBS) void k_decode_l0(DecPlan D) {
     set_status(D, -4);
     return;
   }
-  const uint32_t nc = min(64u, v.nch - t * 64);
+  const uint32_t nc = min(min(64u, v.nch - t * 64), kbeg + 16u);
   const uint8_t *pay = v.p + v.Poff;
   const uint32_t *exv = reinterpret_cast<const uint32_t *>(v.p + v.Xoff);
 #pragma unroll 1
-  for (uint32_t k = 0; k < nc; k++) {
+  for (uint32_t k = kbeg; k < nc; k++) {
     const uint32_t wk = rl32(w, (int)k), wok = rl32(wo, (int)k), xok = rl32(xo, (int)k);
     const uint64_t emk = rl64(em, (int)k);
     const uint32_t j = (t * 64 + k) * 64 + (uint32_t)lane;
@@ -353,22 +392,30 @@ __global__ __launch_bounds__(kBS) void k_decode_thin(DecPlan D) {
 void launch_decode(const DecPlan &p, hipStream_t s) {
   const Geo &g = p.g;
   const int L = g.nL - 1;
-  if (L >= 1) {
+  int64_t o[3], hi[3];
+  block_ext(g, 0, o, hi);  // the first block is the largest
+  if (L >= 2 && p.lo <= L) {
     prof_mark("k_decode_coarse", s, 0);
     k_decode_coarse<<<dim3((unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
     prof_mark("k_decode_coarse", s, 1);
   }
+  if (L >= 1 && p.lo <= 1) {
+    const Sec s1 = sec_geom(o, hi, 1, L);
+    const int64_t nt1 = ceil_div(ceil_div(s1.npts, 64), 64);
+    prof_mark("k_decode_l1", s, 0);
+    k_decode_l1<<<dim3((unsigned)(nt1 > 0 ? nt1 : 1), (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
+    prof_mark("k_decode_l1", s, 1);
+  }
   if (p.lo == 0) {
-    // the largest level-0 section belongs to the first block
-    int64_t o[3], hi[3];
-    block_ext(g, 0, o, hi);
     const Sec s0 = sec_geom(o, hi, 0, L);
     const int64_t ntile = ceil_div(ceil_div(s0.npts, 64), 64);
     const bool slab32 = (double)(hi[0] - o[0] + 1) * (double)g.n[1] * (double)g.n[2] < 4294967296.0;
-    const dim3 grid((unsigned)ceil_div(ntile > 0 ? ntile : 1, kWaves), (unsigned)g.nblocks);
     prof_mark("k_decode_fine", s, 0);
-    if (L >= 1 && slab32) k_decode_l0<<<grid, dim3(kBS), 0, s>>>(p);
-    else k_decode_fine<<<grid, dim3(kBS), 0, s>>>(p);
+    if (L >= 1 && slab32) {
+      k_decode_l0<<<dim3((unsigned)(ntile > 0 ? ntile : 1), (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
+    } else {
+      k_decode_fine<<<dim3((unsigned)ceil_div(ntile > 0 ? ntile : 1, kWaves), (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
+    }
     prof_mark("k_decode_fine", s, 1);
     if (L >= 1) {
       prof_mark("k_decode_thin", s, 0);

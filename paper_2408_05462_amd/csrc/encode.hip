@@ -189,7 +189,7 @@ __device__ inline void owned_end(const Geo &g, const int64_t o[3], int64_t own[3
   for (int a = 0; a < 3; a++) own[a] = (o[a] + g.B < g.n[a] - 1) ? o[a] + g.B : g.n[a];
 }
 
-// Levels nL-1 .. 1 of one block per workgroup.
+// Levels nL-1 .. 2 of one block per workgroup.
 __global__ __launch_bounds__(kBS) void k_encode_coarse(EncPlan P) {
   __shared__ uint32_t pack[kWaves][32];
   const Geo &g = P.g;
@@ -201,7 +201,7 @@ __global__ __launch_bounds__(kBS) void k_encode_coarse(EncPlan P) {
   owned_end(g, o, own);
   Part acc;
   part_init(acc);
-  for (int l = L; l >= 1; l--) {
+  for (int l = L; l >= 2; l--) {
     if (l < L) {
       // the block's points of the coarser grid carry over unchanged
       const int sh = l + 1;
@@ -224,6 +224,43 @@ __global__ __launch_bounds__(kBS) void k_encode_coarse(EncPlan P) {
     __syncthreads();
   }
   part_store(acc, &P.part[b * P.part_per_block + (P.part_per_block - 1)]);
+}
+
+// Level 1 over (chunk groups, blocks); the block's level-2 points are
+// copied into the level-1 grid by the same workgroups.
+__global__ __launch_bounds__(kBS) void k_encode_l1(EncPlan P) {
+  __shared__ uint32_t pack[kWaves][32];
+  const Geo &g = P.g;
+  const int L = g.nL - 1;
+  uint32_t bx, by;
+  xcd_remap(bx, by);
+  const int64_t b = by;
+  const int wave = threadIdx.x / kWave;
+  int64_t o[3], hi[3], own[3];
+  block_ext(g, b, o, hi);
+  owned_end(g, o, own);
+  if (L >= 2) {
+    const int sh = 2;
+    const int64_t c0 = ((hi[0] - o[0]) >> sh) + 1, c1 = ((hi[1] - o[1]) >> sh) + 1, c2 = ((hi[2] - o[2]) >> sh) + 1;
+    const float *src = P.G + P.g_off[2];
+    float *dst = P.G + P.g_off[1];
+    for (int64_t i = (int64_t)bx * kBS + threadIdx.x; i < c0 * c1 * c2; i += (int64_t)gridDim.x * kBS) {
+      const int64_t u = i % c2, v = (i / c2) % c1, w = i / (c2 * c1);
+      const int64_t zc = (o[0] >> sh) + w, yc = (o[1] >> sh) + v, xc = (o[2] >> sh) + u;
+      dst[((2 * zc) * P.gd[1][1] + 2 * yc) * P.gd[1][2] + 2 * xc] = src[(zc * P.gd[2][1] + yc) * P.gd[2][2] + xc];
+    }
+  }
+  const Sec s = sec_geom(o, hi, 1, L);
+  const uint32_t nch = (s.npts + 63) / 64;
+  Part acc;
+  part_init(acc);
+  for (int k = 0; k < kChunksPerWave; k++) {
+    const uint32_t c = (bx * kChunksPerWave + k) * kWaves + wave;
+    if (c >= P.maxch[1]) break;
+    if (c < nch) enc_chunk(P, 1, b, o, own, s, c, pack[wave], acc);
+    else zero_slot(P, 1, b, c);
+  }
+  part_store(acc, &P.part[b * P.part_per_block + P.part_l1 + bx]);
 }
 
 // Level 0: a 2D grid of (chunk groups, blocks).
@@ -285,7 +322,8 @@ template <bool AUX>
 __global__ __launch_bounds__(kBS) void k_encode_l0(EncPlan P) {
   __shared__ uint32_t pack[kWaves][32];
   const Geo &g = P.g;
-  const uint32_t b = blockIdx.y;
+  uint32_t gxi, b;
+  xcd_remap(gxi, b);
   const int wave = threadIdx.x / kWave;
   const int lane = lane_id();
   const BlockPos bp = block_pos(g, P.l0, b);
@@ -303,7 +341,7 @@ __global__ __launch_bounds__(kBS) void k_encode_l0(EncPlan P) {
   part_init(acc);
 #pragma unroll 1
   for (int k = 0; k < kChunksPerWave; k++) {
-    const uint32_t c = (blockIdx.x * kChunksPerWave + k) * kWaves + wave;
+    const uint32_t c = (gxi * kChunksPerWave + k) * kWaves + wave;
     if (c >= P.maxch[0]) break;
     if (c >= nch) {
       if (lane == 0) P.cnt[slot0 + c] = U4{0, 0, 0, 0};
@@ -355,7 +393,7 @@ __global__ __launch_bounds__(kBS) void k_encode_l0(EncPlan P) {
     }
     pack_chunk(P, slot0 + c, zz, E, x, pack[wave]);
   }
-  part_store(acc, &P.part[b * P.part_per_block + blockIdx.x]);
+  part_store(acc, &P.part[(int64_t)b * P.part_per_block + gxi]);
 }
 
 // Byte size of every section from the scanned chunk sizes.
@@ -488,7 +526,7 @@ __device__ uint32_t block_sum(uint32_t v) {
 
 // Block table: folds the block's workgroup records (min/max of the
 // reconstructed values, input range, counts) and checksums its byte range.
-__global__ __launch_bounds__(kBS) void k_block_table(EncPlan P, int64_t nfine, int has_coarse) {
+__global__ __launch_bounds__(kBS) void k_block_table(EncPlan P) {
   const Geo &g = P.g;
   const int64_t b = blockIdx.x;
   const uint64_t total = P.payload_off + P.secoff[g.nblocks * g.nL];
@@ -503,8 +541,13 @@ __global__ __launch_bounds__(kBS) void k_block_table(EncPlan P, int64_t nfine, i
   Part acc;
   part_init(acc);
   const Part *rec = P.part + b * P.part_per_block;
-  for (int64_t i = threadIdx.x; i < nfine + (has_coarse ? 1 : 0); i += kBS) {
-    const Part r = rec[i < nfine ? i : P.part_per_block - 1];
+  const int L = g.nL - 1;
+  for (int64_t i = threadIdx.x; i < P.part_per_block; i += kBS) {
+    // records exist for level-0 workgroups, level-1 workgroups (nL >= 2) and
+    // the coarse-level workgroup (nL >= 3)
+    if (i == P.part_per_block - 1 && L < 2) continue;
+    if (i >= P.part_l1 && i < P.part_per_block - 1 && L < 1) continue;
+    const Part r = rec[i];
     acc.rmin = min(acc.rmin, r.rmin); acc.rmax = max(acc.rmax, r.rmax);
     acc.xmin = min(acc.xmin, r.xmin); acc.xmax = max(acc.xmax, r.xmax);
     acc.nonfinite |= r.nonfinite; acc.nO += r.nO; acc.nC += r.nC;
@@ -602,6 +645,9 @@ __global__ __launch_bounds__(kBS) void k_header(EncPlan P) {
 }  // namespace
 
 int64_t encode_fine_groups(const EncPlan &p) { return ceil_div(p.maxch[0], (int64_t)kChunksPerWG); }
+int64_t encode_l1_groups(const EncPlan &p) {
+  return p.g.nL >= 2 ? ceil_div(p.maxch[1] > 0 ? p.maxch[1] : 1, (int64_t)kChunksPerWG) : 0;
+}
 
 void encode_pack_layout(EncPlan &p) {
   const int L = p.g.nL - 1;
@@ -619,10 +665,15 @@ void launch_encode(const EncPlan &p, int64_t, U4 *scan_tmp, uint64_t *scan_tmp64
   const int L = g.nL - 1;
   const int64_t nsec = g.nblocks * g.nL;
   const int64_t gx = encode_fine_groups(p);
-  if (L >= 1) {
+  if (L >= 2) {
     prof_mark("k_encode_coarse", s, 0);
     k_encode_coarse<<<dim3((unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
     prof_mark("k_encode_coarse", s, 1);
+  }
+  if (L >= 1) {
+    prof_mark("k_encode_l1", s, 0);
+    k_encode_l1<<<dim3((unsigned)encode_l1_groups(p), (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
+    prof_mark("k_encode_l1", s, 1);
   }
   if (gx > 0) {
     // the level-0 kernel addresses a block's slab of planes with 32-bit offsets
@@ -653,7 +704,7 @@ void launch_encode(const EncPlan &p, int64_t, U4 *scan_tmp, uint64_t *scan_tmp64
     prof_mark("k_pack", s, 1);
   }
   prof_mark("k_block_table", s, 0);
-  k_block_table<<<dim3((unsigned)g.nblocks), dim3(kBS), 0, s>>>(p, gx, L >= 1 ? 1 : 0);
+  k_block_table<<<dim3((unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
   prof_mark("k_block_table", s, 1);
   prof_mark("k_header", s, 0);
   k_header<<<dim3(1), dim3(kBS), 0, s>>>(p);

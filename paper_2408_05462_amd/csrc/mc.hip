@@ -3,16 +3,17 @@
 //
 // The field is reduced once to one bit per point (f < k) in 64-bit words
 // along x; everything after that works on words:
-//  1. k_mc_bits:  coalesced streaming pass, a ballot per 64 points.
-//  2. k_mc_count: one lane per word: the word's crossing +x/+y/+z edges
-//     (XORs of neighbouring words, popcount) and the triangles of the word's
-//     active cells (cells whose 8 corners disagree, iterated as set bits;
-//     triangle count from the generated table in LDS).
-//  3. scan of the per-word {vertices, triangles}.
-//  4. k_mc_emit:  one lane per word: vertices in (point, axis) order, then
-//     triangles in (cell, table order) order; the id of the vertex on an edge
-//     owned by point x' of word W is W's vertex base plus the popcount of W's
-//     crossing masks below x' -- no per-point id array.
+//  1. k_mc_bits:   coalesced streaming pass, a ballot per 64 points.
+//  2. k_mc_count:  one lane per word: its crossing +x/+y/+z edges (XORs of
+//     neighbouring words, popcount), the points carrying them, its active
+//     cells (corners disagree) and their triangles (generated table in LDS).
+//  3. scan of the per-word {vertices, triangles, crossing points, active cells}.
+//  4. k_mc_expand: one lane per word writes compact lists of its crossing
+//     points and of its active cells (with each cell's first triangle id).
+//  5. k_mc_verts / k_mc_tris: one lane per list entry, so lanes stay dense
+//     however sparse the surface is.  The id of the vertex on an edge owned by
+//     point x' of word W is W's vertex base plus the popcount of W's crossing
+//     masks below x' -- no per-point id array.
 #include "chr_plan.h"
 #include "mc_table.h"
 
@@ -21,41 +22,36 @@ namespace {
 
 constexpr int kBS = 256;
 constexpr int kWaves = kBS / kWave;
-constexpr int kWordsPerWave = 16;
+constexpr int kWordsPerWave = 8;
 
 constexpr mct::Table kTable = mct::make_table();
 __constant__ mct::Table c_table = kTable;
 
 typedef unsigned long long u64;
 
-// f < k for 64 consecutive points per word; a wave covers kWordsPerWave
-// words with all loads issued before the ballots.
+// f < k for 64 consecutive points per word.  One wave per row of points;
+// it issues the loads of kWordsPerWave words before their ballots.
 __global__ __launch_bounds__(kBS) void k_mc_bits(McPlan M) {
-  const int64_t nwords = M.nrows * M.nw;
-  const int64_t w0 = ((int64_t)blockIdx.x * kWaves + threadIdx.x / kWave) * kWordsPerWave;
-  if (w0 >= nwords) return;
+  const int64_t row = (int64_t)blockIdx.x * kWaves + threadIdx.x / kWave;
+  if (row >= M.nrows) return;
   const int lane = lane_id();
-  const int64_t nx = M.n[2];
-  float v[kWordsPerWave];
+  const uint32_t nx = (uint32_t)M.n[2], nw = (uint32_t)M.nw;
+  const float *__restrict__ f = M.f + row * M.n[2];
+  u64 *out = M.bits + row * M.nw;
+  const float k = M.k;
+  for (uint32_t w0 = 0; w0 < nw; w0 += kWordsPerWave) {
+    float v[kWordsPerWave];
 #pragma unroll
-  for (int k = 0; k < kWordsPerWave; k++) {
-    const int64_t wi = w0 + k;
-    v[k] = 0.f;
-    if (wi < nwords) {
-      const int64_t row = wi / M.nw, x = (wi - row * M.nw) * 64 + lane;
-      if (x < nx) v[k] = M.f[row * nx + x];
+    for (int j = 0; j < kWordsPerWave; j++) {
+      const uint32_t x = (w0 + j) * 64u + (uint32_t)lane;
+      v[j] = (x < nx) ? f[x] : 0.f;
     }
-  }
 #pragma unroll
-  for (int k = 0; k < kWordsPerWave; k++) {
-    const int64_t wi = w0 + k;
-    bool below = false;
-    if (wi < nwords) {
-      const int64_t row = wi / M.nw, x = (wi - row * M.nw) * 64 + lane;
-      below = (x < nx) && (v[k] < M.k);
+    for (int j = 0; j < kWordsPerWave; j++) {
+      const uint32_t x = (w0 + j) * 64u + (uint32_t)lane;
+      const u64 m = __ballot((x < nx) && (v[j] < k));
+      if (lane == 0 && w0 + j < nw) out[w0 + j] = m;
     }
-    const u64 m = __ballot(below);
-    if (lane == 0 && wi < nwords) M.bits[wi] = m;
   }
 }
 
@@ -142,17 +138,19 @@ __global__ __launch_bounds__(kBS) void k_mc_count(McPlan M) {
   const WordCtx c = word_ctx(M, gw);
   const Cross x = cross_of(M, c.z, c.y, c.w);
   const uint32_t nv = (uint32_t)(__popcll(x.cx) + __popcll(x.cy) + __popcll(x.cz));
-  uint32_t nt = 0;
+  const uint32_t npv = (uint32_t)__popcll(x.cx | x.cy | x.cz);
+  uint32_t nt = 0, nac = 0;
   if (c.y + 1 < M.n[1] && c.z + 1 < M.n[0]) {
     const Corners C = corners_of(M, c.row, c.w);
     u64 act = active_cells(C, c.validx);
+    nac = (uint32_t)__popcll(act);
     while (act) {
       const int i = __ffsll((long long)act) - 1;
       act &= act - 1;
       nt += ntri[case_at(C, i)];
     }
   }
-  M.cnt[gw] = U4{nv, nt, 0u, 0u};
+  M.cnt[gw] = U4{nv, nt, npv, nac};
 }
 
 __device__ inline float interp(float fa, float fb, float k) {
@@ -171,7 +169,87 @@ __device__ inline int popc3_below(const Cross &c, int x) {
   return __popcll(c.cx & bm) + __popcll(c.cy & bm) + __popcll(c.cz & bm);
 }
 
-__global__ __launch_bounds__(kBS) void k_mc_emit(McPlan M) {
+// Lists the word's crossing points and active cells (each cell with the id
+// of its first triangle).  Entries are word*64 + bit.
+__global__ __launch_bounds__(kBS) void k_mc_expand(McPlan M) {
+  __shared__ uint8_t ntri[256];
+  for (int i = threadIdx.x; i < 256; i += kBS) ntri[i] = c_table.ntri[i];
+  __syncthreads();
+  const int64_t gw = (int64_t)blockIdx.x * kBS + threadIdx.x;
+  if (gw >= M.nrows * M.nw) return;
+  const U4 p0 = M.P[gw], p1 = M.P[gw + 1];
+  if (p1.z != p0.z) {
+    const WordCtx c = word_ctx(M, gw);
+    const Cross x = cross_of(M, c.z, c.y, c.w);
+    u64 pts = x.cx | x.cy | x.cz;
+    uint32_t r = p0.z;
+    while (pts) {
+      const int i = __ffsll((long long)pts) - 1;
+      pts &= pts - 1;
+      M.vlist[r++] = (uint32_t)(gw * 64 + i);
+    }
+  }
+  if (p1.w != p0.w) {
+    const WordCtx c = word_ctx(M, gw);
+    const Corners C = corners_of(M, c.row, c.w);
+    u64 act = active_cells(C, c.validx);
+    uint32_t r = p0.w, t = p0.y;
+    while (act) {
+      const int i = __ffsll((long long)act) - 1;
+      act &= act - 1;
+      M.clist[r++] = make_uint2((uint32_t)(gw * 64 + i), t);
+      t += ntri[case_at(C, i)];
+    }
+  }
+}
+
+// One lane per crossing point: its vertices in axis order x, y, z.
+__global__ __launch_bounds__(kBS) void k_mc_verts(McPlan M) {
+  const int64_t nwords = M.nrows * M.nw;
+  const uint32_t n = M.P[nwords].z;
+  const int64_t n1 = M.n[1], n2 = M.n[2];
+  const float *f = M.f;
+  const float k = M.k, sp = M.spacing;
+  for (uint32_t e = blockIdx.x * kBS + threadIdx.x; e < n; e += gridDim.x * kBS) {
+    const uint32_t code = M.vlist[e];
+    const int64_t gw = code >> 6;
+    const int i = code & 63;
+    const WordCtx c = word_ctx(M, gw);
+    const Cross x = cross_of(M, c.z, c.y, c.w);
+    uint64_t id = M.P[gw].x + popc3_below(x, i);
+    const int64_t xx = c.w * 64 + i;
+    const size_t gi = ((size_t)c.z * n1 + c.y) * n2 + xx;
+    const float fa = f[gi];
+    const float px = (float)xx, py = (float)c.y, pz = (float)c.z;
+    if ((x.cx >> i) & 1ull) {
+      if ((int64_t)id < M.cap_v) {
+        const float t = interp(fa, f[gi + 1], k);
+        float *v = M.verts + 3 * id;
+        v[0] = __fmul_rn(__fadd_rn(px, t), sp); v[1] = __fmul_rn(py, sp); v[2] = __fmul_rn(pz, sp);
+      }
+      id++;
+    }
+    if ((x.cy >> i) & 1ull) {
+      if ((int64_t)id < M.cap_v) {
+        const float t = interp(fa, f[gi + n2], k);
+        float *v = M.verts + 3 * id;
+        v[0] = __fmul_rn(px, sp); v[1] = __fmul_rn(__fadd_rn(py, t), sp); v[2] = __fmul_rn(pz, sp);
+      }
+      id++;
+    }
+    if ((x.cz >> i) & 1ull) {
+      if ((int64_t)id < M.cap_v) {
+        const float t = interp(fa, f[gi + (size_t)n1 * n2], k);
+        float *v = M.verts + 3 * id;
+        v[0] = __fmul_rn(px, sp); v[1] = __fmul_rn(py, sp); v[2] = __fmul_rn(__fadd_rn(pz, t), sp);
+      }
+    }
+  }
+}
+
+// One lane per active cell: its triangles in table order, each corner the id
+// of the vertex on the cell edge it names.
+__global__ __launch_bounds__(kBS) void k_mc_tris(McPlan M) {
   __shared__ mct::Table tab;
   {
     const uint8_t *src = reinterpret_cast<const uint8_t *>(&c_table);
@@ -179,98 +257,57 @@ __global__ __launch_bounds__(kBS) void k_mc_emit(McPlan M) {
     for (int i = threadIdx.x; i < (int)sizeof(mct::Table); i += kBS) dst[i] = src[i];
   }
   __syncthreads();
-  const int64_t gw = (int64_t)blockIdx.x * kBS + threadIdx.x;
-  if (gw >= M.nrows * M.nw) return;
-  const U4 p0 = M.P[gw], p1 = M.P[gw + 1];
-  if (p0.x == p1.x && p0.y == p1.y) return;
-  const WordCtx c = word_ctx(M, gw);
-  const int64_t n1 = M.n[1], n2 = M.n[2];
-  const float *f = M.f;
-  const float k = M.k, sp = M.spacing;
-
-  // vertices of this word's points, in (point, axis) order
-  if (p1.x != p0.x) {
-    const Cross x = cross_of(M, c.z, c.y, c.w);
-    uint64_t id = p0.x;
-    u64 pts = x.cx | x.cy | x.cz;
-    const float py = (float)c.y, pz = (float)c.z;
-    while (pts) {
-      const int i = __ffsll((long long)pts) - 1;
-      pts &= pts - 1;
-      const int64_t xx = c.w * 64 + i;
-      const size_t gi = ((size_t)c.z * n1 + c.y) * n2 + xx;
-      const float fa = f[gi];
-      const float px = (float)xx;
-      if ((x.cx >> i) & 1ull) {
-        if ((int64_t)id < M.cap_v) {
-          const float t = interp(fa, f[gi + 1], k);
-          float *v = M.verts + 3 * id;
-          v[0] = __fmul_rn(__fadd_rn(px, t), sp); v[1] = __fmul_rn(py, sp); v[2] = __fmul_rn(pz, sp);
-        }
-        id++;
-      }
-      if ((x.cy >> i) & 1ull) {
-        if ((int64_t)id < M.cap_v) {
-          const float t = interp(fa, f[gi + n2], k);
-          float *v = M.verts + 3 * id;
-          v[0] = __fmul_rn(px, sp); v[1] = __fmul_rn(__fadd_rn(py, t), sp); v[2] = __fmul_rn(pz, sp);
-        }
-        id++;
-      }
-      if ((x.cz >> i) & 1ull) {
-        if ((int64_t)id < M.cap_v) {
-          const float t = interp(fa, f[gi + (size_t)n1 * n2], k);
-          float *v = M.verts + 3 * id;
-          v[0] = __fmul_rn(px, sp); v[1] = __fmul_rn(py, sp); v[2] = __fmul_rn(__fadd_rn(pz, t), sp);
-        }
-        id++;
-      }
-    }
-  }
-
-  // triangles of this word's cells, in (cell, table order) order
-  if (p1.y != p0.y) {
+  const int64_t nwords = M.nrows * M.nw;
+  const uint32_t n = M.P[nwords].w;
+  const int64_t n1 = M.n[1];
+  for (uint32_t e = blockIdx.x * kBS + threadIdx.x; e < n; e += gridDim.x * kBS) {
+    const uint2 ent = M.clist[e];
+    const int64_t gw = ent.x >> 6;
+    const int i = ent.x & 63;
+    const WordCtx c = word_ctx(M, gw);
+    const Corners C = corners_of(M, c.row, c.w);
+    const uint32_t cs = case_at(C, i);
+    const int nt = tab.ntri[cs];
     const int64_t rows[4] = {c.row, c.row + 1, c.row + n1, c.row + n1 + 1};
     const int64_t ry[4] = {c.y, c.y + 1, c.y, c.y + 1}, rz[4] = {c.z, c.z, c.z + 1, c.z + 1};
-    Owner own[4];
+    Cross own0[4];
+    uint64_t vb0[4];
     for (int r = 0; r < 4; r++) {
-      own[r].c0 = cross_of(M, rz[r], ry[r], c.w);
-      own[r].c1 = cross_of(M, rz[r], ry[r], c.w + 1);
-      own[r].v0 = M.P[rows[r] * M.nw + c.w].x;
-      own[r].v1 = (c.w + 1 < M.nw) ? M.P[rows[r] * M.nw + c.w + 1].x : 0;
+      own0[r] = cross_of(M, rz[r], ry[r], c.w);
+      vb0[r] = M.P[rows[r] * M.nw + c.w].x;
     }
-    const Corners C = corners_of(M, c.row, c.w);
-    u64 act = active_cells(C, c.validx);
-    uint64_t tid = p0.y;
-    while (act) {
-      const int i = __ffsll((long long)act) - 1;
-      act &= act - 1;
-      const uint32_t cs = case_at(C, i);
-      const int nt = tab.ntri[cs];
-      for (int t = 0; t < nt; t++, tid++) {
-        int32_t ids[3];
-        for (int q = 0; q < 3; q++) {
-          const int e = tab.tri[cs][3 * t + q];
-          const int axis = e >> 2, i2 = e & 3;
-          int dx = 0, dy = 0, dz = 0;
-          if (axis == 0) { dy = i2 & 1; dz = i2 >> 1; }
-          if (axis == 1) { dx = i2 & 1; dz = i2 >> 1; }
-          if (axis == 2) { dx = i2 & 1; dy = i2 >> 1; }
-          const Owner &o = own[dy + 2 * dz];
-          const int xo = i + dx;
-          uint64_t id;
-          u64 mx, my;
-          int bit;
-          if (xo < 64) { id = o.v0 + popc3_below(o.c0, xo); mx = o.c0.cx; my = o.c0.cy; bit = xo; }
-          else { id = o.v1; mx = o.c1.cx; my = o.c1.cy; bit = 0; }
-          if (axis >= 1) id += (mx >> bit) & 1ull;
-          if (axis >= 2) id += (my >> bit) & 1ull;
-          ids[q] = (int32_t)id;
+    uint64_t tid = ent.y;
+    for (int t = 0; t < nt; t++, tid++) {
+      int32_t ids[3];
+      for (int q = 0; q < 3; q++) {
+        const int ed = tab.tri[cs][3 * t + q];
+        const int axis = ed >> 2, i2 = ed & 3;
+        int dx = 0, dy = 0, dz = 0;
+        if (axis == 0) { dy = i2 & 1; dz = i2 >> 1; }
+        if (axis == 1) { dx = i2 & 1; dz = i2 >> 1; }
+        if (axis == 2) { dx = i2 & 1; dy = i2 >> 1; }
+        const int R = dy + 2 * dz;
+        const int xo = i + dx;
+        uint64_t id;
+        u64 mx, my;
+        int bit;
+        if (xo < 64) {
+          id = vb0[R] + popc3_below(own0[R], xo);
+          mx = own0[R].cx; my = own0[R].cy; bit = xo;
+        } else {
+          // the edge's owner point starts the next word (its vertex base is
+          // that word's; it is inside the row because the cell is)
+          const Cross c1 = cross_of(M, rz[R], ry[R], c.w + 1);
+          id = M.P[rows[R] * M.nw + c.w + 1].x;
+          mx = c1.cx; my = c1.cy; bit = 0;
         }
-        if ((int64_t)tid < M.cap_t) {
-          int32_t *o = M.tris + 3 * tid;
-          o[0] = ids[0]; o[1] = ids[1]; o[2] = ids[2];
-        }
+        if (axis >= 1) id += (mx >> bit) & 1ull;
+        if (axis >= 2) id += (my >> bit) & 1ull;
+        ids[q] = (int32_t)id;
+      }
+      if ((int64_t)tid < M.cap_t) {
+        int32_t *o = M.tris + 3 * tid;
+        o[0] = ids[0]; o[1] = ids[1]; o[2] = ids[2];
       }
     }
   }
@@ -335,21 +372,28 @@ __global__ void k_range_fin(uint32_t *acc) {
 void launch_mc(const McPlan &p, U4 *scan_tmp, hipStream_t s) {
   const int64_t nwords = p.nrows * p.nw;
   prof_mark("k_mc_bits", s, 0);
-  k_mc_bits<<<dim3((unsigned)ceil_div(nwords, (int64_t)kWaves * kWordsPerWave)), dim3(kBS), 0, s>>>(p);
+  k_mc_bits<<<dim3((unsigned)ceil_div(p.nrows, kWaves)), dim3(kBS), 0, s>>>(p);
   prof_mark("k_mc_bits", s, 1);
   prof_mark("k_mc_count", s, 0);
   k_mc_count<<<dim3((unsigned)ceil_div(nwords, kBS)), dim3(kBS), 0, s>>>(p);
   prof_mark("k_mc_count", s, 1);
   scan_u4(p.cnt, p.P, nwords, scan_tmp, s);
-  prof_mark("k_mc_emit", s, 0);
-  k_mc_emit<<<dim3((unsigned)ceil_div(nwords, kBS)), dim3(kBS), 0, s>>>(p);
-  prof_mark("k_mc_emit", s, 1);
+  prof_mark("k_mc_expand", s, 0);
+  k_mc_expand<<<dim3((unsigned)ceil_div(nwords, kBS)), dim3(kBS), 0, s>>>(p);
+  prof_mark("k_mc_expand", s, 1);
+  // list lengths live on the device: a fixed grid strides over them
+  prof_mark("k_mc_verts", s, 0);
+  k_mc_verts<<<dim3(2048), dim3(kBS), 0, s>>>(p);
+  prof_mark("k_mc_verts", s, 1);
+  prof_mark("k_mc_tris", s, 0);
+  k_mc_tris<<<dim3(2048), dim3(kBS), 0, s>>>(p);
+  prof_mark("k_mc_tris", s, 1);
   k_mc_counts<<<dim3(1), dim3(64), 0, s>>>(p);
 }
 
 void launch_mc_cases(const McPlan &p, hipStream_t s) {
   const int64_t nwords = p.nrows * p.nw;
-  k_mc_bits<<<dim3((unsigned)ceil_div(nwords, (int64_t)kWaves * kWordsPerWave)), dim3(kBS), 0, s>>>(p);
+  k_mc_bits<<<dim3((unsigned)ceil_div(p.nrows, kWaves)), dim3(kBS), 0, s>>>(p);
   if (p.n[0] > 1 && p.n[1] > 1 && p.n[2] > 1)
     k_mc_cases<<<dim3((unsigned)ceil_div(nwords, kBS)), dim3(kBS), 0, s>>>(p);
 }
