@@ -279,7 +279,7 @@ __global__ __launch_bounds__(kBS) void k_decode_l0(DecPlan D) {
   const uint32_t kbeg = (threadIdx.x / kWave) * 16u;
   const int lane = lane_id();
   const BlockPos bp = block_pos(g, D.l0, b);
-  const Sec &s = D.l0.sec[bp.cls];
+  const Sec s = D.l0.sec[bp.cls];  // by value: stays in scalar registers across the stores
   const uint32_t nch = (s.npts + 63) / 64;
   if (t >= (nch + 63) / 64) return;
   const SecView v = open_section(D, b, 0, s.npts);

@@ -81,9 +81,14 @@ __device__ inline void quantize(const Geo &g, float x, float p, int32_t &q, int 
 
 // Number of candidate isovalues k with k <= v; equal counts for x and x'
 // mean x' lies on the same side of every candidate as x.
-__device__ inline int rank_of(const Geo &g, float v) {
+// KB is a compile-time bound on the number of candidates (K <= KB), so
+// the loop is fully unrolled with constant indices.
+template <int KB>
+__device__ inline int rank_of(const float (&iso)[KB], int K, float v) {
   int r = 0;
-  for (int j = 0; j < g.K; j++) r += (g.iso[j] <= v) ? 1 : 0;
+#pragma unroll
+  for (int j = 0; j < KB; j++)
+    if (j < K) r += (iso[j] <= v) ? 1 : 0;
   return r;
 }
 
@@ -115,9 +120,13 @@ __device__ void part_store(const Part &a, Part *dst) {
 }
 
 // Encodes chunk c of the level-l section of block b into its slot.
+template <int KB>
 __device__ void enc_chunk(const EncPlan &P, int l, int64_t b, const int64_t o[3], const int64_t own[3],
                           const Sec &s, uint32_t c, uint32_t *pack, Part &acc) {
   const Geo &g = P.g;
+  float iso[KB];
+#pragma unroll
+  for (int jj = 0; jj < KB; jj++) iso[jj] = g.iso[jj];
   const int L = g.nL - 1;
   const int lane = lane_id();
   const uint32_t j = c * kWave + (uint32_t)lane;
@@ -137,7 +146,7 @@ __device__ void enc_chunk(const EncPlan &P, int l, int64_t b, const int64_t o[3]
       p = predict(P.G + P.g_off[l + 1], (uint32_t)gd[0], (uint32_t)gd[1], (uint32_t)gd[2], l, z, y, xx);
     }
     quantize(g, x, p, q, O, xr);
-    if (!O && g.K > 0) C = rank_of(g, x) != rank_of(g, xr);
+    if (!O && g.K > 0) C = rank_of<KB>(iso, g.K, x) != rank_of<KB>(iso, g.K, xr);
     if (O || C) { xr = x; q = 0; }
     if (l >= 1) {
       const int64_t *gd = P.gd[l];
@@ -190,6 +199,7 @@ __device__ inline void owned_end(const Geo &g, const int64_t o[3], int64_t own[3
 }
 
 // Levels nL-1 .. 2 of one block per workgroup.
+template <int KB>
 __global__ __launch_bounds__(kBS) void k_encode_coarse(EncPlan P) {
   __shared__ uint32_t pack[kWaves][32];
   const Geo &g = P.g;
@@ -218,7 +228,7 @@ __global__ __launch_bounds__(kBS) void k_encode_coarse(EncPlan P) {
     const Sec s = sec_geom(o, hi, l, L);
     const uint32_t nch = (s.npts + 63) / 64;
     for (uint32_t c = wave; c < P.maxch[l]; c += kWaves) {
-      if (c < nch) enc_chunk(P, l, b, o, own, s, c, pack[wave], acc);
+      if (c < nch) enc_chunk<KB>(P, l, b, o, own, s, c, pack[wave], acc);
       else zero_slot(P, l, b, c);
     }
     __syncthreads();
@@ -228,6 +238,7 @@ __global__ __launch_bounds__(kBS) void k_encode_coarse(EncPlan P) {
 
 // Level 1 over (chunk groups, blocks); the block's level-2 points are
 // copied into the level-1 grid by the same workgroups.
+template <int KB>
 __global__ __launch_bounds__(kBS) void k_encode_l1(EncPlan P) {
   __shared__ uint32_t pack[kWaves][32];
   const Geo &g = P.g;
@@ -257,13 +268,14 @@ __global__ __launch_bounds__(kBS) void k_encode_l1(EncPlan P) {
   for (int k = 0; k < kChunksPerWave; k++) {
     const uint32_t c = (bx * kChunksPerWave + k) * kWaves + wave;
     if (c >= P.maxch[1]) break;
-    if (c < nch) enc_chunk(P, 1, b, o, own, s, c, pack[wave], acc);
+    if (c < nch) enc_chunk<KB>(P, 1, b, o, own, s, c, pack[wave], acc);
     else zero_slot(P, 1, b, c);
   }
   part_store(acc, &P.part[b * P.part_per_block + P.part_l1 + bx]);
 }
 
 // Level 0: a 2D grid of (chunk groups, blocks).
+template <int KB>
 __global__ __launch_bounds__(kBS) void k_encode_fine(EncPlan P) {
   __shared__ uint32_t pack[kWaves][32];
   const Geo &g = P.g;
@@ -280,7 +292,7 @@ __global__ __launch_bounds__(kBS) void k_encode_fine(EncPlan P) {
   for (int k = 0; k < kChunksPerWave; k++) {
     const uint32_t c = (blockIdx.x * kChunksPerWave + k) * kWaves + wave;
     if (c >= P.maxch[0]) break;
-    if (c < nch) enc_chunk(P, 0, b, o, own, s, c, pack[wave], acc);
+    if (c < nch) enc_chunk<KB>(P, 0, b, o, own, s, c, pack[wave], acc);
     else zero_slot(P, 0, b, c);
   }
   part_store(acc, &P.part[b * P.part_per_block + blockIdx.x]);
@@ -318,33 +330,47 @@ __device__ inline void pack_chunk(const EncPlan &P, int64_t slot, uint32_t zz, b
 // uniform base pointers (the block's first plane of the field and of the
 // level-1 grid), and the optional per-point outputs compiled in only when
 // requested.
-template <bool AUX>
+template <bool AUX, int KB>
 __global__ __launch_bounds__(kBS) void k_encode_l0(EncPlan P) {
   __shared__ uint32_t pack[kWaves][32];
-  const Geo &g = P.g;
   uint32_t gxi, b;
   xcd_remap(gxi, b);
   const int wave = threadIdx.x / kWave;
   const int lane = lane_id();
-  const BlockPos bp = block_pos(g, P.l0, b);
-  const Sec &s = P.l0.sec[bp.cls];
+  // Every uniform value the loop needs is copied into a local first, so it
+  // stays in scalar registers across the loop's stores.
+  const BlockPos bp = block_pos(P.g, P.l0, b);
+  const Sec s = P.l0.sec[bp.cls];
   const uint32_t nch = (s.npts + 63) / 64;
-  const uint32_t n1 = (uint32_t)g.n[1], n2 = (uint32_t)g.n[2];
+  const uint32_t maxch = P.maxch[0];
+  const uint32_t n1 = (uint32_t)P.g.n[1], n2 = (uint32_t)P.g.n[2];
   const uint32_t oy = bp.o[1], ox = bp.o[2];
   const float *__restrict__ xb = P.x + (size_t)bp.o[0] * n1 * n2;
   const uint32_t g0 = (uint32_t)P.gd[1][0], g1 = (uint32_t)P.gd[1][1], g2 = (uint32_t)P.gd[1][2];
   const uint32_t zg = bp.o[0] >> 1;
   const float *__restrict__ G1 = P.G + P.g_off[1] + (size_t)zg * g1 * g2;
   const uint32_t ownz = bp.own[0] - bp.o[0], owny = bp.own[1], ownx = bp.own[2];
-  const int64_t slot0 = P.slot_base[0] + (int64_t)b * P.maxch[0];
+  const int64_t slot0 = P.slot_base[0] + (int64_t)b * maxch;
+  U4 *__restrict__ cnt = P.cnt;
+  uint32_t *__restrict__ pay = P.pay;
+  unsigned long long *__restrict__ emask = P.emask;
+  float *__restrict__ exv = P.exv;
+  int32_t *codes = P.codes;
+  uint8_t *flags = P.flags;
+  const Geo &gq = P.g;
+  const int K = P.g.K;
+  float iso[KB];
+#pragma unroll
+  for (int jj = 0; jj < KB; jj++) iso[jj] = P.g.iso[jj];
   Part acc;
   part_init(acc);
 #pragma unroll 1
   for (int k = 0; k < kChunksPerWave; k++) {
     const uint32_t c = (gxi * kChunksPerWave + k) * kWaves + wave;
-    if (c >= P.maxch[0]) break;
+    if (c >= maxch) break;
+    const int64_t slot = slot0 + c;
     if (c >= nch) {
-      if (lane == 0) P.cnt[slot0 + c] = U4{0, 0, 0, 0};
+      if (lane == 0) cnt[slot] = U4{0, 0, 0, 0};
       continue;
     }
     const uint32_t j = c * kWave + (uint32_t)lane;
@@ -375,8 +401,8 @@ __global__ __launch_bounds__(kBS) void k_encode_l0(EncPlan P) {
       int32_t q;
       int O, C = 0;
       float xr;
-      quantize(g, x, p, q, O, xr);
-      if (!O && g.K > 0) C = rank_of(g, x) != rank_of(g, xr);
+      quantize(gq, x, p, q, O, xr);
+      if (!O && K > 0) C = rank_of<KB>(iso, K, x) != rank_of<KB>(iso, K, xr);
       if (O || C) { xr = x; q = 0; }
       E = O || C;
       zz = ((uint32_t)q << 1) ^ (uint32_t)(q >> 31);
@@ -387,11 +413,33 @@ __global__ __launch_bounds__(kBS) void k_encode_l0(EncPlan P) {
       if (w < ownz && y < owny && xx < ownx) { acc.nO += O; acc.nC += C; }
       if (AUX) {
         const size_t gi = ((size_t)(bp.o[0] + w) * n1 + y) * n2 + xx;
-        if (P.codes) P.codes[gi] = q;
-        if (P.flags) P.flags[gi] = (uint8_t)(O | (C << 1));
+        if (codes) codes[gi] = q;
+        if (flags) flags[gi] = (uint8_t)(O | (C << 1));
       }
     }
-    pack_chunk(P, slot0 + c, zz, E, x, pack[wave]);
+    // pack the codes at bit lane*wb through LDS
+    uint32_t *pk = pack[wave];
+    const uint32_t orv = wave_or_dpp(zz);
+    const int wb = orv ? 32 - __clz((int)orv) : 0;
+    const unsigned long long em = __ballot(E);
+    if (lane < 32) pk[lane] = 0u;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (zz) {
+      const uint32_t bit = (uint32_t)lane * (uint32_t)wb, wi = bit >> 5, off = bit & 31u;
+      __hip_atomic_fetch_or(&pk[wi], zz << off, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+      if (off + (uint32_t)wb > 32u)
+        __hip_atomic_fetch_or(&pk[wi + 1], zz >> (32u - off), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (lane < 2 * wb) pay[slot * 32 + lane] = pk[lane];
+    if (E) exv[slot * 64 + lanes_below(em)] = x;
+    if (lane == 0) {
+      cnt[slot] = U4{(uint32_t)wb, em ? 1u : 0u, (uint32_t)__popcll(em), 0u};
+      if (em) emask[slot] = em;
+    }
+    __builtin_amdgcn_wave_barrier();
   }
   part_store(acc, &P.part[(int64_t)b * P.part_per_block + gxi]);
 }
@@ -475,9 +523,14 @@ __global__ __launch_bounds__(kBS) void k_pack(EncPlan P) {
   const int64_t rel = wg - P.pack_base[l];
   const int64_t b = rel / P.pack_gpb[l];
   const uint32_t grp = (uint32_t)(rel % P.pack_gpb[l]);
-  int64_t o[3], hi[3];
-  block_ext(g, b, o, hi);
-  const Sec s = sec_geom(o, hi, l, L);
+  Sec s;
+  if (l == 0) {
+    s = P.l0.sec[block_pos(g, P.l0, (uint32_t)b).cls];
+  } else {
+    int64_t o[3], hi[3];
+    block_ext(g, b, o, hi);
+    s = sec_geom(o, hi, l, L);
+  }
   const uint32_t nch = (s.npts + 63) / 64;
   const uint32_t ntile = (nch + 63) / 64;
   const int64_t s0 = P.slot_base[l] + b * (int64_t)P.maxch[l];
@@ -486,11 +539,15 @@ __global__ __launch_bounds__(kBS) void k_pack(EncPlan P) {
   const uint64_t so = P.payload_off + P.secoff[b * g.nL + (L - l)];
   const uint64_t A = 16 + pad8(12 * (uint64_t)ntile), Poff = A + pad8(nch);
   const uint64_t Moff = Poff + 8 * (uint64_t)W, Xoff = Moff + 8 * (uint64_t)NE;
+  const U4 *__restrict__ Pp = P.P;
+  const U4 *__restrict__ cntp = P.cnt;
+  const uint32_t *__restrict__ pay = P.pay;
+  const float *__restrict__ exv = P.exv;
   for (int k = 0; k < kChunksPerWave; k++) {
     const uint32_t c = grp * kChunksPerWG + k * kWaves + wave;
     if (c >= nch) break;
     const int64_t slot = s0 + c;
-    const U4 cur = P.P[slot], cc = P.cnt[slot];
+    const U4 cur = Pp[slot], cc = cntp[slot];
     const uint32_t pw = cur.x - a.x, pe = cur.y - a.y, px = cur.z - a.z;
     if (lane == 0) {
       if (c % 64 == 0) {
@@ -502,9 +559,9 @@ __global__ __launch_bounds__(kBS) void k_pack(EncPlan P) {
       put8(P, so + A + c, (uint8_t)(cc.x | (cc.y ? 0x80u : 0u)));
       if (cc.y) put64(P, so + Moff + 8 * (uint64_t)pe, P.emask[slot]);
     }
-    if (lane < 2 * (int)cc.x) put32(P, so + Poff + 8 * (uint64_t)pw + 4 * lane, P.pay[slot * 32 + lane]);
+    if (lane < 2 * (int)cc.x) put32(P, so + Poff + 8 * (uint64_t)pw + 4 * lane, pay[slot * 32 + lane]);
     if (lane < (int)cc.z)
-      put32(P, so + Xoff + 4 * ((uint64_t)px + lane), __float_as_uint(P.exv[slot * 64 + lane]));
+      put32(P, so + Xoff + 4 * ((uint64_t)px + lane), __float_as_uint(exv[slot * 64 + lane]));
   }
 }
 
@@ -660,19 +717,19 @@ void encode_pack_layout(EncPlan &p) {
   for (int l = L + 1; l < kMaxLevels; l++) { p.pack_base[l] = base; p.pack_gpb[l] = 1; }
 }
 
-void launch_encode(const EncPlan &p, int64_t, U4 *scan_tmp, uint64_t *scan_tmp64, hipStream_t s) {
+template <int KB>
+void launch_encode_levels(const EncPlan &p, hipStream_t s) {
   const Geo &g = p.g;
   const int L = g.nL - 1;
-  const int64_t nsec = g.nblocks * g.nL;
   const int64_t gx = encode_fine_groups(p);
   if (L >= 2) {
     prof_mark("k_encode_coarse", s, 0);
-    k_encode_coarse<<<dim3((unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
+    k_encode_coarse<KB><<<dim3((unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
     prof_mark("k_encode_coarse", s, 1);
   }
   if (L >= 1) {
     prof_mark("k_encode_l1", s, 0);
-    k_encode_l1<<<dim3((unsigned)encode_l1_groups(p), (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
+    k_encode_l1<KB><<<dim3((unsigned)encode_l1_groups(p), (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
     prof_mark("k_encode_l1", s, 1);
   }
   if (gx > 0) {
@@ -682,13 +739,23 @@ void launch_encode(const EncPlan &p, int64_t, U4 *scan_tmp, uint64_t *scan_tmp64
     const bool slab32 = (double)(hi[0] - o[0] + 1) * (double)g.n[1] * (double)g.n[2] < 4294967296.0;
     prof_mark("k_encode_fine", s, 0);
     if (L >= 1 && slab32 && !p.codes && !p.flags)
-      k_encode_l0<false><<<dim3((unsigned)gx, (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
+      k_encode_l0<false, KB><<<dim3((unsigned)gx, (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
     else if (L >= 1 && slab32)
-      k_encode_l0<true><<<dim3((unsigned)gx, (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
+      k_encode_l0<true, KB><<<dim3((unsigned)gx, (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
     else
-      k_encode_fine<<<dim3((unsigned)gx, (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
+      k_encode_fine<KB><<<dim3((unsigned)gx, (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
     prof_mark("k_encode_fine", s, 1);
   }
+}
+
+void launch_encode(const EncPlan &p, int64_t, U4 *scan_tmp, uint64_t *scan_tmp64, hipStream_t s) {
+  const Geo &g = p.g;
+  const int L = g.nL - 1;
+  const int64_t nsec = g.nblocks * g.nL;
+  if (g.K <= 1) launch_encode_levels<1>(p, s);
+  else if (g.K <= 2) launch_encode_levels<2>(p, s);
+  else if (g.K <= 4) launch_encode_levels<4>(p, s);
+  else launch_encode_levels<16>(p, s);
   scan_u4(p.cnt, p.P, p.nslots, scan_tmp, s);
   prof_mark("k_sections", s, 0);
   k_sections<<<dim3((unsigned)ceil_div(nsec, kBS)), dim3(kBS), 0, s>>>(p);
