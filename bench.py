@@ -45,7 +45,10 @@ def parse_args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="phantom512", choices=["phantom512", "taylor_green256", "gaussians64"])
+    ap.add_argument("--workload", default="phantom512",
+                    choices=["phantom512", "taylor_green256", "gaussians64", "batch64"])
+    ap.add_argument("--batch-items", type=int, default=64, help="batch64: number of timesteps")
+    ap.add_argument("--tune-cache", default="", help="batch64: autotuner cache file (default: none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-planes", type=int, default=0,
                     help="z-planes of the field the oracle baseline runs on (0: automatic)")
@@ -75,12 +78,134 @@ def profile_traffic(kernel):
     return float(m.group(1))
 
 
+def run_batch(args):
+    """64 timesteps of uneven sizes: plain per-item launches against the
+    autotuned batch replayed as one captured graph (same outputs, checked)."""
+    import torch
+
+    from paper_2408_05462_amd import api, inputs
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    t0 = time.time()
+    sizes = inputs.batch_sizes(args.batch_items)
+    levels, block = 5, 64
+    xs, es, isos = [], [], []
+    for i, n in enumerate(sizes):
+        x = inputs.grf_torch(n, 0.05 * i, device=dev)
+        xs.append(x)
+        lo, hi = float(x.min()), float(x.max())
+        es.append(1e-3 * (hi - lo))
+        isos.append(inputs.sample_quantiles(x, 8))
+    torch.cuda.synchronize()
+    N = sum(int(x.numel()) for x in xs)
+    log(f"batch of {len(xs)} fields ({N} points) generated in {time.time() - t0:.1f}s")
+    p = api.params(levels, block)
+
+    # plain: the single-field calls, one after another on one stream
+    t0 = time.time()
+    plain = api.Batch(xs, es, isos, [p] * len(xs))   # buffers (and mesh capacities) of the same shapes
+    ws_c = torch.empty(max(api.chr_compress_workspace(x.shape, p) for x in xs), dtype=torch.uint8, device=dev)
+    ws_m = torch.empty(max(api.iso_workspace(x.shape) for x in xs), dtype=torch.uint8, device=dev)
+    infos = []
+    for i, x in enumerate(xs):
+        api.chr_compress(x, es[i], isos[i], p, plain.streams[i], plain.results[i], ws_c)
+    torch.cuda.synchronize()
+    for i in range(len(xs)):
+        infos.append(api.chr_stream_info_dev(plain.streams[i])[0])
+    ws_r = torch.empty(max(api.chr_reconstruct_workspace(inf, 0) for inf in infos), dtype=torch.uint8, device=dev)
+
+    def plain_step():
+        for i, x in enumerate(xs):
+            api.chr_compress(x, es[i], isos[i], p, plain.streams[i], plain.results[i], ws_c)
+            api.chr_reconstruct(infos[i], plain.streams[i], 0, es[i], plain.recon[i], plain.status[i], ws_r)
+            for j, k in enumerate(isos[i]):
+                api.iso_extract(plain.recon[i], k, 1.0, plain.verts[i][j], plain.tris[i][j], plain.counts[i][j], ws_m)
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    ms_plain = timed(plain_step, args.steps, args.warmup)
+    log(f"plain {ms_plain:.3f} ms/step ({time.time() - t0:.1f}s)")
+
+    t0 = time.time()
+    batch = api.Batch(xs, es, isos, [p] * len(xs))
+    batch.autotune(args.tune_cache or None)
+    cfg = batch.config()
+    log(f"autotuned {cfg} in {time.time() - t0:.1f}s")
+    ms_graph = timed(batch.replay, args.steps, args.warmup)
+    log(f"graph {ms_graph:.3f} ms/step")
+
+    # the batch's outputs are the single calls' outputs
+    for i in range(len(xs)):
+        rp, rb = api.read_result(plain.results[i]), api.read_result(batch.results[i])
+        assert rp["status"] == 0 and rb == rp, i
+        nb = rp["stream_bytes"]
+        assert torch.equal(plain.streams[i][:nb], batch.streams[i][:nb]), i
+        assert torch.equal(plain.recon[i].view(torch.int32), batch.recon[i].view(torch.int32)), i
+        assert torch.equal(plain.counts[i], batch.counts[i]), i
+        assert int(batch.status[i].item()) == 0, i
+    cnt = [c.cpu().numpy() for c in batch.counts]
+    stream_bytes = sum(api.read_result(r)["stream_bytes"] for r in batch.results)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        order = sorted(range(len(xs)), key=lambda i: sizes[i])
+        tc, nsub, used = 0.0, 0, []
+        for i in order:
+            if nsub >= (16 << 20):
+                break
+            f = xs[i].cpu().numpy()
+            t1 = time.perf_counter()
+            ref = oracle.compress(f, es[i], isos[i], levels=levels, block=block)
+            y = oracle.decompress(ref["stream"])
+            for k in isos[i]:
+                oracle.mc(y, k)
+            tc += time.perf_counter() - t1
+            nsub += f.size
+            used.append(i)
+        cpu = {"value": round(4.0 * nsub / tc / 1e9, 4), "unit": "GB/s", "cores": int(oracle.threads()),
+               "kind": "oracle",
+               "sample": f"{len(used)} smallest timesteps ({nsub} points), compress+reconstruct+MC for 8 "
+                         f"isovalues each, {tc:.2f}s"}
+
+    gbs = 4.0 * N / (ms_graph * 1e-3) / 1e9
+    out = {
+        "metric": METRIC, "value": round(gbs, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_graph, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batch64", "items": len(xs), "sizes": sizes, "points": N, "levels": levels,
+                   "block": block, "error_bound": "1e-3 x range per item", "isovalues_per_item": 8},
+        "hbm_frac_input": round(gbs / HBM_PEAK_GBS, 4),
+        "plain": {"ms_per_step": round(ms_plain, 4), "value": round(4.0 * N / (ms_plain * 1e-3) / 1e9, 2)},
+        "speedup_vs_plain": round(ms_plain / ms_graph, 3), "tuned": cfg,
+        "compression_ratio": round(4.0 * N / stream_bytes, 3),
+        "triangles": int(sum(int(c[:, 1].sum()) for c in cnt)),
+        "roofline": None, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "bench.py measures one GPU only: every GPU box here has one GPU; "
                                    "run with --gpus 1"}))
         sys.exit(2)
+    if args.workload == "batch64":
+        return run_batch(args)
 
     import torch
 

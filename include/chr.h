@@ -188,6 +188,89 @@ int chr_mc_table(uint8_t *ntri, int8_t *tri);
  * non-finite values (uint32), [3] unused. */
 int chr_range(const float *d_field, int64_t n, float *d_out, void *stream);
 
+/* ---- tile shapes ----------------------------------------------------------- */
+
+/* Work distribution of the level-0 kernels: chunks (64 points) per wave for
+ * compression (1, 2, 4, 8 or 16) and for reconstruction (8, 16, 32 or 64).
+ * Results never depend on these; they apply to calls issued afterwards from
+ * any thread of the process (not for use while another thread launches). */
+int chr_set_tiles(int enc_chunks_per_wave, int dec_chunks_per_wave);
+
+/* ---- batches (many fields of uneven sizes in one captured launch) --------- */
+
+/* The per-field workflow of Sec. II (compress with the topology check of
+ * Sec. II.B, reconstruct, extract the isosurfaces) applied to many fields at
+ * once: timesteps or bricks of uneven sizes, each with its own isovalues.
+ * Nothing in the arithmetic changes: every item runs the same kernels with
+ * the same launch plans as chr_compress (no codes/flags output),
+ * chr_reconstruct at level 0 and iso_extract, so each of its outputs is bit
+ * for bit what those calls give. */
+
+/* One field of a batch.  All pointers are caller-owned device buffers that
+ * must stay valid while the batch (or its captured graph) is in use. */
+typedef struct chr_batch_item {
+  const float *d_field;        /* float32 [dims[0]][dims[1]][dims[2]], x fastest */
+  int64_t dims[3];
+  double error_bound;          /* absolute, >= 0 (0 = lossless) */
+  int n_iso;                   /* 0..16 */
+  float isovalues[16];         /* candidates protected by compression, each extracted in order */
+  chr_params params;
+  void *d_stream;              /* stream output, stream_capacity bytes (chr_compress_bound suffices) */
+  size_t stream_capacity;
+  chr_result *d_result;        /* as chr_compress's */
+  float *d_recon;              /* level-0 reconstruction, same dims as the field */
+  float *d_vertices[16];       /* mesh of isovalue j: vertices [cap_v[j]][3], triangles ... */
+  int64_t cap_v[16];
+  int32_t *d_tris[16];         /* ... [cap_t[j]][3] (either may be NULL with capacity 0) ... */
+  int64_t cap_t[16];
+  int64_t *d_counts;           /* ... and {V, T} of isovalue j at d_counts[2j] (int64 [n_iso][2]) */
+  int32_t *d_status;           /* optional: reconstruction status, reset to 0 by every run */
+  float spacing;               /* grid spacing of the extracted vertices */
+} chr_batch_item;
+
+typedef struct chr_batch chr_batch;
+
+/* Plans a batch (host only, no device call; items are copied).  Items are
+ * spread over up to min(8, n_items) parallel branches, longest first onto
+ * the least-loaded branch.  Errors: CHR_E_INVAL (bad parameters, NULL
+ * pointer, bad mesh capacity; chr_last_error names the item),
+ * CHR_E_CAPACITY (stream capacity below the header and tables). */
+int chr_batch_create(const chr_batch_item *items, int n_items, chr_batch **out);
+
+/* Device scratch bytes the batch needs for any branch count and tile shape
+ * (one region per branch; items of a branch reuse it in turn). */
+size_t chr_batch_workspace(const chr_batch *b);
+
+/* Launches the whole batch on `stream`: forked over the branches' own
+ * streams with an event and joined back into `stream` with one.  Stream
+ * overflow and non-finite input are reported per item in d_result, as by
+ * chr_compress; a corrupt section in d_status. */
+int chr_batch_run(chr_batch *b, void *d_ws, size_t ws_bytes, void *stream);
+
+/* Captures the same launches into a HIP graph (replacing any earlier one;
+ * `stream` is unused: capture happens on a stream of the batch's own).  The
+ * graph keeps the workspace address; nothing runs until a replay. */
+int chr_batch_capture(chr_batch *b, void *d_ws, size_t ws_bytes, void *stream);
+
+/* Launches the captured graph on `stream` (CHR_E_INVAL before a capture). */
+int chr_batch_replay(chr_batch *b, void *stream);
+
+/* Chooses the branch count (1, 2, 4, 8) and the level-0 tiles
+ * (chr_set_tiles' candidates) by timing replays of the captured batch:
+ * coordinate descent from the current configuration over branches, then
+ * compression tiles, then reconstruction tiles; a change is kept when it is
+ * at least 1% faster.  Ends with the chosen configuration captured.
+ * cache_path (may be NULL): text file of "signature branches enc dec" lines,
+ * signature = hash of the items' shapes and parameters and the device; a
+ * matching line skips the search, a new result is appended. */
+int chr_batch_autotune(chr_batch *b, void *d_ws, size_t ws_bytes, void *stream, const char *cache_path);
+
+/* Current configuration and the duration of the last timed replay (ms). */
+int chr_batch_config(const chr_batch *b, int *branches, int *enc_cpw, int *dec_cpw, float *last_ms);
+
+/* Releases the batch's streams, events and graph (not the caller's buffers). */
+int chr_batch_destroy(chr_batch *b);
+
 /* ---- measurement support ------------------------------------------------ */
 
 /* While enabled, every launch of the kernel named `kernel` (for example

@@ -22,7 +22,9 @@ STATUS_NAMES = {0: "CHR_OK", -1: "CHR_E_INVAL", -2: "CHR_E_ACCURACY", -3: "CHR_E
 EXPORTS = ["chr_last_error", "chr_version", "chr_compress_bound", "chr_compress_workspace", "chr_compress",
            "chr_stream_info", "chr_stream_verify", "chr_reconstruct_workspace", "chr_reconstruct",
            "iso_workspace", "iso_extract", "iso_cases", "chr_mc_table", "chr_range", "chr_prof_enable",
-           "chr_prof_collect", "chr_prof_disable"]
+           "chr_prof_collect", "chr_prof_disable", "chr_set_tiles", "chr_batch_create", "chr_batch_workspace",
+           "chr_batch_run", "chr_batch_capture", "chr_batch_replay", "chr_batch_autotune", "chr_batch_config",
+           "chr_batch_destroy"]
 
 
 class ChrError(RuntimeError):
@@ -47,6 +49,15 @@ class chr_info(C.Structure):
                 ("nblocks", C.c_int64), ("nb", C.c_int * 3), ("flags", C.c_uint32),
                 ("total_bytes", C.c_uint64), ("n_outlier", C.c_uint64), ("n_corrected", C.c_uint64),
                 ("payload_offset", C.c_uint64)]
+
+
+class chr_batch_item(C.Structure):
+    _fields_ = [("d_field", C.c_void_p), ("dims", C.c_int64 * 3), ("error_bound", C.c_double), ("n_iso", C.c_int),
+                ("isovalues", C.c_float * 16), ("params", chr_params), ("d_stream", C.c_void_p),
+                ("stream_capacity", C.c_size_t), ("d_result", C.c_void_p), ("d_recon", C.c_void_p),
+                ("d_vertices", C.c_void_p * 16), ("cap_v", C.c_int64 * 16), ("d_tris", C.c_void_p * 16),
+                ("cap_t", C.c_int64 * 16), ("d_counts", C.c_void_p), ("d_status", C.c_void_p),
+                ("spacing", C.c_float)]
 
 
 RESULT_BYTES = C.sizeof(chr_result)
@@ -99,6 +110,25 @@ def load():
     L.chr_prof_collect.argtypes = [vp, C.c_int, C.POINTER(C.c_int)]
     L.chr_prof_collect.restype = C.c_int
     L.chr_prof_disable.restype = C.c_int
+    L.chr_set_tiles.argtypes = [C.c_int, C.c_int]
+    L.chr_set_tiles.restype = C.c_int
+    L.chr_batch_create.argtypes = [C.POINTER(chr_batch_item), C.c_int, C.POINTER(vp)]
+    L.chr_batch_create.restype = C.c_int
+    L.chr_batch_workspace.argtypes = [vp]
+    L.chr_batch_workspace.restype = C.c_size_t
+    L.chr_batch_run.argtypes = [vp, vp, C.c_size_t, vp]
+    L.chr_batch_run.restype = C.c_int
+    L.chr_batch_capture.argtypes = [vp, vp, C.c_size_t, vp]
+    L.chr_batch_capture.restype = C.c_int
+    L.chr_batch_replay.argtypes = [vp, vp]
+    L.chr_batch_replay.restype = C.c_int
+    L.chr_batch_autotune.argtypes = [vp, vp, C.c_size_t, vp, C.c_char_p]
+    L.chr_batch_autotune.restype = C.c_int
+    ip = C.POINTER(C.c_int)
+    L.chr_batch_config.argtypes = [vp, ip, ip, ip, C.POINTER(C.c_float)]
+    L.chr_batch_config.restype = C.c_int
+    L.chr_batch_destroy.argtypes = [vp]
+    L.chr_batch_destroy.restype = C.c_int
     _lib = L
     return L
 

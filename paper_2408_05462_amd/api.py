@@ -219,3 +219,122 @@ def field_range(field):
     torch.cuda.synchronize(field.device)
     v = out.cpu()
     return float(v[0]), float(v[1]), int(v[2:3].view(torch.int32).item())
+
+
+# ------------------------------------------------------------------ tiles and batches
+
+def chr_set_tiles(enc_chunks_per_wave=4, dec_chunks_per_wave=16):
+    L.check(L.load().chr_set_tiles(int(enc_chunks_per_wave), int(dec_chunks_per_wave)), "chr_set_tiles")
+
+
+class Batch:
+    """Device buffers of a batch plus its chr_batch handle.
+
+    fields: list of float32 CUDA tensors (any shapes); error_bounds and
+    isovalues (a list per field, at most 16) and params (chr_params) per
+    field.  mesh_caps[i][j] = (cap_v, cap_t) for field i, isovalue j; with
+    mesh_caps=None the capacities are found by one eager run with no mesh
+    outputs (the counts are written regardless), then the batch is planned
+    again with buffers of exactly that size.
+    """
+
+    def __init__(self, fields, error_bounds, isovalues, params_list, spacing=1.0, mesh_caps=None, stream=None):
+        self.fields = fields
+        self.error_bounds = [float(e) for e in error_bounds]
+        self.isovalues = [[float(np.float32(k)) for k in ks] for ks in isovalues]
+        self.params = params_list
+        self.spacing = float(spacing)
+        dev = fields[0].device
+        self.streams = [torch.empty(chr_compress_bound(f.shape, p), dtype=torch.uint8, device=dev)
+                        for f, p in zip(fields, params_list)]
+        self.results = [torch.zeros(64, dtype=torch.uint8, device=dev) for _ in fields]
+        self.recon = [torch.empty_like(f) for f in fields]
+        self.counts = [torch.zeros((max(len(k), 1), 2), dtype=torch.int64, device=dev) for k in self.isovalues]
+        self.status = [torch.zeros(1, dtype=torch.int32, device=dev) for _ in fields]
+        self.handle = None
+        self.ws = None
+        if mesh_caps is None:
+            self._plan([[(0, 0)] * len(k) for k in self.isovalues])
+            self.run(stream)
+            torch.cuda.synchronize(dev)
+            mesh_caps = [[(int(c[j, 0]), int(c[j, 1])) for j in range(len(k))]
+                         for c, k in zip((c.cpu().numpy() for c in self.counts), self.isovalues)]
+        self._plan(mesh_caps)
+
+    def _plan(self, mesh_caps):
+        dev = self.fields[0].device
+        self.verts = [[torch.empty((max(cv, 1), 3), dtype=torch.float32, device=dev) for cv, _ in mc]
+                      for mc in mesh_caps]
+        self.tris = [[torch.empty((max(ct, 1), 3), dtype=torch.int32, device=dev) for _, ct in mc]
+                     for mc in mesh_caps]
+        items = (L.chr_batch_item * len(self.fields))()
+        for i, f in enumerate(self.fields):
+            _need_cuda_f32(f, "field")
+            it = items[i]
+            it.d_field = f.data_ptr()
+            for a in range(3):
+                it.dims[a] = int(f.shape[a])
+            it.error_bound = self.error_bounds[i]
+            it.n_iso = len(self.isovalues[i])
+            for j, k in enumerate(self.isovalues[i]):
+                it.isovalues[j] = k
+                it.d_vertices[j] = self.verts[i][j].data_ptr()
+                it.cap_v[j] = mesh_caps[i][j][0]
+                it.d_tris[j] = self.tris[i][j].data_ptr()
+                it.cap_t[j] = mesh_caps[i][j][1]
+            it.params = self.params[i]
+            it.d_stream = self.streams[i].data_ptr()
+            it.stream_capacity = self.streams[i].numel()
+            it.d_result = self.results[i].data_ptr()
+            it.d_recon = self.recon[i].data_ptr()
+            it.d_counts = self.counts[i].data_ptr()
+            it.d_status = self.status[i].data_ptr()
+            it.spacing = self.spacing
+        self.close()
+        h = C.c_void_p()
+        L.check(L.load().chr_batch_create(items, len(self.fields), C.byref(h)), "chr_batch_create")
+        self.handle = h
+        nws = L.load().chr_batch_workspace(h)
+        if self.ws is None or self.ws.numel() < nws:
+            self.ws = torch.empty(nws, dtype=torch.uint8, device=dev)
+
+    def run(self, stream=None):
+        L.check(L.load().chr_batch_run(self.handle, _p(self.ws), self.ws.numel(), _s(stream)), "chr_batch_run")
+
+    def capture(self, stream=None):
+        L.check(L.load().chr_batch_capture(self.handle, _p(self.ws), self.ws.numel(), _s(stream)),
+                "chr_batch_capture")
+
+    def replay(self, stream=None):
+        L.check(L.load().chr_batch_replay(self.handle, _s(stream)), "chr_batch_replay")
+
+    def autotune(self, cache_path=None, stream=None):
+        L.check(L.load().chr_batch_autotune(self.handle, _p(self.ws), self.ws.numel(), _s(stream),
+                                            None if cache_path is None else str(cache_path).encode()),
+                "chr_batch_autotune")
+
+    def config(self):
+        b, e, d, ms = C.c_int(), C.c_int(), C.c_int(), C.c_float()
+        L.check(L.load().chr_batch_config(self.handle, C.byref(b), C.byref(e), C.byref(d), C.byref(ms)),
+                "chr_batch_config")
+        return dict(branches=b.value, enc_cpw=e.value, dec_cpw=d.value, last_ms=ms.value)
+
+    def outputs(self, i):
+        """Host copies of item i: (stream bytes, result, reconstruction, [(verts, tris)...], status)."""
+        r = read_result(self.results[i])
+        c = self.counts[i].cpu().numpy()
+        meshes = [(self.verts[i][j][: int(c[j, 0])].cpu().numpy(), self.tris[i][j][: int(c[j, 1])].cpu().numpy())
+                  for j in range(len(self.isovalues[i]))]
+        return (bytes(self.streams[i][: r["stream_bytes"]].cpu().numpy()), r, self.recon[i].cpu().numpy(), meshes,
+                int(self.status[i].item()))
+
+    def close(self):
+        if self.handle is not None:
+            L.load().chr_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -7,14 +7,20 @@
 #include <string>
 #include <vector>
 
-#include "../../include/chr.h"
-#include "chr_plan.h"
+#include "capi_internal.h"
 
 using namespace chr;
 
 namespace {
 
 thread_local std::string g_err;
+
+// Tile shapes of the level-0 kernels (work distribution only; results do not
+// depend on them).  Set by chr_set_tiles, or per batch by its autotuner.
+struct Tune {
+  int enc_cpw0 = 4;
+  int dec_cpw0 = 16;
+} g_tune;
 
 int fail(int code, const std::string &msg) {
   g_err = msg;
@@ -102,7 +108,7 @@ uint32_t max_chunks(const Geo &g, int l) {
 
 struct EncLayout {
   size_t off_G, off_cnt, off_P, off_scan, off_pay, off_emask, off_exv, off_part, off_bst, off_secsz, off_secoff,
-      off_scan64, total;
+      off_scan64, total, part_records;
 };
 
 EncLayout enc_layout(EncPlan &P) {
@@ -137,8 +143,14 @@ EncLayout enc_layout(EncPlan &P) {
   Lo.off_exv = o; o = align256(o + sizeof(float) * 64 * (size_t)P.nslots);
   P.part_l1 = encode_fine_groups(P);
   P.part_per_block = P.part_l1 + encode_l1_groups(P) + 1;
+  {
+    EncPlan q = P;
+    q.cpw0 = 1;  // workspace sized for the finest level-0 tiling
+    const int64_t ppb_max = encode_fine_groups(q) + encode_l1_groups(q) + 1;
+    Lo.part_records = (size_t)(g.nblocks * ppb_max);
+  }
   encode_pack_layout(P);
-  Lo.off_part = o; o = align256(o + sizeof(Part) * (size_t)(g.nblocks * P.part_per_block));
+  Lo.off_part = o; o = align256(o + sizeof(Part) * Lo.part_records);
   Lo.off_bst = o; o = align256(o + sizeof(Part) * (size_t)g.nblocks);
   Lo.off_secsz = o; o = align256(o + sizeof(uint64_t) * (size_t)nsec);
   Lo.off_secoff = o; o = align256(o + sizeof(uint64_t) * (size_t)(nsec + 1));
@@ -197,6 +209,174 @@ struct Prof {
 }  // namespace
 
 namespace chr {
+int api_fail(int code, const std::string &msg) { return fail(code, msg); }
+int api_check_launch(const char *what) { return check_hip(what); }
+bool tiles_ok(int enc_cpw, int dec_cpw) {
+  const bool e = enc_cpw == 1 || enc_cpw == 2 || enc_cpw == 4 || enc_cpw == 8 || enc_cpw == 16;
+  const bool d = dec_cpw == 8 || dec_cpw == 16 || dec_cpw == 32 || dec_cpw == 64;
+  return e && d;
+}
+
+size_t enc_workspace_bytes(const int64_t dims[3], const chr_params *p) {
+  std::string why;
+  if (!params_ok(dims, p, why)) { g_err = why; return 0; }
+  EncPlan P;
+  std::memset(&P, 0, sizeof(P));
+  P.cpw0 = 4;
+  fill_geo(P.g, dims, p->levels, p->block, p->qmax);
+  return enc_layout(P).total;
+}
+
+int enc_geometry(const int64_t dims[3], double error_bound, const float *h_iso, int n_iso, const chr_params *p,
+                 Geo &g, uint64_t &payload_off) {
+  std::string why;
+  if (!params_ok(dims, p, why)) return fail(CHR_E_INVAL, why);
+  if (!(error_bound >= 0) || !std::isfinite(error_bound)) return fail(CHR_E_INVAL, "error_bound must be finite and >= 0");
+  fill_geo(g, dims, p->levels, p->block, p->qmax);
+  if (prepare_iso(h_iso, n_iso, g, why)) return fail(CHR_E_INVAL, why);
+  set_quant(g, error_bound);
+  if (g.nblocks > 65535) return fail(CHR_E_INVAL, "more than 65535 blocks: use a larger block");
+  payload_off = kHeaderBytes + 16 * (uint64_t)g.nblocks * g.nL + 16 * (uint64_t)g.nblocks;
+  return CHR_OK;
+}
+
+int enc_prepare(const float *d_field, const int64_t dims[3], double error_bound, const float *h_iso, int n_iso,
+                const chr_params *p, void *d_stream, size_t capacity, chr_result *d_result, int32_t *d_codes,
+                uint8_t *d_flags, void *d_ws, size_t ws_bytes, int cpw0, EncJob &J) {
+  if (!d_field || !d_stream || !d_result || !d_ws) return fail(CHR_E_INVAL, "NULL device pointer");
+  EncPlan &P = J.P;
+  std::memset(&P, 0, sizeof(P));
+  uint64_t poff = 0;
+  int rc = enc_geometry(dims, error_bound, h_iso, n_iso, p, P.g, poff);
+  if (rc) return rc;
+  P.cpw0 = cpw0;
+  make_l0geo(P.g, P.l0);
+  EncLayout Lo = enc_layout(P);
+  if (ws_bytes < Lo.total) return fail(CHR_E_NOMEM, "workspace too small: need " + std::to_string(Lo.total));
+  if (capacity < P.payload_off) return fail(CHR_E_CAPACITY, "capacity below the header and tables");
+  uint8_t *ws = static_cast<uint8_t *>(d_ws);
+  P.x = d_field;
+  P.G = reinterpret_cast<float *>(ws + Lo.off_G);
+  P.cnt = reinterpret_cast<U4 *>(ws + Lo.off_cnt);
+  P.P = reinterpret_cast<U4 *>(ws + Lo.off_P);
+  P.pay = reinterpret_cast<uint32_t *>(ws + Lo.off_pay);
+  P.emask = reinterpret_cast<unsigned long long *>(ws + Lo.off_emask);
+  P.exv = reinterpret_cast<float *>(ws + Lo.off_exv);
+  P.part = reinterpret_cast<Part *>(ws + Lo.off_part);
+  P.bst = reinterpret_cast<Part *>(ws + Lo.off_bst);
+  P.secsz = reinterpret_cast<uint64_t *>(ws + Lo.off_secsz);
+  P.secoff = reinterpret_cast<uint64_t *>(ws + Lo.off_secoff);
+  P.out = static_cast<uint8_t *>(d_stream);
+  P.cap = capacity;
+  P.result = d_result;
+  P.codes = d_codes;
+  P.flags = d_flags;
+  J.scan = reinterpret_cast<U4 *>(ws + Lo.off_scan);
+  J.scan64 = reinterpret_cast<uint64_t *>(ws + Lo.off_scan64);
+  return CHR_OK;
+}
+
+// Workspace of a reconstruction to `level`: the compact grids of the levels
+// above it (the output holds level `level` itself).
+static size_t dec_need(const Geo &g, int level) {
+  const int L = g.nL - 1;
+  size_t need = 0;
+  for (int l = std::max(level, 1); l <= L; l++) {
+    if (l == level) continue;
+    need = align256(need + sizeof(float) * (size_t)(lvl_dim(g.n[0], l) * lvl_dim(g.n[1], l) * lvl_dim(g.n[2], l)));
+  }
+  return need;
+}
+
+size_t dec_workspace_bytes(const Geo &g, int level) { return std::max<size_t>(dec_need(g, level), 256); }
+
+int dec_prepare(const Geo &g, uint64_t payload_off, int level, const void *d_stream, uint64_t stream_bytes,
+                float *d_out, int32_t *d_status, void *d_ws, size_t ws_bytes, int cpw0, DecJob &J) {
+  DecPlan &D = J.D;
+  std::memset(&D, 0, sizeof(D));
+  if (!d_stream || !d_out) return fail(CHR_E_INVAL, "NULL argument");
+  if (level < 0 || level >= g.nL) return fail(CHR_E_LEVEL, "level outside the hierarchy");
+  if (g.nblocks > 65535) return fail(CHR_E_INVAL, "more than 65535 blocks");
+  const size_t need = dec_need(g, level);
+  if (ws_bytes < need || (need && !d_ws)) return fail(CHR_E_NOMEM, "workspace too small: need " + std::to_string(need));
+  D.g = g;
+  make_l0geo(D.g, D.l0);
+  D.cpw0 = cpw0;
+  D.lo = level;
+  const int L = g.nL - 1;
+  for (int l = 0; l < kMaxLevels; l++)
+    for (int a = 0; a < 3; a++) D.gd[l][a] = (l <= L) ? lvl_dim(g.n[a], l) : 0;
+  size_t off = 0;
+  uint8_t *ws = static_cast<uint8_t *>(d_ws);
+  for (int l = std::max(level, 1); l <= L; l++) {
+    if (l == level) { D.gp[l] = d_out; continue; }
+    D.gp[l] = reinterpret_cast<float *>(ws + off);
+    off = align256(off + sizeof(float) * (size_t)(D.gd[l][0] * D.gd[l][1] * D.gd[l][2]));
+  }
+  D.payload_off = payload_off;
+  D.s = static_cast<const uint8_t *>(d_stream);
+  D.sbytes = stream_bytes;
+  D.out = d_out;
+  D.status = d_status;
+  return CHR_OK;
+}
+
+static int mc_plan(const float *d_field, const int64_t dims[3], McPlan &M, size_t &need, size_t off[6]) {
+  std::memset(&M, 0, sizeof(M));
+  if (!dims_ok(dims)) return fail(CHR_E_INVAL, "dims must be in [1, 2^30]");
+  for (int a = 0; a < 3; a++) M.n[a] = dims[a];
+  M.nrows = dims[0] * dims[1];
+  M.nw = ceil_div(dims[2], 64);
+  if ((double)M.nrows * (double)M.nw * 64.0 >= 4294967296.0)
+    return fail(CHR_E_INVAL, "field too large for marching cubes (2^32 padded points)");
+  M.f = d_field;
+  size_t o = 0;
+  off[0] = o; o = align256(o + 8 * (size_t)(M.nrows * M.nw));
+  const int64_t nwords = M.nrows * M.nw;
+  off[1] = o; o = align256(o + sizeof(U4) * (size_t)nwords);
+  off[2] = o; o = align256(o + sizeof(U4) * (size_t)(nwords + 1));
+  off[3] = o; o = align256(o + sizeof(U4) * (size_t)scan_tmp_elems(nwords));
+  off[4] = o; o = align256(o + sizeof(uint32_t) * (size_t)(nwords * 64));
+  off[5] = o; o = align256(o + sizeof(uint2) * (size_t)(nwords * 64));
+  need = o;
+  return CHR_OK;
+}
+
+size_t mc_workspace_bytes(const int64_t dims[3]) {
+  McPlan M;
+  size_t need = 0, off[6];
+  if (mc_plan(nullptr, dims, M, need, off)) return 0;
+  return need;
+}
+
+int mc_prepare(const float *d_field, const int64_t dims[3], float isovalue, float spacing, float *d_vertices,
+               int64_t cap_v, int32_t *d_tris, int64_t cap_t, int64_t *d_counts, void *d_ws, size_t ws_bytes,
+               McJob &J) {
+  if (!d_field || !d_counts || !d_ws) return fail(CHR_E_INVAL, "NULL argument");
+  if (cap_v < 0 || cap_t < 0 || (cap_v && !d_vertices) || (cap_t && !d_tris)) return fail(CHR_E_INVAL, "bad capacity");
+  if (!std::isfinite(isovalue) || !std::isfinite(spacing)) return fail(CHR_E_INVAL, "isovalue and spacing must be finite");
+  McPlan &M = J.M;
+  size_t need = 0, off[6];
+  int rc = mc_plan(d_field, dims, M, need, off);
+  if (rc) return rc;
+  if (ws_bytes < need) return fail(CHR_E_NOMEM, "workspace too small: need " + std::to_string(need));
+  uint8_t *ws = static_cast<uint8_t *>(d_ws);
+  M.bits = reinterpret_cast<unsigned long long *>(ws + off[0]);
+  M.cnt = reinterpret_cast<U4 *>(ws + off[1]);
+  M.P = reinterpret_cast<U4 *>(ws + off[2]);
+  M.vlist = reinterpret_cast<uint32_t *>(ws + off[4]);
+  M.clist = reinterpret_cast<uint2 *>(ws + off[5]);
+  M.k = isovalue;
+  M.spacing = spacing;
+  M.verts = d_vertices;
+  M.tris = d_tris;
+  M.cap_v = cap_v;
+  M.cap_t = cap_t;
+  M.counts = d_counts;
+  J.scan = reinterpret_cast<U4 *>(ws + off[3]);
+  return CHR_OK;
+}
+
 void prof_mark(const char *kernel, hipStream_t s, int end) {
   if (!g_prof.on || g_prof.name != kernel) return;
   if (!end && g_prof.used + 2 > (int)g_prof.ev.size()) return;
@@ -244,6 +424,14 @@ int chr_prof_disable(void) {
 
 const char *chr_last_error(void) { return g_err.c_str(); }
 
+int chr_set_tiles(int enc_chunks_per_wave, int dec_chunks_per_wave) {
+  if (!tiles_ok(enc_chunks_per_wave, dec_chunks_per_wave))
+    return fail(CHR_E_INVAL, "tiles: compression 1, 2, 4, 8 or 16; reconstruction 8, 16, 32 or 64 chunks per wave");
+  g_tune.enc_cpw0 = enc_chunks_per_wave;
+  g_tune.dec_cpw0 = dec_chunks_per_wave;
+  return CHR_OK;
+}
+
 int chr_version(void) { return 1; }
 
 size_t chr_compress_bound(const int64_t dims[3], const chr_params *p) {
@@ -269,51 +457,16 @@ size_t chr_compress_bound(const int64_t dims[3], const chr_params *p) {
   return total;
 }
 
-size_t chr_compress_workspace(const int64_t dims[3], const chr_params *p) {
-  std::string why;
-  if (!params_ok(dims, p, why)) { g_err = why; return 0; }
-  EncPlan P;
-  std::memset(&P, 0, sizeof(P));
-  fill_geo(P.g, dims, p->levels, p->block, p->qmax);
-  return enc_layout(P).total;
-}
+size_t chr_compress_workspace(const int64_t dims[3], const chr_params *p) { return enc_workspace_bytes(dims, p); }
 
 int chr_compress(const float *d_field, const int64_t dims[3], double error_bound, const float *h_isovalues,
                  int n_iso, const chr_params *p, void *d_stream, size_t capacity, chr_result *d_result,
                  int32_t *d_codes, uint8_t *d_flags, void *d_ws, size_t ws_bytes, void *stream) {
-  std::string why;
-  if (!params_ok(dims, p, why)) return fail(CHR_E_INVAL, why);
-  if (!d_field || !d_stream || !d_result || !d_ws) return fail(CHR_E_INVAL, "NULL device pointer");
-  if (!(error_bound >= 0) || !std::isfinite(error_bound)) return fail(CHR_E_INVAL, "error_bound must be finite and >= 0");
-  EncPlan P;
-  std::memset(&P, 0, sizeof(P));
-  fill_geo(P.g, dims, p->levels, p->block, p->qmax);
-  if (prepare_iso(h_isovalues, n_iso, P.g, why)) return fail(CHR_E_INVAL, why);
-  set_quant(P.g, error_bound);
-  make_l0geo(P.g, P.l0);
-  EncLayout Lo = enc_layout(P);
-  if (ws_bytes < Lo.total) return fail(CHR_E_NOMEM, "workspace too small: need " + std::to_string(Lo.total));
-  if (P.g.nblocks > 65535) return fail(CHR_E_INVAL, "more than 65535 blocks: use a larger block");
-  if (capacity < P.payload_off) return fail(CHR_E_CAPACITY, "capacity below the header and tables");
-  uint8_t *ws = static_cast<uint8_t *>(d_ws);
-  P.x = d_field;
-  P.G = reinterpret_cast<float *>(ws + Lo.off_G);
-  P.cnt = reinterpret_cast<U4 *>(ws + Lo.off_cnt);
-  P.P = reinterpret_cast<U4 *>(ws + Lo.off_P);
-  P.pay = reinterpret_cast<uint32_t *>(ws + Lo.off_pay);
-  P.emask = reinterpret_cast<unsigned long long *>(ws + Lo.off_emask);
-  P.exv = reinterpret_cast<float *>(ws + Lo.off_exv);
-  P.part = reinterpret_cast<Part *>(ws + Lo.off_part);
-  P.bst = reinterpret_cast<Part *>(ws + Lo.off_bst);
-  P.secsz = reinterpret_cast<uint64_t *>(ws + Lo.off_secsz);
-  P.secoff = reinterpret_cast<uint64_t *>(ws + Lo.off_secoff);
-  P.out = static_cast<uint8_t *>(d_stream);
-  P.cap = capacity;
-  P.result = d_result;
-  P.codes = d_codes;
-  P.flags = d_flags;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  launch_encode(P, 0, reinterpret_cast<U4 *>(ws + Lo.off_scan), reinterpret_cast<uint64_t *>(ws + Lo.off_scan64), s);
+  EncJob J;
+  int rc = enc_prepare(d_field, dims, error_bound, h_isovalues, n_iso, p, d_stream, capacity, d_result, d_codes,
+                       d_flags, d_ws, ws_bytes, g_tune.enc_cpw0, J);
+  if (rc) return rc;
+  launch_encode(J.P, 0, J.scan, J.scan64, static_cast<hipStream_t>(stream));
   return check_hip("chr_compress launch");
 }
 
@@ -378,121 +531,56 @@ int chr_stream_verify(const void *h_stream, size_t n) {
   return CHR_OK;
 }
 
-static int dec_plan(const chr_info *I, int level, DecPlan &D, size_t &need) {
-  std::memset(&D, 0, sizeof(D));
+// Geometry of a stream from its parsed header, checked for consistency.
+static int info_geo(const chr_info *I, Geo &g) {
   chr_params p{I->levels, I->block, I->qmax};
   std::string why;
   if (!params_ok(I->dims, &p, why)) return fail(CHR_E_CORRUPT, why);
-  if (level < 0 || level >= I->levels) return fail(CHR_E_LEVEL, "level outside the hierarchy");
-  fill_geo(D.g, I->dims, I->levels, I->block, I->qmax);
-  set_quant(D.g, I->error_bound);
-  if (std::memcmp(&D.g.inv, &I->inv, 4) || std::memcmp(&D.g.step, &I->step, 4))
+  fill_geo(g, I->dims, I->levels, I->block, I->qmax);
+  set_quant(g, I->error_bound);
+  if (std::memcmp(&g.inv, &I->inv, 4) || std::memcmp(&g.step, &I->step, 4))
     return fail(CHR_E_CORRUPT, "quantizer constants do not match the error bound");
-  if ((D.g.lossless ? 1u : 0u) != (I->flags & 1u)) return fail(CHR_E_CORRUPT, "lossless flag mismatch");
-  D.g.K = I->n_iso;
-  for (int j = 0; j < kMaxIso; j++) D.g.iso[j] = I->isovalues[j];
-  make_l0geo(D.g, D.l0);
-  D.lo = level;
-  const int L = I->levels - 1;
-  need = 0;
-  for (int l = 0; l < kMaxLevels; l++)
-    for (int a = 0; a < 3; a++) D.gd[l][a] = (l <= L) ? lvl_dim(I->dims[a], l) : 0;
-  for (int l = std::max(level, 1); l <= L; l++) {
-    if (l == level) continue;  // the output itself
-    need = align256(need + sizeof(float) * (size_t)(D.gd[l][0] * D.gd[l][1] * D.gd[l][2]));
-  }
-  D.payload_off = I->payload_offset;
-  if (D.g.nblocks > 65535) return fail(CHR_E_INVAL, "more than 65535 blocks");
+  if ((g.lossless ? 1u : 0u) != (I->flags & 1u)) return fail(CHR_E_CORRUPT, "lossless flag mismatch");
+  if (I->n_iso < 0 || I->n_iso > kMaxIso) return fail(CHR_E_CORRUPT, "bad isovalue count");
+  g.K = I->n_iso;
+  for (int j = 0; j < kMaxIso; j++) g.iso[j] = I->isovalues[j];
   return CHR_OK;
 }
 
 size_t chr_reconstruct_workspace(const chr_info *info, int level) {
   if (!info) return 0;
-  DecPlan D;
-  size_t need = 0;
-  if (dec_plan(info, level, D, need)) return 0;
-  return std::max<size_t>(need, 256);
+  Geo g;
+  if (info_geo(info, g)) return 0;
+  if (level < 0 || level >= g.nL) { g_err = "level outside the hierarchy"; return 0; }
+  return dec_workspace_bytes(g, level);
 }
 
 int chr_reconstruct(const chr_info *info, const void *d_stream, size_t stream_bytes, int level, double error_bound,
                     float *d_out, int32_t *d_status, void *d_ws, size_t ws_bytes, void *stream) {
   if (!info || !d_stream || !d_out) return fail(CHR_E_INVAL, "NULL argument");
-  DecPlan D;
-  size_t need = 0;
-  int rc = dec_plan(info, level, D, need);
+  Geo g;
+  int rc = info_geo(info, g);
   if (rc) return rc;
+  if (level < 0 || level >= g.nL) return fail(CHR_E_LEVEL, "level outside the hierarchy");
   if (!(error_bound >= info->error_bound)) return fail(CHR_E_ACCURACY, "requested error bound below the stream's");
   if (stream_bytes < info->total_bytes) return fail(CHR_E_CORRUPT, "stream shorter than its header states");
-  if (ws_bytes < need || (need && !d_ws)) return fail(CHR_E_NOMEM, "workspace too small: need " + std::to_string(need));
-  const int L = info->levels - 1;
-  size_t off = 0;
-  uint8_t *ws = static_cast<uint8_t *>(d_ws);
-  for (int l = std::max(level, 1); l <= L; l++) {
-    if (l == level) { D.gp[l] = d_out; continue; }
-    D.gp[l] = reinterpret_cast<float *>(ws + off);
-    off = align256(off + sizeof(float) * (size_t)(D.gd[l][0] * D.gd[l][1] * D.gd[l][2]));
-  }
-  D.s = static_cast<const uint8_t *>(d_stream);
-  D.sbytes = info->total_bytes;
-  D.out = d_out;
-  D.status = d_status;
-  launch_decode(D, static_cast<hipStream_t>(stream));
+  DecJob J;
+  rc = dec_prepare(g, info->payload_offset, level, d_stream, info->total_bytes, d_out, d_status, d_ws, ws_bytes,
+                   g_tune.dec_cpw0, J);
+  if (rc) return rc;
+  launch_decode(J.D, static_cast<hipStream_t>(stream));
   return check_hip("chr_reconstruct launch");
 }
 
-static int mc_plan(const float *d_field, const int64_t dims[3], McPlan &M, size_t &need, size_t off[6]) {
-  std::memset(&M, 0, sizeof(M));
-  if (!dims_ok(dims)) return fail(CHR_E_INVAL, "dims must be in [1, 2^30]");
-  for (int a = 0; a < 3; a++) M.n[a] = dims[a];
-  M.nrows = dims[0] * dims[1];
-  M.nw = ceil_div(dims[2], 64);
-  if ((double)M.nrows * (double)M.nw * 64.0 >= 4294967296.0)
-    return fail(CHR_E_INVAL, "field too large for marching cubes (2^32 padded points)");
-  M.f = d_field;
-  size_t o = 0;
-  off[0] = o; o = align256(o + 8 * (size_t)(M.nrows * M.nw));
-  const int64_t nwords = M.nrows * M.nw;
-  off[1] = o; o = align256(o + sizeof(U4) * (size_t)nwords);
-  off[2] = o; o = align256(o + sizeof(U4) * (size_t)(nwords + 1));
-  off[3] = o; o = align256(o + sizeof(U4) * (size_t)scan_tmp_elems(nwords));
-  off[4] = o; o = align256(o + sizeof(uint32_t) * (size_t)(nwords * 64));
-  off[5] = o; o = align256(o + sizeof(uint2) * (size_t)(nwords * 64));
-  need = o;
-  return CHR_OK;
-}
-
-size_t iso_workspace(const int64_t dims[3]) {
-  McPlan M;
-  size_t need = 0, off[6];
-  if (mc_plan(nullptr, dims, M, need, off)) return 0;
-  return need;
-}
+size_t iso_workspace(const int64_t dims[3]) { return mc_workspace_bytes(dims); }
 
 int iso_extract(const float *d_field, const int64_t dims[3], float isovalue, float spacing, float *d_vertices,
                 int64_t cap_v, int32_t *d_tris, int64_t cap_t, int64_t *d_counts, void *d_ws, size_t ws_bytes,
                 void *stream) {
-  if (!d_field || !d_counts || !d_ws) return fail(CHR_E_INVAL, "NULL argument");
-  if (cap_v < 0 || cap_t < 0 || (cap_v && !d_vertices) || (cap_t && !d_tris)) return fail(CHR_E_INVAL, "bad capacity");
-  if (!std::isfinite(isovalue) || !std::isfinite(spacing)) return fail(CHR_E_INVAL, "isovalue and spacing must be finite");
-  McPlan M;
-  size_t need = 0, off[6];
-  int rc = mc_plan(d_field, dims, M, need, off);
+  McJob J;
+  int rc = mc_prepare(d_field, dims, isovalue, spacing, d_vertices, cap_v, d_tris, cap_t, d_counts, d_ws, ws_bytes, J);
   if (rc) return rc;
-  if (ws_bytes < need) return fail(CHR_E_NOMEM, "workspace too small: need " + std::to_string(need));
-  uint8_t *ws = static_cast<uint8_t *>(d_ws);
-  M.bits = reinterpret_cast<unsigned long long *>(ws + off[0]);
-  M.cnt = reinterpret_cast<U4 *>(ws + off[1]);
-  M.P = reinterpret_cast<U4 *>(ws + off[2]);
-  M.vlist = reinterpret_cast<uint32_t *>(ws + off[4]);
-  M.clist = reinterpret_cast<uint2 *>(ws + off[5]);
-  M.k = isovalue;
-  M.spacing = spacing;
-  M.verts = d_vertices;
-  M.tris = d_tris;
-  M.cap_v = cap_v;
-  M.cap_t = cap_t;
-  M.counts = d_counts;
-  launch_mc(M, reinterpret_cast<U4 *>(ws + off[3]), static_cast<hipStream_t>(stream));
+  launch_mc(J.M, J.scan, static_cast<hipStream_t>(stream));
   return check_hip("iso_extract launch");
 }
 

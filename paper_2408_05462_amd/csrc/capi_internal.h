@@ -1,0 +1,57 @@
+// capi_internal.h -- host-side planning shared by the single-field calls
+// (capi.hip) and the batch runner (batch.hip).  Each *_prepare function
+// validates its arguments, lays the workspace out and fills a launch plan;
+// the caller then launches it on a stream of its choice.
+#pragma once
+
+#include <string>
+
+#include "../../include/chr.h"
+#include "chr_plan.h"
+
+namespace chr {
+
+// Sets the calling thread's chr_last_error() text; returns code.
+int api_fail(int code, const std::string &msg);
+// Turns a pending HIP launch error into CHR_E_HIP.
+int api_check_launch(const char *what);
+
+struct EncJob {
+  EncPlan P;
+  U4 *scan;
+  uint64_t *scan64;
+};
+
+struct DecJob {
+  DecPlan D;
+};
+
+struct McJob {
+  McPlan M;
+  U4 *scan;
+};
+
+size_t enc_workspace_bytes(const int64_t dims[3], const chr_params *p);
+int enc_prepare(const float *d_field, const int64_t dims[3], double error_bound, const float *h_iso, int n_iso,
+                const chr_params *p, void *d_stream, size_t capacity, chr_result *d_result, int32_t *d_codes,
+                uint8_t *d_flags, void *d_ws, size_t ws_bytes, int cpw0, EncJob &J);
+
+// Reconstruction plan from the compression geometry (quantizer constants and
+// isovalues already set), for streams whose header is not on the host.
+size_t dec_workspace_bytes(const Geo &g, int level);
+int dec_prepare(const Geo &g, uint64_t payload_off, int level, const void *d_stream, uint64_t stream_bytes,
+                float *d_out, int32_t *d_status, void *d_ws, size_t ws_bytes, int cpw0, DecJob &J);
+
+size_t mc_workspace_bytes(const int64_t dims[3]);
+int mc_prepare(const float *d_field, const int64_t dims[3], float isovalue, float spacing, float *d_vertices,
+               int64_t cap_v, int32_t *d_tris, int64_t cap_t, int64_t *d_counts, void *d_ws, size_t ws_bytes,
+               McJob &J);
+
+// Compression geometry of a field (no device pointers): block grid,
+// quantizer constants, sorted distinct isovalues, stream table size.
+int enc_geometry(const int64_t dims[3], double error_bound, const float *h_iso, int n_iso, const chr_params *p,
+                 Geo &g, uint64_t &payload_off);
+
+bool tiles_ok(int enc_cpw, int dec_cpw);
+
+}  // namespace chr

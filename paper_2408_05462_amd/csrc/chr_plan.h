@@ -22,6 +22,7 @@ struct Part {
 struct EncPlan {
   Geo g;
   L0Geo l0;
+  int cpw0;                      // level-0 chunks per wave (tile shape; results do not depend on it)
   int64_t slot_base[kMaxLevels];
   uint32_t maxch[kMaxLevels];
   int64_t nslots;
@@ -52,6 +53,7 @@ struct EncPlan {
 struct DecPlan {
   Geo g;
   L0Geo l0;
+  int cpw0;                      // level-0 chunks per wave: 8, 16, 32 or 64
   int lo;
   int64_t gd[kMaxLevels][3];
   float *gp[kMaxLevels];         // compact grid of level l (gp[lo] = output when lo >= 1)
@@ -89,6 +91,7 @@ int64_t encode_fine_groups(const EncPlan &p);   // level-0 workgroups per block
 int64_t encode_l1_groups(const EncPlan &p);     // level-1 workgroups per block
 void encode_pack_layout(EncPlan &p);            // fills pack_base / pack_gpb
 void launch_decode(const DecPlan &p, hipStream_t s);
+void launch_status_reset(int32_t *status, hipStream_t s);  // *status = 0 by a kernel (capturable)
 void launch_mc(const McPlan &p, U4 *scan_tmp, hipStream_t s);
 void launch_mc_cases(const McPlan &p, hipStream_t s);
 void launch_range(const float *f, int64_t n, float *out, hipStream_t s);

@@ -274,9 +274,11 @@ __global__ __launch_bounds__(kBS) void k_decode_l1(DecPlan D) {
 // owns, plus the even points of even rows taken from level 1.
 __global__ __launch_bounds__(kBS) void k_decode_l0(DecPlan D) {
   const Geo &g = D.g;
-  uint32_t t, b;
-  xcd_remap(t, b);
-  const uint32_t kbeg = (threadIdx.x / kWave) * 16u;
+  uint32_t gxi, b;
+  xcd_remap(gxi, b);
+  const uint32_t cpw = (uint32_t)D.cpw0;
+  const uint32_t cbeg = (gxi * kWaves + threadIdx.x / kWave) * cpw;  // first chunk of this wave
+  const uint32_t t = cbeg >> 6, kbeg = cbeg & 63u;
   const int lane = lane_id();
   const BlockPos bp = block_pos(g, D.l0, b);
   const Sec s = D.l0.sec[bp.cls];  // by value: stays in scalar registers across the stores
@@ -316,7 +318,7 @@ __global__ __launch_bounds__(kBS) void k_decode_l0(DecPlan D) {
     set_status(D, -4);
     return;
   }
-  const uint32_t nc = min(min(64u, v.nch - t * 64), kbeg + 16u);
+  const uint32_t nc = min(min(64u, v.nch - t * 64), kbeg + cpw);
   const uint8_t *pay = v.p + v.Poff;
   const uint32_t *exv = reinterpret_cast<const uint32_t *>(v.p + v.Xoff);
 #pragma unroll 1
@@ -412,7 +414,9 @@ void launch_decode(const DecPlan &p, hipStream_t s) {
     const bool slab32 = (double)(hi[0] - o[0] + 1) * (double)g.n[1] * (double)g.n[2] < 4294967296.0;
     prof_mark("k_decode_fine", s, 0);
     if (L >= 1 && slab32) {
-      k_decode_l0<<<dim3((unsigned)(ntile > 0 ? ntile : 1), (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
+      const int64_t nch0 = ceil_div(s0.npts, 64);
+      const int64_t gx0 = ceil_div(nch0 > 0 ? nch0 : 1, (int64_t)kWaves * p.cpw0);
+      k_decode_l0<<<dim3((unsigned)gx0, (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
     } else {
       k_decode_fine<<<dim3((unsigned)ceil_div(ntile > 0 ? ntile : 1, kWaves), (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
     }
@@ -424,5 +428,11 @@ void launch_decode(const DecPlan &p, hipStream_t s) {
     }
   }
 }
+
+__global__ void k_status_reset(int32_t *status) {
+  if (threadIdx.x == 0) *status = 0;
+}
+
+void launch_status_reset(int32_t *status, hipStream_t s) { k_status_reset<<<dim3(1), dim3(64), 0, s>>>(status); }
 
 }  // namespace chr

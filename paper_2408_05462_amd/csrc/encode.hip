@@ -289,8 +289,8 @@ __global__ __launch_bounds__(kBS) void k_encode_fine(EncPlan P) {
   const uint32_t nch = (s.npts + 63) / 64;
   Part acc;
   part_init(acc);
-  for (int k = 0; k < kChunksPerWave; k++) {
-    const uint32_t c = (blockIdx.x * kChunksPerWave + k) * kWaves + wave;
+  for (int k = 0; k < P.cpw0; k++) {
+    const uint32_t c = (blockIdx.x * P.cpw0 + k) * kWaves + wave;
     if (c >= P.maxch[0]) break;
     if (c < nch) enc_chunk<KB>(P, 0, b, o, own, s, c, pack[wave], acc);
     else zero_slot(P, 0, b, c);
@@ -364,9 +364,10 @@ __global__ __launch_bounds__(kBS) void k_encode_l0(EncPlan P) {
   for (int jj = 0; jj < KB; jj++) iso[jj] = P.g.iso[jj];
   Part acc;
   part_init(acc);
+  const int cpw = P.cpw0;
 #pragma unroll 1
-  for (int k = 0; k < kChunksPerWave; k++) {
-    const uint32_t c = (gxi * kChunksPerWave + k) * kWaves + wave;
+  for (int k = 0; k < cpw; k++) {
+    const uint32_t c = (gxi * cpw + k) * kWaves + wave;
     if (c >= maxch) break;
     const int64_t slot = slot0 + c;
     if (c >= nch) {
@@ -701,7 +702,7 @@ __global__ __launch_bounds__(kBS) void k_header(EncPlan P) {
 
 }  // namespace
 
-int64_t encode_fine_groups(const EncPlan &p) { return ceil_div(p.maxch[0], (int64_t)kChunksPerWG); }
+int64_t encode_fine_groups(const EncPlan &p) { return ceil_div(p.maxch[0], (int64_t)kWaves * p.cpw0); }
 int64_t encode_l1_groups(const EncPlan &p) {
   return p.g.nL >= 2 ? ceil_div(p.maxch[1] > 0 ? p.maxch[1] : 1, (int64_t)kChunksPerWG) : 0;
 }

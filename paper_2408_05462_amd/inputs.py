@@ -126,6 +126,41 @@ def grf(n: int, t: float = 0.0, seed: int = SEED_BASE + 4) -> np.ndarray:
     return f.astype(np.float32)
 
 
+def grf_torch(n: int, t: float = 0.0, seed: int = SEED_BASE + 4, device="cuda"):
+    """The recipe of ``grf`` drawn with torch's generator on `device` (for
+    fields too large to synthesise quickly on the host): same spectrum,
+    phase drift and normalisation; different random draws."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed) * 4099 + int(n))
+    kz = torch.fft.fftfreq(n, device=device, dtype=torch.float32) * n
+    kx = torch.fft.rfftfreq(n, device=device, dtype=torch.float32) * n
+    kk = torch.sqrt(kz[:, None, None] ** 2 + kz[None, :, None] ** 2 + kx[None, None, :] ** 2)
+    amp = torch.where(kk > 0, kk.clamp_min(1e-30) ** (-11.0 / 6.0), torch.zeros_like(kk))
+    re = torch.randn(kk.shape, generator=g, device=device)
+    im = torch.randn(kk.shape, generator=g, device=device)
+    ph = 0.1 * kk ** (2.0 / 3.0) * float(t)
+    spec = torch.complex(amp * (re * torch.cos(ph) - im * torch.sin(ph)), amp * (re * torch.sin(ph) + im * torch.cos(ph)))
+    del re, im, ph, amp, kk
+    spec[0, 0, 0] = 0
+    f = torch.fft.irfftn(spec, s=(n, n, n), dim=(0, 1, 2))
+    del spec
+    f = (f - f.mean()) / f.std()
+    return f.float().contiguous()
+
+
+def sample_quantiles(values, count: int = 8, max_samples: int = 1 << 20):
+    """Isovalues at the (2j+1)/(2 count) quantiles of an evenly strided sample
+    (numpy array or torch tensor), as float32 values."""
+    flat = values.reshape(-1)
+    step = max(1, flat.shape[0] // max_samples)
+    sample = flat[::step]
+    sample = sample.cpu().numpy() if hasattr(sample, "cpu") else np.asarray(sample)
+    qs = [(2 * j + 1) / (2 * count) for j in range(count)]
+    return [float(np.float32(v)) for v in np.quantile(sample.astype(np.float64), qs)]
+
+
 def batch_sizes(count: int = 64, seed: int = SEED_BASE + 4):
     rng = np.random.default_rng(seed)
     return [int(s) for s in rng.choice([96, 128, 192, 256, 384], size=count)]
