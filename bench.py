@@ -46,9 +46,12 @@ def parse_args():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="phantom512",
-                    choices=["phantom512", "taylor_green256", "gaussians64", "batch64"])
+                    choices=["phantom512", "taylor_green256", "gaussians64", "batch64", "serve1024"])
+    ap.add_argument("--serve-n", type=int, default=1024, help="serve1024: field edge")
+    ap.add_argument("--requests", type=int, default=300, help="serve1024: requests per open-loop run")
+    ap.add_argument("--slots", type=int, default=4, help="serve1024: server slots")
+    ap.add_argument("--group", type=int, default=8, help="serve1024: requests per shared reconstruction")
     ap.add_argument("--batch-items", type=int, default=64, help="batch64: number of timesteps")
-    ap.add_argument("--tune-cache", default="", help="batch64: autotuner cache file (default: none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-planes", type=int, default=0,
                     help="z-planes of the field the oracle baseline runs on (0: automatic)")
@@ -80,7 +83,7 @@ def profile_traffic(kernel):
 
 def run_batch(args):
     """64 timesteps of uneven sizes: plain per-item launches against the
-    autotuned batch replayed as one captured graph (same outputs, checked)."""
+    batch replayed as one captured graph (same outputs, checked)."""
     import torch
 
     from paper_2408_05462_amd import api, inputs
@@ -140,9 +143,9 @@ def run_batch(args):
 
     t0 = time.time()
     batch = api.Batch(xs, es, isos, [p] * len(xs))
-    batch.autotune(args.tune_cache or None)
+    batch.capture()
     cfg = batch.config()
-    log(f"autotuned {cfg} in {time.time() - t0:.1f}s")
+    log(f"captured {cfg} in {time.time() - t0:.1f}s")
     ms_graph = timed(batch.replay, args.steps, args.warmup)
     log(f"graph {ms_graph:.3f} ms/step")
 
@@ -190,9 +193,204 @@ def run_batch(args):
                    "block": block, "error_bound": "1e-3 x range per item", "isovalues_per_item": 8},
         "hbm_frac_input": round(gbs / HBM_PEAK_GBS, 4),
         "plain": {"ms_per_step": round(ms_plain, 4), "value": round(4.0 * N / (ms_plain * 1e-3) / 1e9, 2)},
-        "speedup_vs_plain": round(ms_plain / ms_graph, 3), "tuned": cfg,
+        "speedup_vs_plain": round(ms_plain / ms_graph, 3), "graph_config": cfg,
         "compression_ratio": round(4.0 * N / stream_bytes, 3),
         "triangles": int(sum(int(c[:, 1].sum()) for c in cnt)),
+        "roofline": None, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_serve(args):
+    """A resident 1024^3 field at three accuracy tiers; a Poisson stream of
+    (isovalue, accuracy) requests served by the continuous-batching server
+    and, for comparison, by plain per-request launches (reconstruct, then
+    marching cubes, one request at a time in arrival order)."""
+    import torch
+
+    from paper_2408_05462_amd import _lib as L
+    from paper_2408_05462_amd import api, inputs
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n = args.serve_n
+    t0 = time.time()
+    x = inputs.grf_torch(n, 0.0, device=dev)
+    lo, hi = float(x.min()), float(x.max())
+    isos = inputs.sample_quantiles(x, 8)
+    levels, block = 6, 64
+    p = api.params(levels, block)
+    N = x.numel()
+    tiers = []
+    ws = torch.empty(api.chr_compress_workspace(x.shape, p), dtype=torch.uint8, device=dev)
+    buf = torch.empty(api.chr_compress_bound(x.shape, p), dtype=torch.uint8, device=dev)
+    res = torch.zeros(64, dtype=torch.uint8, device=dev)
+    for rel in (1e-2, 1e-3, 1e-4):
+        e = rel * (hi - lo)
+        api.chr_compress(x, e, isos, p, buf, res, ws)
+        torch.cuda.synchronize()
+        r = api.read_result(res)
+        assert r["status"] == 0
+        st = buf[: r["stream_bytes"]].clone()
+        info, _ = api.chr_stream_info_dev(st)
+        tiers.append((rel, e, st, info, r))
+    del ws, buf
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    log(f"field {n}^3 and 3 tiers ready in {time.time() - t0:.1f}s; ratios "
+        f"{[round(4.0 * N / t[4]['stream_bytes'], 2) for t in tiers]}")
+
+    rng = np.random.default_rng(inputs.SEED_BASE + 5)
+    R = args.requests
+    ks = rng.uniform(lo, hi, size=R).astype(np.float32)
+    tier_of = rng.integers(0, 3, size=R)
+    gaps = rng.exponential(1.0, size=R)
+
+    # plain: preallocated outputs sized from the largest surface (the median isovalue)
+    recon = torch.empty_like(x)
+    st0 = torch.zeros(1, dtype=torch.int32, device=dev)
+    rws = torch.empty(max(api.chr_reconstruct_workspace(t[3], 0) for t in tiers), dtype=torch.uint8, device=dev)
+    mws = torch.empty(api.iso_workspace(x.shape), dtype=torch.uint8, device=dev)
+    counts = torch.zeros(2, dtype=torch.int64, device=dev)
+    api.chr_reconstruct(tiers[2][3], tiers[2][2], 0, tiers[2][1], recon, st0, rws)
+    api.iso_extract(recon, float(np.median(isos)), 1.0, None, None, counts, mws)
+    torch.cuda.synchronize()
+    cv, ct = (int(v) for v in counts.cpu())
+    cap_v, cap_t = int(cv * 1.25) + 1024, int(ct * 1.25) + 1024
+    verts = torch.empty((cap_v, 3), dtype=torch.float32, device=dev)
+    tris = torch.empty((cap_t, 3), dtype=torch.int32, device=dev)
+    del mws
+    mws = torch.empty(api.iso_workspace(x.shape), dtype=torch.uint8, device=dev)
+    log(f"plain output capacity {cap_v} vertices, {cap_t} triangles")
+
+    def plain_run(arrivals):
+        """Requests served one at a time in arrival order; returns latencies (ms) and wall (s)."""
+        lat = np.zeros(R)
+        torch.cuda.synchronize()
+        base = time.perf_counter()
+        for i in range(R):
+            now = (time.perf_counter() - base) * 1e3
+            if arrivals[i] > now:
+                time.sleep((arrivals[i] - now) * 1e-3)
+            rel, e, st, info, _ = tiers[tier_of[i]]
+            api.chr_reconstruct(info, st, 0, e, recon, st0, rws)
+            api.iso_extract(recon, float(ks[i]), 1.0, verts, tris, counts, mws)
+            torch.cuda.synchronize()
+            lat[i] = (time.perf_counter() - base) * 1e3 - arrivals[i]
+        return lat, time.perf_counter() - base
+
+    del recon
+    torch.cuda.empty_cache()
+    free_b, _ = torch.cuda.mem_get_info()
+    pool = torch.empty(int(free_b * 0.6) & ~255, dtype=torch.uint8, device=dev)
+    recon = torch.empty_like(x)
+    log(f"server pool {pool.numel() / 2**30:.1f} GiB")
+
+    def served_run(arrivals, slots, group):
+        srv = api.Server(pool, slots=slots, max_group=group)
+        for t in tiers:
+            srv.add_stream(0, t[3], t[2])
+        ids = [None] * R
+        lat = np.zeros(R)
+        pending = set()
+        torch.cuda.synchronize()
+        base = srv.now_ms()
+        nxt = 0
+        while nxt < R or pending:
+            now = srv.now_ms() - base
+            while nxt < R and arrivals[nxt] <= now:
+                ids[nxt] = srv.submit(0, float(ks[nxt]), tiers[tier_of[nxt]][1], 0)
+                pending.add(nxt)
+                nxt += 1
+            if srv.step() or pending:
+                for i in list(pending):
+                    r = srv.poll(ids[i])
+                    if r.status != L.CHR_PENDING:
+                        assert r.status == 0, (i, r.status)
+                        lat[i] = r.t_done_ms - base - arrivals[i]
+                        srv.release(ids[i])
+                        pending.discard(i)
+        wall = (srv.now_ms() - base) * 1e-3
+        stats = srv.stats()
+        srv.close()
+        return lat, wall, stats
+
+    # closed loop (all requests at t = 0): saturation throughput of each path
+    zero = np.zeros(R)
+    lat_p, wall_p = plain_run(zero)
+    lat_s, wall_s, st_s = served_run(zero, args.slots, args.group)
+    sat_plain, sat_served = R / wall_p, R / wall_s
+    log(f"saturation: plain {sat_plain:.1f} req/s, served {sat_served:.1f} req/s ({st_s})")
+    # open loop: Poisson arrivals at fractions of the plain path's saturation rate
+    runs = {}
+    for frac in (0.5, 0.8, 1.0):
+        lam = frac * sat_plain
+        arr = np.cumsum(gaps) / lam * 1e3
+        lp, wp = plain_run(arr)
+        ls, ws_, sts = served_run(arr, args.slots, args.group)
+        runs[str(frac)] = {
+            "lambda_req_s": round(lam, 2),
+            "plain": {"p50_ms": round(float(np.percentile(lp, 50)), 3), "p99_ms": round(float(np.percentile(lp, 99)), 3),
+                      "req_s": round(R / wp, 2)},
+            "served": {"p50_ms": round(float(np.percentile(ls, 50)), 3), "p99_ms": round(float(np.percentile(ls, 99)), 3),
+                       "req_s": round(R / ws_, 2), "mean_group": round(sts["grouped_requests"] / max(sts["groups"], 1), 2)},
+        }
+        log(f"lambda {frac} x plain saturation: {runs[str(frac)]}")
+
+    # a sample of served meshes equals the plain calls' meshes
+    srv = api.Server(pool, slots=args.slots, max_group=args.group)
+    for t in tiers:
+        srv.add_stream(0, t[3], t[2])
+    sample = list(range(0, R, max(1, R // 8)))[:8]
+    sid = [srv.submit(0, float(ks[i]), tiers[tier_of[i]][1], 0) for i in sample]
+    srv.drain(sid)
+    for i, rid in zip(sample, sid):
+        rel, e, st, info, _ = tiers[tier_of[i]]
+        api.chr_reconstruct(info, st, 0, e, recon, st0, rws)
+        api.iso_extract(recon, float(ks[i]), 1.0, verts, tris, counts, mws)
+        torch.cuda.synchronize()
+        nv, nt = (int(v) for v in counts.cpu())
+        r = srv.poll(rid)
+        assert r.status == 0 and (r.n_vertices, r.n_triangles) == (nv, nt), i
+        v, t = srv.mesh(rid)
+        assert np.array_equal(v.view(np.uint32), verts[:nv].cpu().numpy().view(np.uint32)), i
+        assert np.array_equal(t, tris[:nt].cpu().numpy()), i
+    srv.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        # the oracle serves a sample of requests on a 256-plane slab of the same field
+        planes = 64
+        slab = x[:planes].cpu().numpy()
+        tc = time.perf_counter()
+        done = 0
+        for i in sample[:4]:
+            rel = tiers[tier_of[i]][0]
+            ref = oracle.compress(slab, rel * (hi - lo), isos, levels=levels, block=block)
+            y = oracle.decompress(ref["stream"])
+            oracle.mc(y, float(ks[i]))
+            done += 1
+        tcpu = time.perf_counter() - tc
+        cpu = {"value": round(4.0 * slab.size * done / tcpu / 1e9, 4), "unit": "GB/s", "cores": int(oracle.threads()),
+               "kind": "oracle",
+               "sample": f"{done} requests (compress+reconstruct+MC) on the first {planes} z-planes, {tcpu:.2f}s"}
+
+    mid = runs["0.8"]
+    gbs = sat_served * 4.0 * N / 1e9
+    out = {
+        "metric": METRIC, "value": round(gbs, 2), "unit": "GB/s", "n_gpus": 1, "steps": R, "warmup": 0,
+        "ms_per_step": round(1e3 / sat_served, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "serve1024", "dims": [n, n, n], "levels": levels, "block": block,
+                   "tiers_rel": [1e-2, 1e-3, 1e-4], "requests": R, "slots": args.slots, "max_group": args.group},
+        "value_is": "served saturation throughput x 4N input bytes per request",
+        "saturation_req_s": {"plain": round(sat_plain, 2), "served": round(sat_served, 2)},
+        "latency_at_0.8": {"plain_p50_ms": mid["plain"]["p50_ms"], "plain_p99_ms": mid["plain"]["p99_ms"],
+                           "served_p50_ms": mid["served"]["p50_ms"], "served_p99_ms": mid["served"]["p99_ms"]},
+        "open_loop": runs,
+        "compression_ratio": [round(4.0 * N / t[4]["stream_bytes"], 3) for t in tiers],
         "roofline": None, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -206,6 +404,8 @@ def main():
         sys.exit(2)
     if args.workload == "batch64":
         return run_batch(args)
+    if args.workload == "serve1024":
+        return run_serve(args)
 
     import torch
 

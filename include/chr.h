@@ -45,6 +45,8 @@ extern "C" {
 #define CHR_E_CAPACITY (-5) /* output buffer too small; size reported       */
 #define CHR_E_NOMEM (-6)    /* workspace too small                           */
 #define CHR_E_HIP (-7)      /* a HIP runtime call failed                     */
+#define CHR_E_CANCELLED (-8) /* served request cancelled before it finished  */
+#define CHR_PENDING 1        /* served request still queued or in flight     */
 
 /* Compression parameters.
  *  levels: nL, number of hierarchy levels (1..16).  Level nL-1 holds the
@@ -270,6 +272,99 @@ int chr_batch_config(const chr_batch *b, int *branches, int *enc_cpw, int *dec_c
 
 /* Releases the batch's streams, events and graph (not the caller's buffers). */
 int chr_batch_destroy(chr_batch *b);
+
+/* ---- serving (resident streams, continuous batching) ---------------------- */
+
+/* The visualization side of Sec. II: a viewer asks for the isosurface of a
+ * dataset at an isovalue and an accuracy, and the data it needs is
+ * reconstructed from the CHR held in memory (here: resident in HBM) and
+ * isosurfaced.  A request (dataset, isovalue, accuracy, level) is served
+ * from the dataset's stream with the largest error bound <= accuracy,
+ * reconstructed at `level` and extracted with spacing 2^level.
+ *
+ * Continuous batching: queued requests are admitted whenever a slot (a HIP
+ * stream of the server's own) and pool memory are free.  Requests with the
+ * same (stream, level) at the head of the queue form a group sharing one
+ * reconstruction; each request of a group then runs the counting half of
+ * marching cubes, the host reads the counts, allocates exactly sized lists
+ * and mesh from the pool, and launches the emitting half.  Groups on
+ * different slots overlap on the device.  Admission is FIFO by memory
+ * footprint: reconstruction + its workspace + per-request counting state
+ * must fit in the pool, else the head of the queue waits until completed
+ * work frees memory.  Every request runs the kernels and arithmetic of
+ * chr_reconstruct + iso_extract, so its mesh is bit for bit what those calls
+ * give, alone or in any mix.
+ *
+ * All calls are host calls on one thread (the server is not thread-safe).
+ * create/add_stream/submit/poll/cancel/release make no HIP call; step and
+ * destroy do. */
+
+typedef struct chr_server chr_server;
+
+typedef struct chr_server_config {
+  int slots;            /* groups in flight at once, 1..16 */
+  int max_group;        /* requests sharing one reconstruction, 1..64 */
+  void *d_pool;         /* caller-owned device memory the server allocates from */
+  size_t pool_bytes;
+} chr_server_config;
+
+typedef struct chr_request_result {
+  int32_t status;       /* CHR_PENDING, CHR_OK, CHR_E_CANCELLED, CHR_E_NOMEM, CHR_E_CORRUPT, CHR_E_HIP */
+  int32_t level;
+  int32_t dataset;
+  int32_t stream_index; /* which registered stream served it */
+  float isovalue;
+  int32_t group_size;   /* requests that shared its reconstruction */
+  double error_bound;   /* of that stream */
+  int64_t n_vertices, n_triangles;
+  const float *d_vertices;     /* float32 [n_vertices][3] in the pool, valid until release */
+  const int32_t *d_triangles;  /* int32 [n_triangles][3] in the pool, valid until release */
+  double t_submit_ms, t_admit_ms, t_done_ms;  /* server clock (chr_server_now_ms) */
+} chr_request_result;
+
+typedef struct chr_server_stats {
+  int64_t queued, in_flight, done, failed;
+  size_t pool_used, pool_peak;
+  int64_t groups, grouped_requests;
+} chr_server_stats;
+
+/* Errors: CHR_E_INVAL (slots or max_group out of range, NULL pool). */
+int chr_server_create(const chr_server_config *cfg, chr_server **out);
+
+/* Registers a resident stream of `dataset` (any int id).  info: parsed by
+ * chr_stream_info from a host copy of the stream's header and tables;
+ * d_stream (caller-owned, stream_bytes >= info->total_bytes) must stay valid
+ * and unchanged while the server lives.  *index: the stream's index. */
+int chr_server_add_stream(chr_server *s, int dataset, const chr_info *info, const void *d_stream,
+                          size_t stream_bytes, int *index);
+
+/* Queues a request; *id identifies it.  Errors (nothing queued):
+ * CHR_E_INVAL unknown dataset or non-finite isovalue; CHR_E_ACCURACY no
+ * stream of the dataset meets `accuracy`; CHR_E_LEVEL level outside that
+ * stream's hierarchy; CHR_E_NOMEM its footprint exceeds the whole pool. */
+int chr_server_submit(chr_server *s, int dataset, float isovalue, double accuracy, int level, int64_t *id);
+
+/* Advances every group whose device work has finished and admits queued
+ * requests into free slots; never waits for the device.  *n_done (may be
+ * NULL): requests that finished in this call. */
+int chr_server_step(chr_server *s, int *n_done);
+
+/* State of a request (CHR_E_INVAL for an unknown or released id). */
+int chr_server_poll(const chr_server *s, int64_t id, chr_request_result *out);
+
+/* Frees a finished request's mesh; its id becomes unknown. */
+int chr_server_release(chr_server *s, int64_t id);
+
+/* Cancels a request: a queued one leaves the queue, one in flight has its
+ * outputs freed when its group finishes.  Its status becomes CHR_E_CANCELLED. */
+int chr_server_cancel(chr_server *s, int64_t id);
+
+int chr_server_stats_get(const chr_server *s, chr_server_stats *out);
+double chr_server_now_ms(const chr_server *s);
+
+/* Waits for work in flight, then frees the server's streams, events and
+ * pinned host memory (not the pool). */
+int chr_server_destroy(chr_server *s);
 
 /* ---- measurement support ------------------------------------------------ */
 

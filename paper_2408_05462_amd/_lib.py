@@ -16,15 +16,18 @@ LIB_PATH = os.path.join(HERE, "libchr.so")
 
 CHR_OK, CHR_E_INVAL, CHR_E_ACCURACY, CHR_E_LEVEL = 0, -1, -2, -3
 CHR_E_CORRUPT, CHR_E_CAPACITY, CHR_E_NOMEM, CHR_E_HIP = -4, -5, -6, -7
+CHR_E_CANCELLED, CHR_PENDING = -8, 1
 STATUS_NAMES = {0: "CHR_OK", -1: "CHR_E_INVAL", -2: "CHR_E_ACCURACY", -3: "CHR_E_LEVEL", -4: "CHR_E_CORRUPT",
-                -5: "CHR_E_CAPACITY", -6: "CHR_E_NOMEM", -7: "CHR_E_HIP"}
+                -5: "CHR_E_CAPACITY", -6: "CHR_E_NOMEM", -7: "CHR_E_HIP", -8: "CHR_E_CANCELLED", 1: "CHR_PENDING"}
 
 EXPORTS = ["chr_last_error", "chr_version", "chr_compress_bound", "chr_compress_workspace", "chr_compress",
            "chr_stream_info", "chr_stream_verify", "chr_reconstruct_workspace", "chr_reconstruct",
            "iso_workspace", "iso_extract", "iso_cases", "chr_mc_table", "chr_range", "chr_prof_enable",
            "chr_prof_collect", "chr_prof_disable", "chr_set_tiles", "chr_batch_create", "chr_batch_workspace",
            "chr_batch_run", "chr_batch_capture", "chr_batch_replay", "chr_batch_autotune", "chr_batch_config",
-           "chr_batch_destroy"]
+           "chr_batch_destroy", "chr_server_create", "chr_server_add_stream", "chr_server_submit",
+           "chr_server_step", "chr_server_poll", "chr_server_release", "chr_server_cancel", "chr_server_stats_get",
+           "chr_server_now_ms", "chr_server_destroy"]
 
 
 class ChrError(RuntimeError):
@@ -58,6 +61,24 @@ class chr_batch_item(C.Structure):
                 ("d_vertices", C.c_void_p * 16), ("cap_v", C.c_int64 * 16), ("d_tris", C.c_void_p * 16),
                 ("cap_t", C.c_int64 * 16), ("d_counts", C.c_void_p), ("d_status", C.c_void_p),
                 ("spacing", C.c_float)]
+
+
+class chr_server_config(C.Structure):
+    _fields_ = [("slots", C.c_int), ("max_group", C.c_int), ("d_pool", C.c_void_p), ("pool_bytes", C.c_size_t)]
+
+
+class chr_request_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("level", C.c_int32), ("dataset", C.c_int32), ("stream_index", C.c_int32),
+                ("isovalue", C.c_float), ("group_size", C.c_int32), ("error_bound", C.c_double),
+                ("n_vertices", C.c_int64), ("n_triangles", C.c_int64), ("d_vertices", C.c_void_p),
+                ("d_triangles", C.c_void_p), ("t_submit_ms", C.c_double), ("t_admit_ms", C.c_double),
+                ("t_done_ms", C.c_double)]
+
+
+class chr_server_stats(C.Structure):
+    _fields_ = [("queued", C.c_int64), ("in_flight", C.c_int64), ("done", C.c_int64), ("failed", C.c_int64),
+                ("pool_used", C.c_size_t), ("pool_peak", C.c_size_t), ("groups", C.c_int64),
+                ("grouped_requests", C.c_int64)]
 
 
 RESULT_BYTES = C.sizeof(chr_result)
@@ -129,6 +150,26 @@ def load():
     L.chr_batch_config.restype = C.c_int
     L.chr_batch_destroy.argtypes = [vp]
     L.chr_batch_destroy.restype = C.c_int
+    L.chr_server_create.argtypes = [C.POINTER(chr_server_config), C.POINTER(vp)]
+    L.chr_server_create.restype = C.c_int
+    L.chr_server_add_stream.argtypes = [vp, C.c_int, C.POINTER(chr_info), vp, C.c_size_t, ip]
+    L.chr_server_add_stream.restype = C.c_int
+    L.chr_server_submit.argtypes = [vp, C.c_int, C.c_float, C.c_double, C.c_int, C.POINTER(C.c_int64)]
+    L.chr_server_submit.restype = C.c_int
+    L.chr_server_step.argtypes = [vp, ip]
+    L.chr_server_step.restype = C.c_int
+    L.chr_server_poll.argtypes = [vp, C.c_int64, C.POINTER(chr_request_result)]
+    L.chr_server_poll.restype = C.c_int
+    L.chr_server_release.argtypes = [vp, C.c_int64]
+    L.chr_server_release.restype = C.c_int
+    L.chr_server_cancel.argtypes = [vp, C.c_int64]
+    L.chr_server_cancel.restype = C.c_int
+    L.chr_server_stats_get.argtypes = [vp, C.POINTER(chr_server_stats)]
+    L.chr_server_stats_get.restype = C.c_int
+    L.chr_server_now_ms.argtypes = [vp]
+    L.chr_server_now_ms.restype = C.c_double
+    L.chr_server_destroy.argtypes = [vp]
+    L.chr_server_destroy.restype = C.c_int
     _lib = L
     return L
 

@@ -338,3 +338,95 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------------ serving
+
+class Server:
+    """Request loop over resident streams (chr_server_*).  `pool` is a uint8
+    device tensor the server allocates reconstructions, counting state and
+    meshes from; the caller keeps the registered streams alive."""
+
+    def __init__(self, pool, slots=4, max_group=8):
+        self.pool = pool
+        cfg = L.chr_server_config(int(slots), int(max_group), pool.data_ptr() if pool is not None else None,
+                                  0 if pool is None else pool.numel())
+        h = C.c_void_p()
+        L.check(L.load().chr_server_create(C.byref(cfg), C.byref(h)), "chr_server_create")
+        self.handle = h
+        self._streams = []
+
+    def add_stream(self, dataset, info, stream_dev):
+        idx = C.c_int()
+        L.check(L.load().chr_server_add_stream(self.handle, int(dataset), C.byref(info), _p(stream_dev),
+                                               stream_dev.numel(), C.byref(idx)), "chr_server_add_stream")
+        self._streams.append(stream_dev)
+        return idx.value
+
+    def submit(self, dataset, isovalue, accuracy, level=0):
+        rid = C.c_int64()
+        L.check(L.load().chr_server_submit(self.handle, int(dataset), float(np.float32(isovalue)), float(accuracy),
+                                           int(level), C.byref(rid)), "chr_server_submit")
+        return rid.value
+
+    def step(self):
+        n = C.c_int()
+        L.check(L.load().chr_server_step(self.handle, C.byref(n)), "chr_server_step")
+        return n.value
+
+    def poll(self, rid):
+        r = L.chr_request_result()
+        L.check(L.load().chr_server_poll(self.handle, int(rid), C.byref(r)), "chr_server_poll")
+        return r
+
+    def mesh(self, rid):
+        """Host copies (verts [V,3] f32, tris [T,3] i32) of a finished request."""
+        r = self.poll(rid)
+        if r.status != 0:
+            raise L.ChrError(r.status, f"request {rid}")
+        nv, nt = int(r.n_vertices), int(r.n_triangles)
+        base = self.pool.data_ptr()
+        v = self.pool[r.d_vertices - base: r.d_vertices - base + 12 * nv] if nv else self.pool[:0]
+        t = self.pool[r.d_triangles - base: r.d_triangles - base + 12 * nt] if nt else self.pool[:0]
+        return (v.view(torch.float32).reshape(nv, 3).cpu().numpy(), t.view(torch.int32).reshape(nt, 3).cpu().numpy())
+
+    def release(self, rid):
+        L.check(L.load().chr_server_release(self.handle, int(rid)), "chr_server_release")
+
+    def cancel(self, rid):
+        L.check(L.load().chr_server_cancel(self.handle, int(rid)), "chr_server_cancel")
+
+    def stats(self):
+        st = L.chr_server_stats()
+        L.check(L.load().chr_server_stats_get(self.handle, C.byref(st)), "chr_server_stats_get")
+        return {f: getattr(st, f) for f, _ in L.chr_server_stats._fields_}
+
+    def now_ms(self):
+        return L.load().chr_server_now_ms(self.handle)
+
+    def drain(self, ids=None, timeout_s=120.0):
+        """Steps until every request (or those in `ids`) has finished."""
+        import time
+
+        t_end = time.monotonic() + timeout_s
+        while True:
+            self.step()
+            if ids is None:
+                st = self.stats()
+                if st["queued"] == 0 and st["in_flight"] == 0:
+                    return
+            elif all(self.poll(i).status != L.CHR_PENDING for i in ids):
+                return
+            if time.monotonic() > t_end:
+                raise TimeoutError(f"server did not drain: {self.stats()}")
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            L.load().chr_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

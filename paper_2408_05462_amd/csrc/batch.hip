@@ -23,6 +23,11 @@ using namespace chr;
 namespace {
 
 constexpr int kMaxBranches = 8;
+// The replay-timed search re-captures and re-instantiates the graph for every
+// candidate.  One GPU run aborted inside it (no fault message; the single
+// capture + replay path has never failed); it stays off until that is
+// explained.
+constexpr bool kAutotuneEnabled = false;
 
 size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
 
@@ -303,6 +308,9 @@ int chr_batch_replay(chr_batch *b, void *stream) {
 
 int chr_batch_autotune(chr_batch *b, void *d_ws, size_t ws_bytes, void *stream, const char *cache_path) {
   if (!b) return api_fail(CHR_E_INVAL, "NULL batch");
+  if (!kAutotuneEnabled)
+    return api_fail(CHR_E_INVAL, "chr_batch_autotune is switched off: one run aborted inside its capture/replay "
+                                 "search on the GPU and the cause is not yet known");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const std::string sig = signature(b);
   int cb, ce, cd;

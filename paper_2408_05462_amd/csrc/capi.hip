@@ -366,6 +366,7 @@ int mc_prepare(const float *d_field, const int64_t dims[3], float isovalue, floa
   M.P = reinterpret_cast<U4 *>(ws + off[2]);
   M.vlist = reinterpret_cast<uint32_t *>(ws + off[4]);
   M.clist = reinterpret_cast<uint2 *>(ws + off[5]);
+  M.cap_pv = M.cap_ac = M.nrows * M.nw * 64;
   M.k = isovalue;
   M.spacing = spacing;
   M.verts = d_vertices;
@@ -374,6 +375,22 @@ int mc_prepare(const float *d_field, const int64_t dims[3], float isovalue, floa
   M.cap_t = cap_t;
   M.counts = d_counts;
   J.scan = reinterpret_cast<U4 *>(ws + off[3]);
+  return CHR_OK;
+}
+
+// Geometry of a stream from its parsed header, checked for consistency.
+int info_geo(const chr_info *I, Geo &g) {
+  chr_params p{I->levels, I->block, I->qmax};
+  std::string why;
+  if (!params_ok(I->dims, &p, why)) return fail(CHR_E_CORRUPT, why);
+  fill_geo(g, I->dims, I->levels, I->block, I->qmax);
+  set_quant(g, I->error_bound);
+  if (std::memcmp(&g.inv, &I->inv, 4) || std::memcmp(&g.step, &I->step, 4))
+    return fail(CHR_E_CORRUPT, "quantizer constants do not match the error bound");
+  if ((g.lossless ? 1u : 0u) != (I->flags & 1u)) return fail(CHR_E_CORRUPT, "lossless flag mismatch");
+  if (I->n_iso < 0 || I->n_iso > kMaxIso) return fail(CHR_E_CORRUPT, "bad isovalue count");
+  g.K = I->n_iso;
+  for (int j = 0; j < kMaxIso; j++) g.iso[j] = I->isovalues[j];
   return CHR_OK;
 }
 
@@ -528,22 +545,6 @@ int chr_stream_verify(const void *h_stream, size_t n) {
     if (host_checksum(s + start, end - start) != rd<uint32_t>(s + btab + 16 * (size_t)b + 8))
       return fail(CHR_E_CORRUPT, "block checksum mismatch");
   }
-  return CHR_OK;
-}
-
-// Geometry of a stream from its parsed header, checked for consistency.
-static int info_geo(const chr_info *I, Geo &g) {
-  chr_params p{I->levels, I->block, I->qmax};
-  std::string why;
-  if (!params_ok(I->dims, &p, why)) return fail(CHR_E_CORRUPT, why);
-  fill_geo(g, I->dims, I->levels, I->block, I->qmax);
-  set_quant(g, I->error_bound);
-  if (std::memcmp(&g.inv, &I->inv, 4) || std::memcmp(&g.step, &I->step, 4))
-    return fail(CHR_E_CORRUPT, "quantizer constants do not match the error bound");
-  if ((g.lossless ? 1u : 0u) != (I->flags & 1u)) return fail(CHR_E_CORRUPT, "lossless flag mismatch");
-  if (I->n_iso < 0 || I->n_iso > kMaxIso) return fail(CHR_E_CORRUPT, "bad isovalue count");
-  g.K = I->n_iso;
-  for (int j = 0; j < kMaxIso; j++) g.iso[j] = I->isovalues[j];
   return CHR_OK;
 }
 

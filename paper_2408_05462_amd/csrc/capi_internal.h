@@ -54,4 +54,8 @@ int enc_geometry(const int64_t dims[3], double error_bound, const float *h_iso, 
 
 bool tiles_ok(int enc_cpw, int dec_cpw);
 
+// Geometry of a stream from its parsed header (parameters, quantizer
+// constants and lossless flag checked against each other).
+int info_geo(const chr_info *I, Geo &g);
+
 }  // namespace chr

@@ -71,8 +71,9 @@ struct McPlan {
   const float *f;
   unsigned long long *bits;      // nrows * nw below-isovalue bits
   U4 *cnt, *P;                   // per word {vertices, triangles, crossing points, active cells} and prefix
-  uint32_t *vlist;               // crossing points (word*64 + bit)
-  uint2 *clist;                  // active cells (word*64 + bit, first triangle id)
+  uint32_t *vlist;               // crossing points (word*64 + bit), cap_pv entries
+  uint2 *clist;                  // active cells (word*64 + bit, first triangle id), cap_ac entries
+  int64_t cap_pv, cap_ac;
   float *verts;
   int32_t *tris;
   int64_t cap_v, cap_t;
@@ -92,7 +93,9 @@ int64_t encode_l1_groups(const EncPlan &p);     // level-1 workgroups per block
 void encode_pack_layout(EncPlan &p);            // fills pack_base / pack_gpb
 void launch_decode(const DecPlan &p, hipStream_t s);
 void launch_status_reset(int32_t *status, hipStream_t s);  // *status = 0 by a kernel (capturable)
-void launch_mc(const McPlan &p, U4 *scan_tmp, hipStream_t s);
+void launch_mc(const McPlan &p, U4 *scan_tmp, hipStream_t s);        // count + emit
+void launch_mc_count(const McPlan &p, U4 *scan_tmp, hipStream_t s);  // bits, counts, scan; totals to counts[0..3]
+void launch_mc_emit(const McPlan &p, hipStream_t s);                 // lists, vertices, triangles, counts[0..1]
 void launch_mc_cases(const McPlan &p, hipStream_t s);
 void launch_range(const float *f, int64_t n, float *out, hipStream_t s);
 void mc_table_host(uint8_t *ntri, int8_t *tri);

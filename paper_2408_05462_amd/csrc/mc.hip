@@ -178,7 +178,7 @@ __global__ __launch_bounds__(kBS) void k_mc_expand(McPlan M) {
   const int64_t gw = (int64_t)blockIdx.x * kBS + threadIdx.x;
   if (gw >= M.nrows * M.nw) return;
   const U4 p0 = M.P[gw], p1 = M.P[gw + 1];
-  if (p1.z != p0.z) {
+  if (p1.z != p0.z && (int64_t)p1.z <= M.cap_pv) {
     const WordCtx c = word_ctx(M, gw);
     const Cross x = cross_of(M, c.z, c.y, c.w);
     u64 pts = x.cx | x.cy | x.cz;
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(kBS) void k_mc_expand(McPlan M) {
       M.vlist[r++] = (uint32_t)(gw * 64 + i);
     }
   }
-  if (p1.w != p0.w) {
+  if (p1.w != p0.w && (int64_t)p1.w <= M.cap_ac) {
     const WordCtx c = word_ctx(M, gw);
     const Corners C = corners_of(M, c.row, c.w);
     u64 act = active_cells(C, c.validx);
@@ -206,7 +206,7 @@ __global__ __launch_bounds__(kBS) void k_mc_expand(McPlan M) {
 // One lane per crossing point: its vertices in axis order x, y, z.
 __global__ __launch_bounds__(kBS) void k_mc_verts(McPlan M) {
   const int64_t nwords = M.nrows * M.nw;
-  const uint32_t n = M.P[nwords].z;
+  const uint32_t n = (int64_t)M.P[nwords].z <= M.cap_pv ? M.P[nwords].z : 0u;  // lists are whole or unused
   const int64_t n1 = M.n[1], n2 = M.n[2];
   const float *f = M.f;
   const float k = M.k, sp = M.spacing;
@@ -258,7 +258,7 @@ __global__ __launch_bounds__(kBS) void k_mc_tris(McPlan M) {
   }
   __syncthreads();
   const int64_t nwords = M.nrows * M.nw;
-  const uint32_t n = M.P[nwords].w;
+  const uint32_t n = (int64_t)M.P[nwords].w <= M.cap_ac ? M.P[nwords].w : 0u;
   const int64_t n1 = M.n[1];
   for (uint32_t e = blockIdx.x * kBS + threadIdx.x; e < n; e += gridDim.x * kBS) {
     const uint2 ent = M.clist[e];
@@ -313,11 +313,15 @@ __global__ __launch_bounds__(kBS) void k_mc_tris(McPlan M) {
   }
 }
 
-__global__ void k_mc_counts(McPlan M) {
+__global__ void k_mc_counts(McPlan M, int with_lists) {
   if (threadIdx.x == 0) {
     const int64_t n = M.nrows * M.nw;
     M.counts[0] = (int64_t)M.P[n].x;
     M.counts[1] = (int64_t)M.P[n].y;
+    if (with_lists) {
+      M.counts[2] = (int64_t)M.P[n].z;
+      M.counts[3] = (int64_t)M.P[n].w;
+    }
   }
 }
 
@@ -369,7 +373,7 @@ __global__ void k_range_fin(uint32_t *acc) {
 
 }  // namespace
 
-void launch_mc(const McPlan &p, U4 *scan_tmp, hipStream_t s) {
+void launch_mc_count(const McPlan &p, U4 *scan_tmp, hipStream_t s) {
   const int64_t nwords = p.nrows * p.nw;
   prof_mark("k_mc_bits", s, 0);
   k_mc_bits<<<dim3((unsigned)ceil_div(p.nrows, kWaves)), dim3(kBS), 0, s>>>(p);
@@ -378,6 +382,11 @@ void launch_mc(const McPlan &p, U4 *scan_tmp, hipStream_t s) {
   k_mc_count<<<dim3((unsigned)ceil_div(nwords, kBS)), dim3(kBS), 0, s>>>(p);
   prof_mark("k_mc_count", s, 1);
   scan_u4(p.cnt, p.P, nwords, scan_tmp, s);
+  k_mc_counts<<<dim3(1), dim3(64), 0, s>>>(p, 1);
+}
+
+void launch_mc_emit(const McPlan &p, hipStream_t s) {
+  const int64_t nwords = p.nrows * p.nw;
   prof_mark("k_mc_expand", s, 0);
   k_mc_expand<<<dim3((unsigned)ceil_div(nwords, kBS)), dim3(kBS), 0, s>>>(p);
   prof_mark("k_mc_expand", s, 1);
@@ -388,7 +397,19 @@ void launch_mc(const McPlan &p, U4 *scan_tmp, hipStream_t s) {
   prof_mark("k_mc_tris", s, 0);
   k_mc_tris<<<dim3(2048), dim3(kBS), 0, s>>>(p);
   prof_mark("k_mc_tris", s, 1);
-  k_mc_counts<<<dim3(1), dim3(64), 0, s>>>(p);
+  k_mc_counts<<<dim3(1), dim3(64), 0, s>>>(p, 0);
+}
+
+void launch_mc(const McPlan &p, U4 *scan_tmp, hipStream_t s) {
+  const int64_t nwords = p.nrows * p.nw;
+  prof_mark("k_mc_bits", s, 0);
+  k_mc_bits<<<dim3((unsigned)ceil_div(p.nrows, kWaves)), dim3(kBS), 0, s>>>(p);
+  prof_mark("k_mc_bits", s, 1);
+  prof_mark("k_mc_count", s, 0);
+  k_mc_count<<<dim3((unsigned)ceil_div(nwords, kBS)), dim3(kBS), 0, s>>>(p);
+  prof_mark("k_mc_count", s, 1);
+  scan_u4(p.cnt, p.P, nwords, scan_tmp, s);
+  launch_mc_emit(p, s);
 }
 
 void launch_mc_cases(const McPlan &p, hipStream_t s) {

@@ -100,6 +100,8 @@ def test_batch_graph_replays_match_single_calls(data):
     b.close()
 
 
+@pytest.mark.skip(reason="chr_batch_autotune is switched off: one GPU run aborted inside its replay-timed search "
+                         "(SIGABRT, no fault message) and the cause is not yet known")
 def test_batch_autotune_and_cache(data, tmp_path):
     fields, xs, singles = data
     cache = tmp_path / "tune.txt"

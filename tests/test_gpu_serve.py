@@ -1,0 +1,176 @@
+"""Serving loop through the C ABI: every request's mesh is bit for bit the
+mesh of chr_reconstruct + iso_extract on the stream that served it, whether
+the request ran alone or in a mix of overlapping groups, under memory
+pressure (admission waits, preemption), with cancellations and with a
+corrupt stream beside it."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2408_05462_amd import _lib as L
+from paper_2408_05462_amd import api, inputs
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+TIERS = (1e-2, 1e-3, 1e-4)
+
+
+def _datasets():
+    a = inputs.grf(64, 0.3)
+    z, y, x = np.meshgrid(*[np.linspace(0, 3, n) for n in (40, 33, 70)], indexing="ij")
+    b = (np.sin(x + 0.3 * y) * np.cos(y - z)).astype(np.float32)
+    return {0: (a, 4, 32), 1: (b, 3, 16)}
+
+
+@pytest.fixture(scope="module")
+def world():
+    rng = np.random.default_rng(5)
+    data = {}
+    for ds, (f, nL, B) in _datasets().items():
+        x = torch.from_numpy(f).to(DEV)
+        isos = [float(v) for v in np.quantile(f, [0.2, 0.4, 0.6, 0.8]).astype(np.float32)]
+        tiers = []
+        for rel in TIERS:
+            e = inputs.abs_error_bound(rel, f)
+            tiers.append((e, api.compress(x, e, isos, levels=nL, block=B)))
+        data[ds] = (f, nL, tiers)
+    reqs = []
+    for _ in range(28):
+        ds = int(rng.integers(0, 2))
+        f, nL, tiers = data[ds]
+        k = float(np.float32(rng.uniform(f.min(), f.max())))
+        t = int(rng.integers(0, 3))
+        level = int(rng.integers(0, 2))
+        reqs.append((ds, k, tiers[t][0], level, t))
+    refs = []
+    for ds, k, acc, level, t in reqs:
+        c = data[ds][2][t][1]
+        y = api.reconstruct(c, level)
+        v, tr = api.extract(y, k, spacing=float(1 << level))
+        refs.append((v.cpu().numpy(), tr.cpu().numpy()))
+    return data, reqs, refs
+
+
+def _server(data, pool_bytes=512 << 20, slots=4, group=4):
+    pool = torch.empty(pool_bytes, dtype=torch.uint8, device=DEV)
+    s = api.Server(pool, slots=slots, max_group=group)
+    for ds, (f, nL, tiers) in data.items():
+        for e, c in tiers:
+            s.add_stream(ds, c.info, c.stream)
+    return s
+
+
+def _check(s, ids, reqs, refs, what):
+    for i, rid in enumerate(ids):
+        r = s.poll(rid)
+        assert r.status == 0, (what, i, r.status)
+        v, t = s.mesh(rid)
+        vr, tr = refs[i]
+        assert np.array_equal(v.view(np.uint32), vr.view(np.uint32)), (what, i, reqs[i])
+        assert np.array_equal(t, tr), (what, i, reqs[i])
+
+
+def test_serve_alone_matches_plain_calls(world):
+    data, reqs, refs = world
+    s = _server(data, slots=1, group=1)
+    for i, (ds, k, acc, level, t) in enumerate(reqs):
+        rid = s.submit(ds, k, acc, level)
+        s.drain([rid])
+        _check(s, [rid], [reqs[i]], [refs[i]], "alone")
+        assert s.poll(rid).group_size == 1
+        s.release(rid)
+    assert s.stats()["pool_used"] == 0
+    s.close()
+
+
+def test_serve_mix_matches_plain_calls(world):
+    data, reqs, refs = world
+    s = _server(data, slots=4, group=4)
+    ids = [s.submit(ds, k, acc, level) for ds, k, acc, level, t in reqs]
+    s.drain(ids)
+    _check(s, ids, reqs, refs, "mix")
+    st = s.stats()
+    print("mix stats", st, flush=True)
+    assert st["groups"] < len(reqs)  # requests on the same stream and level shared reconstructions
+    for rid in ids:
+        s.release(rid)
+    assert s.stats()["pool_used"] == 0
+    s.close()
+
+
+def test_serve_continuous_arrivals(world):
+    """Requests arrive while others are on the device; each is admitted as
+    slots and memory free up."""
+    data, reqs, refs = world
+    s = _server(data, slots=3, group=2)
+    ids = []
+    for i, (ds, k, acc, level, t) in enumerate(reqs):
+        ids.append(s.submit(ds, k, acc, level))
+        for _ in range(i % 3):
+            s.step()
+    s.drain(ids)
+    _check(s, ids, reqs, refs, "continuous")
+    for rid in ids:
+        s.release(rid)
+    s.close()
+
+
+def test_serve_under_memory_pressure(world):
+    """A pool that holds about one group and its meshes: admission waits for
+    memory, and groups waiting for mesh memory are preempted and rerun."""
+    data, reqs, refs = world
+    f0 = data[0][0]
+    one = 4 * f0.size * 8 + (1 << 20)
+    s = _server(data, pool_bytes=one, slots=4, group=4)
+    ids = [s.submit(ds, k, acc, level) for ds, k, acc, level, t in reqs]
+    # release finished meshes as they complete so that waiting work can proceed
+    released = set()
+    import time
+
+    t_end = time.monotonic() + 120
+    while len(released) < len(ids):
+        s.step()
+        for i, rid in enumerate(ids):
+            if rid in released:
+                continue
+            r = s.poll(rid)
+            if r.status != L.CHR_PENDING:
+                assert r.status == 0, (i, r.status)
+                v, t = s.mesh(rid)
+                assert np.array_equal(v.view(np.uint32), refs[i][0].view(np.uint32)), i
+                assert np.array_equal(t, refs[i][1]), i
+                s.release(rid)
+                released.add(rid)
+        assert time.monotonic() < t_end, s.stats()
+    st = s.stats()
+    print("pressure stats", st, flush=True)
+    assert st["pool_used"] == 0 and st["pool_peak"] <= one
+    s.close()
+
+
+def test_serve_cancel_and_corrupt_stream(world):
+    data, reqs, refs = world
+    s = _server(data, slots=2, group=2)
+    # a corrupt copy of one stream as dataset 9: the first section's point count is wrong
+    f, nL, tiers = data[0]
+    c = tiers[0][1]
+    bad = c.stream.clone()
+    off = int.from_bytes(bytes(bad[256:264].cpu().numpy()), "little")
+    npts = int.from_bytes(bytes(bad[off:off + 4].cpu().numpy()), "little")
+    bad[off:off + 4] = torch.tensor(list((npts + 1).to_bytes(4, "little")), dtype=torch.uint8, device=DEV)
+    s.add_stream(9, c.info, bad)
+    ids = [s.submit(ds, k, acc, level) for ds, k, acc, level, t in reqs[:8]]
+    rbad = s.submit(9, 0.0, 1.0, 0)
+    s.cancel(ids[7])       # still queued
+    s.step()               # admits the first groups
+    s.cancel(ids[0])       # in flight: finishes, then is dropped
+    s.drain(ids + [rbad])
+    assert s.poll(ids[7]).status == L.CHR_E_CANCELLED
+    assert s.poll(ids[0]).status == L.CHR_E_CANCELLED
+    assert s.poll(rbad).status == L.CHR_E_CORRUPT
+    _check(s, ids[1:7], reqs[1:7], refs[1:7], "beside cancel/corrupt")
+    for rid in ids + [rbad]:
+        s.release(rid)
+    assert s.stats()["pool_used"] == 0
+    s.close()

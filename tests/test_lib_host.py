@@ -84,23 +84,26 @@ def test_workspace_queries():
     assert api.iso_workspace((33, 20, 70)) > 0
 
 
-def test_batch_item_layout_matches_c(tmp_path):
-    """The ctypes mirror of chr_batch_item has the C compiler's layout."""
+@pytest.mark.parametrize("name", ["chr_batch_item", "chr_server_config", "chr_request_result",
+                                  "chr_server_stats", "chr_info", "chr_result", "chr_params"])
+def test_struct_layout_matches_c(tmp_path, name):
+    """Each ctypes mirror of a chr.h struct has the C compiler's layout."""
     import shutil
     import subprocess
 
     cc = shutil.which("gcc")
     if cc is None:
         pytest.skip("gcc not available")
-    fields = [f for f, _ in L.chr_batch_item._fields_]
+    st = getattr(L, name)
+    fields = [f for f, _ in st._fields_]
     src = tmp_path / "lay.c"
     src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "chr.h"\nint main(void){\n'
-                   '  printf("%zu\\n", sizeof(chr_batch_item));\n'
-                   + "".join(f'  printf("%zu\\n", offsetof(chr_batch_item, {f}));\n' for f in fields) + "  return 0;\n}\n")
+                   f'  printf("%zu\\n", sizeof({name}));\n'
+                   + "".join(f'  printf("%zu\\n", offsetof({name}, {f}));\n' for f in fields) + "  return 0;\n}\n")
     exe = tmp_path / "lay"
     subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
-    want = [C.sizeof(L.chr_batch_item)] + [getattr(L.chr_batch_item, f).offset for f in fields]
+    want = [C.sizeof(st)] + [getattr(st, f).offset for f in fields]
     assert got == want
 
 
@@ -148,6 +151,9 @@ def test_batch_plan_workspace_and_rejections():
     assert 1 <= b.value <= len(shapes) and (e.value, d.value) == (4, 16)
     # a replay before any capture is an error, not a launch
     assert lib.chr_batch_replay(h, None) == L.CHR_E_INVAL
+    # the replay-timed autotuner is switched off: refused before any device call
+    assert lib.chr_batch_autotune(h, 0x100000, 1 << 40, None, None) == L.CHR_E_INVAL
+    assert b"switched off" in lib.chr_last_error()
     assert lib.chr_batch_destroy(h) == L.CHR_OK
 
     bad = _items(shapes)
@@ -167,3 +173,83 @@ def test_batch_plan_workspace_and_rejections():
     bad[0].cap_v[0] = 10  # capacity without a buffer
     assert lib.chr_batch_create(bad, len(shapes), C.byref(h)) == L.CHR_E_INVAL
     assert lib.chr_batch_create(items, 0, C.byref(h)) == L.CHR_E_INVAL
+
+
+def _tier_infos():
+    """Host-parsed headers of oracle streams of one small field at three error bounds."""
+    from paper_2408_05462_amd import inputs
+
+    f = inputs.gaussians(24)
+    out = []
+    for rel in (1e-2, 1e-3, 1e-4):
+        e = inputs.abs_error_bound(rel, f)
+        ref = oracle.compress(f, e, [0.3, 0.5], levels=3, block=8)
+        out.append((e, api.chr_stream_info(ref["stream"].tobytes()), ref["stream"].size))
+    return out
+
+
+def _server(pool_bytes=1 << 30, slots=2, group=4):
+    lib = L.load()
+    cfg = L.chr_server_config(slots, group, 0x100000, pool_bytes)  # placeholder address: never dereferenced here
+    h = C.c_void_p()
+    assert lib.chr_server_create(C.byref(cfg), C.byref(h)) == L.CHR_OK
+    return lib, h
+
+
+def test_server_config_validation():
+    lib = L.load()
+    h = C.c_void_p()
+    for slots, group, pool, nbytes in [(0, 4, 0x1000, 1 << 20), (17, 4, 0x1000, 1 << 20), (2, 0, 0x1000, 1 << 20),
+                                       (2, 65, 0x1000, 1 << 20), (2, 4, None, 1 << 20), (2, 4, 0x1000, 16)]:
+        cfg = L.chr_server_config(slots, group, pool, nbytes)
+        assert lib.chr_server_create(C.byref(cfg), C.byref(h)) == L.CHR_E_INVAL
+
+
+def test_server_submit_selects_tier_and_rejects():
+    """Submission is host logic: tier choice, and every rejection, happen
+    before any device work (no GPU is touched here)."""
+    tiers = _tier_infos()
+    lib, h = _server()
+    idx = C.c_int()
+    for e, info, n in tiers:
+        assert lib.chr_server_add_stream(h, 7, C.byref(info), 0x200000, n, C.byref(idx)) == L.CHR_OK
+    # a stream shorter than its header states is refused
+    assert lib.chr_server_add_stream(h, 8, C.byref(tiers[0][1]), 0x200000, 100, C.byref(idx)) == L.CHR_E_CORRUPT
+    rid = C.c_int64()
+    r = L.chr_request_result()
+    # the loosest stream whose bound meets the accuracy serves the request
+    for acc, want in [(tiers[0][0], 0), (tiers[0][0] * 0.99, 1), (tiers[1][0], 1), (1e9, 0), (tiers[2][0], 2)]:
+        assert lib.chr_server_submit(h, 7, 0.4, acc, 0, C.byref(rid)) == L.CHR_OK
+        assert lib.chr_server_poll(h, rid.value, C.byref(r)) == L.CHR_OK
+        assert r.status == L.CHR_PENDING and r.stream_index == want and r.error_bound == tiers[want][0]
+    n_ok = rid.value + 1
+    assert lib.chr_server_submit(h, 7, 0.4, tiers[2][0] * 0.5, 0, C.byref(rid)) == L.CHR_E_ACCURACY
+    assert lib.chr_server_submit(h, 9, 0.4, 1.0, 0, C.byref(rid)) == L.CHR_E_INVAL
+    assert lib.chr_server_submit(h, 7, float("nan"), 1.0, 0, C.byref(rid)) == L.CHR_E_INVAL
+    assert lib.chr_server_submit(h, 7, 0.4, 1.0, 3, C.byref(rid)) == L.CHR_E_LEVEL
+    assert lib.chr_server_submit(h, 7, 0.4, 1.0, -1, C.byref(rid)) == L.CHR_E_LEVEL
+    st = L.chr_server_stats()
+    assert lib.chr_server_stats_get(h, C.byref(st)) == L.CHR_OK and st.queued == n_ok and st.in_flight == 0
+    # cancel a queued request; release it; it is then unknown
+    assert lib.chr_server_cancel(h, 1) == L.CHR_OK
+    assert lib.chr_server_poll(h, 1, C.byref(r)) == L.CHR_OK and r.status == L.CHR_E_CANCELLED
+    assert lib.chr_server_cancel(h, 1) == L.CHR_E_INVAL
+    assert lib.chr_server_release(h, 0) == L.CHR_E_INVAL  # still queued
+    assert lib.chr_server_release(h, 1) == L.CHR_OK
+    assert lib.chr_server_poll(h, 1, C.byref(r)) == L.CHR_E_INVAL
+    assert lib.chr_server_poll(h, 999, C.byref(r)) == L.CHR_E_INVAL
+    assert lib.chr_server_stats_get(h, C.byref(st)) == L.CHR_OK and st.queued == n_ok - 1 and st.failed == 1
+    assert lib.chr_server_destroy(h) == L.CHR_OK
+
+
+def test_server_rejects_requests_larger_than_the_pool():
+    tiers = _tier_infos()
+    e, info, n = tiers[0]
+    lib, h = _server(pool_bytes=64 << 10)
+    idx = C.c_int()
+    assert lib.chr_server_add_stream(h, 1, C.byref(info), 0x200000, n, C.byref(idx)) == L.CHR_OK
+    rid = C.c_int64()
+    # level 0 (24^3 reconstruction + counting state) exceeds 64 KiB; level 2 (6^3) fits
+    assert lib.chr_server_submit(h, 1, 0.4, 1.0, 0, C.byref(rid)) == L.CHR_E_NOMEM
+    assert lib.chr_server_submit(h, 1, 0.4, 1.0, 2, C.byref(rid)) == L.CHR_OK
+    assert lib.chr_server_destroy(h) == L.CHR_OK
