@@ -116,9 +116,11 @@ size_t chr_compress_workspace(const int64_t dims[3], const chr_params *p);
  * d_codes, d_flags: optional (may be NULL) per-point outputs in field layout:
  *   quantization code (0 where stored exactly) and flags (bit 0 outlier,
  *   bit 1 topology correction).
+ * d_stream must be 8-byte aligned (CHR_E_INVAL otherwise).
  * Device-detected: non-finite input -> status CHR_E_INVAL (stream invalid);
  * stream larger than capacity -> status CHR_E_CAPACITY, stream_bytes = the
- * required size, nothing written beyond capacity. */
+ * required size, nothing written beyond capacity (sections that do not fit
+ * are not written at all). */
 int chr_compress(const float *d_field, const int64_t dims[3], double error_bound,
                  const float *h_isovalues, int n_iso, const chr_params *p,
                  void *d_stream, size_t capacity, chr_result *d_result,
@@ -141,7 +143,8 @@ int chr_stream_verify(const void *h_stream, size_t n);
 /* Workspace bytes chr_reconstruct needs for this stream and level. */
 size_t chr_reconstruct_workspace(const chr_info *info, int level);
 
-/* Reconstructs level `level` of a stream held on the device.
+/* Reconstructs level `level` of a stream held on the device (d_stream
+ * 8-byte aligned, else CHR_E_INVAL).
  * info: header parsed by chr_stream_info from a host copy of the stream.
  * Output: d_out, float32 [((nz-1)>>level)+1][((ny-1)>>level)+1][((nx-1)>>level)+1],
  *   the reconstructed values of the points whose coordinates are multiples

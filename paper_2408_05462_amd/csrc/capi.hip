@@ -244,6 +244,7 @@ int enc_prepare(const float *d_field, const int64_t dims[3], double error_bound,
                 const chr_params *p, void *d_stream, size_t capacity, chr_result *d_result, int32_t *d_codes,
                 uint8_t *d_flags, void *d_ws, size_t ws_bytes, int cpw0, EncJob &J) {
   if (!d_field || !d_stream || !d_result || !d_ws) return fail(CHR_E_INVAL, "NULL device pointer");
+  if (reinterpret_cast<uintptr_t>(d_stream) & 7) return fail(CHR_E_INVAL, "stream buffer must be 8-byte aligned");
   EncPlan &P = J.P;
   std::memset(&P, 0, sizeof(P));
   uint64_t poff = 0;
@@ -295,6 +296,7 @@ int dec_prepare(const Geo &g, uint64_t payload_off, int level, const void *d_str
   DecPlan &D = J.D;
   std::memset(&D, 0, sizeof(D));
   if (!d_stream || !d_out) return fail(CHR_E_INVAL, "NULL argument");
+  if (reinterpret_cast<uintptr_t>(d_stream) & 7) return fail(CHR_E_INVAL, "stream must be 8-byte aligned");
   if (level < 0 || level >= g.nL) return fail(CHR_E_LEVEL, "level outside the hierarchy");
   if (g.nblocks > 65535) return fail(CHR_E_INVAL, "more than 65535 blocks");
   const size_t need = dec_need(g, level);

@@ -79,6 +79,7 @@ struct McPlan {
   int64_t cap_v, cap_t;
   int64_t *counts;
   uint8_t *cases;
+  FastDiv d_nw, d_n1;            // word -> (row, word in row), row -> (z, y); set by the launchers
 };
 
 // Measurement hook: records a HIP event around launches of the kernel

@@ -509,10 +509,17 @@ __global__ __launch_bounds__(kBS) void k_sec_table(EncPlan P) {
   for (uint64_t i = Xend; i < end; i++) put8(P, so + i, 0);
 }
 
-// Copies chunks from their slots into the stream; one workgroup per
-// (level, block, group of kChunksPerWG chunks).  Levels are laid out from the
-// coarsest (first workgroups) to level 0.
+// Copies the chunks of one tile (64 chunks) of one section from their slots
+// into the stream: chunk header bytes, the tile-table entry, payload words,
+// exact masks and exact values.  Payload words are flattened over the tile,
+// so consecutive threads move consecutive 8-byte words of the stream.  One
+// workgroup per (level, block, tile); levels are laid out from the coarsest
+// (first workgroups) to level 0.  A section that does not fit the capacity is
+// not written (the result then reports the required size).
 __global__ __launch_bounds__(kBS) void k_pack(EncPlan P) {
+  __shared__ uint16_t s_own[64 * kMaxW];  // chunk (within the tile) of each payload word
+  __shared__ uint32_t s_pw[64], s_px[64], s_nx[64];
+  __shared__ uint32_t s_tot, s_base;
   const Geo &g = P.g;
   const int L = g.nL - 1;
   const int lane = lane_id();
@@ -523,7 +530,7 @@ __global__ __launch_bounds__(kBS) void k_pack(EncPlan P) {
     if (wg >= P.pack_base[t]) l = t;
   const int64_t rel = wg - P.pack_base[l];
   const int64_t b = rel / P.pack_gpb[l];
-  const uint32_t grp = (uint32_t)(rel % P.pack_gpb[l]);
+  const uint32_t tile = (uint32_t)(rel - b * P.pack_gpb[l]);
   Sec s;
   if (l == 0) {
     s = P.l0.sec[block_pos(g, P.l0, (uint32_t)b).cls];
@@ -534,35 +541,61 @@ __global__ __launch_bounds__(kBS) void k_pack(EncPlan P) {
   }
   const uint32_t nch = (s.npts + 63) / 64;
   const uint32_t ntile = (nch + 63) / 64;
+  if (tile >= ntile) return;
+  const int64_t sec = b * g.nL + (L - l);
+  const uint64_t so = P.payload_off + P.secoff[sec];
+  if (so + P.secsz[sec] > P.cap) return;
   const int64_t s0 = P.slot_base[l] + b * (int64_t)P.maxch[l];
   const U4 a = P.P[s0], e = P.P[s0 + nch];
   const uint32_t W = e.x - a.x, NE = e.y - a.y;
-  const uint64_t so = P.payload_off + P.secoff[b * g.nL + (L - l)];
   const uint64_t A = 16 + pad8(12 * (uint64_t)ntile), Poff = A + pad8(nch);
   const uint64_t Moff = Poff + 8 * (uint64_t)W, Xoff = Moff + 8 * (uint64_t)NE;
-  const U4 *__restrict__ Pp = P.P;
-  const U4 *__restrict__ cntp = P.cnt;
-  const uint32_t *__restrict__ pay = P.pay;
-  const float *__restrict__ exv = P.exv;
-  for (int k = 0; k < kChunksPerWave; k++) {
-    const uint32_t c = grp * kChunksPerWG + k * kWaves + wave;
-    if (c >= nch) break;
-    const int64_t slot = s0 + c;
-    const U4 cur = Pp[slot], cc = cntp[slot];
-    const uint32_t pw = cur.x - a.x, pe = cur.y - a.y, px = cur.z - a.z;
+  const uint32_t c0 = tile * 64, tn = min(64u, nch - c0);
+  uint8_t *out = P.out + so;
+  const int64_t slot0 = s0 + c0;
+  if (wave == 0) {
+    const bool on = (uint32_t)lane < tn;
+    const U4 cur = on ? P.P[slot0 + lane] : U4{0, 0, 0, 0};
+    const U4 cc = on ? P.cnt[slot0 + lane] : U4{0, 0, 0, 0};
+    const uint32_t base_w = __builtin_amdgcn_readfirstlane(cur.x);
+    const uint32_t pw = cur.x - base_w;  // payload words of the tile before this chunk
     if (lane == 0) {
-      if (c % 64 == 0) {
-        const uint64_t t = so + 16 + 12 * (uint64_t)(c / 64);
-        put32(P, t, pw);
-        put32(P, t + 4, pe);
-        put32(P, t + 8, px);
-      }
-      put8(P, so + A + c, (uint8_t)(cc.x | (cc.y ? 0x80u : 0u)));
-      if (cc.y) put64(P, so + Moff + 8 * (uint64_t)pe, P.emask[slot]);
+      uint32_t *tt = reinterpret_cast<uint32_t *>(out + 16 + 12 * (uint64_t)tile);
+      tt[0] = cur.x - a.x;
+      tt[1] = cur.y - a.y;
+      tt[2] = cur.z - a.z;
     }
-    if (lane < 2 * (int)cc.x) put32(P, so + Poff + 8 * (uint64_t)pw + 4 * lane, pay[slot * 32 + lane]);
-    if (lane < (int)cc.z)
-      put32(P, so + Xoff + 4 * ((uint64_t)px + lane), __float_as_uint(exv[slot * 64 + lane]));
+    if (on) {
+      out[A + c0 + lane] = (uint8_t)(cc.x | (cc.y ? 0x80u : 0u));
+      if (cc.y) {
+        uint32_t *m = reinterpret_cast<uint32_t *>(out + Moff + 8 * (uint64_t)(cur.y - a.y));
+        const unsigned long long em = P.emask[slot0 + lane];
+        m[0] = (uint32_t)em;
+        m[1] = (uint32_t)(em >> 32);
+      }
+      for (uint32_t k = 0; k < cc.x; k++) s_own[pw + k] = (uint16_t)lane;
+    }
+    s_pw[lane] = pw;
+    s_px[lane] = cur.z - a.z;
+    s_nx[lane] = on ? cc.z : 0u;
+    if ((uint32_t)lane == tn - 1) s_tot = pw + cc.x;
+    if (lane == 0) s_base = cur.x - a.x;
+  }
+  __syncthreads();
+  // payload: 8-byte words of the tile in stream order
+  const uint32_t tot = s_tot, base = s_base;
+  const unsigned long long *__restrict__ pay = reinterpret_cast<const unsigned long long *>(P.pay);
+  unsigned long long *__restrict__ dst = reinterpret_cast<unsigned long long *>(out + Poff) + base;
+  for (uint32_t u = threadIdx.x; u < tot; u += kBS) {
+    const uint32_t c = s_own[u];
+    dst[u] = pay[(slot0 + c) * 16 + (u - s_pw[c])];
+  }
+  // exact values: one wave per chunk that has any
+  const uint32_t *__restrict__ exv = reinterpret_cast<const uint32_t *>(P.exv);
+  uint32_t *xo = reinterpret_cast<uint32_t *>(out + Xoff);
+  for (uint32_t c = (uint32_t)wave; c < tn; c += kWaves) {
+    const uint32_t nx = s_nx[c];
+    if ((uint32_t)lane < nx) xo[s_px[c] + lane] = exv[(slot0 + c) * 64 + lane];
   }
 }
 
@@ -712,7 +745,7 @@ void encode_pack_layout(EncPlan &p) {
   int64_t base = 0;
   for (int l = L; l >= 0; l--) {
     p.pack_base[l] = base;
-    p.pack_gpb[l] = ceil_div(p.maxch[l] > 0 ? p.maxch[l] : 1, (int64_t)kChunksPerWG);
+    p.pack_gpb[l] = ceil_div(p.maxch[l] > 0 ? p.maxch[l] : 1, (int64_t)64);  // tiles of 64 chunks
     base += p.g.nblocks * p.pack_gpb[l];
   }
   for (int l = L + 1; l < kMaxLevels; l++) { p.pack_base[l] = base; p.pack_gpb[l] = 1; }

@@ -27,6 +27,14 @@ constexpr int kWordsPerWave = 8;
 constexpr mct::Table kTable = mct::make_table();
 __constant__ mct::Table c_table = kTable;
 
+constexpr int max_ntri(const mct::Table &t) {
+  int m = 0;
+  for (int c = 0; c < 256; c++) m = t.ntri[c] > m ? t.ntri[c] : m;
+  return m;
+}
+constexpr int kMaxTri = max_ntri(kTable);  // triangles of one cell at most
+static_assert(kMaxTri <= 5, "triangle staging assumes at most 5 triangles per cell");
+
 typedef unsigned long long u64;
 
 // f < k for 64 consecutive points per word.  One wave per row of points;
@@ -70,6 +78,20 @@ __device__ inline WordCtx word_ctx(const McPlan &M, int64_t gw) {
   c.valid = rem >= 64 ? ~0ull : ((1ull << rem) - 1ull);
   const int64_t remx = rem - 1;
   c.validx = remx >= 64 ? ~0ull : (remx <= 0 ? 0ull : ((1ull << remx) - 1ull));
+  return c;
+}
+
+// 32-bit form (word indices are below 2^26: padded points are below 2^32).
+struct WordCtx32 {
+  uint32_t row, w, z, y;
+};
+
+__device__ inline WordCtx32 word_ctx32(const McPlan &M, uint32_t gw) {
+  WordCtx32 c;
+  c.row = fdiv(gw, M.d_nw);
+  c.w = gw - c.row * (uint32_t)M.nw;
+  c.z = fdiv(c.row, M.d_n1);
+  c.y = c.row - c.z * (uint32_t)M.n[1];
   return c;
 }
 
@@ -157,13 +179,6 @@ __device__ inline float interp(float fa, float fb, float k) {
   return __fdiv_rn(__fsub_rn(k, fa), __fsub_rn(fb, fa));
 }
 
-// Vertex-id context of one owner row for word w: crossing masks of words w
-// and w+1 and their vertex bases.
-struct Owner {
-  Cross c0, c1;
-  uint64_t v0, v1;
-};
-
 __device__ inline int popc3_below(const Cross &c, int x) {
   const u64 bm = (x >= 64) ? ~0ull : ((1ull << x) - 1ull);
   return __popcll(c.cx & bm) + __popcll(c.cy & bm) + __popcll(c.cz & bm);
@@ -203,21 +218,22 @@ __global__ __launch_bounds__(kBS) void k_mc_expand(McPlan M) {
   }
 }
 
-// One lane per crossing point: its vertices in axis order x, y, z.
+// One lane per crossing point: its vertices in axis order x, y, z (a lane's
+// vertices are consecutive, and so are consecutive lanes').
 __global__ __launch_bounds__(kBS) void k_mc_verts(McPlan M) {
-  const int64_t nwords = M.nrows * M.nw;
+  const uint32_t nwords = (uint32_t)(M.nrows * M.nw);
   const uint32_t n = (int64_t)M.P[nwords].z <= M.cap_pv ? M.P[nwords].z : 0u;  // lists are whole or unused
-  const int64_t n1 = M.n[1], n2 = M.n[2];
+  const uint32_t n1 = (uint32_t)M.n[1], n2 = (uint32_t)M.n[2];
   const float *f = M.f;
   const float k = M.k, sp = M.spacing;
   for (uint32_t e = blockIdx.x * kBS + threadIdx.x; e < n; e += gridDim.x * kBS) {
     const uint32_t code = M.vlist[e];
-    const int64_t gw = code >> 6;
+    const uint32_t gw = code >> 6;
     const int i = code & 63;
-    const WordCtx c = word_ctx(M, gw);
+    const WordCtx32 c = word_ctx32(M, gw);
     const Cross x = cross_of(M, c.z, c.y, c.w);
-    uint64_t id = M.P[gw].x + popc3_below(x, i);
-    const int64_t xx = c.w * 64 + i;
+    uint64_t id = M.P[gw].x + (uint32_t)popc3_below(x, i);
+    const uint32_t xx = c.w * 64u + (uint32_t)i;
     const size_t gi = ((size_t)c.z * n1 + c.y) * n2 + xx;
     const float fa = f[gi];
     const float px = (float)xx, py = (float)c.y, pz = (float)c.z;
@@ -247,69 +263,103 @@ __global__ __launch_bounds__(kBS) void k_mc_verts(McPlan M) {
   }
 }
 
-// One lane per active cell: its triangles in table order, each corner the id
-// of the vertex on the cell edge it names.
+// Vertex id of the owner point at bit `xo` (0..64) of word w of a row, and
+// that point's +x / +y crossing bits (the vertex on its +y edge follows the
+// one on +x, the one on +z follows both).
+struct Owner {
+  uint32_t base, bx, by;
+};
+
+__device__ inline Owner owner_at(const McPlan &M, uint32_t z, uint32_t y, uint32_t row, uint32_t w, const Cross &c,
+                                 uint32_t vb, int xo) {
+  Owner o;
+  if (xo < 64) {
+    o.base = vb + (uint32_t)popc3_below(c, xo);
+    o.bx = (uint32_t)((c.cx >> xo) & 1ull);
+    o.by = (uint32_t)((c.cy >> xo) & 1ull);
+  } else {
+    // the owner starts the next word (inside the row because the cell is)
+    const Cross c1 = cross_of(M, z, y, w + 1);
+    o.base = M.P[row * (uint32_t)M.nw + w + 1].x;
+    o.bx = (uint32_t)(c1.cx & 1ull);
+    o.by = (uint32_t)(c1.cy & 1ull);
+  }
+  return o;
+}
+
+// One lane per active cell: the ids of its 12 edge vertices go to LDS, then
+// its triangles in table order.  A workgroup takes 256 consecutive active
+// cells, whose triangles are one contiguous id range; they are staged in LDS
+// and written out coalesced.
 __global__ __launch_bounds__(kBS) void k_mc_tris(McPlan M) {
+  constexpr int kIdStride = 13;  // 12 edge ids per lane, odd stride against bank conflicts
   __shared__ mct::Table tab;
+  __shared__ int32_t st[kBS * kMaxTri * 3];
+  __shared__ int32_t sid[kBS * kIdStride];
   {
     const uint8_t *src = reinterpret_cast<const uint8_t *>(&c_table);
     uint8_t *dst = reinterpret_cast<uint8_t *>(&tab);
     for (int i = threadIdx.x; i < (int)sizeof(mct::Table); i += kBS) dst[i] = src[i];
   }
   __syncthreads();
-  const int64_t nwords = M.nrows * M.nw;
+  const uint32_t nwords = (uint32_t)(M.nrows * M.nw);
   const uint32_t n = (int64_t)M.P[nwords].w <= M.cap_ac ? M.P[nwords].w : 0u;
-  const int64_t n1 = M.n[1];
-  for (uint32_t e = blockIdx.x * kBS + threadIdx.x; e < n; e += gridDim.x * kBS) {
-    const uint2 ent = M.clist[e];
-    const int64_t gw = ent.x >> 6;
-    const int i = ent.x & 63;
-    const WordCtx c = word_ctx(M, gw);
-    const Corners C = corners_of(M, c.row, c.w);
-    const uint32_t cs = case_at(C, i);
-    const int nt = tab.ntri[cs];
-    const int64_t rows[4] = {c.row, c.row + 1, c.row + n1, c.row + n1 + 1};
-    const int64_t ry[4] = {c.y, c.y + 1, c.y, c.y + 1}, rz[4] = {c.z, c.z, c.z + 1, c.z + 1};
-    Cross own0[4];
-    uint64_t vb0[4];
-    for (int r = 0; r < 4; r++) {
-      own0[r] = cross_of(M, rz[r], ry[r], c.w);
-      vb0[r] = M.P[rows[r] * M.nw + c.w].x;
+  const uint32_t T = M.P[nwords].y;
+  const uint32_t n1 = (uint32_t)M.n[1], nw = (uint32_t)M.nw;
+  int32_t *my = sid + threadIdx.x * kIdStride;
+  for (uint32_t e0 = blockIdx.x * kBS; e0 < n; e0 += gridDim.x * kBS) {
+    const uint32_t e = e0 + threadIdx.x;
+    const uint32_t tbase = M.clist[e0].y;
+    const uint32_t e_end = min(e0 + (uint32_t)kBS, n);
+    const uint32_t tend = e_end < n ? M.clist[e_end].y : T;
+    if (e < n) {
+      const uint2 ent = M.clist[e];
+      const uint32_t gw = ent.x >> 6;
+      const int i = ent.x & 63;
+      const WordCtx32 c = word_ctx32(M, gw);
+      const Corners C = corners_of(M, c.row, c.w);
+      const uint32_t cs = case_at(C, i);
+      const int nt = tab.ntri[cs];
+      // owner rows R = dy + 2 dz
+      const uint32_t r0 = c.row, r1 = c.row + 1, r2 = c.row + n1, r3 = c.row + n1 + 1;
+      const Cross k0 = cross_of(M, c.z, c.y, c.w), k1 = cross_of(M, c.z, c.y + 1, c.w);
+      const Cross k2 = cross_of(M, c.z + 1, c.y, c.w), k3 = cross_of(M, c.z + 1, c.y + 1, c.w);
+      const uint32_t v0 = M.P[r0 * nw + c.w].x, v1 = M.P[r1 * nw + c.w].x;
+      const uint32_t v2 = M.P[r2 * nw + c.w].x, v3 = M.P[r3 * nw + c.w].x;
+      const Owner a00 = owner_at(M, c.z, c.y, r0, c.w, k0, v0, i);          // (dx,dy,dz) = (0,0,0)
+      const Owner a10 = owner_at(M, c.z, c.y, r0, c.w, k0, v0, i + 1);      // (1,0,0)
+      const Owner b00 = owner_at(M, c.z, c.y + 1, r1, c.w, k1, v1, i);      // (0,1,0)
+      const Owner b10 = owner_at(M, c.z, c.y + 1, r1, c.w, k1, v1, i + 1);  // (1,1,0)
+      const Owner d00 = owner_at(M, c.z + 1, c.y, r2, c.w, k2, v2, i);      // (0,0,1)
+      const Owner d10 = owner_at(M, c.z + 1, c.y, r2, c.w, k2, v2, i + 1);  // (1,0,1)
+      const Owner e00 = owner_at(M, c.z + 1, c.y + 1, r3, c.w, k3, v3, i);  // (0,1,1)
+      // x edges 0..3 at (dy,dz) = (0,0), (1,0), (0,1), (1,1)
+      my[0] = (int32_t)a00.base;
+      my[1] = (int32_t)b00.base;
+      my[2] = (int32_t)d00.base;
+      my[3] = (int32_t)e00.base;
+      // y edges 4..7 at (dx,dz) = (0,0), (1,0), (0,1), (1,1)
+      my[4] = (int32_t)(a00.base + a00.bx);
+      my[5] = (int32_t)(a10.base + a10.bx);
+      my[6] = (int32_t)(d00.base + d00.bx);
+      my[7] = (int32_t)(d10.base + d10.bx);
+      // z edges 8..11 at (dx,dy) = (0,0), (1,0), (0,1), (1,1)
+      my[8] = (int32_t)(a00.base + a00.bx + a00.by);
+      my[9] = (int32_t)(a10.base + a10.bx + a10.by);
+      my[10] = (int32_t)(b00.base + b00.bx + b00.by);
+      my[11] = (int32_t)(b10.base + b10.bx + b10.by);
+      const uint32_t so = ent.y - tbase;
+      for (int t = 0; t < nt; t++)
+        for (int q = 0; q < 3; q++) st[3 * (so + t) + q] = my[tab.tri[cs][3 * t + q]];
     }
-    uint64_t tid = ent.y;
-    for (int t = 0; t < nt; t++, tid++) {
-      int32_t ids[3];
-      for (int q = 0; q < 3; q++) {
-        const int ed = tab.tri[cs][3 * t + q];
-        const int axis = ed >> 2, i2 = ed & 3;
-        int dx = 0, dy = 0, dz = 0;
-        if (axis == 0) { dy = i2 & 1; dz = i2 >> 1; }
-        if (axis == 1) { dx = i2 & 1; dz = i2 >> 1; }
-        if (axis == 2) { dx = i2 & 1; dy = i2 >> 1; }
-        const int R = dy + 2 * dz;
-        const int xo = i + dx;
-        uint64_t id;
-        u64 mx, my;
-        int bit;
-        if (xo < 64) {
-          id = vb0[R] + popc3_below(own0[R], xo);
-          mx = own0[R].cx; my = own0[R].cy; bit = xo;
-        } else {
-          // the edge's owner point starts the next word (its vertex base is
-          // that word's; it is inside the row because the cell is)
-          const Cross c1 = cross_of(M, rz[R], ry[R], c.w + 1);
-          id = M.P[rows[R] * M.nw + c.w + 1].x;
-          mx = c1.cx; my = c1.cy; bit = 0;
-        }
-        if (axis >= 1) id += (mx >> bit) & 1ull;
-        if (axis >= 2) id += (my >> bit) & 1ull;
-        ids[q] = (int32_t)id;
-      }
-      if ((int64_t)tid < M.cap_t) {
-        int32_t *o = M.tris + 3 * tid;
-        o[0] = ids[0]; o[1] = ids[1]; o[2] = ids[2];
-      }
+    __syncthreads();
+    const uint32_t nint = 3 * (tend - tbase);
+    const uint64_t capi = 3 * (uint64_t)M.cap_t;
+    for (uint32_t q = threadIdx.x; q < nint; q += kBS) {
+      const uint64_t g = 3 * (uint64_t)tbase + q;
+      if (g < capi) M.tris[g] = st[q];
     }
+    __syncthreads();
   }
 }
 
@@ -373,7 +423,15 @@ __global__ void k_range_fin(uint32_t *acc) {
 
 }  // namespace
 
-void launch_mc_count(const McPlan &p, U4 *scan_tmp, hipStream_t s) {
+static McPlan with_divisors(const McPlan &p) {
+  McPlan q = p;
+  q.d_nw = make_fastdiv((uint32_t)p.nw);
+  q.d_n1 = make_fastdiv((uint32_t)p.n[1]);
+  return q;
+}
+
+void launch_mc_count(const McPlan &p0, U4 *scan_tmp, hipStream_t s) {
+  const McPlan p = with_divisors(p0);
   const int64_t nwords = p.nrows * p.nw;
   prof_mark("k_mc_bits", s, 0);
   k_mc_bits<<<dim3((unsigned)ceil_div(p.nrows, kWaves)), dim3(kBS), 0, s>>>(p);
@@ -385,7 +443,8 @@ void launch_mc_count(const McPlan &p, U4 *scan_tmp, hipStream_t s) {
   k_mc_counts<<<dim3(1), dim3(64), 0, s>>>(p, 1);
 }
 
-void launch_mc_emit(const McPlan &p, hipStream_t s) {
+void launch_mc_emit(const McPlan &p0, hipStream_t s) {
+  const McPlan p = with_divisors(p0);
   const int64_t nwords = p.nrows * p.nw;
   prof_mark("k_mc_expand", s, 0);
   k_mc_expand<<<dim3((unsigned)ceil_div(nwords, kBS)), dim3(kBS), 0, s>>>(p);
@@ -400,7 +459,8 @@ void launch_mc_emit(const McPlan &p, hipStream_t s) {
   k_mc_counts<<<dim3(1), dim3(64), 0, s>>>(p, 0);
 }
 
-void launch_mc(const McPlan &p, U4 *scan_tmp, hipStream_t s) {
+void launch_mc(const McPlan &p0, U4 *scan_tmp, hipStream_t s) {
+  const McPlan p = with_divisors(p0);
   const int64_t nwords = p.nrows * p.nw;
   prof_mark("k_mc_bits", s, 0);
   k_mc_bits<<<dim3((unsigned)ceil_div(p.nrows, kWaves)), dim3(kBS), 0, s>>>(p);
@@ -412,7 +472,8 @@ void launch_mc(const McPlan &p, U4 *scan_tmp, hipStream_t s) {
   launch_mc_emit(p, s);
 }
 
-void launch_mc_cases(const McPlan &p, hipStream_t s) {
+void launch_mc_cases(const McPlan &p0, hipStream_t s) {
+  const McPlan p = with_divisors(p0);
   const int64_t nwords = p.nrows * p.nw;
   k_mc_bits<<<dim3((unsigned)ceil_div(p.nrows, kWaves)), dim3(kBS), 0, s>>>(p);
   if (p.n[0] > 1 && p.n[1] > 1 && p.n[2] > 1)
