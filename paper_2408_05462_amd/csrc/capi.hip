@@ -107,7 +107,7 @@ uint32_t max_chunks(const Geo &g, int l) {
 }
 
 struct EncLayout {
-  size_t off_G, off_cnt, off_P, off_scan, off_pay, off_emask, off_exv, off_part, off_bst, off_secsz, off_secoff,
+  size_t off_G, off_cnt, off_P, off_scan, off_pay, off_emask, off_exv, off_part, off_bst, off_csum, off_secsz, off_secoff,
       off_scan64, total, part_records;
 };
 
@@ -152,6 +152,7 @@ EncLayout enc_layout(EncPlan &P) {
   encode_pack_layout(P);
   Lo.off_part = o; o = align256(o + sizeof(Part) * Lo.part_records);
   Lo.off_bst = o; o = align256(o + sizeof(Part) * (size_t)g.nblocks);
+  Lo.off_csum = o; o = align256(o + sizeof(uint32_t) * kSumSegs * (size_t)(g.nblocks + 1));
   Lo.off_secsz = o; o = align256(o + sizeof(uint64_t) * (size_t)nsec);
   Lo.off_secoff = o; o = align256(o + sizeof(uint64_t) * (size_t)(nsec + 1));
   Lo.off_scan64 = o; o = align256(o + sizeof(uint64_t) * (size_t)scan_tmp_elems(nsec));
@@ -265,6 +266,7 @@ int enc_prepare(const float *d_field, const int64_t dims[3], double error_bound,
   P.exv = reinterpret_cast<float *>(ws + Lo.off_exv);
   P.part = reinterpret_cast<Part *>(ws + Lo.off_part);
   P.bst = reinterpret_cast<Part *>(ws + Lo.off_bst);
+  P.csum = reinterpret_cast<uint32_t *>(ws + Lo.off_csum);
   P.secsz = reinterpret_cast<uint64_t *>(ws + Lo.off_secsz);
   P.secoff = reinterpret_cast<uint64_t *>(ws + Lo.off_secoff);
   P.out = static_cast<uint8_t *>(d_stream);

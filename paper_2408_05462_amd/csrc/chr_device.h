@@ -72,7 +72,8 @@ __host__ __device__ inline void block_ext(const Geo &g, int64_t b, int64_t o[3],
 // mulhi(n, m) >> (l-1) for every n < 2^31 (Granlund-Montgomery).
 struct FastDiv {
   uint32_t d, m;
-  int sh;   // l - 1, or -1 when d == 1
+  uint32_t sh;    // l - 1 (0 when d == 1)
+  uint32_t one;   // d == 1: the quotient is n itself
 };
 
 __host__ __device__ inline FastDiv make_fastdiv(uint32_t d) {
@@ -82,21 +83,24 @@ __host__ __device__ inline FastDiv make_fastdiv(uint32_t d) {
   while (((uint64_t)1 << l) < (uint64_t)d) l++;
   if (l == 0) {
     f.m = 0;
-    f.sh = -1;
+    f.sh = 0;
+    f.one = 1;
   } else {
     f.m = (uint32_t)((((uint64_t)1) << (31 + l)) / d + 1);
-    f.sh = l - 1;
+    f.sh = (uint32_t)(l - 1);
+    f.one = 0;
   }
   return f;
 }
 
+// Branch-free: one multiply-high, one shift, one select.
 __host__ __device__ inline uint32_t fdiv(uint32_t n, const FastDiv &f) {
-  if (f.sh < 0) return n;
 #ifdef __HIP_DEVICE_COMPILE__
-  return __umulhi(n, f.m) >> f.sh;
+  const uint32_t q = __umulhi(n, f.m) >> f.sh;
 #else
-  return (uint32_t)(((uint64_t)n * f.m) >> 32) >> f.sh;
+  const uint32_t q = (uint32_t)(((uint64_t)n * f.m) >> 32) >> f.sh;
 #endif
+  return f.one ? n : q;
 }
 
 // Level-l section of one closed block: the points of the block's 2^l grid
@@ -158,6 +162,41 @@ __host__ __device__ inline void sec_point(const Sec &s, uint32_t j, uint32_t &w,
     v = fdiv(r, s.d_mx);
     u = r - v * s.mx;
   }
+}
+
+__device__ inline float avg2(float a, float b) { return __fmul_rn(__fadd_rn(a, b), 0.5f); }
+
+// Multilinear midpoint from the coarser compact grid, given the parent rows
+// (za,ya), (za,yb), (zb,ya), (zb,yb) and x positions xa, xb: along each odd
+// axis the two parents are averaged (xu, yu, zu false: the lower parent
+// alone), first along x, then y, then z.  Every parent is loaded before any
+// arithmetic, so the eight loads are in flight together instead of one
+// dependent round trip per axis.
+__device__ inline float midpoint8(float a0, float a1, float b0, float b1, float c0, float c1, float d0, float d1,
+                                  bool zu, bool yu, bool xu) {
+  const float A = xu ? avg2(a0, a1) : a0, B = xu ? avg2(b0, b1) : b0;
+  const float Cz = xu ? avg2(c0, c1) : c0, D = xu ? avg2(d0, d1) : d0;
+  const float p0 = yu ? avg2(A, B) : A;
+  const float p1 = yu ? avg2(Cz, D) : Cz;
+  return zu ? avg2(p0, p1) : p0;
+}
+
+__device__ inline float midpoint_rows(const float *__restrict__ r00, const float *__restrict__ r01,
+                                      const float *__restrict__ r10, const float *__restrict__ r11, uint32_t xa,
+                                      uint32_t xb, bool zu, bool yu, bool xu) {
+  return midpoint8(r00[xa], r00[xb], r01[xa], r01[xb], r10[xa], r10[xb], r11[xa], r11[xb], zu, yu, xu);
+}
+
+// Load of a float at a 32-bit byte offset from a uniform base (lets the
+// compiler use the scalar-base + 32-bit vector-offset addressing form).
+__device__ inline float ldf(const char *__restrict__ base, uint32_t off) {
+  return *reinterpret_cast<const float *>(base + off);
+}
+__device__ inline uint32_t ldu(const char *__restrict__ base, uint32_t off) {
+  return *reinterpret_cast<const uint32_t *>(base + off);
+}
+__device__ inline void stf(char *__restrict__ base, uint32_t off, float v) {
+  *reinterpret_cast<float *>(base + off) = v;
 }
 
 // Level-0 section geometry of the (at most 8) block shapes -- interior or

@@ -7,6 +7,7 @@
 namespace chr {
 
 constexpr int kMaxLevels = 16;
+constexpr int kSumSegs = 8;      // workgroups that checksum one block's stream bytes
 
 // Statistics of the points one workgroup encoded (ordered images of
 // binary32 values; counts cover the points the block owns).
@@ -40,6 +41,7 @@ struct EncPlan {
   int64_t part_per_block;        // records per block: level-0 workgroups, level-1 workgroups, coarse levels
   int64_t part_l1;               // first level-1 record of a block
   Part *bst;                     // per block reduction of its records
+  uint32_t *csum;                // per block, kSumSegs partial checksums of its byte range
   int64_t pack_base[kMaxLevels]; // first packing workgroup of each level
   int64_t pack_gpb[kMaxLevels];  // packing workgroups per block and level
   uint64_t *secsz, *secoff;      // nblocks*nL (+1)

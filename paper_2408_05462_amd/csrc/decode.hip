@@ -18,8 +18,6 @@ namespace {
 constexpr int kBS = 256;
 constexpr int kWaves = kBS / kWave;
 
-__device__ inline float avg2(float a, float b) { return __fmul_rn(__fadd_rn(a, b), 0.5f); }
-
 // Same prediction as compression (multilinear midpoints from the coarser
 // compact grid of dims g0 x g1 x g2, x then y then z, lower parent alone at
 // the domain edge).
@@ -33,20 +31,10 @@ __device__ inline float predict(const float *__restrict__ Gp, uint32_t g0, uint3
   const bool zu = oz && (zl + 1 < g0);
   const bool yu = oy && (yl + 1 < g1);
   const bool xu = ox && (xl + 1 < g2);
-  auto row = [&](uint32_t zi, uint32_t yi) {
-    const float *r = Gp + ((size_t)zi * g1 + yi) * g2;
-    float a = r[xl];
-    if (xu) a = avg2(a, r[xl + 1]);
-    return a;
-  };
-  float p = row(zl, yl);
-  if (yu) p = avg2(p, row(zl, yl + 1));
-  if (zu) {
-    float p1 = row(zl + 1, yl);
-    if (yu) p1 = avg2(p1, row(zl + 1, yl + 1));
-    p = avg2(p, p1);
-  }
-  return p;
+  const uint32_t zb = zu ? zl + 1 : zl, yb = yu ? yl + 1 : yl, xb = xu ? xl + 1 : xl;
+  const float *r00 = Gp + ((size_t)zl * g1 + yl) * g2, *r01 = Gp + ((size_t)zl * g1 + yb) * g2;
+  const float *r10 = Gp + ((size_t)zb * g1 + yl) * g2, *r11 = Gp + ((size_t)zb * g1 + yb) * g2;
+  return midpoint_rows(r00, r01, r10, r11, xl, xb, zu, yu, xu);
 }
 
 __device__ inline uint32_t ld32(const uint8_t *p) { return *reinterpret_cast<const uint32_t *>(p); }
@@ -164,7 +152,7 @@ __global__ __launch_bounds__(kBS) void k_decode_coarse(DecPlan D) {
   const int L = g.nL - 1;
   const int64_t b = blockIdx.x;
   const int wave = threadIdx.x / kWave;
-  const int lmin = D.lo > 2 ? D.lo : 2;
+  const int lmin = D.lo > 3 ? D.lo : 3;  // levels 2 and 1 have wide kernels of their own
   int64_t o[3], hi[3];
   block_ext(g, b, o, hi);
   for (int l = L; l >= lmin; l--) {
@@ -172,12 +160,17 @@ __global__ __launch_bounds__(kBS) void k_decode_coarse(DecPlan D) {
     const int64_t *gd = D.gd[l];
     if (l < L) {
       const int sh = l + 1;
-      const int64_t c0 = ((hi[0] - o[0]) >> sh) + 1, c1 = ((hi[1] - o[1]) >> sh) + 1, c2 = ((hi[2] - o[2]) >> sh) + 1;
+      const uint32_t c0 = (uint32_t)((hi[0] - o[0]) >> sh) + 1, c1 = (uint32_t)((hi[1] - o[1]) >> sh) + 1;
+      const uint32_t c2 = (uint32_t)((hi[2] - o[2]) >> sh) + 1;
       const float *src = D.gp[l + 1];
-      for (int64_t i = threadIdx.x; i < c0 * c1 * c2; i += kBS) {
-        const int64_t u = i % c2, v = (i / c2) % c1, w = i / (c2 * c1);
-        const int64_t zc = (o[0] >> sh) + w, yc = (o[1] >> sh) + v, xc = (o[2] >> sh) + u;
-        dst[((2 * zc) * gd[1] + 2 * yc) * gd[2] + 2 * xc] = src[(zc * D.gd[l + 1][1] + yc) * D.gd[l + 1][2] + xc];
+      const uint32_t zo = (uint32_t)(o[0] >> sh), yo = (uint32_t)(o[1] >> sh), xo = (uint32_t)(o[2] >> sh);
+      const uint32_t s1 = (uint32_t)D.gd[l + 1][1], s2 = (uint32_t)D.gd[l + 1][2];
+      const uint32_t d1 = (uint32_t)gd[1], d2 = (uint32_t)gd[2];
+      for (uint32_t r = wave; r < c0 * c1; r += kWaves) {
+        const uint32_t w = r / c1, v = r - (r / c1) * c1;
+        const size_t srow = ((size_t)(zo + w) * s1 + (yo + v)) * s2 + xo;
+        const size_t drow = ((size_t)(2 * (zo + w)) * d1 + 2 * (yo + v)) * d2 + 2 * xo;
+        for (uint32_t u = lane_id(); u < c2; u += kWave) dst[drow + 2 * u] = src[srow + u];
       }
     }
     const Sec s = sec_geom(o, hi, l, L);
@@ -234,7 +227,10 @@ __global__ __launch_bounds__(kBS) void k_decode_fine(DecPlan D) {
 // Level 1 (nL >= 2) over (tiles, blocks): one workgroup per tile, each wave
 // 16 of its chunks; the block's level-2 points are copied into the level-1
 // grid (the output when level 1 is requested) by the same workgroups.
-__global__ __launch_bounds__(kBS) void k_decode_l1(DecPlan D) {
+// One level l in {1, 2} of every block: workgroup (t, b) decodes tile t of
+// block b's level-l section (16 chunks per wave) after carrying the block's
+// level-(l+1) points over into the level-l compact grid.
+__global__ __launch_bounds__(kBS) void k_decode_level(DecPlan D, int l) {
   const Geo &g = D.g;
   const int L = g.nL - 1;
   uint32_t t, b;
@@ -242,28 +238,35 @@ __global__ __launch_bounds__(kBS) void k_decode_l1(DecPlan D) {
   const int wave = threadIdx.x / kWave;
   int64_t o[3], hi[3];
   block_ext(g, b, o, hi);
-  float *dst = D.gp[1];
-  const int64_t *gd = D.gd[1];
-  if (L >= 2) {
-    const int sh = 2;
-    const int64_t c0 = ((hi[0] - o[0]) >> sh) + 1, c1 = ((hi[1] - o[1]) >> sh) + 1, c2 = ((hi[2] - o[2]) >> sh) + 1;
-    const float *src = D.gp[2];
-    for (int64_t i = (int64_t)t * kBS + threadIdx.x; i < c0 * c1 * c2; i += (int64_t)gridDim.x * kBS) {
-      const int64_t u = i % c2, v = (i / c2) % c1, w = i / (c2 * c1);
-      const int64_t zc = (o[0] >> sh) + w, yc = (o[1] >> sh) + v, xc = (o[2] >> sh) + u;
-      dst[((2 * zc) * gd[1] + 2 * yc) * gd[2] + 2 * xc] = src[(zc * D.gd[2][1] + yc) * D.gd[2][2] + xc];
+  float *dst = D.gp[l];
+  const int64_t *gd = D.gd[l];
+  if (l < L) {
+    const int sh = l + 1;
+    const uint32_t c0 = (uint32_t)((hi[0] - o[0]) >> sh) + 1, c1 = (uint32_t)((hi[1] - o[1]) >> sh) + 1;
+    const uint32_t c2 = (uint32_t)((hi[2] - o[2]) >> sh) + 1;
+    const float *src = D.gp[l + 1];
+    const uint32_t zo = (uint32_t)(o[0] >> sh), yo = (uint32_t)(o[1] >> sh), xo = (uint32_t)(o[2] >> sh);
+    const uint32_t s1 = (uint32_t)D.gd[l + 1][1], s2 = (uint32_t)D.gd[l + 1][2];
+    const uint32_t d1 = (uint32_t)gd[1], d2 = (uint32_t)gd[2];
+    // one row of the coarser block grid per wave step
+    for (uint32_t r = t * kWaves + wave; r < c0 * c1; r += gridDim.x * kWaves) {
+      const uint32_t w = r / c1, v = r - (r / c1) * c1;
+      const size_t srow = ((size_t)(zo + w) * s1 + (yo + v)) * s2 + xo;
+      const size_t drow = ((size_t)(2 * (zo + w)) * d1 + 2 * (yo + v)) * d2 + 2 * xo;
+      for (uint32_t u = lane_id(); u < c2; u += kWave) dst[drow + 2 * u] = src[srow + u];
     }
   }
-  const Sec s = sec_geom(o, hi, 1, L);
+  const Sec s = sec_geom(o, hi, l, L);
   const uint32_t nch = (s.npts + 63) / 64;
   if (t >= (nch + 63) / 64) return;
-  const SecView v = open_section(D, b, 1, s.npts);
+  const SecView v = open_section(D, b, l, s.npts);
   if (!v.ok) {
     if (threadIdx.x == 0) set_status(D, -4);
     return;
   }
-  dec_tile(D, v, 1, o, s, t, wave * 16u, wave * 16u + 16u, [&](uint32_t z, uint32_t y, uint32_t x, float r) {
-    dst[((size_t)(z >> 1) * (uint32_t)gd[1] + (y >> 1)) * (uint32_t)gd[2] + (x >> 1)] = r;
+  const int lv = l;
+  dec_tile(D, v, l, o, s, t, wave * 16u, wave * 16u + 16u, [&](uint32_t z, uint32_t y, uint32_t x, float r) {
+    dst[((size_t)(z >> lv) * (uint32_t)gd[1] + (y >> lv)) * (uint32_t)gd[2] + (x >> lv)] = r;
   });
 }
 
@@ -297,6 +300,10 @@ __global__ __launch_bounds__(kBS) void k_decode_l0(DecPlan D) {
   const uint32_t g0 = (uint32_t)D.gd[1][0], g1 = (uint32_t)D.gd[1][1], g2 = (uint32_t)D.gd[1][2];
   const uint32_t zg = bp.o[0] >> 1;
   const float *__restrict__ G1 = D.gp[1] + (size_t)zg * g1 * g2;
+  // uniform bases; the launcher guarantees the block's slab spans < 4 GiB
+  const char *__restrict__ G1b = reinterpret_cast<const char *>(G1);
+  char *__restrict__ obase = reinterpret_cast<char *>(ob);
+  const uint32_t g2x4 = g2 * 4u, g12x4 = g1 * g2 * 4u;
   const float step = g.step;
   const int lossless = g.lossless;
 
@@ -319,56 +326,60 @@ __global__ __launch_bounds__(kBS) void k_decode_l0(DecPlan D) {
     return;
   }
   const uint32_t nc = min(min(64u, v.nch - t * 64), kbeg + cpw);
-  const uint8_t *pay = v.p + v.Poff;
-  const uint32_t *exv = reinterpret_cast<const uint32_t *>(v.p + v.Xoff);
+  const char *__restrict__ payb = reinterpret_cast<const char *>(v.p + v.Poff);
+  const char *__restrict__ exvb = reinterpret_cast<const char *>(v.p + v.Xoff);
 #pragma unroll 1
   for (uint32_t k = kbeg; k < nc; k++) {
     const uint32_t wk = rl32(w, (int)k), wok = rl32(wo, (int)k), xok = rl32(xo, (int)k);
     const uint64_t emk = rl64(em, (int)k);
     const uint32_t j = (t * 64 + k) * 64 + (uint32_t)lane;
     if (j >= s.npts) continue;
-    uint32_t zc = 0;
-    if (wk) {
-      const uint32_t bit = (uint32_t)lane * wk, off = bit & 31u;
-      const uint32_t *wp = reinterpret_cast<const uint32_t *>(pay + 8 * (uint64_t)wok) + (bit >> 5);
-      zc = wp[0] >> off;
-      if (off + wk > 32u) zc |= wp[1] << (32u - off);
-      zc &= (1u << wk) - 1u;
-    }
     uint32_t zz_, vv, uu;
     sec_point(s, j, zz_, vv, uu);
     const uint32_t y = oy + vv, x = ox + uu;
     const uint32_t zl = zz_ >> 1, yl = y >> 1, xl = x >> 1;
+    const uint32_t pz = zz_ & 1u, py = y & 1u, px = x & 1u;
+    const bool zu = pz && (zg + zl + 1 < g0), yu = py && (yl + 1 < g1), xu = px && (xl + 1 < g2);
+    // every load of this point is issued before any is used: payload words,
+    // the exact value, the eight parents
+    uint32_t pw0 = 0, pw1 = 0;
+    const uint32_t bit = (uint32_t)lane * wk, off = bit & 31u;
+    if (wk) {
+      const uint32_t wb = 8u * wok + 4u * (bit >> 5);
+      pw0 = ldu(payb, wb);
+      pw1 = ldu(payb, wb + ((off + wk > 32u) ? 4u : 0u));
+    }
+    const bool ex = (emk >> lane) & 1ull;
+    uint32_t xv = 0;
+    if (ex) xv = ldu(exvb, 4u * (xok + lanes_below(emk)));
+    const uint32_t o00 = ((zl * g1 + yl) * g2 + xl) * 4u;
+    const uint32_t dxo = xu ? 4u : 0u, dyo = yu ? g2x4 : 0u, dzo = zu ? g12x4 : 0u;
+    const uint32_t o01 = o00 + dyo, o10 = o00 + dzo, o11 = o10 + dyo;
+    const float a0 = ldf(G1b, o00), a1 = ldf(G1b, o00 + dxo);
+    const float b0 = ldf(G1b, o01), b1 = ldf(G1b, o01 + dxo), c0 = ldf(G1b, o10), c1 = ldf(G1b, o10 + dxo);
+    const float d0 = ldf(G1b, o11), d1 = ldf(G1b, o11 + dxo);
     float r;
-    if ((emk >> lane) & 1ull) {
-      r = __uint_as_float(exv[xok + lanes_below(emk)]);
+    if (ex) {
+      r = __uint_as_float(xv);
     } else {
-      const uint32_t pz = zz_ & 1u, py = y & 1u, px = x & 1u;
-      const bool zu = pz && (zg + zl + 1 < g0), yu = py && (yl + 1 < g1), xu = px && (xl + 1 < g2);
-      auto row = [&](uint32_t zi, uint32_t yi) {
-        const float *rr = G1 + (zi * g1 + yi) * g2;
-        float a = rr[xl];
-        if (xu) a = avg2(a, rr[xl + 1]);
-        return a;
-      };
-      float p = row(zl, yl);
-      if (yu) p = avg2(p, row(zl, yl + 1));
-      if (zu) {
-        float p1 = row(zl + 1, yl);
-        if (yu) p1 = avg2(p1, row(zl + 1, yl + 1));
-        p = avg2(p, p1);
+      const float p = midpoint8(a0, a1, b0, b1, c0, c1, d0, d1, zu, yu, xu);
+      uint32_t zc = 0;
+      if (wk) {
+        zc = pw0 >> off;
+        if (off + wk > 32u) zc |= pw1 << (32u - off);
+        zc &= (1u << wk) - 1u;
       }
       const int32_t q = (int32_t)(zc >> 1) ^ -(int32_t)(zc & 1u);
       r = lossless ? p : __fadd_rn(p, __fmul_rn((float)q, step));
     }
     if (zz_ < ownz && y < owny) {
-      float *orow = ob + (zz_ * n1 + y) * n2;
-      if (x < ownx) orow[x] = r;
+      const uint32_t orow = (zz_ * n1 + y) * n2 * 4u;
+      if (x < ownx) stf(obase, orow + 4u * x, r);
       if (!((zz_ | y) & 1u) && (x & 1u)) {
-        // even row of an even plane: the neighbouring even points come from level 1
-        const float *grow = G1 + (zl * g1 + yl) * g2;
-        orow[x - 1] = grow[xl];
-        if (x + 1 == bp.hi[2] && lastx) orow[x + 1] = grow[xl + 1];
+        // even row of an even plane: the neighbouring even points come from
+        // level 1 (they are this point's two x parents)
+        stf(obase, orow + 4u * (x - 1), a0);
+        if (x + 1 == bp.hi[2] && lastx) stf(obase, orow + 4u * (x + 1), a1);
       }
     }
   }
@@ -396,22 +407,24 @@ void launch_decode(const DecPlan &p, hipStream_t s) {
   const int L = g.nL - 1;
   int64_t o[3], hi[3];
   block_ext(g, 0, o, hi);  // the first block is the largest
-  if (L >= 2 && p.lo <= L) {
+  if (L >= 3 && p.lo <= L) {
     prof_mark("k_decode_coarse", s, 0);
     k_decode_coarse<<<dim3((unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
     prof_mark("k_decode_coarse", s, 1);
   }
-  if (L >= 1 && p.lo <= 1) {
-    const Sec s1 = sec_geom(o, hi, 1, L);
-    const int64_t nt1 = ceil_div(ceil_div(s1.npts, 64), 64);
-    prof_mark("k_decode_l1", s, 0);
-    k_decode_l1<<<dim3((unsigned)(nt1 > 0 ? nt1 : 1), (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
-    prof_mark("k_decode_l1", s, 1);
+  for (int l = 2; l >= 1; l--) {
+    if (L >= l && p.lo <= l) {
+      const Sec sl = sec_geom(o, hi, l, L);
+      const int64_t ntl = ceil_div(ceil_div(sl.npts, 64), 64);
+      prof_mark(l == 1 ? "k_decode_l1" : "k_decode_l2", s, 0);
+      k_decode_level<<<dim3((unsigned)(ntl > 0 ? ntl : 1), (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p, l);
+      prof_mark(l == 1 ? "k_decode_l1" : "k_decode_l2", s, 1);
+    }
   }
   if (p.lo == 0) {
     const Sec s0 = sec_geom(o, hi, 0, L);
     const int64_t ntile = ceil_div(ceil_div(s0.npts, 64), 64);
-    const bool slab32 = (double)(hi[0] - o[0] + 1) * (double)g.n[1] * (double)g.n[2] < 4294967296.0;
+    const bool slab32 = 4.0 * (double)(hi[0] - o[0] + 1) * (double)g.n[1] * (double)g.n[2] < 4294967296.0;
     prof_mark("k_decode_fine", s, 0);
     if (L >= 1 && slab32) {
       const int64_t nch0 = ceil_div(s0.npts, 64);

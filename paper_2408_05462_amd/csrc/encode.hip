@@ -25,8 +25,6 @@ constexpr int kWaves = kBS / kWave;
 constexpr int kChunksPerWave = 4;
 constexpr int kChunksPerWG = kWaves * kChunksPerWave;
 
-__device__ inline float avg2(float a, float b) { return __fmul_rn(__fadd_rn(a, b), 0.5f); }
-
 // Multilinear midpoint prediction of point (z,y,x) of level l from the
 // compact grid Gp of level l+1 (dims g0 x g1 x g2): along each axis where the
 // coordinate is an odd multiple of 2^l the two parents at -2^l and +2^l are
@@ -42,20 +40,28 @@ __device__ inline float predict(const float *__restrict__ Gp, uint32_t g0, uint3
   const bool zu = oz && (zl + 1 < g0);
   const bool yu = oy && (yl + 1 < g1);
   const bool xu = ox && (xl + 1 < g2);
-  auto row = [&](uint32_t zi, uint32_t yi) {
-    const float *r = Gp + ((size_t)zi * g1 + yi) * g2;
-    float a = r[xl];
-    if (xu) a = avg2(a, r[xl + 1]);
-    return a;
-  };
-  float p = row(zl, yl);
-  if (yu) p = avg2(p, row(zl, yl + 1));
-  if (zu) {
-    float p1 = row(zl + 1, yl);
-    if (yu) p1 = avg2(p1, row(zl + 1, yl + 1));
-    p = avg2(p, p1);
+  const uint32_t zb = zu ? zl + 1 : zl, yb = yu ? yl + 1 : yl, xb = xu ? xl + 1 : xl;
+  const float *r00 = Gp + ((size_t)zl * g1 + yl) * g2, *r01 = Gp + ((size_t)zl * g1 + yb) * g2;
+  const float *r10 = Gp + ((size_t)zb * g1 + yl) * g2, *r11 = Gp + ((size_t)zb * g1 + yb) * g2;
+  return midpoint_rows(r00, r01, r10, r11, xl, xb, zu, yu, xu);
+}
+
+// Carries the block's points of the coarser compact grid (dims sd, shift sh
+// from full resolution) over to the even positions of the finer one (dims
+// dd): one row per wave step, starting at wave `first`, stepping by `step`.
+__device__ inline void copy_coarse(const float *__restrict__ src, const int64_t *sd, float *__restrict__ dst,
+                                   const int64_t *dd, const int64_t o[3], const int64_t hi[3], int sh,
+                                   uint32_t first, uint32_t step) {
+  const uint32_t c0 = (uint32_t)((hi[0] - o[0]) >> sh) + 1, c1 = (uint32_t)((hi[1] - o[1]) >> sh) + 1;
+  const uint32_t c2 = (uint32_t)((hi[2] - o[2]) >> sh) + 1;
+  const uint32_t zo = (uint32_t)(o[0] >> sh), yo = (uint32_t)(o[1] >> sh), xo = (uint32_t)(o[2] >> sh);
+  const uint32_t s1 = (uint32_t)sd[1], s2 = (uint32_t)sd[2], d1 = (uint32_t)dd[1], d2 = (uint32_t)dd[2];
+  for (uint32_t r = first; r < c0 * c1; r += step) {
+    const uint32_t w = r / c1, v = r - w * c1;
+    const size_t srow = ((size_t)(zo + w) * s1 + (yo + v)) * s2 + xo;
+    const size_t drow = ((size_t)(2 * (zo + w)) * d1 + 2 * (yo + v)) * d2 + 2 * xo;
+    for (uint32_t u = lane_id(); u < c2; u += kWave) dst[drow + 2 * u] = src[srow + u];
   }
-  return p;
 }
 
 // Error-bounded linear quantization: q = rint((x-p)/(2e)) (half even), the
@@ -215,15 +221,7 @@ __global__ __launch_bounds__(kBS) void k_encode_coarse(EncPlan P) {
     if (l < L) {
       // the block's points of the coarser grid carry over unchanged
       const int sh = l + 1;
-      const int64_t c0 = ((hi[0] - o[0]) >> sh) + 1, c1 = ((hi[1] - o[1]) >> sh) + 1, c2 = ((hi[2] - o[2]) >> sh) + 1;
-      const float *src = P.G + P.g_off[l + 1];
-      float *dst = P.G + P.g_off[l];
-      for (int64_t i = threadIdx.x; i < c0 * c1 * c2; i += kBS) {
-        const int64_t u = i % c2, v = (i / c2) % c1, w = i / (c2 * c1);
-        const int64_t zc = (o[0] >> sh) + w, yc = (o[1] >> sh) + v, xc = (o[2] >> sh) + u;
-        dst[((2 * zc) * P.gd[l][1] + 2 * yc) * P.gd[l][2] + 2 * xc] =
-            src[(zc * P.gd[l + 1][1] + yc) * P.gd[l + 1][2] + xc];
-      }
+      copy_coarse(P.G + P.g_off[l + 1], P.gd[l + 1], P.G + P.g_off[l], P.gd[l], o, hi, sh, wave, kWaves);
     }
     const Sec s = sec_geom(o, hi, l, L);
     const uint32_t nch = (s.npts + 63) / 64;
@@ -251,15 +249,8 @@ __global__ __launch_bounds__(kBS) void k_encode_l1(EncPlan P) {
   block_ext(g, b, o, hi);
   owned_end(g, o, own);
   if (L >= 2) {
-    const int sh = 2;
-    const int64_t c0 = ((hi[0] - o[0]) >> sh) + 1, c1 = ((hi[1] - o[1]) >> sh) + 1, c2 = ((hi[2] - o[2]) >> sh) + 1;
-    const float *src = P.G + P.g_off[2];
-    float *dst = P.G + P.g_off[1];
-    for (int64_t i = (int64_t)bx * kBS + threadIdx.x; i < c0 * c1 * c2; i += (int64_t)gridDim.x * kBS) {
-      const int64_t u = i % c2, v = (i / c2) % c1, w = i / (c2 * c1);
-      const int64_t zc = (o[0] >> sh) + w, yc = (o[1] >> sh) + v, xc = (o[2] >> sh) + u;
-      dst[((2 * zc) * P.gd[1][1] + 2 * yc) * P.gd[1][2] + 2 * xc] = src[(zc * P.gd[2][1] + yc) * P.gd[2][2] + xc];
-    }
+    copy_coarse(P.G + P.g_off[2], P.gd[2], P.G + P.g_off[1], P.gd[1], o, hi, 2, bx * kWaves + wave,
+                gridDim.x * kWaves);
   }
   const Sec s = sec_geom(o, hi, 1, L);
   const uint32_t nch = (s.npts + 63) / 64;
@@ -349,6 +340,10 @@ __global__ __launch_bounds__(kBS) void k_encode_l0(EncPlan P) {
   const uint32_t g0 = (uint32_t)P.gd[1][0], g1 = (uint32_t)P.gd[1][1], g2 = (uint32_t)P.gd[1][2];
   const uint32_t zg = bp.o[0] >> 1;
   const float *__restrict__ G1 = P.G + P.g_off[1] + (size_t)zg * g1 * g2;
+  // uniform bases; the launcher guarantees the block's slab spans < 4 GiB
+  const char *__restrict__ xbase = reinterpret_cast<const char *>(xb);
+  const char *__restrict__ G1b = reinterpret_cast<const char *>(G1);
+  const uint32_t g2x4 = g2 * 4u, g12x4 = g1 * g2 * 4u;
   const uint32_t ownz = bp.own[0] - bp.o[0], owny = bp.own[1], ownx = bp.own[2];
   const int64_t slot0 = P.slot_base[0] + (int64_t)b * maxch;
   U4 *__restrict__ cnt = P.cnt;
@@ -382,23 +377,16 @@ __global__ __launch_bounds__(kBS) void k_encode_l0(EncPlan P) {
       uint32_t w, v, u;
       sec_point(s, j, w, v, u);
       const uint32_t y = oy + v, xx = ox + u;
-      x = xb[(w * n1 + y) * n2 + xx];
+      x = ldf(xbase, ((w * n1 + y) * n2 + xx) * 4u);
       const uint32_t pz = w & 1u, py = y & 1u, px = xx & 1u;
       const uint32_t zl = w >> 1, yl = y >> 1, xl = xx >> 1;
       const bool zu = pz && (zg + zl + 1 < g0), yu = py && (yl + 1 < g1), xu = px && (xl + 1 < g2);
-      auto row = [&](uint32_t zi, uint32_t yi) {
-        const float *r = G1 + (zi * g1 + yi) * g2;
-        float a = r[xl];
-        if (xu) a = avg2(a, r[xl + 1]);
-        return a;
-      };
-      float p = row(zl, yl);
-      if (yu) p = avg2(p, row(zl, yl + 1));
-      if (zu) {
-        float p1 = row(zl + 1, yl);
-        if (yu) p1 = avg2(p1, row(zl + 1, yl + 1));
-        p = avg2(p, p1);
-      }
+      // byte offsets of the eight parents in the block's slab of the level-1 grid
+      const uint32_t o00 = ((zl * g1 + yl) * g2 + xl) * 4u;
+      const uint32_t dxo = xu ? 4u : 0u, dyo = yu ? g2x4 : 0u, dzo = zu ? g12x4 : 0u;
+      const uint32_t o01 = o00 + dyo, o10 = o00 + dzo, o11 = o10 + dyo;
+      const float p = midpoint8(ldf(G1b, o00), ldf(G1b, o00 + dxo), ldf(G1b, o01), ldf(G1b, o01 + dxo),
+                                ldf(G1b, o10), ldf(G1b, o10 + dxo), ldf(G1b, o11), ldf(G1b, o11 + dxo), zu, yu, xu);
       int32_t q;
       int O, C = 0;
       float xr;
@@ -617,18 +605,48 @@ __device__ uint32_t block_sum(uint32_t v) {
 
 // Block table: folds the block's workgroup records (min/max of the
 // reconstructed values, input range, counts) and checksums its byte range.
+// Partial checksums of the blocks' byte ranges: workgroup (b, seg) sums the
+// words of its share of block b's sections, 8 bytes per thread and load.
+// This workgroup's share (segment seg of kSumSegs) of the checksum of the
+// 8-byte aligned byte range [start, end) of the stream, end - start a multiple
+// of 8; word indices count from start.
+__device__ uint32_t range_sum(const EncPlan &P, uint64_t start, uint64_t end, uint32_t seg) {
+  uint32_t sum = 0;
+  const uint32_t npair = (uint32_t)((end - start) / 8);
+  const uint32_t per = (npair + kSumSegs - 1) / kSumSegs;
+  const uint32_t lo = min(npair, seg * per), hi = min(npair, lo + per);
+  const uint2 *__restrict__ src = reinterpret_cast<const uint2 *>(P.out + start);
+  for (uint32_t i = lo + threadIdx.x; i < hi; i += kBS) {
+    const uint2 v = src[i];
+    sum += fmix32(v.x ^ (2u * i) * 0x9E3779B9u) + fmix32(v.y ^ (2u * i + 1u) * 0x9E3779B9u);
+  }
+  return block_sum<kBS>(sum);
+}
+
+__global__ __launch_bounds__(kBS) void k_block_sum(EncPlan P) {
+  const Geo &g = P.g;
+  const uint32_t b = blockIdx.x / kSumSegs, seg = blockIdx.x % kSumSegs;
+  const uint64_t total = P.payload_off + P.secoff[g.nblocks * g.nL];
+  const uint64_t start = P.payload_off + P.secoff[(int64_t)b * g.nL];
+  const uint64_t end = P.payload_off + P.secoff[(int64_t)(b + 1) * g.nL];
+  const uint32_t sum = total <= P.cap ? range_sum(P, start, end, seg) : 0u;
+  if (threadIdx.x == 0) P.csum[blockIdx.x] = sum;
+}
+
+// Partial checksums of the section and block tables (after the block table
+// is written), into the kSumSegs slots after the blocks' partials.
+__global__ __launch_bounds__(kBS) void k_table_sum(EncPlan P) {
+  const Geo &g = P.g;
+  const uint64_t total = P.payload_off + P.secoff[g.nblocks * g.nL];
+  const uint32_t sum = total <= P.cap ? range_sum(P, kHeaderBytes, P.payload_off, blockIdx.x) : 0u;
+  if (threadIdx.x == 0) P.csum[g.nblocks * kSumSegs + blockIdx.x] = sum;
+}
+
 __global__ __launch_bounds__(kBS) void k_block_table(EncPlan P) {
   const Geo &g = P.g;
   const int64_t b = blockIdx.x;
-  const uint64_t total = P.payload_off + P.secoff[g.nblocks * g.nL];
-  const bool fits = total <= P.cap;
-  const uint64_t start = P.payload_off + P.secoff[b * g.nL];
-  const uint64_t end = P.payload_off + P.secoff[(b + 1) * g.nL];
   uint32_t sum = 0;
-  if (fits)
-    for (uint64_t j = threadIdx.x; j < (end - start) / 4; j += kBS)
-      sum += fmix32(get32(P, start + 4 * j) ^ (uint32_t)((uint32_t)j * 0x9E3779B9u));
-  sum = block_sum<kBS>(sum);
+  for (int sgm = 0; sgm < kSumSegs; sgm++) sum += P.csum[b * kSumSegs + sgm];
   Part acc;
   part_init(acc);
   const Part *rec = P.part + b * P.part_per_block;
@@ -684,10 +702,7 @@ __global__ __launch_bounds__(kBS) void k_header(EncPlan P) {
   }
   __syncthreads();
   uint32_t sum = 0;
-  if (fits)
-    for (uint64_t j = threadIdx.x; j < (P.payload_off - kHeaderBytes) / 4; j += kBS)
-      sum += fmix32(get32(P, kHeaderBytes + 4 * j) ^ (uint32_t)((uint32_t)j * 0x9E3779B9u));
-  sum = block_sum<kBS>(sum);
+  for (int sgm = 0; sgm < kSumSegs; sgm++) sum += P.csum[g.nblocks * kSumSegs + sgm];
   if (threadIdx.x != 0) return;
   for (int i = 1; i < kWaves; i++) {
     red[0][0] = min(red[0][0], red[i][0]); red[0][1] = max(red[0][1], red[i][1]); red[0][2] |= red[i][2];
@@ -770,7 +785,7 @@ void launch_encode_levels(const EncPlan &p, hipStream_t s) {
     // the level-0 kernel addresses a block's slab of planes with 32-bit offsets
     int64_t o[3], hi[3];
     block_ext(g, 0, o, hi);
-    const bool slab32 = (double)(hi[0] - o[0] + 1) * (double)g.n[1] * (double)g.n[2] < 4294967296.0;
+    const bool slab32 = 4.0 * (double)(hi[0] - o[0] + 1) * (double)g.n[1] * (double)g.n[2] < 4294967296.0;
     prof_mark("k_encode_fine", s, 0);
     if (L >= 1 && slab32 && !p.codes && !p.flags)
       k_encode_l0<false, KB><<<dim3((unsigned)gx, (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
@@ -805,7 +820,9 @@ void launch_encode(const EncPlan &p, int64_t, U4 *scan_tmp, uint64_t *scan_tmp64
     prof_mark("k_pack", s, 1);
   }
   prof_mark("k_block_table", s, 0);
+  k_block_sum<<<dim3((unsigned)(g.nblocks * kSumSegs)), dim3(kBS), 0, s>>>(p);
   k_block_table<<<dim3((unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
+  k_table_sum<<<dim3((unsigned)kSumSegs), dim3(kBS), 0, s>>>(p);
   prof_mark("k_block_table", s, 1);
   prof_mark("k_header", s, 0);
   k_header<<<dim3(1), dim3(kBS), 0, s>>>(p);
