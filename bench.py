@@ -541,6 +541,25 @@ def main():
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "avg_launch_ms": round(kern_ms, 4), "algorithmic_bytes": alg}
 
+    # the paper's error translation (Sec. II.B) on the same field: min(D), and
+    # the n-th smallest entry for 99% topology accuracy (n = ceil(0.01 |D|))
+    tws = torch.empty(lib.chr_topology_workspace(), dtype=torch.uint8, device=dev)
+    tout = torch.zeros(2, dtype=torch.float64, device=dev)
+    topo = {}
+    for label, nth_of in (("min", lambda m: 1), ("p99", lambda m: max(1, -(-m // 100)))):
+        api.chr_topology_error_bound(x, isos, 1, tout, tws)
+        torch.cuda.synchronize()
+        m = int(tout[1].item())
+        nth = nth_of(m)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(3):
+            api.chr_topology_error_bound(x, isos, nth, tout, tws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        topo[label] = {"nth": nth, "bound": float(tout[0].item()), "ms": round(e0.elapsed_time(e1) / 3, 4)}
+    topo["n_D"] = m
+
     # CPU oracle baseline on a bounded sample of the same workload
     cpu = None
     if not args.no_cpu_baseline:
@@ -574,7 +593,7 @@ def main():
                        "mc_per_isovalue": round(4.0 * N * len(isos) / stage_ms[2] / 1e6, 1)},
         "compression_ratio": round(cr, 3), "stream_bytes": nbytes, "n_outlier": r["n_outlier"],
         "n_corrected": r["n_corrected"], "triangles": [int(c[1]) for c in cnt],
-        "wall_s_timed": round(wall, 3), "roofline": roofline, "cpu_baseline": cpu,
+        "wall_s_timed": round(wall, 3), "topology_error_bound": topo, "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 

@@ -185,6 +185,27 @@ int iso_cases(const float *d_field, const int64_t dims[3], float isovalue,
  * ntri[256]; tri[256][15] cell-edge ids (unused entries -1). */
 int chr_mc_table(uint8_t *ntri, int8_t *tri);
 
+/* ---- error translation (Sec. II.B, the paper's three steps) -------------- */
+
+/* Device scratch bytes chr_topology_error_bound needs (a few KB). */
+size_t chr_topology_workspace(void);
+
+/* The paper's translation of topology preservation into an error bound:
+ * (1) find every grid edge (two points adjacent along x, y or z) whose end
+ *     values s0 <= s1 enclose an isovalue k strictly, s0 < k < s1;
+ * (2) collect d0 = k - s0 and d1 = s1 - k (in double) of each such edge and
+ *     isovalue into the multiset D (isovalues as given, duplicates counted);
+ * (3) return the nth smallest entry of D: nth <= 1 gives min(D), which keeps
+ *     every crossing edge crossing; a larger nth tolerates the crossings of
+ *     the smaller entries changing (a topology accuracy below 100%).
+ * nth above |D| selects the largest entry.  d_out: device double[2] =
+ * {bound, |D|}; the bound is +inf when D is empty.  Non-finite field values
+ * never enclose an isovalue.  Asynchronous; d_ws holds the selection state
+ * (chr_topology_workspace bytes). */
+int chr_topology_error_bound(const float *d_field, const int64_t dims[3], const float *h_isovalues,
+                             int n_iso, int64_t nth, double *d_out, void *d_ws, size_t ws_bytes,
+                             void *stream);
+
 /* ---- range (validation helper for relative error bounds) ---------------- */
 
 /* Range of n values (Sec. II.B error translation works in absolute units; a

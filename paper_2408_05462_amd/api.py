@@ -430,3 +430,23 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------------ error translation
+
+def chr_topology_error_bound(field, isovalues, nth, out, ws, stream=None):
+    _need_cuda_f32(field, "field")
+    iso = np.ascontiguousarray(np.asarray(isovalues, np.float32).reshape(-1))
+    rc = L.load().chr_topology_error_bound(_p(field), L.dims3(field.shape), iso.ctypes.data_as(C.c_void_p), len(iso),
+                                           int(nth), _p(out), _p(ws), ws.numel(), _s(stream))
+    L.check(rc, "chr_topology_error_bound")
+
+
+def topology_error_bound(field, isovalues, nth=1):
+    """Synchronous: (bound, |D|) of the paper's error translation."""
+    out = torch.zeros(2, dtype=torch.float64, device=field.device)
+    ws = torch.empty(L.load().chr_topology_workspace(), dtype=torch.uint8, device=field.device)
+    chr_topology_error_bound(field, isovalues, nth, out, ws)
+    torch.cuda.synchronize(field.device)
+    v = out.cpu().numpy()
+    return float(v[0]), int(v[1])

@@ -611,6 +611,22 @@ int chr_mc_table(uint8_t *ntri, int8_t *tri) {
   return CHR_OK;
 }
 
+size_t chr_topology_workspace(void) { return align256(topo_workspace_bytes()); }
+
+int chr_topology_error_bound(const float *d_field, const int64_t dims[3], const float *h_isovalues, int n_iso,
+                             int64_t nth, double *d_out, void *d_ws, size_t ws_bytes, void *stream) {
+  if (!d_field || !d_out || !d_ws) return fail(CHR_E_INVAL, "NULL argument");
+  if (!dims_ok(dims)) return fail(CHR_E_INVAL, "dims must be in [1, 2^30]");
+  if ((double)dims[0] * (double)dims[1] * (double)ceil_div(dims[2], 64) >= 2147483648.0)
+    return fail(CHR_E_INVAL, "more than 2^31 words of 64 points");
+  if (n_iso < 0 || n_iso > kMaxIso || (n_iso > 0 && !h_isovalues)) return fail(CHR_E_INVAL, "n_iso must be in [0, 16]");
+  for (int j = 0; j < n_iso; j++)
+    if (!std::isfinite(h_isovalues[j])) return fail(CHR_E_INVAL, "isovalues must be finite");
+  if (ws_bytes < align256(topo_workspace_bytes())) return fail(CHR_E_NOMEM, "workspace too small");
+  launch_topology(d_field, dims, h_isovalues, n_iso, nth, d_out, d_ws, static_cast<hipStream_t>(stream));
+  return check_hip("chr_topology_error_bound launch");
+}
+
 int chr_range(const float *d_field, int64_t n, float *d_out, void *stream) {
   if (!d_field || !d_out || n < 1) return fail(CHR_E_INVAL, "bad argument");
   launch_range(d_field, n, d_out, static_cast<hipStream_t>(stream));

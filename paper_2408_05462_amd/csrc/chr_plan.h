@@ -101,6 +101,9 @@ void launch_mc_count(const McPlan &p, U4 *scan_tmp, hipStream_t s);  // bits, co
 void launch_mc_emit(const McPlan &p, hipStream_t s);                 // lists, vertices, triangles, counts[0..1]
 void launch_mc_cases(const McPlan &p, hipStream_t s);
 void launch_range(const float *f, int64_t n, float *out, hipStream_t s);
+size_t topo_workspace_bytes();
+int launch_topology(const float *f, const int64_t dims[3], const float *iso, int K, int64_t nth, double *out,
+                    void *ws, hipStream_t s);
 void mc_table_host(uint8_t *ntri, int8_t *tri);
 
 }  // namespace chr

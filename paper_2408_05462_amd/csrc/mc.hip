@@ -95,27 +95,39 @@ __device__ inline WordCtx32 word_ctx32(const McPlan &M, uint32_t gw) {
   return c;
 }
 
+// Word w of point row `row`, 0 past the row's last word.  The load itself is
+// unconditional (clamped to the last word), so that the loads of a lane's
+// words can all be in flight together.
 __device__ inline u64 bitsw(const McPlan &M, int64_t row, int64_t w) {
-  return (w < M.nw) ? M.bits[row * M.nw + w] : 0ull;
+  const bool in = w < M.nw;
+  const u64 v = M.bits[row * M.nw + (in ? w : M.nw - 1)];
+  return in ? v : 0ull;
 }
 
 struct Cross {
   u64 cx, cy, cz;
 };
 
-// Crossing masks of the owned +x/+y/+z edges of word w of point row (z, y).
+// Crossing masks of the owned +x/+y/+z edges of word w of point row (z, y)
+// (all zero for a word past the row's end).  Rows past the grid are read as
+// the row itself and masked off.
 __device__ inline Cross cross_of(const McPlan &M, int64_t z, int64_t y, int64_t w) {
-  Cross c{0, 0, 0};
-  if (w >= M.nw) return c;
+  const bool inw = w < M.nw;
+  const int64_t wc = inw ? w : M.nw - 1;
   const int64_t row = z * M.n[1] + y;
-  const int64_t rem = M.n[2] - w * 64;
+  const int64_t rem = M.n[2] - wc * 64;
   const u64 valid = rem >= 64 ? ~0ull : ((1ull << rem) - 1ull);
   const int64_t remx = rem - 1;
   const u64 validx = remx >= 64 ? ~0ull : (remx <= 0 ? 0ull : ((1ull << remx) - 1ull));
-  const u64 m = bitsw(M, row, w);
-  c.cx = (m ^ ((m >> 1) | (bitsw(M, row, w + 1) << 63))) & validx;
-  if (y + 1 < M.n[1]) c.cy = (m ^ bitsw(M, row + 1, w)) & valid;
-  if (z + 1 < M.n[0]) c.cz = (m ^ bitsw(M, row + M.n[1], w)) & valid;
+  const bool hy = y + 1 < M.n[1], hz = z + 1 < M.n[0];
+  const u64 m = bitsw(M, row, wc);
+  const u64 mn = bitsw(M, row, wc + 1);
+  const u64 my = bitsw(M, hy ? row + 1 : row, wc);
+  const u64 mz = bitsw(M, hz ? row + M.n[1] : row, wc);
+  Cross c;
+  c.cx = inw ? (m ^ ((m >> 1) | (mn << 63))) & validx : 0ull;
+  c.cy = (inw && hy) ? (m ^ my) & valid : 0ull;
+  c.cz = (inw && hz) ? (m ^ mz) & valid : 0ull;
   return c;
 }
 
@@ -235,11 +247,16 @@ __global__ __launch_bounds__(kBS) void k_mc_verts(McPlan M) {
     uint64_t id = M.P[gw].x + (uint32_t)popc3_below(x, i);
     const uint32_t xx = c.w * 64u + (uint32_t)i;
     const size_t gi = ((size_t)c.z * n1 + c.y) * n2 + xx;
+    // the point and its three neighbours, loaded together with the masks
+    // (a missing neighbour reads the point itself and is never used)
     const float fa = f[gi];
+    const float fx = f[xx + 1 < n2 ? gi + 1 : gi];
+    const float fy = f[c.y + 1 < n1 ? gi + n2 : gi];
+    const float fz = f[c.z + 1 < (uint32_t)M.n[0] ? gi + (size_t)n1 * n2 : gi];
     const float px = (float)xx, py = (float)c.y, pz = (float)c.z;
     if ((x.cx >> i) & 1ull) {
       if ((int64_t)id < M.cap_v) {
-        const float t = interp(fa, f[gi + 1], k);
+        const float t = interp(fa, fx, k);
         float *v = M.verts + 3 * id;
         v[0] = __fmul_rn(__fadd_rn(px, t), sp); v[1] = __fmul_rn(py, sp); v[2] = __fmul_rn(pz, sp);
       }
@@ -247,7 +264,7 @@ __global__ __launch_bounds__(kBS) void k_mc_verts(McPlan M) {
     }
     if ((x.cy >> i) & 1ull) {
       if ((int64_t)id < M.cap_v) {
-        const float t = interp(fa, f[gi + n2], k);
+        const float t = interp(fa, fy, k);
         float *v = M.verts + 3 * id;
         v[0] = __fmul_rn(px, sp); v[1] = __fmul_rn(__fadd_rn(py, t), sp); v[2] = __fmul_rn(pz, sp);
       }
@@ -255,7 +272,7 @@ __global__ __launch_bounds__(kBS) void k_mc_verts(McPlan M) {
     }
     if ((x.cz >> i) & 1ull) {
       if ((int64_t)id < M.cap_v) {
-        const float t = interp(fa, f[gi + (size_t)n1 * n2], k);
+        const float t = interp(fa, fz, k);
         float *v = M.verts + 3 * id;
         v[0] = __fmul_rn(px, sp); v[1] = __fmul_rn(py, sp); v[2] = __fmul_rn(__fadd_rn(pz, t), sp);
       }
@@ -272,15 +289,18 @@ struct Owner {
 
 __device__ inline Owner owner_at(const McPlan &M, uint32_t z, uint32_t y, uint32_t row, uint32_t w, const Cross &c,
                                  uint32_t vb, int xo) {
+  // the owner may start the next word (inside the row because the cell is);
+  // both candidates are computed and the right one selected
+  const Cross c1 = cross_of(M, z, y, w + 1);
+  const uint32_t wn = w + 1 < (uint32_t)M.nw ? w + 1 : w;
+  const uint32_t vb1 = M.P[row * (uint32_t)M.nw + wn].x;
   Owner o;
   if (xo < 64) {
     o.base = vb + (uint32_t)popc3_below(c, xo);
     o.bx = (uint32_t)((c.cx >> xo) & 1ull);
     o.by = (uint32_t)((c.cy >> xo) & 1ull);
   } else {
-    // the owner starts the next word (inside the row because the cell is)
-    const Cross c1 = cross_of(M, z, y, w + 1);
-    o.base = M.P[row * (uint32_t)M.nw + w + 1].x;
+    o.base = vb1;
     o.bx = (uint32_t)(c1.cx & 1ull);
     o.by = (uint32_t)(c1.cy & 1ull);
   }
@@ -317,22 +337,68 @@ __global__ __launch_bounds__(kBS) void k_mc_tris(McPlan M) {
       const uint32_t gw = ent.x >> 6;
       const int i = ent.x & 63;
       const WordCtx32 c = word_ctx32(M, gw);
-      const Corners C = corners_of(M, c.row, c.w);
+      // Every word this cell needs, loaded at once: point rows (z+dz, y+dy)
+      // for dz, dy in 0..2 (not both 2), words w and w+1.  Rows and words
+      // past the grid are read clamped and masked off below.
+      const uint32_t n0 = (uint32_t)M.n[0], n2 = (uint32_t)M.n[2];
+      const bool hy2 = c.y + 2 < n1, hz2 = c.z + 2 < n0, hn = c.w + 1 < nw;
+      const uint32_t wn = hn ? c.w + 1 : c.w;
+      const uint32_t ra0 = c.row, ra1 = ra0 + 1, ra2 = hy2 ? ra0 + 2 : ra1;
+      const uint32_t rb0 = ra0 + n1, rb1 = rb0 + 1, rb2 = hy2 ? rb0 + 2 : rb1;
+      const uint32_t rc0 = hz2 ? rb0 + n1 : rb0, rc1 = hz2 ? rb1 + n1 : rb1;
+      const u64 *__restrict__ B = M.bits;
+      const u64 a0 = B[ra0 * nw + c.w], a0n = B[ra0 * nw + wn], a1 = B[ra1 * nw + c.w], a1n = B[ra1 * nw + wn];
+      const u64 a2 = B[ra2 * nw + c.w], a2n = B[ra2 * nw + wn];
+      const u64 b0 = B[rb0 * nw + c.w], b0n = B[rb0 * nw + wn], b1 = B[rb1 * nw + c.w], b1n = B[rb1 * nw + wn];
+      const u64 b2 = B[rb2 * nw + c.w];
+      const u64 c0 = B[rc0 * nw + c.w], c1 = B[rc1 * nw + c.w];
+      const uint32_t v0 = M.P[ra0 * nw + c.w].x, v1 = M.P[ra1 * nw + c.w].x;
+      const uint32_t v2 = M.P[rb0 * nw + c.w].x, v3 = M.P[rb1 * nw + c.w].x;
+      const uint32_t v0n = M.P[ra0 * nw + wn].x, v1n = M.P[ra1 * nw + wn].x, v2n = M.P[rb0 * nw + wn].x;
+      // corners of the cells of word w (rows (dy,dz) = 00, 10, 01, 11)
+      const u64 nx0 = hn ? a0n : 0ull, nx1 = hn ? a1n : 0ull, nx2 = hn ? b0n : 0ull, nx3 = hn ? b1n : 0ull;
+      Corners C;
+      C.m[0] = a0; C.m[1] = shr1(a0, nx0);
+      C.m[2] = a1; C.m[3] = shr1(a1, nx1);
+      C.m[4] = b0; C.m[5] = shr1(b0, nx2);
+      C.m[6] = b1; C.m[7] = shr1(b1, nx3);
       const uint32_t cs = case_at(C, i);
       const int nt = tab.ntri[cs];
-      // owner rows R = dy + 2 dz
-      const uint32_t r0 = c.row, r1 = c.row + 1, r2 = c.row + n1, r3 = c.row + n1 + 1;
-      const Cross k0 = cross_of(M, c.z, c.y, c.w), k1 = cross_of(M, c.z, c.y + 1, c.w);
-      const Cross k2 = cross_of(M, c.z + 1, c.y, c.w), k3 = cross_of(M, c.z + 1, c.y + 1, c.w);
-      const uint32_t v0 = M.P[r0 * nw + c.w].x, v1 = M.P[r1 * nw + c.w].x;
-      const uint32_t v2 = M.P[r2 * nw + c.w].x, v3 = M.P[r3 * nw + c.w].x;
-      const Owner a00 = owner_at(M, c.z, c.y, r0, c.w, k0, v0, i);          // (dx,dy,dz) = (0,0,0)
-      const Owner a10 = owner_at(M, c.z, c.y, r0, c.w, k0, v0, i + 1);      // (1,0,0)
-      const Owner b00 = owner_at(M, c.z, c.y + 1, r1, c.w, k1, v1, i);      // (0,1,0)
-      const Owner b10 = owner_at(M, c.z, c.y + 1, r1, c.w, k1, v1, i + 1);  // (1,1,0)
-      const Owner d00 = owner_at(M, c.z + 1, c.y, r2, c.w, k2, v2, i);      // (0,0,1)
-      const Owner d10 = owner_at(M, c.z + 1, c.y, r2, c.w, k2, v2, i + 1);  // (1,0,1)
-      const Owner e00 = owner_at(M, c.z + 1, c.y + 1, r3, c.w, k3, v3, i);  // (0,1,1)
+      // crossing masks of the four owner rows at word w
+      const int64_t rem = (int64_t)n2 - (int64_t)c.w * 64;
+      const u64 valid = rem >= 64 ? ~0ull : ((1ull << rem) - 1ull);
+      const u64 validx = rem - 1 >= 64 ? ~0ull : (rem - 1 <= 0 ? 0ull : ((1ull << (rem - 1)) - 1ull));
+      Cross k0, k1, k2, k3;
+      k0.cx = (a0 ^ shr1(a0, nx0)) & validx; k0.cy = (a0 ^ a1) & valid; k0.cz = (a0 ^ b0) & valid;
+      k1.cx = (a1 ^ shr1(a1, nx1)) & validx; k1.cy = hy2 ? (a1 ^ a2) & valid : 0ull; k1.cz = (a1 ^ b1) & valid;
+      k2.cx = (b0 ^ shr1(b0, nx2)) & validx; k2.cy = (b0 ^ b1) & valid; k2.cz = hz2 ? (b0 ^ c0) & valid : 0ull;
+      k3.cx = (b1 ^ shr1(b1, nx3)) & validx; k3.cy = hy2 ? (b1 ^ b2) & valid : 0ull; k3.cz = hz2 ? (b1 ^ c1) & valid : 0ull;
+      // the first point of word w+1 (owner of the +x corner when i = 63):
+      // its +x / +y crossing bits
+      const bool x1 = (uint64_t)(c.w + 1) * 64u + 1u < n2;  // it has a +x neighbour
+      const uint32_t a0x = x1 ? (uint32_t)((a0n ^ (a0n >> 1)) & 1ull) : 0u;
+      const uint32_t a1x = x1 ? (uint32_t)((a1n ^ (a1n >> 1)) & 1ull) : 0u;
+      const uint32_t b0x = x1 ? (uint32_t)((b0n ^ (b0n >> 1)) & 1ull) : 0u;
+      const uint32_t a0y = (uint32_t)((a0n ^ a1n) & 1ull);
+      const uint32_t a1y = hy2 ? (uint32_t)((a1n ^ a2n) & 1ull) : 0u;
+      auto own = [&](const Cross &k, uint32_t vb, uint32_t vbn, uint32_t bxn, uint32_t byn, int xo) {
+        Owner o;
+        if (xo < 64) {
+          o.base = vb + (uint32_t)popc3_below(k, xo);
+          o.bx = (uint32_t)((k.cx >> xo) & 1ull);
+          o.by = (uint32_t)((k.cy >> xo) & 1ull);
+        } else {
+          o.base = vbn; o.bx = bxn; o.by = byn;
+        }
+        return o;
+      };
+      const Owner a00 = own(k0, v0, v0n, a0x, a0y, i);          // (dx,dy,dz) = (0,0,0)
+      const Owner a10 = own(k0, v0, v0n, a0x, a0y, i + 1);      // (1,0,0)
+      const Owner b00 = own(k1, v1, v1n, a1x, a1y, i);          // (0,1,0)
+      const Owner b10 = own(k1, v1, v1n, a1x, a1y, i + 1);      // (1,1,0)
+      const Owner d00 = own(k2, v2, v2n, b0x, 0u, i);           // (0,0,1)
+      const Owner d10 = own(k2, v2, v2n, b0x, 0u, i + 1);       // (1,0,1)
+      const Owner e00 = own(k3, v3, v3, 0u, 0u, i);             // (0,1,1)
       // x edges 0..3 at (dy,dz) = (0,0), (1,0), (0,1), (1,1)
       my[0] = (int32_t)a00.base;
       my[1] = (int32_t)b00.base;

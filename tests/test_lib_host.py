@@ -253,3 +253,19 @@ def test_server_rejects_requests_larger_than_the_pool():
     assert lib.chr_server_submit(h, 1, 0.4, 1.0, 0, C.byref(rid)) == L.CHR_E_NOMEM
     assert lib.chr_server_submit(h, 1, 0.4, 1.0, 2, C.byref(rid)) == L.CHR_OK
     assert lib.chr_server_destroy(h) == L.CHR_OK
+
+
+def test_topology_bound_rejects_bad_arguments():
+    """Argument checks happen before any device work."""
+    lib = L.load()
+    ws_n = lib.chr_topology_workspace()
+    assert 0 < ws_n < 1 << 16
+    iso = (C.c_float * 2)(0.1, 0.2)
+    fake = 0x100000
+    dims = L.dims3((4, 5, 6))
+    assert lib.chr_topology_error_bound(None, dims, iso, 2, 1, fake, fake, ws_n, None) == L.CHR_E_INVAL
+    assert lib.chr_topology_error_bound(fake, L.dims3((0, 5, 6)), iso, 2, 1, fake, fake, ws_n, None) == L.CHR_E_INVAL
+    assert lib.chr_topology_error_bound(fake, dims, iso, 17, 1, fake, fake, ws_n, None) == L.CHR_E_INVAL
+    bad = (C.c_float * 1)(float("inf"))
+    assert lib.chr_topology_error_bound(fake, dims, bad, 1, 1, fake, fake, ws_n, None) == L.CHR_E_INVAL
+    assert lib.chr_topology_error_bound(fake, dims, iso, 2, 1, fake, fake, ws_n - 1, None) == L.CHR_E_NOMEM
