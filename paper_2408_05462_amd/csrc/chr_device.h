@@ -203,7 +203,8 @@ __device__ inline void stf(char *__restrict__ base, uint32_t off, float v) {
 // last block along each axis -- plus divisors that split a block index into
 // (bz, by, bx); filled on the host so kernels skip the 64-bit arithmetic.
 struct L0Geo {
-  Sec sec[8];
+  Sec sec[8];    // level 0
+  Sec sec1[8];   // level 1 (when the hierarchy has one)
   FastDiv d_nb2, d_nb1;
   uint32_t nb[3];
 };
@@ -217,6 +218,7 @@ __host__ inline void make_l0geo(const Geo &g, L0Geo &G) {
     int64_t o[3], hi[3];
     block_ext(g, (bz * g.nb[1] + by) * g.nb[2] + bx, o, hi);
     G.sec[cls] = sec_geom(o, hi, 0, g.nL - 1);
+    G.sec1[cls] = sec_geom(o, hi, g.nL >= 2 ? 1 : 0, g.nL - 1);
   }
 }
 

@@ -236,8 +236,8 @@ __global__ __launch_bounds__(kBS) void k_decode_level(DecPlan D, int l) {
   uint32_t t, b;
   xcd_remap(t, b);
   const int wave = threadIdx.x / kWave;
-  int64_t o[3], hi[3];
-  block_ext(g, b, o, hi);
+  const BlockPos bp = block_pos(g, D.l0, b);
+  const int64_t o[3] = {bp.o[0], bp.o[1], bp.o[2]}, hi[3] = {bp.hi[0], bp.hi[1], bp.hi[2]};
   float *dst = D.gp[l];
   const int64_t *gd = D.gd[l];
   if (l < L) {
@@ -256,7 +256,7 @@ __global__ __launch_bounds__(kBS) void k_decode_level(DecPlan D, int l) {
       for (uint32_t u = lane_id(); u < c2; u += kWave) dst[drow + 2 * u] = src[srow + u];
     }
   }
-  const Sec s = sec_geom(o, hi, l, L);
+  const Sec s = (l == 1) ? D.l0.sec1[bp.cls] : sec_geom(o, hi, l, L);
   const uint32_t nch = (s.npts + 63) / 64;
   if (t >= (nch + 63) / 64) return;
   const SecView v = open_section(D, b, l, s.npts);

@@ -433,6 +433,98 @@ __global__ __launch_bounds__(kBS) void k_encode_l0(EncPlan P) {
   part_store(acc, &P.part[(int64_t)b * P.part_per_block + gxi]);
 }
 
+// Level 1 below a coarser level (nL >= 3): the arithmetic of enc_chunk
+// with the level fixed at 1.  Section coordinates (w, v, u) are the block's
+// 2-grid, so parities and parents follow from them directly; 32-bit byte
+// offsets from uniform bases (the block's first plane of the field, of the
+// level-2 grid it predicts from and of the level-1 grid it fills).
+template <bool AUX, int KB>
+__global__ __launch_bounds__(kBS) void k_encode_l1s(EncPlan P) {
+  __shared__ uint32_t pack[kWaves][32];
+  uint32_t bx, by;
+  xcd_remap(bx, by);
+  const uint32_t b = by;
+  const int wave = threadIdx.x / kWave;
+  const int lane = lane_id();
+  const Geo &g = P.g;
+  const BlockPos bp = block_pos(g, P.l0, b);
+  const int64_t o[3] = {bp.o[0], bp.o[1], bp.o[2]}, hi[3] = {bp.hi[0], bp.hi[1], bp.hi[2]};
+  // the block's level-2 points carry over into the level-1 grid unchanged
+  copy_coarse(P.G + P.g_off[2], P.gd[2], P.G + P.g_off[1], P.gd[1], o, hi, 2, bx * kWaves + wave,
+              gridDim.x * kWaves);
+  const Sec s = P.l0.sec1[bp.cls];
+  const uint32_t nch = (s.npts + 63) / 64;
+  const uint32_t maxch = P.maxch[1];
+  const uint32_t n1 = (uint32_t)g.n[1], n2 = (uint32_t)g.n[2];
+  const uint32_t oy = bp.o[1], ox = bp.o[2];
+  const uint32_t ownz = bp.own[0] - bp.o[0], owny = bp.own[1], ownx = bp.own[2];
+  // level-2 grid (parents): block origin o / 4; level-1 grid (output): o / 2
+  const uint32_t h0 = (uint32_t)P.gd[2][0], h1 = (uint32_t)P.gd[2][1], h2 = (uint32_t)P.gd[2][2];
+  const uint32_t f1 = (uint32_t)P.gd[1][1], f2 = (uint32_t)P.gd[1][2];
+  const uint32_t z4 = (uint32_t)(o[0] >> 2), y4 = oy >> 2, x4 = ox >> 2;
+  const uint32_t y2 = oy >> 1, x2 = ox >> 1;
+  const char *__restrict__ xbase = reinterpret_cast<const char *>(P.x + (size_t)o[0] * n1 * n2);
+  const char *__restrict__ G2b = reinterpret_cast<const char *>(P.G + P.g_off[2] + (size_t)z4 * h1 * h2);
+  char *__restrict__ G1b = reinterpret_cast<char *>(P.G + P.g_off[1] + (size_t)(o[0] >> 1) * f1 * f2);
+  const uint32_t h2x4 = h2 * 4u, h12x4 = h1 * h2 * 4u;
+  const int64_t slot0 = P.slot_base[1] + (int64_t)b * maxch;
+  const int K = g.K;
+  float iso[KB];
+#pragma unroll
+  for (int jj = 0; jj < KB; jj++) iso[jj] = g.iso[jj];
+  Part acc;
+  part_init(acc);
+#pragma unroll 1
+  for (int k = 0; k < kChunksPerWave; k++) {
+    const uint32_t c = (bx * kChunksPerWave + k) * kWaves + wave;
+    if (c >= maxch) break;
+    const int64_t slot = slot0 + c;
+    if (c >= nch) {
+      if (lane == 0) P.cnt[slot] = U4{0, 0, 0, 0};
+      continue;
+    }
+    const uint32_t j = c * kWave + (uint32_t)lane;
+    float x = 0.f;
+    uint32_t zz = 0;
+    bool E = false;
+    if (j < s.npts) {
+      uint32_t w, v, u;
+      sec_point(s, j, w, v, u);
+      const uint32_t zr = 2 * w, y = oy + 2 * v, xx = ox + 2 * u;  // zr relative to the block
+      x = ldf(xbase, ((zr * n1 + y) * n2 + xx) * 4u);
+      const uint32_t pz = w & 1u, py = v & 1u, px = u & 1u;
+      const uint32_t zl = w >> 1, yl = y4 + (v >> 1), xl = x4 + (u >> 1);  // zl relative to the slab
+      const bool zu = pz && (z4 + zl + 1 < h0), yu = py && (yl + 1 < h1), xu = px && (xl + 1 < h2);
+      const uint32_t o00 = ((zl * h1 + yl) * h2 + xl) * 4u;
+      const uint32_t dxo = xu ? 4u : 0u, dyo = yu ? h2x4 : 0u, dzo = zu ? h12x4 : 0u;
+      const uint32_t o01 = o00 + dyo, o10 = o00 + dzo, o11 = o10 + dyo;
+      const float p = midpoint8(ldf(G2b, o00), ldf(G2b, o00 + dxo), ldf(G2b, o01), ldf(G2b, o01 + dxo),
+                                ldf(G2b, o10), ldf(G2b, o10 + dxo), ldf(G2b, o11), ldf(G2b, o11 + dxo), zu, yu, xu);
+      int32_t q;
+      int O, C = 0;
+      float xr;
+      quantize(g, x, p, q, O, xr);
+      if (!O && K > 0) C = rank_of<KB>(iso, K, x) != rank_of<KB>(iso, K, xr);
+      if (O || C) { xr = x; q = 0; }
+      E = O || C;
+      zz = ((uint32_t)q << 1) ^ (uint32_t)(q >> 31);
+      stf(G1b, ((w * f1 + (y2 + v)) * f2 + (x2 + u)) * 4u, xr);
+      const uint32_t ro = ord_of(xr), xo = ord_of(x);
+      acc.rmin = min(acc.rmin, ro); acc.rmax = max(acc.rmax, ro);
+      acc.xmin = min(acc.xmin, xo); acc.xmax = max(acc.xmax, xo);
+      acc.nonfinite |= !isfinite(x);
+      if (zr < ownz && y < owny && xx < ownx) { acc.nO += O; acc.nC += C; }
+      if (AUX) {
+        const size_t gi = ((size_t)(o[0] + zr) * n1 + y) * n2 + xx;
+        if (P.codes) P.codes[gi] = q;
+        if (P.flags) P.flags[gi] = (uint8_t)(O | (C << 1));
+      }
+    }
+    pack_chunk(P, slot, zz, E, x, pack[wave]);
+  }
+  part_store(acc, &P.part[(int64_t)b * P.part_per_block + P.part_l1 + bx]);
+}
+
 // Byte size of every section from the scanned chunk sizes.
 __global__ __launch_bounds__(kBS) void k_sections(EncPlan P) {
   const Geo &g = P.g;
@@ -777,8 +869,17 @@ void launch_encode_levels(const EncPlan &p, hipStream_t s) {
     prof_mark("k_encode_coarse", s, 1);
   }
   if (L >= 1) {
+    int64_t o[3], hi[3];
+    block_ext(g, 0, o, hi);
+    const bool slab32 = 4.0 * (double)(hi[0] - o[0] + 1) * (double)g.n[1] * (double)g.n[2] < 4294967296.0;
+    const dim3 grid1((unsigned)encode_l1_groups(p), (unsigned)g.nblocks);
     prof_mark("k_encode_l1", s, 0);
-    k_encode_l1<KB><<<dim3((unsigned)encode_l1_groups(p), (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
+    if (L >= 2 && slab32 && !p.codes && !p.flags)
+      k_encode_l1s<false, KB><<<grid1, dim3(kBS), 0, s>>>(p);
+    else if (L >= 2 && slab32)
+      k_encode_l1s<true, KB><<<grid1, dim3(kBS), 0, s>>>(p);
+    else
+      k_encode_l1<KB><<<grid1, dim3(kBS), 0, s>>>(p);
     prof_mark("k_encode_l1", s, 1);
   }
   if (gx > 0) {
