@@ -51,6 +51,8 @@ def parse_args():
     ap.add_argument("--requests", type=int, default=300, help="serve1024: requests per open-loop run")
     ap.add_argument("--slots", type=int, default=4, help="serve1024: server slots")
     ap.add_argument("--group", type=int, default=8, help="serve1024: requests per shared reconstruction")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-latency part of the default run")
+    ap.add_argument("--serve-requests", type=int, default=200, help="requests of the default run's served part")
     ap.add_argument("--batch-items", type=int, default=64, help="batch64: number of timesteps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-planes", type=int, default=0,
@@ -201,24 +203,23 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
-def run_serve(args):
-    """A resident 1024^3 field at three accuracy tiers; a Poisson stream of
-    (isovalue, accuracy) requests served by the continuous-batching server
-    and, for comparison, by plain per-request launches (reconstruct, then
-    marching cubes, one request at a time in arrival order)."""
+def serve_experiment(x, isos, levels, block, R, slots, group, fracs=(0.5, 0.8, 1.0), seed_offset=5,
+                     pool_frac=0.6, verify=8):
+    """Three resident streams of field x at e = {1e-2, 1e-3, 1e-4} x range; R
+    requests (isovalue ~ U(range), accuracy uniform over the tiers, level 0)
+    served by the continuous-batching server and, for comparison, by plain
+    per-request launches (reconstruct, then marching cubes, one request at a
+    time in arrival order).  Closed loop (all requests at t = 0) gives each
+    path's saturation rate; open loop (Poisson arrivals at `fracs` x the plain
+    path's saturation rate) gives p50/p99 latency.  `verify` served meshes
+    are checked bit for bit against the plain calls."""
     import torch
 
     from paper_2408_05462_amd import _lib as L
     from paper_2408_05462_amd import api, inputs
 
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    n = args.serve_n
-    t0 = time.time()
-    x = inputs.grf_torch(n, 0.0, device=dev)
+    dev = x.device
     lo, hi = float(x.min()), float(x.max())
-    isos = inputs.sample_quantiles(x, 8)
-    levels, block = 6, 64
     p = api.params(levels, block)
     N = x.numel()
     tiers = []
@@ -237,11 +238,8 @@ def run_serve(args):
     del ws, buf
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
-    log(f"field {n}^3 and 3 tiers ready in {time.time() - t0:.1f}s; ratios "
-        f"{[round(4.0 * N / t[4]['stream_bytes'], 2) for t in tiers]}")
 
-    rng = np.random.default_rng(inputs.SEED_BASE + 5)
-    R = args.requests
+    rng = np.random.default_rng(inputs.SEED_BASE + seed_offset)
     ks = rng.uniform(lo, hi, size=R).astype(np.float32)
     tier_of = rng.integers(0, 3, size=R)
     gaps = rng.exponential(1.0, size=R)
@@ -253,18 +251,19 @@ def run_serve(args):
     mws = torch.empty(api.iso_workspace(x.shape), dtype=torch.uint8, device=dev)
     counts = torch.zeros(2, dtype=torch.int64, device=dev)
     api.chr_reconstruct(tiers[2][3], tiers[2][2], 0, tiers[2][1], recon, st0, rws)
-    api.iso_extract(recon, float(np.median(isos)), 1.0, None, None, counts, mws)
+    # capacity for every request's mesh (counted on the finest tier, plus a margin for the others)
+    cap_v = cap_t = 1024
+    allc = torch.zeros((R, 2), dtype=torch.int64, device=dev)
+    for i in range(R):
+        api.iso_extract(recon, float(ks[i]), 1.0, None, None, allc[i], mws)
     torch.cuda.synchronize()
-    cv, ct = (int(v) for v in counts.cpu())
-    cap_v, cap_t = int(cv * 1.25) + 1024, int(ct * 1.25) + 1024
+    mx = allc.max(dim=0).values.cpu().numpy()
+    cap_v, cap_t = int(mx[0] * 1.25) + 1024, int(mx[1] * 1.25) + 1024
+    del allc
     verts = torch.empty((cap_v, 3), dtype=torch.float32, device=dev)
     tris = torch.empty((cap_t, 3), dtype=torch.int32, device=dev)
-    del mws
-    mws = torch.empty(api.iso_workspace(x.shape), dtype=torch.uint8, device=dev)
-    log(f"plain output capacity {cap_v} vertices, {cap_t} triangles")
 
     def plain_run(arrivals):
-        """Requests served one at a time in arrival order; returns latencies (ms) and wall (s)."""
         lat = np.zeros(R)
         torch.cuda.synchronize()
         base = time.perf_counter()
@@ -279,14 +278,10 @@ def run_serve(args):
             lat[i] = (time.perf_counter() - base) * 1e3 - arrivals[i]
         return lat, time.perf_counter() - base
 
-    del recon
-    torch.cuda.empty_cache()
     free_b, _ = torch.cuda.mem_get_info()
-    pool = torch.empty(int(free_b * 0.6) & ~255, dtype=torch.uint8, device=dev)
-    recon = torch.empty_like(x)
-    log(f"server pool {pool.numel() / 2**30:.1f} GiB")
+    pool = torch.empty(int(free_b * pool_frac) & ~255, dtype=torch.uint8, device=dev)
 
-    def served_run(arrivals, slots, group):
+    def served_run(arrivals):
         srv = api.Server(pool, slots=slots, max_group=group)
         for t in tiers:
             srv.add_stream(0, t[3], t[2])
@@ -315,19 +310,17 @@ def run_serve(args):
         srv.close()
         return lat, wall, stats
 
-    # closed loop (all requests at t = 0): saturation throughput of each path
     zero = np.zeros(R)
     lat_p, wall_p = plain_run(zero)
-    lat_s, wall_s, st_s = served_run(zero, args.slots, args.group)
+    lat_s, wall_s, st_s = served_run(zero)
     sat_plain, sat_served = R / wall_p, R / wall_s
     log(f"saturation: plain {sat_plain:.1f} req/s, served {sat_served:.1f} req/s ({st_s})")
-    # open loop: Poisson arrivals at fractions of the plain path's saturation rate
     runs = {}
-    for frac in (0.5, 0.8, 1.0):
+    for frac in fracs:
         lam = frac * sat_plain
         arr = np.cumsum(gaps) / lam * 1e3
         lp, wp = plain_run(arr)
-        ls, ws_, sts = served_run(arr, args.slots, args.group)
+        ls, ws_, sts = served_run(arr)
         runs[str(frac)] = {
             "lambda_req_s": round(lam, 2),
             "plain": {"p50_ms": round(float(np.percentile(lp, 50)), 3), "p99_ms": round(float(np.percentile(lp, 99)), 3),
@@ -337,60 +330,81 @@ def run_serve(args):
         }
         log(f"lambda {frac} x plain saturation: {runs[str(frac)]}")
 
-    # a sample of served meshes equals the plain calls' meshes
-    srv = api.Server(pool, slots=args.slots, max_group=args.group)
-    for t in tiers:
-        srv.add_stream(0, t[3], t[2])
-    sample = list(range(0, R, max(1, R // 8)))[:8]
-    sid = [srv.submit(0, float(ks[i]), tiers[tier_of[i]][1], 0) for i in sample]
-    srv.drain(sid)
-    for i, rid in zip(sample, sid):
-        rel, e, st, info, _ = tiers[tier_of[i]]
-        api.chr_reconstruct(info, st, 0, e, recon, st0, rws)
-        api.iso_extract(recon, float(ks[i]), 1.0, verts, tris, counts, mws)
-        torch.cuda.synchronize()
-        nv, nt = (int(v) for v in counts.cpu())
-        r = srv.poll(rid)
-        assert r.status == 0 and (r.n_vertices, r.n_triangles) == (nv, nt), i
-        v, t = srv.mesh(rid)
-        assert np.array_equal(v.view(np.uint32), verts[:nv].cpu().numpy().view(np.uint32)), i
-        assert np.array_equal(t, tris[:nt].cpu().numpy()), i
-    srv.close()
+    sample = list(range(0, R, max(1, R // max(verify, 1))))[:verify]
+    if verify:
+        srv = api.Server(pool, slots=slots, max_group=group)
+        for t in tiers:
+            srv.add_stream(0, t[3], t[2])
+        sid = [srv.submit(0, float(ks[i]), tiers[tier_of[i]][1], 0) for i in sample]
+        srv.drain(sid)
+        for i, rid in zip(sample, sid):
+            rel, e, st, info, _ = tiers[tier_of[i]]
+            api.chr_reconstruct(info, st, 0, e, recon, st0, rws)
+            api.iso_extract(recon, float(ks[i]), 1.0, verts, tris, counts, mws)
+            torch.cuda.synchronize()
+            nv, nt = (int(v) for v in counts.cpu())
+            assert nv <= verts.shape[0] and nt <= tris.shape[0], "plain output capacity too small"
+            r = srv.poll(rid)
+            assert r.status == 0 and (r.n_vertices, r.n_triangles) == (nv, nt), i
+            v, t = srv.mesh(rid)
+            assert np.array_equal(v.view(np.uint32), verts[:nv].cpu().numpy().view(np.uint32)), i
+            assert np.array_equal(t, tris[:nt].cpu().numpy()), i
+        srv.close()
+    del pool, recon, verts, tris, mws, rws
+    torch.cuda.empty_cache()
+    return {"sat_plain": sat_plain, "sat_served": sat_served, "runs": runs, "N": N,
+            "ratios": [round(4.0 * N / t[4]["stream_bytes"], 3) for t in tiers], "sample": sample, "ks": ks,
+            "tier_of": tier_of, "lo": lo, "hi": hi, "requests": R}
 
+
+def run_serve(args):
+    """The 1024^3 serving workload (see serve_experiment)."""
+    import torch
+
+    from paper_2408_05462_amd import inputs
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n = args.serve_n
+    t0 = time.time()
+    x = inputs.grf_torch(n, 0.0, device=dev)
+    isos = inputs.sample_quantiles(x, 8)
+    levels, block = 6, 64
+    log(f"field {n}^3 ready in {time.time() - t0:.1f}s")
+    ex = serve_experiment(x, isos, levels, block, args.requests, args.slots, args.group)
+    N = ex["N"]
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
 
-        # the oracle serves a sample of requests on a 256-plane slab of the same field
         planes = 64
         slab = x[:planes].cpu().numpy()
         tc = time.perf_counter()
         done = 0
-        for i in sample[:4]:
-            rel = tiers[tier_of[i]][0]
-            ref = oracle.compress(slab, rel * (hi - lo), isos, levels=levels, block=block)
+        for i in ex["sample"][:4]:
+            rel = (1e-2, 1e-3, 1e-4)[ex["tier_of"][i]]
+            ref = oracle.compress(slab, rel * (ex["hi"] - ex["lo"]), isos, levels=levels, block=block)
             y = oracle.decompress(ref["stream"])
-            oracle.mc(y, float(ks[i]))
+            oracle.mc(y, float(ex["ks"][i]))
             done += 1
         tcpu = time.perf_counter() - tc
         cpu = {"value": round(4.0 * slab.size * done / tcpu / 1e9, 4), "unit": "GB/s", "cores": int(oracle.threads()),
                "kind": "oracle",
                "sample": f"{done} requests (compress+reconstruct+MC) on the first {planes} z-planes, {tcpu:.2f}s"}
-
-    mid = runs["0.8"]
-    gbs = sat_served * 4.0 * N / 1e9
+    mid = ex["runs"]["0.8"]
+    gbs = ex["sat_served"] * 4.0 * N / 1e9
     out = {
-        "metric": METRIC, "value": round(gbs, 2), "unit": "GB/s", "n_gpus": 1, "steps": R, "warmup": 0,
-        "ms_per_step": round(1e3 / sat_served, 4), "higher_is_better": True, "scaling": "weak",
+        "metric": METRIC, "value": round(gbs, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.requests, "warmup": 0,
+        "ms_per_step": round(1e3 / ex["sat_served"], 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "serve1024", "dims": [n, n, n], "levels": levels, "block": block,
-                   "tiers_rel": [1e-2, 1e-3, 1e-4], "requests": R, "slots": args.slots, "max_group": args.group},
+                   "tiers_rel": [1e-2, 1e-3, 1e-4], "requests": args.requests, "slots": args.slots,
+                   "max_group": args.group},
         "value_is": "served saturation throughput x 4N input bytes per request",
-        "saturation_req_s": {"plain": round(sat_plain, 2), "served": round(sat_served, 2)},
+        "saturation_req_s": {"plain": round(ex["sat_plain"], 2), "served": round(ex["sat_served"], 2)},
         "latency_at_0.8": {"plain_p50_ms": mid["plain"]["p50_ms"], "plain_p99_ms": mid["plain"]["p99_ms"],
                            "served_p50_ms": mid["served"]["p50_ms"], "served_p99_ms": mid["served"]["p99_ms"]},
-        "open_loop": runs,
-        "compression_ratio": [round(4.0 * N / t[4]["stream_bytes"], 3) for t in tiers],
+        "open_loop": ex["runs"], "compression_ratio": ex["ratios"],
         "roofline": None, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -560,6 +574,21 @@ def main():
         topo[label] = {"nth": nth, "bound": float(tout[0].item()), "ms": round(e0.elapsed_time(e1) / 3, 4)}
     topo["n_D"] = m
 
+    # served latency on the same field (the metric's second half): requests
+    # at random isovalues and accuracy tiers, continuous-batching server vs
+    # plain per-request launches at 0.8 x the plain path's saturation rate
+    served = None
+    if not args.no_serve:
+        del cws
+        torch.cuda.empty_cache()
+        ex = serve_experiment(x, isos, w["levels"], w["block"], args.serve_requests, args.slots, args.group,
+                              fracs=(0.8,), verify=4)
+        r8 = ex["runs"]["0.8"]
+        served = {"requests": ex["requests"], "tiers_rel": [1e-2, 1e-3, 1e-4],
+                  "saturation_req_s": {"plain": round(ex["sat_plain"], 2), "served": round(ex["sat_served"], 2)},
+                  "at_0.8_plain_saturation": r8, "p99_ms": r8["served"]["p99_ms"],
+                  "plain_p99_ms": r8["plain"]["p99_ms"]}
+
     # CPU oracle baseline on a bounded sample of the same workload
     cpu = None
     if not args.no_cpu_baseline:
@@ -593,7 +622,8 @@ def main():
                        "mc_per_isovalue": round(4.0 * N * len(isos) / stage_ms[2] / 1e6, 1)},
         "compression_ratio": round(cr, 3), "stream_bytes": nbytes, "n_outlier": r["n_outlier"],
         "n_corrected": r["n_corrected"], "triangles": [int(c[1]) for c in cnt],
-        "wall_s_timed": round(wall, 3), "topology_error_bound": topo, "roofline": roofline, "cpu_baseline": cpu,
+        "wall_s_timed": round(wall, 3), "served": served, "topology_error_bound": topo, "roofline": roofline,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
