@@ -157,6 +157,20 @@ int chr_reconstruct(const chr_info *info, const void *d_stream, size_t stream_by
                     int level, double error_bound, float *d_out, int32_t *d_status,
                     void *d_ws, size_t ws_bytes, void *stream);
 
+/* Reconstruction restricted to what isosurfaces at isovalues in [kmin, kmax]
+ * need (Sec. II.A: the block index lets the viewer touch only the blocks an
+ * isovalue needs).  Blocks whose block-table range [min, max] admits no k in
+ * [kmin, kmax] with min < k <= max are not decoded; their owned points get a
+ * single value on the same side of every such k (the block's min or max).
+ * For every isovalue k in [kmin, kmax], iso_extract / iso_cases on the result
+ * give exactly what they give on the full chr_reconstruct output; the other
+ * values are only guaranteed in reconstructed blocks.  Arguments, output and
+ * errors as chr_reconstruct, plus CHR_E_INVAL for a non-finite or empty
+ * range. */
+int chr_reconstruct_range(const chr_info *info, const void *d_stream, size_t stream_bytes,
+                          int level, double error_bound, float kmin, float kmax, float *d_out,
+                          int32_t *d_status, void *d_ws, size_t ws_bytes, void *stream);
+
 /* ---- isosurface extraction (marching cubes, Sec. I and Sec. II.B) ------- */
 
 /* Workspace bytes iso_extract / iso_cases need for a field of these dims. */

@@ -27,7 +27,8 @@ EXPORTS = ["chr_last_error", "chr_version", "chr_compress_bound", "chr_compress_
            "chr_batch_run", "chr_batch_capture", "chr_batch_replay", "chr_batch_autotune", "chr_batch_config",
            "chr_batch_destroy", "chr_server_create", "chr_server_add_stream", "chr_server_submit",
            "chr_server_step", "chr_server_poll", "chr_server_release", "chr_server_cancel", "chr_server_stats_get",
-           "chr_server_now_ms", "chr_server_destroy", "chr_topology_workspace", "chr_topology_error_bound"]
+           "chr_server_now_ms", "chr_server_destroy", "chr_topology_workspace", "chr_topology_error_bound",
+           "chr_reconstruct_range"]
 
 
 class ChrError(RuntimeError):
@@ -170,6 +171,9 @@ def load():
     L.chr_server_now_ms.restype = C.c_double
     L.chr_server_destroy.argtypes = [vp]
     L.chr_server_destroy.restype = C.c_int
+    L.chr_reconstruct_range.argtypes = [C.POINTER(chr_info), vp, C.c_size_t, C.c_int, C.c_double, C.c_float,
+                                        C.c_float, vp, vp, vp, C.c_size_t, vp]
+    L.chr_reconstruct_range.restype = C.c_int
     L.chr_topology_workspace.restype = C.c_size_t
     L.chr_topology_error_bound.argtypes = [vp, i64p, vp, C.c_int, C.c_int64, vp, vp, C.c_size_t, vp]
     L.chr_topology_error_bound.restype = C.c_int

@@ -137,6 +137,27 @@ def chr_reconstruct(info, stream_dev, level, error_bound, out, status, ws, strea
     L.check(rc, "chr_reconstruct")
 
 
+def chr_reconstruct_range(info, stream_dev, level, error_bound, kmin, kmax, out, status, ws, stream=None):
+    rc = L.load().chr_reconstruct_range(C.byref(info), _p(stream_dev), stream_dev.numel(), level, float(error_bound),
+                                        float(np.float32(kmin)), float(np.float32(kmax)), _p(out), _p(status), _p(ws),
+                                        0 if ws is None else ws.numel(), _s(stream))
+    L.check(rc, "chr_reconstruct_range")
+
+
+def reconstruct_range(c: Compressed, kmin, kmax, level=0):
+    """Synchronous restricted reconstruction (see chr_reconstruct_range)."""
+    dev = c.stream.device
+    out = torch.empty(level_shape(c.info, level), dtype=torch.float32, device=dev)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    ws = torch.empty(max(chr_reconstruct_workspace(c.info, level), 256), dtype=torch.uint8, device=dev)
+    chr_reconstruct_range(c.info, c.stream, level, c.info.error_bound, kmin, kmax, out, status, ws)
+    torch.cuda.synchronize(dev)
+    st = int(status.item())
+    if st != 0:
+        raise L.ChrError(st, "chr_reconstruct_range (device status)")
+    return out
+
+
 def reconstruct(c: Compressed, level=0, error_bound=None):
     eb = c.info.error_bound if error_bound is None else error_bound
     dev = c.stream.device

@@ -560,8 +560,29 @@ size_t chr_reconstruct_workspace(const chr_info *info, int level) {
   return dec_workspace_bytes(g, level);
 }
 
+static int reconstruct_impl(const chr_info *info, const void *d_stream, size_t stream_bytes, int level,
+                            double error_bound, const float *krange, float *d_out, int32_t *d_status, void *d_ws,
+                            size_t ws_bytes, void *stream);
+
 int chr_reconstruct(const chr_info *info, const void *d_stream, size_t stream_bytes, int level, double error_bound,
                     float *d_out, int32_t *d_status, void *d_ws, size_t ws_bytes, void *stream) {
+  return reconstruct_impl(info, d_stream, stream_bytes, level, error_bound, nullptr, d_out, d_status, d_ws, ws_bytes,
+                          stream);
+}
+
+int chr_reconstruct_range(const chr_info *info, const void *d_stream, size_t stream_bytes, int level,
+                          double error_bound, float kmin, float kmax, float *d_out, int32_t *d_status, void *d_ws,
+                          size_t ws_bytes, void *stream) {
+  if (!std::isfinite(kmin) || !std::isfinite(kmax) || !(kmin <= kmax))
+    return fail(CHR_E_INVAL, "isovalue range must be finite with kmin <= kmax");
+  const float kr[2] = {kmin, kmax};
+  return reconstruct_impl(info, d_stream, stream_bytes, level, error_bound, kr, d_out, d_status, d_ws, ws_bytes,
+                          stream);
+}
+
+static int reconstruct_impl(const chr_info *info, const void *d_stream, size_t stream_bytes, int level,
+                            double error_bound, const float *krange, float *d_out, int32_t *d_status, void *d_ws,
+                            size_t ws_bytes, void *stream) {
   if (!info || !d_stream || !d_out) return fail(CHR_E_INVAL, "NULL argument");
   Geo g;
   int rc = info_geo(info, g);
@@ -573,6 +594,11 @@ int chr_reconstruct(const chr_info *info, const void *d_stream, size_t stream_by
   rc = dec_prepare(g, info->payload_offset, level, d_stream, info->total_bytes, d_out, d_status, d_ws, ws_bytes,
                    g_tune.dec_cpw0, J);
   if (rc) return rc;
+  if (krange) {
+    J.D.prune = 1;
+    J.D.kmin = krange[0];
+    J.D.kmax = krange[1];
+  }
   launch_decode(J.D, static_cast<hipStream_t>(stream));
   return check_hip("chr_reconstruct launch");
 }

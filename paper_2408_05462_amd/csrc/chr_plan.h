@@ -64,6 +64,8 @@ struct DecPlan {
   uint64_t payload_off;
   float *out;                    // full-resolution output when lo == 0
   int32_t *status;
+  int prune;                     // reconstruct only blocks that can hold an isosurface for k in [kmin, kmax]
+  float kmin, kmax;
 };
 
 struct McPlan {

@@ -86,6 +86,24 @@ __device__ inline void set_status(const DecPlan &D, int32_t code) {
   if (D.status) atomicMin(D.status, code);
 }
 
+// Block-table range [min, max] of block b's reconstructed values.
+__device__ inline void block_range(const DecPlan &D, int64_t b, float &mn, float &mx) {
+  const uint64_t off = kHeaderBytes + 16 * ((uint64_t)D.g.nblocks * D.g.nL + (uint64_t)b);
+  mn = __uint_as_float(ld32(D.s + off));
+  mx = __uint_as_float(ld32(D.s + off + 4));
+}
+
+// Whether block b is reconstructed: always, unless the reconstruction is
+// restricted to isovalues k in [kmin, kmax]; then only blocks whose range
+// gives min < k <= max for some such k (the others hold no cell whose
+// corners lie on both sides of any such k).
+__device__ inline bool block_needed(const DecPlan &D, int64_t b) {
+  if (!D.prune) return true;
+  float mn, mx;
+  block_range(D, b, mn, mx);
+  return mn < mx && mn < D.kmax && D.kmin <= mx;
+}
+
 // Decodes chunks [kbeg, kend) of tile t of a section (every lane of the
 // wave takes part in the tile's offset scan); calls emit(z, y, x, value) for
 // every point.
@@ -151,6 +169,7 @@ __global__ __launch_bounds__(kBS) void k_decode_coarse(DecPlan D) {
   const Geo &g = D.g;
   const int L = g.nL - 1;
   const int64_t b = blockIdx.x;
+  if (!block_needed(D, b)) return;
   const int wave = threadIdx.x / kWave;
   const int lmin = D.lo > 3 ? D.lo : 3;  // levels 2 and 1 have wide kernels of their own
   int64_t o[3], hi[3];
@@ -193,6 +212,7 @@ __global__ __launch_bounds__(kBS) void k_decode_fine(DecPlan D) {
   const Geo &g = D.g;
   const int L = g.nL - 1;
   const int64_t b = blockIdx.y;
+  if (!block_needed(D, b)) return;
   const uint32_t t = blockIdx.x * kWaves + threadIdx.x / kWave;
   int64_t o[3], hi[3];
   block_ext(g, b, o, hi);
@@ -211,15 +231,19 @@ __global__ __launch_bounds__(kBS) void k_decode_fine(DecPlan D) {
   const float *G1 = (L >= 1) ? D.gp[1] : nullptr;
   const int64_t *gd1 = D.gd[1];
   float *out = D.out;
+  // each block writes the points it owns -- or, in a restricted
+  // reconstruction, its whole closed extent (a neighbour owning the shared
+  // faces may be left out; both write identical values where both run)
+  const bool all = D.prune != 0;
   dec_tile(D, v, 0, o, s, t, 0u, 64u, [&](uint32_t z, uint32_t y, uint32_t x, float r) {
-    if (z >= ez || y >= ey) return;
+    if (!all && (z >= ez || y >= ey)) return;
     float *row = out + ((size_t)z * (uint32_t)n1 + y) * (uint32_t)n2;
-    if (x < ex) row[x] = r;
+    if (all || x < ex) row[x] = r;
     if (L >= 1 && !((z | y) & 1u) && (x & 1u)) {
       // even row of an even plane: the neighbouring even points come from level 1
       const float *g1 = G1 + ((size_t)(z >> 1) * (uint32_t)gd1[1] + (y >> 1)) * (uint32_t)gd1[2];
       row[x - 1] = g1[(x - 1) >> 1];
-      if (x + 1 == hi[2] && hi[2] == g.n[2] - 1) row[x + 1] = g1[(x + 1) >> 1];
+      if (x + 1 == hi[2] && (all || hi[2] == g.n[2] - 1)) row[x + 1] = g1[(x + 1) >> 1];
     }
   });
 }
@@ -235,6 +259,7 @@ __global__ __launch_bounds__(kBS) void k_decode_level(DecPlan D, int l) {
   const int L = g.nL - 1;
   uint32_t t, b;
   xcd_remap(t, b);
+  if (!block_needed(D, b)) return;
   const int wave = threadIdx.x / kWave;
   const BlockPos bp = block_pos(g, D.l0, b);
   const int64_t o[3] = {bp.o[0], bp.o[1], bp.o[2]}, hi[3] = {bp.hi[0], bp.hi[1], bp.hi[2]};
@@ -279,6 +304,7 @@ __global__ __launch_bounds__(kBS) void k_decode_l0(DecPlan D) {
   const Geo &g = D.g;
   uint32_t gxi, b;
   xcd_remap(gxi, b);
+  if (!block_needed(D, b)) return;
   const uint32_t cpw = (uint32_t)D.cpw0;
   const uint32_t cbeg = (gxi * kWaves + threadIdx.x / kWave) * cpw;  // first chunk of this wave
   const uint32_t t = cbeg >> 6, kbeg = cbeg & 63u;
@@ -296,6 +322,7 @@ __global__ __launch_bounds__(kBS) void k_decode_l0(DecPlan D) {
   const uint32_t oy = bp.o[1], ox = bp.o[2];
   const uint32_t ownz = bp.own[0] - bp.o[0], owny = bp.own[1], ownx = bp.own[2];
   const bool lastx = (bp.hi[2] == (uint32_t)g.n[2] - 1);
+  const bool all = D.prune != 0;
   float *__restrict__ ob = D.out + (size_t)bp.o[0] * n1 * n2;
   const uint32_t g0 = (uint32_t)D.gd[1][0], g1 = (uint32_t)D.gd[1][1], g2 = (uint32_t)D.gd[1][2];
   const uint32_t zg = bp.o[0] >> 1;
@@ -372,14 +399,17 @@ __global__ __launch_bounds__(kBS) void k_decode_l0(DecPlan D) {
       const int32_t q = (int32_t)(zc >> 1) ^ -(int32_t)(zc & 1u);
       r = lossless ? p : __fadd_rn(p, __fmul_rn((float)q, step));
     }
-    if (zz_ < ownz && y < owny) {
+    // the points the block owns -- or, in a restricted reconstruction, its
+    // whole closed extent (a neighbour owning the shared faces may be left
+    // out; both write identical values where both run)
+    if (all || (zz_ < ownz && y < owny)) {
       const uint32_t orow = (zz_ * n1 + y) * n2 * 4u;
-      if (x < ownx) stf(obase, orow + 4u * x, r);
+      if (all || x < ownx) stf(obase, orow + 4u * x, r);
       if (!((zz_ | y) & 1u) && (x & 1u)) {
         // even row of an even plane: the neighbouring even points come from
         // level 1 (they are this point's two x parents)
         stf(obase, orow + 4u * (x - 1), a0);
-        if (x + 1 == bp.hi[2] && lastx) stf(obase, orow + 4u * (x + 1), a1);
+        if (x + 1 == bp.hi[2] && (lastx || all)) stf(obase, orow + 4u * (x + 1), a1);
       }
     }
   }
@@ -390,6 +420,7 @@ __global__ __launch_bounds__(kBS) void k_decode_l0(DecPlan D) {
 __global__ __launch_bounds__(kBS) void k_decode_thin(DecPlan D) {
   const Geo &g = D.g;
   const int64_t b = blockIdx.x;
+  if (!block_needed(D, b)) return;
   int64_t o[3], hi[3];
   block_ext(g, b, o, hi);
   if (hi[2] != o[2]) return;
@@ -402,11 +433,45 @@ __global__ __launch_bounds__(kBS) void k_decode_thin(DecPlan D) {
 
 }  // namespace
 
+// Blocks left out of a restricted reconstruction: their owned points (the
+// closed extent minus the upper faces, which neighbours own) at the output
+// level get one value on the same side of every requested isovalue as the
+// whole block -- its min when min >= kmax (or the block is constant), else
+// its max.  Runs before the decoders, whose closed-extent writes then
+// restore the true values on faces shared with reconstructed blocks.
+__global__ __launch_bounds__(kBS) void k_prune_fill(DecPlan D) {
+  const Geo &g = D.g;
+  const int64_t b = blockIdx.y;
+  if (block_needed(D, b)) return;
+  float mn, mx;
+  block_range(D, b, mn, mx);
+  const float c = (mn >= D.kmax || mn == mx) ? mn : mx;
+  int64_t o[3], hi[3];
+  block_ext(g, b, o, hi);
+  const int lo = D.lo;
+  uint32_t lo3[3], hi3[3], dim[3];
+  for (int a = 0; a < 3; a++) {
+    const int64_t own = (hi[a] == g.n[a] - 1) ? g.n[a] : hi[a];  // exclusive end of the owned range
+    lo3[a] = (uint32_t)(o[a] >> lo);
+    hi3[a] = (uint32_t)((own + ((int64_t)1 << lo) - 1) >> lo);
+    dim[a] = (uint32_t)(lo == 0 ? g.n[a] : D.gd[lo][a]);
+  }
+  float *out = lo == 0 ? D.out : D.gp[lo];
+  const uint32_t cz = hi3[0] - lo3[0], cy = hi3[1] - lo3[1];
+  const int wave = threadIdx.x / kWave;
+  for (uint32_t r = blockIdx.x * kWaves + wave; r < cz * cy; r += gridDim.x * kWaves) {
+    const uint32_t z = lo3[0] + r / cy, y = lo3[1] + r % cy;
+    float *row = out + ((size_t)z * dim[1] + y) * dim[2];
+    for (uint32_t x = lo3[2] + lane_id(); x < hi3[2]; x += kWave) row[x] = c;
+  }
+}
+
 void launch_decode(const DecPlan &p, hipStream_t s) {
   const Geo &g = p.g;
   const int L = g.nL - 1;
   int64_t o[3], hi[3];
   block_ext(g, 0, o, hi);  // the first block is the largest
+  if (p.prune) k_prune_fill<<<dim3(8, (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
   if (L >= 3 && p.lo <= L) {
     prof_mark("k_decode_coarse", s, 0);
     k_decode_coarse<<<dim3((unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);

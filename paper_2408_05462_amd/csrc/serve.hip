@@ -234,6 +234,15 @@ int launch_group(chr_server *s, int j) {
   const int rc = dec_prepare(R.g, R.info.payload_offset, G.level, R.d, R.info.total_bytes, recon, status, dws,
                              dec_workspace_bytes(R.g, G.level), 16, dj);
   if (rc) return rc;
+  // only the blocks the group's isovalues need are reconstructed
+  float kmin = s->reqs[G.reqs[0]].k, kmax = kmin;
+  for (int64_t id : G.reqs) {
+    kmin = std::min(kmin, s->reqs[id].k);
+    kmax = std::max(kmax, s->reqs[id].k);
+  }
+  dj.D.prune = 1;
+  dj.D.kmin = kmin;
+  dj.D.kmax = kmax;
   launch_status_reset(status, hs);
   launch_decode(dj.D, hs);
   int64_t *pin = s->h_pinned + slot_pinned_words(s) * j;
