@@ -385,20 +385,14 @@ __global__ __launch_bounds__(kBS) void k_decode_l0(DecPlan D) {
     const float a0 = ldf(G1b, o00), a1 = ldf(G1b, o00 + dxo);
     const float b0 = ldf(G1b, o01), b1 = ldf(G1b, o01 + dxo), c0 = ldf(G1b, o10), c1 = ldf(G1b, o10 + dxo);
     const float d0 = ldf(G1b, o11), d1 = ldf(G1b, o11 + dxo);
-    float r;
-    if (ex) {
-      r = __uint_as_float(xv);
-    } else {
-      const float p = midpoint8(a0, a1, b0, b1, c0, c1, d0, d1, zu, yu, xu);
-      uint32_t zc = 0;
-      if (wk) {
-        zc = pw0 >> off;
-        if (off + wk > 32u) zc |= pw1 << (32u - off);
-        zc &= (1u << wk) - 1u;
-      }
-      const int32_t q = (int32_t)(zc >> 1) ^ -(int32_t)(zc & 1u);
-      r = lossless ? p : __fadd_rn(p, __fmul_rn((float)q, step));
-    }
+    // every point computes the prediction (keeps all loads above the
+    // selects, so the compiler does not sink them into a branch)
+    const float p = midpoint8(a0, a1, b0, b1, c0, c1, d0, d1, zu, yu, xu);
+    uint32_t zc = (off + wk > 32u) ? ((pw0 >> off) | (pw1 << (32u - off))) : (pw0 >> off);
+    zc = wk ? (zc & ((1u << wk) - 1u)) : 0u;
+    const int32_t q = (int32_t)(zc >> 1) ^ -(int32_t)(zc & 1u);
+    const float rq = lossless ? p : __fadd_rn(p, __fmul_rn((float)q, step));
+    const float r = ex ? __uint_as_float(xv) : rq;
     // the points the block owns -- or, in a restricted reconstruction, its
     // whole closed extent (a neighbour owning the shared faces may be left
     // out; both write identical values where both run)
