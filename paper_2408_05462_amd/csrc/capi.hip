@@ -18,7 +18,7 @@ thread_local std::string g_err;
 // Tile shapes of the level-0 kernels (work distribution only; results do not
 // depend on them).  Set by chr_set_tiles, or per batch by its autotuner.
 struct Tune {
-  int enc_cpw0 = 4;
+  int enc_cpw0 = 8;
   int dec_cpw0 = 16;
 } g_tune;
 

@@ -25,6 +25,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stdint.h>
 
 namespace chr {
@@ -164,6 +165,69 @@ __host__ __device__ inline void sec_point(const Sec &s, uint32_t j, uint32_t &w,
   }
 }
 
+// Division by a block-shape constant d without 32-bit multiplies: with r the
+// smallest binary32 value >= 1/d, trunc(fl(n * r)) equals floor(n / d) for
+// every n, d < 2^21.  (n * r exceeds n/d by at most n/d * 2^-23 and rounding
+// adds at most half an ulp of a value below 2^21/d + 1, so the result stays
+// below the next integer, whose distance from n/d is at least 1/d; it never
+// drops below floor(n/d), which is representable.)
+struct SecR {
+  float r_pair, r_rp, r_mx;  // reciprocals of Pe + Po, rowE + mx and mx
+};
+
+__host__ inline float rcp_up(uint32_t d) {
+  const double t = 1.0 / (double)d;
+  float r = (float)t;
+  if ((double)r < t) r = nextafterf(r, 3.0e38f);
+  return r;
+}
+
+__host__ inline SecR sec_rcp(const Sec &s) {
+  SecR r;
+  r.r_pair = rcp_up(s.Pe + s.Po);
+  r.r_rp = rcp_up(s.rowE + s.mx);
+  r.r_mx = rcp_up(s.mx);
+  return r;
+}
+
+__device__ inline uint32_t qdiv(uint32_t n, float r) { return (uint32_t)__fmul_rn((float)n, r); }
+
+// 24-bit multiplies (operands < 2^24, low 32 bits of the product) in one
+// full-rate instruction each; the compiler otherwise may fold the operand
+// masks of __umul24 away and emit a quarter-rate 32-bit multiply.  `s`: the
+// second operand is wave-uniform (a scalar register).
+__device__ inline uint32_t mad24s(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t r;
+  asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
+  return r;
+}
+__device__ inline uint32_t mul24s(uint32_t a, uint32_t b) {
+  uint32_t r;
+  asm("v_mul_u32_u24 %0, %1, %2" : "=v"(r) : "s"(b), "v"(a));
+  return r;
+}
+__device__ inline uint32_t mul24v(uint32_t a, uint32_t b) {
+  uint32_t r;
+  asm("v_mul_u32_u24 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
+// sec_point for a section below the top level with npts < 2^21: full-rate
+// arithmetic only (the reciprocal division above and 24-bit multiplies).
+__device__ inline void sec_point24(const Sec &s, const SecR &rc, uint32_t j, uint32_t &w, uint32_t &v,
+                                   uint32_t &u) {
+  const uint32_t w2 = qdiv(j, rc.r_pair);
+  const uint32_t r = j - mul24s(w2, s.Pe + s.Po);
+  const bool ev = r < s.Pe;  // even plane: rows alternate odd-u-only and full
+  const uint32_t n = ev ? r : r - s.Pe;
+  const uint32_t q = qdiv(n, ev ? rc.r_rp : rc.r_mx);
+  const uint32_t t = n - mul24v(q, ev ? s.rowE + s.mx : s.mx);
+  const bool odd_only = ev && t < s.rowE;
+  w = 2 * w2 + (ev ? 0u : 1u);
+  v = ev ? 2 * q + (odd_only ? 0u : 1u) : q;
+  u = odd_only ? 2 * t + 1 : (ev ? t - s.rowE : t);
+}
+
 __device__ inline float avg2(float a, float b) { return __fmul_rn(__fadd_rn(a, b), 0.5f); }
 
 // Multilinear midpoint from the coarser compact grid, given the parent rows
@@ -187,6 +251,12 @@ __device__ inline float midpoint_rows(const float *__restrict__ r00, const float
   return midpoint8(r00[xa], r00[xb], r01[xa], r01[xb], r10[xa], r10[xb], r11[xa], r11[xb], zu, yu, xu);
 }
 
+// Holds a value in a register at this point of the program: the arithmetic
+// that produces it stays above, instead of being moved into the branch that
+// uses it (so every load it reads is waited for before any later store).
+__device__ inline void hold(float &v) { asm volatile("" : "+v"(v)); }
+__device__ inline void hold(uint32_t &v) { asm volatile("" : "+v"(v)); }
+
 // Load of a float at a 32-bit byte offset from a uniform base (lets the
 // compiler use the scalar-base + 32-bit vector-offset addressing form).
 __device__ inline float ldf(const char *__restrict__ base, uint32_t off) {
@@ -205,8 +275,11 @@ __device__ inline void stf(char *__restrict__ base, uint32_t off, float v) {
 struct L0Geo {
   Sec sec[8];    // level 0
   Sec sec1[8];   // level 1 (when the hierarchy has one)
+  SecR rc[8];    // level-0 reciprocals (valid when small)
   FastDiv d_nb2, d_nb1;
   uint32_t nb[3];
+  int small;     // every level-0 section has < 2^21 points and the index
+                 // products of the level-0 kernels stay below 2^24
 };
 
 __host__ inline void make_l0geo(const Geo &g, L0Geo &G) {
@@ -219,7 +292,16 @@ __host__ inline void make_l0geo(const Geo &g, L0Geo &G) {
     block_ext(g, (bz * g.nb[1] + by) * g.nb[2] + bx, o, hi);
     G.sec[cls] = sec_geom(o, hi, 0, g.nL - 1);
     G.sec1[cls] = sec_geom(o, hi, g.nL >= 2 ? 1 : 0, g.nL - 1);
+    G.rc[cls] = sec_rcp(G.sec[cls]);
   }
+  // row products w * n1 + y and plane offsets of the field and of the
+  // level-1 grid within a block's slab, as 24-bit multiplier operands
+  const int64_t lim = (int64_t)1 << 21, lim24 = (int64_t)1 << 24;
+  int64_t maxpts = 0;
+  for (int cls = 0; cls < 8; cls++) maxpts = maxpts > G.sec[cls].npts ? maxpts : G.sec[cls].npts;
+  const int64_t n1 = g.n[1], n2 = g.n[2], g1 = (n1 + 1) / 2, g2 = (n2 + 1) / 2;
+  G.small = maxpts < lim && (int64_t)(g.B + 1) * n1 < lim24 && n2 < lim24 &&
+            (int64_t)(g.B / 2 + 2) * g1 < lim24 && g2 < lim24 && g.B + 1 < lim;
 }
 
 // Block b's origin, closed-extent end, first non-owned coordinate and shape class.
@@ -344,6 +426,9 @@ __device__ inline uint32_t wave_or_dpp(uint32_t v) { return wave_reduce_dpp(v, O
 __device__ inline uint32_t wave_min_dpp(uint32_t v) { return wave_reduce_dpp(v, OpMin(), 0xffffffffu); }
 __device__ inline uint32_t wave_max_dpp(uint32_t v) { return wave_reduce_dpp(v, OpMax(), 0u); }
 __device__ inline uint32_t wave_sum_dpp(uint32_t v) { return wave_reduce_dpp(v, OpAdd(), 0u); }
+
+// Index of this wave in its workgroup, as a wave-uniform (scalar) value.
+__device__ inline uint32_t wave_index() { return __builtin_amdgcn_readfirstlane(threadIdx.x / kWave); }
 
 // number of set bits of m below this lane
 __device__ inline uint32_t lanes_below(uint64_t m) {

@@ -108,4 +108,8 @@ int launch_topology(const float *f, const int64_t dims[3], const float *iso, int
                     void *ws, hipStream_t s);
 void mc_table_host(uint8_t *ntri, int8_t *tri);
 
+// plans travel as kernel arguments (at most 4 KiB)
+static_assert(sizeof(EncPlan) <= 4096 && sizeof(DecPlan) <= 4096 && sizeof(McPlan) <= 4096,
+              "a plan must fit the kernel argument space");
+
 }  // namespace chr

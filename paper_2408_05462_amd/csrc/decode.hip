@@ -17,6 +17,7 @@ namespace {
 
 constexpr int kBS = 256;
 constexpr int kWaves = kBS / kWave;
+constexpr int kDecGroup = 2;  // level-0 decoder: chunks whose loads a wave issues together
 
 // Same prediction as compression (multilinear midpoints from the coarser
 // compact grid of dims g0 x g1 x g2, x then y then z, lower parent alone at
@@ -306,7 +307,7 @@ __global__ __launch_bounds__(kBS) void k_decode_l0(DecPlan D) {
   xcd_remap(gxi, b);
   if (!block_needed(D, b)) return;
   const uint32_t cpw = (uint32_t)D.cpw0;
-  const uint32_t cbeg = (gxi * kWaves + threadIdx.x / kWave) * cpw;  // first chunk of this wave
+  const uint32_t cbeg = (gxi * kWaves + wave_index()) * cpw;  // first chunk of this wave
   const uint32_t t = cbeg >> 6, kbeg = cbeg & 63u;
   const int lane = lane_id();
   const BlockPos bp = block_pos(g, D.l0, b);
@@ -355,55 +356,89 @@ __global__ __launch_bounds__(kBS) void k_decode_l0(DecPlan D) {
   const uint32_t nc = min(min(64u, v.nch - t * 64), kbeg + cpw);
   const char *__restrict__ payb = reinterpret_cast<const char *>(v.p + v.Poff);
   const char *__restrict__ exvb = reinterpret_cast<const char *>(v.p + v.Xoff);
+  const SecR rc = D.l0.rc[bp.cls];
+  const uint32_t jmax = s.npts - 1;  // npts > 0: this wave's tile holds a chunk
+  const uint32_t hi2 = bp.hi[2];
+  // kDecGroup chunks at a time: coordinates and addresses of all of them,
+  // then every load (the eight parents of each point, payload words, exact
+  // values), then every value is computed before any store, so no load is
+  // left pending on a path and no store sits between a load and its use.  A
+  // chunk past the wave's range repeats the last one and lanes past the
+  // section read a clamped point; neither is written.
 #pragma unroll 1
-  for (uint32_t k = kbeg; k < nc; k++) {
-    const uint32_t wk = rl32(w, (int)k), wok = rl32(wo, (int)k), xok = rl32(xo, (int)k);
-    const uint64_t emk = rl64(em, (int)k);
-    const uint32_t j = (t * 64 + k) * 64 + (uint32_t)lane;
-    if (j >= s.npts) continue;
-    uint32_t zz_, vv, uu;
-    sec_point(s, j, zz_, vv, uu);
-    const uint32_t y = oy + vv, x = ox + uu;
-    const uint32_t zl = zz_ >> 1, yl = y >> 1, xl = x >> 1;
-    const uint32_t pz = zz_ & 1u, py = y & 1u, px = x & 1u;
-    const bool zu = pz && (zg + zl + 1 < g0), yu = py && (yl + 1 < g1), xu = px && (xl + 1 < g2);
-    // every load of this point is issued before any is used: payload words,
-    // the exact value, the eight parents
-    uint32_t pw0 = 0, pw1 = 0;
-    const uint32_t bit = (uint32_t)lane * wk, off = bit & 31u;
-    if (wk) {
-      const uint32_t wb = 8u * wok + 4u * (bit >> 5);
-      pw0 = ldu(payb, wb);
-      pw1 = ldu(payb, wb + ((off + wk > 32u) ? 4u : 0u));
+  for (uint32_t k0 = kbeg; k0 < nc; k0 += kDecGroup) {
+    float pa[kDecGroup][8], r[kDecGroup];
+    uint32_t pw0[kDecGroup], pw1[kDecGroup], xv[kDecGroup], orow[kDecGroup], xs[kDecGroup], off[kDecGroup];
+    bool zu[kDecGroup], yu[kDecGroup], xu[kDecGroup], ex[kDecGroup], wr[kDecGroup], wx[kDecGroup], ev[kDecGroup],
+        e1[kDecGroup];
+#pragma unroll
+    for (int u = 0; u < kDecGroup; u++) {
+      const uint32_t k = min(k0 + (uint32_t)u, nc - 1);
+      const uint32_t wk = rl32(w, (int)k), wok = rl32(wo, (int)k), xok = rl32(xo, (int)k);
+      const uint64_t emk = rl64(em, (int)k);
+      const uint32_t jr = (t * 64 + k) * 64 + (uint32_t)lane;
+      uint32_t zz_, vv, uu;
+      sec_point24(s, rc, min(jr, jmax), zz_, vv, uu);
+      const uint32_t y = oy + vv, x = ox + uu;
+      const uint32_t zl = zz_ >> 1, yl = y >> 1, xl = x >> 1;
+      zu[u] = (zz_ & 1u) && (zg + zl + 1 < g0);
+      yu[u] = (y & 1u) && (yl + 1 < g1);
+      xu[u] = (x & 1u) && (xl + 1 < g2);
+      const uint32_t o00 = mad24s(mad24s(zl, g1, yl), g2, xl) * 4u;
+      const uint32_t dxo = xu[u] ? 4u : 0u, dyo = yu[u] ? g2x4 : 0u, dzo = zu[u] ? g12x4 : 0u;
+      const uint32_t o01 = o00 + dyo, o10 = o00 + dzo, o11 = o10 + dyo;
+      pa[u][0] = ldf(G1b, o00); pa[u][1] = ldf(G1b, o00 + dxo);
+      pa[u][2] = ldf(G1b, o01); pa[u][3] = ldf(G1b, o01 + dxo);
+      pa[u][4] = ldf(G1b, o10); pa[u][5] = ldf(G1b, o10 + dxo);
+      pa[u][6] = ldf(G1b, o11); pa[u][7] = ldf(G1b, o11 + dxo);
+      const uint32_t bit = mul24s((uint32_t)lane, wk);
+      off[u] = bit & 31u;
+      pw0[u] = 0u;
+      pw1[u] = 0u;
+      if (wk) {
+        const uint32_t wb = 8u * wok + 4u * (bit >> 5);
+        pw0[u] = ldu(payb, wb);
+        pw1[u] = ldu(payb, wb + ((off[u] + wk > 32u) ? 4u : 0u));
+      }
+      ex[u] = (emk >> lane) & 1ull;
+      xv[u] = 0u;
+      if (ex[u]) xv[u] = ldu(exvb, 4u * (xok + lanes_below(emk)));
+      // the points the block owns -- or, in a restricted reconstruction, its
+      // whole closed extent (a neighbour owning the shared faces may be left
+      // out; both write identical values where both run)
+      const bool valid = (k0 + (uint32_t)u < nc) && (jr < s.npts);
+      wr[u] = valid && (all || (zz_ < ownz && y < owny));
+      wx[u] = all || x < ownx;
+      // even row of an even plane: the neighbouring even points come from
+      // level 1 (they are this point's two x parents)
+      ev[u] = !((zz_ | y) & 1u) && (x & 1u);
+      e1[u] = x + 1 == hi2 && (lastx || all);
+      orow[u] = mul24s(mad24s(zz_, n1, y), n2) * 4u;
+      xs[u] = x;
     }
-    const bool ex = (emk >> lane) & 1ull;
-    uint32_t xv = 0;
-    if (ex) xv = ldu(exvb, 4u * (xok + lanes_below(emk)));
-    const uint32_t o00 = ((zl * g1 + yl) * g2 + xl) * 4u;
-    const uint32_t dxo = xu ? 4u : 0u, dyo = yu ? g2x4 : 0u, dzo = zu ? g12x4 : 0u;
-    const uint32_t o01 = o00 + dyo, o10 = o00 + dzo, o11 = o10 + dyo;
-    const float a0 = ldf(G1b, o00), a1 = ldf(G1b, o00 + dxo);
-    const float b0 = ldf(G1b, o01), b1 = ldf(G1b, o01 + dxo), c0 = ldf(G1b, o10), c1 = ldf(G1b, o10 + dxo);
-    const float d0 = ldf(G1b, o11), d1 = ldf(G1b, o11 + dxo);
-    // every point computes the prediction (keeps all loads above the
-    // selects, so the compiler does not sink them into a branch)
-    const float p = midpoint8(a0, a1, b0, b1, c0, c1, d0, d1, zu, yu, xu);
-    uint32_t zc = (off + wk > 32u) ? ((pw0 >> off) | (pw1 << (32u - off))) : (pw0 >> off);
-    zc = wk ? (zc & ((1u << wk) - 1u)) : 0u;
-    const int32_t q = (int32_t)(zc >> 1) ^ -(int32_t)(zc & 1u);
-    const float rq = lossless ? p : __fadd_rn(p, __fmul_rn((float)q, step));
-    const float r = ex ? __uint_as_float(xv) : rq;
-    // the points the block owns -- or, in a restricted reconstruction, its
-    // whole closed extent (a neighbour owning the shared faces may be left
-    // out; both write identical values where both run)
-    if (all || (zz_ < ownz && y < owny)) {
-      const uint32_t orow = (zz_ * n1 + y) * n2 * 4u;
-      if (all || x < ownx) stf(obase, orow + 4u * x, r);
-      if (!((zz_ | y) & 1u) && (x & 1u)) {
-        // even row of an even plane: the neighbouring even points come from
-        // level 1 (they are this point's two x parents)
-        stf(obase, orow + 4u * (x - 1), a0);
-        if (x + 1 == bp.hi[2] && (lastx || all)) stf(obase, orow + 4u * (x + 1), a1);
+#pragma unroll
+    for (int u = 0; u < kDecGroup; u++) {
+      const uint32_t wk = rl32(w, (int)min(k0 + (uint32_t)u, nc - 1));
+      const float p = midpoint8(pa[u][0], pa[u][1], pa[u][2], pa[u][3], pa[u][4], pa[u][5], pa[u][6], pa[u][7],
+                                zu[u], yu[u], xu[u]);
+      const uint32_t o = off[u];
+      uint32_t zc = (o + wk > 32u) ? ((pw0[u] >> o) | (pw1[u] << (32u - o))) : (pw0[u] >> o);
+      zc = wk ? (zc & ((1u << wk) - 1u)) : 0u;
+      const int32_t q = (int32_t)(zc >> 1) ^ -(int32_t)(zc & 1u);
+      const float rq = lossless ? p : __fadd_rn(p, __fmul_rn((float)q, step));
+      r[u] = ex[u] ? __uint_as_float(xv[u]) : rq;
+      hold(r[u]);
+      hold(pa[u][0]);
+      hold(pa[u][1]);
+    }
+#pragma unroll
+    for (int u = 0; u < kDecGroup; u++) {
+      if (!wr[u]) continue;
+      const uint32_t ro = orow[u] + 4u * xs[u];
+      if (wx[u]) stf(obase, ro, r[u]);
+      if (ev[u]) {
+        stf(obase, ro - 4u, pa[u][0]);
+        if (e1[u]) stf(obase, ro + 4u, pa[u][1]);
       }
     }
   }
@@ -485,7 +520,7 @@ void launch_decode(const DecPlan &p, hipStream_t s) {
     const int64_t ntile = ceil_div(ceil_div(s0.npts, 64), 64);
     const bool slab32 = 4.0 * (double)(hi[0] - o[0] + 1) * (double)g.n[1] * (double)g.n[2] < 4294967296.0;
     prof_mark("k_decode_fine", s, 0);
-    if (L >= 1 && slab32) {
+    if (L >= 1 && slab32 && p.l0.small) {
       const int64_t nch0 = ceil_div(s0.npts, 64);
       const int64_t gx0 = ceil_div(nch0 > 0 ? nch0 : 1, (int64_t)kWaves * p.cpw0);
       k_decode_l0<<<dim3((unsigned)gx0, (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);

@@ -320,13 +320,15 @@ __device__ inline void pack_chunk(const EncPlan &P, int64_t slot, uint32_t zz, b
 // enc_chunk with the level fixed at 0, block-relative 32-bit offsets from
 // uniform base pointers (the block's first plane of the field and of the
 // level-1 grid), and the optional per-point outputs compiled in only when
-// requested.
-template <bool AUX, int KB>
+// requested.  G chunks at a time: the loads of all of them are issued before
+// any is used, so a wave keeps several chunks' reads in flight (G divides the
+// chunks per wave).
+template <bool AUX, int KB, int G>
 __global__ __launch_bounds__(kBS) void k_encode_l0(EncPlan P) {
   __shared__ uint32_t pack[kWaves][32];
   uint32_t gxi, b;
   xcd_remap(gxi, b);
-  const int wave = threadIdx.x / kWave;
+  const uint32_t wave = wave_index();
   const int lane = lane_id();
   // Every uniform value the loop needs is copied into a local first, so it
   // stays in scalar registers across the loop's stores.
@@ -360,75 +362,108 @@ __global__ __launch_bounds__(kBS) void k_encode_l0(EncPlan P) {
   Part acc;
   part_init(acc);
   const int cpw = P.cpw0;
+  const uint32_t jmax = s.npts ? s.npts - 1 : 0u;
+  const SecR rc = P.l0.rc[bp.cls];
+  // lanes past the section (and chunks past it) read a clamped point and
+  // discard it
 #pragma unroll 1
-  for (int k = 0; k < cpw; k++) {
-    const uint32_t c = (gxi * cpw + k) * kWaves + wave;
-    if (c >= maxch) break;
-    const int64_t slot = slot0 + c;
-    if (c >= nch) {
-      if (lane == 0) cnt[slot] = U4{0, 0, 0, 0};
-      continue;
-    }
-    const uint32_t j = c * kWave + (uint32_t)lane;
-    float x = 0.f;
-    uint32_t zz = 0;
-    bool E = false;
-    if (j < s.npts) {
-      uint32_t w, v, u;
-      sec_point(s, j, w, v, u);
-      const uint32_t y = oy + v, xx = ox + u;
-      x = ldf(xbase, ((w * n1 + y) * n2 + xx) * 4u);
-      const uint32_t pz = w & 1u, py = y & 1u, px = xx & 1u;
+  for (int k0 = 0; k0 < cpw; k0 += G) {
+    float xs[G], pa[G][8];
+    bool zu[G], yu[G], xu[G], in[G], own[G];
+    uint32_t gi[G];
+#pragma unroll
+    for (int u = 0; u < G; u++) {
+      const uint32_t c = (gxi * cpw + k0 + u) * kWaves + wave;
+      const uint32_t jr = c * kWave + (uint32_t)lane;
+      uint32_t w, v, uu;
+      sec_point24(s, rc, min(jr, jmax), w, v, uu);
+      const uint32_t y = oy + v, xx = ox + uu;
+      const uint32_t prow = mad24s(w, n1, y);
+      xs[u] = ldf(xbase, mad24s(prow, n2, xx) * 4u);
       const uint32_t zl = w >> 1, yl = y >> 1, xl = xx >> 1;
-      const bool zu = pz && (zg + zl + 1 < g0), yu = py && (yl + 1 < g1), xu = px && (xl + 1 < g2);
+      zu[u] = (w & 1u) && (zg + zl + 1 < g0);
+      yu[u] = (y & 1u) && (yl + 1 < g1);
+      xu[u] = (xx & 1u) && (xl + 1 < g2);
       // byte offsets of the eight parents in the block's slab of the level-1 grid
-      const uint32_t o00 = ((zl * g1 + yl) * g2 + xl) * 4u;
-      const uint32_t dxo = xu ? 4u : 0u, dyo = yu ? g2x4 : 0u, dzo = zu ? g12x4 : 0u;
+      const uint32_t o00 = mad24s(mad24s(zl, g1, yl), g2, xl) * 4u;
+      const uint32_t dxo = xu[u] ? 4u : 0u, dyo = yu[u] ? g2x4 : 0u, dzo = zu[u] ? g12x4 : 0u;
       const uint32_t o01 = o00 + dyo, o10 = o00 + dzo, o11 = o10 + dyo;
-      const float p = midpoint8(ldf(G1b, o00), ldf(G1b, o00 + dxo), ldf(G1b, o01), ldf(G1b, o01 + dxo),
-                                ldf(G1b, o10), ldf(G1b, o10 + dxo), ldf(G1b, o11), ldf(G1b, o11 + dxo), zu, yu, xu);
+      pa[u][0] = ldf(G1b, o00); pa[u][1] = ldf(G1b, o00 + dxo);
+      pa[u][2] = ldf(G1b, o01); pa[u][3] = ldf(G1b, o01 + dxo);
+      pa[u][4] = ldf(G1b, o10); pa[u][5] = ldf(G1b, o10 + dxo);
+      pa[u][6] = ldf(G1b, o11); pa[u][7] = ldf(G1b, o11 + dxo);
+      in[u] = jr < s.npts;
+      own[u] = w < ownz && y < owny && xx < ownx;
+      gi[u] = AUX ? mad24s(prow, n2, xx) : 0u;  // offset of the point in the block's slab
+    }
+    // every point's arithmetic before any branch, so every load is consumed
+    // on every path (lanes past the section compute on their clamped point
+    // and are masked)
+    uint32_t zzs[G];
+    bool Es[G];
+#pragma unroll
+    for (int u = 0; u < G; u++) {
+      const float x = xs[u];
+      const float p = midpoint8(pa[u][0], pa[u][1], pa[u][2], pa[u][3], pa[u][4], pa[u][5], pa[u][6], pa[u][7],
+                                zu[u], yu[u], xu[u]);
       int32_t q;
       int O, C = 0;
       float xr;
       quantize(gq, x, p, q, O, xr);
       if (!O && K > 0) C = rank_of<KB>(iso, K, x) != rank_of<KB>(iso, K, xr);
       if (O || C) { xr = x; q = 0; }
-      E = O || C;
-      zz = ((uint32_t)q << 1) ^ (uint32_t)(q >> 31);
-      const uint32_t ro = ord_of(xr), xo = ord_of(x);
-      acc.rmin = min(acc.rmin, ro); acc.rmax = max(acc.rmax, ro);
-      acc.xmin = min(acc.xmin, xo); acc.xmax = max(acc.xmax, xo);
-      acc.nonfinite |= !isfinite(x);
-      if (w < ownz && y < owny && xx < ownx) { acc.nO += O; acc.nC += C; }
-      if (AUX) {
-        const size_t gi = ((size_t)(bp.o[0] + w) * n1 + y) * n2 + xx;
-        if (codes) codes[gi] = q;
-        if (flags) flags[gi] = (uint8_t)(O | (C << 1));
+      zzs[u] = in[u] ? (((uint32_t)q << 1) ^ (uint32_t)(q >> 31)) : 0u;
+      Es[u] = in[u] && (O || C);
+      if (in[u]) {
+        const uint32_t ro = ord_of(xr), xo = ord_of(x);
+        acc.rmin = min(acc.rmin, ro); acc.rmax = max(acc.rmax, ro);
+        acc.xmin = min(acc.xmin, xo); acc.xmax = max(acc.xmax, xo);
+        acc.nonfinite |= !isfinite(x);
+        if (own[u]) { acc.nO += O; acc.nC += C; }
+        if (AUX) {
+          const size_t gidx = (size_t)bp.o[0] * n1 * n2 + gi[u];
+          if (codes) codes[gidx] = q;
+          if (flags) flags[gidx] = (uint8_t)(O | (C << 1));
+        }
       }
+      hold(zzs[u]);
     }
-    // pack the codes at bit lane*wb through LDS
-    uint32_t *pk = pack[wave];
-    const uint32_t orv = wave_or_dpp(zz);
-    const int wb = orv ? 32 - __clz((int)orv) : 0;
-    const unsigned long long em = __ballot(E);
-    if (lane < 32) pk[lane] = 0u;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    if (zz) {
-      const uint32_t bit = (uint32_t)lane * (uint32_t)wb, wi = bit >> 5, off = bit & 31u;
-      __hip_atomic_fetch_or(&pk[wi], zz << off, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-      if (off + (uint32_t)wb > 32u)
-        __hip_atomic_fetch_or(&pk[wi + 1], zz >> (32u - off), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+#pragma unroll
+    for (int u = 0; u < G; u++) {
+      const uint32_t c = (gxi * cpw + k0 + u) * kWaves + wave;
+      if (c >= maxch) break;
+      const int64_t slot = slot0 + c;
+      if (c >= nch) {
+        if (lane == 0) cnt[slot] = U4{0, 0, 0, 0};
+        continue;
+      }
+      const float x = xs[u];
+      const uint32_t zz = zzs[u];
+      const bool E = Es[u];
+      // pack the codes at bit lane*wb through LDS
+      uint32_t *pk = pack[wave];
+      const uint32_t orv = wave_or_dpp(zz);
+      const int wb = orv ? 32 - __clz((int)orv) : 0;
+      const unsigned long long em = __ballot(E);
+      if (lane < 32) pk[lane] = 0u;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      if (zz) {
+        const uint32_t bit = (uint32_t)lane * (uint32_t)wb, wi = bit >> 5, off = bit & 31u;
+        __hip_atomic_fetch_or(&pk[wi], zz << off, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        if (off + (uint32_t)wb > 32u)
+          __hip_atomic_fetch_or(&pk[wi + 1], zz >> (32u - off), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      if (lane < 2 * wb) pay[slot * 32 + lane] = pk[lane];
+      if (E) exv[slot * 64 + lanes_below(em)] = x;
+      if (lane == 0) {
+        cnt[slot] = U4{(uint32_t)wb, em ? 1u : 0u, (uint32_t)__popcll(em), 0u};
+        if (em) emask[slot] = em;
+      }
+      __builtin_amdgcn_wave_barrier();
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    if (lane < 2 * wb) pay[slot * 32 + lane] = pk[lane];
-    if (E) exv[slot * 64 + lanes_below(em)] = x;
-    if (lane == 0) {
-      cnt[slot] = U4{(uint32_t)wb, em ? 1u : 0u, (uint32_t)__popcll(em), 0u};
-      if (em) emask[slot] = em;
-    }
-    __builtin_amdgcn_wave_barrier();
   }
   part_store(acc, &P.part[(int64_t)b * P.part_per_block + gxi]);
 }
@@ -888,10 +923,17 @@ void launch_encode_levels(const EncPlan &p, hipStream_t s) {
     block_ext(g, 0, o, hi);
     const bool slab32 = 4.0 * (double)(hi[0] - o[0] + 1) * (double)g.n[1] * (double)g.n[2] < 4294967296.0;
     prof_mark("k_encode_fine", s, 0);
-    if (L >= 1 && slab32 && !p.codes && !p.flags)
-      k_encode_l0<false, KB><<<dim3((unsigned)gx, (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
-    else if (L >= 1 && slab32)
-      k_encode_l0<true, KB><<<dim3((unsigned)gx, (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
+    const dim3 grid0((unsigned)gx, (unsigned)g.nblocks);
+    // the specialized kernel: 32-bit offsets within a block's slab and the
+    // full-rate index arithmetic of small block shapes
+    const bool fast = L >= 1 && slab32 && p.l0.small;
+    if (fast && !p.codes && !p.flags) {
+      if (p.cpw0 % 4 == 0) k_encode_l0<false, KB, 4><<<grid0, dim3(kBS), 0, s>>>(p);
+      else if (p.cpw0 % 2 == 0) k_encode_l0<false, KB, 2><<<grid0, dim3(kBS), 0, s>>>(p);
+      else k_encode_l0<false, KB, 1><<<grid0, dim3(kBS), 0, s>>>(p);
+    } else if (fast) {
+      k_encode_l0<true, KB, 1><<<grid0, dim3(kBS), 0, s>>>(p);
+    }
     else
       k_encode_fine<KB><<<dim3((unsigned)gx, (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
     prof_mark("k_encode_fine", s, 1);
@@ -900,7 +942,6 @@ void launch_encode_levels(const EncPlan &p, hipStream_t s) {
 
 void launch_encode(const EncPlan &p, int64_t, U4 *scan_tmp, uint64_t *scan_tmp64, hipStream_t s) {
   const Geo &g = p.g;
-  const int L = g.nL - 1;
   const int64_t nsec = g.nblocks * g.nL;
   if (g.K <= 1) launch_encode_levels<1>(p, s);
   else if (g.K <= 2) launch_encode_levels<2>(p, s);

@@ -145,4 +145,4 @@ def test_tiles_do_not_change_results(data):
             y = api.reconstruct(c, 0).cpu().numpy()
             assert np.array_equal(y.view(np.uint32), y_ref.view(np.uint32)), dc
     finally:
-        api.chr_set_tiles(4, 16)
+        api.chr_set_tiles(8, 16)

@@ -114,7 +114,7 @@ def test_set_tiles_validates():
     for e in (1, 2, 4, 8, 16):
         for d in (8, 16, 32, 64):
             assert lib.chr_set_tiles(e, d) == L.CHR_OK
-    assert lib.chr_set_tiles(4, 16) == L.CHR_OK
+    assert lib.chr_set_tiles(8, 16) == L.CHR_OK  # the defaults
 
 
 def _items(shapes, n_iso=2, fake=0x100000):
