@@ -52,6 +52,7 @@ def parse_args():
     ap.add_argument("--slots", type=int, default=4, help="serve1024: server slots")
     ap.add_argument("--group", type=int, default=8, help="serve1024: requests per shared reconstruction")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-latency part of the default run")
+    ap.add_argument("--no-topology", action="store_true", help="skip the error-translation part of the default run")
     ap.add_argument("--serve-requests", type=int, default=200, help="requests of the default run's served part")
     ap.add_argument("--batch-items", type=int, default=64, help="batch64: number of timesteps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -560,7 +561,7 @@ def main():
     tws = torch.empty(lib.chr_topology_workspace(), dtype=torch.uint8, device=dev)
     tout = torch.zeros(2, dtype=torch.float64, device=dev)
     topo = {}
-    for label, nth_of in (("min", lambda m: 1), ("p99", lambda m: max(1, -(-m // 100)))):
+    for label, nth_of in () if args.no_topology else (("min", lambda m: 1), ("p99", lambda m: max(1, -(-m // 100)))):
         api.chr_topology_error_bound(x, isos, 1, tout, tws)
         torch.cuda.synchronize()
         m = int(tout[1].item())
@@ -572,7 +573,7 @@ def main():
         e1.record(stream)
         torch.cuda.synchronize()
         topo[label] = {"nth": nth, "bound": float(tout[0].item()), "ms": round(e0.elapsed_time(e1) / 3, 4)}
-    topo["n_D"] = m
+        topo["n_D"] = m
 
     # served latency on the same field (the metric's second half): requests
     # at random isovalues and accuracy tiers, continuous-batching server vs
@@ -622,7 +623,7 @@ def main():
                        "mc_per_isovalue": round(4.0 * N * len(isos) / stage_ms[2] / 1e6, 1)},
         "compression_ratio": round(cr, 3), "stream_bytes": nbytes, "n_outlier": r["n_outlier"],
         "n_corrected": r["n_corrected"], "triangles": [int(c[1]) for c in cnt],
-        "wall_s_timed": round(wall, 3), "served": served, "topology_error_bound": topo, "roofline": roofline,
+        "wall_s_timed": round(wall, 3), "served": served, "topology_error_bound": topo or None, "roofline": roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

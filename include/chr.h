@@ -272,7 +272,8 @@ typedef struct chr_batch chr_batch;
 
 /* Plans a batch (host only, no device call; items are copied).  Items are
  * spread over up to min(8, n_items) parallel branches, longest first onto
- * the least-loaded branch.  Errors: CHR_E_INVAL (bad parameters, NULL
+ * the least-loaded branch; level-0 tiles are those of chr_set_tiles at
+ * creation.  Errors: CHR_E_INVAL (bad parameters, NULL
  * pointer, bad mesh capacity; chr_last_error names the item),
  * CHR_E_CAPACITY (stream capacity below the header and tables). */
 int chr_batch_create(const chr_batch_item *items, int n_items, chr_batch **out);

@@ -50,7 +50,7 @@ struct chr_batch {
   size_t ws_branch = 0;     // workspace bytes of one branch
   int max_branches = 1;
   int branches = 1;
-  int enc_cpw = 4, dec_cpw = 16;
+  int enc_cpw = 8, dec_cpw = 16;  // the process-wide tiles when created
   float last_ms = 0.f;
   std::vector<hipStream_t> streams;
   hipStream_t origin = nullptr;   // capture origin (the caller's stream may be the null stream)
@@ -246,6 +246,7 @@ int chr_batch_create(const chr_batch_item *items, int n_items, chr_batch **out) 
   if (!out || !items || n_items < 1) return api_fail(CHR_E_INVAL, "need at least one item and an output pointer");
   *out = nullptr;
   chr_batch *b = new chr_batch;
+  current_tiles(b->enc_cpw, b->dec_cpw);
   b->items.assign(items, items + n_items);
   b->geo.resize(n_items);
   b->payload_off.resize(n_items);

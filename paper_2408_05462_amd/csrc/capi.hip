@@ -212,6 +212,11 @@ struct Prof {
 namespace chr {
 int api_fail(int code, const std::string &msg) { return fail(code, msg); }
 int api_check_launch(const char *what) { return check_hip(what); }
+void current_tiles(int &enc_cpw, int &dec_cpw) {
+  enc_cpw = g_tune.enc_cpw0;
+  dec_cpw = g_tune.dec_cpw0;
+}
+
 bool tiles_ok(int enc_cpw, int dec_cpw) {
   const bool e = enc_cpw == 1 || enc_cpw == 2 || enc_cpw == 4 || enc_cpw == 8 || enc_cpw == 16;
   const bool d = dec_cpw == 8 || dec_cpw == 16 || dec_cpw == 32 || dec_cpw == 64;

@@ -53,6 +53,8 @@ int enc_geometry(const int64_t dims[3], double error_bound, const float *h_iso, 
                  Geo &g, uint64_t &payload_off);
 
 bool tiles_ok(int enc_cpw, int dec_cpw);
+// The process-wide level-0 tiles (chr_set_tiles).
+void current_tiles(int &enc_cpw, int &dec_cpw);
 
 // Geometry of a stream from its parsed header (parameters, quantizer
 // constants and lossless flag checked against each other).

@@ -276,6 +276,7 @@ struct L0Geo {
   Sec sec[8];    // level 0
   Sec sec1[8];   // level 1 (when the hierarchy has one)
   SecR rc[8];    // level-0 reciprocals (valid when small)
+  SecR rc1[8];   // level-1 reciprocals
   FastDiv d_nb2, d_nb1;
   uint32_t nb[3];
   int small;     // every level-0 section has < 2^21 points and the index
@@ -293,6 +294,7 @@ __host__ inline void make_l0geo(const Geo &g, L0Geo &G) {
     G.sec[cls] = sec_geom(o, hi, 0, g.nL - 1);
     G.sec1[cls] = sec_geom(o, hi, g.nL >= 2 ? 1 : 0, g.nL - 1);
     G.rc[cls] = sec_rcp(G.sec[cls]);
+    G.rc1[cls] = sec_rcp(G.sec1[cls]);
   }
   // row products w * n1 + y and plane offsets of the field and of the
   // level-1 grid within a block's slab, as 24-bit multiplier operands

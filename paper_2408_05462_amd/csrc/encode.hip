@@ -316,85 +316,97 @@ __device__ inline void pack_chunk(const EncPlan &P, int64_t slot, uint32_t zz, b
   __builtin_amdgcn_wave_barrier();
 }
 
-// Level 0 below a coarser level (nL >= 2): the same arithmetic as
-// enc_chunk with the level fixed at 0, block-relative 32-bit offsets from
-// uniform base pointers (the block's first plane of the field and of the
-// level-1 grid), and the optional per-point outputs compiled in only when
-// requested.  G chunks at a time: the loads of all of them are issued before
-// any is used, so a wave keeps several chunks' reads in flight (G divides the
-// chunks per wave).
-template <bool AUX, int KB, int G>
-__global__ __launch_bounds__(kBS) void k_encode_l0(EncPlan P) {
-  __shared__ uint32_t pack[kWaves][32];
+// Levels 0 and 1 below a coarser level (level LV + 1 exists): the
+// arithmetic of enc_chunk with the level fixed, for block shapes whose index
+// products fit 24 bits (the host table's reciprocals divide the section
+// index; 32-bit byte offsets from uniform bases: the block's first plane of
+// the field, of the parent grid LV + 1 and, at level 1, of the level-1 grid
+// it fills).  A wave handles CPW chunks (P.cpw0 at level 0, kChunksPerWave at
+// level 1), G at a time: the loads of all G are issued first, every value is
+// computed before any branch or store, so a wave keeps several chunks' reads
+// in flight and no load is left pending on a path.  The optional per-point
+// outputs are compiled in only when requested.
+template <int LV, bool AUX, int KB, int G>
+__device__ __forceinline__ void encode_fast(const EncPlan &P, uint32_t (*pack)[32]) {
   uint32_t gxi, b;
   xcd_remap(gxi, b);
   const uint32_t wave = wave_index();
   const int lane = lane_id();
   // Every uniform value the loop needs is copied into a local first, so it
   // stays in scalar registers across the loop's stores.
-  const BlockPos bp = block_pos(P.g, P.l0, b);
-  const Sec s = P.l0.sec[bp.cls];
+  const Geo &gq = P.g;
+  const BlockPos bp = block_pos(gq, P.l0, b);
+  if (LV == 1) {
+    // the block's level-2 points carry over into the level-1 grid unchanged
+    const int64_t o[3] = {bp.o[0], bp.o[1], bp.o[2]}, hi[3] = {bp.hi[0], bp.hi[1], bp.hi[2]};
+    copy_coarse(P.G + P.g_off[2], P.gd[2], P.G + P.g_off[1], P.gd[1], o, hi, 2, gxi * kWaves + wave,
+                gridDim.x * kWaves);
+  }
+  const Sec s = LV == 0 ? P.l0.sec[bp.cls] : P.l0.sec1[bp.cls];
+  const SecR rc = LV == 0 ? P.l0.rc[bp.cls] : P.l0.rc1[bp.cls];
   const uint32_t nch = (s.npts + 63) / 64;
-  const uint32_t maxch = P.maxch[0];
-  const uint32_t n1 = (uint32_t)P.g.n[1], n2 = (uint32_t)P.g.n[2];
-  const uint32_t oy = bp.o[1], ox = bp.o[2];
-  const float *__restrict__ xb = P.x + (size_t)bp.o[0] * n1 * n2;
-  const uint32_t g0 = (uint32_t)P.gd[1][0], g1 = (uint32_t)P.gd[1][1], g2 = (uint32_t)P.gd[1][2];
-  const uint32_t zg = bp.o[0] >> 1;
-  const float *__restrict__ G1 = P.G + P.g_off[1] + (size_t)zg * g1 * g2;
+  const uint32_t maxch = (uint32_t)P.maxch[LV];
+  const uint32_t n1 = (uint32_t)gq.n[1], n2 = (uint32_t)gq.n[2];
+  // block origin on the level-LV grid (y, x) and the parent grid's slab
+  const uint32_t oyl = bp.o[1] >> LV, oxl = bp.o[2] >> LV;
+  const uint32_t h0 = (uint32_t)P.gd[LV + 1][0], h1 = (uint32_t)P.gd[LV + 1][1], h2 = (uint32_t)P.gd[LV + 1][2];
+  const uint32_t zp = bp.o[0] >> (LV + 1);
+  const uint32_t f1 = (uint32_t)P.gd[1][1], f2 = (uint32_t)P.gd[1][2];
   // uniform bases; the launcher guarantees the block's slab spans < 4 GiB
-  const char *__restrict__ xbase = reinterpret_cast<const char *>(xb);
-  const char *__restrict__ G1b = reinterpret_cast<const char *>(G1);
-  const uint32_t g2x4 = g2 * 4u, g12x4 = g1 * g2 * 4u;
+  const char *__restrict__ xbase = reinterpret_cast<const char *>(P.x + (size_t)bp.o[0] * n1 * n2);
+  const char *__restrict__ Pb = reinterpret_cast<const char *>(P.G + P.g_off[LV + 1] + (size_t)zp * h1 * h2);
+  char *__restrict__ G1b = reinterpret_cast<char *>(P.G + P.g_off[1] + (size_t)(bp.o[0] >> 1) * f1 * f2);
+  const uint32_t h2x4 = h2 * 4u, h12x4 = h1 * h2 * 4u;
   const uint32_t ownz = bp.own[0] - bp.o[0], owny = bp.own[1], ownx = bp.own[2];
-  const int64_t slot0 = P.slot_base[0] + (int64_t)b * maxch;
+  const int64_t slot0 = P.slot_base[LV] + (int64_t)b * maxch;
   U4 *__restrict__ cnt = P.cnt;
   uint32_t *__restrict__ pay = P.pay;
   unsigned long long *__restrict__ emask = P.emask;
   float *__restrict__ exv = P.exv;
   int32_t *codes = P.codes;
   uint8_t *flags = P.flags;
-  const Geo &gq = P.g;
-  const int K = P.g.K;
+  const int K = gq.K;
   float iso[KB];
 #pragma unroll
-  for (int jj = 0; jj < KB; jj++) iso[jj] = P.g.iso[jj];
+  for (int jj = 0; jj < KB; jj++) iso[jj] = gq.iso[jj];
   Part acc;
   part_init(acc);
-  const int cpw = P.cpw0;
+  const int cpw = LV == 0 ? P.cpw0 : kChunksPerWave;
   const uint32_t jmax = s.npts ? s.npts - 1 : 0u;
-  const SecR rc = P.l0.rc[bp.cls];
   // lanes past the section (and chunks past it) read a clamped point and
   // discard it
 #pragma unroll 1
   for (int k0 = 0; k0 < cpw; k0 += G) {
-    float xs[G], pa[G][8];
+    float xs[G], pa[G][8], xrs[G];
     bool zu[G], yu[G], xu[G], in[G], own[G];
-    uint32_t gi[G];
+    uint32_t gi[G], go[G];
 #pragma unroll
     for (int u = 0; u < G; u++) {
       const uint32_t c = (gxi * cpw + k0 + u) * kWaves + wave;
       const uint32_t jr = c * kWave + (uint32_t)lane;
       uint32_t w, v, uu;
       sec_point24(s, rc, min(jr, jmax), w, v, uu);
-      const uint32_t y = oy + v, xx = ox + uu;
-      const uint32_t prow = mad24s(w, n1, y);
+      // (w, V, U): the point on the level-LV grid (w relative to the block)
+      const uint32_t V = oyl + v, U = oxl + uu;
+      const uint32_t zr = w << LV, y = V << LV, xx = U << LV;
+      const uint32_t prow = mad24s(zr, n1, y);
       xs[u] = ldf(xbase, mad24s(prow, n2, xx) * 4u);
-      const uint32_t zl = w >> 1, yl = y >> 1, xl = xx >> 1;
-      zu[u] = (w & 1u) && (zg + zl + 1 < g0);
-      yu[u] = (y & 1u) && (yl + 1 < g1);
-      xu[u] = (xx & 1u) && (xl + 1 < g2);
-      // byte offsets of the eight parents in the block's slab of the level-1 grid
-      const uint32_t o00 = mad24s(mad24s(zl, g1, yl), g2, xl) * 4u;
-      const uint32_t dxo = xu[u] ? 4u : 0u, dyo = yu[u] ? g2x4 : 0u, dzo = zu[u] ? g12x4 : 0u;
+      const uint32_t zl = w >> 1, yl = V >> 1, xl = U >> 1;
+      zu[u] = (w & 1u) && (zp + zl + 1 < h0);
+      yu[u] = (V & 1u) && (yl + 1 < h1);
+      xu[u] = (U & 1u) && (xl + 1 < h2);
+      // byte offsets of the eight parents in the block's slab of grid LV + 1
+      const uint32_t o00 = mad24s(mad24s(zl, h1, yl), h2, xl) * 4u;
+      const uint32_t dxo = xu[u] ? 4u : 0u, dyo = yu[u] ? h2x4 : 0u, dzo = zu[u] ? h12x4 : 0u;
       const uint32_t o01 = o00 + dyo, o10 = o00 + dzo, o11 = o10 + dyo;
-      pa[u][0] = ldf(G1b, o00); pa[u][1] = ldf(G1b, o00 + dxo);
-      pa[u][2] = ldf(G1b, o01); pa[u][3] = ldf(G1b, o01 + dxo);
-      pa[u][4] = ldf(G1b, o10); pa[u][5] = ldf(G1b, o10 + dxo);
-      pa[u][6] = ldf(G1b, o11); pa[u][7] = ldf(G1b, o11 + dxo);
+      pa[u][0] = ldf(Pb, o00); pa[u][1] = ldf(Pb, o00 + dxo);
+      pa[u][2] = ldf(Pb, o01); pa[u][3] = ldf(Pb, o01 + dxo);
+      pa[u][4] = ldf(Pb, o10); pa[u][5] = ldf(Pb, o10 + dxo);
+      pa[u][6] = ldf(Pb, o11); pa[u][7] = ldf(Pb, o11 + dxo);
       in[u] = jr < s.npts;
-      own[u] = w < ownz && y < owny && xx < ownx;
-      gi[u] = AUX ? mad24s(prow, n2, xx) : 0u;  // offset of the point in the block's slab
+      own[u] = zr < ownz && y < owny && xx < ownx;
+      gi[u] = AUX ? mad24s(prow, n2, xx) : 0u;                  // the point in the block's slab
+      go[u] = LV == 1 ? mad24s(mad24s(w, f1, V), f2, U) * 4u : 0u;  // its slot in the level-1 grid
     }
     // every point's arithmetic before any branch, so every load is consumed
     // on every path (lanes past the section compute on their clamped point
@@ -414,6 +426,7 @@ __global__ __launch_bounds__(kBS) void k_encode_l0(EncPlan P) {
       if (O || C) { xr = x; q = 0; }
       zzs[u] = in[u] ? (((uint32_t)q << 1) ^ (uint32_t)(q >> 31)) : 0u;
       Es[u] = in[u] && (O || C);
+      xrs[u] = xr;
       if (in[u]) {
         const uint32_t ro = ord_of(xr), xo = ord_of(x);
         acc.rmin = min(acc.rmin, ro); acc.rmax = max(acc.rmax, ro);
@@ -427,6 +440,7 @@ __global__ __launch_bounds__(kBS) void k_encode_l0(EncPlan P) {
         }
       }
       hold(zzs[u]);
+      hold(xrs[u]);
     }
 #pragma unroll
     for (int u = 0; u < G; u++) {
@@ -437,6 +451,8 @@ __global__ __launch_bounds__(kBS) void k_encode_l0(EncPlan P) {
         if (lane == 0) cnt[slot] = U4{0, 0, 0, 0};
         continue;
       }
+      // level 1: the reconstructed value is the level-0 kernel's parent
+      if (LV == 1 && in[u]) stf(G1b, go[u], xrs[u]);
       const float x = xs[u];
       const uint32_t zz = zzs[u];
       const bool E = Es[u];
@@ -465,99 +481,19 @@ __global__ __launch_bounds__(kBS) void k_encode_l0(EncPlan P) {
       __builtin_amdgcn_wave_barrier();
     }
   }
-  part_store(acc, &P.part[(int64_t)b * P.part_per_block + gxi]);
+  part_store(acc, &P.part[(int64_t)b * P.part_per_block + (LV == 0 ? 0 : P.part_l1) + gxi]);
 }
 
-// Level 1 below a coarser level (nL >= 3): the arithmetic of enc_chunk
-// with the level fixed at 1.  Section coordinates (w, v, u) are the block's
-// 2-grid, so parities and parents follow from them directly; 32-bit byte
-// offsets from uniform bases (the block's first plane of the field, of the
-// level-2 grid it predicts from and of the level-1 grid it fills).
-template <bool AUX, int KB>
+template <bool AUX, int KB, int G>
+__global__ __launch_bounds__(kBS) void k_encode_l0(EncPlan P) {
+  __shared__ uint32_t pack[kWaves][32];
+  encode_fast<0, AUX, KB, G>(P, pack);
+}
+
+template <bool AUX, int KB, int G>
 __global__ __launch_bounds__(kBS) void k_encode_l1s(EncPlan P) {
   __shared__ uint32_t pack[kWaves][32];
-  uint32_t bx, by;
-  xcd_remap(bx, by);
-  const uint32_t b = by;
-  const int wave = threadIdx.x / kWave;
-  const int lane = lane_id();
-  const Geo &g = P.g;
-  const BlockPos bp = block_pos(g, P.l0, b);
-  const int64_t o[3] = {bp.o[0], bp.o[1], bp.o[2]}, hi[3] = {bp.hi[0], bp.hi[1], bp.hi[2]};
-  // the block's level-2 points carry over into the level-1 grid unchanged
-  copy_coarse(P.G + P.g_off[2], P.gd[2], P.G + P.g_off[1], P.gd[1], o, hi, 2, bx * kWaves + wave,
-              gridDim.x * kWaves);
-  const Sec s = P.l0.sec1[bp.cls];
-  const uint32_t nch = (s.npts + 63) / 64;
-  const uint32_t maxch = P.maxch[1];
-  const uint32_t n1 = (uint32_t)g.n[1], n2 = (uint32_t)g.n[2];
-  const uint32_t oy = bp.o[1], ox = bp.o[2];
-  const uint32_t ownz = bp.own[0] - bp.o[0], owny = bp.own[1], ownx = bp.own[2];
-  // level-2 grid (parents): block origin o / 4; level-1 grid (output): o / 2
-  const uint32_t h0 = (uint32_t)P.gd[2][0], h1 = (uint32_t)P.gd[2][1], h2 = (uint32_t)P.gd[2][2];
-  const uint32_t f1 = (uint32_t)P.gd[1][1], f2 = (uint32_t)P.gd[1][2];
-  const uint32_t z4 = (uint32_t)(o[0] >> 2), y4 = oy >> 2, x4 = ox >> 2;
-  const uint32_t y2 = oy >> 1, x2 = ox >> 1;
-  const char *__restrict__ xbase = reinterpret_cast<const char *>(P.x + (size_t)o[0] * n1 * n2);
-  const char *__restrict__ G2b = reinterpret_cast<const char *>(P.G + P.g_off[2] + (size_t)z4 * h1 * h2);
-  char *__restrict__ G1b = reinterpret_cast<char *>(P.G + P.g_off[1] + (size_t)(o[0] >> 1) * f1 * f2);
-  const uint32_t h2x4 = h2 * 4u, h12x4 = h1 * h2 * 4u;
-  const int64_t slot0 = P.slot_base[1] + (int64_t)b * maxch;
-  const int K = g.K;
-  float iso[KB];
-#pragma unroll
-  for (int jj = 0; jj < KB; jj++) iso[jj] = g.iso[jj];
-  Part acc;
-  part_init(acc);
-#pragma unroll 1
-  for (int k = 0; k < kChunksPerWave; k++) {
-    const uint32_t c = (bx * kChunksPerWave + k) * kWaves + wave;
-    if (c >= maxch) break;
-    const int64_t slot = slot0 + c;
-    if (c >= nch) {
-      if (lane == 0) P.cnt[slot] = U4{0, 0, 0, 0};
-      continue;
-    }
-    const uint32_t j = c * kWave + (uint32_t)lane;
-    float x = 0.f;
-    uint32_t zz = 0;
-    bool E = false;
-    if (j < s.npts) {
-      uint32_t w, v, u;
-      sec_point(s, j, w, v, u);
-      const uint32_t zr = 2 * w, y = oy + 2 * v, xx = ox + 2 * u;  // zr relative to the block
-      x = ldf(xbase, ((zr * n1 + y) * n2 + xx) * 4u);
-      const uint32_t pz = w & 1u, py = v & 1u, px = u & 1u;
-      const uint32_t zl = w >> 1, yl = y4 + (v >> 1), xl = x4 + (u >> 1);  // zl relative to the slab
-      const bool zu = pz && (z4 + zl + 1 < h0), yu = py && (yl + 1 < h1), xu = px && (xl + 1 < h2);
-      const uint32_t o00 = ((zl * h1 + yl) * h2 + xl) * 4u;
-      const uint32_t dxo = xu ? 4u : 0u, dyo = yu ? h2x4 : 0u, dzo = zu ? h12x4 : 0u;
-      const uint32_t o01 = o00 + dyo, o10 = o00 + dzo, o11 = o10 + dyo;
-      const float p = midpoint8(ldf(G2b, o00), ldf(G2b, o00 + dxo), ldf(G2b, o01), ldf(G2b, o01 + dxo),
-                                ldf(G2b, o10), ldf(G2b, o10 + dxo), ldf(G2b, o11), ldf(G2b, o11 + dxo), zu, yu, xu);
-      int32_t q;
-      int O, C = 0;
-      float xr;
-      quantize(g, x, p, q, O, xr);
-      if (!O && K > 0) C = rank_of<KB>(iso, K, x) != rank_of<KB>(iso, K, xr);
-      if (O || C) { xr = x; q = 0; }
-      E = O || C;
-      zz = ((uint32_t)q << 1) ^ (uint32_t)(q >> 31);
-      stf(G1b, ((w * f1 + (y2 + v)) * f2 + (x2 + u)) * 4u, xr);
-      const uint32_t ro = ord_of(xr), xo = ord_of(x);
-      acc.rmin = min(acc.rmin, ro); acc.rmax = max(acc.rmax, ro);
-      acc.xmin = min(acc.xmin, xo); acc.xmax = max(acc.xmax, xo);
-      acc.nonfinite |= !isfinite(x);
-      if (zr < ownz && y < owny && xx < ownx) { acc.nO += O; acc.nC += C; }
-      if (AUX) {
-        const size_t gi = ((size_t)(o[0] + zr) * n1 + y) * n2 + xx;
-        if (P.codes) P.codes[gi] = q;
-        if (P.flags) P.flags[gi] = (uint8_t)(O | (C << 1));
-      }
-    }
-    pack_chunk(P, slot, zz, E, x, pack[wave]);
-  }
-  part_store(acc, &P.part[(int64_t)b * P.part_per_block + P.part_l1 + bx]);
+  encode_fast<1, AUX, KB, G>(P, pack);
 }
 
 // Byte size of every section from the scanned chunk sizes.
@@ -909,10 +845,10 @@ void launch_encode_levels(const EncPlan &p, hipStream_t s) {
     const bool slab32 = 4.0 * (double)(hi[0] - o[0] + 1) * (double)g.n[1] * (double)g.n[2] < 4294967296.0;
     const dim3 grid1((unsigned)encode_l1_groups(p), (unsigned)g.nblocks);
     prof_mark("k_encode_l1", s, 0);
-    if (L >= 2 && slab32 && !p.codes && !p.flags)
-      k_encode_l1s<false, KB><<<grid1, dim3(kBS), 0, s>>>(p);
-    else if (L >= 2 && slab32)
-      k_encode_l1s<true, KB><<<grid1, dim3(kBS), 0, s>>>(p);
+    if (L >= 2 && slab32 && p.l0.small && !p.codes && !p.flags)
+      k_encode_l1s<false, KB, 4><<<grid1, dim3(kBS), 0, s>>>(p);
+    else if (L >= 2 && slab32 && p.l0.small)
+      k_encode_l1s<true, KB, 1><<<grid1, dim3(kBS), 0, s>>>(p);
     else
       k_encode_l1<KB><<<grid1, dim3(kBS), 0, s>>>(p);
     prof_mark("k_encode_l1", s, 1);

@@ -41,6 +41,7 @@ CASES = [
     ("normal", (9, 1, 5), 1, 1, 0.1, 1),
     ("normal", (65, 66, 67), 3, 32, 0.0, 1),     # lossless
     ("smooth", (70, 65, 129), 6, 64, 5e-4, 16),  # partial blocks on every axis, 16 isovalues
+    ("grf", (129, 257, 257), 3, 256, 1e-3, 2),   # level-0 sections of > 2^21 points: the general kernels
 ]
 
 
@@ -68,6 +69,9 @@ def test_compress_bitexact(case):
     assert c.result["n_outlier"] == int((ref["flags"] & 1).sum())
     assert c.result["n_corrected"] == int((ref["flags"] >> 1).sum())
     assert c.result["vmin"] == f.min() and c.result["vmax"] == f.max()
+    # without the per-point outputs the specialized level-0 kernel runs
+    c2 = api.compress(x, e, isos, levels=case[2], block=case[3])
+    assert np.array_equal(c2.stream.cpu().numpy(), ref["stream"])
 
 
 @pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}-{'x'.join(map(str, c[1]))}-L{c[2]}-B{c[3]}")

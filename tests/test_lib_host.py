@@ -148,7 +148,7 @@ def test_batch_plan_workspace_and_rejections():
     assert ws <= len(shapes) * (per + 256 + 4 * 64 ** 3)
     b, e, d, ms = C.c_int(), C.c_int(), C.c_int(), C.c_float()
     assert lib.chr_batch_config(h, C.byref(b), C.byref(e), C.byref(d), C.byref(ms)) == L.CHR_OK
-    assert 1 <= b.value <= len(shapes) and (e.value, d.value) == (4, 16)
+    assert 1 <= b.value <= len(shapes) and (e.value, d.value) == (8, 16)  # the process-wide tiles
     # a replay before any capture is an error, not a launch
     assert lib.chr_batch_replay(h, None) == L.CHR_E_INVAL
     # the replay-timed autotuner is switched off: refused before any device call
@@ -269,3 +269,19 @@ def test_topology_bound_rejects_bad_arguments():
     bad = (C.c_float * 1)(float("inf"))
     assert lib.chr_topology_error_bound(fake, dims, bad, 1, 1, fake, fake, ws_n, None) == L.CHR_E_INVAL
     assert lib.chr_topology_error_bound(fake, dims, iso, 2, 1, fake, fake, ws_n - 1, None) == L.CHR_E_NOMEM
+
+
+def test_reciprocal_division_rule():
+    """The level-0 kernels divide by block-shape constants d as trunc(fl(n * r))
+    with r the smallest binary32 value >= 1/d; this equals floor(n / d) for
+    n, d < 2^21 (checked for every n against small and sampled large d)."""
+    n = np.arange(1 << 21, dtype=np.uint32)
+    nf = n.astype(np.float32)
+    rng = np.random.default_rng(3)
+    ds = list(range(1, 200)) + [int(v) for v in rng.integers(200, 1 << 21, 60)] + [(1 << 21) - 1]
+    for d in ds:
+        r = np.float32(1.0 / d)
+        if float(r) < 1.0 / d:
+            r = np.nextafter(r, np.float32(np.inf))
+        q = (nf * r).astype(np.uint32)
+        assert np.array_equal(q, n // np.uint32(d)), d
