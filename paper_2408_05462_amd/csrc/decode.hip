@@ -296,42 +296,65 @@ __global__ __launch_bounds__(kBS) void k_decode_level(DecPlan D, int l) {
   });
 }
 
-// Level 0 below a coarser level (nL >= 2) over (tile groups, blocks): one
-// wave per tile, block geometry from the host-filled shape table, and
-// block-relative 32-bit offsets from uniform base pointers (the block's first
-// plane of the output and of the level-1 grid).  Writes the points the block
-// owns, plus the even points of even rows taken from level 1.
-__global__ __launch_bounds__(kBS) void k_decode_l0(DecPlan D) {
+// Levels 0 and 1 below a coarser level (level LV + 1 exists) over (tile
+// groups, blocks), for block shapes whose index products fit 24 bits: each
+// wave decodes CPW consecutive chunks of one tile (P.cpw0 at level 0, 16 at
+// level 1), with block geometry and reciprocals from the host-filled shape
+// table and block-relative 32-bit offsets from uniform base pointers (the
+// block's first plane of the output and of the parent grid).  Level 0 writes
+// the points the block owns plus the even points of even rows taken from
+// level 1; level 1 writes every point of its section into the level-1 grid,
+// after carrying the block's level-2 points over into it.
+template <int LV>
+__device__ __forceinline__ void decode_fast(const DecPlan &D) {
   const Geo &g = D.g;
   uint32_t gxi, b;
   xcd_remap(gxi, b);
   if (!block_needed(D, b)) return;
-  const uint32_t cpw = (uint32_t)D.cpw0;
-  const uint32_t cbeg = (gxi * kWaves + wave_index()) * cpw;  // first chunk of this wave
-  const uint32_t t = cbeg >> 6, kbeg = cbeg & 63u;
+  const uint32_t wave = wave_index();
   const int lane = lane_id();
   const BlockPos bp = block_pos(g, D.l0, b);
-  const Sec s = D.l0.sec[bp.cls];  // by value: stays in scalar registers across the stores
+  if (LV == 1) {
+    // one row of the block's level-2 grid per wave step
+    const uint32_t c0 = ((bp.hi[0] - bp.o[0]) >> 2) + 1, c1 = ((bp.hi[1] - bp.o[1]) >> 2) + 1;
+    const uint32_t c2 = ((bp.hi[2] - bp.o[2]) >> 2) + 1;
+    const float *src = D.gp[2];
+    float *dst = D.gp[1];
+    const uint32_t zo = bp.o[0] >> 2, yo = bp.o[1] >> 2, xo = bp.o[2] >> 2;
+    const uint32_t s1 = (uint32_t)D.gd[2][1], s2 = (uint32_t)D.gd[2][2];
+    const uint32_t d1 = (uint32_t)D.gd[1][1], d2 = (uint32_t)D.gd[1][2];
+    for (uint32_t r = gxi * kWaves + wave; r < c0 * c1; r += gridDim.x * kWaves) {
+      const uint32_t w = r / c1, v = r - w * c1;
+      const size_t srow = ((size_t)(zo + w) * s1 + (yo + v)) * s2 + xo;
+      const size_t drow = ((size_t)(2 * (zo + w)) * d1 + 2 * (yo + v)) * d2 + 2 * xo;
+      for (uint32_t u = (uint32_t)lane; u < c2; u += kWave) dst[drow + 2 * u] = src[srow + u];
+    }
+  }
+  const uint32_t cpw = LV == 0 ? (uint32_t)D.cpw0 : 16u;
+  const uint32_t cbeg = (gxi * kWaves + wave) * cpw;  // first chunk of this wave
+  const uint32_t t = cbeg >> 6, kbeg = cbeg & 63u;
+  const Sec s = LV == 0 ? D.l0.sec[bp.cls] : D.l0.sec1[bp.cls];  // by value: scalar registers
   const uint32_t nch = (s.npts + 63) / 64;
   if (t >= (nch + 63) / 64) return;
-  const SecView v = open_section(D, b, 0, s.npts);
+  const SecView v = open_section(D, b, LV, s.npts);
   if (!v.ok) {
     if (lane == 0) set_status(D, -4);
     return;
   }
   const uint32_t n1 = (uint32_t)g.n[1], n2 = (uint32_t)g.n[2];
-  const uint32_t oy = bp.o[1], ox = bp.o[2];
+  const uint32_t oyl = bp.o[1] >> LV, oxl = bp.o[2] >> LV;
   const uint32_t ownz = bp.own[0] - bp.o[0], owny = bp.own[1], ownx = bp.own[2];
   const bool lastx = (bp.hi[2] == (uint32_t)g.n[2] - 1);
   const bool all = D.prune != 0;
-  float *__restrict__ ob = D.out + (size_t)bp.o[0] * n1 * n2;
-  const uint32_t g0 = (uint32_t)D.gd[1][0], g1 = (uint32_t)D.gd[1][1], g2 = (uint32_t)D.gd[1][2];
-  const uint32_t zg = bp.o[0] >> 1;
-  const float *__restrict__ G1 = D.gp[1] + (size_t)zg * g1 * g2;
+  // output: the field (level 0) or the level-1 grid, from the block's first plane
+  const uint32_t f1 = (uint32_t)D.gd[1][1], f2 = (uint32_t)D.gd[1][2];
+  char *__restrict__ obase = LV == 0 ? reinterpret_cast<char *>(D.out + (size_t)bp.o[0] * n1 * n2)
+                                     : reinterpret_cast<char *>(D.gp[1] + (size_t)(bp.o[0] >> 1) * f1 * f2);
+  const uint32_t h0 = (uint32_t)D.gd[LV + 1][0], h1 = (uint32_t)D.gd[LV + 1][1], h2 = (uint32_t)D.gd[LV + 1][2];
+  const uint32_t zp = bp.o[0] >> (LV + 1);
   // uniform bases; the launcher guarantees the block's slab spans < 4 GiB
-  const char *__restrict__ G1b = reinterpret_cast<const char *>(G1);
-  char *__restrict__ obase = reinterpret_cast<char *>(ob);
-  const uint32_t g2x4 = g2 * 4u, g12x4 = g1 * g2 * 4u;
+  const char *__restrict__ Pb = reinterpret_cast<const char *>(D.gp[LV + 1] + (size_t)zp * h1 * h2);
+  const uint32_t h2x4 = h2 * 4u, h12x4 = h1 * h2 * 4u;
   const float step = g.step;
   const int lossless = g.lossless;
 
@@ -356,7 +379,7 @@ __global__ __launch_bounds__(kBS) void k_decode_l0(DecPlan D) {
   const uint32_t nc = min(min(64u, v.nch - t * 64), kbeg + cpw);
   const char *__restrict__ payb = reinterpret_cast<const char *>(v.p + v.Poff);
   const char *__restrict__ exvb = reinterpret_cast<const char *>(v.p + v.Xoff);
-  const SecR rc = D.l0.rc[bp.cls];
+  const SecR rc = LV == 0 ? D.l0.rc[bp.cls] : D.l0.rc1[bp.cls];
   const uint32_t jmax = s.npts - 1;  // npts > 0: this wave's tile holds a chunk
   const uint32_t hi2 = bp.hi[2];
   // kDecGroup chunks at a time: coordinates and addresses of all of them,
@@ -368,7 +391,7 @@ __global__ __launch_bounds__(kBS) void k_decode_l0(DecPlan D) {
 #pragma unroll 1
   for (uint32_t k0 = kbeg; k0 < nc; k0 += kDecGroup) {
     float pa[kDecGroup][8], r[kDecGroup];
-    uint32_t pw0[kDecGroup], pw1[kDecGroup], xv[kDecGroup], orow[kDecGroup], xs[kDecGroup], off[kDecGroup];
+    uint32_t pw0[kDecGroup], pw1[kDecGroup], xv[kDecGroup], orow[kDecGroup], off[kDecGroup];
     bool zu[kDecGroup], yu[kDecGroup], xu[kDecGroup], ex[kDecGroup], wr[kDecGroup], wx[kDecGroup], ev[kDecGroup],
         e1[kDecGroup];
 #pragma unroll
@@ -379,18 +402,19 @@ __global__ __launch_bounds__(kBS) void k_decode_l0(DecPlan D) {
       const uint32_t jr = (t * 64 + k) * 64 + (uint32_t)lane;
       uint32_t zz_, vv, uu;
       sec_point24(s, rc, min(jr, jmax), zz_, vv, uu);
-      const uint32_t y = oy + vv, x = ox + uu;
-      const uint32_t zl = zz_ >> 1, yl = y >> 1, xl = x >> 1;
-      zu[u] = (zz_ & 1u) && (zg + zl + 1 < g0);
-      yu[u] = (y & 1u) && (yl + 1 < g1);
-      xu[u] = (x & 1u) && (xl + 1 < g2);
-      const uint32_t o00 = mad24s(mad24s(zl, g1, yl), g2, xl) * 4u;
-      const uint32_t dxo = xu[u] ? 4u : 0u, dyo = yu[u] ? g2x4 : 0u, dzo = zu[u] ? g12x4 : 0u;
+      // (zz_, V, U): the point on the level-LV grid (zz_ relative to the block)
+      const uint32_t V = oyl + vv, U = oxl + uu;
+      const uint32_t zl = zz_ >> 1, yl = V >> 1, xl = U >> 1;
+      zu[u] = (zz_ & 1u) && (zp + zl + 1 < h0);
+      yu[u] = (V & 1u) && (yl + 1 < h1);
+      xu[u] = (U & 1u) && (xl + 1 < h2);
+      const uint32_t o00 = mad24s(mad24s(zl, h1, yl), h2, xl) * 4u;
+      const uint32_t dxo = xu[u] ? 4u : 0u, dyo = yu[u] ? h2x4 : 0u, dzo = zu[u] ? h12x4 : 0u;
       const uint32_t o01 = o00 + dyo, o10 = o00 + dzo, o11 = o10 + dyo;
-      pa[u][0] = ldf(G1b, o00); pa[u][1] = ldf(G1b, o00 + dxo);
-      pa[u][2] = ldf(G1b, o01); pa[u][3] = ldf(G1b, o01 + dxo);
-      pa[u][4] = ldf(G1b, o10); pa[u][5] = ldf(G1b, o10 + dxo);
-      pa[u][6] = ldf(G1b, o11); pa[u][7] = ldf(G1b, o11 + dxo);
+      pa[u][0] = ldf(Pb, o00); pa[u][1] = ldf(Pb, o00 + dxo);
+      pa[u][2] = ldf(Pb, o01); pa[u][3] = ldf(Pb, o01 + dxo);
+      pa[u][4] = ldf(Pb, o10); pa[u][5] = ldf(Pb, o10 + dxo);
+      pa[u][6] = ldf(Pb, o11); pa[u][7] = ldf(Pb, o11 + dxo);
       const uint32_t bit = mul24s((uint32_t)lane, wk);
       off[u] = bit & 31u;
       pw0[u] = 0u;
@@ -403,18 +427,25 @@ __global__ __launch_bounds__(kBS) void k_decode_l0(DecPlan D) {
       ex[u] = (emk >> lane) & 1ull;
       xv[u] = 0u;
       if (ex[u]) xv[u] = ldu(exvb, 4u * (xok + lanes_below(emk)));
-      // the points the block owns -- or, in a restricted reconstruction, its
-      // whole closed extent (a neighbour owning the shared faces may be left
-      // out; both write identical values where both run)
       const bool valid = (k0 + (uint32_t)u < nc) && (jr < s.npts);
-      wr[u] = valid && (all || (zz_ < ownz && y < owny));
-      wx[u] = all || x < ownx;
-      // even row of an even plane: the neighbouring even points come from
-      // level 1 (they are this point's two x parents)
-      ev[u] = !((zz_ | y) & 1u) && (x & 1u);
-      e1[u] = x + 1 == hi2 && (lastx || all);
-      orow[u] = mul24s(mad24s(zz_, n1, y), n2) * 4u;
-      xs[u] = x;
+      if (LV == 0) {
+        // the points the block owns -- or, in a restricted reconstruction,
+        // its whole closed extent (a neighbour owning the shared faces may
+        // be left out; both write identical values where both run)
+        wr[u] = valid && (all || (zz_ < ownz && V < owny));
+        wx[u] = all || U < ownx;
+        // even row of an even plane: the neighbouring even points come from
+        // level 1 (they are this point's two x parents)
+        ev[u] = !((zz_ | V) & 1u) && (U & 1u);
+        e1[u] = U + 1 == hi2 && (lastx || all);
+        orow[u] = (mul24s(mad24s(zz_, n1, V), n2) + U) * 4u;
+      } else {
+        wr[u] = valid;
+        wx[u] = true;
+        ev[u] = false;
+        e1[u] = false;
+        orow[u] = mad24s(mad24s(zz_, f1, V), f2, U) * 4u;
+      }
     }
 #pragma unroll
     for (int u = 0; u < kDecGroup; u++) {
@@ -434,15 +465,18 @@ __global__ __launch_bounds__(kBS) void k_decode_l0(DecPlan D) {
 #pragma unroll
     for (int u = 0; u < kDecGroup; u++) {
       if (!wr[u]) continue;
-      const uint32_t ro = orow[u] + 4u * xs[u];
+      const uint32_t ro = orow[u];
       if (wx[u]) stf(obase, ro, r[u]);
-      if (ev[u]) {
+      if (LV == 0 && ev[u]) {
         stf(obase, ro - 4u, pa[u][0]);
         if (e1[u]) stf(obase, ro + 4u, pa[u][1]);
       }
     }
   }
 }
+
+__global__ __launch_bounds__(kBS) void k_decode_l0(DecPlan D) { decode_fast<0>(D); }
+__global__ __launch_bounds__(kBS) void k_decode_l1(DecPlan D) { decode_fast<1>(D); }
 
 // Even points of even rows in blocks one point wide along x (no level-0
 // point in those rows writes them).
@@ -506,19 +540,24 @@ void launch_decode(const DecPlan &p, hipStream_t s) {
     k_decode_coarse<<<dim3((unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
     prof_mark("k_decode_coarse", s, 1);
   }
+  // the specialized kernels address a block's slab with 32-bit offsets
+  const bool slab32 = 4.0 * (double)(hi[0] - o[0] + 1) * (double)g.n[1] * (double)g.n[2] < 4294967296.0;
   for (int l = 2; l >= 1; l--) {
     if (L >= l && p.lo <= l) {
       const Sec sl = sec_geom(o, hi, l, L);
       const int64_t ntl = ceil_div(ceil_div(sl.npts, 64), 64);
+      const dim3 grid((unsigned)(ntl > 0 ? ntl : 1), (unsigned)g.nblocks);
       prof_mark(l == 1 ? "k_decode_l1" : "k_decode_l2", s, 0);
-      k_decode_level<<<dim3((unsigned)(ntl > 0 ? ntl : 1), (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p, l);
+      if (l == 1 && L >= 2 && slab32 && p.l0.small)
+        k_decode_l1<<<grid, dim3(kBS), 0, s>>>(p);  // one tile per workgroup: 16 chunks per wave
+      else
+        k_decode_level<<<grid, dim3(kBS), 0, s>>>(p, l);
       prof_mark(l == 1 ? "k_decode_l1" : "k_decode_l2", s, 1);
     }
   }
   if (p.lo == 0) {
     const Sec s0 = sec_geom(o, hi, 0, L);
     const int64_t ntile = ceil_div(ceil_div(s0.npts, 64), 64);
-    const bool slab32 = 4.0 * (double)(hi[0] - o[0] + 1) * (double)g.n[1] * (double)g.n[2] < 4294967296.0;
     prof_mark("k_decode_fine", s, 0);
     if (L >= 1 && slab32 && p.l0.small) {
       const int64_t nch0 = ceil_div(s0.npts, 64);

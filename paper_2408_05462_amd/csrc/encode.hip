@@ -568,14 +568,17 @@ __global__ __launch_bounds__(kBS) void k_sec_table(EncPlan P) {
 // (first workgroups) to level 0.  A section that does not fit the capacity is
 // not written (the result then reports the required size).
 __global__ __launch_bounds__(kBS) void k_pack(EncPlan P) {
-  __shared__ uint16_t s_own[64 * kMaxW];  // chunk (within the tile) of each payload word
-  __shared__ uint32_t s_pw[64], s_px[64], s_nx[64];
-  __shared__ uint32_t s_tot, s_base;
+  __shared__ uint16_t s_own_all[kWaves][64 * kMaxW];  // chunk (within the tile) of each payload word
+  __shared__ uint32_t s_pw_all[kWaves][64];
   const Geo &g = P.g;
   const int L = g.nL - 1;
   const int lane = lane_id();
-  const int wave = threadIdx.x / kWave;
-  const int64_t wg = blockIdx.x;
+  const uint32_t wave = wave_index();
+  uint16_t *s_own = s_own_all[wave];
+  uint32_t *s_pw = s_pw_all[wave];
+  // one wave per tile of 64 chunks (tiles of every section in level-major order)
+  const int64_t wg = (int64_t)blockIdx.x * kWaves + wave;
+  if (wg >= P.pack_base[0] + g.nblocks * P.pack_gpb[0]) return;
   int l = L;
   for (int t = L - 1; t >= 0; t--)
     if (wg >= P.pack_base[t]) l = t;
@@ -585,6 +588,8 @@ __global__ __launch_bounds__(kBS) void k_pack(EncPlan P) {
   Sec s;
   if (l == 0) {
     s = P.l0.sec[block_pos(g, P.l0, (uint32_t)b).cls];
+  } else if (l == 1) {
+    s = P.l0.sec1[block_pos(g, P.l0, (uint32_t)b).cls];
   } else {
     int64_t o[3], hi[3];
     block_ext(g, b, o, hi);
@@ -604,49 +609,50 @@ __global__ __launch_bounds__(kBS) void k_pack(EncPlan P) {
   const uint32_t c0 = tile * 64, tn = min(64u, nch - c0);
   uint8_t *out = P.out + so;
   const int64_t slot0 = s0 + c0;
-  if (wave == 0) {
-    const bool on = (uint32_t)lane < tn;
-    const U4 cur = on ? P.P[slot0 + lane] : U4{0, 0, 0, 0};
-    const U4 cc = on ? P.cnt[slot0 + lane] : U4{0, 0, 0, 0};
-    const uint32_t base_w = __builtin_amdgcn_readfirstlane(cur.x);
-    const uint32_t pw = cur.x - base_w;  // payload words of the tile before this chunk
-    if (lane == 0) {
-      uint32_t *tt = reinterpret_cast<uint32_t *>(out + 16 + 12 * (uint64_t)tile);
-      tt[0] = cur.x - a.x;
-      tt[1] = cur.y - a.y;
-      tt[2] = cur.z - a.z;
-    }
-    if (on) {
-      out[A + c0 + lane] = (uint8_t)(cc.x | (cc.y ? 0x80u : 0u));
-      if (cc.y) {
-        uint32_t *m = reinterpret_cast<uint32_t *>(out + Moff + 8 * (uint64_t)(cur.y - a.y));
-        const unsigned long long em = P.emask[slot0 + lane];
-        m[0] = (uint32_t)em;
-        m[1] = (uint32_t)(em >> 32);
-      }
-      for (uint32_t k = 0; k < cc.x; k++) s_own[pw + k] = (uint16_t)lane;
-    }
-    s_pw[lane] = pw;
-    s_px[lane] = cur.z - a.z;
-    s_nx[lane] = on ? cc.z : 0u;
-    if ((uint32_t)lane == tn - 1) s_tot = pw + cc.x;
-    if (lane == 0) s_base = cur.x - a.x;
+  const bool on = (uint32_t)lane < tn;
+  const U4 cur = on ? P.P[slot0 + lane] : U4{0, 0, 0, 0};
+  const U4 cc = on ? P.cnt[slot0 + lane] : U4{0, 0, 0, 0};
+  const unsigned long long em = (on && cc.y) ? P.emask[slot0 + lane] : 0ull;
+  const uint32_t base_w = __builtin_amdgcn_readfirstlane(cur.x);
+  const uint32_t pw = cur.x - base_w;  // payload words of the tile before this chunk
+  if (lane == 0) {
+    uint32_t *tt = reinterpret_cast<uint32_t *>(out + 16 + 12 * (uint64_t)tile);
+    tt[0] = cur.x - a.x;
+    tt[1] = cur.y - a.y;
+    tt[2] = cur.z - a.z;
   }
-  __syncthreads();
+  if (on) {
+    out[A + c0 + lane] = (uint8_t)(cc.x | (cc.y ? 0x80u : 0u));
+    if (cc.y) {
+      uint32_t *m = reinterpret_cast<uint32_t *>(out + Moff + 8 * (uint64_t)(cur.y - a.y));
+      m[0] = (uint32_t)em;
+      m[1] = (uint32_t)(em >> 32);
+    }
+    for (uint32_t k = 0; k < cc.x; k++) s_own[pw + k] = (uint16_t)lane;
+  }
+  s_pw[lane] = pw;
+  const uint32_t tot = __shfl(pw + cc.x, (int)tn - 1, kWave);  // payload words of the tile
+  const uint32_t base = cur.x - a.x;                            // (lane 0's) before the tile
+  const uint32_t base0 = __builtin_amdgcn_readfirstlane(base);
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
   // payload: 8-byte words of the tile in stream order
-  const uint32_t tot = s_tot, base = s_base;
   const unsigned long long *__restrict__ pay = reinterpret_cast<const unsigned long long *>(P.pay);
-  unsigned long long *__restrict__ dst = reinterpret_cast<unsigned long long *>(out + Poff) + base;
-  for (uint32_t u = threadIdx.x; u < tot; u += kBS) {
+  unsigned long long *__restrict__ dst = reinterpret_cast<unsigned long long *>(out + Poff) + base0;
+  for (uint32_t u = (uint32_t)lane; u < tot; u += kWave) {
     const uint32_t c = s_own[u];
     dst[u] = pay[(slot0 + c) * 16 + (u - s_pw[c])];
   }
-  // exact values: one wave per chunk that has any
+  // exact values of the chunks that have any, one chunk at a time
   const uint32_t *__restrict__ exv = reinterpret_cast<const uint32_t *>(P.exv);
   uint32_t *xo = reinterpret_cast<uint32_t *>(out + Xoff);
-  for (uint32_t c = (uint32_t)wave; c < tn; c += kWaves) {
-    const uint32_t nx = s_nx[c];
-    if ((uint32_t)lane < nx) xo[s_px[c] + lane] = exv[(slot0 + c) * 64 + lane];
+  const uint32_t px = cur.z - a.z;
+  unsigned long long mx = __ballot(on && cc.z > 0);
+  while (mx) {
+    const int c = __builtin_ctzll(mx);
+    mx &= mx - 1;
+    const uint32_t nx = __shfl(cc.z, c, kWave), pxc = __shfl(px, c, kWave);
+    if ((uint32_t)lane < nx) xo[pxc + lane] = exv[(slot0 + c) * 64 + lane];
   }
 }
 
@@ -894,7 +900,7 @@ void launch_encode(const EncPlan &p, int64_t, U4 *scan_tmp, uint64_t *scan_tmp64
   const int64_t npack = p.pack_base[0] + g.nblocks * p.pack_gpb[0];
   if (p.nslots > 0 && npack > 0) {
     prof_mark("k_pack", s, 0);
-    k_pack<<<dim3((unsigned)npack), dim3(kBS), 0, s>>>(p);
+    k_pack<<<dim3((unsigned)ceil_div(npack, kWaves)), dim3(kBS), 0, s>>>(p);
     prof_mark("k_pack", s, 1);
   }
   prof_mark("k_block_table", s, 0);
