@@ -142,11 +142,13 @@ EncLayout enc_layout(EncPlan &P) {
   Lo.off_emask = o; o = align256(o + sizeof(uint64_t) * (size_t)P.nslots);
   Lo.off_exv = o; o = align256(o + sizeof(float) * 64 * (size_t)P.nslots);
   P.part_l1 = encode_fine_groups(P);
-  P.part_per_block = P.part_l1 + encode_l1_groups(P) + 1;
+  P.part_l2 = P.part_l1 + encode_l1_groups(P);
+  P.part_per_block = P.part_l2 + encode_l2_groups(P) + 1;
+  P.l2fast = encode_l2_fast(P) ? 1 : 0;
   {
     EncPlan q = P;
     q.cpw0 = 1;  // workspace sized for the finest level-0 tiling
-    const int64_t ppb_max = encode_fine_groups(q) + encode_l1_groups(q) + 1;
+    const int64_t ppb_max = encode_fine_groups(q) + encode_l1_groups(q) + encode_l2_groups(q) + 1;
     Lo.part_records = (size_t)(g.nblocks * ppb_max);
   }
   encode_pack_layout(P);

@@ -275,8 +275,10 @@ __device__ inline void stf(char *__restrict__ base, uint32_t off, float v) {
 struct L0Geo {
   Sec sec[8];    // level 0
   Sec sec1[8];   // level 1 (when the hierarchy has one)
+  Sec sec2[8];   // level 2 (when the hierarchy has one)
   SecR rc[8];    // level-0 reciprocals (valid when small)
   SecR rc1[8];   // level-1 reciprocals
+  SecR rc2[8];   // level-2 reciprocals
   FastDiv d_nb2, d_nb1;
   uint32_t nb[3];
   int small;     // every level-0 section has < 2^21 points and the index
@@ -293,8 +295,10 @@ __host__ inline void make_l0geo(const Geo &g, L0Geo &G) {
     block_ext(g, (bz * g.nb[1] + by) * g.nb[2] + bx, o, hi);
     G.sec[cls] = sec_geom(o, hi, 0, g.nL - 1);
     G.sec1[cls] = sec_geom(o, hi, g.nL >= 2 ? 1 : 0, g.nL - 1);
+    G.sec2[cls] = sec_geom(o, hi, g.nL >= 3 ? 2 : 0, g.nL - 1);
     G.rc[cls] = sec_rcp(G.sec[cls]);
     G.rc1[cls] = sec_rcp(G.sec1[cls]);
+    G.rc2[cls] = sec_rcp(G.sec2[cls]);
   }
   // row products w * n1 + y and plane offsets of the field and of the
   // level-1 grid within a block's slab, as 24-bit multiplier operands

@@ -38,8 +38,10 @@ struct EncPlan {
   unsigned long long *emask;     // nslots
   float *exv;                    // nslots * 64
   Part *part;                    // per block: part_per_block workgroup records
-  int64_t part_per_block;        // records per block: level-0 workgroups, level-1 workgroups, coarse levels
+  int64_t part_per_block;        // records per block: level-0, level-1 and level-2 workgroups, coarse levels
   int64_t part_l1;               // first level-1 record of a block
+  int64_t part_l2;               // first level-2 record of a block
+  int l2fast;                    // level 2 runs in its own wide kernel (else with the coarse levels)
   Part *bst;                     // per block reduction of its records
   uint32_t *csum;                // per block, kSumSegs partial checksums of its byte range
   int64_t pack_base[kMaxLevels]; // first packing workgroup of each level
@@ -95,6 +97,8 @@ void launch_encode(const EncPlan &p, int64_t scan_tmp_elems_u4, U4 *scan_tmp, ui
                    hipStream_t s);
 int64_t encode_fine_groups(const EncPlan &p);   // level-0 workgroups per block
 int64_t encode_l1_groups(const EncPlan &p);     // level-1 workgroups per block
+int64_t encode_l2_groups(const EncPlan &p);     // level-2 workgroups per block (records reserved)
+bool encode_l2_fast(const EncPlan &p);          // whether level 2 runs in its own wide kernel
 void encode_pack_layout(EncPlan &p);            // fills pack_base / pack_gpb
 void launch_decode(const DecPlan &p, hipStream_t s);
 void launch_status_reset(int32_t *status, hipStream_t s);  // *status = 0 by a kernel (capturable)

@@ -296,15 +296,15 @@ __global__ __launch_bounds__(kBS) void k_decode_level(DecPlan D, int l) {
   });
 }
 
-// Levels 0 and 1 below a coarser level (level LV + 1 exists) over (tile
+// Levels 0, 1 and 2 below a coarser level (level LV + 1 exists) over (tile
 // groups, blocks), for block shapes whose index products fit 24 bits: each
-// wave decodes CPW consecutive chunks of one tile (P.cpw0 at level 0, 16 at
-// level 1), with block geometry and reciprocals from the host-filled shape
+// wave decodes CPW consecutive chunks of one tile (P.cpw0 at level 0, 16
+// above), with block geometry and reciprocals from the host-filled shape
 // table and block-relative 32-bit offsets from uniform base pointers (the
 // block's first plane of the output and of the parent grid).  Level 0 writes
 // the points the block owns plus the even points of even rows taken from
-// level 1; level 1 writes every point of its section into the level-1 grid,
-// after carrying the block's level-2 points over into it.
+// level 1; levels 1 and 2 write every point of their section into grid LV,
+// after carrying the block's points of grid LV + 1 over into it.
 template <int LV>
 __device__ __forceinline__ void decode_fast(const DecPlan &D) {
   const Geo &g = D.g;
@@ -314,15 +314,16 @@ __device__ __forceinline__ void decode_fast(const DecPlan &D) {
   const uint32_t wave = wave_index();
   const int lane = lane_id();
   const BlockPos bp = block_pos(g, D.l0, b);
-  if (LV == 1) {
-    // one row of the block's level-2 grid per wave step
-    const uint32_t c0 = ((bp.hi[0] - bp.o[0]) >> 2) + 1, c1 = ((bp.hi[1] - bp.o[1]) >> 2) + 1;
-    const uint32_t c2 = ((bp.hi[2] - bp.o[2]) >> 2) + 1;
-    const float *src = D.gp[2];
-    float *dst = D.gp[1];
-    const uint32_t zo = bp.o[0] >> 2, yo = bp.o[1] >> 2, xo = bp.o[2] >> 2;
-    const uint32_t s1 = (uint32_t)D.gd[2][1], s2 = (uint32_t)D.gd[2][2];
-    const uint32_t d1 = (uint32_t)D.gd[1][1], d2 = (uint32_t)D.gd[1][2];
+  if (LV >= 1) {
+    // one row of the block's grid LV + 1 per wave step
+    constexpr int sh = LV + 1;
+    const uint32_t c0 = ((bp.hi[0] - bp.o[0]) >> sh) + 1, c1 = ((bp.hi[1] - bp.o[1]) >> sh) + 1;
+    const uint32_t c2 = ((bp.hi[2] - bp.o[2]) >> sh) + 1;
+    const float *src = D.gp[LV + 1];
+    float *dst = D.gp[LV];
+    const uint32_t zo = bp.o[0] >> sh, yo = bp.o[1] >> sh, xo = bp.o[2] >> sh;
+    const uint32_t s1 = (uint32_t)D.gd[LV + 1][1], s2 = (uint32_t)D.gd[LV + 1][2];
+    const uint32_t d1 = (uint32_t)D.gd[LV][1], d2 = (uint32_t)D.gd[LV][2];
     for (uint32_t r = gxi * kWaves + wave; r < c0 * c1; r += gridDim.x * kWaves) {
       const uint32_t w = r / c1, v = r - w * c1;
       const size_t srow = ((size_t)(zo + w) * s1 + (yo + v)) * s2 + xo;
@@ -333,7 +334,7 @@ __device__ __forceinline__ void decode_fast(const DecPlan &D) {
   const uint32_t cpw = LV == 0 ? (uint32_t)D.cpw0 : 16u;
   const uint32_t cbeg = (gxi * kWaves + wave) * cpw;  // first chunk of this wave
   const uint32_t t = cbeg >> 6, kbeg = cbeg & 63u;
-  const Sec s = LV == 0 ? D.l0.sec[bp.cls] : D.l0.sec1[bp.cls];  // by value: scalar registers
+  const Sec s = LV == 0 ? D.l0.sec[bp.cls] : LV == 1 ? D.l0.sec1[bp.cls] : D.l0.sec2[bp.cls];  // scalar registers
   const uint32_t nch = (s.npts + 63) / 64;
   if (t >= (nch + 63) / 64) return;
   const SecView v = open_section(D, b, LV, s.npts);
@@ -346,10 +347,10 @@ __device__ __forceinline__ void decode_fast(const DecPlan &D) {
   const uint32_t ownz = bp.own[0] - bp.o[0], owny = bp.own[1], ownx = bp.own[2];
   const bool lastx = (bp.hi[2] == (uint32_t)g.n[2] - 1);
   const bool all = D.prune != 0;
-  // output: the field (level 0) or the level-1 grid, from the block's first plane
-  const uint32_t f1 = (uint32_t)D.gd[1][1], f2 = (uint32_t)D.gd[1][2];
+  // output: the field (level 0) or grid LV, from the block's first plane
+  const uint32_t f1 = (uint32_t)D.gd[LV][1], f2 = (uint32_t)D.gd[LV][2];
   char *__restrict__ obase = LV == 0 ? reinterpret_cast<char *>(D.out + (size_t)bp.o[0] * n1 * n2)
-                                     : reinterpret_cast<char *>(D.gp[1] + (size_t)(bp.o[0] >> 1) * f1 * f2);
+                                     : reinterpret_cast<char *>(D.gp[LV] + (size_t)(bp.o[0] >> LV) * f1 * f2);
   const uint32_t h0 = (uint32_t)D.gd[LV + 1][0], h1 = (uint32_t)D.gd[LV + 1][1], h2 = (uint32_t)D.gd[LV + 1][2];
   const uint32_t zp = bp.o[0] >> (LV + 1);
   // uniform bases; the launcher guarantees the block's slab spans < 4 GiB
@@ -379,7 +380,7 @@ __device__ __forceinline__ void decode_fast(const DecPlan &D) {
   const uint32_t nc = min(min(64u, v.nch - t * 64), kbeg + cpw);
   const char *__restrict__ payb = reinterpret_cast<const char *>(v.p + v.Poff);
   const char *__restrict__ exvb = reinterpret_cast<const char *>(v.p + v.Xoff);
-  const SecR rc = LV == 0 ? D.l0.rc[bp.cls] : D.l0.rc1[bp.cls];
+  const SecR rc = LV == 0 ? D.l0.rc[bp.cls] : LV == 1 ? D.l0.rc1[bp.cls] : D.l0.rc2[bp.cls];
   const uint32_t jmax = s.npts - 1;  // npts > 0: this wave's tile holds a chunk
   const uint32_t hi2 = bp.hi[2];
   // kDecGroup chunks at a time: coordinates and addresses of all of them,
@@ -477,6 +478,7 @@ __device__ __forceinline__ void decode_fast(const DecPlan &D) {
 
 __global__ __launch_bounds__(kBS) void k_decode_l0(DecPlan D) { decode_fast<0>(D); }
 __global__ __launch_bounds__(kBS) void k_decode_l1(DecPlan D) { decode_fast<1>(D); }
+__global__ __launch_bounds__(kBS) void k_decode_l2(DecPlan D) { decode_fast<2>(D); }
 
 // Even points of even rows in blocks one point wide along x (no level-0
 // point in those rows writes them).
@@ -550,6 +552,8 @@ void launch_decode(const DecPlan &p, hipStream_t s) {
       prof_mark(l == 1 ? "k_decode_l1" : "k_decode_l2", s, 0);
       if (l == 1 && L >= 2 && slab32 && p.l0.small)
         k_decode_l1<<<grid, dim3(kBS), 0, s>>>(p);  // one tile per workgroup: 16 chunks per wave
+      else if (l == 2 && L >= 3 && slab32 && p.l0.small)
+        k_decode_l2<<<grid, dim3(kBS), 0, s>>>(p);
       else
         k_decode_level<<<grid, dim3(kBS), 0, s>>>(p, l);
       prof_mark(l == 1 ? "k_decode_l1" : "k_decode_l2", s, 1);

@@ -206,7 +206,7 @@ __device__ inline void owned_end(const Geo &g, const int64_t o[3], int64_t own[3
 
 // Levels nL-1 .. 2 of one block per workgroup.
 template <int KB>
-__global__ __launch_bounds__(kBS) void k_encode_coarse(EncPlan P) {
+__global__ __launch_bounds__(kBS) void k_encode_coarse(EncPlan P, int lmin) {
   __shared__ uint32_t pack[kWaves][32];
   const Geo &g = P.g;
   const int L = g.nL - 1;
@@ -217,7 +217,7 @@ __global__ __launch_bounds__(kBS) void k_encode_coarse(EncPlan P) {
   owned_end(g, o, own);
   Part acc;
   part_init(acc);
-  for (int l = L; l >= 2; l--) {
+  for (int l = L; l >= lmin; l--) {
     if (l < L) {
       // the block's points of the coarser grid carry over unchanged
       const int sh = l + 1;
@@ -316,13 +316,13 @@ __device__ inline void pack_chunk(const EncPlan &P, int64_t slot, uint32_t zz, b
   __builtin_amdgcn_wave_barrier();
 }
 
-// Levels 0 and 1 below a coarser level (level LV + 1 exists): the
+// Levels 0, 1 and 2 below a coarser level (level LV + 1 exists): the
 // arithmetic of enc_chunk with the level fixed, for block shapes whose index
 // products fit 24 bits (the host table's reciprocals divide the section
 // index; 32-bit byte offsets from uniform bases: the block's first plane of
-// the field, of the parent grid LV + 1 and, at level 1, of the level-1 grid
-// it fills).  A wave handles CPW chunks (P.cpw0 at level 0, kChunksPerWave at
-// level 1), G at a time: the loads of all G are issued first, every value is
+// the field, of the parent grid LV + 1 and, above level 0, of grid LV, which
+// it fills).  A wave handles CPW chunks (P.cpw0 at level 0, kChunksPerWave
+// above), G at a time: the loads of all G are issued first, every value is
 // computed before any branch or store, so a wave keeps several chunks' reads
 // in flight and no load is left pending on a path.  The optional per-point
 // outputs are compiled in only when requested.
@@ -336,14 +336,14 @@ __device__ __forceinline__ void encode_fast(const EncPlan &P, uint32_t (*pack)[3
   // stays in scalar registers across the loop's stores.
   const Geo &gq = P.g;
   const BlockPos bp = block_pos(gq, P.l0, b);
-  if (LV == 1) {
-    // the block's level-2 points carry over into the level-1 grid unchanged
+  if (LV >= 1) {
+    // the block's points of grid LV + 1 carry over into grid LV unchanged
     const int64_t o[3] = {bp.o[0], bp.o[1], bp.o[2]}, hi[3] = {bp.hi[0], bp.hi[1], bp.hi[2]};
-    copy_coarse(P.G + P.g_off[2], P.gd[2], P.G + P.g_off[1], P.gd[1], o, hi, 2, gxi * kWaves + wave,
-                gridDim.x * kWaves);
+    copy_coarse(P.G + P.g_off[LV + 1], P.gd[LV + 1], P.G + P.g_off[LV], P.gd[LV], o, hi, LV + 1,
+                gxi * kWaves + wave, gridDim.x * kWaves);
   }
-  const Sec s = LV == 0 ? P.l0.sec[bp.cls] : P.l0.sec1[bp.cls];
-  const SecR rc = LV == 0 ? P.l0.rc[bp.cls] : P.l0.rc1[bp.cls];
+  const Sec s = LV == 0 ? P.l0.sec[bp.cls] : LV == 1 ? P.l0.sec1[bp.cls] : P.l0.sec2[bp.cls];
+  const SecR rc = LV == 0 ? P.l0.rc[bp.cls] : LV == 1 ? P.l0.rc1[bp.cls] : P.l0.rc2[bp.cls];
   const uint32_t nch = (s.npts + 63) / 64;
   const uint32_t maxch = (uint32_t)P.maxch[LV];
   const uint32_t n1 = (uint32_t)gq.n[1], n2 = (uint32_t)gq.n[2];
@@ -351,11 +351,11 @@ __device__ __forceinline__ void encode_fast(const EncPlan &P, uint32_t (*pack)[3
   const uint32_t oyl = bp.o[1] >> LV, oxl = bp.o[2] >> LV;
   const uint32_t h0 = (uint32_t)P.gd[LV + 1][0], h1 = (uint32_t)P.gd[LV + 1][1], h2 = (uint32_t)P.gd[LV + 1][2];
   const uint32_t zp = bp.o[0] >> (LV + 1);
-  const uint32_t f1 = (uint32_t)P.gd[1][1], f2 = (uint32_t)P.gd[1][2];
+  const uint32_t f1 = (uint32_t)P.gd[LV][1], f2 = (uint32_t)P.gd[LV][2];  // grid LV (filled for LV >= 1)
   // uniform bases; the launcher guarantees the block's slab spans < 4 GiB
   const char *__restrict__ xbase = reinterpret_cast<const char *>(P.x + (size_t)bp.o[0] * n1 * n2);
   const char *__restrict__ Pb = reinterpret_cast<const char *>(P.G + P.g_off[LV + 1] + (size_t)zp * h1 * h2);
-  char *__restrict__ G1b = reinterpret_cast<char *>(P.G + P.g_off[1] + (size_t)(bp.o[0] >> 1) * f1 * f2);
+  char *__restrict__ GLb = reinterpret_cast<char *>(P.G + P.g_off[LV] + (size_t)(bp.o[0] >> LV) * f1 * f2);
   const uint32_t h2x4 = h2 * 4u, h12x4 = h1 * h2 * 4u;
   const uint32_t ownz = bp.own[0] - bp.o[0], owny = bp.own[1], ownx = bp.own[2];
   const int64_t slot0 = P.slot_base[LV] + (int64_t)b * maxch;
@@ -406,7 +406,7 @@ __device__ __forceinline__ void encode_fast(const EncPlan &P, uint32_t (*pack)[3
       in[u] = jr < s.npts;
       own[u] = zr < ownz && y < owny && xx < ownx;
       gi[u] = AUX ? mad24s(prow, n2, xx) : 0u;                  // the point in the block's slab
-      go[u] = LV == 1 ? mad24s(mad24s(w, f1, V), f2, U) * 4u : 0u;  // its slot in the level-1 grid
+      go[u] = LV >= 1 ? mad24s(mad24s(w, f1, V), f2, U) * 4u : 0u;  // its slot in grid LV
     }
     // every point's arithmetic before any branch, so every load is consumed
     // on every path (lanes past the section compute on their clamped point
@@ -451,8 +451,8 @@ __device__ __forceinline__ void encode_fast(const EncPlan &P, uint32_t (*pack)[3
         if (lane == 0) cnt[slot] = U4{0, 0, 0, 0};
         continue;
       }
-      // level 1: the reconstructed value is the level-0 kernel's parent
-      if (LV == 1 && in[u]) stf(G1b, go[u], xrs[u]);
+      // levels >= 1: the reconstructed value is a parent of the next level
+      if (LV >= 1 && in[u]) stf(GLb, go[u], xrs[u]);
       const float x = xs[u];
       const uint32_t zz = zzs[u];
       const bool E = Es[u];
@@ -481,7 +481,7 @@ __device__ __forceinline__ void encode_fast(const EncPlan &P, uint32_t (*pack)[3
       __builtin_amdgcn_wave_barrier();
     }
   }
-  part_store(acc, &P.part[(int64_t)b * P.part_per_block + (LV == 0 ? 0 : P.part_l1) + gxi]);
+  part_store(acc, &P.part[(int64_t)b * P.part_per_block + (LV == 0 ? 0 : LV == 1 ? P.part_l1 : P.part_l2) + gxi]);
 }
 
 template <bool AUX, int KB, int G>
@@ -494,6 +494,12 @@ template <bool AUX, int KB, int G>
 __global__ __launch_bounds__(kBS) void k_encode_l1s(EncPlan P) {
   __shared__ uint32_t pack[kWaves][32];
   encode_fast<1, AUX, KB, G>(P, pack);
+}
+
+template <bool AUX, int KB, int G>
+__global__ __launch_bounds__(kBS) void k_encode_l2s(EncPlan P) {
+  __shared__ uint32_t pack[kWaves][32];
+  encode_fast<2, AUX, KB, G>(P, pack);
 }
 
 // Byte size of every section from the scanned chunk sizes.
@@ -721,10 +727,12 @@ __global__ __launch_bounds__(kBS) void k_block_table(EncPlan P) {
   const Part *rec = P.part + b * P.part_per_block;
   const int L = g.nL - 1;
   for (int64_t i = threadIdx.x; i < P.part_per_block; i += kBS) {
-    // records exist for level-0 workgroups, level-1 workgroups (nL >= 2) and
-    // the coarse-level workgroup (nL >= 3)
+    // records exist for level-0 workgroups, level-1 workgroups (nL >= 2),
+    // level-2 workgroups (when level 2 has its own kernel) and the
+    // coarse-level workgroup (nL >= 3)
     if (i == P.part_per_block - 1 && L < 2) continue;
-    if (i >= P.part_l1 && i < P.part_per_block - 1 && L < 1) continue;
+    if (i >= P.part_l1 && i < P.part_l2 && L < 1) continue;
+    if (i >= P.part_l2 && i < P.part_per_block - 1 && !P.l2fast) continue;
     const Part r = rec[i];
     acc.rmin = min(acc.rmin, r.rmin); acc.rmax = max(acc.rmax, r.rmax);
     acc.xmin = min(acc.xmin, r.xmin); acc.xmax = max(acc.xmax, r.xmax);
@@ -823,6 +831,18 @@ int64_t encode_fine_groups(const EncPlan &p) { return ceil_div(p.maxch[0], (int6
 int64_t encode_l1_groups(const EncPlan &p) {
   return p.g.nL >= 2 ? ceil_div(p.maxch[1] > 0 ? p.maxch[1] : 1, (int64_t)kChunksPerWG) : 0;
 }
+int64_t encode_l2_groups(const EncPlan &p) {
+  return p.g.nL >= 4 ? ceil_div(p.maxch[2] > 0 ? p.maxch[2] : 1, (int64_t)kChunksPerWG) : 0;
+}
+
+// A block's slab of planes spans < 4 GiB (the specialized kernels' 32-bit offsets).
+static bool slab32(const Geo &g) {
+  int64_t o[3], hi[3];
+  block_ext(g, 0, o, hi);
+  return 4.0 * (double)(hi[0] - o[0] + 1) * (double)g.n[1] * (double)g.n[2] < 4294967296.0;
+}
+
+bool encode_l2_fast(const EncPlan &p) { return p.g.nL >= 4 && slab32(p.g) && p.l0.small; }
 
 void encode_pack_layout(EncPlan &p) {
   const int L = p.g.nL - 1;
@@ -842,42 +862,40 @@ void launch_encode_levels(const EncPlan &p, hipStream_t s) {
   const int64_t gx = encode_fine_groups(p);
   if (L >= 2) {
     prof_mark("k_encode_coarse", s, 0);
-    k_encode_coarse<KB><<<dim3((unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
+    k_encode_coarse<KB><<<dim3((unsigned)g.nblocks), dim3(kBS), 0, s>>>(p, p.l2fast ? 3 : 2);
+    if (p.l2fast) {
+      const dim3 grid2((unsigned)encode_l2_groups(p), (unsigned)g.nblocks);
+      if (!p.codes && !p.flags) k_encode_l2s<false, KB, 4><<<grid2, dim3(kBS), 0, s>>>(p);
+      else k_encode_l2s<true, KB, 1><<<grid2, dim3(kBS), 0, s>>>(p);
+    }
     prof_mark("k_encode_coarse", s, 1);
   }
+  // the specialized kernels: 32-bit offsets within a block's slab and the
+  // full-rate index arithmetic of small block shapes
+  const bool fast = slab32(g) && p.l0.small;
   if (L >= 1) {
-    int64_t o[3], hi[3];
-    block_ext(g, 0, o, hi);
-    const bool slab32 = 4.0 * (double)(hi[0] - o[0] + 1) * (double)g.n[1] * (double)g.n[2] < 4294967296.0;
     const dim3 grid1((unsigned)encode_l1_groups(p), (unsigned)g.nblocks);
     prof_mark("k_encode_l1", s, 0);
-    if (L >= 2 && slab32 && p.l0.small && !p.codes && !p.flags)
+    if (L >= 2 && fast && !p.codes && !p.flags)
       k_encode_l1s<false, KB, 4><<<grid1, dim3(kBS), 0, s>>>(p);
-    else if (L >= 2 && slab32 && p.l0.small)
+    else if (L >= 2 && fast)
       k_encode_l1s<true, KB, 1><<<grid1, dim3(kBS), 0, s>>>(p);
     else
       k_encode_l1<KB><<<grid1, dim3(kBS), 0, s>>>(p);
     prof_mark("k_encode_l1", s, 1);
   }
   if (gx > 0) {
-    // the level-0 kernel addresses a block's slab of planes with 32-bit offsets
-    int64_t o[3], hi[3];
-    block_ext(g, 0, o, hi);
-    const bool slab32 = 4.0 * (double)(hi[0] - o[0] + 1) * (double)g.n[1] * (double)g.n[2] < 4294967296.0;
     prof_mark("k_encode_fine", s, 0);
     const dim3 grid0((unsigned)gx, (unsigned)g.nblocks);
-    // the specialized kernel: 32-bit offsets within a block's slab and the
-    // full-rate index arithmetic of small block shapes
-    const bool fast = L >= 1 && slab32 && p.l0.small;
-    if (fast && !p.codes && !p.flags) {
+    if (L >= 1 && fast && !p.codes && !p.flags) {
       if (p.cpw0 % 4 == 0) k_encode_l0<false, KB, 4><<<grid0, dim3(kBS), 0, s>>>(p);
       else if (p.cpw0 % 2 == 0) k_encode_l0<false, KB, 2><<<grid0, dim3(kBS), 0, s>>>(p);
       else k_encode_l0<false, KB, 1><<<grid0, dim3(kBS), 0, s>>>(p);
-    } else if (fast) {
+    } else if (L >= 1 && fast) {
       k_encode_l0<true, KB, 1><<<grid0, dim3(kBS), 0, s>>>(p);
+    } else {
+      k_encode_fine<KB><<<grid0, dim3(kBS), 0, s>>>(p);
     }
-    else
-      k_encode_fine<KB><<<dim3((unsigned)gx, (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
     prof_mark("k_encode_fine", s, 1);
   }
 }
