@@ -38,13 +38,15 @@ static_assert(kMaxTri <= 5, "triangle staging assumes at most 5 triangles per ce
 typedef unsigned long long u64;
 
 // f < k for 64 consecutive points per word.  One wave per row of points;
-// it issues the loads of kWordsPerWave words before their ballots.
+// it issues the loads of kWordsPerWave words (unconditional: past the row's
+// end a lane reads the row's last point and is masked) before their ballots,
+// and lane j stores word j, so the words of a step take one store.
 __global__ __launch_bounds__(kBS) void k_mc_bits(McPlan M) {
-  const int64_t row = (int64_t)blockIdx.x * kWaves + threadIdx.x / kWave;
+  const int64_t row = (int64_t)blockIdx.x * kWaves + wave_index();
   if (row >= M.nrows) return;
   const int lane = lane_id();
   const uint32_t nx = (uint32_t)M.n[2], nw = (uint32_t)M.nw;
-  const float *__restrict__ f = M.f + row * M.n[2];
+  const char *__restrict__ fb = reinterpret_cast<const char *>(M.f + row * M.n[2]);
   u64 *out = M.bits + row * M.nw;
   const float k = M.k;
   for (uint32_t w0 = 0; w0 < nw; w0 += kWordsPerWave) {
@@ -52,14 +54,16 @@ __global__ __launch_bounds__(kBS) void k_mc_bits(McPlan M) {
 #pragma unroll
     for (int j = 0; j < kWordsPerWave; j++) {
       const uint32_t x = (w0 + j) * 64u + (uint32_t)lane;
-      v[j] = (x < nx) ? f[x] : 0.f;
+      v[j] = ldf(fb, min(x, nx - 1u) * 4u);
     }
+    u64 mine = 0;
 #pragma unroll
     for (int j = 0; j < kWordsPerWave; j++) {
       const uint32_t x = (w0 + j) * 64u + (uint32_t)lane;
       const u64 m = __ballot((x < nx) && (v[j] < k));
-      if (lane == 0 && w0 + j < nw) out[w0 + j] = m;
+      if (lane == j) mine = m;
     }
+    if (lane < kWordsPerWave && w0 + (uint32_t)lane < nw) out[w0 + lane] = mine;
   }
 }
 
@@ -68,15 +72,19 @@ struct WordCtx {
   u64 valid, validx;   // points of the word / points with a +x neighbour
 };
 
-__device__ inline WordCtx word_ctx(const McPlan &M, int64_t gw) {
+// Word indices are below 2^26 (the launcher keeps padded points below
+// 2^32), so the split uses the launcher's 32-bit divisors.
+__device__ inline WordCtx word_ctx(const McPlan &M, int64_t gw64) {
   WordCtx c;
-  c.row = gw / M.nw;
-  c.w = gw - c.row * M.nw;
-  c.z = c.row / M.n[1];
-  c.y = c.row - c.z * M.n[1];
-  const int64_t rem = M.n[2] - c.w * 64;
+  const uint32_t gw = (uint32_t)gw64;
+  const uint32_t row = fdiv(gw, M.d_nw), z = fdiv(row, M.d_n1);
+  c.row = row;
+  c.w = gw - row * (uint32_t)M.nw;
+  c.z = z;
+  c.y = row - z * (uint32_t)M.n[1];
+  const int32_t rem = (int32_t)M.n[2] - (int32_t)c.w * 64;
   c.valid = rem >= 64 ? ~0ull : ((1ull << rem) - 1ull);
-  const int64_t remx = rem - 1;
+  const int32_t remx = rem - 1;
   c.validx = remx >= 64 ? ~0ull : (remx <= 0 ? 0ull : ((1ull << remx) - 1ull));
   return c;
 }
@@ -98,9 +106,10 @@ __device__ inline WordCtx32 word_ctx32(const McPlan &M, uint32_t gw) {
 // Word w of point row `row`, 0 past the row's last word.  The load itself is
 // unconditional (clamped to the last word), so that the loads of a lane's
 // words can all be in flight together.
-__device__ inline u64 bitsw(const McPlan &M, int64_t row, int64_t w) {
-  const bool in = w < M.nw;
-  const u64 v = M.bits[row * M.nw + (in ? w : M.nw - 1)];
+__device__ inline u64 bitsw(const McPlan &M, uint32_t row, uint32_t w) {
+  const uint32_t nw = (uint32_t)M.nw;
+  const bool in = w < nw;
+  const u64 v = M.bits[row * nw + (in ? w : nw - 1)];
   return in ? v : 0ull;
 }
 
@@ -111,19 +120,20 @@ struct Cross {
 // Crossing masks of the owned +x/+y/+z edges of word w of point row (z, y)
 // (all zero for a word past the row's end).  Rows past the grid are read as
 // the row itself and masked off.
-__device__ inline Cross cross_of(const McPlan &M, int64_t z, int64_t y, int64_t w) {
-  const bool inw = w < M.nw;
-  const int64_t wc = inw ? w : M.nw - 1;
-  const int64_t row = z * M.n[1] + y;
-  const int64_t rem = M.n[2] - wc * 64;
+__device__ inline Cross cross_of(const McPlan &M, uint32_t z, uint32_t y, uint32_t w) {
+  const uint32_t nw = (uint32_t)M.nw, n1 = (uint32_t)M.n[1];
+  const bool inw = w < nw;
+  const uint32_t wc = inw ? w : nw - 1;
+  const uint32_t row = z * n1 + y;
+  const int32_t rem = (int32_t)M.n[2] - (int32_t)wc * 64;
   const u64 valid = rem >= 64 ? ~0ull : ((1ull << rem) - 1ull);
-  const int64_t remx = rem - 1;
+  const int32_t remx = rem - 1;
   const u64 validx = remx >= 64 ? ~0ull : (remx <= 0 ? 0ull : ((1ull << remx) - 1ull));
-  const bool hy = y + 1 < M.n[1], hz = z + 1 < M.n[0];
+  const bool hy = y + 1 < n1, hz = z + 1 < (uint32_t)M.n[0];
   const u64 m = bitsw(M, row, wc);
   const u64 mn = bitsw(M, row, wc + 1);
   const u64 my = bitsw(M, hy ? row + 1 : row, wc);
-  const u64 mz = bitsw(M, hz ? row + M.n[1] : row, wc);
+  const u64 mz = bitsw(M, hz ? row + n1 : row, wc);
   Cross c;
   c.cx = inw ? (m ^ ((m >> 1) | (mn << 63))) & validx : 0ull;
   c.cy = (inw && hy) ? (m ^ my) & valid : 0ull;
@@ -138,9 +148,10 @@ struct Corners {
   u64 m[8];
 };
 
-__device__ inline Corners corners_of(const McPlan &M, int64_t row, int64_t w) {
+__device__ inline Corners corners_of(const McPlan &M, uint32_t row, uint32_t w) {
   Corners C;
-  const int64_t r[4] = {row, row + 1, row + M.n[1], row + M.n[1] + 1};  // (dy,dz) = 00, 10, 01, 11
+  const uint32_t n1 = (uint32_t)M.n[1];
+  const uint32_t r[4] = {row, row + 1, row + n1, row + n1 + 1};  // (dy,dz) = 00, 10, 01, 11
   for (int i = 0; i < 4; i++) {
     const u64 a = bitsw(M, r[i], w), b = bitsw(M, r[i], w + 1);
     C.m[2 * i] = a;               // corner dx = 0
@@ -280,32 +291,12 @@ __global__ __launch_bounds__(kBS) void k_mc_verts(McPlan M) {
   }
 }
 
-// Vertex id of the owner point at bit `xo` (0..64) of word w of a row, and
-// that point's +x / +y crossing bits (the vertex on its +y edge follows the
-// one on +x, the one on +z follows both).
+// Vertex id of an edge's owner point and that point's +x / +y crossing bits
+// (the vertex on its +y edge follows the one on +x, the one on +z follows
+// both).
 struct Owner {
   uint32_t base, bx, by;
 };
-
-__device__ inline Owner owner_at(const McPlan &M, uint32_t z, uint32_t y, uint32_t row, uint32_t w, const Cross &c,
-                                 uint32_t vb, int xo) {
-  // the owner may start the next word (inside the row because the cell is);
-  // both candidates are computed and the right one selected
-  const Cross c1 = cross_of(M, z, y, w + 1);
-  const uint32_t wn = w + 1 < (uint32_t)M.nw ? w + 1 : w;
-  const uint32_t vb1 = M.P[row * (uint32_t)M.nw + wn].x;
-  Owner o;
-  if (xo < 64) {
-    o.base = vb + (uint32_t)popc3_below(c, xo);
-    o.bx = (uint32_t)((c.cx >> xo) & 1ull);
-    o.by = (uint32_t)((c.cy >> xo) & 1ull);
-  } else {
-    o.base = vb1;
-    o.bx = (uint32_t)(c1.cx & 1ull);
-    o.by = (uint32_t)(c1.cy & 1ull);
-  }
-  return o;
-}
 
 // One lane per active cell: the ids of its 12 edge vertices go to LDS, then
 // its triangles in table order.  A workgroup takes 256 consecutive active
