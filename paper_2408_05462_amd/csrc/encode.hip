@@ -758,9 +758,13 @@ struct ResultDev {
 };
 
 // Stream header, table checksum, header checksum, and the result record.
+__device__ void header_words(const EncPlan &P, uint64_t total, bool fits, uint32_t sum, uint32_t (*red)[3],
+                             unsigned long long (*redc)[2], uint32_t *hdr);
+
 __global__ __launch_bounds__(kBS) void k_header(EncPlan P) {
   __shared__ uint32_t red[kWaves][3];
   __shared__ unsigned long long redc[kWaves][2];
+  __shared__ uint32_t hdr[kHeaderBytes / 4];
   const Geo &g = P.g;
   const uint64_t total = P.payload_off + P.secoff[g.nblocks * g.nL];
   const bool fits = total <= P.cap;
@@ -780,40 +784,55 @@ __global__ __launch_bounds__(kBS) void k_header(EncPlan P) {
   __syncthreads();
   uint32_t sum = 0;
   for (int sgm = 0; sgm < kSumSegs; sgm++) sum += P.csum[g.nblocks * kSumSegs + sgm];
-  if (threadIdx.x != 0) return;
+  if (threadIdx.x == 0) header_words(P, total, fits, sum, red, redc, hdr);
+  __syncthreads();
+  if (fits && threadIdx.x < kHeaderBytes / 4) put32(P, 4 * threadIdx.x, hdr[threadIdx.x]);
+}
+
+// Thread 0 of k_header: the header words and the compression result.
+__device__ void header_words(const EncPlan &P, uint64_t total, bool fits, uint32_t sum, uint32_t (*red)[3],
+                             unsigned long long (*redc)[2], uint32_t *hdr) {
+  const Geo &g = P.g;
   for (int i = 1; i < kWaves; i++) {
     red[0][0] = min(red[0][0], red[i][0]); red[0][1] = max(red[0][1], red[i][1]); red[0][2] |= red[i][2];
     redc[0][0] += redc[i][0]; redc[0][1] += redc[i][1];
   }
   const float vmin = of_ord(red[0][0]), vmax = of_ord(red[0][1]);
   if (fits) {
-    for (int i = 0; i < kHeaderBytes; i += 4) put32(P, i, 0u);
-    put32(P, 0, kMagic);
-    put32(P, 4, kVersion);
-    for (int a = 0; a < 3; a++) put64(P, 8 + 8 * a, (uint64_t)g.n[a]);
-    put32(P, 32, (uint32_t)g.nL);
-    put32(P, 36, (uint32_t)g.B);
-    put32(P, 40, (uint32_t)g.qmax);
-    put32(P, 44, (uint32_t)g.K);
+    // the header's words in LDS and its checksum from them; the workgroup
+    // writes them out together
+    uint32_t *h = hdr;
+    for (int i = 0; i < kHeaderBytes / 4; i++) h[i] = 0u;
+    auto h64 = [&](int off, uint64_t v) {
+      h[off / 4] = (uint32_t)v;
+      h[off / 4 + 1] = (uint32_t)(v >> 32);
+    };
+    h[0] = kMagic;
+    h[1] = kVersion;
+    for (int a = 0; a < 3; a++) h64(8 + 8 * a, (uint64_t)g.n[a]);
+    h[32 / 4] = (uint32_t)g.nL;
+    h[36 / 4] = (uint32_t)g.B;
+    h[40 / 4] = (uint32_t)g.qmax;
+    h[44 / 4] = (uint32_t)g.K;
     uint64_t eb;
     __builtin_memcpy(&eb, &g.e, 8);
-    put64(P, 48, eb);
-    put32(P, 56, __float_as_uint(g.inv));
-    put32(P, 60, __float_as_uint(g.step));
-    for (int j = 0; j < kMaxIso; j++) put32(P, 64 + 4 * j, __float_as_uint(j < g.K ? g.iso[j] : 0.0f));
-    put32(P, 128, __float_as_uint(vmin));
-    put32(P, 132, __float_as_uint(vmax));
-    put64(P, 136, (uint64_t)g.nblocks);
-    for (int a = 0; a < 3; a++) put32(P, 144 + 4 * a, (uint32_t)g.nb[a]);
-    put32(P, 156, g.lossless ? 1u : 0u);
-    put64(P, 160, total);
-    put64(P, 168, redc[0][0]);
-    put64(P, 176, redc[0][1]);
-    put64(P, 184, P.payload_off);
-    put32(P, 248, sum);
+    h64(48, eb);
+    h[56 / 4] = __float_as_uint(g.inv);
+    h[60 / 4] = __float_as_uint(g.step);
+    for (int j = 0; j < kMaxIso; j++) h[(64 + 4 * j) / 4] = __float_as_uint(j < g.K ? g.iso[j] : 0.0f);
+    h[128 / 4] = __float_as_uint(vmin);
+    h[132 / 4] = __float_as_uint(vmax);
+    h64(136, (uint64_t)g.nblocks);
+    for (int a = 0; a < 3; a++) h[(144 + 4 * a) / 4] = (uint32_t)g.nb[a];
+    h[156 / 4] = g.lossless ? 1u : 0u;
+    h64(160, total);
+    h64(168, redc[0][0]);
+    h64(176, redc[0][1]);
+    h64(184, P.payload_off);
+    h[248 / 4] = sum;
     uint32_t hs = 0;
-    for (uint32_t j = 0; j < 63; j++) hs += fmix32(get32(P, 4 * j) ^ (j * 0x9E3779B9u));
-    put32(P, 252, hs);
+    for (uint32_t j = 0; j < 63; j++) hs += fmix32(h[j] ^ (j * 0x9E3779B9u));
+    h[252 / 4] = hs;
   }
   ResultDev *r = reinterpret_cast<ResultDev *>(P.result);
   r->stream_bytes = total;

@@ -3,6 +3,7 @@
 // Three launches: per-tile totals (coalesced striped loads), one workgroup
 // scanning the tile totals, and a downsweep that scans each tile as eight
 // 256-element rows with wave-level shuffles and adds the tile's prefix.
+// Small inputs take one launch.
 #include "scan.h"
 
 #include "chr_device.h"
@@ -98,9 +99,43 @@ __global__ __launch_bounds__(kBS) void k_scan_down(const T *__restrict__ in, T *
   }
 }
 
+// The whole scan in one workgroup (small n): striped coalesced loads into
+// LDS, all in flight together; each thread then sums a consecutive run, one
+// workgroup scan places the runs, and each thread writes its run.
+template <class T>
+constexpr int64_t single_max() { return 32768 / (int64_t)sizeof(T); }  // 32 KiB of LDS
+
+template <class T>
+__global__ __launch_bounds__(kBS) void k_scan_single(const T *__restrict__ in, T *__restrict__ out, int64_t n) {
+  constexpr int64_t kMax = single_max<T>();
+  __shared__ T buf[kMax];
+  __shared__ T lds[kBS / kWave];
+#pragma unroll
+  for (int64_t i = 0; i < kMax / kBS; i++) {
+    const int64_t k = i * kBS + threadIdx.x;
+    if (k < n) buf[k] = in[k];
+  }
+  __syncthreads();
+  constexpr int64_t per = kMax / kBS;
+  const int64_t b0 = (int64_t)threadIdx.x * per, b1 = b0 + per < n ? b0 + per : n;
+  T s = zero<T>();
+  for (int64_t k = b0; k < b1; k++) s = add(s, buf[k]);
+  T tot;
+  T run = block_excl_scan(s, &tot, lds);
+  for (int64_t k = b0; k < b1; k++) {
+    out[k] = run;
+    run = add(run, buf[k]);
+  }
+  if (threadIdx.x == 0) out[n] = tot;
+}
+
 template <class T>
 void scan_impl(const T *in, T *out, int64_t n, T *tmp, hipStream_t s) {
-  int64_t ntiles = ceil_div(n > 0 ? n : 1, kTile);
+  if (n <= single_max<T>()) {
+    k_scan_single<T><<<dim3(1), dim3(kBS), 0, s>>>(in, out, n);
+    return;
+  }
+  int64_t ntiles = ceil_div(n, kTile);
   k_scan_reduce<T><<<dim3((unsigned)ntiles), dim3(kBS), 0, s>>>(in, tmp, n);
   k_scan_part<T><<<dim3(1), dim3(kBS), 0, s>>>(tmp, ntiles, out + n);
   k_scan_down<T><<<dim3((unsigned)ntiles), dim3(kBS), 0, s>>>(in, out, tmp, n);
