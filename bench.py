@@ -55,7 +55,10 @@ def parse_args():
     ap.add_argument("--no-topology", action="store_true", help="skip the error-translation part of the default run")
     ap.add_argument("--serve-requests", type=int, default=200, help="requests of the default run's served part")
     ap.add_argument("--batch-items", type=int, default=64, help="batch64: number of timesteps")
+    ap.add_argument("--branches", type=int, default=0, help="batch64: parallel branches of the graph (default: 4)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tiles", default="",
+                    help="level-0 chunks per wave 'E,D' for compression and reconstruction (default: the library's)")
     ap.add_argument("--cpu-planes", type=int, default=0,
                     help="z-planes of the field the oracle baseline runs on (0: automatic)")
     ap.add_argument("--kernel", default="", help="kernel timed with HIP events (default: the dominant one)")
@@ -146,6 +149,9 @@ def run_batch(args):
 
     t0 = time.time()
     batch = api.Batch(xs, es, isos, [p] * len(xs))
+    if args.branches:
+        c0 = batch.config()
+        batch.set_config(args.branches, c0["enc_cpw"], c0["dec_cpw"])
     batch.capture()
     cfg = batch.config()
     log(f"captured {cfg} in {time.time() - t0:.1f}s")
@@ -417,6 +423,10 @@ def main():
         print(json.dumps({"error": "bench.py measures one GPU only: every GPU box here has one GPU; "
                                    "run with --gpus 1"}))
         sys.exit(2)
+    if args.tiles:
+        from paper_2408_05462_amd import api as _api
+        e_cpw, d_cpw = (int(v) for v in args.tiles.split(","))
+        _api.chr_set_tiles(e_cpw, d_cpw)
     if args.workload == "batch64":
         return run_batch(args)
     if args.workload == "serve1024":

@@ -271,9 +271,9 @@ typedef struct chr_batch_item {
 typedef struct chr_batch chr_batch;
 
 /* Plans a batch (host only, no device call; items are copied).  Items are
- * spread over up to min(8, n_items) parallel branches, longest first onto
- * the least-loaded branch; level-0 tiles are those of chr_set_tiles at
- * creation.  Errors: CHR_E_INVAL (bad parameters, NULL
+ * spread over min(8, n_items) parallel branches by default (see
+ * chr_batch_set_config), longest first onto the least-loaded branch;
+ * level-0 tiles are those of chr_set_tiles at creation.  Errors: CHR_E_INVAL (bad parameters, NULL
  * pointer, bad mesh capacity; chr_last_error names the item),
  * CHR_E_CAPACITY (stream capacity below the header and tables). */
 int chr_batch_create(const chr_batch_item *items, int n_items, chr_batch **out);
@@ -308,6 +308,12 @@ int chr_batch_autotune(chr_batch *b, void *d_ws, size_t ws_bytes, void *stream, 
 
 /* Current configuration and the duration of the last timed replay (ms). */
 int chr_batch_config(const chr_batch *b, int *branches, int *enc_cpw, int *dec_cpw, float *last_ms);
+
+/* Sets the configuration by hand (branches 1 .. min(8, n_items); tiles as in
+ * chr_set_tiles) for the next chr_batch_run or chr_batch_capture; an earlier
+ * capture keeps its own until captured again.  Host only.  Errors:
+ * CHR_E_INVAL (NULL batch, a value out of range; nothing changes). */
+int chr_batch_set_config(chr_batch *b, int branches, int enc_cpw, int dec_cpw);
 
 /* Releases the batch's streams, events and graph (not the caller's buffers). */
 int chr_batch_destroy(chr_batch *b);

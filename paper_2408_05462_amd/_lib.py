@@ -24,7 +24,7 @@ EXPORTS = ["chr_last_error", "chr_version", "chr_compress_bound", "chr_compress_
            "chr_stream_info", "chr_stream_verify", "chr_reconstruct_workspace", "chr_reconstruct",
            "iso_workspace", "iso_extract", "iso_cases", "chr_mc_table", "chr_range", "chr_prof_enable",
            "chr_prof_collect", "chr_prof_disable", "chr_set_tiles", "chr_batch_create", "chr_batch_workspace",
-           "chr_batch_run", "chr_batch_capture", "chr_batch_replay", "chr_batch_autotune", "chr_batch_config",
+           "chr_batch_run", "chr_batch_capture", "chr_batch_replay", "chr_batch_autotune", "chr_batch_config", "chr_batch_set_config",
            "chr_batch_destroy", "chr_server_create", "chr_server_add_stream", "chr_server_submit",
            "chr_server_step", "chr_server_poll", "chr_server_release", "chr_server_cancel", "chr_server_stats_get",
            "chr_server_now_ms", "chr_server_destroy", "chr_topology_workspace", "chr_topology_error_bound",
@@ -149,6 +149,8 @@ def load():
     ip = C.POINTER(C.c_int)
     L.chr_batch_config.argtypes = [vp, ip, ip, ip, C.POINTER(C.c_float)]
     L.chr_batch_config.restype = C.c_int
+    L.chr_batch_set_config.argtypes = [vp, C.c_int, C.c_int, C.c_int]
+    L.chr_batch_set_config.restype = C.c_int
     L.chr_batch_destroy.argtypes = [vp]
     L.chr_batch_destroy.restype = C.c_int
     L.chr_server_create.argtypes = [C.POINTER(chr_server_config), C.POINTER(vp)]

@@ -244,7 +244,7 @@ def field_range(field):
 
 # ------------------------------------------------------------------ tiles and batches
 
-def chr_set_tiles(enc_chunks_per_wave=4, dec_chunks_per_wave=16):
+def chr_set_tiles(enc_chunks_per_wave=8, dec_chunks_per_wave=16):
     L.check(L.load().chr_set_tiles(int(enc_chunks_per_wave), int(dec_chunks_per_wave)), "chr_set_tiles")
 
 
@@ -333,6 +333,10 @@ class Batch:
         L.check(L.load().chr_batch_autotune(self.handle, _p(self.ws), self.ws.numel(), _s(stream),
                                             None if cache_path is None else str(cache_path).encode()),
                 "chr_batch_autotune")
+
+    def set_config(self, branches, enc_cpw=8, dec_cpw=16):
+        L.check(L.load().chr_batch_set_config(self.handle, int(branches), int(enc_cpw), int(dec_cpw)),
+                "chr_batch_set_config")
 
     def config(self):
         b, e, d, ms = C.c_int(), C.c_int(), C.c_int(), C.c_float()

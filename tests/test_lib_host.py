@@ -149,6 +149,14 @@ def test_batch_plan_workspace_and_rejections():
     b, e, d, ms = C.c_int(), C.c_int(), C.c_int(), C.c_float()
     assert lib.chr_batch_config(h, C.byref(b), C.byref(e), C.byref(d), C.byref(ms)) == L.CHR_OK
     assert 1 <= b.value <= len(shapes) and (e.value, d.value) == (8, 16)  # the process-wide tiles
+    # manual configuration: validated, applied whole or not at all
+    for bad_cfg in [(0, 8, 16), (len(shapes) + 1, 8, 16), (1, 3, 16), (1, 8, 12)]:
+        assert lib.chr_batch_set_config(h, *bad_cfg) == L.CHR_E_INVAL
+    assert lib.chr_batch_config(h, C.byref(b), C.byref(e), C.byref(d), C.byref(ms)) == L.CHR_OK
+    assert (e.value, d.value) == (8, 16)
+    assert lib.chr_batch_set_config(h, 1, 2, 32) == L.CHR_OK
+    assert lib.chr_batch_config(h, C.byref(b), C.byref(e), C.byref(d), C.byref(ms)) == L.CHR_OK
+    assert (b.value, e.value, d.value) == (1, 2, 32)
     # a replay before any capture is an error, not a launch
     assert lib.chr_batch_replay(h, None) == L.CHR_E_INVAL
     # the replay-timed autotuner is switched off: refused before any device call
