@@ -100,6 +100,22 @@ def test_batch_graph_replays_match_single_calls(data):
     b.close()
 
 
+def test_batch_branch_counts_give_the_same_outputs(data):
+    fields, xs, singles = data
+    for br, ec, dc in [(1, 8, 16), (3, 2, 32), (len(ITEMS), 16, 8)]:
+        b = _batch(fields, xs)
+        b.set_config(br, ec, dc)
+        b.capture()
+        assert b.config()["branches"] == br
+        for r in b.recon:
+            r.fill_(float("nan"))
+        torch.cuda.synchronize()
+        b.replay()
+        torch.cuda.synchronize()
+        _check(b, singles, f"branches {br}, tiles {ec}/{dc}")
+        b.close()
+
+
 @pytest.mark.skip(reason="chr_batch_autotune is switched off: one GPU run aborted inside its replay-timed search "
                          "(SIGABRT, no fault message) and the cause is not yet known")
 def test_batch_autotune_and_cache(data, tmp_path):
