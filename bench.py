@@ -87,6 +87,20 @@ def profile_traffic(kernel):
     return float(m.group(1))
 
 
+def workflow_model(raw_bytes, cr, stage_ms, link_gbps=1.0):
+    """The in-transit workflow of Sec. III as a model on the measured stages:
+    sending the raw field over a link of `link_gbps` and extracting the
+    isosurface at the receiver, against compressing, sending the stream,
+    reconstructing and extracting.  Speedup = raw / CHR time.  A model only:
+    no network is involved."""
+    link = link_gbps * 1e9 / 8.0
+    t_c, t_d, t_iso = (v * 1e-3 for v in stage_ms)
+    t_raw = raw_bytes / link + t_iso
+    t_chr = t_c + raw_bytes / cr / link + t_d + t_iso
+    return {"link_gbps": link_gbps, "raw_s": round(t_raw, 4), "chr_s": round(t_chr, 4),
+            "speedup": round(t_raw / t_chr, 2)}
+
+
 def run_batch(args):
     """64 timesteps of uneven sizes: plain per-item launches against the
     batch replayed as one captured graph (same outputs, checked)."""
@@ -584,6 +598,20 @@ def main():
         torch.cuda.synchronize()
         topo[label] = {"nth": nth, "bound": float(tout[0].item()), "ms": round(e0.elapsed_time(e1) / 3, 4)}
         topo["n_D"] = m
+        # the bound in use: compression just below it, without the per-vertex
+        # correction (no candidate isovalues); the share of cells whose case
+        # is unchanged at each isovalue (all of them below min(D))
+        e_t = float(np.nextafter(topo[label]["bound"], 0.0))
+        if e_t > 0 and np.isfinite(e_t):
+            ct = api.compress(x, e_t, [], levels=w["levels"], block=w["block"])
+            yt = api.reconstruct(ct, 0)
+            same = []
+            for kk in isos:
+                same.append(float((api.cases(yt, kk) == api.cases(x, kk)).double().mean().item()))
+            topo[label]["cells_same_case"] = same
+            topo[label]["compression_ratio"] = round(4.0 * N / int(ct.result["stream_bytes"]), 3)
+            del ct, yt
+            torch.cuda.empty_cache()
 
     # served latency on the same field (the metric's second half): requests
     # at random isovalues and accuracy tiers, continuous-batching server vs
@@ -635,6 +663,7 @@ def main():
         "n_corrected": r["n_corrected"], "triangles": [int(c[1]) for c in cnt],
         "wall_s_timed": round(wall, 3), "served": served, "topology_error_bound": topo or None, "roofline": roofline,
         "cpu_baseline": cpu,
+        "workflow_model": workflow_model(4.0 * N, cr, stage_ms),
     }
     print(json.dumps(out), flush=True)
 
