@@ -23,6 +23,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "chr_oracle.c")
+_SRC_ENT = os.path.join(_HERE, "chr_entropy.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 OK, E_INVAL, E_ACCURACY, E_LEVEL, E_CORRUPT, E_CAPACITY, E_NOMEM = 0, -1, -2, -3, -4, -5, -6
@@ -38,7 +39,7 @@ class OracleError(RuntimeError):
 def build() -> str:
     """Compile the oracle (gcc, -O2 -ffp-contract=off, OpenMP)."""
     cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
-           "-shared", "-std=c11", "-Wall", "-Wextra", _SRC, "-o", _LIB + ".tmp", "-lm"]
+           "-shared", "-std=c11", "-Wall", "-Wextra", _SRC, _SRC_ENT, "-o", _LIB + ".tmp", "-lm"]
     subprocess.check_call(cmd, cwd=_HERE)
     os.replace(_LIB + ".tmp", _LIB)
     return _LIB
@@ -82,6 +83,14 @@ def lib():
         L.orc_topology_error_bound.restype = C.c_double
         L.orc_stream_info.argtypes = [C.c_void_p, C.c_size_t, C.c_void_p]
         L.orc_threads.restype = C.c_int
+        u64p = C.POINTER(C.c_uint64)
+        L.orc_huff_lengths.argtypes = [C.c_void_p, C.c_int, C.c_void_p]
+        L.orc_huff_codes.argtypes = [C.c_void_p, C.c_void_p]
+        L.orc_entropy_bound.argtypes = [C.c_uint64, C.c_uint32, C.c_int]
+        L.orc_entropy_bound.restype = C.c_uint64
+        L.orc_entropy_encode.argtypes = [C.c_void_p, C.c_uint64, C.c_uint32, C.c_int, C.c_void_p, C.c_uint64, u64p]
+        L.orc_entropy_info.argtypes = [C.c_void_p, C.c_uint64, u64p, C.POINTER(C.c_uint32)]
+        L.orc_entropy_decode.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64, u64p]
         _lib = L
     return _lib
 
@@ -244,3 +253,56 @@ def topology_error_bound(f, isovalues, nth=1):
     nd = C.c_int64()
     r = lib().orc_topology_error_bound(pf, _dims(f.shape), iso.ctypes.data, len(iso), nth, C.byref(nd))
     return r, nd.value
+
+
+# ---- entropy stage (chr_entropy.c) ------------------------------------------
+ENTROPY_CHUNK = 512
+ENTROPY_MAXLEN = 12
+
+
+def huff_lengths(hist, maxlen=ENTROPY_MAXLEN):
+    """Code lengths of the 256 byte values from their counts."""
+    h = np.ascontiguousarray(np.asarray(hist, np.uint64).reshape(256))
+    out = np.zeros(256, np.uint8)
+    rc = lib().orc_huff_lengths(h.ctypes.data, maxlen, out.ctypes.data)
+    if rc:
+        raise OracleError(rc, "huff_lengths")
+    return out
+
+
+def huff_codes(lengths):
+    """Canonical codes (most significant bit first) of the lengths."""
+    ln = np.ascontiguousarray(np.asarray(lengths, np.uint8).reshape(256))
+    out = np.zeros(256, np.uint32)
+    rc = lib().orc_huff_codes(ln.ctypes.data, out.ctypes.data)
+    if rc:
+        raise OracleError(rc, "huff_codes")
+    return out
+
+
+def entropy_encode(data, chunk=ENTROPY_CHUNK, maxlen=ENTROPY_MAXLEN):
+    """The entropy stage's encoding of a byte string (uint8 array)."""
+    d = np.ascontiguousarray(np.frombuffer(bytes(data), np.uint8) if not isinstance(data, np.ndarray) else data,
+                             np.uint8)
+    cap = int(lib().orc_entropy_bound(d.size, chunk, maxlen))
+    out = np.zeros(max(cap, 1), np.uint8)
+    nb = C.c_uint64()
+    rc = lib().orc_entropy_encode(d.ctypes.data, d.size, chunk, maxlen, out.ctypes.data, cap, C.byref(nb))
+    if rc:
+        raise OracleError(rc, "entropy_encode")
+    return out[: nb.value].copy()
+
+
+def entropy_decode(enc):
+    """Decodes an entropy-stage stream (uint8 array) back to its bytes."""
+    e = np.ascontiguousarray(enc, np.uint8)
+    n = C.c_uint64()
+    ch = C.c_uint32()
+    rc = lib().orc_entropy_info(e.ctypes.data, e.size, C.byref(n), C.byref(ch))
+    if rc:
+        raise OracleError(rc, "entropy_info")
+    out = np.zeros(max(n.value, 1), np.uint8)
+    rc = lib().orc_entropy_decode(e.ctypes.data, e.size, out.ctypes.data, n.value, C.byref(n))
+    if rc:
+        raise OracleError(rc, "entropy_decode")
+    return out[: n.value].copy()

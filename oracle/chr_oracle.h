@@ -133,6 +133,25 @@ double orc_topology_error_bound(const float *f, const int64_t dims[3],
                                 const float *iso, int n_iso, int64_t nth,
                                 int64_t *n_d);
 
+/* ---- entropy stage (chr_entropy.c): order-0 Huffman over a byte stream ---- */
+
+/* Code lengths of the 256 byte values from their counts, at most maxlen
+ * bits (8..31); 0 for absent values, 1 for a value that is alone. */
+int orc_huff_lengths(const uint64_t hist[256], int maxlen, uint8_t len[256]);
+/* Canonical codes of the lengths (most significant bit first). */
+int orc_huff_codes(const uint8_t len[256], uint32_t code[256]);
+/* Encoded size bound of n bytes. */
+uint64_t orc_entropy_bound(uint64_t n, uint32_t chunk, int maxlen);
+/* Encodes n bytes (chunk bytes per independently decodable chunk, a multiple
+ * of 4; maxlen 8..24); *out_bytes receives the size (the required size on
+ * ORC_E_CAPACITY). */
+int orc_entropy_encode(const uint8_t *in, uint64_t n, uint32_t chunk, int maxlen, uint8_t *out, uint64_t cap,
+                       uint64_t *out_bytes);
+/* Decoded size and chunk bytes of an encoded stream (ORC_E_CORRUPT if it is not one). */
+int orc_entropy_info(const uint8_t *in, uint64_t nbytes, uint64_t *n, uint32_t *chunk);
+/* Decodes a whole encoded stream; *n_out receives the decoded size. */
+int orc_entropy_decode(const uint8_t *in, uint64_t nbytes, uint8_t *out, uint64_t out_cap, uint64_t *n_out);
+
 #ifdef __cplusplus
 }
 #endif
