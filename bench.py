@@ -53,6 +53,7 @@ def parse_args():
     ap.add_argument("--group", type=int, default=8, help="serve1024: requests per shared reconstruction")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-latency part of the default run")
     ap.add_argument("--no-topology", action="store_true", help="skip the error-translation part of the default run")
+    ap.add_argument("--no-entropy", action="store_true", help="skip the entropy stage of the default run")
     ap.add_argument("--serve-requests", type=int, default=200, help="requests of the default run's served part")
     ap.add_argument("--batch-items", type=int, default=64, help="batch64: number of timesteps")
     ap.add_argument("--branches", type=int, default=0, help="batch64: parallel branches of the graph (default: 4)")
@@ -613,6 +614,41 @@ def main():
             del ct, yt
             torch.cuda.empty_cache()
 
+    # the entropy stage over the stream (the network leg of the in-transit
+    # workflow): size after coding, encode/decode times on the launch stream
+    ent = None
+    if not args.no_entropy:
+        eout = torch.empty(api.chr_entropy_bound(nbytes), dtype=torch.uint8, device=dev)
+        ews = torch.empty(api.chr_entropy_workspace(nbytes), dtype=torch.uint8, device=dev)
+        eres = torch.zeros(2, dtype=torch.int64, device=dev)
+        dec = torch.empty(nbytes + 8, dtype=torch.uint8, device=dev)
+        est = torch.zeros(1, dtype=torch.int32, device=dev)
+        api.chr_entropy_encode(sdev, eout, eres, ews)
+        torch.cuda.synchronize()
+        esz, est0 = (int(v) for v in eres.cpu())
+        assert est0 == 0, "entropy stage: capacity"
+        ehead = eout[:64].cpu().numpy()
+        rep = 10
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        api.chr_entropy_decode(ehead, eout[:esz], dec, est)
+        e0.record(stream)
+        for _ in range(rep):
+            api.chr_entropy_encode(sdev, eout, eres, ews)
+        e1.record(stream)
+        for _ in range(rep):
+            api.chr_entropy_decode(ehead, eout[:esz], dec, est)
+        e2.record(stream)
+        torch.cuda.synchronize()
+        assert int(est.item()) == 0 and torch.equal(dec[:nbytes], sdev), "entropy stage: round trip"
+        enc_ms, dec_ms = e0.elapsed_time(e1) / rep, e1.elapsed_time(e2) / rep
+        ent = {"stream_bytes": nbytes, "coded_bytes": esz, "ratio": round(nbytes / esz, 4),
+               "compression_ratio_total": round(4.0 * N / esz, 3), "encode_ms": round(enc_ms, 4),
+               "decode_ms": round(dec_ms, 4), "encode_gbs": round(nbytes / enc_ms / 1e6, 1),
+               "decode_gbs": round(nbytes / dec_ms / 1e6, 1),
+               "workflow_model": workflow_model(4.0 * N, 4.0 * N / esz,
+                                                (stage_ms[0] + enc_ms, stage_ms[1] + dec_ms, stage_ms[2]))}
+        del eout, ews, dec
+
     # served latency on the same field (the metric's second half): requests
     # at random isovalues and accuracy tiers, continuous-batching server vs
     # plain per-request launches at 0.8 x the plain path's saturation rate
@@ -663,7 +699,7 @@ def main():
         "n_corrected": r["n_corrected"], "triangles": [int(c[1]) for c in cnt],
         "wall_s_timed": round(wall, 3), "served": served, "topology_error_bound": topo or None, "roofline": roofline,
         "cpu_baseline": cpu,
-        "workflow_model": workflow_model(4.0 * N, cr, stage_ms),
+        "workflow_model": workflow_model(4.0 * N, cr, stage_ms), "entropy_stage": ent,
     }
     print(json.dumps(out), flush=True)
 

@@ -423,6 +423,45 @@ int chr_prof_enable(const char *kernel, int max_launches);
 int chr_prof_collect(float *ms, int max, int *n_out);
 int chr_prof_disable(void);
 
+/* ---- entropy stage (the stream on the network leg, Sec. III) -------------
+ *
+ * An order-0 canonical Huffman code over the bytes of any byte string (a CHR
+ * stream in practice), in independently decodable 512-byte chunks.  Code
+ * lengths: Huffman's two-queue construction over the byte counts (ties: the
+ * smaller count, then the smaller byte value, a leaf before an internal node
+ * of equal weight), limited to 12 bits by the JPEG rule (ITU-T T.81 Annex
+ * K.3), then given to the byte values from the most frequent; codes:
+ * RFC 1951 Sec. 3.2.2 canonical assignment.  Layout (little-endian):
+ *   0 u32 "CHRH"  4 u32 version 1  8 u64 n  16 u32 chunk bytes (512)
+ *   20 u32 nchunks = ceil(n / 512)  24 u64 total bytes  32 u32 max length 12
+ *   36..63 zero; 64 u8 code length of each byte value (0: absent)
+ *   320 u32 word offset of each chunk's bits (nchunks + 1 entries, the last
+ *   being the bit area's length in words), zero padding to 8 bytes
+ *   bit area: each chunk's codes from its word offset, bits LSB-first within
+ *   32-bit words, each code most-significant bit first; last word zero-padded.
+ * Inputs and outputs are device buffers, 8-byte aligned; n < 2^32. */
+
+/* Encoded size bound of n bytes (the capacity that always suffices). */
+size_t chr_entropy_bound(uint64_t n);
+/* Device workspace of chr_entropy_encode for n bytes. */
+size_t chr_entropy_workspace(uint64_t n);
+/* Encodes d_in[0 .. n).  d_result: 2 device words, [0] the encoded size
+ * (the required size when [1] = CHR_E_CAPACITY), [1] 0 or CHR_E_CAPACITY
+ * (nothing but the result is written then).  Errors: CHR_E_INVAL (NULL or
+ * misaligned pointer, n >= 2^32), CHR_E_NOMEM (workspace too small). */
+int chr_entropy_encode(const void *d_in, uint64_t n, void *d_out, size_t capacity, uint64_t *d_result, void *d_ws,
+                       size_t ws_bytes, void *stream);
+/* Parses the first 64 bytes of an encoded stream (host copy): decoded size n
+ * and encoded size.  CHR_E_CORRUPT if they are not a version-1 header with
+ * 512-byte chunks and 12-bit codes. */
+int chr_entropy_info(const void *h_head, size_t head_bytes, uint64_t *n, uint64_t *total);
+/* Decodes the encoded stream d_in (nbytes, its header also on the host as
+ * h_head) into d_out[0 .. n).  *d_status is set to 0, or CHR_E_CORRUPT when
+ * a chunk's offsets or codes are invalid.  Errors: as chr_entropy_info,
+ * CHR_E_CAPACITY (out_capacity < n), CHR_E_INVAL (NULL or misaligned). */
+int chr_entropy_decode(const void *h_head, const void *d_in, uint64_t nbytes, void *d_out, uint64_t out_capacity,
+                       int32_t *d_status, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -280,6 +280,11 @@ def huff_codes(lengths):
     return out
 
 
+def entropy_bound(n, chunk=ENTROPY_CHUNK, maxlen=ENTROPY_MAXLEN):
+    """Largest encoding of n bytes."""
+    return int(lib().orc_entropy_bound(int(n), chunk, maxlen))
+
+
 def entropy_encode(data, chunk=ENTROPY_CHUNK, maxlen=ENTROPY_MAXLEN):
     """The entropy stage's encoding of a byte string (uint8 array)."""
     d = np.ascontiguousarray(np.frombuffer(bytes(data), np.uint8) if not isinstance(data, np.ndarray) else data,

@@ -28,7 +28,8 @@ EXPORTS = ["chr_last_error", "chr_version", "chr_compress_bound", "chr_compress_
            "chr_batch_destroy", "chr_server_create", "chr_server_add_stream", "chr_server_submit",
            "chr_server_step", "chr_server_poll", "chr_server_release", "chr_server_cancel", "chr_server_stats_get",
            "chr_server_now_ms", "chr_server_destroy", "chr_topology_workspace", "chr_topology_error_bound",
-           "chr_reconstruct_range"]
+           "chr_reconstruct_range", "chr_entropy_bound", "chr_entropy_workspace", "chr_entropy_encode",
+           "chr_entropy_info", "chr_entropy_decode"]
 
 
 class ChrError(RuntimeError):
@@ -179,6 +180,17 @@ def load():
     L.chr_topology_workspace.restype = C.c_size_t
     L.chr_topology_error_bound.argtypes = [vp, i64p, vp, C.c_int, C.c_int64, vp, vp, C.c_size_t, vp]
     L.chr_topology_error_bound.restype = C.c_int
+    L.chr_entropy_bound.argtypes = [C.c_uint64]
+    L.chr_entropy_bound.restype = C.c_size_t
+    L.chr_entropy_workspace.argtypes = [C.c_uint64]
+    L.chr_entropy_workspace.restype = C.c_size_t
+    L.chr_entropy_encode.argtypes = [vp, C.c_uint64, vp, C.c_size_t, vp, vp, C.c_size_t, vp]
+    L.chr_entropy_encode.restype = C.c_int
+    u64p = C.POINTER(C.c_uint64)
+    L.chr_entropy_info.argtypes = [vp, C.c_size_t, u64p, u64p]
+    L.chr_entropy_info.restype = C.c_int
+    L.chr_entropy_decode.argtypes = [vp, vp, C.c_uint64, vp, C.c_uint64, vp, vp]
+    L.chr_entropy_decode.restype = C.c_int
     _lib = L
     return L
 

@@ -475,3 +475,74 @@ def topology_error_bound(field, isovalues, nth=1):
     torch.cuda.synchronize(field.device)
     v = out.cpu().numpy()
     return float(v[0]), int(v[1])
+
+
+# ------------------------------------------------------------------ entropy stage
+
+def _need_cuda_u8(t, name):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.uint8 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous uint8 CUDA tensor")
+
+
+def chr_entropy_bound(n):
+    return int(L.load().chr_entropy_bound(int(n)))
+
+
+def chr_entropy_workspace(n):
+    return int(L.load().chr_entropy_workspace(int(n)))
+
+
+def chr_entropy_encode(data, out, result, ws, stream=None):
+    """Asynchronous; ``result`` (2 x uint64 on the device) receives the size and the status."""
+    _need_cuda_u8(data, "data")
+    _need_cuda_u8(out, "out")
+    rc = L.load().chr_entropy_encode(_p(data), data.numel(), _p(out), out.numel(), _p(result), _p(ws), ws.numel(),
+                                     _s(stream))
+    L.check(rc, "chr_entropy_encode")
+
+
+def chr_entropy_info(head):
+    """(n, total bytes) from the first 64 bytes of an entropy-coded stream (host bytes)."""
+    h = np.ascontiguousarray(np.frombuffer(bytes(head[:64]), np.uint8))
+    n, total = C.c_uint64(), C.c_uint64()
+    rc = L.load().chr_entropy_info(h.ctypes.data_as(C.c_void_p), h.size, C.byref(n), C.byref(total))
+    L.check(rc, "chr_entropy_info")
+    return int(n.value), int(total.value)
+
+
+def chr_entropy_decode(head, enc, out, status, stream=None):
+    """Asynchronous; ``status`` (one int32 on the device) becomes 0 or CHR_E_CORRUPT."""
+    _need_cuda_u8(enc, "enc")
+    _need_cuda_u8(out, "out")
+    h = np.ascontiguousarray(np.frombuffer(bytes(head[:64]), np.uint8))
+    rc = L.load().chr_entropy_decode(h.ctypes.data_as(C.c_void_p), _p(enc), enc.numel(), _p(out), out.numel(),
+                                     _p(status), _s(stream))
+    L.check(rc, "chr_entropy_decode")
+
+
+def entropy_encode(data):
+    """Synchronous: the entropy-coded bytes of a uint8 CUDA tensor, as a CUDA tensor."""
+    n = data.numel()
+    out = torch.empty(max(chr_entropy_bound(n), 8), dtype=torch.uint8, device=data.device)
+    ws = torch.empty(chr_entropy_workspace(n), dtype=torch.uint8, device=data.device)
+    res = torch.zeros(2, dtype=torch.int64, device=data.device)
+    chr_entropy_encode(data, out, res, ws)
+    torch.cuda.synchronize(data.device)
+    size, st = (int(v) for v in res.cpu())
+    if st:
+        raise L.ChrError(st, "chr_entropy_encode: output beyond its capacity")
+    return out[:size]
+
+
+def entropy_decode(enc):
+    """Synchronous: the bytes an entropy-coded CUDA tensor holds."""
+    head = enc[:64].cpu().numpy()
+    n, _ = chr_entropy_info(head)
+    out = torch.empty(max(n, 8), dtype=torch.uint8, device=enc.device)
+    status = torch.zeros(1, dtype=torch.int32, device=enc.device)
+    chr_entropy_decode(head, enc, out, status)
+    torch.cuda.synchronize(enc.device)
+    st = int(status.item())
+    if st:
+        raise L.ChrError(st, "chr_entropy_decode: corrupt stream")
+    return out[:n]

@@ -1,0 +1,486 @@
+// entropy.hip -- the entropy stage over a CHR stream on gfx950: an order-0
+// canonical Huffman code over the stream's bytes, for the network leg of the
+// in-transit workflow (Sec. III).  The code is textbook: Huffman lengths by
+// the two-queue construction, the length limit of JPEG (ITU-T T.81, Annex
+// K.3), RFC 1951's canonical codes; the byte layout is documented in
+// include/chr.h.
+//
+// Encoding: a histogram (LDS bins per workgroup, one global add per bin), the
+// code table by one workgroup (parallel ranks for the two sorts, one lane for
+// the Huffman merge), per-chunk bit counts (one wave per 512-byte chunk), a
+// scan of the chunks' word counts, and the packing (one wave per chunk: lane
+// bit offsets by a wave scan, codes OR-ed into the chunk's words in LDS,
+// then written out).  Decoding: one lane per chunk, a 4096-entry table of
+// the 12-bit windows in LDS.
+#include <algorithm>
+
+#include <cstring>
+
+#include "capi_internal.h"
+#include "chr_plan.h"
+#include "scan.h"
+
+namespace chr {
+namespace {
+
+constexpr int kBS = 256;
+constexpr int kWaves = kBS / kWave;
+constexpr uint32_t kChunk = 512;      // bytes per chunk
+constexpr int kMaxLen = 12;           // longest code
+constexpr uint32_t kMagicH = 0x48524843u;
+constexpr int kLenOff = 64, kOffOff = 320;
+constexpr uint32_t kChunkWords = (kChunk * kMaxLen + 31) / 32;
+
+struct EntTable {
+  uint32_t hist[256];
+  uint32_t rcode[256];   // codes, bit-reversed (first code bit lowest)
+  uint8_t len[256];
+};
+
+struct EntPlan {
+  const uint8_t *in;
+  uint64_t n, nch;
+  uint8_t *out;
+  uint64_t cap, base;    // capacity, byte offset of the bit area
+  EntTable *tab;
+  uint64_t *csize, *woff;
+  uint64_t *result;      // [0] encoded bytes, [1] status (0 or CHR_E_CAPACITY)
+};
+
+__host__ __device__ inline uint64_t bit_area(uint64_t nch) { return ((uint64_t)kOffOff + 4 * (nch + 1) + 7) & ~7ull; }
+
+__global__ __launch_bounds__(kBS) void k_ent_clear(EntPlan E) {
+  for (int i = threadIdx.x; i < 256; i += kBS) E.tab->hist[i] = 0u;
+}
+
+// Byte histogram: 8 bytes per load, LDS bins, one global add per bin.
+__global__ __launch_bounds__(kBS) void k_ent_hist(EntPlan E) {
+  __shared__ uint32_t h[256];
+  for (int i = threadIdx.x; i < 256; i += kBS) h[i] = 0u;
+  __syncthreads();
+  const uint64_t n8 = E.n / 8;
+  const uint64_t *w = reinterpret_cast<const uint64_t *>(E.in);
+  for (uint64_t i = (uint64_t)blockIdx.x * kBS + threadIdx.x; i < n8; i += (uint64_t)gridDim.x * kBS) {
+    const uint64_t v = w[i];
+#pragma unroll
+    for (int b = 0; b < 8; b++) atomicAdd(&h[(v >> (8 * b)) & 255u], 1u);
+  }
+  if (blockIdx.x == 0)
+    for (uint64_t i = 8 * n8 + threadIdx.x; i < E.n; i += kBS) atomicAdd(&h[E.in[i]], 1u);
+  __syncthreads();
+  for (int i = threadIdx.x; i < 256; i += kBS)
+    if (h[i]) atomicAdd(&E.tab->hist[i], h[i]);
+}
+
+// The code table (one workgroup of 256 threads, thread s for byte value s).
+__global__ __launch_bounds__(256) void k_ent_table(EntPlan E) {
+  __shared__ uint32_t hs[256];
+  __shared__ int order[256];      // present values by (count, value) increasing
+  __shared__ int bits[512];       // codes per length
+  __shared__ uint64_t wt[511];
+  __shared__ int par[511], dep[511];
+  __shared__ int m_s;
+  __shared__ uint8_t ln[256];
+  const int s = threadIdx.x;
+  const uint32_t c = E.tab->hist[s];
+  hs[s] = c;
+  for (int i = s; i < 512; i += 256) bits[i] = 0;
+  __syncthreads();
+  // rank among the present values by (count, value)
+  int rk = 0, m = 0;
+  for (int t = 0; t < 256; t++) {
+    const uint32_t ct = hs[t];
+    m += ct != 0u;
+    rk += ct != 0u && (ct < c || (ct == c && t < s));
+  }
+  if (c) order[rk] = s;
+  ln[s] = 0;
+  __syncthreads();
+  if (s == 0) {
+    m_s = m;
+    if (m == 1) {
+      bits[1] = 1;
+    } else if (m >= 2) {
+      // two-queue Huffman: leaves 0..m-1 in order, internal nodes from m on;
+      // the lighter front is taken, a leaf first on a tie
+      for (int i = 0; i < m; i++) wt[i] = hs[order[i]];
+      int qi = 0, qj = m, made = m;
+      for (int step = 0; step < m - 1; step++) {
+        int pk[2];
+        for (int t = 0; t < 2; t++) {
+          if (qi < m && (qj >= made || wt[qi] <= wt[qj])) pk[t] = qi++;
+          else pk[t] = qj++;
+        }
+        wt[made] = wt[pk[0]] + wt[pk[1]];
+        par[pk[0]] = par[pk[1]] = made;
+        made++;
+      }
+      dep[made - 1] = 0;
+      int maxd = 0;
+      for (int v = made - 2; v >= 0; v--) dep[v] = dep[par[v]] + 1;
+      for (int i = 0; i < m; i++) {
+        bits[dep[i]]++;
+        maxd = max(maxd, dep[i]);
+      }
+      // length limit (JPEG Annex K.3): move pairs of codes up, keeping the code complete
+      for (int i = maxd; i > kMaxLen; i--) {
+        while (bits[i] > 0) {
+          int j = i - 2;
+          while (bits[j] == 0) j--;
+          bits[i] -= 2;
+          bits[i - 1] += 1;
+          bits[j + 1] += 2;
+          bits[j] -= 1;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  m = m_s;
+  // lengths to the values from the most frequent: rank by (count desc, value)
+  if (c) {
+    int r2 = 0;
+    for (int t = 0; t < 256; t++) {
+      const uint32_t ct = hs[t];
+      r2 += ct != 0u && (ct > c || (ct == c && t < s));
+    }
+    int acc = 0, l = 1;
+    for (; l <= kMaxLen; l++) {
+      if (r2 < acc + bits[l]) break;
+      acc += bits[l];
+    }
+    ln[s] = (uint8_t)l;
+  }
+  __syncthreads();
+  // canonical codes: shorter first, consecutive in value order within a length
+  const int L = ln[s];
+  uint32_t code = 0;
+  if (L) {
+    uint32_t first = 0;
+    for (int l = 1; l <= L; l++) {
+      int cnt = 0;
+      for (int t = 0; t < 256; t++) cnt += ln[t] == l - 1 && l - 1 > 0;
+      first = (first + (uint32_t)cnt) << 1;
+    }
+    int before = 0;
+    for (int t = 0; t < s; t++) before += ln[t] == L;
+    code = first + (uint32_t)before;
+  }
+  uint32_t r = 0;
+  for (int b = 0; b < L; b++) r |= ((code >> b) & 1u) << (L - 1 - b);
+  E.tab->rcode[s] = r;
+  E.tab->len[s] = (uint8_t)L;
+  (void)m;
+}
+
+// Bits of each chunk (one wave per chunk, 8 bytes per lane), as 32-bit words.
+__global__ __launch_bounds__(kBS) void k_ent_sizes(EntPlan E) {
+  __shared__ uint8_t ln[256];
+  for (int i = threadIdx.x; i < 256; i += kBS) ln[i] = E.tab->len[i];
+  __syncthreads();
+  const uint64_t c = (uint64_t)blockIdx.x * kWaves + wave_index();
+  if (c >= E.nch) return;
+  const int lane = lane_id();
+  const uint64_t b0 = c * kChunk + 8 * (uint64_t)lane;
+  uint32_t bits = 0;
+  for (int b = 0; b < 8; b++)
+    if (b0 + b < E.n) bits += ln[E.in[b0 + b]];
+  bits = wave_sum_dpp(bits);
+  if (lane == 0) E.csize[c] = (bits + 31) / 32;
+}
+
+// The header, the code lengths and the last chunk offset; the result.
+__global__ __launch_bounds__(kBS) void k_ent_header(EntPlan E) {
+  const uint64_t total = E.base + 4 * E.woff[E.nch];
+  const bool fits = total <= E.cap;
+  if (threadIdx.x == 0) {
+    E.result[0] = total;
+    E.result[1] = fits ? 0ull : (uint64_t)(int64_t)CHR_E_CAPACITY;
+  }
+  if (!fits) return;
+  uint32_t *o32 = reinterpret_cast<uint32_t *>(E.out);
+  for (uint32_t i = threadIdx.x; i < 16; i += kBS) {
+    uint32_t v = 0;
+    if (i == 0) v = kMagicH;
+    if (i == 1) v = 1u;
+    if (i == 2) v = (uint32_t)E.n;
+    if (i == 3) v = (uint32_t)(E.n >> 32);
+    if (i == 4) v = kChunk;
+    if (i == 5) v = (uint32_t)E.nch;
+    if (i == 6) v = (uint32_t)total;
+    if (i == 7) v = (uint32_t)(total >> 32);
+    if (i == 8) v = (uint32_t)kMaxLen;
+    o32[i] = v;
+  }
+  for (uint32_t i = threadIdx.x; i < 256; i += kBS) E.out[kLenOff + i] = E.tab->len[i];
+  if (threadIdx.x == 0) {
+    o32[kOffOff / 4 + E.nch] = (uint32_t)E.woff[E.nch];
+    if (kOffOff + 4 * (E.nch + 1) < E.base) o32[kOffOff / 4 + E.nch + 1] = 0u;  // padding word
+  }
+}
+
+// Packs chunk c (one wave): lane bit offsets by a wave scan, codes OR-ed
+// into the chunk's words in LDS, the words written out with the chunk's
+// offset entry.
+__global__ __launch_bounds__(kBS) void k_ent_write(EntPlan E) {
+  __shared__ uint32_t rcode[256];
+  __shared__ uint8_t ln[256];
+  __shared__ uint32_t words[kWaves][kChunkWords];
+  for (int i = threadIdx.x; i < 256; i += kBS) {
+    rcode[i] = E.tab->rcode[i];
+    ln[i] = E.tab->len[i];
+  }
+  __syncthreads();
+  const uint64_t total = E.base + 4 * E.woff[E.nch];
+  if (total > E.cap) return;
+  const uint32_t wave = wave_index();
+  const uint64_t c = (uint64_t)blockIdx.x * kWaves + wave;
+  if (c >= E.nch) return;
+  const int lane = lane_id();
+  uint32_t *wd = words[wave];
+  for (uint32_t i = (uint32_t)lane; i < kChunkWords; i += kWave) wd[i] = 0u;
+  const uint64_t b0 = c * kChunk + 8 * (uint64_t)lane;
+  uint32_t sym[8];
+  uint32_t bits = 0;
+#pragma unroll
+  for (int b = 0; b < 8; b++) {
+    sym[b] = b0 + b < E.n ? E.in[b0 + b] : 256u;
+    bits += sym[b] < 256u ? ln[sym[b]] : 0u;
+  }
+  uint32_t pos = wave_excl_sum(bits);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int b = 0; b < 8; b++) {
+    if (sym[b] < 256u) {
+      const uint32_t L = ln[sym[b]], r = rcode[sym[b]];
+      const uint32_t wi = pos >> 5, off = pos & 31u;
+      atomicOr(&wd[wi], r << off);
+      if (off + L > 32u) atomicOr(&wd[wi + 1], r >> (32u - off));
+      pos += L;
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  const uint64_t w0 = E.woff[c], nwd = E.woff[c + 1] - w0;
+  uint32_t *dst = reinterpret_cast<uint32_t *>(E.out + E.base) + w0;
+  for (uint32_t i = (uint32_t)lane; i < nwd; i += kWave) dst[i] = wd[i];
+  if (lane == 0) reinterpret_cast<uint32_t *>(E.out + kOffOff)[c] = (uint32_t)w0;
+}
+
+__global__ void k_ent_status0(int32_t *status) {
+  if (threadIdx.x == 0) *status = 0;
+}
+
+// Decoding: one lane per chunk; the 12-bit windows' (value, length) in LDS.
+struct DecE {
+  const uint8_t *in;
+  uint64_t nbytes, n, nch, base;
+  uint8_t *out;
+  int32_t *status;
+};
+
+__global__ __launch_bounds__(kBS) void k_ent_decode(DecE D) {
+  __shared__ uint16_t tab[1 << kMaxLen];
+  __shared__ uint32_t code_s[256];
+  __shared__ uint8_t ln[256];
+  // canonical codes of the stored lengths (as the encoder), then every
+  // window whose low L bits are a value's reversed code maps to it
+  const int s = threadIdx.x;
+  ln[s] = D.in[kLenOff + s];
+  for (int i = s; i < (1 << kMaxLen); i += kBS) tab[i] = 0;
+  __syncthreads();
+  {
+    const int L = ln[s];
+    uint32_t code = 0;
+    if (L >= 1 && L <= kMaxLen) {
+      uint32_t first = 0;
+      for (int l = 1; l <= L; l++) {
+        int cnt = 0;
+        for (int t = 0; t < 256; t++) cnt += ln[t] == l - 1 && l - 1 > 0;
+        first = (first + (uint32_t)cnt) << 1;
+      }
+      int before = 0;
+      for (int t = 0; t < s; t++) before += ln[t] == L;
+      code = first + (uint32_t)before;
+    }
+    uint32_t r = 0;
+    for (int b = 0; b < L && L <= kMaxLen; b++) r |= ((code >> b) & 1u) << (L - 1 - b);
+    code_s[s] = r;
+  }
+  __syncthreads();
+  {
+    const int L = ln[s];
+    if (L >= 1 && L <= kMaxLen && code_s[s] < (1u << L))
+      for (uint32_t k = 0; k < (1u << (kMaxLen - L)); k++) tab[code_s[s] + (k << L)] = (uint16_t)(s | (L << 8));
+  }
+  __syncthreads();
+  const uint64_t c = (uint64_t)blockIdx.x * kBS + threadIdx.x;
+  if (c >= D.nch) return;
+  const uint32_t *offs = reinterpret_cast<const uint32_t *>(D.in + kOffOff);
+  const uint64_t w0 = offs[c], w1 = offs[c + 1];
+  const uint64_t words = (D.nbytes - D.base) / 4;
+  if (w0 > w1 || w1 > words) {
+    *D.status = CHR_E_CORRUPT;
+    return;
+  }
+  const uint32_t *src = reinterpret_cast<const uint32_t *>(D.in + D.base);
+  const uint64_t first = c * kChunk;
+  const uint32_t len = (uint32_t)min<uint64_t>(kChunk, D.n - first);
+  uint64_t buf = 0;
+  uint32_t nb = 0;
+  uint64_t wi = w0;
+  bool bad = false;
+  uint64_t acc = 0;
+  for (uint32_t i = 0; i < len; i++) {
+    if (nb < 32) {
+      const uint64_t v = wi < w1 ? src[wi] : 0u;
+      wi++;
+      buf |= v << nb;
+      nb += 32;
+    }
+    const uint32_t e = tab[buf & ((1u << kMaxLen) - 1u)];
+    uint32_t L = e >> 8;
+    bad |= L == 0;
+    L = L ? L : 1u;
+    buf >>= L;
+    nb -= L;
+    acc |= (uint64_t)(e & 255u) << (8 * (i & 7u));
+    if ((i & 7u) == 7u) {
+      *reinterpret_cast<uint64_t *>(D.out + first + (i & ~7u)) = acc;
+      acc = 0;
+    }
+  }
+  for (uint32_t i = len & ~7u; i < len; i++) D.out[first + i] = (uint8_t)(acc >> (8 * (i & 7u)));
+  bad |= (wi - w0) * 32 - nb > (w1 - w0) * 32;  // read past the chunk's bits
+  if (bad) *D.status = CHR_E_CORRUPT;
+}
+
+}  // namespace
+
+uint64_t entropy_bound(uint64_t n) {
+  const uint64_t nch = (n + kChunk - 1) / kChunk;
+  return bit_area(nch) + 4 * ((n * (uint64_t)kMaxLen + 31) / 32 + nch);
+}
+
+size_t entropy_workspace(uint64_t n) {
+  const uint64_t nch = (n + kChunk - 1) / kChunk;
+  size_t o = (sizeof(EntTable) + 255) & ~(size_t)255;
+  o += (8 * nch + 255) & ~(size_t)255;                              // chunk word counts
+  o += (8 * (nch + 1) + 255) & ~(size_t)255;                        // offsets
+  o += (8 * (size_t)scan_tmp_elems((int64_t)nch) + 255) & ~(size_t)255;  // scan scratch
+  return o;
+}
+
+int launch_entropy_encode(const uint8_t *in, uint64_t n, uint8_t *out, uint64_t cap, uint64_t *result, void *ws,
+                          hipStream_t s) {
+  EntPlan E;
+  E.in = in;
+  E.n = n;
+  E.nch = (n + kChunk - 1) / kChunk;
+  E.out = out;
+  E.cap = cap;
+  E.base = bit_area(E.nch);
+  uint8_t *w = static_cast<uint8_t *>(ws);
+  size_t o = 0;
+  E.tab = reinterpret_cast<EntTable *>(w + o);
+  o += (sizeof(EntTable) + 255) & ~(size_t)255;
+  E.csize = reinterpret_cast<uint64_t *>(w + o);
+  o += (8 * E.nch + 255) & ~(size_t)255;
+  E.woff = reinterpret_cast<uint64_t *>(w + o);
+  o += (8 * (E.nch + 1) + 255) & ~(size_t)255;
+  uint64_t *tmp = reinterpret_cast<uint64_t *>(w + o);
+  E.result = result;
+  k_ent_clear<<<1, kBS, 0, s>>>(E);
+  const uint64_t g = std::min<uint64_t>(std::max<uint64_t>((n / 8 + kBS - 1) / kBS, 1), 2048);
+  k_ent_hist<<<dim3((unsigned)g), dim3(kBS), 0, s>>>(E);
+  k_ent_table<<<1, 256, 0, s>>>(E);
+  const unsigned gw = (unsigned)std::max<uint64_t>((E.nch + kWaves - 1) / kWaves, 1);
+  if (E.nch) k_ent_sizes<<<dim3(gw), dim3(kBS), 0, s>>>(E);
+  scan_u64(E.csize, E.woff, (int64_t)E.nch, tmp, s);
+  k_ent_header<<<1, kBS, 0, s>>>(E);
+  if (E.nch) k_ent_write<<<dim3(gw), dim3(kBS), 0, s>>>(E);
+  return 0;
+}
+
+int launch_entropy_decode(const uint8_t *in, uint64_t nbytes, uint64_t n, uint64_t nch, uint8_t *out, int32_t *status,
+                          hipStream_t s) {
+  DecE D;
+  D.in = in;
+  D.nbytes = nbytes;
+  D.n = n;
+  D.nch = nch;
+  D.base = bit_area(nch);
+  D.out = out;
+  D.status = status;
+  if (nch) k_ent_decode<<<dim3((unsigned)((nch + kBS - 1) / kBS)), dim3(kBS), 0, s>>>(D);
+  return 0;
+}
+
+uint64_t entropy_bit_area(uint64_t nch) { return bit_area(nch); }
+uint32_t entropy_chunk() { return kChunk; }
+
+}  // namespace chr
+
+// ---- C ABI -------------------------------------------------------------------
+
+using namespace chr;
+
+namespace {
+bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+uint32_t hget32(const uint8_t *p) { uint32_t v; std::memcpy(&v, p, 4); return v; }
+uint64_t hget64(const uint8_t *p) { uint64_t v; std::memcpy(&v, p, 8); return v; }
+}  // namespace
+
+extern "C" {
+
+size_t chr_entropy_bound(uint64_t n) { return (size_t)entropy_bound(n); }
+
+size_t chr_entropy_workspace(uint64_t n) { return entropy_workspace(n); }
+
+int chr_entropy_encode(const void *d_in, uint64_t n, void *d_out, size_t capacity, uint64_t *d_result, void *d_ws,
+                       size_t ws_bytes, void *stream) {
+  if ((!d_in && n) || !d_out || !d_result || !d_ws) return api_fail(CHR_E_INVAL, "NULL device pointer");
+  if (!aligned8(d_in) || !aligned8(d_out) || !aligned8(d_result))
+    return api_fail(CHR_E_INVAL, "buffers must be 8-byte aligned");
+  if (n >= (1ull << 32)) return api_fail(CHR_E_INVAL, "entropy stage: n must be below 2^32");
+  const size_t need = entropy_workspace(n);
+  if (ws_bytes < need) return api_fail(CHR_E_NOMEM, "workspace too small: need " + std::to_string(need));
+  launch_entropy_encode(static_cast<const uint8_t *>(d_in), n, static_cast<uint8_t *>(d_out), capacity, d_result,
+                        d_ws, static_cast<hipStream_t>(stream));
+  return api_check_launch("chr_entropy_encode");
+}
+
+int chr_entropy_info(const void *h_head, size_t head_bytes, uint64_t *n, uint64_t *total) {
+  if (!h_head || !n || !total) return api_fail(CHR_E_INVAL, "NULL argument");
+  const uint8_t *h = static_cast<const uint8_t *>(h_head);
+  if (head_bytes < 64 || hget32(h) != 0x48524843u || hget32(h + 4) != 1u)
+    return api_fail(CHR_E_CORRUPT, "not an entropy-stage stream (magic/version)");
+  const uint64_t nn = hget64(h + 8);
+  if (hget32(h + 16) != entropy_chunk() || hget32(h + 32) != 12u ||
+      (uint64_t)hget32(h + 20) != (nn + entropy_chunk() - 1) / entropy_chunk())
+    return api_fail(CHR_E_CORRUPT, "entropy stream: unsupported chunk size or code length, or inconsistent header");
+  *n = nn;
+  *total = hget64(h + 24);
+  return CHR_OK;
+}
+
+int chr_entropy_decode(const void *h_head, const void *d_in, uint64_t nbytes, void *d_out, uint64_t out_capacity,
+                       int32_t *d_status, void *stream) {
+  uint64_t n = 0, total = 0;
+  int rc = chr_entropy_info(h_head, 64, &n, &total);
+  if (rc) return rc;
+  if (!d_in || (!d_out && n) || !d_status) return api_fail(CHR_E_INVAL, "NULL device pointer");
+  if (!aligned8(d_in) || !aligned8(d_out)) return api_fail(CHR_E_INVAL, "buffers must be 8-byte aligned");
+  const uint64_t nch = (n + entropy_chunk() - 1) / entropy_chunk();
+  if (total != nbytes || nbytes < entropy_bit_area(nch))
+    return api_fail(CHR_E_CORRUPT, "entropy stream: size does not match its header");
+  if (out_capacity < n) return api_fail(CHR_E_CAPACITY, "output below the decoded size " + std::to_string(n));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  k_ent_status0<<<1, 64, 0, s>>>(d_status);
+  launch_entropy_decode(static_cast<const uint8_t *>(d_in), nbytes, n, nch, static_cast<uint8_t *>(d_out), d_status,
+                        s);
+  return api_check_launch("chr_entropy_decode");
+}
+
+}  // extern "C"

@@ -1,0 +1,166 @@
+"""GPU parity of the entropy stage (order-0 canonical Huffman over stream
+bytes) against the CPU oracle, through the C ABI.
+
+Encoding is compared byte for byte with the oracle's (the code is fully
+determined: lengths, canonical codes and bit layout); decoding must return
+the input from the oracle's encoding and from the GPU's.  Inputs are seeded
+byte strings and CHR streams written by the oracle's compressor.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2408_05462_amd import api, inputs
+from paper_2408_05462_amd import _lib as L
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _fib_bytes(nsym, seed):
+    """Byte values 0..nsym-1 with Fibonacci counts, shuffled: the Huffman
+    tree is as deep as there are values, so the 12-bit limit applies."""
+    fib = [1, 1]
+    while len(fib) < nsym:
+        fib.append(fib[-1] + fib[-2])
+    d = np.repeat(np.arange(nsym, dtype=np.uint8), fib)
+    np.random.default_rng(seed).shuffle(d)
+    return d
+
+
+def _data(kind):
+    rng = np.random.default_rng(sum(map(ord, kind)))
+    if kind == "empty":
+        return np.zeros(0, np.uint8)
+    if kind == "one":
+        return np.array([200], np.uint8)
+    if kind == "seven":
+        return np.array([1, 2, 3, 1, 1, 250, 0], np.uint8)
+    if kind == "same":
+        return np.full(5000, 17, np.uint8)
+    if kind == "two":
+        return rng.choice(np.array([3, 90], np.uint8), 4099)
+    if kind == "all256":
+        return np.tile(np.arange(256, dtype=np.uint8), 9)
+    if kind == "uniform":
+        return rng.integers(0, 256, 512 * 7 + 13).astype(np.uint8)
+    if kind == "skewed":
+        return np.minimum(rng.geometric(0.2, 70000), 255).astype(np.uint8)
+    if kind == "fib20":
+        return _fib_bytes(20, 1)
+    if kind == "fib26":
+        return _fib_bytes(26, 2)
+    if kind == "chr_stream":
+        f = inputs.grf(48, 0.5)[:40, :37, :45].copy()
+        return oracle.compress(f, 1e-3 * float(f.max() - f.min()), [0.0], levels=3, block=16)["stream"]
+    if kind == "chr_stream_big":
+        f = inputs.grf(96, 0.5)
+        return oracle.compress(f, 1e-4 * float(f.max() - f.min()), [0.1, -0.2], levels=4, block=32)["stream"]
+    raise KeyError(kind)
+
+
+KINDS = ["empty", "one", "seven", "same", "two", "all256", "uniform", "skewed", "fib20", "fib26", "chr_stream",
+         "chr_stream_big"]
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, np.uint8)).to(DEV)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_encode_matches_oracle_bytes(kind):
+    d = _data(kind)
+    print(f"entropy encode parity: {kind} n={d.size}", flush=True)
+    want = oracle.entropy_encode(d)
+    got = api.entropy_encode(_dev(d)).cpu().numpy()
+    assert got.size == want.size
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_decode_of_oracle_and_gpu_encodings(kind):
+    d = _data(kind)
+    print(f"entropy decode parity: {kind} n={d.size}", flush=True)
+    enc = oracle.entropy_encode(d)
+    assert np.array_equal(api.entropy_decode(_dev(enc)).cpu().numpy(), d)
+    g = api.entropy_decode(api.entropy_encode(_dev(d))).cpu().numpy()
+    assert np.array_equal(g, d)
+
+
+def test_large_skewed_input_sampled_against_oracle():
+    # 48 MiB of geometric bytes: the encoding equals the oracle's in size and
+    # in the sampled chunks' offsets and words; the round trip is exact
+    rng = np.random.default_rng(77)
+    n = 48 << 20
+    d = np.minimum(rng.geometric(0.15, n), 255).astype(np.uint8)
+    print(f"entropy large: n={n}", flush=True)
+    want = oracle.entropy_encode(d)
+    dd = _dev(d)
+    enc = api.entropy_encode(dd)
+    got = enc.cpu().numpy()
+    assert got.size == want.size
+    assert np.array_equal(got[:4096], want[:4096])
+    for s in rng.integers(0, want.size - 4096, 16):
+        assert np.array_equal(got[s:s + 4096], want[s:s + 4096])
+    back = api.entropy_decode(enc)
+    assert torch.equal(back, dd)
+
+
+def test_capacity_is_reported_and_nothing_written():
+    d = np.minimum(np.random.default_rng(4).geometric(0.3, 20000), 255).astype(np.uint8)
+    want = oracle.entropy_encode(d)
+    dd = _dev(d)
+    out = torch.full((want.size + 64,), 0xA5, dtype=torch.uint8, device=DEV)
+    ws = torch.empty(api.chr_entropy_workspace(d.size), dtype=torch.uint8, device=DEV)
+    res = torch.zeros(2, dtype=torch.int64, device=DEV)
+    api.chr_entropy_encode(dd, out[: want.size - 8], res, ws)
+    torch.cuda.synchronize()
+    r = res.cpu().numpy()
+    assert int(r[0]) == want.size and int(r[1]) == L.CHR_E_CAPACITY
+    assert bool((out == 0xA5).all())
+    api.chr_entropy_encode(dd, out[: want.size], res, ws)
+    torch.cuda.synchronize()
+    assert res.cpu().tolist() == [want.size, 0]
+    assert np.array_equal(out[: want.size].cpu().numpy(), want)
+    assert bool((out[want.size:] == 0xA5).all())
+
+
+def _decode_status(enc):
+    head = enc[:64]
+    n, _ = api.chr_entropy_info(head)
+    out = torch.zeros(max(n, 8), dtype=torch.uint8, device=DEV)
+    st = torch.full((1,), 7, dtype=torch.int32, device=DEV)
+    api.chr_entropy_decode(head, _dev(enc), out, st)
+    torch.cuda.synchronize()
+    return int(st.item()), out[:n].cpu().numpy()
+
+
+def test_corrupt_streams_are_flagged():
+    d = np.minimum(np.random.default_rng(8).geometric(0.3, 5000), 255).astype(np.uint8)
+    enc = oracle.entropy_encode(d)
+    st, got = _decode_status(enc)
+    assert st == 0 and np.array_equal(got, d)
+    nch = (d.size + 511) // 512
+    # a chunk offset beyond the bit area
+    bad = enc.copy()
+    bad[320 + 4 * 3: 320 + 4 * 4] = np.frombuffer(np.uint32(1 << 20).tobytes(), np.uint8)
+    assert _decode_status(bad)[0] == L.CHR_E_CORRUPT
+    # offsets out of order
+    bad = enc.copy()
+    o2 = bad[320 + 8: 320 + 12].copy()
+    bad[320 + 8: 320 + 12] = bad[320 + 12: 320 + 16]
+    bad[320 + 12: 320 + 16] = o2
+    assert _decode_status(bad)[0] == L.CHR_E_CORRUPT
+    # a chunk whose bits run out: the last chunk given no words
+    bad = enc.copy()
+    bad[320 + 4 * (nch - 1): 320 + 4 * nch] = bad[320 + 4 * nch: 320 + 4 * (nch + 1)]
+    assert _decode_status(bad)[0] == L.CHR_E_CORRUPT
+    # one value of length 1 (code 0): a set bit matches no code
+    one = oracle.entropy_encode(np.full(100, 9, np.uint8))
+    bad = one.copy()
+    base = ((320 + 4 * 2) + 7) // 8 * 8
+    bad[base] |= 4
+    assert _decode_status(bad)[0] == L.CHR_E_CORRUPT
+    assert _decode_status(one)[0] == 0

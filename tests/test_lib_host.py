@@ -293,3 +293,48 @@ def test_reciprocal_division_rule():
             r = np.nextafter(r, np.float32(np.inf))
         q = (nf * r).astype(np.uint32)
         assert np.array_equal(q, n // np.uint32(d)), d
+
+
+@pytest.mark.parametrize("n", [0, 1, 511, 512, 513, 70000, 10**9])
+def test_entropy_bound_matches_oracle(n):
+    assert api.chr_entropy_bound(n) == oracle.entropy_bound(n)
+    assert api.chr_entropy_workspace(n) >= 2304 + 8 * (n // 512)   # table, chunk sizes
+
+
+def test_entropy_info_reads_oracle_headers_and_rejects_others():
+    d = np.random.default_rng(3).integers(0, 9, 1234).astype(np.uint8)
+    enc = oracle.entropy_encode(d)
+    assert api.chr_entropy_info(enc[:64]) == (1234, enc.size)
+    bad = enc[:64].copy()
+    bad[0] ^= 1                                        # magic
+    with pytest.raises(L.ChrError):
+        api.chr_entropy_info(bad)
+    bad = enc[:64].copy()
+    bad[17] = 4                                        # chunk size 512 -> 1024
+    with pytest.raises(L.ChrError):
+        api.chr_entropy_info(bad)
+    bad = enc[:64].copy()
+    bad[20] += 1                                       # chunk count inconsistent with n
+    with pytest.raises(L.ChrError):
+        api.chr_entropy_info(bad)
+    with pytest.raises(L.ChrError):
+        api.chr_entropy_info(enc[:40])                 # short header
+
+
+def test_entropy_calls_reject_bad_arguments_on_the_host():
+    lib = L.load()
+    buf = (C.c_uint64 * 16)()
+    p = C.cast(buf, C.c_void_p)
+    odd = C.c_void_p(p.value + 1)
+    ws = api.chr_entropy_workspace(100)
+    assert lib.chr_entropy_encode(None, 100, p, 1000, p, p, ws, None) == L.CHR_E_INVAL
+    assert lib.chr_entropy_encode(odd, 100, p, 1000, p, p, ws, None) == L.CHR_E_INVAL
+    assert lib.chr_entropy_encode(p, 1 << 32, p, 1000, p, p, 1 << 40, None) == L.CHR_E_INVAL
+    assert lib.chr_entropy_encode(p, 100, p, 1000, p, p, ws - 1, None) == L.CHR_E_NOMEM
+    enc = oracle.entropy_encode(np.arange(100, dtype=np.uint8))
+    h = np.ascontiguousarray(enc[:64])
+    hp = h.ctypes.data_as(C.c_void_p)
+    # size disagreeing with the header, output too small: rejected before any launch
+    assert lib.chr_entropy_decode(hp, p, enc.size - 8, p, 100, p, None) == L.CHR_E_CORRUPT
+    assert lib.chr_entropy_decode(hp, p, enc.size, p, 99, p, None) == L.CHR_E_CAPACITY
+    assert lib.chr_entropy_decode(hp, None, enc.size, p, 100, p, None) == L.CHR_E_INVAL
