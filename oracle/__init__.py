@@ -51,7 +51,8 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        if not os.path.exists(_LIB) or any(os.path.getmtime(f) > os.path.getmtime(_LIB)
+                                           for f in (_SRC, _SRC_ENT, os.path.join(_HERE, "chr_oracle.h"))):
             build()
         L = C.CDLL(_LIB)
         i64p = C.POINTER(C.c_int64)
@@ -65,7 +66,7 @@ def lib():
         L.orc_rank.restype = C.c_int
         L.orc_compress_bound.argtypes = [i64p, C.c_int, C.c_int]
         L.orc_compress_bound.restype = C.c_size_t
-        L.orc_compress.argtypes = [C.c_void_p, i64p, C.c_double, C.c_void_p, C.c_int, C.c_int, C.c_int,
+        L.orc_compress.argtypes = [C.c_void_p, i64p, C.c_double, C.c_double, C.c_void_p, C.c_int, C.c_int, C.c_int,
                                    C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
                                    C.POINTER(C.c_size_t)]
         L.orc_compress.restype = C.c_int
@@ -132,8 +133,10 @@ def compress_bound(shape, nL, block):
     return lib().orc_compress_bound(_dims(shape), nL, block)
 
 
-def compress(x, error_bound, isovalues=(), levels=3, block=64, qmax=32767):
-    """Returns dict(stream=bytes(np.uint8), q, flags, xr)."""
+def compress(x, error_bound, isovalues=(), levels=3, block=64, qmax=32767, error_bound_far=0.0):
+    """Returns dict(stream=bytes(np.uint8), q, flags, xr).  error_bound_far > 0
+    selects differentiated error control (the far bound away from blocks that
+    cross a candidate isovalue)."""
     x, px = _f32(x)
     iso = np.ascontiguousarray(np.asarray(isovalues, np.float32).reshape(-1))
     cap = compress_bound(x.shape, levels, block)
@@ -142,7 +145,8 @@ def compress(x, error_bound, isovalues=(), levels=3, block=64, qmax=32767):
     fl = np.zeros(x.shape, np.uint8)
     xr = np.zeros(x.shape, np.float32)
     nbytes = C.c_size_t()
-    rc = lib().orc_compress(px, _dims(x.shape), float(error_bound), iso.ctypes.data, len(iso), levels,
+    rc = lib().orc_compress(px, _dims(x.shape), float(error_bound), float(error_bound_far), iso.ctypes.data,
+                            len(iso), levels,
                             block, qmax, q.ctypes.data, fl.ctypes.data, xr.ctypes.data,
                             stream.ctypes.data, cap, C.byref(nbytes))
     if rc != OK:
@@ -155,7 +159,8 @@ class Info(C.Structure):
                 ("n_iso", C.c_int), ("error_bound", C.c_double), ("inv", C.c_float), ("step", C.c_float),
                 ("iso", C.c_float * 16), ("vmin", C.c_float), ("vmax", C.c_float), ("nblocks", C.c_int64),
                 ("nb", C.c_int * 3), ("flags", C.c_uint32), ("total_bytes", C.c_uint64),
-                ("n_outlier", C.c_uint64), ("n_corrected", C.c_uint64), ("payload_offset", C.c_uint64)]
+                ("n_outlier", C.c_uint64), ("n_corrected", C.c_uint64), ("payload_offset", C.c_uint64),
+                ("error_bound_far", C.c_double), ("inv_far", C.c_float), ("step_far", C.c_float)]
 
 
 def stream_info(stream):
@@ -187,7 +192,10 @@ def stream_codes(stream):
 def decompress(stream, level=0, error_bound=None):
     s = np.ascontiguousarray(stream, np.uint8)
     info = stream_info(s)
-    eb = info.error_bound if error_bound is None else error_bound
+    if error_bound is None:
+        eb = info.error_bound_far if info.flags & 2 else info.error_bound
+    else:
+        eb = error_bound
     shape = tuple(((int(n) - 1) >> level) + 1 for n in info.dims)
     out = np.zeros(shape, np.float32)
     rc = lib().orc_decompress(s.ctypes.data, s.size, level, float(eb), out.ctypes.data)

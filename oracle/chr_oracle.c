@@ -245,6 +245,58 @@ static int64_t section_points(const int64_t o[3], const int64_t hi[3], int l, in
 }
 
 /* ------------------------------------------------------------------------ */
+/* differentiated error control (Sec. II.A, reading R19)                    */
+/* ------------------------------------------------------------------------ */
+
+/* A block is active when the input on its closed extent crosses a candidate
+ * isovalue: min < k <= max for some candidate k (with the bit convention of
+ * R1 a cell has a crossing iff one corner lies below k and another does
+ * not, and a connected extent holding values on both sides has such a cell). */
+static void block_activity(const float *x, const int64_t d[3], int64_t B, const int64_t nb[3],
+                           const float *iso, int K, uint8_t *act) {
+  int64_t nblocks = nb[0] * nb[1] * nb[2];
+  for (int64_t b = 0; b < nblocks; b++) {
+    int64_t bi[3] = {b / (nb[1] * nb[2]), (b / nb[2]) % nb[1], b % nb[2]}, o[3], hi[3];
+    block_extent(d, B, bi, o, hi);
+    float mn = x[idx3(d, o[0], o[1], o[2])], mx = mn;
+    for (int64_t z = o[0]; z <= hi[0]; z++)
+      for (int64_t y = o[1]; y <= hi[1]; y++)
+        for (int64_t xx = o[2]; xx <= hi[2]; xx++) {
+          float v = x[idx3(d, z, y, xx)];
+          if (v < mn) mn = v;
+          if (v > mx) mx = v;
+        }
+    act[b] = 0;
+    for (int j = 0; j < K; j++)
+      if (mn < iso[j] && iso[j] <= mx) act[b] = 1;
+  }
+}
+
+/* Blocks along one axis whose closed extent contains coordinate p: c0..c1
+ * (two when p is on the face between them). */
+static void axis_blocks(int64_t p, int64_t B, int64_t nb, int64_t *c0, int64_t *c1) {
+  int64_t c = p / B;
+  *c1 = c < nb ? c : nb - 1;
+  *c0 = (p % B == 0 && c > 0 && c - 1 < *c1) ? c - 1 : *c1;
+}
+
+/* A point takes the near bound when any block whose closed extent contains
+ * it is active.  Points shared by blocks so get one bound (their values are
+ * the same in every block), and both ends of every crossing edge of a
+ * candidate isovalue lie in an active block. */
+static int point_near(const uint8_t *act, const int64_t nb[3], int64_t B, int64_t z, int64_t y, int64_t x) {
+  int64_t lo[3], hi[3];
+  axis_blocks(z, B, nb[0], &lo[0], &hi[0]);
+  axis_blocks(y, B, nb[1], &lo[1], &hi[1]);
+  axis_blocks(x, B, nb[2], &lo[2], &hi[2]);
+  for (int64_t a = lo[0]; a <= hi[0]; a++)
+    for (int64_t b = lo[1]; b <= hi[1]; b++)
+      for (int64_t c = lo[2]; c <= hi[2]; c++)
+        if (act[(a * nb[1] + b) * nb[2] + c]) return 1;
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* section encoding                                                         */
 /* ------------------------------------------------------------------------ */
 
@@ -378,25 +430,34 @@ static int check_params(const int64_t dims[3], int nL, int block, int qmax) {
   return 0;
 }
 
-int orc_compress(const float *x, const int64_t dims[3], double error_bound,
+int orc_compress(const float *x, const int64_t dims[3], double error_bound, double error_bound_far,
                  const float *iso_in, int n_iso_in, int nL, int block, int qmax,
                  int32_t *q_out, uint8_t *flags_out, float *xr_out,
                  uint8_t *stream, size_t cap, size_t *stream_bytes) {
   if (check_params(dims, nL, block, qmax)) return ORC_E_INVAL;
   if (!(error_bound >= 0) || !isfinite(error_bound)) return ORC_E_INVAL;
+  /* far bound: 0 for one bound everywhere, else finite and >= error_bound */
+  if (error_bound_far != 0 && !(error_bound_far >= error_bound && isfinite(error_bound_far))) return ORC_E_INVAL;
+  const int diff = error_bound_far != 0;
   float iso[16];
   int K = prepare_iso(iso_in, n_iso_in, iso);
   if (K < 0) return ORC_E_INVAL;
   int64_t N = dims[0] * dims[1] * dims[2];
   for (int64_t i = 0; i < N; i++)
     if (!isfinite(x[i])) return ORC_E_INVAL; /* reading R15 */
-  quant_t Q;
+  quant_t Q, Qf;
   quant_setup(error_bound, qmax, &Q);
+  quant_setup(diff ? error_bound_far : 0.0, qmax, &Qf);
+  int64_t nb[3];
+  for (int a = 0; a < 3; a++) nb[a] = nblk_axis(dims[a], block);
+  int64_t nblocks = nb[0] * nb[1] * nb[2];
 
   float *xr = (float *)malloc(sizeof(float) * (size_t)N);
   int32_t *q = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
   uint8_t *fl = (uint8_t *)malloc((size_t)N);
-  if (!xr || !q || !fl) { free(xr); free(q); free(fl); return ORC_E_NOMEM; }
+  uint8_t *act = (uint8_t *)calloc((size_t)nblocks, 1);
+  if (!xr || !q || !fl || !act) { free(xr); free(q); free(fl); free(act); return ORC_E_NOMEM; }
+  if (diff) block_activity(x, dims, block, nb, iso, K, act);
 
   /* Levels from the coarsest; the points of one level depend only on
    * reconstructed values of coarser levels, so their order is immaterial. */
@@ -413,7 +474,8 @@ int orc_compress(const float *x, const int64_t dims[3], double error_bound,
           /* prediction (R6) and quantization (R7) */
           float p = (l == nL - 1) ? 0.0f : predict_in(xr, dims, xx, y, z, h);
           int32_t code; int O; float r;
-          quantize_q(v, p, &Q, &code, &O, &r);
+          const quant_t *Qp = (diff && !point_near(act, nb, block, z, y, xx)) ? &Qf : &Q;
+          quantize_q(v, p, Qp, &code, &O, &r);
           /* topology check on the candidate reconstruction (R2, R8): the
            * vertex must stay on the same side of every candidate isovalue */
           int C = 0;
@@ -430,9 +492,6 @@ int orc_compress(const float *x, const int64_t dims[3], double error_bound,
   }
 
   /* stream (reading R9) */
-  int64_t nb[3];
-  for (int a = 0; a < 3; a++) nb[a] = nblk_axis(dims[a], block);
-  int64_t nblocks = nb[0] * nb[1] * nb[2];
   size_t tab = HEADER_BYTES, btab = tab + 16 * (size_t)nblocks * (size_t)nL;
   size_t payload = btab + 16 * (size_t)nblocks;
 
@@ -452,7 +511,7 @@ int orc_compress(const float *x, const int64_t dims[3], double error_bound,
   uint8_t *se = (uint8_t *)malloc((size_t)(maxn ? maxn : 1));
   float *sx = (float *)malloc(sizeof(float) * (size_t)(maxn ? maxn : 1));
   if (!pts || !sq || !se || !sx) {
-    free(pts); free(sq); free(se); free(sx); free(xr); free(q); free(fl);
+    free(pts); free(sq); free(se); free(sx); free(xr); free(q); free(fl); free(act);
     return ORC_E_NOMEM;
   }
   for (int pass = 0; pass < 2; pass++) {
@@ -486,14 +545,14 @@ int orc_compress(const float *x, const int64_t dims[3], double error_bound,
         putf(be, bmin);
         putf(be + 4, bmax);
         put32(be + 8, checksum(stream + bstart, off - bstart));
-        put32(be + 12, 0);
+        put32(be + 12, diff ? (uint32_t)act[b] : 0u);  /* bit 0: active block (R19) */
       }
     }
     total = off;
     if (pass == 0) {
       if (stream_bytes) *stream_bytes = total;
       if (!stream || cap < total) {
-        free(pts); free(sq); free(se); free(sx); free(xr); free(q); free(fl);
+        free(pts); free(sq); free(se); free(sx); free(xr); free(q); free(fl); free(act);
         return ORC_E_CAPACITY;
       }
       memset(stream, 0, total);
@@ -523,18 +582,23 @@ int orc_compress(const float *x, const int64_t dims[3], double error_bound,
   putf(H + 132, vmax);
   put64(H + 136, (uint64_t)nblocks);
   for (int a = 0; a < 3; a++) put32(H + 144 + 4 * a, (uint32_t)nb[a]);
-  put32(H + 156, Q.lossless ? 1u : 0u);
+  put32(H + 156, (Q.lossless ? 1u : 0u) | (diff ? 2u : 0u) | (diff && Qf.lossless ? 4u : 0u));
   put64(H + 160, total);
   put64(H + 168, nO);
   put64(H + 176, nC);
   put64(H + 184, payload);
+  if (diff) {
+    putd(H + 192, error_bound_far);
+    putf(H + 200, Qf.inv);
+    putf(H + 204, Qf.step);
+  }
   put32(H + 248, checksum(stream + HEADER_BYTES, payload - HEADER_BYTES));
   put32(H + 252, checksum(H, 252));
 
   if (q_out) memcpy(q_out, q, sizeof(int32_t) * (size_t)N);
   if (flags_out) memcpy(flags_out, fl, (size_t)N);
   if (xr_out) memcpy(xr_out, xr, sizeof(float) * (size_t)N);
-  free(xr); free(q); free(fl);
+  free(xr); free(q); free(fl); free(act);
   return ORC_OK;
 }
 
@@ -565,6 +629,10 @@ int orc_stream_info(const uint8_t *s, size_t n, orc_info *I) {
   I->n_outlier = get64(s + 168);
   I->n_corrected = get64(s + 176);
   I->payload_offset = get64(s + 184);
+  I->error_bound_far = getd(s + 192);
+  I->inv_far = getf(s + 200);
+  I->step_far = getf(s + 204);
+  if ((I->flags & 2u) && !(I->error_bound_far >= I->error_bound && isfinite(I->error_bound_far))) return ORC_E_CORRUPT;
   if (check_params(I->dims, I->levels, I->block, I->qmax)) return ORC_E_CORRUPT;
   if (I->n_iso < 0 || I->n_iso > 16) return ORC_E_CORRUPT;
   if (I->total_bytes > n) return ORC_E_CORRUPT;
@@ -701,10 +769,21 @@ int orc_decompress(const uint8_t *s, size_t n, int level, double eb, float *out)
   if (rc) return rc;
   int nL = I.levels;
   if (level < 0 || level >= nL) return ORC_E_LEVEL;
-  if (!(eb >= I.error_bound)) return ORC_E_ACCURACY;
-  quant_t Q;
+  const int diff = (I.flags & 2u) != 0;
+  /* accuracy: the loosest bound the stream holds */
+  if (!(eb >= (diff ? I.error_bound_far : I.error_bound))) return ORC_E_ACCURACY;
+  quant_t Q, Qf;
   quant_setup(I.error_bound, I.qmax, &Q);
+  quant_setup(diff ? I.error_bound_far : 0.0, I.qmax, &Qf);
   if (f2u(Q.inv) != f2u(I.inv) || f2u(Q.step) != f2u(I.step)) return ORC_E_CORRUPT;
+  if (diff && (f2u(Qf.inv) != f2u(I.inv_far) || f2u(Qf.step) != f2u(I.step_far))) return ORC_E_CORRUPT;
+  const int64_t nbk[3] = {I.nb[0], I.nb[1], I.nb[2]};
+  uint8_t *act = (uint8_t *)calloc((size_t)I.nblocks, 1);
+  if (!act) return ORC_E_NOMEM;
+  {
+    size_t btab = HEADER_BYTES + 16 * (size_t)I.nblocks * (size_t)I.levels;
+    for (int64_t b = 0; b < I.nblocks; b++) act[b] = diff && (get32(s + btab + 16 * (size_t)b + 12) & 1u);
+  }
   int64_t od[3];
   for (int a = 0; a < 3; a++) od[a] = ((I.dims[a] - 1) >> level) + 1;
   int64_t B = I.block;
@@ -715,7 +794,7 @@ int orc_decompress(const uint8_t *s, size_t n, int level, double eb, float *out)
   int32_t *sq = (int32_t *)malloc(sizeof(int32_t) * le);
   uint8_t *se = (uint8_t *)malloc(le);
   float *sx = (float *)malloc(sizeof(float) * le);
-  if (!loc || !pts || !sq || !se || !sx) { free(loc); free(pts); free(sq); free(se); free(sx); return ORC_E_NOMEM; }
+  if (!loc || !pts || !sq || !se || !sx) { free(loc); free(pts); free(sq); free(se); free(sx); free(act); return ORC_E_NOMEM; }
   rc = ORC_OK;
   for (int64_t b = 0; b < I.nblocks && rc == ORC_OK; b++) {
     int64_t bi[3] = {b / ((int64_t)I.nb[1] * I.nb[2]), (b / I.nb[2]) % I.nb[1], b % I.nb[2]}, o[3], hi[3];
@@ -736,8 +815,9 @@ int orc_decompress(const uint8_t *s, size_t n, int level, double eb, float *out)
           r = sx[j];
         } else {
           float p = (l == nL - 1) ? 0.0f : predict_in(loc, le3, x, y, z, h);
-          if (Q.lossless) r = p;
-          else { float t = (float)sq[j] * Q.step; r = p + t; }
+          const quant_t *Qp = (diff && !point_near(act, nbk, B, pts[3 * j], pts[3 * j + 1], pts[3 * j + 2])) ? &Qf : &Q;
+          if (Qp->lossless) r = p;
+          else { float t = (float)sq[j] * Qp->step; r = p + t; }
         }
         loc[idx3(le3, z, y, x)] = r;
       }
@@ -750,7 +830,7 @@ int orc_decompress(const uint8_t *s, size_t n, int level, double eb, float *out)
           out[idx3(od, z >> level, y >> level, x >> level)] =
               loc[idx3(le3, z - o[0], y - o[1], x - o[2])];
   }
-  free(loc); free(pts); free(sq); free(se); free(sx);
+  free(loc); free(pts); free(sq); free(se); free(sx); free(act);
   return rc;
 }
 

@@ -69,8 +69,11 @@ size_t orc_compress_bound(const int64_t dims[3], int nL, int block);
  * layout (may be NULL): q is the quantization code (0 where the value is
  * stored exactly), flags bit0 = outlier (O), bit1 = topology correction (C),
  * xr = reconstructed value.  Writes the stream into `stream` (capacity cap),
- * its size into *stream_bytes (the required size on ORC_E_CAPACITY). */
-int orc_compress(const float *x, const int64_t dims[3], double error_bound,
+ * its size into *stream_bytes (the required size on ORC_E_CAPACITY).
+ * error_bound_far = 0: one bound everywhere; otherwise (finite, >= error_bound)
+ * differentiated error control (reading R19): points of no block crossing a
+ * candidate isovalue are quantized with the far bound. */
+int orc_compress(const float *x, const int64_t dims[3], double error_bound, double error_bound_far,
                  const float *iso, int n_iso, int nL, int block, int qmax,
                  int32_t *q_out, uint8_t *flags_out, float *xr_out,
                  uint8_t *stream, size_t cap, size_t *stream_bytes);
@@ -87,6 +90,8 @@ typedef struct {
   int nb[3];
   uint32_t flags;
   uint64_t total_bytes, n_outlier, n_corrected, payload_offset;
+  double error_bound_far;  /* flags bit 1: differentiated error control */
+  float inv_far, step_far;
 } orc_info;
 
 int orc_stream_info(const uint8_t *stream, size_t n, orc_info *out);
