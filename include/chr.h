@@ -64,6 +64,14 @@ typedef struct chr_params {
   int levels;
   int block;
   int qmax;
+  /* Differentiated error control (Sec. II.A, blocks with different error
+   * bounds): 0 = error_bound everywhere; otherwise finite and >= error_bound,
+   * the bound of every point that no block crossing a candidate isovalue
+   * contains.  A block crosses isovalue k when min < k <= max over the input
+   * on its closed extent; points of such blocks keep error_bound, so the
+   * meshes of the candidate isovalues equal those of a stream compressed
+   * with error_bound everywhere. */
+  double error_bound_far;
 } chr_params;
 
 /* Device-side result of chr_compress (caller-allocated device memory). */
@@ -86,8 +94,10 @@ typedef struct chr_info {
   float vmin, vmax;
   int64_t nblocks;
   int nb[3];
-  uint32_t flags;        /* bit 0: lossless mode */
+  uint32_t flags;        /* bit 0: lossless mode; bit 1: differentiated error control; bit 2: far quantizer lossless */
   uint64_t total_bytes, n_outlier, n_corrected, payload_offset;
+  double error_bound_far;      /* flags bit 1: bound of points outside every active block (header bytes 192..199) */
+  float inv_far, step_far;     /* its 1/(2e) and 2e (bytes 200..207) */
 } chr_info;
 
 const char *chr_last_error(void);

@@ -39,7 +39,7 @@ class ChrError(RuntimeError):
 
 
 class chr_params(C.Structure):
-    _fields_ = [("levels", C.c_int), ("block", C.c_int), ("qmax", C.c_int)]
+    _fields_ = [("levels", C.c_int), ("block", C.c_int), ("qmax", C.c_int), ("error_bound_far", C.c_double)]
 
 
 class chr_result(C.Structure):
@@ -53,7 +53,8 @@ class chr_info(C.Structure):
                 ("isovalues", C.c_float * 16), ("vmin", C.c_float), ("vmax", C.c_float),
                 ("nblocks", C.c_int64), ("nb", C.c_int * 3), ("flags", C.c_uint32),
                 ("total_bytes", C.c_uint64), ("n_outlier", C.c_uint64), ("n_corrected", C.c_uint64),
-                ("payload_offset", C.c_uint64)]
+                ("payload_offset", C.c_uint64), ("error_bound_far", C.c_double), ("inv_far", C.c_float),
+                ("step_far", C.c_float)]
 
 
 class chr_batch_item(C.Structure):

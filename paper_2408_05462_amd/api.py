@@ -31,8 +31,9 @@ def _need_cuda_f32(t, name):
         raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
 
 
-def params(levels=3, block=64, qmax=32767):
-    return L.chr_params(levels, block, qmax)
+def params(levels=3, block=64, qmax=32767, error_bound_far=0.0):
+    """error_bound_far > 0: differentiated error control (include/chr.h)."""
+    return L.chr_params(levels, block, qmax, float(error_bound_far))
 
 
 # ------------------------------------------------------------------ compress
@@ -76,9 +77,10 @@ class Compressed:
     result: dict
 
 
-def compress(field, error_bound, isovalues=(), levels=3, block=64, qmax=32767, codes=None, flags=None):
+def compress(field, error_bound, isovalues=(), levels=3, block=64, qmax=32767, codes=None, flags=None,
+             error_bound_far=0.0):
     """Synchronous compression; raises ChrError on any device-side status."""
-    p = params(levels, block, qmax)
+    p = params(levels, block, qmax, error_bound_far)
     dev = field.device
     cap = chr_compress_bound(field.shape, p)
     out = torch.empty(cap, dtype=torch.uint8, device=dev)
@@ -120,6 +122,12 @@ def chr_stream_verify(host_bytes):
 
 # ------------------------------------------------------------------ reconstruct
 
+def stream_bound(info):
+    """The bound a stream guarantees at every point (its far bound under
+    differentiated error control)."""
+    return info.error_bound_far if info.flags & 2 else info.error_bound
+
+
 def level_shape(info, level):
     return tuple(((int(n) - 1) >> level) + 1 for n in info.dims)
 
@@ -150,7 +158,7 @@ def reconstruct_range(c: Compressed, kmin, kmax, level=0):
     out = torch.empty(level_shape(c.info, level), dtype=torch.float32, device=dev)
     status = torch.zeros(1, dtype=torch.int32, device=dev)
     ws = torch.empty(max(chr_reconstruct_workspace(c.info, level), 256), dtype=torch.uint8, device=dev)
-    chr_reconstruct_range(c.info, c.stream, level, c.info.error_bound, kmin, kmax, out, status, ws)
+    chr_reconstruct_range(c.info, c.stream, level, stream_bound(c.info), kmin, kmax, out, status, ws)
     torch.cuda.synchronize(dev)
     st = int(status.item())
     if st != 0:
@@ -159,7 +167,7 @@ def reconstruct_range(c: Compressed, kmin, kmax, level=0):
 
 
 def reconstruct(c: Compressed, level=0, error_bound=None):
-    eb = c.info.error_bound if error_bound is None else error_bound
+    eb = stream_bound(c.info) if error_bound is None else error_bound
     dev = c.stream.device
     out = torch.empty(level_shape(c.info, level), dtype=torch.float32, device=dev)
     status = torch.zeros(1, dtype=torch.int32, device=dev)

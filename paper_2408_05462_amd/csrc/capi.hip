@@ -98,6 +98,17 @@ void set_quant(Geo &g, double e) {
   g.lossless = (!(e > 0) || g.step == 0.0f || !std::isfinite(g.step)) ? 1 : 0;
 }
 
+// The far quantizer of differentiated error control (same rule as set_quant).
+void set_quant_far(Geo &g, double e2) {
+  Geo t = g;
+  set_quant(t, e2);
+  g.diff = 1;
+  g.e2 = t.e;
+  g.inv2 = t.inv;
+  g.step2 = t.step;
+  g.lossless2 = t.lossless;
+}
+
 // max chunks of a level-l section (the first block is the largest)
 uint32_t max_chunks(const Geo &g, int l) {
   int64_t o[3], hi[3];
@@ -108,7 +119,7 @@ uint32_t max_chunks(const Geo &g, int l) {
 
 struct EncLayout {
   size_t off_G, off_cnt, off_P, off_scan, off_pay, off_emask, off_exv, off_part, off_bst, off_csum, off_secsz, off_secoff,
-      off_scan64, total, part_records;
+      off_scan64, off_act, total, part_records;
 };
 
 EncLayout enc_layout(EncPlan &P) {
@@ -158,6 +169,7 @@ EncLayout enc_layout(EncPlan &P) {
   Lo.off_secsz = o; o = align256(o + sizeof(uint64_t) * (size_t)nsec);
   Lo.off_secoff = o; o = align256(o + sizeof(uint64_t) * (size_t)(nsec + 1));
   Lo.off_scan64 = o; o = align256(o + sizeof(uint64_t) * (size_t)scan_tmp_elems(nsec));
+  Lo.off_act = o; o = align256(o + sizeof(uint32_t) * (size_t)g.nblocks);
   Lo.total = o;
   return Lo;
 }
@@ -240,9 +252,13 @@ int enc_geometry(const int64_t dims[3], double error_bound, const float *h_iso, 
   std::string why;
   if (!params_ok(dims, p, why)) return fail(CHR_E_INVAL, why);
   if (!(error_bound >= 0) || !std::isfinite(error_bound)) return fail(CHR_E_INVAL, "error_bound must be finite and >= 0");
+  const double far = p->error_bound_far;
+  if (far != 0 && !(far >= error_bound && std::isfinite(far)))
+    return fail(CHR_E_INVAL, "error_bound_far must be 0 or finite and >= error_bound");
   fill_geo(g, dims, p->levels, p->block, p->qmax);
   if (prepare_iso(h_iso, n_iso, g, why)) return fail(CHR_E_INVAL, why);
   set_quant(g, error_bound);
+  if (far != 0) set_quant_far(g, far);
   if (g.nblocks > 65535) return fail(CHR_E_INVAL, "more than 65535 blocks: use a larger block");
   payload_off = kHeaderBytes + 16 * (uint64_t)g.nblocks * g.nL + 16 * (uint64_t)g.nblocks;
   return CHR_OK;
@@ -281,6 +297,7 @@ int enc_prepare(const float *d_field, const int64_t dims[3], double error_bound,
   P.result = d_result;
   P.codes = d_codes;
   P.flags = d_flags;
+  P.act = reinterpret_cast<uint32_t *>(ws + Lo.off_act);
   J.scan = reinterpret_cast<U4 *>(ws + Lo.off_scan);
   J.scan64 = reinterpret_cast<uint64_t *>(ws + Lo.off_scan64);
   return CHR_OK;
@@ -399,6 +416,14 @@ int info_geo(const chr_info *I, Geo &g) {
   if (std::memcmp(&g.inv, &I->inv, 4) || std::memcmp(&g.step, &I->step, 4))
     return fail(CHR_E_CORRUPT, "quantizer constants do not match the error bound");
   if ((g.lossless ? 1u : 0u) != (I->flags & 1u)) return fail(CHR_E_CORRUPT, "lossless flag mismatch");
+  if (I->flags & 2u) {
+    if (!(I->error_bound_far >= I->error_bound && std::isfinite(I->error_bound_far)))
+      return fail(CHR_E_CORRUPT, "bad far error bound");
+    set_quant_far(g, I->error_bound_far);
+    if (std::memcmp(&g.inv2, &I->inv_far, 4) || std::memcmp(&g.step2, &I->step_far, 4))
+      return fail(CHR_E_CORRUPT, "far quantizer constants do not match the far error bound");
+    if ((g.lossless2 ? 4u : 0u) != (I->flags & 4u)) return fail(CHR_E_CORRUPT, "far lossless flag mismatch");
+  }
   if (I->n_iso < 0 || I->n_iso > kMaxIso) return fail(CHR_E_CORRUPT, "bad isovalue count");
   g.K = I->n_iso;
   for (int j = 0; j < kMaxIso; j++) g.iso[j] = I->isovalues[j];
@@ -523,7 +548,10 @@ int chr_stream_info(const void *h_stream, size_t n, chr_info *I) {
   I->n_outlier = rd<uint64_t>(s + 168);
   I->n_corrected = rd<uint64_t>(s + 176);
   I->payload_offset = rd<uint64_t>(s + 184);
-  chr_params p{I->levels, I->block, I->qmax};
+  I->error_bound_far = rd<double>(s + 192);
+  I->inv_far = rd<float>(s + 200);
+  I->step_far = rd<float>(s + 204);
+  chr_params p{I->levels, I->block, I->qmax, 0.0};
   std::string why;
   if (!params_ok(I->dims, &p, why)) return fail(CHR_E_CORRUPT, "header parameters invalid: " + why);
   if (I->n_iso < 0 || I->n_iso > kMaxIso) return fail(CHR_E_CORRUPT, "bad isovalue count");
@@ -595,7 +623,7 @@ static int reconstruct_impl(const chr_info *info, const void *d_stream, size_t s
   int rc = info_geo(info, g);
   if (rc) return rc;
   if (level < 0 || level >= g.nL) return fail(CHR_E_LEVEL, "level outside the hierarchy");
-  if (!(error_bound >= info->error_bound)) return fail(CHR_E_ACCURACY, "requested error bound below the stream's");
+  if (!(error_bound >= stream_bound(*info))) return fail(CHR_E_ACCURACY, "requested error bound below the stream's");
   if (stream_bytes < info->total_bytes) return fail(CHR_E_CORRUPT, "stream shorter than its header states");
   DecJob J;
   rc = dec_prepare(g, info->payload_offset, level, d_stream, info->total_bytes, d_out, d_status, d_ws, ws_bytes,

@@ -16,6 +16,10 @@ int api_fail(int code, const std::string &msg);
 // Turns a pending HIP launch error into CHR_E_HIP.
 int api_check_launch(const char *what);
 
+// The bound a stream guarantees at every point: its far bound under
+// differentiated error control, its error bound otherwise.
+inline double stream_bound(const chr_info &I) { return (I.flags & 2u) ? I.error_bound_far : I.error_bound; }
+
 struct EncJob {
   EncPlan P;
   U4 *scan;

@@ -47,7 +47,28 @@ struct Geo {
   float inv, step;
   int lossless;
   float iso[kMaxIso];
+  // differentiated error control: points of no block crossing a candidate
+  // isovalue use the far quantizer (diff = 0: one quantizer everywhere)
+  double e2;
+  float inv2, step2;
+  int lossless2, diff;
 };
+
+// The quantizer constants of one point.
+struct QuantP {
+  double e;
+  float inv, step;
+  int lossless;
+};
+
+__host__ __device__ inline QuantP quant_pick(const Geo &g, bool far) {
+  QuantP q;
+  q.e = far ? g.e2 : g.e;
+  q.inv = far ? g.inv2 : g.inv;
+  q.step = far ? g.step2 : g.step;
+  q.lossless = far ? g.lossless2 : g.lossless;
+  return q;
+}
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -66,6 +87,57 @@ __host__ __device__ inline void block_ext(const Geo &g, int64_t b, int64_t o[3],
     hi[a] = o[a] + g.B;
     if (hi[a] > g.n[a] - 1) hi[a] = g.n[a] - 1;
   }
+}
+
+// Differentiated error control (Sec. II.A: blocks with different error
+// bounds).  A block is active when the input on its closed extent crosses a
+// candidate isovalue; a point takes the near bound when any block whose
+// closed extent contains it is active.  A point shared by blocks so gets one
+// bound, hence one value, in all of them.  Block b's points fall in 27
+// position classes: per axis 0 on the face shared with the lower neighbour,
+// 2 on the face shared with the upper one, 1 otherwise; bit 9cz + 3cy + cx
+// of `lut` tells whether the class takes the near bound.
+struct NearSel {
+  uint32_t lut;
+  uint32_t lo[3], hi[3];   // coordinates of the shared faces (0xffffffff: no neighbour)
+};
+
+// act[i * stride] bit 0: block i is active.  Every lane of the wave takes
+// part (two ballots); lane t < 27 looks at neighbour t, then at class t.
+__device__ inline NearSel near_sel(const Geo &g, const uint32_t *act, uint32_t stride, int64_t b,
+                                   const int64_t o[3], const int64_t hi[3]) {
+  const int64_t bi[3] = {b / (g.nb[2] * g.nb[1]), (b / g.nb[2]) % g.nb[1], b % g.nb[2]};
+  const int lane = (int)__lane_id();
+  bool a = false;
+  if (lane < 27) {
+    const int64_t nz = bi[0] + lane / 9 - 1, ny = bi[1] + (lane / 3) % 3 - 1, nx = bi[2] + lane % 3 - 1;
+    if (nz >= 0 && nz < g.nb[0] && ny >= 0 && ny < g.nb[1] && nx >= 0 && nx < g.nb[2])
+      a = (act[(uint64_t)((nz * g.nb[1] + ny) * g.nb[2] + nx) * stride] & 1u) != 0;
+  }
+  const uint64_t M = __ballot(a);
+  bool nr = false;
+  if (lane < 27) {
+    // the blocks holding a point of class (cz, cy, cx): offsets {0, c - 1} per axis
+    const int cz = lane / 9, cy = (lane / 3) % 3, cx = lane % 3;
+    for (int dz = min(cz - 1, 0); dz <= max(cz - 1, 0); dz++)
+      for (int dy = min(cy - 1, 0); dy <= max(cy - 1, 0); dy++)
+        for (int dx = min(cx - 1, 0); dx <= max(cx - 1, 0); dx++)
+          nr |= ((M >> ((dz + 1) * 9 + (dy + 1) * 3 + (dx + 1))) & 1ull) != 0;
+  }
+  NearSel s;
+  s.lut = (uint32_t)__ballot(nr);
+  for (int ax = 0; ax < 3; ax++) {
+    s.lo[ax] = bi[ax] > 0 ? (uint32_t)o[ax] : 0xffffffffu;
+    s.hi[ax] = bi[ax] + 1 < g.nb[ax] ? (uint32_t)hi[ax] : 0xffffffffu;
+  }
+  return s;
+}
+
+__device__ inline bool near_at(const NearSel &s, uint32_t z, uint32_t y, uint32_t x) {
+  const uint32_t cz = z == s.lo[0] ? 0u : (z == s.hi[0] ? 2u : 1u);
+  const uint32_t cy = y == s.lo[1] ? 0u : (y == s.hi[1] ? 2u : 1u);
+  const uint32_t cx = x == s.lo[2] ? 0u : (x == s.hi[2] ? 2u : 1u);
+  return ((s.lut >> (cz * 9u + cy * 3u + cx)) & 1u) != 0;
 }
 
 // Division by a runtime constant d for dividends below 2^31: with

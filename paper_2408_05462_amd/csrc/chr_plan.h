@@ -51,6 +51,7 @@ struct EncPlan {
   void *result;                  // chr_result*
   int32_t *codes;
   uint8_t *flags;
+  uint32_t *act;                 // per block: 1 = active (differentiated error control only)
 };
 
 // Reconstruction of levels L..lo.

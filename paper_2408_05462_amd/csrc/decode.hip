@@ -83,6 +83,15 @@ __device__ inline SecView open_section(const DecPlan &D, int64_t b, int l, uint3
   return v;
 }
 
+// Block activity flags of a differentiated stream: bit 0 of the spare word
+// of each block-table record (stride 4 words).
+__device__ inline NearSel dec_near(const DecPlan &D, int64_t b, const int64_t o[3], const int64_t hi[3]) {
+  const Geo &g = D.g;
+  const uint32_t *act =
+      reinterpret_cast<const uint32_t *>(D.s + kHeaderBytes + 16 * (uint64_t)g.nblocks * (uint64_t)g.nL + 12);
+  return near_sel(g, act, 4u, b, o, hi);
+}
+
 __device__ inline void set_status(const DecPlan &D, int32_t code) {
   if (D.status) atomicMin(D.status, code);
 }
@@ -109,8 +118,8 @@ __device__ inline bool block_needed(const DecPlan &D, int64_t b) {
 // wave takes part in the tile's offset scan); calls emit(z, y, x, value) for
 // every point.
 template <class Emit>
-__device__ void dec_tile(const DecPlan &D, const SecView &v, int l, const int64_t o[3], const Sec &s, uint32_t t,
-                         uint32_t kbeg, uint32_t kend, Emit emit) {
+__device__ void dec_tile(const DecPlan &D, const SecView &v, int l, const int64_t o[3], const NearSel &ns, const Sec &s,
+                         uint32_t t, uint32_t kbeg, uint32_t kend, Emit emit) {
   const Geo &g = D.g;
   const int L = g.nL - 1;
   const int lane = lane_id();
@@ -159,7 +168,8 @@ __device__ void dec_tile(const DecPlan &D, const SecView &v, int l, const int64_
     } else {
       const float p = (l == L) ? 0.0f : predict(Gp, g0, g1, g2, l, z, y, x);
       const int32_t q = (int32_t)(zc >> 1) ^ -(int32_t)(zc & 1u);
-      r = g.lossless ? p : __fadd_rn(p, __fmul_rn((float)q, g.step));
+      const QuantP qp = quant_pick(g, g.diff && !near_at(ns, z, y, x));
+      r = qp.lossless ? p : __fadd_rn(p, __fmul_rn((float)q, qp.step));
     }
     emit(z, y, x, r);
   }
@@ -175,6 +185,7 @@ __global__ __launch_bounds__(kBS) void k_decode_coarse(DecPlan D) {
   const int lmin = D.lo > 3 ? D.lo : 3;  // levels 2 and 1 have wide kernels of their own
   int64_t o[3], hi[3];
   block_ext(g, b, o, hi);
+  const NearSel ns = g.diff ? dec_near(D, b, o, hi) : NearSel{};
   for (int l = L; l >= lmin; l--) {
     float *dst = D.gp[l];
     const int64_t *gd = D.gd[l];
@@ -199,7 +210,7 @@ __global__ __launch_bounds__(kBS) void k_decode_coarse(DecPlan D) {
       if (threadIdx.x == 0) set_status(D, -4);
     } else {
       for (uint32_t t = wave; t < v.ntile; t += kWaves)
-        dec_tile(D, v, l, o, s, t, 0u, 64u, [&](uint32_t z, uint32_t y, uint32_t x, float r) {
+        dec_tile(D, v, l, o, ns, s, t, 0u, 64u, [&](uint32_t z, uint32_t y, uint32_t x, float r) {
           dst[((size_t)(z >> l) * (uint32_t)gd[1] + (y >> l)) * (uint32_t)gd[2] + (x >> l)] = r;
         });
     }
@@ -236,7 +247,8 @@ __global__ __launch_bounds__(kBS) void k_decode_fine(DecPlan D) {
   // reconstruction, its whole closed extent (a neighbour owning the shared
   // faces may be left out; both write identical values where both run)
   const bool all = D.prune != 0;
-  dec_tile(D, v, 0, o, s, t, 0u, 64u, [&](uint32_t z, uint32_t y, uint32_t x, float r) {
+  const NearSel ns = g.diff ? dec_near(D, b, o, hi) : NearSel{};
+  dec_tile(D, v, 0, o, ns, s, t, 0u, 64u, [&](uint32_t z, uint32_t y, uint32_t x, float r) {
     if (!all && (z >= ez || y >= ey)) return;
     float *row = out + ((size_t)z * (uint32_t)n1 + y) * (uint32_t)n2;
     if (all || x < ex) row[x] = r;
@@ -291,7 +303,8 @@ __global__ __launch_bounds__(kBS) void k_decode_level(DecPlan D, int l) {
     return;
   }
   const int lv = l;
-  dec_tile(D, v, l, o, s, t, wave * 16u, wave * 16u + 16u, [&](uint32_t z, uint32_t y, uint32_t x, float r) {
+  const NearSel ns = g.diff ? dec_near(D, b, o, hi) : NearSel{};
+  dec_tile(D, v, l, o, ns, s, t, wave * 16u, wave * 16u + 16u, [&](uint32_t z, uint32_t y, uint32_t x, float r) {
     dst[((size_t)(z >> lv) * (uint32_t)gd[1] + (y >> lv)) * (uint32_t)gd[2] + (x >> lv)] = r;
   });
 }
@@ -305,7 +318,7 @@ __global__ __launch_bounds__(kBS) void k_decode_level(DecPlan D, int l) {
 // the points the block owns plus the even points of even rows taken from
 // level 1; levels 1 and 2 write every point of their section into grid LV,
 // after carrying the block's points of grid LV + 1 over into it.
-template <int LV>
+template <int LV, bool DIFF>
 __device__ __forceinline__ void decode_fast(const DecPlan &D) {
   const Geo &g = D.g;
   uint32_t gxi, b;
@@ -358,6 +371,11 @@ __device__ __forceinline__ void decode_fast(const DecPlan &D) {
   const uint32_t h2x4 = h2 * 4u, h12x4 = h1 * h2 * 4u;
   const float step = g.step;
   const int lossless = g.lossless;
+  NearSel ns{};
+  if (DIFF) {
+    const int64_t o3[3] = {bp.o[0], bp.o[1], bp.o[2]}, hi3[3] = {bp.hi[0], bp.hi[1], bp.hi[2]};
+    ns = dec_near(D, b, o3, hi3);
+  }
 
   const uint32_t c = t * 64 + (uint32_t)lane;
   const uint8_t *tt = v.p + 16 + 12 * (uint64_t)t;
@@ -394,7 +412,7 @@ __device__ __forceinline__ void decode_fast(const DecPlan &D) {
     float pa[kDecGroup][8], r[kDecGroup];
     uint32_t pw0[kDecGroup], pw1[kDecGroup], xv[kDecGroup], orow[kDecGroup], off[kDecGroup];
     bool zu[kDecGroup], yu[kDecGroup], xu[kDecGroup], ex[kDecGroup], wr[kDecGroup], wx[kDecGroup], ev[kDecGroup],
-        e1[kDecGroup];
+        e1[kDecGroup], far[kDecGroup];
 #pragma unroll
     for (int u = 0; u < kDecGroup; u++) {
       const uint32_t k = min(k0 + (uint32_t)u, nc - 1);
@@ -405,6 +423,7 @@ __device__ __forceinline__ void decode_fast(const DecPlan &D) {
       sec_point24(s, rc, min(jr, jmax), zz_, vv, uu);
       // (zz_, V, U): the point on the level-LV grid (zz_ relative to the block)
       const uint32_t V = oyl + vv, U = oxl + uu;
+      far[u] = DIFF && !near_at(ns, bp.o[0] + (zz_ << LV), V << LV, U << LV);
       const uint32_t zl = zz_ >> 1, yl = V >> 1, xl = U >> 1;
       zu[u] = (zz_ & 1u) && (zp + zl + 1 < h0);
       yu[u] = (V & 1u) && (yl + 1 < h1);
@@ -457,7 +476,9 @@ __device__ __forceinline__ void decode_fast(const DecPlan &D) {
       uint32_t zc = (o + wk > 32u) ? ((pw0[u] >> o) | (pw1[u] << (32u - o))) : (pw0[u] >> o);
       zc = wk ? (zc & ((1u << wk) - 1u)) : 0u;
       const int32_t q = (int32_t)(zc >> 1) ^ -(int32_t)(zc & 1u);
-      const float rq = lossless ? p : __fadd_rn(p, __fmul_rn((float)q, step));
+      const float st = DIFF && far[u] ? g.step2 : step;
+      const int ll = DIFF && far[u] ? g.lossless2 : lossless;
+      const float rq = ll ? p : __fadd_rn(p, __fmul_rn((float)q, st));
       r[u] = ex[u] ? __uint_as_float(xv[u]) : rq;
       hold(r[u]);
       hold(pa[u][0]);
@@ -476,9 +497,12 @@ __device__ __forceinline__ void decode_fast(const DecPlan &D) {
   }
 }
 
-__global__ __launch_bounds__(kBS) void k_decode_l0(DecPlan D) { decode_fast<0>(D); }
-__global__ __launch_bounds__(kBS) void k_decode_l1(DecPlan D) { decode_fast<1>(D); }
-__global__ __launch_bounds__(kBS) void k_decode_l2(DecPlan D) { decode_fast<2>(D); }
+template <bool DIFF>
+__global__ __launch_bounds__(kBS) void k_decode_l0(DecPlan D) { decode_fast<0, DIFF>(D); }
+template <bool DIFF>
+__global__ __launch_bounds__(kBS) void k_decode_l1(DecPlan D) { decode_fast<1, DIFF>(D); }
+template <bool DIFF>
+__global__ __launch_bounds__(kBS) void k_decode_l2(DecPlan D) { decode_fast<2, DIFF>(D); }
 
 // Even points of even rows in blocks one point wide along x (no level-0
 // point in those rows writes them).
@@ -550,10 +574,14 @@ void launch_decode(const DecPlan &p, hipStream_t s) {
       const int64_t ntl = ceil_div(ceil_div(sl.npts, 64), 64);
       const dim3 grid((unsigned)(ntl > 0 ? ntl : 1), (unsigned)g.nblocks);
       prof_mark(l == 1 ? "k_decode_l1" : "k_decode_l2", s, 0);
-      if (l == 1 && L >= 2 && slab32 && p.l0.small)
-        k_decode_l1<<<grid, dim3(kBS), 0, s>>>(p);  // one tile per workgroup: 16 chunks per wave
-      else if (l == 2 && L >= 3 && slab32 && p.l0.small)
-        k_decode_l2<<<grid, dim3(kBS), 0, s>>>(p);
+      if (l == 1 && L >= 2 && slab32 && p.l0.small) {
+        // one tile per workgroup: 16 chunks per wave
+        if (g.diff) k_decode_l1<true><<<grid, dim3(kBS), 0, s>>>(p);
+        else k_decode_l1<false><<<grid, dim3(kBS), 0, s>>>(p);
+      } else if (l == 2 && L >= 3 && slab32 && p.l0.small) {
+        if (g.diff) k_decode_l2<true><<<grid, dim3(kBS), 0, s>>>(p);
+        else k_decode_l2<false><<<grid, dim3(kBS), 0, s>>>(p);
+      }
       else
         k_decode_level<<<grid, dim3(kBS), 0, s>>>(p, l);
       prof_mark(l == 1 ? "k_decode_l1" : "k_decode_l2", s, 1);
@@ -566,7 +594,8 @@ void launch_decode(const DecPlan &p, hipStream_t s) {
     if (L >= 1 && slab32 && p.l0.small) {
       const int64_t nch0 = ceil_div(s0.npts, 64);
       const int64_t gx0 = ceil_div(nch0 > 0 ? nch0 : 1, (int64_t)kWaves * p.cpw0);
-      k_decode_l0<<<dim3((unsigned)gx0, (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
+      if (g.diff) k_decode_l0<true><<<dim3((unsigned)gx0, (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
+      else k_decode_l0<false><<<dim3((unsigned)gx0, (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
     } else {
       k_decode_fine<<<dim3((unsigned)ceil_div(ntile > 0 ? ntile : 1, kWaves), (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
     }

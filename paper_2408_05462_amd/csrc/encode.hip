@@ -67,7 +67,7 @@ __device__ inline void copy_coarse(const float *__restrict__ src, const int64_t 
 // Error-bounded linear quantization: q = rint((x-p)/(2e)) (half even), the
 // reconstruction p + q*2e, an outlier when |q| > qmax or the reconstruction
 // misses the bound (checked in double).  Lossless mode: q = 0, x' = p.
-__device__ inline void quantize(const Geo &g, float x, float p, int32_t &q, int &O, float &xr) {
+__device__ inline void quantize(const QuantP &g, int qmax, float x, float p, int32_t &q, int &O, float &xr) {
   if (g.lossless) {
     q = 0;
     xr = p;
@@ -76,13 +76,17 @@ __device__ inline void quantize(const Geo &g, float x, float p, int32_t &q, int 
   }
   const float d = __fsub_rn(x, p);
   const float qf = rintf(__fmul_rn(d, g.inv));
-  if (!(fabsf(qf) <= (float)g.qmax)) {
+  if (!(fabsf(qf) <= (float)qmax)) {
     q = 0; O = 1; xr = p;
     return;
   }
   xr = __fadd_rn(p, __fmul_rn(qf, g.step));
   q = (int32_t)qf;
   O = !(fabs((double)xr - (double)x) <= g.e);
+}
+
+__device__ inline void quantize(const Geo &g, float x, float p, int32_t &q, int &O, float &xr) {
+  quantize(quant_pick(g, false), g.qmax, x, p, q, O, xr);
 }
 
 // Number of candidate isovalues k with k <= v; equal counts for x and x'
@@ -128,7 +132,7 @@ __device__ void part_store(const Part &a, Part *dst) {
 // Encodes chunk c of the level-l section of block b into its slot.
 template <int KB>
 __device__ void enc_chunk(const EncPlan &P, int l, int64_t b, const int64_t o[3], const int64_t own[3],
-                          const Sec &s, uint32_t c, uint32_t *pack, Part &acc) {
+                          const NearSel &ns, const Sec &s, uint32_t c, uint32_t *pack, Part &acc) {
   const Geo &g = P.g;
   float iso[KB];
 #pragma unroll
@@ -151,7 +155,7 @@ __device__ void enc_chunk(const EncPlan &P, int l, int64_t b, const int64_t o[3]
       const int64_t *gd = P.gd[l + 1];
       p = predict(P.G + P.g_off[l + 1], (uint32_t)gd[0], (uint32_t)gd[1], (uint32_t)gd[2], l, z, y, xx);
     }
-    quantize(g, x, p, q, O, xr);
+    quantize(quant_pick(g, g.diff && !near_at(ns, z, y, xx)), g.qmax, x, p, q, O, xr);
     if (!O && g.K > 0) C = rank_of<KB>(iso, g.K, x) != rank_of<KB>(iso, g.K, xr);
     if (O || C) { xr = x; q = 0; }
     if (l >= 1) {
@@ -215,6 +219,7 @@ __global__ __launch_bounds__(kBS) void k_encode_coarse(EncPlan P, int lmin) {
   int64_t o[3], hi[3], own[3];
   block_ext(g, b, o, hi);
   owned_end(g, o, own);
+  const NearSel ns = g.diff ? near_sel(g, P.act, 1u, b, o, hi) : NearSel{};
   Part acc;
   part_init(acc);
   for (int l = L; l >= lmin; l--) {
@@ -226,7 +231,7 @@ __global__ __launch_bounds__(kBS) void k_encode_coarse(EncPlan P, int lmin) {
     const Sec s = sec_geom(o, hi, l, L);
     const uint32_t nch = (s.npts + 63) / 64;
     for (uint32_t c = wave; c < P.maxch[l]; c += kWaves) {
-      if (c < nch) enc_chunk<KB>(P, l, b, o, own, s, c, pack[wave], acc);
+      if (c < nch) enc_chunk<KB>(P, l, b, o, own, ns, s, c, pack[wave], acc);
       else zero_slot(P, l, b, c);
     }
     __syncthreads();
@@ -248,6 +253,7 @@ __global__ __launch_bounds__(kBS) void k_encode_l1(EncPlan P) {
   int64_t o[3], hi[3], own[3];
   block_ext(g, b, o, hi);
   owned_end(g, o, own);
+  const NearSel ns = g.diff ? near_sel(g, P.act, 1u, b, o, hi) : NearSel{};
   if (L >= 2) {
     copy_coarse(P.G + P.g_off[2], P.gd[2], P.G + P.g_off[1], P.gd[1], o, hi, 2, bx * kWaves + wave,
                 gridDim.x * kWaves);
@@ -259,7 +265,7 @@ __global__ __launch_bounds__(kBS) void k_encode_l1(EncPlan P) {
   for (int k = 0; k < kChunksPerWave; k++) {
     const uint32_t c = (bx * kChunksPerWave + k) * kWaves + wave;
     if (c >= P.maxch[1]) break;
-    if (c < nch) enc_chunk<KB>(P, 1, b, o, own, s, c, pack[wave], acc);
+    if (c < nch) enc_chunk<KB>(P, 1, b, o, own, ns, s, c, pack[wave], acc);
     else zero_slot(P, 1, b, c);
   }
   part_store(acc, &P.part[b * P.part_per_block + P.part_l1 + bx]);
@@ -276,6 +282,7 @@ __global__ __launch_bounds__(kBS) void k_encode_fine(EncPlan P) {
   int64_t o[3], hi[3], own[3];
   block_ext(g, b, o, hi);
   owned_end(g, o, own);
+  const NearSel ns = g.diff ? near_sel(g, P.act, 1u, b, o, hi) : NearSel{};
   const Sec s = sec_geom(o, hi, 0, L);
   const uint32_t nch = (s.npts + 63) / 64;
   Part acc;
@@ -283,7 +290,7 @@ __global__ __launch_bounds__(kBS) void k_encode_fine(EncPlan P) {
   for (int k = 0; k < P.cpw0; k++) {
     const uint32_t c = (blockIdx.x * P.cpw0 + k) * kWaves + wave;
     if (c >= P.maxch[0]) break;
-    if (c < nch) enc_chunk<KB>(P, 0, b, o, own, s, c, pack[wave], acc);
+    if (c < nch) enc_chunk<KB>(P, 0, b, o, own, ns, s, c, pack[wave], acc);
     else zero_slot(P, 0, b, c);
   }
   part_store(acc, &P.part[b * P.part_per_block + blockIdx.x]);
@@ -325,8 +332,9 @@ __device__ inline void pack_chunk(const EncPlan &P, int64_t slot, uint32_t zz, b
 // above), G at a time: the loads of all G are issued first, every value is
 // computed before any branch or store, so a wave keeps several chunks' reads
 // in flight and no load is left pending on a path.  The optional per-point
-// outputs are compiled in only when requested.
-template <int LV, bool AUX, int KB, int G>
+// outputs, and the per-point choice of quantizer of differentiated error
+// control, are compiled in only when requested.
+template <int LV, bool AUX, int KB, int G, bool DIFF>
 __device__ __forceinline__ void encode_fast(const EncPlan &P, uint32_t (*pack)[32]) {
   uint32_t gxi, b;
   xcd_remap(gxi, b);
@@ -336,6 +344,11 @@ __device__ __forceinline__ void encode_fast(const EncPlan &P, uint32_t (*pack)[3
   // stays in scalar registers across the loop's stores.
   const Geo &gq = P.g;
   const BlockPos bp = block_pos(gq, P.l0, b);
+  NearSel ns{};
+  if (DIFF) {
+    const int64_t o[3] = {bp.o[0], bp.o[1], bp.o[2]}, hi[3] = {bp.hi[0], bp.hi[1], bp.hi[2]};
+    ns = near_sel(gq, P.act, 1u, b, o, hi);
+  }
   if (LV >= 1) {
     // the block's points of grid LV + 1 carry over into grid LV unchanged
     const int64_t o[3] = {bp.o[0], bp.o[1], bp.o[2]}, hi[3] = {bp.hi[0], bp.hi[1], bp.hi[2]};
@@ -378,7 +391,7 @@ __device__ __forceinline__ void encode_fast(const EncPlan &P, uint32_t (*pack)[3
 #pragma unroll 1
   for (int k0 = 0; k0 < cpw; k0 += G) {
     float xs[G], pa[G][8], xrs[G];
-    bool zu[G], yu[G], xu[G], in[G], own[G];
+    bool zu[G], yu[G], xu[G], in[G], own[G], far[G];
     uint32_t gi[G], go[G];
 #pragma unroll
     for (int u = 0; u < G; u++) {
@@ -405,6 +418,7 @@ __device__ __forceinline__ void encode_fast(const EncPlan &P, uint32_t (*pack)[3
       pa[u][6] = ldf(Pb, o11); pa[u][7] = ldf(Pb, o11 + dxo);
       in[u] = jr < s.npts;
       own[u] = zr < ownz && y < owny && xx < ownx;
+      far[u] = DIFF && !near_at(ns, bp.o[0] + zr, y, xx);
       gi[u] = AUX ? mad24s(prow, n2, xx) : 0u;                  // the point in the block's slab
       go[u] = LV >= 1 ? mad24s(mad24s(w, f1, V), f2, U) * 4u : 0u;  // its slot in grid LV
     }
@@ -421,7 +435,8 @@ __device__ __forceinline__ void encode_fast(const EncPlan &P, uint32_t (*pack)[3
       int32_t q;
       int O, C = 0;
       float xr;
-      quantize(gq, x, p, q, O, xr);
+      if (DIFF) quantize(quant_pick(gq, far[u]), gq.qmax, x, p, q, O, xr);
+      else quantize(gq, x, p, q, O, xr);
       if (!O && K > 0) C = rank_of<KB>(iso, K, x) != rank_of<KB>(iso, K, xr);
       if (O || C) { xr = x; q = 0; }
       zzs[u] = in[u] ? (((uint32_t)q << 1) ^ (uint32_t)(q >> 31)) : 0u;
@@ -484,22 +499,57 @@ __device__ __forceinline__ void encode_fast(const EncPlan &P, uint32_t (*pack)[3
   part_store(acc, &P.part[(int64_t)b * P.part_per_block + (LV == 0 ? 0 : LV == 1 ? P.part_l1 : P.part_l2) + gxi]);
 }
 
-template <bool AUX, int KB, int G>
+template <bool AUX, int KB, int G, bool DIFF>
 __global__ __launch_bounds__(kBS) void k_encode_l0(EncPlan P) {
   __shared__ uint32_t pack[kWaves][32];
-  encode_fast<0, AUX, KB, G>(P, pack);
+  encode_fast<0, AUX, KB, G, DIFF>(P, pack);
 }
 
-template <bool AUX, int KB, int G>
+template <bool AUX, int KB, int G, bool DIFF>
 __global__ __launch_bounds__(kBS) void k_encode_l1s(EncPlan P) {
   __shared__ uint32_t pack[kWaves][32];
-  encode_fast<1, AUX, KB, G>(P, pack);
+  encode_fast<1, AUX, KB, G, DIFF>(P, pack);
 }
 
-template <bool AUX, int KB, int G>
+template <bool AUX, int KB, int G, bool DIFF>
 __global__ __launch_bounds__(kBS) void k_encode_l2s(EncPlan P) {
   __shared__ uint32_t pack[kWaves][32];
-  encode_fast<2, AUX, KB, G>(P, pack);
+  encode_fast<2, AUX, KB, G, DIFF>(P, pack);
+}
+
+// Differentiated error control: block b is active when the input on its
+// closed extent crosses a candidate isovalue (min < k <= max).  One
+// workgroup per block, a wave per row of the extent.
+__global__ __launch_bounds__(kBS) void k_block_active(EncPlan P) {
+  __shared__ uint32_t red[kWaves][2];
+  const Geo &g = P.g;
+  const int64_t b = blockIdx.x;
+  int64_t o[3], hi[3];
+  block_ext(g, b, o, hi);
+  const uint32_t ny = (uint32_t)(hi[1] - o[1] + 1), nx = (uint32_t)(hi[2] - o[2] + 1);
+  const uint32_t nrows = (uint32_t)(hi[0] - o[0] + 1) * ny;
+  const int wave = threadIdx.x / kWave, lane = lane_id();
+  uint32_t mn = 0xffffffffu, mx = 0u;  // order-preserving keys of the values
+  for (uint32_t r = wave; r < nrows; r += kWaves) {
+    const uint32_t z = r / ny, y = r - z * ny;
+    const float *row = P.x + ((size_t)(o[0] + z) * (size_t)g.n[1] + (size_t)(o[1] + y)) * (size_t)g.n[2] + o[2];
+    for (uint32_t x = lane; x < nx; x += kWave) {
+      const uint32_t k = ord_of(row[x]);
+      mn = min(mn, k);
+      mx = max(mx, k);
+    }
+  }
+  mn = wave_min_u(mn);
+  mx = wave_max_u(mx);
+  if (lane == 0) { red[wave][0] = mn; red[wave][1] = mx; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < kWaves; i++) { mn = min(mn, red[i][0]); mx = max(mx, red[i][1]); }
+    const float vmn = of_ord(mn), vmx = of_ord(mx);
+    uint32_t a = 0;
+    for (int j = 0; j < g.K; j++) a |= (vmn < g.iso[j] && g.iso[j] <= vmx) ? 1u : 0u;
+    P.act[b] = a;
+  }
 }
 
 // Byte size of every section from the scanned chunk sizes.
@@ -746,7 +796,7 @@ __global__ __launch_bounds__(kBS) void k_block_table(EncPlan P) {
     put32(P, bt, __float_as_uint(of_ord(t.rmin)));
     put32(P, bt + 4, __float_as_uint(of_ord(t.rmax)));
     put32(P, bt + 8, sum);
-    put32(P, bt + 12, 0);
+    put32(P, bt + 12, g.diff ? P.act[b] : 0u);   // bit 0: active block (differentiated error control)
   }
 }
 
@@ -824,11 +874,18 @@ __device__ void header_words(const EncPlan &P, uint64_t total, bool fits, uint32
     h[132 / 4] = __float_as_uint(vmax);
     h64(136, (uint64_t)g.nblocks);
     for (int a = 0; a < 3; a++) h[(144 + 4 * a) / 4] = (uint32_t)g.nb[a];
-    h[156 / 4] = g.lossless ? 1u : 0u;
+    h[156 / 4] = (g.lossless ? 1u : 0u) | (g.diff ? 2u : 0u) | (g.diff && g.lossless2 ? 4u : 0u);
     h64(160, total);
     h64(168, redc[0][0]);
     h64(176, redc[0][1]);
     h64(184, P.payload_off);
+    if (g.diff) {
+      uint64_t e2;
+      __builtin_memcpy(&e2, &g.e2, 8);
+      h64(192, e2);
+      h[200 / 4] = __float_as_uint(g.inv2);
+      h[204 / 4] = __float_as_uint(g.step2);
+    }
     h[248 / 4] = sum;
     uint32_t hs = 0;
     for (uint32_t j = 0; j < 63; j++) hs += fmix32(h[j] ^ (j * 0x9E3779B9u));
@@ -874,7 +931,7 @@ void encode_pack_layout(EncPlan &p) {
   for (int l = L + 1; l < kMaxLevels; l++) { p.pack_base[l] = base; p.pack_gpb[l] = 1; }
 }
 
-template <int KB>
+template <int KB, bool DIFF>
 void launch_encode_levels(const EncPlan &p, hipStream_t s) {
   const Geo &g = p.g;
   const int L = g.nL - 1;
@@ -884,8 +941,8 @@ void launch_encode_levels(const EncPlan &p, hipStream_t s) {
     k_encode_coarse<KB><<<dim3((unsigned)g.nblocks), dim3(kBS), 0, s>>>(p, p.l2fast ? 3 : 2);
     if (p.l2fast) {
       const dim3 grid2((unsigned)encode_l2_groups(p), (unsigned)g.nblocks);
-      if (!p.codes && !p.flags) k_encode_l2s<false, KB, 4><<<grid2, dim3(kBS), 0, s>>>(p);
-      else k_encode_l2s<true, KB, 1><<<grid2, dim3(kBS), 0, s>>>(p);
+      if (!p.codes && !p.flags) k_encode_l2s<false, KB, 4, DIFF><<<grid2, dim3(kBS), 0, s>>>(p);
+      else k_encode_l2s<true, KB, 1, DIFF><<<grid2, dim3(kBS), 0, s>>>(p);
     }
     prof_mark("k_encode_coarse", s, 1);
   }
@@ -896,9 +953,9 @@ void launch_encode_levels(const EncPlan &p, hipStream_t s) {
     const dim3 grid1((unsigned)encode_l1_groups(p), (unsigned)g.nblocks);
     prof_mark("k_encode_l1", s, 0);
     if (L >= 2 && fast && !p.codes && !p.flags)
-      k_encode_l1s<false, KB, 4><<<grid1, dim3(kBS), 0, s>>>(p);
+      k_encode_l1s<false, KB, 4, DIFF><<<grid1, dim3(kBS), 0, s>>>(p);
     else if (L >= 2 && fast)
-      k_encode_l1s<true, KB, 1><<<grid1, dim3(kBS), 0, s>>>(p);
+      k_encode_l1s<true, KB, 1, DIFF><<<grid1, dim3(kBS), 0, s>>>(p);
     else
       k_encode_l1<KB><<<grid1, dim3(kBS), 0, s>>>(p);
     prof_mark("k_encode_l1", s, 1);
@@ -907,11 +964,11 @@ void launch_encode_levels(const EncPlan &p, hipStream_t s) {
     prof_mark("k_encode_fine", s, 0);
     const dim3 grid0((unsigned)gx, (unsigned)g.nblocks);
     if (L >= 1 && fast && !p.codes && !p.flags) {
-      if (p.cpw0 % 4 == 0) k_encode_l0<false, KB, 4><<<grid0, dim3(kBS), 0, s>>>(p);
-      else if (p.cpw0 % 2 == 0) k_encode_l0<false, KB, 2><<<grid0, dim3(kBS), 0, s>>>(p);
-      else k_encode_l0<false, KB, 1><<<grid0, dim3(kBS), 0, s>>>(p);
+      if (p.cpw0 % 4 == 0) k_encode_l0<false, KB, 4, DIFF><<<grid0, dim3(kBS), 0, s>>>(p);
+      else if (p.cpw0 % 2 == 0) k_encode_l0<false, KB, 2, DIFF><<<grid0, dim3(kBS), 0, s>>>(p);
+      else k_encode_l0<false, KB, 1, DIFF><<<grid0, dim3(kBS), 0, s>>>(p);
     } else if (L >= 1 && fast) {
-      k_encode_l0<true, KB, 1><<<grid0, dim3(kBS), 0, s>>>(p);
+      k_encode_l0<true, KB, 1, DIFF><<<grid0, dim3(kBS), 0, s>>>(p);
     } else {
       k_encode_fine<KB><<<grid0, dim3(kBS), 0, s>>>(p);
     }
@@ -922,10 +979,19 @@ void launch_encode_levels(const EncPlan &p, hipStream_t s) {
 void launch_encode(const EncPlan &p, int64_t, U4 *scan_tmp, uint64_t *scan_tmp64, hipStream_t s) {
   const Geo &g = p.g;
   const int64_t nsec = g.nblocks * g.nL;
-  if (g.K <= 1) launch_encode_levels<1>(p, s);
-  else if (g.K <= 2) launch_encode_levels<2>(p, s);
-  else if (g.K <= 4) launch_encode_levels<4>(p, s);
-  else launch_encode_levels<16>(p, s);
+  if (g.diff) {
+    // block activity on the input (closed extents) for the per-point quantizer choice
+    k_block_active<<<dim3((unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
+    if (g.K <= 1) launch_encode_levels<1, true>(p, s);
+    else if (g.K <= 2) launch_encode_levels<2, true>(p, s);
+    else if (g.K <= 4) launch_encode_levels<4, true>(p, s);
+    else launch_encode_levels<16, true>(p, s);
+  } else {
+    if (g.K <= 1) launch_encode_levels<1, false>(p, s);
+    else if (g.K <= 2) launch_encode_levels<2, false>(p, s);
+    else if (g.K <= 4) launch_encode_levels<4, false>(p, s);
+    else launch_encode_levels<16, false>(p, s);
+  }
   scan_u4(p.cnt, p.P, p.nslots, scan_tmp, s);
   prof_mark("k_sections", s, 0);
   k_sections<<<dim3((unsigned)ceil_div(nsec, kBS)), dim3(kBS), 0, s>>>(p);

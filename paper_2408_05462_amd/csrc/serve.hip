@@ -440,7 +440,7 @@ int chr_server_submit(chr_server *s, int dataset, float isovalue, double accurac
     const StreamRec &r = s->streams[i];
     if (r.dataset != dataset) continue;
     known = true;
-    if (r.info.error_bound <= accuracy && (best < 0 || r.info.error_bound > s->streams[best].info.error_bound))
+    if (stream_bound(r.info) <= accuracy && (best < 0 || stream_bound(r.info) > stream_bound(s->streams[best].info)))
       best = (int)i;
   }
   if (!known) return api_fail(CHR_E_INVAL, "unknown dataset");
@@ -589,7 +589,7 @@ int chr_server_poll(const chr_server *s, int64_t id, chr_request_result *out) {
   out->stream_index = r.sidx;
   out->isovalue = r.k;
   out->group_size = r.group_size;
-  out->error_bound = s->streams[r.sidx].info.error_bound;
+  out->error_bound = stream_bound(s->streams[r.sidx].info);
   out->t_submit_ms = r.t_submit;
   out->t_admit_ms = r.t_admit;
   out->t_done_ms = r.t_done;
