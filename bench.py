@@ -54,6 +54,7 @@ def parse_args():
     ap.add_argument("--no-serve", action="store_true", help="skip the served-latency part of the default run")
     ap.add_argument("--no-topology", action="store_true", help="skip the error-translation part of the default run")
     ap.add_argument("--no-entropy", action="store_true", help="skip the entropy stage of the default run")
+    ap.add_argument("--no-diff", action="store_true", help="skip differentiated error control in the default run")
     ap.add_argument("--serve-requests", type=int, default=200, help="requests of the default run's served part")
     ap.add_argument("--batch-items", type=int, default=64, help="batch64: number of timesteps")
     ap.add_argument("--branches", type=int, default=0, help="batch64: parallel branches of the graph (default: 4)")
@@ -649,6 +650,47 @@ def main():
                                                 (stage_ms[0] + enc_ms, stage_ms[1] + dec_ms, stage_ms[2]))}
         del eout, ews, dec
 
+    # differentiated error control on the same field: points of blocks that
+    # cross no candidate isovalue take a far bound of 10 e; the candidate
+    # meshes must stay those of the single-bound stream
+    dif = None
+    if not args.no_diff:
+        ef = 10.0 * e
+        pd = api.params(w["levels"], w["block"], error_bound_far=ef)
+        dbuf = torch.empty(cap, dtype=torch.uint8, device=dev)
+        api.chr_compress(x, e, isos, pd, dbuf, res, cws)
+        torch.cuda.synchronize()
+        rd_ = api.read_result(res)
+        assert rd_["status"] == 0
+        dbytes = rd_["stream_bytes"]
+        dinfo, dhead = api.chr_stream_info_dev(dbuf[:dbytes])
+        bt = 256 + 16 * dinfo.nblocks * dinfo.levels
+        act = np.frombuffer(dhead[bt: bt + 16 * dinfo.nblocks], np.uint32).reshape(-1, 4)[:, 3]
+        drec = torch.empty(shape, dtype=torch.float32, device=dev)
+        rep = 5
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record(stream)
+        for _ in range(rep):
+            api.chr_compress(x, e, isos, pd, dbuf, res, cws)
+        e1.record(stream)
+        for _ in range(rep):
+            api.chr_reconstruct(dinfo, dbuf[:dbytes], 0, ef, drec, st, rws)
+        e2.record(stream)
+        torch.cuda.synchronize()
+        assert int(st.item()) == 0
+        same = True
+        for k in isos:
+            vd, td = api.extract(drec, k)
+            vu, tu = api.extract(recon, k)
+            same &= bool(torch.equal(td, tu) and torch.equal(vd.view(torch.int32), vu.view(torch.int32)))
+        err = (drec.double() - x.double()).abs().max().item()
+        assert err <= ef and same, "differentiated stream: bound or candidate meshes"
+        dif = {"far_bound": ef, "active_blocks": round(float(act.mean()), 4),
+               "compression_ratio": round(4.0 * N / dbytes, 3), "stream_bytes": dbytes,
+               "compress_ms": round(e0.elapsed_time(e1) / rep, 4), "reconstruct_ms": round(e1.elapsed_time(e2) / rep, 4),
+               "candidate_meshes_equal_single_bound": same}
+        del dbuf, drec
+
     # served latency on the same field (the metric's second half): requests
     # at random isovalues and accuracy tiers, continuous-batching server vs
     # plain per-request launches at 0.8 x the plain path's saturation rate
@@ -700,6 +742,7 @@ def main():
         "wall_s_timed": round(wall, 3), "served": served, "topology_error_bound": topo or None, "roofline": roofline,
         "cpu_baseline": cpu,
         "workflow_model": workflow_model(4.0 * N, cr, stage_ms), "entropy_stage": ent,
+        "differentiated_error_control": dif,
     }
     print(json.dumps(out), flush=True)
 

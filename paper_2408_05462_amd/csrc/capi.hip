@@ -169,7 +169,8 @@ EncLayout enc_layout(EncPlan &P) {
   Lo.off_secsz = o; o = align256(o + sizeof(uint64_t) * (size_t)nsec);
   Lo.off_secoff = o; o = align256(o + sizeof(uint64_t) * (size_t)(nsec + 1));
   Lo.off_scan64 = o; o = align256(o + sizeof(uint64_t) * (size_t)scan_tmp_elems(nsec));
-  Lo.off_act = o; o = align256(o + sizeof(uint32_t) * (size_t)g.nblocks);
+  // activity flags, then 16 partial (min, max) key pairs per block
+  Lo.off_act = o; o = align256(o + sizeof(uint32_t) * (size_t)g.nblocks * (1 + 2 * kActSplit));
   Lo.total = o;
   return Lo;
 }

@@ -97,6 +97,8 @@ __host__ __device__ inline void block_ext(const Geo &g, int64_t b, int64_t o[3],
 // position classes: per axis 0 on the face shared with the lower neighbour,
 // 2 on the face shared with the upper one, 1 otherwise; bit 9cz + 3cy + cx
 // of `lut` tells whether the class takes the near bound.
+constexpr uint32_t kNearAll = (1u << 27) - 1u;   // every class near
+
 struct NearSel {
   uint32_t lut;
   uint32_t lo[3], hi[3];   // coordinates of the shared faces (0xffffffff: no neighbour)

@@ -20,6 +20,10 @@ struct Part {
 // Compression: per-level chunk slots hold one 64-point chunk each before the
 // stream is assembled (width/exact counts, packed codes, exact mask, exact
 // values); slots of level l for block b start at slot_base[l] + b*maxch[l].
+// Workgroups per block of the block-activity pass (differentiated error
+// control); the workspace holds 2 partial keys per block and workgroup.
+constexpr int kActSplit = 16;
+
 struct EncPlan {
   Geo g;
   L0Geo l0;

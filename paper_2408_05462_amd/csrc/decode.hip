@@ -372,10 +372,16 @@ __device__ __forceinline__ void decode_fast(const DecPlan &D) {
   const float step = g.step;
   const int lossless = g.lossless;
   NearSel ns{};
+  bool mixed = false, allfar = false;
   if (DIFF) {
     const int64_t o3[3] = {bp.o[0], bp.o[1], bp.o[2]}, hi3[3] = {bp.hi[0], bp.hi[1], bp.hi[2]};
     ns = dec_near(D, b, o3, hi3);
+    mixed = ns.lut != 0u && ns.lut != kNearAll;   // else one quantizer for the whole block
+    allfar = ns.lut == 0u;
   }
+  // scalar constants of an unmixed block
+  const float stepb = DIFF && allfar ? g.step2 : step;
+  const int llb = DIFF && allfar ? g.lossless2 : lossless;
 
   const uint32_t c = t * 64 + (uint32_t)lane;
   const uint8_t *tt = v.p + 16 + 12 * (uint64_t)t;
@@ -423,7 +429,7 @@ __device__ __forceinline__ void decode_fast(const DecPlan &D) {
       sec_point24(s, rc, min(jr, jmax), zz_, vv, uu);
       // (zz_, V, U): the point on the level-LV grid (zz_ relative to the block)
       const uint32_t V = oyl + vv, U = oxl + uu;
-      far[u] = DIFF && !near_at(ns, bp.o[0] + (zz_ << LV), V << LV, U << LV);
+      far[u] = DIFF && mixed && !near_at(ns, bp.o[0] + (zz_ << LV), V << LV, U << LV);
       const uint32_t zl = zz_ >> 1, yl = V >> 1, xl = U >> 1;
       zu[u] = (zz_ & 1u) && (zp + zl + 1 < h0);
       yu[u] = (V & 1u) && (yl + 1 < h1);
@@ -476,8 +482,8 @@ __device__ __forceinline__ void decode_fast(const DecPlan &D) {
       uint32_t zc = (o + wk > 32u) ? ((pw0[u] >> o) | (pw1[u] << (32u - o))) : (pw0[u] >> o);
       zc = wk ? (zc & ((1u << wk) - 1u)) : 0u;
       const int32_t q = (int32_t)(zc >> 1) ^ -(int32_t)(zc & 1u);
-      const float st = DIFF && far[u] ? g.step2 : step;
-      const int ll = DIFF && far[u] ? g.lossless2 : lossless;
+      const float st = DIFF && far[u] ? g.step2 : stepb;
+      const int ll = DIFF && far[u] ? g.lossless2 : llb;
       const float rq = ll ? p : __fadd_rn(p, __fmul_rn((float)q, st));
       r[u] = ex[u] ? __uint_as_float(xv[u]) : rq;
       hold(r[u]);

@@ -345,10 +345,14 @@ __device__ __forceinline__ void encode_fast(const EncPlan &P, uint32_t (*pack)[3
   const Geo &gq = P.g;
   const BlockPos bp = block_pos(gq, P.l0, b);
   NearSel ns{};
+  bool mixed = false, allfar = false;
   if (DIFF) {
     const int64_t o[3] = {bp.o[0], bp.o[1], bp.o[2]}, hi[3] = {bp.hi[0], bp.hi[1], bp.hi[2]};
     ns = near_sel(gq, P.act, 1u, b, o, hi);
+    mixed = ns.lut != 0u && ns.lut != kNearAll;   // else one quantizer for the whole block
+    allfar = ns.lut == 0u;
   }
+  const QuantP qblk = quant_pick(gq, allfar);     // scalar constants of an unmixed block
   if (LV >= 1) {
     // the block's points of grid LV + 1 carry over into grid LV unchanged
     const int64_t o[3] = {bp.o[0], bp.o[1], bp.o[2]}, hi[3] = {bp.hi[0], bp.hi[1], bp.hi[2]};
@@ -418,7 +422,7 @@ __device__ __forceinline__ void encode_fast(const EncPlan &P, uint32_t (*pack)[3
       pa[u][6] = ldf(Pb, o11); pa[u][7] = ldf(Pb, o11 + dxo);
       in[u] = jr < s.npts;
       own[u] = zr < ownz && y < owny && xx < ownx;
-      far[u] = DIFF && !near_at(ns, bp.o[0] + zr, y, xx);
+      far[u] = DIFF && mixed && !near_at(ns, bp.o[0] + zr, y, xx);
       gi[u] = AUX ? mad24s(prow, n2, xx) : 0u;                  // the point in the block's slab
       go[u] = LV >= 1 ? mad24s(mad24s(w, f1, V), f2, U) * 4u : 0u;  // its slot in grid LV
     }
@@ -435,7 +439,8 @@ __device__ __forceinline__ void encode_fast(const EncPlan &P, uint32_t (*pack)[3
       int32_t q;
       int O, C = 0;
       float xr;
-      if (DIFF) quantize(quant_pick(gq, far[u]), gq.qmax, x, p, q, O, xr);
+      if (DIFF && mixed) quantize(quant_pick(gq, far[u]), gq.qmax, x, p, q, O, xr);
+      else if (DIFF) quantize(qblk, gq.qmax, x, p, q, O, xr);
       else quantize(gq, x, p, q, O, xr);
       if (!O && K > 0) C = rank_of<KB>(iso, K, x) != rank_of<KB>(iso, K, xr);
       if (O || C) { xr = x; q = 0; }
@@ -518,38 +523,66 @@ __global__ __launch_bounds__(kBS) void k_encode_l2s(EncPlan P) {
 }
 
 // Differentiated error control: block b is active when the input on its
-// closed extent crosses a candidate isovalue (min < k <= max).  One
-// workgroup per block, a wave per row of the extent.
-__global__ __launch_bounds__(kBS) void k_block_active(EncPlan P) {
+// closed extent crosses a candidate isovalue (min < k <= max).  Workgroup
+// (s, b) reduces planes s, s + kActSplit, ... of block b's extent (each
+// thread four points at a time, loads issued together) into partial
+// order-preserving min/max keys; k_block_active_final combines them.
+
+__global__ __launch_bounds__(kBS) void k_block_minmax(EncPlan P) {
   __shared__ uint32_t red[kWaves][2];
   const Geo &g = P.g;
-  const int64_t b = blockIdx.x;
+  const int64_t b = blockIdx.y;
   int64_t o[3], hi[3];
   block_ext(g, b, o, hi);
-  const uint32_t ny = (uint32_t)(hi[1] - o[1] + 1), nx = (uint32_t)(hi[2] - o[2] + 1);
-  const uint32_t nrows = (uint32_t)(hi[0] - o[0] + 1) * ny;
-  const int wave = threadIdx.x / kWave, lane = lane_id();
-  uint32_t mn = 0xffffffffu, mx = 0u;  // order-preserving keys of the values
-  for (uint32_t r = wave; r < nrows; r += kWaves) {
-    const uint32_t z = r / ny, y = r - z * ny;
-    const float *row = P.x + ((size_t)(o[0] + z) * (size_t)g.n[1] + (size_t)(o[1] + y)) * (size_t)g.n[2] + o[2];
-    for (uint32_t x = lane; x < nx; x += kWave) {
-      const uint32_t k = ord_of(row[x]);
-      mn = min(mn, k);
-      mx = max(mx, k);
+  const uint32_t nz = (uint32_t)(hi[0] - o[0] + 1), ny = (uint32_t)(hi[1] - o[1] + 1), nx = (uint32_t)(hi[2] - o[2] + 1);
+  const uint32_t plane = ny * nx;
+  const size_t n1 = (size_t)g.n[1], n2 = (size_t)g.n[2];
+  uint32_t mn = 0xffffffffu, mx = 0u;
+  for (uint32_t z = blockIdx.x; z < nz; z += kActSplit) {
+    const float *pz = P.x + ((size_t)(o[0] + z) * n1 + (size_t)o[1]) * n2 + (size_t)o[2];
+    for (uint32_t i0 = threadIdx.x; i0 < plane; i0 += 4 * kBS) {
+      float v[4];
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const uint32_t i = min(i0 + (uint32_t)u * kBS, plane - 1);  // repeats a point: harmless for min/max
+        const uint32_t y = i / nx, x = i - y * nx;
+        v[u] = pz[(size_t)y * n2 + x];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const uint32_t k = ord_of(v[u]);
+        mn = min(mn, k);
+        mx = max(mx, k);
+      }
     }
   }
   mn = wave_min_u(mn);
   mx = wave_max_u(mx);
-  if (lane == 0) { red[wave][0] = mn; red[wave][1] = mx; }
+  const int wave = threadIdx.x / kWave;
+  if (lane_id() == 0) { red[wave][0] = mn; red[wave][1] = mx; }
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int i = 1; i < kWaves; i++) { mn = min(mn, red[i][0]); mx = max(mx, red[i][1]); }
-    const float vmn = of_ord(mn), vmx = of_ord(mx);
-    uint32_t a = 0;
-    for (int j = 0; j < g.K; j++) a |= (vmn < g.iso[j] && g.iso[j] <= vmx) ? 1u : 0u;
-    P.act[b] = a;
+    uint32_t *part = P.act + g.nblocks + 2 * (b * kActSplit + blockIdx.x);
+    part[0] = mn;
+    part[1] = mx;
   }
+}
+
+__global__ __launch_bounds__(kBS) void k_block_active_final(EncPlan P) {
+  const Geo &g = P.g;
+  const int64_t b = (int64_t)blockIdx.x * kBS + threadIdx.x;
+  if (b >= g.nblocks) return;
+  uint32_t mn = 0xffffffffu, mx = 0u;
+  for (int s2 = 0; s2 < kActSplit; s2++) {
+    const uint32_t *part = P.act + g.nblocks + 2 * (b * kActSplit + s2);
+    mn = min(mn, part[0]);
+    mx = max(mx, part[1]);
+  }
+  const float vmn = of_ord(mn), vmx = of_ord(mx);
+  uint32_t a = 0;
+  for (int j = 0; j < g.K; j++) a |= (vmn < g.iso[j] && g.iso[j] <= vmx) ? 1u : 0u;
+  P.act[b] = a;
 }
 
 // Byte size of every section from the scanned chunk sizes.
@@ -981,7 +1014,8 @@ void launch_encode(const EncPlan &p, int64_t, U4 *scan_tmp, uint64_t *scan_tmp64
   const int64_t nsec = g.nblocks * g.nL;
   if (g.diff) {
     // block activity on the input (closed extents) for the per-point quantizer choice
-    k_block_active<<<dim3((unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
+    k_block_minmax<<<dim3((unsigned)kActSplit, (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
+    k_block_active_final<<<dim3((unsigned)ceil_div(g.nblocks, kBS)), dim3(kBS), 0, s>>>(p);
     if (g.K <= 1) launch_encode_levels<1, true>(p, s);
     else if (g.K <= 2) launch_encode_levels<2, true>(p, s);
     else if (g.K <= 4) launch_encode_levels<4, true>(p, s);

@@ -72,19 +72,46 @@ __global__ __launch_bounds__(kBS) void k_ent_hist(EntPlan E) {
     if (h[i]) atomicAdd(&E.tab->hist[i], h[i]);
 }
 
+// 256 values held four per lane of one wave: value i in register i >> 6 of
+// lane i & 63; reads and writes at a wave-uniform index i.
+struct Lanes4 {
+  uint32_t r[4];
+};
+
+__device__ inline uint32_t l4_get(const Lanes4 &a, uint32_t i) {
+  const int l = (int)(i & 63u);
+  const uint32_t v0 = (uint32_t)__builtin_amdgcn_readlane((int)a.r[0], l);
+  const uint32_t v1 = (uint32_t)__builtin_amdgcn_readlane((int)a.r[1], l);
+  const uint32_t v2 = (uint32_t)__builtin_amdgcn_readlane((int)a.r[2], l);
+  const uint32_t v3 = (uint32_t)__builtin_amdgcn_readlane((int)a.r[3], l);
+  const uint32_t k = i >> 6;
+  return k == 0 ? v0 : k == 1 ? v1 : k == 2 ? v2 : v3;
+}
+
+__device__ inline void l4_set(Lanes4 &a, uint32_t i, uint32_t v) {
+  const bool mine = (uint32_t)lane_id() == (i & 63u);
+  const uint32_t k = i >> 6;
+  for (int r = 0; r < 4; r++) a.r[r] = (mine && k == (uint32_t)r) ? v : a.r[r];
+}
+
 // The code table (one workgroup of 256 threads, thread s for byte value s).
+// The Huffman merge runs on wave 0 with the queues in registers; the leaf
+// depths follow by pointer jumping over the parent links.
 __global__ __launch_bounds__(256) void k_ent_table(EntPlan E) {
   __shared__ uint32_t hs[256];
   __shared__ int order[256];      // present values by (count, value) increasing
   __shared__ int bits[512];       // codes per length
-  __shared__ uint64_t wt[511];
-  __shared__ int par[511], dep[511];
-  __shared__ int m_s;
+  __shared__ int par[512], anc[512], dep[512];
+  __shared__ int blc[kMaxLen + 1];
+  __shared__ uint32_t nextc[kMaxLen + 1];
+  __shared__ int maxd_s;
   __shared__ uint8_t ln[256];
   const int s = threadIdx.x;
   const uint32_t c = E.tab->hist[s];
   hs[s] = c;
   for (int i = s; i < 512; i += 256) bits[i] = 0;
+  if (s <= kMaxLen) blc[s] = 0;
+  if (s == 0) maxd_s = 0;
   __syncthreads();
   // rank among the present values by (count, value)
   int rk = 0, m = 0;
@@ -96,37 +123,87 @@ __global__ __launch_bounds__(256) void k_ent_table(EntPlan E) {
   if (c) order[rk] = s;
   ln[s] = 0;
   __syncthreads();
+  // two-queue Huffman on wave 0: leaves 0..m-1 in order, internal node j
+  // (tree node m + j) made at step j; the lighter front is taken, a leaf
+  // first on a tie (weights fit 32 bits: they sum to at most n < 2^32)
+  const int nn = 2 * m - 1;   // tree nodes when m >= 2
+  if (m >= 2 && s < kWave) {
+    Lanes4 lw, nw, pl, pn;    // leaf weights, node weights, leaf parents, node parents
+    for (int k = 0; k < 4; k++) {
+      const int idx = s + kWave * k;
+      lw.r[k] = idx < m ? hs[order[idx]] : 0u;
+      nw.r[k] = pl.r[k] = pn.r[k] = 0u;
+    }
+    uint32_t qi = 0, qj = 0, made = 0;
+    for (int step = 0; step < m - 1; step++) {
+      uint32_t wsum = 0;
+      for (int t = 0; t < 2; t++) {
+        const bool lok = qi < (uint32_t)m, nok = qj < made;
+        const uint32_t a = lok ? l4_get(lw, qi) : 0u, bw = nok ? l4_get(nw, qj) : 0u;
+        if (lok && (!nok || a <= bw)) {
+          wsum += a;
+          l4_set(pl, qi, made);
+          qi++;
+        } else {
+          wsum += bw;
+          l4_set(pn, qj, made);
+          qj++;
+        }
+      }
+      l4_set(nw, made, wsum);
+      made++;
+    }
+    for (int k = 0; k < 4; k++) {
+      const int idx = s + kWave * k;
+      if (idx < m) par[idx] = m + (int)pl.r[k];
+      if (idx < m - 1) par[m + idx] = m + (int)pn.r[k];
+    }
+  }
+  __syncthreads();
+  if (m >= 2) {
+    // depth = number of ancestors, by pointer jumping (depths stay below 256)
+    const int root = nn - 1;
+    for (int v = s; v < nn; v += 256) {
+      anc[v] = v == root ? v : par[v];
+      dep[v] = v == root ? 0 : 1;
+    }
+    __syncthreads();
+    for (int it = 0; it < 9; it++) {
+      int nd[2], na[2];
+      for (int u = 0; u < 2; u++) {
+        const int v = s + 256 * u;
+        if (v < nn) {
+          const int a = anc[v];
+          nd[u] = dep[v] + (a == v ? 0 : dep[a]);
+          na[u] = anc[a];
+        }
+      }
+      __syncthreads();
+      for (int u = 0; u < 2; u++) {
+        const int v = s + 256 * u;
+        if (v < nn) {
+          dep[v] = nd[u];
+          anc[v] = na[u];
+        }
+      }
+      __syncthreads();
+    }
+    if (s < m) {
+      const int d = min(dep[s], 511);
+      atomicAdd(&bits[d], 1);
+      atomicMax(&maxd_s, d);
+    }
+  }
+  __syncthreads();
   if (s == 0) {
-    m_s = m;
     if (m == 1) {
       bits[1] = 1;
     } else if (m >= 2) {
-      // two-queue Huffman: leaves 0..m-1 in order, internal nodes from m on;
-      // the lighter front is taken, a leaf first on a tie
-      for (int i = 0; i < m; i++) wt[i] = hs[order[i]];
-      int qi = 0, qj = m, made = m;
-      for (int step = 0; step < m - 1; step++) {
-        int pk[2];
-        for (int t = 0; t < 2; t++) {
-          if (qi < m && (qj >= made || wt[qi] <= wt[qj])) pk[t] = qi++;
-          else pk[t] = qj++;
-        }
-        wt[made] = wt[pk[0]] + wt[pk[1]];
-        par[pk[0]] = par[pk[1]] = made;
-        made++;
-      }
-      dep[made - 1] = 0;
-      int maxd = 0;
-      for (int v = made - 2; v >= 0; v--) dep[v] = dep[par[v]] + 1;
-      for (int i = 0; i < m; i++) {
-        bits[dep[i]]++;
-        maxd = max(maxd, dep[i]);
-      }
       // length limit (JPEG Annex K.3): move pairs of codes up, keeping the code complete
-      for (int i = maxd; i > kMaxLen; i--) {
+      for (int i = maxd_s; i > kMaxLen; i--) {
         while (bits[i] > 0) {
           int j = i - 2;
-          while (bits[j] == 0) j--;
+          while (j > 1 && bits[j] == 0) j--;   // a complete code always has one (j >= 1)
           bits[i] -= 2;
           bits[i - 1] += 1;
           bits[j + 1] += 2;
@@ -136,7 +213,6 @@ __global__ __launch_bounds__(256) void k_ent_table(EntPlan E) {
     }
   }
   __syncthreads();
-  m = m_s;
   // lengths to the values from the most frequent: rank by (count desc, value)
   if (c) {
     int r2 = 0;
@@ -150,27 +226,29 @@ __global__ __launch_bounds__(256) void k_ent_table(EntPlan E) {
       acc += bits[l];
     }
     ln[s] = (uint8_t)l;
+    atomicAdd(&blc[l], 1);
   }
   __syncthreads();
   // canonical codes: shorter first, consecutive in value order within a length
+  if (s == 0) {
+    uint32_t code = 0;
+    for (int l = 1; l <= kMaxLen; l++) {
+      code = (code + (uint32_t)(l > 1 ? blc[l - 1] : 0)) << 1;
+      nextc[l] = code;
+    }
+  }
+  __syncthreads();
   const int L = ln[s];
   uint32_t code = 0;
   if (L) {
-    uint32_t first = 0;
-    for (int l = 1; l <= L; l++) {
-      int cnt = 0;
-      for (int t = 0; t < 256; t++) cnt += ln[t] == l - 1 && l - 1 > 0;
-      first = (first + (uint32_t)cnt) << 1;
-    }
     int before = 0;
     for (int t = 0; t < s; t++) before += ln[t] == L;
-    code = first + (uint32_t)before;
+    code = nextc[L] + (uint32_t)before;
   }
   uint32_t r = 0;
   for (int b = 0; b < L; b++) r |= ((code >> b) & 1u) << (L - 1 - b);
   E.tab->rcode[s] = r;
   E.tab->len[s] = (uint8_t)L;
-  (void)m;
 }
 
 // Bits of each chunk (one wave per chunk, 8 bytes per lane), as 32-bit words.
@@ -282,37 +360,37 @@ struct DecE {
 
 __global__ __launch_bounds__(kBS) void k_ent_decode(DecE D) {
   __shared__ uint16_t tab[1 << kMaxLen];
-  __shared__ uint32_t code_s[256];
   __shared__ uint8_t ln[256];
+  __shared__ int blc[kMaxLen + 1];
+  __shared__ uint32_t nextc[kMaxLen + 1];
   // canonical codes of the stored lengths (as the encoder), then every
   // window whose low L bits are a value's reversed code maps to it
   const int s = threadIdx.x;
   ln[s] = D.in[kLenOff + s];
+  if (s <= kMaxLen) blc[s] = 0;
   for (int i = s; i < (1 << kMaxLen); i += kBS) tab[i] = 0;
   __syncthreads();
-  {
-    const int L = ln[s];
+  const int L = ln[s];
+  const bool has = L >= 1 && L <= kMaxLen;
+  if (has) atomicAdd(&blc[L], 1);
+  __syncthreads();
+  if (s == 0) {
     uint32_t code = 0;
-    if (L >= 1 && L <= kMaxLen) {
-      uint32_t first = 0;
-      for (int l = 1; l <= L; l++) {
-        int cnt = 0;
-        for (int t = 0; t < 256; t++) cnt += ln[t] == l - 1 && l - 1 > 0;
-        first = (first + (uint32_t)cnt) << 1;
-      }
-      int before = 0;
-      for (int t = 0; t < s; t++) before += ln[t] == L;
-      code = first + (uint32_t)before;
+    for (int l = 1; l <= kMaxLen; l++) {
+      code = (code + (uint32_t)(l > 1 ? blc[l - 1] : 0)) << 1;
+      nextc[l] = code;
     }
-    uint32_t r = 0;
-    for (int b = 0; b < L && L <= kMaxLen; b++) r |= ((code >> b) & 1u) << (L - 1 - b);
-    code_s[s] = r;
   }
   __syncthreads();
-  {
-    const int L = ln[s];
-    if (L >= 1 && L <= kMaxLen && code_s[s] < (1u << L))
-      for (uint32_t k = 0; k < (1u << (kMaxLen - L)); k++) tab[code_s[s] + (k << L)] = (uint16_t)(s | (L << 8));
+  if (has) {
+    int before = 0;
+    for (int t = 0; t < s; t++) before += ln[t] == L;
+    const uint32_t code = nextc[L] + (uint32_t)before;
+    uint32_t r = 0;
+    for (int b = 0; b < L; b++) r |= ((code >> b) & 1u) << (L - 1 - b);
+    r &= (1u << L) - 1u;
+    // (a corrupt table may overlap: entries stay in range, the result is flagged below)
+    for (uint32_t k = 0; k < (1u << (kMaxLen - L)); k++) tab[r + (k << L)] = (uint16_t)(s | (L << 8));
   }
   __syncthreads();
   const uint64_t c = (uint64_t)blockIdx.x * kBS + threadIdx.x;
@@ -327,24 +405,32 @@ __global__ __launch_bounds__(kBS) void k_ent_decode(DecE D) {
   const uint32_t *src = reinterpret_cast<const uint32_t *>(D.in + D.base);
   const uint64_t first = c * kChunk;
   const uint32_t len = (uint32_t)min<uint64_t>(kChunk, D.n - first);
-  uint64_t buf = 0;
-  uint32_t nb = 0;
+  // two words prefetched ahead of the bit buffer, so a refill does not wait
+  // for memory
   uint64_t wi = w0;
+  uint32_t n0 = wi < w1 ? src[wi] : 0u;
+  wi++;
+  uint32_t n1 = wi < w1 ? src[wi] : 0u;
+  wi++;
+  uint64_t buf = 0;
+  uint32_t nb = 0, used = 0;
   bool bad = false;
   uint64_t acc = 0;
   for (uint32_t i = 0; i < len; i++) {
     if (nb < 32) {
-      const uint64_t v = wi < w1 ? src[wi] : 0u;
-      wi++;
-      buf |= v << nb;
+      buf |= (uint64_t)n0 << nb;
       nb += 32;
+      n0 = n1;
+      n1 = wi < w1 ? src[wi] : 0u;
+      wi++;
     }
     const uint32_t e = tab[buf & ((1u << kMaxLen) - 1u)];
-    uint32_t L = e >> 8;
-    bad |= L == 0;
-    L = L ? L : 1u;
-    buf >>= L;
-    nb -= L;
+    uint32_t Ls = e >> 8;
+    bad |= Ls == 0;
+    Ls = Ls ? Ls : 1u;
+    buf >>= Ls;
+    nb -= Ls;
+    used += Ls;
     acc |= (uint64_t)(e & 255u) << (8 * (i & 7u));
     if ((i & 7u) == 7u) {
       *reinterpret_cast<uint64_t *>(D.out + first + (i & ~7u)) = acc;
@@ -352,7 +438,7 @@ __global__ __launch_bounds__(kBS) void k_ent_decode(DecE D) {
     }
   }
   for (uint32_t i = len & ~7u; i < len; i++) D.out[first + i] = (uint8_t)(acc >> (8 * (i & 7u)));
-  bad |= (wi - w0) * 32 - nb > (w1 - w0) * 32;  // read past the chunk's bits
+  bad |= (uint64_t)used > (w1 - w0) * 32;  // read past the chunk's bits
   if (bad) *D.status = CHR_E_CORRUPT;
 }
 

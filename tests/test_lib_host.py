@@ -338,3 +338,34 @@ def test_entropy_calls_reject_bad_arguments_on_the_host():
     assert lib.chr_entropy_decode(hp, p, enc.size - 8, p, 100, p, None) == L.CHR_E_CORRUPT
     assert lib.chr_entropy_decode(hp, p, enc.size, p, 99, p, None) == L.CHR_E_CAPACITY
     assert lib.chr_entropy_decode(hp, None, enc.size, p, 100, p, None) == L.CHR_E_INVAL
+
+
+def test_differentiated_stream_header_is_parsed():
+    f = np.random.default_rng(6).standard_normal((13, 17, 19)).astype(np.float32)
+    s = oracle.compress(f, 0.01, [2.0], levels=3, block=8, error_bound_far=0.25)["stream"]
+    info = api.chr_stream_info(bytes(s))
+    assert info.flags & 2 and info.error_bound_far == 0.25
+    assert info.inv_far == np.float32(1 / 0.5) and info.step_far == np.float32(0.5)
+    assert api.stream_bound(info) == 0.25
+    assert lib_verify(bytes(s)) == L.CHR_OK
+    u = oracle.compress(f, 0.01, [2.0], levels=3, block=8)["stream"]
+    iu = api.chr_stream_info(bytes(u))
+    assert not iu.flags & 2 and iu.error_bound_far == 0.0 and api.stream_bound(iu) == 0.01
+
+
+def lib_verify(b):
+    return L.load().chr_stream_verify(b, len(b))
+
+
+def test_far_bound_rejected_on_the_host():
+    lib = L.load()
+    fake = C.c_void_p(0x100000)
+    for far in (1e-4, float("inf"), float("nan"), -1.0):
+        p = api.params(3, 8, error_bound_far=far)
+        rc = lib.chr_compress(fake, L.dims3((20, 20, 20)), 1e-3, None, 0, C.byref(p), fake, 1 << 20, fake, None,
+                              None, fake, 1 << 30, None)
+        assert rc == L.CHR_E_INVAL, far
+        items = _items([(20, 20, 20)])
+        items[0].params = p
+        h = C.c_void_p()
+        assert lib.chr_batch_create(items, 1, C.byref(h)) == L.CHR_E_INVAL
