@@ -24,6 +24,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "chr_oracle.c")
 _SRC_ENT = os.path.join(_HERE, "chr_entropy.c")
+_SRC_TIERS = os.path.join(_HERE, "chr_tiers.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 OK, E_INVAL, E_ACCURACY, E_LEVEL, E_CORRUPT, E_CAPACITY, E_NOMEM = 0, -1, -2, -3, -4, -5, -6
@@ -39,7 +40,8 @@ class OracleError(RuntimeError):
 def build() -> str:
     """Compile the oracle (gcc, -O2 -ffp-contract=off, OpenMP)."""
     cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
-           "-shared", "-std=c11", "-Wall", "-Wextra", _SRC, _SRC_ENT, "-o", _LIB + ".tmp", "-lm"]
+           "-shared", "-std=c11", "-Wall", "-Wextra", _SRC, _SRC_ENT, _SRC_TIERS, "-o", _LIB + ".tmp",
+           "-lm"]
     subprocess.check_call(cmd, cwd=_HERE)
     os.replace(_LIB + ".tmp", _LIB)
     return _LIB
@@ -52,7 +54,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB) or any(os.path.getmtime(f) > os.path.getmtime(_LIB)
-                                           for f in (_SRC, _SRC_ENT, os.path.join(_HERE, "chr_oracle.h"))):
+                                           for f in (_SRC, _SRC_ENT, _SRC_TIERS, os.path.join(_HERE, "chr_oracle.h"))):
             build()
         L = C.CDLL(_LIB)
         i64p = C.POINTER(C.c_int64)
@@ -319,3 +321,67 @@ def entropy_decode(enc):
     if rc:
         raise OracleError(rc, "entropy_decode")
     return out[: n.value].copy()
+
+
+# ---- multi-tier progressive accuracy (chr_tiers.c) ---------------------------
+MAX_TIERS = 8
+
+
+def tiers_bound(shape, T, levels, block):
+    L = lib()
+    L.orc_tiers_bound.argtypes = [C.POINTER(C.c_int64), C.c_int, C.c_int, C.c_int]
+    L.orc_tiers_bound.restype = C.c_uint64
+    return int(L.orc_tiers_bound(_dims(shape), T, levels, block))
+
+
+def tiers_compress(x, bounds, isovalues=(), levels=3, block=64, qmax=32767):
+    """The tier container (uint8 array) of x at bounds[0] > bounds[1] > ..."""
+    L = lib()
+    x, px = _f32(x)
+    b = np.ascontiguousarray(np.asarray(bounds, np.float64).reshape(-1))
+    iso = np.ascontiguousarray(np.asarray(isovalues, np.float32).reshape(-1))
+    cap = tiers_bound(x.shape, len(b), levels, block)
+    out = np.zeros(cap, np.uint8)
+    nb = C.c_uint64()
+    L.orc_tiers_compress.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.c_void_p, C.c_int, C.c_void_p, C.c_int,
+                                     C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_uint64, C.POINTER(C.c_uint64)]
+    L.orc_tiers_compress.restype = C.c_int
+    rc = L.orc_tiers_compress(px, _dims(x.shape), b.ctypes.data, len(b), iso.ctypes.data, len(iso), levels, block,
+                              qmax, out.ctypes.data, cap, C.byref(nb))
+    if rc:
+        raise OracleError(rc, "tiers_compress")
+    return out[: nb.value].copy()
+
+
+def tiers_info(container):
+    L = lib()
+    c = np.ascontiguousarray(container, np.uint8)
+    T = C.c_int()
+    b = np.zeros(MAX_TIERS, np.float64)
+    tot = C.c_uint64()
+    L.orc_tiers_info.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(C.c_int), C.c_void_p, C.POINTER(C.c_uint64)]
+    L.orc_tiers_info.restype = C.c_int
+    rc = L.orc_tiers_info(c.ctypes.data, c.size, C.byref(T), b.ctypes.data, C.byref(tot))
+    if rc:
+        raise OracleError(rc, "tiers_info")
+    return T.value, b[: T.value].copy(), tot.value
+
+
+def tiers_decompress_rc(container, eb):
+    """(status, field, last tier used)."""
+    L = lib()
+    c = np.ascontiguousarray(container, np.uint8)
+    dims = tuple(int(v) for v in np.frombuffer(c[16:40].tobytes(), np.int64))
+    out = np.zeros(dims, np.float32)
+    used = C.c_int(-1)
+    L.orc_tiers_decompress.argtypes = [C.c_void_p, C.c_uint64, C.c_double, C.c_void_p, C.POINTER(C.c_int)]
+    L.orc_tiers_decompress.restype = C.c_int
+    rc = L.orc_tiers_decompress(c.ctypes.data, c.size, float(eb), out.ctypes.data, C.byref(used))
+    return rc, out, used.value
+
+
+def tiers_decompress(container, eb):
+    rc, out, used = tiers_decompress_rc(container, eb)
+    if rc:
+        raise OracleError(rc, "tiers_decompress")
+    return out, used

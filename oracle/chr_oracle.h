@@ -157,6 +157,21 @@ int orc_entropy_info(const uint8_t *in, uint64_t nbytes, uint64_t *n, uint32_t *
 /* Decodes a whole encoded stream; *n_out receives the decoded size. */
 int orc_entropy_decode(const uint8_t *in, uint64_t nbytes, uint8_t *out, uint64_t out_cap, uint64_t *n_out);
 
+/* ---- multi-tier progressive accuracy (chr_tiers.c) ---- */
+
+#define ORC_MAX_TIERS 8
+/* Container size bound for T tiers. */
+uint64_t orc_tiers_bound(const int64_t dims[3], int T, int nL, int block);
+/* Tiers at bounds[0] > bounds[1] > ... >= 0 (T <= 8); *out_bytes receives the
+ * container size (the required size on ORC_E_CAPACITY). */
+int orc_tiers_compress(const float *x, const int64_t dims[3], const double *bounds, int T, const float *iso,
+                       int n_iso, int nL, int block, int qmax, uint8_t *out, uint64_t cap, uint64_t *out_bytes);
+/* Tier count, bounds and total size of a container. */
+int orc_tiers_info(const uint8_t *in, uint64_t n, int *T, double *bounds, uint64_t *total);
+/* Reconstruction at accuracy eb from the fewest tiers that meet it
+ * (ORC_E_ACCURACY when no tier does); *tier_used receives the last tier. */
+int orc_tiers_decompress(const uint8_t *in, uint64_t n, double eb, float *out, int *tier_used);
+
 #ifdef __cplusplus
 }
 #endif
