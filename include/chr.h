@@ -472,6 +472,65 @@ int chr_entropy_info(const void *h_head, size_t head_bytes, uint64_t *n, uint64_
 int chr_entropy_decode(const void *h_head, const void *d_in, uint64_t nbytes, void *d_out, uint64_t out_capacity,
                        int32_t *d_status, void *stream);
 
+/* ---- Multi-tier progressive accuracy (Sec. II: data at the accuracy the
+ * viewer requests) ----------------------------------------------------------
+ * Tier 0 is the topology-preserving stream of the field at bound[0]; tier t
+ * >= 1 is the stream, without isovalues, of the binary32 residual
+ * x - y_{t-1} at bound[t] (y_{t-1}: the reconstruction from tiers 0..t-1),
+ * plus, in index order, the index and value of every point where
+ * y_{t-1} + r'_t (binary32) misses bound[t] (checked in double) or lies on
+ * another side of a candidate isovalue than x; those points take x.  A
+ * reconstruction at an accuracy eb decodes tiers 0..t for the first t with
+ * bound[t] <= eb.
+ * Container (little-endian): 0 u32 "CHRT", 4 u32 version 1, 8 u32 tiers,
+ * 12 u32 candidate count, 16 i64 dims[3], 40 u32 levels, 44 u32 block,
+ * 48 u32 qmax, 56 f32 isovalues[16], 120 u64 total bytes; at 128, 8 records
+ * of 64 bytes (f64 bound, u64 stream offset, stream bytes, corrections,
+ * index offset, value offset, 16 zero); from 640 each tier's stream, u64
+ * indices and f32 values, every part 8-aligned and zero-padded. */
+#define CHR_MAX_TIERS 8
+
+typedef struct chr_tier_header {
+  int n_tiers, n_iso;
+  int64_t dims[3];
+  int levels, block, qmax, reserved;
+  float isovalues[16];
+  uint64_t total_bytes;
+  double bound[CHR_MAX_TIERS];
+  uint64_t stream_offset[CHR_MAX_TIERS], stream_bytes[CHR_MAX_TIERS], n_corrections[CHR_MAX_TIERS];
+  uint64_t index_offset[CHR_MAX_TIERS], value_offset[CHR_MAX_TIERS];
+} chr_tier_header;
+
+/* Largest container of n_tiers tiers (0 and chr_last_error on bad parameters). */
+size_t chr_tiers_bound(const int64_t dims[3], int n_tiers, const chr_params *params);
+/* Device scratch bytes of chr_tiers_compress: two fields, one tier stream and
+ * the single-field compression and reconstruction workspaces. */
+size_t chr_tiers_workspace(const int64_t dims[3], const chr_params *params);
+/* Builds the container of `d_field` (float32, dims as chr_compress) on
+ * `stream`.  bounds: 1..CHR_MAX_TIERS host values, finite, >= 0, strictly
+ * decreasing; params.error_bound_far must be 0.  d_out (8-byte aligned,
+ * `capacity` bytes) receives the container; d_result (2 x uint64, device,
+ * 8-byte aligned) the container size (the required size when it does not
+ * fit) and the status (0, CHR_E_INVAL for non-finite input, CHR_E_CAPACITY).
+ * Host errors: CHR_E_INVAL, CHR_E_NOMEM (workspace), CHR_E_CAPACITY (below
+ * the 640-byte header). */
+int chr_tiers_compress(const float *d_field, const int64_t dims[3], const double *h_bounds, int n_tiers,
+                       const float *h_isovalues, int n_iso, const chr_params *params, void *d_out, size_t capacity,
+                       uint64_t *d_result, void *d_ws, size_t ws_bytes, void *stream);
+/* Parses the first 640 bytes of a container (host copy); CHR_E_CORRUPT when
+ * they are not a consistent tier header. */
+int chr_tiers_header(const void *h_head, size_t head_bytes, chr_tier_header *out);
+/* Device scratch bytes of chr_tiers_reconstruct. */
+size_t chr_tiers_reconstruct_workspace(const chr_tier_header *header);
+/* Reconstructs the full-resolution field at accuracy error_bound from the
+ * fewest tiers that meet it (CHR_E_ACCURACY when none does); *tier_used
+ * (host, may be NULL) receives the last tier decoded.  d_container is the
+ * whole container on the device (8-byte aligned, `bytes` long); d_status (one
+ * int32 on the device) is set to 0, or CHR_E_CORRUPT when a stream or a
+ * correction index is inconsistent. */
+int chr_tiers_reconstruct(const chr_tier_header *header, const void *d_container, size_t bytes, double error_bound,
+                          float *d_out, int32_t *d_status, void *d_ws, size_t ws_bytes, int *tier_used, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

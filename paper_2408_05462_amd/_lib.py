@@ -29,7 +29,8 @@ EXPORTS = ["chr_last_error", "chr_version", "chr_compress_bound", "chr_compress_
            "chr_server_step", "chr_server_poll", "chr_server_release", "chr_server_cancel", "chr_server_stats_get",
            "chr_server_now_ms", "chr_server_destroy", "chr_topology_workspace", "chr_topology_error_bound",
            "chr_reconstruct_range", "chr_entropy_bound", "chr_entropy_workspace", "chr_entropy_encode",
-           "chr_entropy_info", "chr_entropy_decode"]
+           "chr_entropy_info", "chr_entropy_decode", "chr_tiers_bound", "chr_tiers_workspace", "chr_tiers_compress",
+           "chr_tiers_header", "chr_tiers_reconstruct_workspace", "chr_tiers_reconstruct"]
 
 
 class ChrError(RuntimeError):
@@ -82,6 +83,18 @@ class chr_server_stats(C.Structure):
     _fields_ = [("queued", C.c_int64), ("in_flight", C.c_int64), ("done", C.c_int64), ("failed", C.c_int64),
                 ("pool_used", C.c_size_t), ("pool_peak", C.c_size_t), ("groups", C.c_int64),
                 ("grouped_requests", C.c_int64)]
+
+
+MAX_TIERS = 8
+
+
+class chr_tier_header(C.Structure):
+    _fields_ = [("n_tiers", C.c_int), ("n_iso", C.c_int), ("dims", C.c_int64 * 3), ("levels", C.c_int),
+                ("block", C.c_int), ("qmax", C.c_int), ("reserved", C.c_int), ("isovalues", C.c_float * 16),
+                ("total_bytes", C.c_uint64), ("bound", C.c_double * MAX_TIERS),
+                ("stream_offset", C.c_uint64 * MAX_TIERS), ("stream_bytes", C.c_uint64 * MAX_TIERS),
+                ("n_corrections", C.c_uint64 * MAX_TIERS), ("index_offset", C.c_uint64 * MAX_TIERS),
+                ("value_offset", C.c_uint64 * MAX_TIERS)]
 
 
 RESULT_BYTES = C.sizeof(chr_result)
@@ -192,6 +205,20 @@ def load():
     L.chr_entropy_info.restype = C.c_int
     L.chr_entropy_decode.argtypes = [vp, vp, C.c_uint64, vp, C.c_uint64, vp, vp]
     L.chr_entropy_decode.restype = C.c_int
+    L.chr_tiers_bound.argtypes = [i64p, C.c_int, C.POINTER(chr_params)]
+    L.chr_tiers_bound.restype = C.c_size_t
+    L.chr_tiers_workspace.argtypes = [i64p, C.POINTER(chr_params)]
+    L.chr_tiers_workspace.restype = C.c_size_t
+    L.chr_tiers_compress.argtypes = [vp, i64p, vp, C.c_int, vp, C.c_int, C.POINTER(chr_params), vp, C.c_size_t, vp,
+                                     vp, C.c_size_t, vp]
+    L.chr_tiers_compress.restype = C.c_int
+    L.chr_tiers_header.argtypes = [vp, C.c_size_t, C.POINTER(chr_tier_header)]
+    L.chr_tiers_header.restype = C.c_int
+    L.chr_tiers_reconstruct_workspace.argtypes = [C.POINTER(chr_tier_header)]
+    L.chr_tiers_reconstruct_workspace.restype = C.c_size_t
+    L.chr_tiers_reconstruct.argtypes = [C.POINTER(chr_tier_header), vp, C.c_size_t, C.c_double, vp, vp, vp,
+                                        C.c_size_t, C.POINTER(C.c_int), vp]
+    L.chr_tiers_reconstruct.restype = C.c_int
     _lib = L
     return L
 

@@ -554,3 +554,78 @@ def entropy_decode(enc):
     if st:
         raise L.ChrError(st, "chr_entropy_decode: corrupt stream")
     return out[:n]
+
+
+# ------------------------------------------------------------------ multi-tier progressive accuracy
+
+def chr_tiers_bound(shape, n_tiers, p):
+    n = L.load().chr_tiers_bound(L.dims3(shape), int(n_tiers), C.byref(p))
+    if n == 0:
+        L.check(L.CHR_E_INVAL, "chr_tiers_bound")
+    return n
+
+
+def chr_tiers_workspace(shape, p):
+    n = L.load().chr_tiers_workspace(L.dims3(shape), C.byref(p))
+    if n == 0:
+        L.check(L.CHR_E_INVAL, "chr_tiers_workspace")
+    return n
+
+
+def chr_tiers_compress(field, bounds, isovalues, p, out, result, ws, stream=None):
+    """Asynchronous; ``result`` (2 x uint64 on the device) receives the size and the status."""
+    _need_cuda_f32(field, "field")
+    b = np.ascontiguousarray(np.asarray(bounds, np.float64).reshape(-1))
+    iso = np.ascontiguousarray(np.asarray(isovalues, np.float32).reshape(-1))
+    rc = L.load().chr_tiers_compress(_p(field), L.dims3(field.shape), b.ctypes.data_as(C.c_void_p), len(b),
+                                     iso.ctypes.data_as(C.c_void_p), len(iso), C.byref(p), _p(out), out.numel(),
+                                     _p(result), _p(ws), ws.numel(), _s(stream))
+    L.check(rc, "chr_tiers_compress")
+
+
+def chr_tiers_header(head):
+    h = np.ascontiguousarray(np.frombuffer(bytes(head[:640]), np.uint8))
+    out = L.chr_tier_header()
+    rc = L.load().chr_tiers_header(h.ctypes.data_as(C.c_void_p), h.size, C.byref(out))
+    L.check(rc, "chr_tiers_header")
+    return out
+
+
+def chr_tiers_reconstruct(header, container, error_bound, out, status, ws, stream=None):
+    """Asynchronous; returns the last tier decoded."""
+    used = C.c_int(-1)
+    rc = L.load().chr_tiers_reconstruct(C.byref(header), _p(container), container.numel(), float(error_bound),
+                                        _p(out), _p(status), _p(ws), ws.numel(), C.byref(used), _s(stream))
+    L.check(rc, "chr_tiers_reconstruct")
+    return used.value
+
+
+def tiers_compress(field, bounds, isovalues=(), levels=3, block=64, qmax=32767):
+    """Synchronous: (container as a uint8 CUDA tensor, parsed header)."""
+    p = params(levels, block, qmax)
+    dev = field.device
+    out = torch.empty(chr_tiers_bound(field.shape, len(bounds), p), dtype=torch.uint8, device=dev)
+    ws = torch.empty(chr_tiers_workspace(field.shape, p), dtype=torch.uint8, device=dev)
+    res = torch.zeros(2, dtype=torch.int64, device=dev)
+    chr_tiers_compress(field, bounds, isovalues, p, out, res, ws)
+    torch.cuda.synchronize(dev)
+    size, st = (int(v) for v in res.cpu())
+    if st:
+        raise L.ChrError(st, "chr_tiers_compress (device status)")
+    c = out[:size]
+    return c, chr_tiers_header(c[:640].cpu().numpy())
+
+
+def tiers_reconstruct(container, header, error_bound):
+    """Synchronous: (field, last tier decoded)."""
+    dev = container.device
+    shape = tuple(int(v) for v in header.dims)
+    out = torch.empty(shape, dtype=torch.float32, device=dev)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    ws = torch.empty(L.load().chr_tiers_reconstruct_workspace(C.byref(header)), dtype=torch.uint8, device=dev)
+    used = chr_tiers_reconstruct(header, container, error_bound, out, status, ws)
+    torch.cuda.synchronize(dev)
+    st = int(status.item())
+    if st:
+        raise L.ChrError(st, "chr_tiers_reconstruct (device status)")
+    return out, used

@@ -85,7 +85,7 @@ def test_workspace_queries():
 
 
 @pytest.mark.parametrize("name", ["chr_batch_item", "chr_server_config", "chr_request_result",
-                                  "chr_server_stats", "chr_info", "chr_result", "chr_params"])
+                                  "chr_server_stats", "chr_info", "chr_result", "chr_params", "chr_tier_header"])
 def test_struct_layout_matches_c(tmp_path, name):
     """Each ctypes mirror of a chr.h struct has the C compiler's layout."""
     import shutil
@@ -369,3 +369,36 @@ def test_far_bound_rejected_on_the_host():
         items[0].params = p
         h = C.c_void_p()
         assert lib.chr_batch_create(items, 1, C.byref(h)) == L.CHR_E_INVAL
+
+
+def test_tier_header_parsed_from_oracle_container():
+    f = np.random.default_rng(12).standard_normal((12, 13, 14)).astype(np.float32)
+    c = oracle.tiers_compress(f, [0.1, 0.01, 0.0], [0.3], levels=3, block=8)
+    h = api.chr_tiers_header(c[:640])
+    assert h.n_tiers == 3 and h.n_iso == 1 and list(h.dims) == [12, 13, 14] and h.total_bytes == c.size
+    assert list(h.bound)[:3] == [0.1, 0.01, 0.0]
+    assert h.stream_offset[0] == 640 and h.n_corrections[0] == 0
+    bad = c[:640].copy()
+    bad[8] = 9                                           # 9 tiers
+    with pytest.raises(L.ChrError):
+        api.chr_tiers_header(bad)
+    bad = c[:640].copy()
+    bad[128:136] = np.frombuffer(np.float64(0.001).tobytes(), np.uint8)   # bounds no longer decreasing
+    with pytest.raises(L.ChrError):
+        api.chr_tiers_header(bad)
+    assert api.chr_tiers_bound((12, 13, 14), 3, api.params(3, 8)) == oracle.tiers_bound((12, 13, 14), 3, 3, 8)
+
+
+def test_tier_bounds_rejected_on_the_host():
+    lib = L.load()
+    fake = C.c_void_p(0x100000)
+    p = api.params(3, 8)
+    for bounds in ([0.01, 0.01], [0.01, 0.02], [-1.0], [float("nan")], [0.1 / 2 ** i for i in range(9)]):
+        b = np.asarray(bounds, np.float64)
+        rc = lib.chr_tiers_compress(fake, L.dims3((20, 20, 20)), b.ctypes.data_as(C.c_void_p), len(b), None, 0,
+                                    C.byref(p), fake, 1 << 30, fake, fake, 1 << 40, None)
+        assert rc == L.CHR_E_INVAL, bounds
+    pf = api.params(3, 8, error_bound_far=0.5)
+    b = np.asarray([0.1], np.float64)
+    assert lib.chr_tiers_compress(fake, L.dims3((20, 20, 20)), b.ctypes.data_as(C.c_void_p), 1, None, 0, C.byref(pf),
+                                  fake, 1 << 30, fake, fake, 1 << 40, None) == L.CHR_E_INVAL
