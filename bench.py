@@ -55,6 +55,7 @@ def parse_args():
     ap.add_argument("--no-topology", action="store_true", help="skip the error-translation part of the default run")
     ap.add_argument("--no-entropy", action="store_true", help="skip the entropy stage of the default run")
     ap.add_argument("--no-diff", action="store_true", help="skip differentiated error control in the default run")
+    ap.add_argument("--no-tiers", action="store_true", help="skip the multi-tier container in the default run")
     ap.add_argument("--serve-requests", type=int, default=200, help="requests of the default run's served part")
     ap.add_argument("--batch-items", type=int, default=64, help="batch64: number of timesteps")
     ap.add_argument("--branches", type=int, default=0, help="batch64: parallel branches of the graph (default: 4)")
@@ -691,6 +692,50 @@ def main():
                "candidate_meshes_equal_single_bound": same}
         del dbuf, drec
 
+    # multi-tier progressive accuracy on the same field: tiers at 10 e, e and
+    # e / 10; bytes per tier, and the reconstruction time at each tier's bound
+    tiers = None
+    if not args.no_tiers:
+        tb = [10.0 * e, e, 0.1 * e]
+        pt = api.params(w["levels"], w["block"])
+        tout = torch.empty(api.chr_tiers_bound(shape, len(tb), pt), dtype=torch.uint8, device=dev)
+        tws = torch.empty(api.chr_tiers_workspace(shape, pt), dtype=torch.uint8, device=dev)
+        tres = torch.zeros(2, dtype=torch.int64, device=dev)
+        api.chr_tiers_compress(x, tb, isos, pt, tout, tres, tws)
+        torch.cuda.synchronize()
+        tsize, tst = (int(v) for v in tres.cpu())
+        assert tst == 0, "tier container status"
+        th = api.chr_tiers_header(tout[:640].cpu().numpy())
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        rep = 3
+        e0.record(stream)
+        for _ in range(rep):
+            api.chr_tiers_compress(x, tb, isos, pt, tout, tres, tws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        comp_ms = e0.elapsed_time(e1) / rep
+        trec = torch.empty(shape, dtype=torch.float32, device=dev)
+        tst_ = torch.zeros(1, dtype=torch.int32, device=dev)
+        rws2 = torch.empty(api.L.load().chr_tiers_reconstruct_workspace(C.byref(th)), dtype=torch.uint8, device=dev)
+        per = []
+        for t, eb in enumerate(tb):
+            api.chr_tiers_reconstruct(th, tout[:tsize], eb, trec, tst_, rws2)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for _ in range(rep):
+                used = api.chr_tiers_reconstruct(th, tout[:tsize], eb, trec, tst_, rws2)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            err = (trec.double() - x.double()).abs().max().item()
+            assert used == t and int(tst_.item()) == 0 and err <= eb, "tier reconstruction"
+            for k in isos:
+                assert torch.equal(api.cases(trec, k), api.cases(x, k)), "tier changed a case"
+            per.append({"bound": eb, "stream_bytes": int(th.stream_bytes[t]), "corrections": int(th.n_corrections[t]),
+                        "cumulative_bytes": int(th.stream_offset[t] + th.stream_bytes[t]),
+                        "reconstruct_ms": round(e0.elapsed_time(e1) / rep, 4)})
+        tiers = {"container_bytes": tsize, "compress_ms": round(comp_ms, 4), "tiers": per}
+        del tout, tws, trec, rws2
+
     # served latency on the same field (the metric's second half): requests
     # at random isovalues and accuracy tiers, continuous-batching server vs
     # plain per-request launches at 0.8 x the plain path's saturation rate
@@ -742,7 +787,7 @@ def main():
         "wall_s_timed": round(wall, 3), "served": served, "topology_error_bound": topo or None, "roofline": roofline,
         "cpu_baseline": cpu,
         "workflow_model": workflow_model(4.0 * N, cr, stage_ms), "entropy_stage": ent,
-        "differentiated_error_control": dif,
+        "differentiated_error_control": dif, "tiers": tiers,
     }
     print(json.dumps(out), flush=True)
 
