@@ -72,36 +72,17 @@ __global__ __launch_bounds__(kBS) void k_ent_hist(EntPlan E) {
     if (h[i]) atomicAdd(&E.tab->hist[i], h[i]);
 }
 
-// 256 values held four per lane of one wave: value i in register i >> 6 of
-// lane i & 63; reads and writes at a wave-uniform index i.
-struct Lanes4 {
-  uint32_t r[4];
-};
-
-__device__ inline uint32_t l4_get(const Lanes4 &a, uint32_t i) {
-  const int l = (int)(i & 63u);
-  const uint32_t v0 = (uint32_t)__builtin_amdgcn_readlane((int)a.r[0], l);
-  const uint32_t v1 = (uint32_t)__builtin_amdgcn_readlane((int)a.r[1], l);
-  const uint32_t v2 = (uint32_t)__builtin_amdgcn_readlane((int)a.r[2], l);
-  const uint32_t v3 = (uint32_t)__builtin_amdgcn_readlane((int)a.r[3], l);
-  const uint32_t k = i >> 6;
-  return k == 0 ? v0 : k == 1 ? v1 : k == 2 ? v2 : v3;
-}
-
-__device__ inline void l4_set(Lanes4 &a, uint32_t i, uint32_t v) {
-  const bool mine = (uint32_t)lane_id() == (i & 63u);
-  const uint32_t k = i >> 6;
-  for (int r = 0; r < 4; r++) a.r[r] = (mine && k == (uint32_t)r) ? v : a.r[r];
-}
-
 // The code table (one workgroup of 256 threads, thread s for byte value s).
-// The Huffman merge runs on wave 0 with the queues in registers; the leaf
-// depths follow by pointer jumping over the parent links.
+// The Huffman merge runs on wave 0 in uniform control flow: the fronts of
+// the two queues stay in scalar registers, so a pick costs one LDS read
+// (the consumed queue's next entry); the leaf depths follow by pointer
+// jumping over the parent links.
 __global__ __launch_bounds__(256) void k_ent_table(EntPlan E) {
   __shared__ uint32_t hs[256];
   __shared__ int order[256];      // present values by (count, value) increasing
   __shared__ int bits[512];       // codes per length
   __shared__ int par[512], anc[512], dep[512];
+  __shared__ uint32_t lw[256], nw[256];   // leaf weights in queue order, node weights in creation order
   __shared__ int blc[kMaxLen + 1];
   __shared__ uint32_t nextc[kMaxLen + 1];
   __shared__ int maxd_s;
@@ -115,6 +96,7 @@ __global__ __launch_bounds__(256) void k_ent_table(EntPlan E) {
   __syncthreads();
   // rank among the present values by (count, value)
   int rk = 0, m = 0;
+#pragma unroll 16
   for (int t = 0; t < 256; t++) {
     const uint32_t ct = hs[t];
     m += ct != 0u;
@@ -123,40 +105,37 @@ __global__ __launch_bounds__(256) void k_ent_table(EntPlan E) {
   if (c) order[rk] = s;
   ln[s] = 0;
   __syncthreads();
+  if (s < m) lw[s] = hs[order[s]];
+  __syncthreads();
   // two-queue Huffman on wave 0: leaves 0..m-1 in order, internal node j
   // (tree node m + j) made at step j; the lighter front is taken, a leaf
   // first on a tie (weights fit 32 bits: they sum to at most n < 2^32)
   const int nn = 2 * m - 1;   // tree nodes when m >= 2
   if (m >= 2 && s < kWave) {
-    Lanes4 lw, nw, pl, pn;    // leaf weights, node weights, leaf parents, node parents
-    for (int k = 0; k < 4; k++) {
-      const int idx = s + kWave * k;
-      lw.r[k] = idx < m ? hs[order[idx]] : 0u;
-      nw.r[k] = pl.r[k] = pn.r[k] = 0u;
-    }
+    // wave-uniform: every lane reads the same LDS word, readfirstlane makes it scalar
+    auto rd = [](const uint32_t *a, uint32_t i) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)a[i]); };
+    const uint32_t mu = (uint32_t)__builtin_amdgcn_readfirstlane(m);
     uint32_t qi = 0, qj = 0, made = 0;
-    for (int step = 0; step < m - 1; step++) {
+    uint32_t a = rd(lw, 0), b = 0;   // fronts: leaf qi (qi < m), node qj (qj < made)
+    for (uint32_t step = 0; step + 1 < mu; step++) {
+      const int node = (int)(mu + made);
       uint32_t wsum = 0;
       for (int t = 0; t < 2; t++) {
-        const bool lok = qi < (uint32_t)m, nok = qj < made;
-        const uint32_t a = lok ? l4_get(lw, qi) : 0u, bw = nok ? l4_get(nw, qj) : 0u;
-        if (lok && (!nok || a <= bw)) {
+        if (qi < mu && (qj >= made || a <= b)) {
           wsum += a;
-          l4_set(pl, qi, made);
+          if (s == 0) par[qi] = node;
           qi++;
+          a = qi < mu ? rd(lw, qi) : 0u;
         } else {
-          wsum += bw;
-          l4_set(pn, qj, made);
+          wsum += b;
+          if (s == 0) par[mu + qj] = node;
           qj++;
+          b = qj < made ? rd(nw, qj) : 0u;
         }
       }
-      l4_set(nw, made, wsum);
+      if (s == 0) nw[made] = wsum;
       made++;
-    }
-    for (int k = 0; k < 4; k++) {
-      const int idx = s + kWave * k;
-      if (idx < m) par[idx] = m + (int)pl.r[k];
-      if (idx < m - 1) par[m + idx] = m + (int)pn.r[k];
+      if (qj + 1 == made) b = wsum;   // the node queue was empty: the new node is its front
     }
   }
   __syncthreads();
@@ -216,6 +195,7 @@ __global__ __launch_bounds__(256) void k_ent_table(EntPlan E) {
   // lengths to the values from the most frequent: rank by (count desc, value)
   if (c) {
     int r2 = 0;
+#pragma unroll 16
     for (int t = 0; t < 256; t++) {
       const uint32_t ct = hs[t];
       r2 += ct != 0u && (ct > c || (ct == c && t < s));
