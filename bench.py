@@ -756,7 +756,7 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
 
-        planes = args.cpu_planes or min(shape[0], max(2, (64 << 20) // (shape[1] * shape[2])))
+        planes = args.cpu_planes or min(shape[0], max(2, (128 << 20) // (shape[1] * shape[2])))
         sub = np.ascontiguousarray(f_np[:planes])
         tc = time.perf_counter()
         ref = oracle.compress(sub, e, isos, levels=w["levels"], block=w["block"])

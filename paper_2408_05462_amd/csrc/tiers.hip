@@ -126,22 +126,23 @@ __global__ __launch_bounds__(kBS) void k_tier_copy(const TierState *S, const uin
     for (uint64_t b = 8 * n8 + threadIdx.x; b < sb; b += kBS) out[so + b] = B[b];
 }
 
-// The tier's corrections in index order (one wave per 64-point word).
+// The tier's corrections in index order (one thread per 64-point word; the
+// words without a correction, nearly all of them, cost one load).
 __global__ __launch_bounds__(kBS) void k_tier_corr(const TierState *S, const unsigned long long *__restrict__ mask,
                                                     const uint64_t *__restrict__ pre, const float *__restrict__ x,
                                                     uint64_t nw, uint8_t *__restrict__ out) {
   if (S->status != 0) return;
-  const int lane = lane_id();
   uint64_t *idx = reinterpret_cast<uint64_t *>(out + S->io);
   float *val = reinterpret_cast<float *>(out + S->vo);
-  for (uint64_t t = (uint64_t)blockIdx.x * kBS + threadIdx.x; t < 64 * nw; t += (uint64_t)gridDim.x * kBS) {
-    const uint64_t w = t / 64;
-    const unsigned long long m = mask[w];
-    if ((m >> lane) & 1ull) {
-      const uint64_t pos = pre[w] + (uint64_t)__popcll(m & ((1ull << lane) - 1ull));
-      const uint64_t i = 64 * w + (uint64_t)lane;
+  for (uint64_t w = (uint64_t)blockIdx.x * kBS + threadIdx.x; w < nw; w += (uint64_t)gridDim.x * kBS) {
+    unsigned long long m = mask[w];
+    uint64_t pos = m ? pre[w] : 0;
+    while (m) {
+      const uint64_t i = 64 * w + (uint64_t)(__ffsll((long long)m) - 1);
       idx[pos] = i;
       val[pos] = x[i];
+      pos++;
+      m &= m - 1;
     }
   }
 }
@@ -329,8 +330,9 @@ int chr_tiers_compress(const float *d_field, const int64_t dims[3], const double
       scan_u64(cnt, pre, (int64_t)nw, tmp, s);
     }
     k_tier_place<<<1, 64, 0, s>>>(S, t, h_bounds[t], res, dst, pre, nw, out, capacity);
-    k_tier_copy<<<grid_for(Lo.Bbytes / 8, kBS), kBS, 0, s>>>(S, B, out);
-    if (t > 0) k_tier_corr<<<grid_for(nw * 64, kBS), kBS, 0, s>>>(S, mask, pre, d_field, nw, out);
+    // grid-stride copy over the stream's actual size (read on the device)
+    k_tier_copy<<<std::min<unsigned>(grid_for(Lo.Bbytes / 8, kBS), 4096u), kBS, 0, s>>>(S, B, out);
+    if (t > 0) k_tier_corr<<<grid_for(nw, kBS), kBS, 0, s>>>(S, mask, pre, d_field, nw, out);
   }
   k_tier_finish<<<1, kBS, 0, s>>>(S, h, out, d_result);
   return api_check_launch("chr_tiers_compress");
