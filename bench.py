@@ -7,7 +7,9 @@ checks for every candidate isovalue) -> reconstruct level 0 from the stream
 input is resident in HBM before the timed region; each step re-runs the whole
 path on the same buffers.
 
-Prints ONE JSON line (see the design doc for the fields).  --gpus must be 1.
+Prints ONE JSON line: the metric, its value, the step time, the roofline of
+the level-0 compression kernel, the CPU oracle baseline and the per-part
+measurements.  --gpus must be 1.
 """
 from __future__ import annotations
 
@@ -28,7 +30,7 @@ sys.path.insert(0, ROOT)
 METRIC = "CHR compress+reconstruct+MC input GB/s (% HBM peak); served p99 latency"
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic bytes per unit, by kernel ("Measurement"):
+# Algorithmic bytes per unit, by kernel:
 #   k_encode_fine : 4 B per level-0 point read + its share of the stream written
 #   k_decode_fine : its share of the stream read + 4 B per output point written
 #   k_mc_bits     : 4 B per point read + 1 bit per point written
@@ -437,8 +439,8 @@ def run_serve(args):
 def main():
     args = parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "bench.py measures one GPU only: every GPU box here has one GPU; "
-                                   "run with --gpus 1"}))
+        print(json.dumps({"error": "bench.py measures the one-GPU path only (the multi-GPU split is a design, "
+                                   "not built): run with --gpus 1"}))
         sys.exit(2)
     if args.tiles:
         from paper_2408_05462_amd import api as _api
