@@ -505,19 +505,19 @@ __device__ __forceinline__ void encode_fast(const EncPlan &P, uint32_t (*pack)[3
 }
 
 template <bool AUX, int KB, int G, bool DIFF>
-__global__ __launch_bounds__(kBS) void k_encode_l0(EncPlan P) {
+__global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(DIFF ? 6 : 1))) void k_encode_l0(EncPlan P) {
   __shared__ uint32_t pack[kWaves][32];
   encode_fast<0, AUX, KB, G, DIFF>(P, pack);
 }
 
 template <bool AUX, int KB, int G, bool DIFF>
-__global__ __launch_bounds__(kBS) void k_encode_l1s(EncPlan P) {
+__global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(DIFF ? 6 : 1))) void k_encode_l1s(EncPlan P) {
   __shared__ uint32_t pack[kWaves][32];
   encode_fast<1, AUX, KB, G, DIFF>(P, pack);
 }
 
 template <bool AUX, int KB, int G, bool DIFF>
-__global__ __launch_bounds__(kBS) void k_encode_l2s(EncPlan P) {
+__global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(DIFF ? 6 : 1))) void k_encode_l2s(EncPlan P) {
   __shared__ uint32_t pack[kWaves][32];
   encode_fast<2, AUX, KB, G, DIFF>(P, pack);
 }

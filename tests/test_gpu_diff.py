@@ -116,3 +116,19 @@ def test_diff_batch_matches_single_calls():
         assert stream == s_ref, i
         assert np.array_equal(y.view(np.uint32), y_ref.view(np.uint32)), i
     b.close()
+
+
+def test_diff_restricted_reconstruction_off_the_candidates():
+    # a range holding no candidate decodes near and far blocks side by side:
+    # their shared points carry one value, so the cases and mesh at any
+    # isovalue of the range equal the full reconstruction's
+    f, e, ef, isos, nL, B = _setup(CASES[0])
+    x = torch.from_numpy(f).to(DEV)
+    cd = api.compress(x, e, isos, levels=nL, block=B, error_bound_far=ef)
+    y = api.reconstruct(cd, 0)
+    for k in (0.5, 1.2):
+        yr = api.reconstruct_range(cd, k, k)
+        assert torch.equal(api.cases(yr, k), api.cases(y, k))
+        v, t = api.extract(y, k)
+        vr, tr = api.extract(yr, k)
+        assert torch.equal(tr, t) and torch.equal(vr.view(torch.int32), v.view(torch.int32))

@@ -22,6 +22,8 @@ CASES = [
     ((17, 30, 9), 2, 4, [1e-2, 2e-3, 4e-4], [0.0, 0.7, 1.4]),
     ((65, 66, 67), 4, 16, [1e-2, 1e-3, 1e-4], [0.2]),
     ((40, 37, 70), 5, 16, [3e-2, 3e-3, 3e-4, 3e-5], [-1.0, 0.0, 1.0, 1.5]),
+    ((1, 30, 31), 2, 2, [1e-2, 1e-3], []),                   # a one-point axis, no candidates
+    ((9, 1, 5), 1, 1, [1e-1, 0.0], [0.2]),                    # one level, lossless last tier
 ]
 IDS = [f"{'x'.join(map(str, c[0]))}-L{c[1]}-T{len(c[3])}" for c in CASES]
 
