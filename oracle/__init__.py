@@ -385,3 +385,44 @@ def tiers_decompress(container, eb):
     if rc:
         raise OracleError(rc, "tiers_decompress")
     return out, used
+
+
+# ---- block merging for extraction ----------------------------------------------
+
+def block_box(stream, kmin, kmax):
+    """(lo, hi) points (z, y, x; inclusive) of the merged box of the blocks
+    that can hold a crossing of an isovalue in [kmin, kmax], or None."""
+    L = lib()
+    s = np.ascontiguousarray(stream, np.uint8)
+    lo = (C.c_int64 * 3)()
+    hi = (C.c_int64 * 3)()
+    found = C.c_int()
+    L.orc_block_box.argtypes = [C.c_void_p, C.c_size_t, C.c_float, C.c_float, C.c_void_p, C.c_void_p,
+                                C.POINTER(C.c_int)]
+    L.orc_block_box.restype = C.c_int
+    rc = L.orc_block_box(s.ctypes.data, s.size, float(np.float32(kmin)), float(np.float32(kmax)), lo, hi,
+                         C.byref(found))
+    if rc:
+        raise OracleError(rc, "block_box")
+    return (tuple(lo), tuple(hi)) if found.value else None
+
+
+def mc_box(f, lo, hi, k, spacing=1.0):
+    """Marching cubes over the box lo..hi of f, with f's coordinates: (verts, tris)."""
+    L = lib()
+    f, pf = _f32(f)
+    lo3 = (C.c_int64 * 3)(*lo)
+    hi3 = (C.c_int64 * 3)(*hi)
+    L.orc_mc_box.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.c_void_p, C.c_void_p, C.c_float, C.c_float,
+                             C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]
+    L.orc_mc_box.restype = C.c_int
+    counts = (C.c_int64 * 2)()
+    rc = L.orc_mc_box(pf, _dims(f.shape), lo3, hi3, float(np.float32(k)), float(spacing), None, 0, None, 0, counts)
+    cap_v, cap_t = counts[0], counts[1]
+    verts = np.zeros((max(cap_v, 1), 3), np.float32)
+    tris = np.zeros((max(cap_t, 1), 3), np.int32)
+    rc = L.orc_mc_box(pf, _dims(f.shape), lo3, hi3, float(np.float32(k)), float(spacing), verts.ctypes.data, cap_v,
+                      tris.ctypes.data, cap_t, counts)
+    if rc not in (OK, E_CAPACITY):
+        raise OracleError(rc, "mc_box")
+    return verts[: counts[0]], tris[: counts[1]]

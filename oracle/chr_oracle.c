@@ -984,8 +984,11 @@ void orc_mc_cases(const float *f, const int64_t d[3], float k, uint8_t *cases) {
       }
 }
 
-int orc_mc(const float *f, const int64_t d[3], float k, float spacing, float *verts,
-           int64_t cap_v, int32_t *tris, int64_t cap_t, int64_t counts[2]) {
+/* Marching cubes over a field whose point (0,0,0) sits at grid coordinates
+ * org (x, y, z) of a larger field: positions use the larger field's
+ * coordinates. */
+static int mc_impl(const float *f, const int64_t d[3], const int64_t org[3], float k, float spacing, float *verts,
+                   int64_t cap_v, int32_t *tris, int64_t cap_t, int64_t counts[2]) {
   static uint8_t ntri[256];
   static int8_t tab[256][3 * ORC_MC_MAXTRI];
   static int have = 0;
@@ -1013,7 +1016,7 @@ int orc_mc(const float *f, const int64_t d[3], float k, float spacing, float *ve
             float num = k - fa, den = fb - fa;
             float t = num / den;
             for (int b = 0; b < 3; b++) {
-              float pc = (float)c[b];
+              float pc = (float)(c[b] + org[b]);
               if (b == a) pc = pc + t;
               verts[3 * nv + b] = pc * spacing;
             }
@@ -1049,6 +1052,57 @@ int orc_mc(const float *f, const int64_t d[3], float k, float spacing, float *ve
   counts[1] = nt;
   if (over || nt > cap_t) return ORC_E_CAPACITY;
   return ORC_OK;
+}
+
+int orc_mc(const float *f, const int64_t d[3], float k, float spacing, float *verts,
+           int64_t cap_v, int32_t *tris, int64_t cap_t, int64_t counts[2]) {
+  const int64_t org[3] = {0, 0, 0};
+  return mc_impl(f, d, org, k, spacing, verts, cap_v, tris, cap_t, counts);
+}
+
+/* Block merging for extraction (reading R21): the blocks whose stored range
+ * can hold a crossing of an isovalue in [kmin, kmax] (min < max, min < kmax,
+ * kmin <= max) merged into their bounding box of points, lo..hi per axis
+ * (z, y, x); *found = 0 when there is none. */
+int orc_block_box(const uint8_t *s, size_t n, float kmin, float kmax, int64_t lo[3], int64_t hi[3], int *found) {
+  orc_info I;
+  int rc = orc_stream_info(s, n, &I);
+  if (rc) return rc;
+  const size_t btab = HEADER_BYTES + 16 * (size_t)I.nblocks * (size_t)I.levels;
+  *found = 0;
+  for (int a = 0; a < 3; a++) { lo[a] = INT64_MAX; hi[a] = -1; }
+  for (int64_t b = 0; b < I.nblocks; b++) {
+    const float mn = getf(s + btab + 16 * (size_t)b), mx = getf(s + btab + 16 * (size_t)b + 4);
+    if (!(mn < mx && mn < kmax && kmin <= mx)) continue;
+    int64_t bi[3] = {b / ((int64_t)I.nb[1] * I.nb[2]), (b / I.nb[2]) % I.nb[1], b % I.nb[2]}, o[3], h[3];
+    block_extent(I.dims, I.block, bi, o, h);
+    for (int a = 0; a < 3; a++) {
+      if (o[a] < lo[a]) lo[a] = o[a];
+      if (h[a] > hi[a]) hi[a] = h[a];
+    }
+    *found = 1;
+  }
+  return ORC_OK;
+}
+
+/* Marching cubes over the box lo..hi (z, y, x; inclusive) of a field, with
+ * the field's coordinates. */
+int orc_mc_box(const float *f, const int64_t d[3], const int64_t lo[3], const int64_t hi[3], float k, float spacing,
+               float *verts, int64_t cap_v, int32_t *tris, int64_t cap_t, int64_t counts[2]) {
+  int64_t bd[3];
+  for (int a = 0; a < 3; a++) {
+    if (lo[a] < 0 || hi[a] >= d[a] || lo[a] > hi[a]) return ORC_E_INVAL;
+    bd[a] = hi[a] - lo[a] + 1;
+  }
+  float *sub = (float *)malloc(sizeof(float) * (size_t)(bd[0] * bd[1] * bd[2]));
+  if (!sub) return ORC_E_NOMEM;
+  for (int64_t z = 0; z < bd[0]; z++)
+    for (int64_t y = 0; y < bd[1]; y++)
+      for (int64_t x = 0; x < bd[2]; x++) sub[idx3(bd, z, y, x)] = f[idx3(d, lo[0] + z, lo[1] + y, lo[2] + x)];
+  const int64_t org[3] = {lo[2], lo[1], lo[0]};
+  int rc = mc_impl(sub, bd, org, k, spacing, verts, cap_v, tris, cap_t, counts);
+  free(sub);
+  return rc;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -138,6 +138,14 @@ double orc_topology_error_bound(const float *f, const int64_t dims[3],
                                 const float *iso, int n_iso, int64_t nth,
                                 int64_t *n_d);
 
+/* Block merging for extraction: bounding box (z, y, x; inclusive) of the
+ * blocks whose stored range can hold a crossing of an isovalue in
+ * [kmin, kmax]; *found = 0 when none can. */
+int orc_block_box(const uint8_t *stream, size_t n, float kmin, float kmax, int64_t lo[3], int64_t hi[3], int *found);
+/* Marching cubes over the box lo..hi of a field, positions in the field's coordinates. */
+int orc_mc_box(const float *f, const int64_t dims[3], const int64_t lo[3], const int64_t hi[3], float k,
+               float spacing, float *verts, int64_t cap_v, int32_t *tris, int64_t cap_t, int64_t counts[2]);
+
 /* ---- entropy stage (chr_entropy.c): order-0 Huffman over a byte stream ---- */
 
 /* Code lengths of the 256 byte values from their counts, at most maxlen
