@@ -738,6 +738,38 @@ def main():
         tiers = {"container_bytes": tsize, "compress_ms": round(comp_ms, 4), "tiers": per}
         del tout, tws, trec, rws2
 
+    # block merging for extraction: the blocks that can hold the isosurface
+    # merged into one box; marching cubes over the box vs over the field
+    boxm = None
+    if not args.no_tiers:
+        _, hd = api.chr_stream_info_dev(sdev)
+        per = []
+        for j, k in enumerate(isos):
+            box = api.chr_block_box(hd, k, k)
+            if box is None:
+                continue
+            lo, hi = box
+            bd = tuple(h - l + 1 for l, h in zip(lo, hi))
+            bws = torch.empty(api.iso_box_workspace(bd), dtype=torch.uint8, device=dev)
+            bcnt = torch.zeros(2, dtype=torch.int64, device=dev)
+            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            rep = 5
+            api.iso_extract_box(recon, lo, hi, k, 1.0, verts, tris, bcnt, bws)
+            e0.record(stream)
+            for _ in range(rep):
+                api.iso_extract(recon, k, 1.0, verts, tris, counts[j], mws)
+            e1.record(stream)
+            for _ in range(rep):
+                api.iso_extract_box(recon, lo, hi, k, 1.0, verts, tris, bcnt, bws)
+            e2.record(stream)
+            torch.cuda.synchronize()
+            assert torch.equal(bcnt, counts[j]), "box mesh size"
+            per.append({"isovalue": k, "box_lo": list(lo), "box_hi": list(hi),
+                        "box_fraction": round(float(np.prod(bd)) / N, 4),
+                        "mc_full_ms": round(e0.elapsed_time(e1) / rep, 4), "mc_box_ms": round(e1.elapsed_time(e2) / rep, 4)})
+            del bws
+        boxm = per
+
     # served latency on the same field (the metric's second half): requests
     # at random isovalues and accuracy tiers, continuous-batching server vs
     # plain per-request launches at 0.8 x the plain path's saturation rate
@@ -789,7 +821,7 @@ def main():
         "wall_s_timed": round(wall, 3), "served": served, "topology_error_bound": topo or None, "roofline": roofline,
         "cpu_baseline": cpu,
         "workflow_model": workflow_model(4.0 * N, cr, stage_ms), "entropy_stage": ent,
-        "differentiated_error_control": dif, "tiers": tiers,
+        "differentiated_error_control": dif, "tiers": tiers, "merged_box_extraction": boxm,
     }
     print(json.dumps(out), flush=True)
 

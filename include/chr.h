@@ -205,6 +205,31 @@ int iso_extract(const float *d_field, const int64_t dims[3], float isovalue, flo
 int iso_cases(const float *d_field, const int64_t dims[3], float isovalue,
               uint8_t *d_cases, void *d_ws, size_t ws_bytes, void *stream);
 
+/* Block merging for extraction (Sec. II.A: blocks merged into a larger
+ * rectangular grid to be visualized more efficiently): the bounding box
+ * lo..hi (z, y, x; inclusive level-0 points) of the blocks whose block-table
+ * range [min, max] admits a crossing of some k in [kmin, kmax] (min < max,
+ * min < kmax, kmin <= max).  h_head: host copy of the stream's header and
+ * tables (payload_offset bytes).  *found = 0 (box untouched) when no block
+ * qualifies.  Every cell with a crossing of such a k lies in the box, so
+ * iso_extract_box over it gives iso_extract's mesh of the full field.
+ * Errors: CHR_E_INVAL (NULL, empty or non-finite range), CHR_E_CORRUPT. */
+int chr_block_box(const void *h_head, size_t head_bytes, float kmin, float kmax, int64_t lo[3], int64_t hi[3],
+                  int *found);
+
+/* Workspace bytes of iso_extract_box for a box of these dims (iso_workspace
+ * of the box: the box is read in place). */
+size_t iso_box_workspace(const int64_t box_dims[3]);
+
+/* Marching cubes over the box lo..hi (z, y, x; inclusive, inside dims) of
+ * d_field, with the field's coordinates: vertices and triangles as
+ * iso_extract, ids in the box's point order (the field's order restricted to
+ * the box).  When every cell with a crossing of `isovalue` lies in the box
+ * (chr_block_box), the mesh equals iso_extract's on the whole field. */
+int iso_extract_box(const float *d_field, const int64_t dims[3], const int64_t lo[3], const int64_t hi[3],
+                    float isovalue, float spacing, float *d_vertices, int64_t cap_v, int32_t *d_tris, int64_t cap_t,
+                    int64_t *d_counts, void *d_ws, size_t ws_bytes, void *stream);
+
 /* Host copy of the library's generated triangle table:
  * ntri[256]; tri[256][15] cell-edge ids (unused entries -1). */
 int chr_mc_table(uint8_t *ntri, int8_t *tri);

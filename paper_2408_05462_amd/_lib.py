@@ -30,7 +30,8 @@ EXPORTS = ["chr_last_error", "chr_version", "chr_compress_bound", "chr_compress_
            "chr_server_now_ms", "chr_server_destroy", "chr_topology_workspace", "chr_topology_error_bound",
            "chr_reconstruct_range", "chr_entropy_bound", "chr_entropy_workspace", "chr_entropy_encode",
            "chr_entropy_info", "chr_entropy_decode", "chr_tiers_bound", "chr_tiers_workspace", "chr_tiers_compress",
-           "chr_tiers_header", "chr_tiers_reconstruct_workspace", "chr_tiers_reconstruct"]
+           "chr_tiers_header", "chr_tiers_reconstruct_workspace", "chr_tiers_reconstruct", "chr_block_box",
+           "iso_box_workspace", "iso_extract_box"]
 
 
 class ChrError(RuntimeError):
@@ -219,6 +220,13 @@ def load():
     L.chr_tiers_reconstruct.argtypes = [C.POINTER(chr_tier_header), vp, C.c_size_t, C.c_double, vp, vp, vp,
                                         C.c_size_t, C.POINTER(C.c_int), vp]
     L.chr_tiers_reconstruct.restype = C.c_int
+    L.chr_block_box.argtypes = [vp, C.c_size_t, C.c_float, C.c_float, i64p, i64p, C.POINTER(C.c_int)]
+    L.chr_block_box.restype = C.c_int
+    L.iso_box_workspace.argtypes = [i64p]
+    L.iso_box_workspace.restype = C.c_size_t
+    L.iso_extract_box.argtypes = [vp, i64p, i64p, i64p, C.c_float, C.c_float, vp, C.c_int64, vp, C.c_int64, vp, vp,
+                                  C.c_size_t, vp]
+    L.iso_extract_box.restype = C.c_int
     _lib = L
     return L
 

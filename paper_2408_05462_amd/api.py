@@ -629,3 +629,48 @@ def tiers_reconstruct(container, header, error_bound):
     if st:
         raise L.ChrError(st, "chr_tiers_reconstruct (device status)")
     return out, used
+
+
+# ------------------------------------------------------------------ block merging for extraction
+
+def chr_block_box(head, kmin, kmax):
+    """(lo, hi) of the merged box of the blocks that can hold an isosurface at
+    some k in [kmin, kmax] (head: header and tables on the host), or None."""
+    h = np.ascontiguousarray(np.frombuffer(bytes(head), np.uint8))
+    lo, hi, found = (C.c_int64 * 3)(), (C.c_int64 * 3)(), C.c_int()
+    rc = L.load().chr_block_box(h.ctypes.data_as(C.c_void_p), h.size, float(kmin), float(kmax), lo, hi,
+                                C.byref(found))
+    L.check(rc, "chr_block_box")
+    return (tuple(lo), tuple(hi)) if found.value else None
+
+
+def iso_box_workspace(box_shape):
+    n = L.load().iso_box_workspace(L.dims3(box_shape))
+    if n == 0:
+        L.check(L.CHR_E_INVAL, "iso_box_workspace")
+    return n
+
+
+def iso_extract_box(field, lo, hi, isovalue, spacing, verts, tris, counts, ws, stream=None):
+    _need_cuda_f32(field, "field")
+    lo3, hi3 = L.dims3(lo), L.dims3(hi)
+    rc = L.load().iso_extract_box(_p(field), L.dims3(field.shape), lo3, hi3, float(isovalue), float(spacing),
+                                  _p(verts), 0 if verts is None else verts.shape[0], _p(tris),
+                                  0 if tris is None else tris.shape[0], _p(counts), _p(ws), ws.numel(), _s(stream))
+    L.check(rc, "iso_extract_box")
+
+
+def extract_box(field, lo, hi, isovalue, spacing=1.0):
+    """Synchronous marching cubes over the box lo..hi: (verts [V,3], tris [T,3])."""
+    dev = field.device
+    bd = tuple(h - l + 1 for l, h in zip(lo, hi))
+    ws = torch.empty(iso_box_workspace(bd), dtype=torch.uint8, device=dev)
+    counts = torch.zeros(2, dtype=torch.int64, device=dev)
+    iso_extract_box(field, lo, hi, isovalue, spacing, None, None, counts, ws)
+    torch.cuda.synchronize(dev)
+    nv, nt = (int(v) for v in counts.cpu())
+    verts = torch.empty((max(nv, 1), 3), dtype=torch.float32, device=dev)
+    tris = torch.empty((max(nt, 1), 3), dtype=torch.int32, device=dev)
+    iso_extract_box(field, lo, hi, isovalue, spacing, verts, tris, counts, ws)
+    torch.cuda.synchronize(dev)
+    return verts[:nv], tris[:nt]

@@ -359,6 +359,8 @@ static int mc_plan(const float *d_field, const int64_t dims[3], McPlan &M, size_
   if ((double)M.nrows * (double)M.nw * 64.0 >= 4294967296.0)
     return fail(CHR_E_INVAL, "field too large for marching cubes (2^32 padded points)");
   M.f = d_field;
+  M.py = dims[2];
+  M.pz = dims[1] * dims[2];
   size_t o = 0;
   off[0] = o; o = align256(o + 8 * (size_t)(M.nrows * M.nw));
   const int64_t nwords = M.nrows * M.nw;
@@ -649,6 +651,66 @@ int iso_extract(const float *d_field, const int64_t dims[3], float isovalue, flo
   if (rc) return rc;
   launch_mc(J.M, J.scan, static_cast<hipStream_t>(stream));
   return check_hip("iso_extract launch");
+}
+
+int chr_block_box(const void *h_head, size_t head_bytes, float kmin, float kmax, int64_t lo[3], int64_t hi[3],
+                  int *found) {
+  if (!h_head || !lo || !hi || !found) return fail(CHR_E_INVAL, "NULL argument");
+  if (!std::isfinite(kmin) || !std::isfinite(kmax) || !(kmin <= kmax))
+    return fail(CHR_E_INVAL, "isovalue range must be finite with kmin <= kmax");
+  chr_info I;
+  int rc = chr_stream_info(h_head, head_bytes, &I);
+  if (rc) return rc;
+  if (head_bytes < I.payload_offset) return fail(CHR_E_INVAL, "h_head must hold the header and tables");
+  Geo g;
+  rc = info_geo(&I, g);
+  if (rc) return rc;
+  const uint8_t *s = static_cast<const uint8_t *>(h_head);
+  const size_t btab = kHeaderBytes + 16 * (size_t)I.nblocks * I.levels;
+  int64_t blo[3] = {INT64_MAX, INT64_MAX, INT64_MAX}, bhi[3] = {-1, -1, -1};
+  int any = 0;
+  for (int64_t b = 0; b < I.nblocks; b++) {
+    const float mn = rd<float>(s + btab + 16 * (size_t)b), mx = rd<float>(s + btab + 16 * (size_t)b + 4);
+    if (!(mn < mx && mn < kmax && kmin <= mx)) continue;
+    int64_t o[3], h[3];
+    block_ext(g, b, o, h);
+    for (int a = 0; a < 3; a++) {
+      blo[a] = std::min(blo[a], o[a]);
+      bhi[a] = std::max(bhi[a], h[a]);
+    }
+    any = 1;
+  }
+  *found = any;
+  if (any)
+    for (int a = 0; a < 3; a++) { lo[a] = blo[a]; hi[a] = bhi[a]; }
+  return CHR_OK;
+}
+
+size_t iso_box_workspace(const int64_t box_dims[3]) { return mc_workspace_bytes(box_dims); }
+
+int iso_extract_box(const float *d_field, const int64_t dims[3], const int64_t lo[3], const int64_t hi[3],
+                    float isovalue, float spacing, float *d_vertices, int64_t cap_v, int32_t *d_tris, int64_t cap_t,
+                    int64_t *d_counts, void *d_ws, size_t ws_bytes, void *stream) {
+  if (!d_field || !dims || !lo || !hi || !d_ws) return fail(CHR_E_INVAL, "NULL argument");
+  if (!dims_ok(dims)) return fail(CHR_E_INVAL, "dims must be in [1, 2^30]");
+  int64_t bd[3];
+  for (int a = 0; a < 3; a++) {
+    if (lo[a] < 0 || hi[a] >= dims[a] || lo[a] > hi[a]) return fail(CHR_E_INVAL, "box outside the field or empty");
+    bd[a] = hi[a] - lo[a] + 1;
+  }
+  const size_t need = iso_box_workspace(bd);
+  if (need == 0) return fail(CHR_E_INVAL, "box too large");
+  if (ws_bytes < need) return fail(CHR_E_NOMEM, "workspace too small: need " + std::to_string(need));
+  // the box read in place: its first point, the field's row and plane pitches
+  const float *f0 = d_field + (lo[0] * dims[1] + lo[1]) * dims[2] + lo[2];
+  McJob J;
+  int rc = mc_prepare(f0, bd, isovalue, spacing, d_vertices, cap_v, d_tris, cap_t, d_counts, d_ws, ws_bytes, J);
+  if (rc) return rc;
+  for (int a = 0; a < 3; a++) J.M.org[a] = (uint32_t)lo[a];
+  J.M.py = dims[2];
+  J.M.pz = dims[1] * dims[2];
+  launch_mc(J.M, J.scan, static_cast<hipStream_t>(stream));
+  return check_hip("iso_extract_box launch");
 }
 
 int iso_cases(const float *d_field, const int64_t dims[3], float isovalue, uint8_t *d_cases, void *d_ws,

@@ -91,6 +91,8 @@ struct McPlan {
   int64_t *counts;
   uint8_t *cases;
   FastDiv d_nw, d_n1;            // word -> (row, word in row), row -> (z, y); set by the launchers
+  uint32_t org[3];               // grid coordinates (z, y, x) of point 0 in a larger field (0: the field itself)
+  int64_t py, pz;                // elements between rows and between planes of f (n[2] and n[1]*n[2] for a whole field)
 };
 
 // Measurement hook: records a HIP event around launches of the kernel

@@ -46,7 +46,8 @@ __global__ __launch_bounds__(kBS) void k_mc_bits(McPlan M) {
   if (row >= M.nrows) return;
   const int lane = lane_id();
   const uint32_t nx = (uint32_t)M.n[2], nw = (uint32_t)M.nw;
-  const char *__restrict__ fb = reinterpret_cast<const char *>(M.f + row * M.n[2]);
+  const uint32_t rz = fdiv((uint32_t)row, M.d_n1), ry = (uint32_t)row - rz * (uint32_t)M.n[1];
+  const char *__restrict__ fb = reinterpret_cast<const char *>(M.f + (int64_t)rz * M.pz + (int64_t)ry * M.py);
   u64 *out = M.bits + row * M.nw;
   const float k = M.k;
   for (uint32_t w0 = 0; w0 < nw; w0 += kWordsPerWave) {
@@ -257,14 +258,14 @@ __global__ __launch_bounds__(kBS) void k_mc_verts(McPlan M) {
     const Cross x = cross_of(M, c.z, c.y, c.w);
     uint64_t id = M.P[gw].x + (uint32_t)popc3_below(x, i);
     const uint32_t xx = c.w * 64u + (uint32_t)i;
-    const size_t gi = ((size_t)c.z * n1 + c.y) * n2 + xx;
+    const size_t gi = (size_t)c.z * (size_t)M.pz + (size_t)c.y * (size_t)M.py + xx;
     // the point and its three neighbours, loaded together with the masks
     // (a missing neighbour reads the point itself and is never used)
     const float fa = f[gi];
     const float fx = f[xx + 1 < n2 ? gi + 1 : gi];
-    const float fy = f[c.y + 1 < n1 ? gi + n2 : gi];
-    const float fz = f[c.z + 1 < (uint32_t)M.n[0] ? gi + (size_t)n1 * n2 : gi];
-    const float px = (float)xx, py = (float)c.y, pz = (float)c.z;
+    const float fy = f[c.y + 1 < n1 ? gi + (size_t)M.py : gi];
+    const float fz = f[c.z + 1 < (uint32_t)M.n[0] ? gi + (size_t)M.pz : gi];
+    const float px = (float)(xx + M.org[2]), py = (float)(c.y + M.org[1]), pz = (float)(c.z + M.org[0]);
     if ((x.cx >> i) & 1ull) {
       if ((int64_t)id < M.cap_v) {
         const float t = interp(fa, fx, k);

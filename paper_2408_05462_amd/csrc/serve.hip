@@ -257,6 +257,8 @@ int launch_group(chr_server *s, int j) {
     M.nrows = z.nrows;
     M.nw = z.nw;
     M.f = recon;
+    M.py = G.dims[2];
+    M.pz = G.dims[1] * G.dims[2];
     M.k = r.k;
     M.spacing = (float)(1 << r.level);
     M.bits = reinterpret_cast<unsigned long long *>(c);

@@ -402,3 +402,17 @@ def test_tier_bounds_rejected_on_the_host():
     b = np.asarray([0.1], np.float64)
     assert lib.chr_tiers_compress(fake, L.dims3((20, 20, 20)), b.ctypes.data_as(C.c_void_p), 1, None, 0, C.byref(pf),
                                   fake, 1 << 30, fake, fake, 1 << 40, None) == L.CHR_E_INVAL
+
+
+def test_block_box_matches_oracle_on_the_host():
+    z, y, x = np.meshgrid(*[np.arange(n, dtype=np.float64) for n in (30, 31, 33)], indexing="ij")
+    f = np.exp(-((z - 7) ** 2 + (y - 8) ** 2 + (x - 9) ** 2) / 18.0).astype(np.float32)
+    s = oracle.compress(f, 1e-4, [0.5], levels=3, block=8)["stream"]
+    info = oracle.stream_info(s)
+    head = bytes(s[: info.payload_offset])
+    for kmin, kmax in [(0.5, 0.5), (0.2, 0.9), (5.0, 6.0), (-1.0, 0.0)]:
+        assert api.chr_block_box(head, kmin, kmax) == oracle.block_box(s, kmin, kmax), (kmin, kmax)
+    with pytest.raises(L.ChrError):
+        api.chr_block_box(head, 1.0, 0.5)
+    with pytest.raises(L.ChrError):
+        api.chr_block_box(head[:300], 0.5, 0.5)
