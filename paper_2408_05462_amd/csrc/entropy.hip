@@ -378,46 +378,58 @@ __global__ __launch_bounds__(kBS) void k_ent_decode(DecE D) {
   const uint32_t *offs = reinterpret_cast<const uint32_t *>(D.in + kOffOff);
   const uint64_t w0 = offs[c], w1 = offs[c + 1];
   const uint64_t words = (D.nbytes - D.base) / 4;
-  if (w0 > w1 || w1 > words) {
+  if (w0 >= w1 || w1 > words) {   // every chunk holds at least one code, so at least one word
     *D.status = CHR_E_CORRUPT;
     return;
   }
   const uint32_t *src = reinterpret_cast<const uint32_t *>(D.in + D.base);
   const uint64_t first = c * kChunk;
   const uint32_t len = (uint32_t)min<uint64_t>(kChunk, D.n - first);
-  // two words prefetched ahead of the bit buffer, so a refill does not wait
-  // for memory
-  uint64_t wi = w0;
-  uint32_t n0 = wi < w1 ? src[wi] : 0u;
-  wi++;
-  uint32_t n1 = wi < w1 ? src[wi] : 0u;
-  wi++;
-  uint64_t buf = 0;
-  uint32_t nb = 0, used = 0;
+  // A fixed schedule: every 4 symbols, the 64 bits at the current position
+  // from three whole words (unconditional loads, clamped to the bit area),
+  // which hold 4 codes of at most 12 bits.  Loads on a per-lane condition
+  // would make the compiler wait for every outstanding load at each refill.
+  // 64 decoded bytes are held in registers and written together, so stores
+  // do not sit between a window's loads and their use either.
+  const uint64_t wlast = words - 1;   // words >= w1 > w0 here
+  uint64_t pos = 0;                   // bits consumed
+  uint32_t used = 0;
   bool bad = false;
-  uint64_t acc = 0;
-  for (uint32_t i = 0; i < len; i++) {
-    if (nb < 32) {
-      buf |= (uint64_t)n0 << nb;
-      nb += 32;
-      n0 = n1;
-      n1 = wi < w1 ? src[wi] : 0u;
-      wi++;
+  for (uint32_t i0 = 0; i0 < len; i0 += 64) {
+    uint64_t o[8];
+#pragma unroll
+    for (int g = 0; g < 16; g++) {
+      const uint64_t wi = w0 + (pos >> 5);
+      const uint32_t sh = (uint32_t)(pos & 31u);
+      uint32_t a = src[min(wi, wlast)], b = src[min(wi + 1, wlast)], d = src[min(wi + 2, wlast)];
+      a = wi < w1 ? a : 0u;
+      b = wi + 1 < w1 ? b : 0u;
+      d = wi + 2 < w1 ? d : 0u;
+      uint64_t win = ((((uint64_t)b << 32) | a) >> sh) | (sh ? (uint64_t)d << (64 - sh) : 0ull);
+      uint64_t acc = 0;
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        const bool live = i0 + (uint32_t)(4 * g + k) < len;
+        const uint32_t e = tab[win & ((1u << kMaxLen) - 1u)];
+        uint32_t Ls = e >> 8;
+        bad |= live && Ls == 0;
+        Ls = live ? (Ls ? Ls : 1u) : 0u;
+        win >>= Ls;
+        pos += Ls;
+        acc |= (uint64_t)(e & 255u) << (8 * k);
+      }
+      if (g & 1) o[g >> 1] |= acc << 32;
+      else o[g >> 1] = acc;
     }
-    const uint32_t e = tab[buf & ((1u << kMaxLen) - 1u)];
-    uint32_t Ls = e >> 8;
-    bad |= Ls == 0;
-    Ls = Ls ? Ls : 1u;
-    buf >>= Ls;
-    nb -= Ls;
-    used += Ls;
-    acc |= (uint64_t)(e & 255u) << (8 * (i & 7u));
-    if ((i & 7u) == 7u) {
-      *reinterpret_cast<uint64_t *>(D.out + first + (i & ~7u)) = acc;
-      acc = 0;
+    uint8_t *dst = D.out + first + i0;
+    if (i0 + 64 <= len) {
+#pragma unroll
+      for (int g = 0; g < 8; g++) reinterpret_cast<uint64_t *>(dst)[g] = o[g];
+    } else {
+      for (uint32_t k = 0; i0 + k < len; k++) dst[k] = (uint8_t)(o[k >> 3] >> (8 * (k & 7u)));
     }
   }
-  for (uint32_t i = len & ~7u; i < len; i++) D.out[first + i] = (uint8_t)(acc >> (8 * (i & 7u)));
+  used = pos > 0xffffffffull ? 0xffffffffu : (uint32_t)pos;
   bad |= (uint64_t)used > (w1 - w0) * 32;  // read past the chunk's bits
   if (bad) *D.status = CHR_E_CORRUPT;
 }
