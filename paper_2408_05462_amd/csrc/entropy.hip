@@ -231,6 +231,15 @@ __global__ __launch_bounds__(256) void k_ent_table(EntPlan E) {
   E.tab->len[s] = (uint8_t)L;
 }
 
+// The 8 input bytes at b (8-aligned): one load inside the input, bytes up
+// to its end otherwise (zero past it).
+__device__ inline uint64_t load8(const EntPlan &E, uint64_t b) {
+  if (b + 8 <= E.n) return *reinterpret_cast<const uint64_t *>(E.in + b);
+  uint64_t v = 0;
+  for (uint64_t i = b; i < E.n; i++) v |= (uint64_t)E.in[i] << (8 * (i - b));
+  return v;
+}
+
 // Bits of each chunk (one wave per chunk, 8 bytes per lane), as 32-bit words.
 __global__ __launch_bounds__(kBS) void k_ent_sizes(EntPlan E) {
   __shared__ uint8_t ln[256];
@@ -240,9 +249,11 @@ __global__ __launch_bounds__(kBS) void k_ent_sizes(EntPlan E) {
   if (c >= E.nch) return;
   const int lane = lane_id();
   const uint64_t b0 = c * kChunk + 8 * (uint64_t)lane;
+  const uint64_t v = load8(E, b0);
   uint32_t bits = 0;
+#pragma unroll
   for (int b = 0; b < 8; b++)
-    if (b0 + b < E.n) bits += ln[E.in[b0 + b]];
+    if (b0 + b < E.n) bits += ln[(v >> (8 * b)) & 255u];
   bits = wave_sum_dpp(bits);
   if (lane == 0) E.csize[c] = (bits + 31) / 32;
 }
@@ -298,11 +309,12 @@ __global__ __launch_bounds__(kBS) void k_ent_write(EntPlan E) {
   uint32_t *wd = words[wave];
   for (uint32_t i = (uint32_t)lane; i < kChunkWords; i += kWave) wd[i] = 0u;
   const uint64_t b0 = c * kChunk + 8 * (uint64_t)lane;
+  const uint64_t v8 = load8(E, b0);
   uint32_t sym[8];
   uint32_t bits = 0;
 #pragma unroll
   for (int b = 0; b < 8; b++) {
-    sym[b] = b0 + b < E.n ? E.in[b0 + b] : 256u;
+    sym[b] = b0 + b < E.n ? (uint32_t)((v8 >> (8 * b)) & 255u) : 256u;
     bits += sym[b] < 256u ? ln[sym[b]] : 0u;
   }
   uint32_t pos = wave_excl_sum(bits);
