@@ -78,7 +78,7 @@ __global__ __launch_bounds__(kBS) void k_ent_hist(EntPlan E) {
 // (the consumed queue's next entry); the leaf depths follow by pointer
 // jumping over the parent links.
 __global__ __launch_bounds__(256) void k_ent_table(EntPlan E) {
-  __shared__ uint32_t hs[256];
+  __shared__ __align__(16) uint32_t hs[256];
   __shared__ int order[256];      // present values by (count, value) increasing
   __shared__ int bits[512];       // codes per length
   __shared__ int par[512], anc[512], dep[512];
@@ -96,11 +96,17 @@ __global__ __launch_bounds__(256) void k_ent_table(EntPlan E) {
   __syncthreads();
   // rank among the present values by (count, value)
   int rk = 0, m = 0;
-#pragma unroll 16
-  for (int t = 0; t < 256; t++) {
-    const uint32_t ct = hs[t];
-    m += ct != 0u;
-    rk += ct != 0u && (ct < c || (ct == c && t < s));
+  const uint4 *h4 = reinterpret_cast<const uint4 *>(hs);   // four counts per LDS read
+#pragma unroll 8
+  for (int t4 = 0; t4 < 64; t4++) {
+    const uint4 q = h4[t4];
+    const uint32_t ct[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      const int t = 4 * t4 + i;
+      m += ct[i] != 0u;
+      rk += ct[i] != 0u && (ct[i] < c || (ct[i] == c && t < s));
+    }
   }
   if (c) order[rk] = s;
   ln[s] = 0;
@@ -195,10 +201,16 @@ __global__ __launch_bounds__(256) void k_ent_table(EntPlan E) {
   // lengths to the values from the most frequent: rank by (count desc, value)
   if (c) {
     int r2 = 0;
-#pragma unroll 16
-    for (int t = 0; t < 256; t++) {
-      const uint32_t ct = hs[t];
-      r2 += ct != 0u && (ct > c || (ct == c && t < s));
+    const uint4 *h4b = reinterpret_cast<const uint4 *>(hs);
+#pragma unroll 8
+    for (int t4 = 0; t4 < 64; t4++) {
+      const uint4 q = h4b[t4];
+      const uint32_t ct[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        const int t = 4 * t4 + i;
+        r2 += ct[i] != 0u && (ct[i] > c || (ct[i] == c && t < s));
+      }
     }
     int acc = 0, l = 1;
     for (; l <= kMaxLen; l++) {
