@@ -6,7 +6,7 @@
 // include/chr.h.
 //
 // Encoding: a histogram (LDS bins per workgroup, one global add per bin), the
-// code table by one workgroup (parallel ranks for the two sorts, one lane for
+// code table by one workgroup (parallel ranks for the two sorts, one wave for
 // the Huffman merge), per-chunk bit counts (one wave per 512-byte chunk), a
 // scan of the chunks' word counts, and the packing (one wave per chunk: lane
 // bit offsets by a wave scan, codes OR-ed into the chunk's words in LDS,
@@ -73,29 +73,35 @@ __global__ __launch_bounds__(kBS) void k_ent_hist(EntPlan E) {
 }
 
 // The code table (one workgroup of 256 threads, thread s for byte value s).
-// The Huffman merge runs on wave 0 in uniform control flow: the fronts of
-// the two queues stay in scalar registers, so a pick costs one LDS read
-// (the consumed queue's next entry); the leaf depths follow by pointer
+// The Huffman merge runs on wave 0 in uniform control flow with both queues
+// held in vector registers across the lanes (a pick reads the consumed
+// queue's next entry with one readlane); the leaf depths follow by pointer
 // jumping over the parent links.
 __global__ __launch_bounds__(256) void k_ent_table(EntPlan E) {
   __shared__ __align__(16) uint32_t hs[256];
   __shared__ int order[256];      // present values by (count, value) increasing
   __shared__ int bits[512];       // codes per length
   __shared__ int par[512], anc[512], dep[512];
-  __shared__ uint32_t lw[256], nw[256];   // leaf weights in queue order, node weights in creation order
+  __shared__ uint32_t lw[256];    // leaf weights in queue order, then leaves consumed per merge step
   __shared__ int blc[kMaxLen + 1];
   __shared__ uint32_t nextc[kMaxLen + 1];
-  __shared__ int maxd_s;
-  __shared__ uint8_t ln[256];
-  const int s = threadIdx.x;
+  __shared__ int wl[kWaves][kMaxLen + 1];   // codes per length in each wave
+  __shared__ int maxd_s, m_s;
+  const int s = threadIdx.x, lane = lane_id(), wave = s / kWave;
   const uint32_t c = E.tab->hist[s];
   hs[s] = c;
   for (int i = s; i < 512; i += 256) bits[i] = 0;
   if (s <= kMaxLen) blc[s] = 0;
-  if (s == 0) maxd_s = 0;
+  if (s == 0) { maxd_s = 0; m_s = 0; }
   __syncthreads();
-  // rank among the present values by (count, value)
-  int rk = 0, m = 0;
+  {
+    const unsigned long long pm = __ballot(c != 0u);
+    if (lane == 0) atomicAdd(&m_s, __popcll(pm));
+  }
+  // ranks among the present values: rk by (count, value) increasing, r2 by
+  // (count decreasing, value); both from one pass over the counts (for an
+  // absent value they are not used)
+  int rk = 0, r2 = 0;
   const uint4 *h4 = reinterpret_cast<const uint4 *>(hs);   // four counts per LDS read
 #pragma unroll 8
   for (int t4 = 0; t4 < 64; t4++) {
@@ -104,12 +110,14 @@ __global__ __launch_bounds__(256) void k_ent_table(EntPlan E) {
 #pragma unroll
     for (int i = 0; i < 4; i++) {
       const int t = 4 * t4 + i;
-      m += ct[i] != 0u;
-      rk += ct[i] != 0u && (ct[i] < c || (ct[i] == c && t < s));
+      const int e = ct[i] == c && t < s;
+      rk += (int)(ct[i] - 1u < c - 1u) + e;   // 0 < count < c
+      r2 += (int)(ct[i] > c) + e;
     }
   }
+  __syncthreads();
+  const int m = m_s;
   if (c) order[rk] = s;
-  ln[s] = 0;
   __syncthreads();
   if (s < m) lw[s] = hs[order[s]];
   __syncthreads();
@@ -117,35 +125,74 @@ __global__ __launch_bounds__(256) void k_ent_table(EntPlan E) {
   // (tree node m + j) made at step j; the lighter front is taken, a leaf
   // first on a tie (weights fit 32 bits: they sum to at most n < 2^32)
   const int nn = 2 * m - 1;   // tree nodes when m >= 2
-  if (m >= 2 && s < kWave) {
-    // wave-uniform: every lane reads the same LDS word, readfirstlane makes it scalar
-    auto rd = [](const uint32_t *a, uint32_t i) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)a[i]); };
+  // (the wave test through readfirstlane, so the compiler sees a uniform
+  // branch and keeps the merge's state in scalar registers)
+  if (m >= 2 && __builtin_amdgcn_readfirstlane(s) < kWave) {
+    // Wave-uniform, with both queues in vector registers: lane i holds
+    // entries i, i + 64, i + 128 and i + 192.  Each queue is read through
+    // the register of its front's 64 entries (switched at those boundaries),
+    // so a pick reads its next front with one readlane, and a new node goes
+    // into the register being filled with one lane select.  The parent links
+    // are not written here: each step records how many leaves have been
+    // consumed, and the links follow from that afterwards.
+    const uint32_t ul = (uint32_t)lane;
+    const uint32_t L1 = lw[ul + 64], L2 = lw[ul + 128], L3 = lw[ul + 192];
+    uint32_t CL = lw[ul];          // leaves 64 (qi / 64) ..
+    uint32_t N1 = 0, N2 = 0;       // finished nodes 64..127 and 128..191
+    uint32_t CW = 0;               // nodes 64 (made / 64) .. made - 1
+    uint32_t CR = 0;               // nodes 64 (qj / 64) .., once finished
+    uint32_t CQ = 0;               // leaves consumed after steps 64 (step / 64) ..
+    auto rl = [](uint32_t r, uint32_t i) { return (uint32_t)__builtin_amdgcn_readlane((int)r, (int)(i & 63u)); };
     const uint32_t mu = (uint32_t)__builtin_amdgcn_readfirstlane(m);
     uint32_t qi = 0, qj = 0, made = 0;
-    uint32_t a = rd(lw, 0), b = 0;   // fronts: leaf qi (qi < m), node qj (qj < made)
+    uint32_t a = rl(CL, 0), b = 0;   // fronts: leaf qi (qi < m), node qj (qj < made)
+    auto u = [](uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); };
     for (uint32_t step = 0; step + 1 < mu; step++) {
-      const int node = (int)(mu + made);
       uint32_t wsum = 0;
       for (int t = 0; t < 2; t++) {
-        if (qi < mu && (qj >= made || a <= b)) {
-          wsum += a;
-          if (s == 0) par[qi] = node;
-          qi++;
-          a = qi < mu ? rd(lw, qi) : 0u;
-        } else {
-          wsum += b;
-          if (s == 0) par[mu + qj] = node;
-          qj++;
-          b = qj < made ? rd(nw, qj) : 0u;
-        }
+        const uint32_t leaf = u((uint32_t)(qi < mu) & ((uint32_t)(qj >= made) | (uint32_t)(a <= b)));
+        wsum += leaf ? a : b;
+        qi += leaf;
+        qj += leaf ^ 1u;
+        if ((qi & 63u) == 0u && leaf) CL = qi == 64u ? L1 : qi == 128u ? L2 : L3;
+        if ((qj & 63u) == 0u && !leaf && (qj >> 6) < (made >> 6)) CR = qj == 64u ? N1 : N2;
+        a = u(rl(CL, qi));
+        b = u(rl((qj >> 6) == (made >> 6) ? CW : CR, qj));
       }
-      if (s == 0) nw[made] = wsum;
+      CW = ul == (made & 63u) ? wsum : CW;
+      CQ = ul == (step & 63u) ? qi : CQ;
       made++;
+      if ((made & 63u) == 0u) {
+        // the register being filled is complete (made <= 255: at most three times)
+        if (made == 128u) N1 = CW;
+        else if (made == 192u) N2 = CW;
+        if ((qj >> 6) == ((made - 1u) >> 6)) CR = CW;
+        CW = 0;
+      }
+      if ((step & 63u) == 63u) lw[(step & ~63u) + ul] = CQ;
       if (qj + 1 == made) b = wsum;   // the node queue was empty: the new node is its front
     }
+    lw[((mu - 2u) & ~63u) + ul] = CQ;
   }
   __syncthreads();
   if (m >= 2) {
+    // Parent links from the per-step leaf counts lw[0..m-2] (non-decreasing,
+    // lw[m-2] = m): leaf i went into the node of the first step j with
+    // lw[j] > i, internal node k into that of the first step j whose node
+    // count 2 (j + 1) - lw[j] exceeds k.
+    for (int v = s; v < nn - 1; v += 256) {
+      const bool isleaf = v < m;
+      const int key = isleaf ? v : v - m;
+      int lo = 0, hi = m - 2;   // the answer lies in [lo, hi]
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        const int cnt = isleaf ? (int)lw[mid] : 2 * (mid + 1) - (int)lw[mid];
+        if (cnt > key) hi = mid;
+        else lo = mid + 1;
+      }
+      par[v] = m + lo;
+    }
+    __syncthreads();
     // depth = number of ancestors, by pointer jumping (depths stay below 256)
     const int root = nn - 1;
     for (int v = s; v < nn; v += 256) {
@@ -198,30 +245,26 @@ __global__ __launch_bounds__(256) void k_ent_table(EntPlan E) {
     }
   }
   __syncthreads();
-  // lengths to the values from the most frequent: rank by (count desc, value)
+  // lengths to the values from the most frequent (rank r2)
+  int L = 0;
   if (c) {
-    int r2 = 0;
-    const uint4 *h4b = reinterpret_cast<const uint4 *>(hs);
-#pragma unroll 8
-    for (int t4 = 0; t4 < 64; t4++) {
-      const uint4 q = h4b[t4];
-      const uint32_t ct[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-      for (int i = 0; i < 4; i++) {
-        const int t = 4 * t4 + i;
-        r2 += ct[i] != 0u && (ct[i] > c || (ct[i] == c && t < s));
-      }
-    }
     int acc = 0, l = 1;
     for (; l <= kMaxLen; l++) {
       if (r2 < acc + bits[l]) break;
       acc += bits[l];
     }
-    ln[s] = (uint8_t)l;
+    L = l;
     atomicAdd(&blc[l], 1);
   }
+  // canonical codes: shorter first, consecutive in value order within a
+  // length; the values of this length below s, counted by ballots per wave
+  int before = 0;
+  for (int l = 1; l <= kMaxLen; l++) {
+    const unsigned long long mk = __ballot(L == l);
+    if (lane == 0) wl[wave][l] = __popcll(mk);
+    if (L == l) before = __popcll(mk & ((1ull << lane) - 1ull));
+  }
   __syncthreads();
-  // canonical codes: shorter first, consecutive in value order within a length
   if (s == 0) {
     uint32_t code = 0;
     for (int l = 1; l <= kMaxLen; l++) {
@@ -230,11 +273,9 @@ __global__ __launch_bounds__(256) void k_ent_table(EntPlan E) {
     }
   }
   __syncthreads();
-  const int L = ln[s];
   uint32_t code = 0;
   if (L) {
-    int before = 0;
-    for (int t = 0; t < s; t++) before += ln[t] == L;
+    for (int w = 0; w < wave; w++) before += wl[w][L];
     code = nextc[L] + (uint32_t)before;
   }
   uint32_t r = 0;

@@ -52,6 +52,13 @@ def _data(kind):
         return _fib_bytes(20, 1)
     if kind == "fib26":
         return _fib_bytes(26, 2)
+    if kind in ("zipf130", "zipf200"):
+        # 130 or 200 distinct values with counts ~ 1/rank: the alphabet ends
+        # inside the second or the fourth block of 64 tree nodes
+        k = int(kind[4:])
+        cnt = np.maximum(1, (40000 / np.arange(1, k + 1)).astype(np.int64))
+        d = np.repeat(rng.permutation(256)[:k].astype(np.uint8), cnt)
+        return d[rng.permutation(d.size)]
     if kind == "chr_stream":
         f = inputs.grf(48, 0.5)[:40, :37, :45].copy()
         return oracle.compress(f, 1e-3 * float(f.max() - f.min()), [0.0], levels=3, block=16)["stream"]
@@ -61,8 +68,8 @@ def _data(kind):
     raise KeyError(kind)
 
 
-KINDS = ["empty", "one", "seven", "same", "two", "all256", "uniform", "skewed", "fib20", "fib26", "chr_stream",
-         "chr_stream_big"]
+KINDS = ["empty", "one", "seven", "same", "two", "all256", "uniform", "skewed", "fib20", "fib26", "zipf130",
+         "zipf200", "chr_stream", "chr_stream_big"]
 
 
 def _dev(a):
