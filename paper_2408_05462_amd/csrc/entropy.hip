@@ -408,6 +408,7 @@ __global__ __launch_bounds__(kBS) void k_ent_decode(DecE D) {
   __shared__ uint8_t ln[256];
   __shared__ int blc[kMaxLen + 1];
   __shared__ uint32_t nextc[kMaxLen + 1];
+  __shared__ int wl[kWaves][kMaxLen + 1];   // codes per length in each wave
   // canonical codes of the stored lengths (as the encoder), then every
   // window whose low L bits are a value's reversed code maps to it
   const int s = threadIdx.x;
@@ -418,6 +419,14 @@ __global__ __launch_bounds__(kBS) void k_ent_decode(DecE D) {
   const int L = ln[s];
   const bool has = L >= 1 && L <= kMaxLen;
   if (has) atomicAdd(&blc[L], 1);
+  // the values of this length below s: ballots per wave, then the waves before
+  const int lane = lane_id(), wave = s / kWave;
+  int before = 0;
+  for (int l = 1; l <= kMaxLen; l++) {
+    const unsigned long long mk = __ballot(has && L == l);
+    if (lane == 0) wl[wave][l] = __popcll(mk);
+    if (has && L == l) before = __popcll(mk & ((1ull << lane) - 1ull));
+  }
   __syncthreads();
   if (s == 0) {
     uint32_t code = 0;
@@ -428,8 +437,7 @@ __global__ __launch_bounds__(kBS) void k_ent_decode(DecE D) {
   }
   __syncthreads();
   if (has) {
-    int before = 0;
-    for (int t = 0; t < s; t++) before += ln[t] == L;
+    for (int w = 0; w < wave; w++) before += wl[w][L];
     const uint32_t code = nextc[L] + (uint32_t)before;
     uint32_t r = 0;
     for (int b = 0; b < L; b++) r |= ((code >> b) & 1u) << (L - 1 - b);
