@@ -491,8 +491,11 @@ int chr_entropy_encode(const void *d_in, uint64_t n, void *d_out, size_t capacit
  * 512-byte chunks and 12-bit codes. */
 int chr_entropy_info(const void *h_head, size_t head_bytes, uint64_t *n, uint64_t *total);
 /* Decodes the encoded stream d_in (nbytes, its header also on the host as
- * h_head) into d_out[0 .. n).  *d_status is set to 0, or CHR_E_CORRUPT when
- * a chunk's offsets or codes are invalid.  Errors: as chr_entropy_info,
+ * h_head) into d_out[0 .. n).  Codes are read canonically (the shortest
+ * length whose prefix is a code of that length), so any length table
+ * decodes deterministically.  *d_status is set to 0, or CHR_E_CORRUPT when a
+ * chunk's offsets or codes are invalid or a stored length exceeds 12.
+ * Errors: as chr_entropy_info,
  * CHR_E_CAPACITY (out_capacity < n), CHR_E_INVAL (NULL or misaligned). */
 int chr_entropy_decode(const void *h_head, const void *d_in, uint64_t nbytes, void *d_out, uint64_t out_capacity,
                        int32_t *d_status, void *stream);

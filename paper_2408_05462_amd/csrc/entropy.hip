@@ -405,22 +405,22 @@ struct DecE {
 
 __global__ __launch_bounds__(kBS) void k_ent_decode(DecE D) {
   __shared__ uint16_t tab[1 << kMaxLen];
-  __shared__ uint8_t ln[256];
-  __shared__ int blc[kMaxLen + 1];
+  __shared__ int blc[kMaxLen + 1], start[kMaxLen + 1];
   __shared__ uint32_t nextc[kMaxLen + 1];
   __shared__ int wl[kWaves][kMaxLen + 1];   // codes per length in each wave
-  // canonical codes of the stored lengths (as the encoder), then every
-  // window whose low L bits are a value's reversed code maps to it
-  const int s = threadIdx.x;
-  ln[s] = D.in[kLenOff + s];
-  if (s <= kMaxLen) blc[s] = 0;
-  for (int i = s; i < (1 << kMaxLen); i += kBS) tab[i] = 0;
-  __syncthreads();
-  const int L = ln[s];
+  __shared__ uint8_t sorted[256];           // the values by (length, value)
+  // Canonical codes of the stored lengths (as the encoder): the codes of
+  // length l are blc[l] consecutive integers from nextc[l], taken by the
+  // values of that length in increasing order.  A length above the limit is
+  // never written by the encoder: the stream is corrupt.
+  const int s = threadIdx.x, lane = lane_id(), wave = s / kWave;
+  const int L = D.in[kLenOff + s];
   const bool has = L >= 1 && L <= kMaxLen;
+  if (L > kMaxLen) *D.status = CHR_E_CORRUPT;
+  if (s <= kMaxLen) blc[s] = 0;
+  __syncthreads();
   if (has) atomicAdd(&blc[L], 1);
   // the values of this length below s: ballots per wave, then the waves before
-  const int lane = lane_id(), wave = s / kWave;
   int before = 0;
   for (int l = 1; l <= kMaxLen; l++) {
     const unsigned long long mk = __ballot(has && L == l);
@@ -430,20 +430,45 @@ __global__ __launch_bounds__(kBS) void k_ent_decode(DecE D) {
   __syncthreads();
   if (s == 0) {
     uint32_t code = 0;
+    int acc = 0;
     for (int l = 1; l <= kMaxLen; l++) {
       code = (code + (uint32_t)(l > 1 ? blc[l - 1] : 0)) << 1;
       nextc[l] = code;
+      start[l] = acc;
+      acc += blc[l];
     }
   }
   __syncthreads();
   if (has) {
     for (int w = 0; w < wave; w++) before += wl[w][L];
-    const uint32_t code = nextc[L] + (uint32_t)before;
-    uint32_t r = 0;
-    for (int b = 0; b < L; b++) r |= ((code >> b) & 1u) << (L - 1 - b);
-    r &= (1u << L) - 1u;
-    // (a corrupt table may overlap: entries stay in range, the result is flagged below)
-    for (uint32_t k = 0; k < (1u << (kMaxLen - L)); k++) tab[r + (k << L)] = (uint16_t)(s | (L << 8));
+    sorted[start[L] + before] = (uint8_t)s;
+  }
+  __syncthreads();
+  // The window table, 16 entries per thread: window i (code bits from its
+  // lowest bit) decodes as the canonical decoder reading bit by bit would,
+  // the shortest length whose prefix is a code of that length; no code: 0.
+  {
+    uint32_t nx[kMaxLen + 1], bc[kMaxLen + 1], st[kMaxLen + 1];
+#pragma unroll
+    for (int l = 1; l <= kMaxLen; l++) {
+      nx[l] = nextc[l];
+      bc[l] = (uint32_t)blc[l];
+      st[l] = (uint32_t)start[l];
+    }
+    for (int i = s; i < (1 << kMaxLen); i += kBS) {
+      const uint32_t rev = __brev((uint32_t)i) >> (32 - kMaxLen);   // first code bit highest
+      uint32_t e = 0;
+      bool found = false;
+#pragma unroll
+      for (int l = 1; l <= kMaxLen; l++) {
+        const uint32_t d = (rev >> (kMaxLen - l)) - nx[l];
+        if (!found && d < bc[l]) {
+          found = true;
+          e = (uint32_t)sorted[st[l] + d] | ((uint32_t)l << 8);
+        }
+      }
+      tab[i] = (uint16_t)e;
+    }
   }
   __syncthreads();
   const uint64_t c = (uint64_t)blockIdx.x * kBS + threadIdx.x;

@@ -144,6 +144,42 @@ def _decode_status(enc):
     return int(st.item()), out[:n].cpu().numpy()
 
 
+def _oracle_or_corrupt(enc):
+    try:
+        return 0, oracle.entropy_decode(enc)
+    except oracle.OracleError:
+        return L.CHR_E_CORRUPT, None
+
+
+def test_edited_length_tables_decode_as_the_oracle():
+    # the window table follows canonical decoding (shortest matching length
+    # first), so even a length table the encoder would never write decodes
+    # to the oracle's bytes, or is flagged where the oracle rejects it
+    d = np.minimum(np.random.default_rng(9).geometric(0.25, 6000), 255).astype(np.uint8)
+    enc = oracle.entropy_encode(d)
+    lens = enc[64:320]
+    absent = np.flatnonzero(lens == 0)
+    present = np.flatnonzero(lens > 0)
+    cases = []
+    bad = enc.copy()
+    bad[64 + int(absent[0])] = 13                        # above the limit
+    cases.append(bad)
+    for extra in (int(lens[present].max()), int(lens[present].min()), 12):
+        bad = enc.copy()
+        bad[64 + int(absent[len(absent) // 2])] = extra   # one code too many
+        cases.append(bad)
+    bad = enc.copy()
+    bad[64 + int(present[0])] = 0                         # one code too few
+    cases.append(bad)
+    for k, bad in enumerate(cases):
+        want_st, want = _oracle_or_corrupt(bad)
+        st, got = _decode_status(bad)
+        assert st == want_st, k
+        if want_st == 0:
+            assert np.array_equal(got, want), k
+    assert _oracle_or_corrupt(cases[0])[0] == L.CHR_E_CORRUPT
+
+
 def test_corrupt_streams_are_flagged():
     d = np.minimum(np.random.default_rng(8).geometric(0.3, 5000), 255).astype(np.uint8)
     enc = oracle.entropy_encode(d)
