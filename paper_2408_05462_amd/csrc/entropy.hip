@@ -53,17 +53,28 @@ __global__ __launch_bounds__(kBS) void k_ent_clear(EntPlan E) {
   for (int i = threadIdx.x; i < 256; i += kBS) E.tab->hist[i] = 0u;
 }
 
-// Byte histogram: 8 bytes per load, LDS bins, one global add per bin.
+// Byte histogram: 8 bytes per load, eight loads of a thread in flight
+// together, LDS bins, one global add per bin.
 __global__ __launch_bounds__(kBS) void k_ent_hist(EntPlan E) {
   __shared__ uint32_t h[256];
   for (int i = threadIdx.x; i < 256; i += kBS) h[i] = 0u;
   __syncthreads();
   const uint64_t n8 = E.n / 8;
   const uint64_t *w = reinterpret_cast<const uint64_t *>(E.in);
-  for (uint64_t i = (uint64_t)blockIdx.x * kBS + threadIdx.x; i < n8; i += (uint64_t)gridDim.x * kBS) {
-    const uint64_t v = w[i];
+  const uint64_t stride = (uint64_t)gridDim.x * kBS;
+  for (uint64_t i = (uint64_t)blockIdx.x * kBS + threadIdx.x; i < n8; i += 8 * stride) {
+    uint64_t v[8];
 #pragma unroll
-    for (int b = 0; b < 8; b++) atomicAdd(&h[(v >> (8 * b)) & 255u], 1u);
+    for (int u = 0; u < 8; u++) {
+      const uint64_t j = i + (uint64_t)u * stride;
+      v[u] = j < n8 ? w[j] : 0ull;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+      if (i + (uint64_t)u * stride >= n8) break;
+#pragma unroll
+      for (int b = 0; b < 8; b++) atomicAdd(&h[(v[u] >> (8 * b)) & 255u], 1u);
+    }
   }
   if (blockIdx.x == 0)
     for (uint64_t i = 8 * n8 + threadIdx.x; i < E.n; i += kBS) atomicAdd(&h[E.in[i]], 1u);
@@ -568,7 +579,7 @@ int launch_entropy_encode(const uint8_t *in, uint64_t n, uint8_t *out, uint64_t 
   uint64_t *tmp = reinterpret_cast<uint64_t *>(w + o);
   E.result = result;
   k_ent_clear<<<1, kBS, 0, s>>>(E);
-  const uint64_t g = std::min<uint64_t>(std::max<uint64_t>((n / 8 + kBS - 1) / kBS, 1), 2048);
+  const uint64_t g = std::min<uint64_t>(std::max<uint64_t>((n / 8 + kBS - 1) / kBS, 1), 512);
   k_ent_hist<<<dim3((unsigned)g), dim3(kBS), 0, s>>>(E);
   k_ent_table<<<1, 256, 0, s>>>(E);
   const unsigned gw = (unsigned)std::max<uint64_t>((E.nch + kWaves - 1) / kWaves, 1);
