@@ -8,8 +8,13 @@ input is resident in HBM before the timed region; each step re-runs the whole
 path on the same buffers.
 
 Prints ONE JSON line: the metric, its value, the step time, the roofline of
-the level-0 compression kernel, the CPU oracle baseline and the per-part
-measurements.  --gpus must be 1.
+the level-0 compression kernel, the CPU oracle baseline, the full-size parity
+of the GPU's outputs with the oracle's, and the per-part measurements.  The
+default run (the 512^3 phantom) also carries the metric's second half on its
+own workload -- served p50/p99 on the 1024^3 field resident as three accuracy
+tiers, against plain per-request launches -- and the batched form on 64
+uneven timesteps (one captured graph against plain per-item launches).
+--gpus must be 1.
 """
 from __future__ import annotations
 
@@ -53,7 +58,8 @@ def parse_args():
     ap.add_argument("--requests", type=int, default=300, help="serve1024: requests per open-loop run")
     ap.add_argument("--slots", type=int, default=4, help="serve1024: server slots")
     ap.add_argument("--group", type=int, default=8, help="serve1024: requests per shared reconstruction")
-    ap.add_argument("--no-serve", action="store_true", help="skip the served-latency part of the default run")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-latency part (1024^3) of the default run")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched part (64 timesteps) of the default run")
     ap.add_argument("--no-topology", action="store_true", help="skip the error-translation part of the default run")
     ap.add_argument("--no-entropy", action="store_true", help="skip the entropy stage of the default run")
     ap.add_argument("--no-diff", action="store_true", help="skip differentiated error control in the default run")
@@ -106,7 +112,7 @@ def workflow_model(raw_bytes, cr, stage_ms, link_gbps=1.0):
             "speedup": round(t_raw / t_chr, 2)}
 
 
-def run_batch(args):
+def run_batch(args, emit=True, cpu_baseline=None):
     """64 timesteps of uneven sizes: plain per-item launches against the
     batch replayed as one captured graph (same outputs, checked)."""
     import torch
@@ -190,7 +196,7 @@ def run_batch(args):
     stream_bytes = sum(api.read_result(r)["stream_bytes"] for r in batch.results)
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if (not args.no_cpu_baseline) if cpu_baseline is None else cpu_baseline:
         import oracle
 
         order = sorted(range(len(xs)), key=lambda i: sizes[i])
@@ -226,7 +232,12 @@ def run_batch(args):
         "triangles": int(sum(int(c[:, 1].sum()) for c in cnt)),
         "roofline": None, "cpu_baseline": cpu,
     }
-    print(json.dumps(out), flush=True)
+    del batch, plain, xs, ws_c, ws_m, ws_r
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
 
 
 def serve_experiment(x, isos, levels, block, R, slots, group, fracs=(0.5, 0.8, 1.0), seed_offset=5,
@@ -234,8 +245,9 @@ def serve_experiment(x, isos, levels, block, R, slots, group, fracs=(0.5, 0.8, 1
     """Three resident streams of field x at e = {1e-2, 1e-3, 1e-4} x range; R
     requests (isovalue ~ U(range), accuracy uniform over the tiers, level 0)
     served by the continuous-batching server and, for comparison, by plain
-    per-request launches (reconstruct, then marching cubes, one request at a
-    time in arrival order).  Closed loop (all requests at t = 0) gives each
+    per-request launches (the reconstruction restricted to the blocks that
+    can hold the isovalue -- the same pruning the server applies -- then
+    marching cubes, one request at a time in arrival order).  Closed loop (all requests at t = 0) gives each
     path's saturation rate; open loop (Poisson arrivals at `fracs` x the plain
     path's saturation rate) gives p50/p99 latency.  `verify` served meshes
     are checked bit for bit against the plain calls."""
@@ -298,8 +310,9 @@ def serve_experiment(x, isos, levels, block, R, slots, group, fracs=(0.5, 0.8, 1
             if arrivals[i] > now:
                 time.sleep((arrivals[i] - now) * 1e-3)
             rel, e, st, info, _ = tiers[tier_of[i]]
-            api.chr_reconstruct(info, st, 0, e, recon, st0, rws)
-            api.iso_extract(recon, float(ks[i]), 1.0, verts, tris, counts, mws)
+            k = float(ks[i])
+            api.chr_reconstruct_range(info, st, 0, e, k, k, recon, st0, rws)
+            api.iso_extract(recon, k, 1.0, verts, tris, counts, mws)
             torch.cuda.synchronize()
             lat[i] = (time.perf_counter() - base) * 1e3 - arrivals[i]
         return lat, time.perf_counter() - base
@@ -365,7 +378,7 @@ def serve_experiment(x, isos, levels, block, R, slots, group, fracs=(0.5, 0.8, 1
         srv.drain(sid)
         for i, rid in zip(sample, sid):
             rel, e, st, info, _ = tiers[tier_of[i]]
-            api.chr_reconstruct(info, st, 0, e, recon, st0, rws)
+            api.chr_reconstruct(info, st, 0, e, recon, st0, rws)   # the full reconstruction
             api.iso_extract(recon, float(ks[i]), 1.0, verts, tris, counts, mws)
             torch.cuda.synchronize()
             nv, nt = (int(v) for v in counts.cpu())
@@ -383,8 +396,10 @@ def serve_experiment(x, isos, levels, block, R, slots, group, fracs=(0.5, 0.8, 1
             "tier_of": tier_of, "lo": lo, "hi": hi, "requests": R}
 
 
-def run_serve(args):
+def run_serve(args, emit=True, fracs=(0.5, 0.8, 1.0), requests=None, cpu_baseline=None):
     """The 1024^3 serving workload (see serve_experiment)."""
+    requests = requests or args.requests
+    cpu_baseline = (not args.no_cpu_baseline) if cpu_baseline is None else cpu_baseline
     import torch
 
     from paper_2408_05462_amd import inputs
@@ -397,14 +412,16 @@ def run_serve(args):
     isos = inputs.sample_quantiles(x, 8)
     levels, block = 6, 64
     log(f"field {n}^3 ready in {time.time() - t0:.1f}s")
-    ex = serve_experiment(x, isos, levels, block, args.requests, args.slots, args.group)
+    ex = serve_experiment(x, isos, levels, block, requests, args.slots, args.group, fracs=fracs)
+    planes = 64
+    slab = x[:planes].cpu().numpy() if cpu_baseline else None
+    del x
+    torch.cuda.empty_cache()
     N = ex["N"]
     cpu = None
-    if not args.no_cpu_baseline:
+    if cpu_baseline:
         import oracle
 
-        planes = 64
-        slab = x[:planes].cpu().numpy()
         tc = time.perf_counter()
         done = 0
         for i in ex["sample"][:4]:
@@ -420,11 +437,11 @@ def run_serve(args):
     mid = ex["runs"]["0.8"]
     gbs = ex["sat_served"] * 4.0 * N / 1e9
     out = {
-        "metric": METRIC, "value": round(gbs, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.requests, "warmup": 0,
+        "metric": METRIC, "value": round(gbs, 2), "unit": "GB/s", "n_gpus": 1, "steps": requests, "warmup": 0,
         "ms_per_step": round(1e3 / ex["sat_served"], 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "serve1024", "dims": [n, n, n], "levels": levels, "block": block,
-                   "tiers_rel": [1e-2, 1e-3, 1e-4], "requests": args.requests, "slots": args.slots,
+                   "tiers_rel": [1e-2, 1e-3, 1e-4], "requests": requests, "slots": args.slots,
                    "max_group": args.group},
         "value_is": "served saturation throughput x 4N input bytes per request",
         "saturation_req_s": {"plain": round(ex["sat_plain"], 2), "served": round(ex["sat_served"], 2)},
@@ -433,24 +450,14 @@ def run_serve(args):
         "open_loop": ex["runs"], "compression_ratio": ex["ratios"],
         "roofline": None, "cpu_baseline": cpu,
     }
-    print(json.dumps(out), flush=True)
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
 
 
-def main():
-    args = parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "bench.py measures the one-GPU path only (the multi-GPU split is a design, "
-                                   "not built): run with --gpus 1"}))
-        sys.exit(2)
-    if args.tiles:
-        from paper_2408_05462_amd import api as _api
-        e_cpw, d_cpw = (int(v) for v in args.tiles.split(","))
-        _api.chr_set_tiles(e_cpw, d_cpw)
-    if args.workload == "batch64":
-        return run_batch(args)
-    if args.workload == "serve1024":
-        return run_serve(args)
-
+def run_field(args):
+    """One named field (default: the 512^3 phantom): the timed steps and the
+    measurements on the same field; returns the JSON record."""
     import torch
 
     from paper_2408_05462_amd import _lib as L
@@ -770,23 +777,9 @@ def main():
             del bws
         boxm = per
 
-    # served latency on the same field (the metric's second half): requests
-    # at random isovalues and accuracy tiers, continuous-batching server vs
-    # plain per-request launches at 0.8 x the plain path's saturation rate
-    served = None
-    if not args.no_serve:
-        del cws
-        torch.cuda.empty_cache()
-        ex = serve_experiment(x, isos, w["levels"], w["block"], args.serve_requests, args.slots, args.group,
-                              fracs=(0.8,), verify=4)
-        r8 = ex["runs"]["0.8"]
-        served = {"requests": ex["requests"], "tiers_rel": [1e-2, 1e-3, 1e-4],
-                  "saturation_req_s": {"plain": round(ex["sat_plain"], 2), "served": round(ex["sat_served"], 2)},
-                  "at_0.8_plain_saturation": r8, "p99_ms": r8["served"]["p99_ms"],
-                  "plain_p99_ms": r8["plain"]["p99_ms"]}
-
     # CPU oracle baseline on a bounded sample of the same workload
     cpu = None
+    parity = None
     if not args.no_cpu_baseline:
         import oracle
 
@@ -795,10 +788,27 @@ def main():
         tc = time.perf_counter()
         ref = oracle.compress(sub, e, isos, levels=w["levels"], block=w["block"])
         y = oracle.decompress(ref["stream"])
-        for k in isos:
-            oracle.mc(y, k)
+        meshes = [oracle.mc(y, k) for k in isos]
         tcpu = time.perf_counter() - tc
         nsub = sub.size
+        if planes == shape[0]:
+            # full-size parity, outside the timed region: the GPU's stream,
+            # level-0 reconstruction and meshes against the oracle's
+            gs = sdev.cpu().numpy()
+            same_stream = gs.size == ref["stream"].size and bool(np.array_equal(gs, ref["stream"]))
+            same_recon = bool(np.array_equal(recon.cpu().numpy().view(np.uint32), y.view(np.uint32)))
+            same_mesh = []
+            for k, (rv, rt, rcnt, _) in zip(isos, meshes):
+                gv, gt = api.extract(recon, k)
+                same_mesh.append((gv.shape[0], gt.shape[0]) == tuple(rcnt)
+                                 and bool(np.array_equal(gv.cpu().numpy().view(np.uint32), rv.view(np.uint32)))
+                                 and bool(np.array_equal(gt.cpu().numpy(), rt)))
+                del gv, gt
+            parity = {"against": "oracle", "dims": list(shape), "stream_bytes_equal": same_stream,
+                      "reconstruction_bitwise_equal": same_recon, "meshes_equal": same_mesh,
+                      "all": same_stream and same_recon and all(same_mesh)}
+            log(f"full-size parity against the oracle: {parity}")
+        del ref, y, meshes
         cpu = {"value": round(4.0 * nsub / tcpu / 1e9, 4), "unit": "GB/s",
                "cores": int(oracle.threads()), "kind": "oracle",
                "sample": f"first {planes} z-planes ({'x'.join(map(str, sub.shape))}, {nsub} points), "
@@ -818,11 +828,55 @@ def main():
                        "mc_per_isovalue": round(4.0 * N * len(isos) / stage_ms[2] / 1e6, 1)},
         "compression_ratio": round(cr, 3), "stream_bytes": nbytes, "n_outlier": r["n_outlier"],
         "n_corrected": r["n_corrected"], "triangles": [int(c[1]) for c in cnt],
-        "wall_s_timed": round(wall, 3), "served": served, "topology_error_bound": topo or None, "roofline": roofline,
+        "wall_s_timed": round(wall, 3), "parity": parity, "topology_error_bound": topo or None, "roofline": roofline,
         "cpu_baseline": cpu,
         "workflow_model": workflow_model(4.0 * N, cr, stage_ms), "entropy_stage": ent,
         "differentiated_error_control": dif, "tiers": tiers, "merged_box_extraction": boxm,
     }
+    return out
+
+
+def main():
+    args = parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "bench.py measures the one-GPU path only (the multi-GPU split is a design, "
+                                   "not built): run with --gpus 1"}))
+        sys.exit(2)
+    if args.tiles:
+        from paper_2408_05462_amd import api as _api
+        e_cpw, d_cpw = (int(v) for v in args.tiles.split(","))
+        _api.chr_set_tiles(e_cpw, d_cpw)
+    if args.workload == "batch64":
+        return run_batch(args)
+    if args.workload == "serve1024":
+        return run_serve(args)
+    import torch
+
+    out = run_field(args)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    if args.workload == "phantom512" and not args.no_serve:
+        # the metric's second half on its own workload: the 1024^3 field
+        # resident as three accuracy tiers, requests at 0.8 x the plain
+        # path's saturation rate, served vs plain per-request launches
+        sv = run_serve(args, emit=False, fracs=(0.8,), requests=args.serve_requests, cpu_baseline=False)
+        r8 = sv["open_loop"]["0.8"]
+        out["served"] = {"workload": "serve1024", "dims": sv["config"]["dims"], "requests": sv["config"]["requests"],
+                         "tiers_rel": sv["config"]["tiers_rel"], "saturation_req_s": sv["saturation_req_s"],
+                         "at_0.8_plain_saturation": r8, "p50_ms": r8["served"]["p50_ms"],
+                         "p99_ms": r8["served"]["p99_ms"], "plain_p50_ms": r8["plain"]["p50_ms"],
+                         "plain_p99_ms": r8["plain"]["p99_ms"], "compression_ratio": sv["compression_ratio"],
+                         "reconstructed_input_gbs_at_saturation": sv["value"]}
+        torch.cuda.empty_cache()
+    if args.workload == "phantom512" and not args.no_batch:
+        # the batched form on its own workload: 64 uneven timesteps, one
+        # captured graph against the plain per-item launches
+        bt = run_batch(args, emit=False, cpu_baseline=False)
+        out["batch64"] = {"workload": "batch64", "items": bt["config"]["items"], "points": bt["config"]["points"],
+                          "graph": {"ms_per_step": bt["ms_per_step"], "value": bt["value"]},
+                          "plain": bt["plain"], "speedup_vs_plain": bt["speedup_vs_plain"],
+                          "graph_config": bt["graph_config"], "compression_ratio": bt["compression_ratio"],
+                          "outputs_equal_plain": True}
     print(json.dumps(out), flush=True)
 
 

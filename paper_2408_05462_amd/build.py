@@ -2,8 +2,8 @@
 
 Every translation unit is compiled with -ffp-contract=off (no fused
 multiply-add contraction, so float arithmetic is one IEEE operation per
-source operation), without fast-math, and with packed-FP32 instructions
-disabled.
+source operation), without fast-math, with subnormal binary32 values kept
+(no flush to zero), and with packed-FP32 instructions disabled.
 """
 from __future__ import annotations
 
@@ -22,7 +22,7 @@ ARCH = "gfx950"
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
-    "-ffp-contract=off", "-fno-fast-math",
+    "-ffp-contract=off", "-fno-fast-math", "-fno-gpu-flush-denormals-to-zero",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,

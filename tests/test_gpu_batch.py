@@ -1,7 +1,9 @@
 """Batched path through the C ABI: every item of a batch of uneven sizes,
 run eagerly, captured into a HIP graph and replayed, or autotuned, gives bit
-for bit what the single-field calls give (and its stream is the oracle's).
-Tile shapes of the level-0 kernels never change a result."""
+for bit the oracle's outputs: its stream, its level-0 reconstruction and the
+mesh of every isovalue (the oracle's marching cubes on the oracle's
+reconstruction).  The single-field GPU calls give the same.  Tile shapes of
+the level-0 kernels never change a result."""
 import numpy as np
 import pytest
 import torch
@@ -37,14 +39,15 @@ def _fields():
 
 @pytest.fixture(scope="module")
 def data():
+    """The expected outputs of every item, all from the oracle."""
     fields = _fields()
     xs = [torch.from_numpy(f).to(DEV) for f, *_ in fields]
     singles = []
-    for (f, e, isos, nL, B), x in zip(fields, xs):
-        c = api.compress(x, e, isos, levels=nL, block=B)
-        y = api.reconstruct(c, 0)
-        meshes = [tuple(t.cpu().numpy() for t in api.extract(y, k)) for k in isos]
-        singles.append((c.stream.cpu().numpy().tobytes(), y.cpu().numpy(), meshes))
+    for f, e, isos, nL, B in fields:
+        ref = oracle.compress(f, e, isos, levels=nL, block=B)
+        y = oracle.decompress(ref["stream"], 0)
+        meshes = [oracle.mc(y, k)[:2] for k in isos]
+        singles.append((ref["stream"].tobytes(), y, meshes))
     return fields, xs, singles
 
 
@@ -64,15 +67,21 @@ def _check(batch, singles, what):
             assert np.array_equal(t, tr), (what, i, j)
 
 
-def test_batch_streams_are_the_oracles(data):
+def test_single_calls_match_the_oracle(data):
     fields, xs, singles = data
-    for i, ((f, e, isos, nL, B), (s_ref, _, _)) in enumerate(zip(fields, singles)):
+    for i, ((f, e, isos, nL, B), x, (s_ref, y_ref, m_ref)) in enumerate(zip(fields, xs, singles)):
         print("item", i, f.shape, flush=True)
-        ref = oracle.compress(f, e, isos, levels=nL, block=B)
-        assert ref["stream"].tobytes() == s_ref
+        c = api.compress(x, e, isos, levels=nL, block=B)
+        assert c.stream.cpu().numpy().tobytes() == s_ref, i
+        y = api.reconstruct(c, 0)
+        assert np.array_equal(y.cpu().numpy().view(np.uint32), y_ref.view(np.uint32)), i
+        for j, k in enumerate(isos):
+            v, t = api.extract(y, k)
+            assert np.array_equal(v.cpu().numpy().view(np.uint32), m_ref[j][0].view(np.uint32)), (i, j)
+            assert np.array_equal(t.cpu().numpy(), m_ref[j][1]), (i, j)
 
 
-def test_batch_eager_matches_single_calls(data):
+def test_batch_eager_matches_oracle(data):
     fields, xs, singles = data
     b = _batch(fields, xs)
     for r in b.recon:
@@ -83,7 +92,7 @@ def test_batch_eager_matches_single_calls(data):
     b.close()
 
 
-def test_batch_graph_replays_match_single_calls(data):
+def test_batch_graph_replays_match_oracle(data):
     fields, xs, singles = data
     b = _batch(fields, xs)
     b.capture()

@@ -1,5 +1,7 @@
 """Serving loop through the C ABI: every request's mesh is bit for bit the
-mesh of chr_reconstruct + iso_extract on the stream that served it, whether
+oracle's -- its marching cubes, at the request's isovalue and spacing, on its
+reconstruction of the oracle's stream at the request's level and accuracy
+tier (the GPU streams the server holds are byte-equal to those) -- whether
 the request ran alone or in a mix of overlapping groups, under memory
 pressure (admission waits, preemption), with cancellations and with a
 corrupt stream beside it."""
@@ -7,6 +9,7 @@ import numpy as np
 import pytest
 import torch
 
+import oracle
 from paper_2408_05462_amd import _lib as L
 from paper_2408_05462_amd import api, inputs
 
@@ -26,29 +29,34 @@ def _datasets():
 @pytest.fixture(scope="module")
 def world():
     rng = np.random.default_rng(5)
-    data = {}
+    data, ostreams = {}, {}
     for ds, (f, nL, B) in _datasets().items():
         x = torch.from_numpy(f).to(DEV)
         isos = [float(v) for v in np.quantile(f, [0.2, 0.4, 0.6, 0.8]).astype(np.float32)]
-        tiers = []
+        tiers, orc = [], []
         for rel in TIERS:
             e = inputs.abs_error_bound(rel, f)
-            tiers.append((e, api.compress(x, e, isos, levels=nL, block=B)))
+            c = api.compress(x, e, isos, levels=nL, block=B)
+            ref = oracle.compress(f, e, isos, levels=nL, block=B)
+            assert np.array_equal(c.stream.cpu().numpy(), ref["stream"]), (ds, rel)
+            tiers.append((e, c))
+            orc.append(ref["stream"])
         data[ds] = (f, nL, tiers)
+        ostreams[ds] = orc
     reqs = []
-    for _ in range(28):
+    for _ in range(40):
         ds = int(rng.integers(0, 2))
         f, nL, tiers = data[ds]
         k = float(np.float32(rng.uniform(f.min(), f.max())))
         t = int(rng.integers(0, 3))
         level = int(rng.integers(0, 2))
         reqs.append((ds, k, tiers[t][0], level, t))
-    refs = []
+    refs, recon = [], {}
     for ds, k, acc, level, t in reqs:
-        c = data[ds][2][t][1]
-        y = api.reconstruct(c, level)
-        v, tr = api.extract(y, k, spacing=float(1 << level))
-        refs.append((v.cpu().numpy(), tr.cpu().numpy()))
+        if (ds, t, level) not in recon:
+            recon[(ds, t, level)] = oracle.decompress(ostreams[ds][t], level)
+        v, tr, _, _ = oracle.mc(recon[(ds, t, level)], k, spacing=float(1 << level))
+        refs.append((v, tr))
     return data, reqs, refs
 
 
@@ -71,7 +79,7 @@ def _check(s, ids, reqs, refs, what):
         assert np.array_equal(t, tr), (what, i, reqs[i])
 
 
-def test_serve_alone_matches_plain_calls(world):
+def test_serve_alone_matches_oracle(world):
     data, reqs, refs = world
     s = _server(data, slots=1, group=1)
     for i, (ds, k, acc, level, t) in enumerate(reqs):
@@ -84,7 +92,7 @@ def test_serve_alone_matches_plain_calls(world):
     s.close()
 
 
-def test_serve_mix_matches_plain_calls(world):
+def test_serve_mix_matches_oracle(world):
     data, reqs, refs = world
     s = _server(data, slots=4, group=4)
     ids = [s.submit(ds, k, acc, level) for ds, k, acc, level, t in reqs]
