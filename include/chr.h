@@ -181,6 +181,25 @@ int chr_reconstruct_range(const chr_info *info, const void *d_stream, size_t str
                           int level, double error_bound, float kmin, float kmax, float *d_out,
                           int32_t *d_status, void *d_ws, size_t ws_bytes, void *stream);
 
+/* Bytes of the device array chr_reconstruct_static keeps the coarser-level
+ * grids in (one copy per GPU, held until the process ends). */
+#define CHR_STATIC_SCRATCH_BYTES ((size_t)96 << 20)
+
+/* chr_reconstruct without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the compact grids of the coarser levels
+ * live in a library-owned device array of CHR_STATIC_SCRATCH_BYTES per GPU
+ * (enough for level 0 of fields up to about 1.7e8 points, e.g. 512^3).
+ * Arguments, output and errors as chr_reconstruct, plus CHR_E_NOMEM (nothing
+ * launched) when the level needs more than the array holds.  Calls no
+ * device allocation; the first call on a device looks the array's address up
+ * (hipGetSymbolAddress), so make that first call outside a graph capture.
+ * Every call on a GPU shares that GPU's array: calls that overlap on one GPU
+ * (several streams or threads) race, so serialise them. */
+int chr_reconstruct_static(const chr_info *info, const void *d_stream, size_t stream_bytes,
+                           int level, double error_bound, float *d_out, int32_t *d_status,
+                           void *stream);
+
 /* ---- isosurface extraction (marching cubes, Sec. I and Sec. II.B) ------- */
 
 /* Workspace bytes iso_extract / iso_cases need for a field of these dims. */

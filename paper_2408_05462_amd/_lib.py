@@ -31,7 +31,7 @@ EXPORTS = ["chr_last_error", "chr_version", "chr_compress_bound", "chr_compress_
            "chr_reconstruct_range", "chr_entropy_bound", "chr_entropy_workspace", "chr_entropy_encode",
            "chr_entropy_info", "chr_entropy_decode", "chr_tiers_bound", "chr_tiers_workspace", "chr_tiers_compress",
            "chr_tiers_header", "chr_tiers_reconstruct_workspace", "chr_tiers_reconstruct", "chr_block_box",
-           "iso_box_workspace", "iso_extract_box"]
+           "iso_box_workspace", "iso_extract_box", "chr_reconstruct_static"]
 
 
 class ChrError(RuntimeError):
@@ -132,6 +132,8 @@ def load():
     L.chr_reconstruct.argtypes = [C.POINTER(chr_info), vp, C.c_size_t, C.c_int, C.c_double, vp, vp, vp,
                                   C.c_size_t, vp]
     L.chr_reconstruct.restype = C.c_int
+    L.chr_reconstruct_static.argtypes = [C.POINTER(chr_info), vp, C.c_size_t, C.c_int, C.c_double, vp, vp, vp]
+    L.chr_reconstruct_static.restype = C.c_int
     L.iso_workspace.argtypes = [i64p]
     L.iso_workspace.restype = C.c_size_t
     L.iso_extract.argtypes = [vp, i64p, C.c_float, C.c_float, vp, C.c_int64, vp, C.c_int64, vp, vp, C.c_size_t,

@@ -145,6 +145,14 @@ def chr_reconstruct(info, stream_dev, level, error_bound, out, status, ws, strea
     L.check(rc, "chr_reconstruct")
 
 
+def chr_reconstruct_static(info, stream_dev, level, error_bound, out, status, stream=None):
+    """chr_reconstruct with the coarser-level grids in the library's static
+    device array (no workspace argument, no allocation)."""
+    rc = L.load().chr_reconstruct_static(C.byref(info), _p(stream_dev), stream_dev.numel(), level,
+                                         float(error_bound), _p(out), _p(status), _s(stream))
+    L.check(rc, "chr_reconstruct_static")
+
+
 def chr_reconstruct_range(info, stream_dev, level, error_bound, kmin, kmax, out, status, ws, stream=None):
     rc = L.load().chr_reconstruct_range(C.byref(info), _p(stream_dev), stream_dev.numel(), level, float(error_bound),
                                         float(np.float32(kmin)), float(np.float32(kmax)), _p(out), _p(status), _p(ws),

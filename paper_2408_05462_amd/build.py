@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libchr.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["capi.hip", "batch.hip", "serve.hip", "topo.hip", "encode.hip", "decode.hip", "mc.hip", "scan.hip", "entropy.hip", "tiers.hip"]
+SOURCES = ["capi.hip", "batch.hip", "serve.hip", "topo.hip", "encode.hip", "decode.hip", "mc.hip", "scan.hip", "entropy.hip", "tiers.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

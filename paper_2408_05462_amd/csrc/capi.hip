@@ -598,14 +598,10 @@ size_t chr_reconstruct_workspace(const chr_info *info, int level) {
   return dec_workspace_bytes(g, level);
 }
 
-static int reconstruct_impl(const chr_info *info, const void *d_stream, size_t stream_bytes, int level,
-                            double error_bound, const float *krange, float *d_out, int32_t *d_status, void *d_ws,
-                            size_t ws_bytes, void *stream);
-
 int chr_reconstruct(const chr_info *info, const void *d_stream, size_t stream_bytes, int level, double error_bound,
                     float *d_out, int32_t *d_status, void *d_ws, size_t ws_bytes, void *stream) {
-  return reconstruct_impl(info, d_stream, stream_bytes, level, error_bound, nullptr, d_out, d_status, d_ws, ws_bytes,
-                          stream);
+  return chr::reconstruct_impl(info, d_stream, stream_bytes, level, error_bound, nullptr, d_out, d_status, d_ws,
+                               ws_bytes, stream);
 }
 
 int chr_reconstruct_range(const chr_info *info, const void *d_stream, size_t stream_bytes, int level,
@@ -614,13 +610,23 @@ int chr_reconstruct_range(const chr_info *info, const void *d_stream, size_t str
   if (!std::isfinite(kmin) || !std::isfinite(kmax) || !(kmin <= kmax))
     return fail(CHR_E_INVAL, "isovalue range must be finite with kmin <= kmax");
   const float kr[2] = {kmin, kmax};
-  return reconstruct_impl(info, d_stream, stream_bytes, level, error_bound, kr, d_out, d_status, d_ws, ws_bytes,
-                          stream);
+  return chr::reconstruct_impl(info, d_stream, stream_bytes, level, error_bound, kr, d_out, d_status, d_ws, ws_bytes,
+                               stream);
 }
 
-static int reconstruct_impl(const chr_info *info, const void *d_stream, size_t stream_bytes, int level,
-                            double error_bound, const float *krange, float *d_out, int32_t *d_status, void *d_ws,
-                            size_t ws_bytes, void *stream) {
+}  // extern "C"
+
+namespace chr {
+
+size_t reconstruct_need(const chr_info *info, int level) {
+  Geo g;
+  if (!info || info_geo(info, g) || level < 0 || level >= g.nL) return 0;
+  return dec_need(g, level);
+}
+
+int reconstruct_impl(const chr_info *info, const void *d_stream, size_t stream_bytes, int level, double error_bound,
+                     const float *krange, float *d_out, int32_t *d_status, void *d_ws, size_t ws_bytes,
+                     void *stream) {
   if (!info || !d_stream || !d_out) return fail(CHR_E_INVAL, "NULL argument");
   Geo g;
   int rc = info_geo(info, g);
@@ -640,6 +646,10 @@ static int reconstruct_impl(const chr_info *info, const void *d_stream, size_t s
   launch_decode(J.D, static_cast<hipStream_t>(stream));
   return check_hip("chr_reconstruct launch");
 }
+
+}  // namespace chr
+
+extern "C" {
 
 size_t iso_workspace(const int64_t dims[3]) { return mc_workspace_bytes(dims); }
 

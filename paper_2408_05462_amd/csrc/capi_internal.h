@@ -56,6 +56,16 @@ int mc_prepare(const float *d_field, const int64_t dims[3], float isovalue, floa
 int enc_geometry(const int64_t dims[3], double error_bound, const float *h_iso, int n_iso, const chr_params *p,
                  Geo &g, uint64_t &payload_off);
 
+// Reconstruction of a parsed stream into d_out with the compact grids of the
+// coarser levels in d_ws (ws_bytes); krange (optional, 2 floats) restricts it
+// to the blocks an isovalue range needs.  Every chr_reconstruct* entry point
+// ends here.
+int reconstruct_impl(const chr_info *info, const void *d_stream, size_t stream_bytes, int level, double error_bound,
+                     const float *krange, float *d_out, int32_t *d_status, void *d_ws, size_t ws_bytes, void *stream);
+// Bytes of coarser-level grids a reconstruction to `level` needs (0 when the
+// header or level is invalid, or when nothing is needed).
+size_t reconstruct_need(const chr_info *info, int level);
+
 bool tiles_ok(int enc_cpw, int dec_cpw);
 // The process-wide level-0 tiles (chr_set_tiles).
 void current_tiles(int &enc_cpw, int &dec_cpw);
