@@ -290,6 +290,13 @@ int chr_range(const float *d_field, int64_t n, float *d_out, void *stream);
  * any thread of the process (not for use while another thread launches). */
 int chr_set_tiles(int enc_chunks_per_wave, int dec_chunks_per_wave);
 
+/* Which level-0 kernels run for 64-cell blocks: 1 (default) = one workgroup
+ * per pair of z-planes of a block, rows along x, codes gathered in LDS and
+ * packed per chunk; 0 = one wave per 64-point chunk (the kernels every other
+ * block size uses).  Results never depend on it; same scope as
+ * chr_set_tiles.  CHR_E_INVAL for any other value. */
+int chr_set_level0_tiles(int on);
+
 /* ---- batches (many fields of uneven sizes in one captured launch) --------- */
 
 /* The per-field workflow of Sec. II (compress with the topology check of

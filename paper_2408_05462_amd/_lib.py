@@ -23,7 +23,7 @@ STATUS_NAMES = {0: "CHR_OK", -1: "CHR_E_INVAL", -2: "CHR_E_ACCURACY", -3: "CHR_E
 EXPORTS = ["chr_last_error", "chr_version", "chr_compress_bound", "chr_compress_workspace", "chr_compress",
            "chr_stream_info", "chr_stream_verify", "chr_reconstruct_workspace", "chr_reconstruct",
            "iso_workspace", "iso_extract", "iso_cases", "chr_mc_table", "chr_range", "chr_prof_enable",
-           "chr_prof_collect", "chr_prof_disable", "chr_set_tiles", "chr_batch_create", "chr_batch_workspace",
+           "chr_prof_collect", "chr_prof_disable", "chr_set_tiles", "chr_set_level0_tiles", "chr_batch_create", "chr_batch_workspace",
            "chr_batch_run", "chr_batch_capture", "chr_batch_replay", "chr_batch_autotune", "chr_batch_config", "chr_batch_set_config",
            "chr_batch_destroy", "chr_server_create", "chr_server_add_stream", "chr_server_submit",
            "chr_server_step", "chr_server_poll", "chr_server_release", "chr_server_cancel", "chr_server_stats_get",
@@ -152,6 +152,8 @@ def load():
     L.chr_prof_disable.restype = C.c_int
     L.chr_set_tiles.argtypes = [C.c_int, C.c_int]
     L.chr_set_tiles.restype = C.c_int
+    L.chr_set_level0_tiles.argtypes = [C.c_int]
+    L.chr_set_level0_tiles.restype = C.c_int
     L.chr_batch_create.argtypes = [C.POINTER(chr_batch_item), C.c_int, C.POINTER(vp)]
     L.chr_batch_create.restype = C.c_int
     L.chr_batch_workspace.argtypes = [vp]

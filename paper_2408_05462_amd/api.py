@@ -264,6 +264,10 @@ def chr_set_tiles(enc_chunks_per_wave=8, dec_chunks_per_wave=16):
     L.check(L.load().chr_set_tiles(int(enc_chunks_per_wave), int(dec_chunks_per_wave)), "chr_set_tiles")
 
 
+def chr_set_level0_tiles(on=True):
+    L.check(L.load().chr_set_level0_tiles(1 if on else 0), "chr_set_level0_tiles")
+
+
 class Batch:
     """Device buffers of a batch plus its chr_batch handle.
 

@@ -20,6 +20,7 @@ thread_local std::string g_err;
 struct Tune {
   int enc_cpw0 = 8;
   int dec_cpw0 = 16;
+  int tile0 = 1;   // level 0 of 64-cell blocks by plane pairs
 } g_tune;
 
 int fail(int code, const std::string &msg) {
@@ -157,9 +158,14 @@ EncLayout enc_layout(EncPlan &P) {
   P.part_per_block = P.part_l2 + encode_l2_groups(P) + 1;
   P.l2fast = encode_l2_fast(P) ? 1 : 0;
   {
+    // workspace sized for the finest level-0 tiling of either level-0 path
     EncPlan q = P;
-    q.cpw0 = 1;  // workspace sized for the finest level-0 tiling
-    const int64_t ppb_max = encode_fine_groups(q) + encode_l1_groups(q) + encode_l2_groups(q) + 1;
+    q.cpw0 = 1;
+    q.tile0 = 0;
+    const int64_t ppb_chunks = encode_fine_groups(q);
+    q.tile0 = 1;
+    const int64_t ppb0 = std::max<int64_t>(ppb_chunks, encode_fine_groups(q));
+    const int64_t ppb_max = ppb0 + encode_l1_groups(q) + encode_l2_groups(q) + 1;
     Lo.part_records = (size_t)(g.nblocks * ppb_max);
   }
   encode_pack_layout(P);
@@ -277,6 +283,9 @@ int enc_prepare(const float *d_field, const int64_t dims[3], double error_bound,
   if (rc) return rc;
   P.cpw0 = cpw0;
   make_l0geo(P.g, P.l0);
+  P.codes = d_codes;
+  P.flags = d_flags;
+  P.tile0 = (g_tune.tile0 && encode_tile0_ok(P)) ? 1 : 0;
   EncLayout Lo = enc_layout(P);
   if (ws_bytes < Lo.total) return fail(CHR_E_NOMEM, "workspace too small: need " + std::to_string(Lo.total));
   if (capacity < P.payload_off) return fail(CHR_E_CAPACITY, "capacity below the header and tables");
@@ -485,6 +494,12 @@ int chr_set_tiles(int enc_chunks_per_wave, int dec_chunks_per_wave) {
     return fail(CHR_E_INVAL, "tiles: compression 1, 2, 4, 8 or 16; reconstruction 8, 16, 32 or 64 chunks per wave");
   g_tune.enc_cpw0 = enc_chunks_per_wave;
   g_tune.dec_cpw0 = dec_chunks_per_wave;
+  return CHR_OK;
+}
+
+int chr_set_level0_tiles(int on) {
+  if (on != 0 && on != 1) return fail(CHR_E_INVAL, "chr_set_level0_tiles: 0 or 1");
+  g_tune.tile0 = on;
   return CHR_OK;
 }
 

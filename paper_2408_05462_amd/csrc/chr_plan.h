@@ -28,6 +28,7 @@ struct EncPlan {
   Geo g;
   L0Geo l0;
   int cpw0;                      // level-0 chunks per wave (tile shape; results do not depend on it)
+  int tile0;                     // level 0 by plane pairs (64-cell blocks; results do not depend on it)
   int64_t slot_base[kMaxLevels];
   uint32_t maxch[kMaxLevels];
   int64_t nslots;
@@ -103,6 +104,8 @@ void prof_mark(const char *kernel, hipStream_t s, int end);
 void launch_encode(const EncPlan &p, int64_t scan_tmp_elems_u4, U4 *scan_tmp, uint64_t *scan_tmp64,
                    hipStream_t s);
 int64_t encode_fine_groups(const EncPlan &p);   // level-0 workgroups per block
+bool encode_tile0_ok(const EncPlan &p);         // level 0 can run by plane pairs
+int64_t encode_tile0_groups(const EncPlan &p);  // plane pairs per block
 int64_t encode_l1_groups(const EncPlan &p);     // level-1 workgroups per block
 int64_t encode_l2_groups(const EncPlan &p);     // level-2 workgroups per block (records reserved)
 bool encode_l2_fast(const EncPlan &p);          // whether level 2 runs in its own wide kernel

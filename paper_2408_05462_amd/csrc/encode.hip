@@ -522,6 +522,379 @@ __global__ __launch_bounds__(kBS) __attribute__((amdgpu_waves_per_eu(DIFF ? 6 : 
   encode_fast<2, AUX, KB, G, DIFF>(P, pack);
 }
 
+// ------------------------------------------------------- level 0 by plane pairs
+//
+// Level 0 of 64-cell blocks (at most 65 points per axis) below a coarser
+// level, one workgroup per (pair of z-planes, block).  The workgroup stages
+// the two planes of the level-1 grid that hold its points' parents in LDS,
+// then predicts and quantizes its points row by row along x (lane = point),
+// so a row's parity pattern, its parent rows and its section offset are
+// wave-uniform, and scatters each code into LDS at its position in the
+// section (the section is lexicographic over the level-0 points of the
+// closed block, so a row's points are consecutive there).  The waves then
+// pack whole 64-point chunks from LDS into their slots.  A chunk that starts
+// in this pair and ends in the next one is finished here: its last points
+// (the first ones of the next even plane) are computed as well and the next
+// workgroup, which computes them again, leaves that chunk alone.
+//
+// Row kinds of a pair (w = 2*w2 even, w + 1 odd; v = row, u = x index):
+//   A: even plane, even rows -- only odd u are level-0 points; two rows per
+//      wave (lanes 0-31: row v, 32-63: row v + 2);
+//   F: every other row (even plane odd rows, all odd-plane rows) -- every u,
+//      u = lane for u < 64;
+//   C: the points u = 64 of the F rows, one row per lane;
+//   S: the points of the chunk tail in the next plane pair.
+
+constexpr int kT0Side = 33;                  // level-1 points per axis of a 64-cell block
+constexpr int kT0Plane = 1152;               // staged plane stride (floats): 33 rows of 33, a byte offset that
+                                             // fits an LDS instruction's immediate
+constexpr int kT0Codes = 7361 + 63;          // most section points of a pair, plus a chunk's tail
+constexpr int kT0Group = 8;                  // rows whose loads a wave issues together
+constexpr uint16_t kT0Exact = 0xffffu;       // LDS code of a point stored exactly (codes are < 2^16 - 1)
+
+// Per-tile state of the finishing steps: LDS codes, the slots' exact values
+// and the wave's counts (wave-uniform: outliers, corrections, non-finite lanes).
+struct T0Ctx {
+  uint32_t jbase;
+  uint16_t *sc;
+  float *exv;          // exact values of the block's level-0 slots, by lane position
+  uint32_t nO, nC;
+  uint64_t nf;
+};
+
+// Ordered key of a binary32 value (as ord_of), in two instructions.
+__device__ __forceinline__ uint32_t t0_ord(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return u ^ ((uint32_t)((int32_t)u >> 31) | 0x80000000u);
+}
+
+// Quantization, the bound and topology checks, the statistics and the code
+// of one point predicted as p, without branches: lanes outside the row hold
+// a copy of a point inside it (same value, same code, same LDS slot), so only
+// the counts are masked (`cmask`: lanes holding a point of the pair that the
+// block owns).  The outlier / correction logic runs on lane masks.  `ci`:
+// the point's LDS code index (points of the previous pair's last chunk map
+// to the spare entry past the codes; their exact values are written by both
+// pairs, identically).  LL: the lossless quantizer.
+template <int KB, bool LL>
+__device__ __forceinline__ void t0_finish(const Geo &gq, const float (&iso)[KB], float x, float p, uint64_t cmask,
+                                          uint32_t j, uint32_t ci, T0Ctx &t, Part &acc) {
+  uint64_t mO;
+  float xc;
+  int32_t q;
+  if (LL) {
+    xc = p;
+    q = 0;
+    mO = __ballot(__float_as_uint(p) != __float_as_uint(x));
+  } else {
+    const float qf = rintf(__fmul_rn(__fsub_rn(x, p), gq.inv));
+    xc = __fadd_rn(p, __fmul_rn(qf, gq.step));
+    q = (int32_t)qf;
+    const uint64_t mq = __ballot(fabsf(qf) <= (float)gq.qmax);
+    const uint64_t mb = __ballot(fabs((double)xc - (double)x) <= gq.e);
+    mO = ~(mq & mb);
+  }
+  const uint64_t mr = __ballot(rank_of<KB>(iso, gq.K, x) != rank_of<KB>(iso, gq.K, xc));
+  const uint64_t mE = mO | mr;                 // outlier, or a correction (side change, not an outlier)
+  const bool E = __builtin_amdgcn_inverse_ballot_w64(mE);
+  const float xr = E ? x : xc;
+  const uint32_t zz = ((uint32_t)q << 1) ^ (uint32_t)(q >> 31);
+  const uint32_t ro = t0_ord(xr), xo = t0_ord(x);
+  acc.rmin = min(acc.rmin, ro); acc.rmax = max(acc.rmax, ro);
+  acc.xmin = min(acc.xmin, xo); acc.xmax = max(acc.xmax, xo);
+  t.nf |= __ballot(!isfinite(x));
+  t.nO += (uint32_t)__popcll(mO & cmask);
+  t.nC += (uint32_t)__popcll(~mO & mr & cmask);
+  t.sc[ci] = E ? kT0Exact : (uint16_t)zz;
+  if (E) t.exv[(size_t)j] = x;    // slot j / 64, lane j % 64
+}
+
+// Average along x of parents a0, a1 (xav false: a0 alone), as a select.
+__device__ __forceinline__ float t0_xavg(float a0, float a1, bool xav) {
+  float m = avg2(a0, a1);
+  hold(m);
+  return xav ? m : a0;
+}
+
+__device__ __forceinline__ float lds_at(const char *base, uint32_t off) {
+  return *reinterpret_cast<const float *>(base + off);
+}
+
+// Multilinear midpoint of a point of the tile from the staged level-1
+// planes, any parity (used for the few C points).
+__device__ __forceinline__ float t0_pred_any(const float *sg, bool zu, uint32_t v, uint32_t u, uint32_t gy,
+                                             uint32_t gx) {
+  const uint32_t yl = v >> 1, xl = u >> 1;
+  const bool yu = (v & 1u) && yl + 1 < gy, xu = (u & 1u) && xl + 1 < gx;
+  const uint32_t yb = yu ? yl + 1 : yl, xb = xu ? xl + 1 : xl;
+  const float *p1 = zu ? sg + kT0Plane : sg;
+  return midpoint8(sg[yl * kT0Side + xl], sg[yl * kT0Side + xb], sg[yb * kT0Side + xl], sg[yb * kT0Side + xb],
+                   p1[yl * kT0Side + xl], p1[yl * kT0Side + xb], p1[yb * kT0Side + xl], p1[yb * kT0Side + xb], zu,
+                   yu, xu);
+}
+
+template <int KB, bool LL>
+__global__ __launch_bounds__(kBS) void k_encode_l0t(EncPlan P) {
+  __shared__ float sg[2 * kT0Plane];
+  __shared__ uint16_t sc[kT0Codes + 1];
+  __shared__ uint32_t pack[kWaves][32];
+  uint32_t w2, b;
+  xcd_remap(w2, b);
+  const Geo &gq = P.g;
+  const BlockPos bp = block_pos(gq, P.l0, b);
+  const Sec s = P.l0.sec[bp.cls];
+  const SecR rc = P.l0.rc[bp.cls];
+  const uint32_t wave = wave_index();
+  const int lane = lane_id();
+  Part acc;
+  part_init(acc);
+  Part *rec = &P.part[(int64_t)b * P.part_per_block + w2];
+  const uint32_t PP = s.Pe + s.Po;
+  const uint32_t J0 = w2 * PP;
+  const int64_t slot0 = P.slot_base[0] + (int64_t)b * P.maxch[0];
+  const uint32_t nch = (s.npts + 63) / 64;
+  if (w2 == 0) {
+    // slots past this block's section (a shorter block than the first)
+    for (uint32_t c = nch + threadIdx.x; c < P.maxch[0]; c += kBS) P.cnt[slot0 + c] = U4{0, 0, 0, 0};
+  }
+  if (J0 >= s.npts) {  // a pair past the block's planes
+    part_store(acc, rec);
+    return;
+  }
+  const uint32_t we = 2 * w2;                  // the even plane (block-relative z)
+  const bool has_odd = we + 1 < s.mz;
+  const uint32_t J1 = has_odd ? J0 + PP : J0 + s.Pe;
+  const uint32_t cfirst = (J0 + 63) / 64, cend = (J1 + 63) / 64;
+  const uint32_t jend = min(cend * 64, s.npts);
+  T0Ctx t;
+  t.jbase = cfirst * 64;
+  t.sc = sc;
+  t.exv = P.exv + slot0 * 64;
+  t.nO = t.nC = 0;
+  t.nf = 0;
+  const uint32_t n1 = (uint32_t)gq.n[1], n2 = (uint32_t)gq.n[2];
+  const uint32_t mx = s.mx, my = s.my, rowE = s.rowE, RP = rowE + mx;
+  // the two level-1 planes (z = (o_z + we) / 2 and the next) of the block
+  const uint32_t h0 = (uint32_t)P.gd[1][0], h1 = (uint32_t)P.gd[1][1], h2 = (uint32_t)P.gd[1][2];
+  const uint32_t zl0 = (bp.o[0] >> 1) + w2, oy1 = bp.o[1] >> 1, ox1 = bp.o[2] >> 1;
+  const uint32_t gy = (bp.hi[1] >> 1) - oy1 + 1, gx = (bp.hi[2] >> 1) - ox1 + 1;
+  const uint32_t np = zl0 + 1 < h0 ? 2u : 1u;
+  {
+    // lanes and rows past the planes load and store a copy of the last one
+    const float *__restrict__ G1 = P.G + P.g_off[1];
+    const uint32_t nrows = np * gy, xl = min((uint32_t)lane, gx - 1);
+    for (uint32_t r0 = wave; r0 < nrows; r0 += 4 * kWaves) {
+      float tv[4];
+      uint32_t so[4];
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const uint32_t r = min(r0 + (uint32_t)u * kWaves, nrows - 1);
+        const uint32_t pz = r >= gy ? 1u : 0u, yy = r - pz * gy;
+        tv[u] = G1[((size_t)(zl0 + pz) * h1 + oy1 + yy) * h2 + ox1 + xl];
+        so[u] = pz * kT0Plane + yy * kT0Side + xl;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; u++) sg[so[u]] = tv[u];
+    }
+  }
+  float iso[KB];
+#pragma unroll
+  for (int jj = 0; jj < KB; jj++) iso[jj] = gq.iso[jj];
+  // the block's slab of the field; the launcher guarantees it spans < 4 GiB
+  const char *__restrict__ xbase = reinterpret_cast<const char *>(P.x + (size_t)bp.o[0] * n1 * n2);
+  const char *__restrict__ sgb = reinterpret_cast<const char *>(sg);
+  const uint32_t ownz = bp.own[0] - bp.o[0], owny = bp.own[1] - bp.o[1], ownx = bp.own[2] - bp.o[2];
+  const bool zu = np == 2;                     // the odd plane has an upper parent plane
+  const uint32_t rowB = n2 * 4u;               // bytes between field rows
+  const uint32_t xe0 = ((we * n1 + bp.o[1]) * n2 + bp.o[2]) * 4u;     // even plane, row 0
+  const uint32_t xo0 = xe0 + n1 * n2 * 4u;                          // odd plane, row 0
+  __syncthreads();
+
+  // ---- A rows: even plane, v = 4a + 2*half, u = 2i + 1 (a row past the
+  // block or a lane past the row works on a copy of a point inside)
+  if (rowE > 0) {
+    const uint32_t half = (uint32_t)lane >> 5, ir = (uint32_t)lane & 31u;
+    const uint32_t i = min(ir, rowE - 1);
+    const uint32_t nA = ((my + 1) / 2 + 1) / 2;
+    const bool xav = i + 1 < gx;
+    const uint64_t lane_in = __ballot(ir < rowE && 2 * ir + 1 < ownx);
+    const uint32_t lx = (2 * i + 1) * 4u, lg = i * 4u;
+    for (uint32_t a0 = wave; a0 < nA; a0 += kT0Group * kWaves) {
+      float xs[kT0Group];
+#pragma unroll
+      for (int u = 0; u < kT0Group; u++) {
+        const uint32_t a = min(a0 + (uint32_t)u * kWaves, nA - 1);
+        const uint32_t vh = 4 * a + 2 * half < my ? 2 * half : 0u;
+        xs[u] = ldf(xbase, xe0 + (4 * a + vh) * rowB + lx);
+      }
+#pragma unroll
+      for (int u = 0; u < kT0Group; u++) {
+        const uint32_t a = a0 + (uint32_t)u * kWaves;
+        if (a >= nA) break;
+        const uint32_t v = 4 * a + 2 * half;
+        const uint32_t vc = v < my ? v : v - 2;
+        const uint32_t ga = (vc >> 1) * (kT0Side * 4u) + lg;
+        const float p = t0_xavg(lds_at(sgb, ga), lds_at(sgb, ga + 4), xav);
+        const uint32_t j = J0 + (vc >> 1) * RP + i;
+        const uint64_t h0 = (4 * a < my && 4 * a < owny) ? 0x00000000ffffffffull : 0ull;
+        const uint64_t h1 = (4 * a + 2 < my && 4 * a + 2 < owny) ? 0xffffffff00000000ull : 0ull;
+        t0_finish<KB, LL>(gq, iso, xs[u], p, we < ownz ? lane_in & (h0 | h1) : 0ull, j,
+                          min(j - t.jbase, (uint32_t)kT0Codes), t, acc);
+      }
+    }
+  }
+  const uint32_t u = min((uint32_t)lane, mx - 1);
+  const uint32_t lx0 = u >> 1;
+  const bool xav = (u & 1u) && lx0 + 1 < gx;
+  const uint64_t lane_in = __ballot((uint32_t)lane < mx && (uint32_t)lane < ownx);
+  const uint32_t lg = lx0 * 4u, lx = u * 4u;
+  constexpr uint32_t kRow = kT0Side * 4u, kPl = kT0Plane * 4u;
+  // ---- B rows: odd rows v = 2f + 1 of the even plane (z even, y odd)
+  {
+    const uint32_t nB = my / 2;
+    for (uint32_t f0 = wave; f0 < nB; f0 += kT0Group * kWaves) {
+      float xs[kT0Group];
+#pragma unroll
+      for (int k = 0; k < kT0Group; k++) {
+        const uint32_t f = min(f0 + (uint32_t)k * kWaves, nB - 1);
+        xs[k] = ldf(xbase, xe0 + (2 * f + 1) * rowB + lx);
+      }
+#pragma unroll
+      for (int k = 0; k < kT0Group; k++) {
+        const uint32_t f = f0 + (uint32_t)k * kWaves;
+        if (f >= nB) break;
+        const bool yu = f + 1 < gy;
+        const uint32_t ga = f * kRow + lg;
+        const float A = t0_xavg(lds_at(sgb, ga), lds_at(sgb, ga + 4), xav);
+        const float B = t0_xavg(lds_at(sgb, ga + kRow), lds_at(sgb, ga + kRow + 4), xav);
+        float pb = avg2(A, B);
+        hold(pb);
+        const float p = yu ? pb : A;
+        const uint32_t jr = J0 + f * RP + rowE;
+        t0_finish<KB, LL>(gq, iso, xs[k], p, (we < ownz && 2 * f + 1 < owny) ? lane_in : 0ull, jr + u,
+                          jr >= t.jbase ? jr - t.jbase + u : min(jr + u - t.jbase, (uint32_t)kT0Codes), t, acc);
+      }
+    }
+  }
+  // ---- C and D rows: the odd plane's rows 2m (y even) and 2m + 1 (y odd)
+  if (has_odd) {
+    const uint32_t nM = (my + 1) / 2;
+    const uint32_t jo = J0 + s.Pe;
+    const bool zown = we + 1 < ownz;
+    for (uint32_t m0 = wave; m0 < nM; m0 += (kT0Group / 2) * kWaves) {
+      float xs[kT0Group];
+#pragma unroll
+      for (int k = 0; k < kT0Group / 2; k++) {
+        const uint32_t m = min(m0 + (uint32_t)k * kWaves, nM - 1);
+        const uint32_t vd = min(2 * m + 1, my - 1);
+        xs[2 * k] = ldf(xbase, xo0 + 2 * m * rowB + lx);
+        xs[2 * k + 1] = ldf(xbase, xo0 + vd * rowB + lx);
+      }
+#pragma unroll
+      for (int k = 0; k < kT0Group / 2; k++) {
+        const uint32_t m = m0 + (uint32_t)k * kWaves;
+        if (m >= nM) break;
+        const uint32_t ga = m * kRow + lg;
+        const float A = t0_xavg(lds_at(sgb, ga), lds_at(sgb, ga + 4), xav);
+        const float Cc = t0_xavg(lds_at(sgb, ga + kPl), lds_at(sgb, ga + kPl + 4), xav);
+        float pc = avg2(A, Cc);
+        hold(pc);
+        const float p = zu ? pc : A;
+        const uint32_t jc = jo + 2 * m * mx;
+        t0_finish<KB, LL>(gq, iso, xs[2 * k], p, (zown && 2 * m < owny) ? lane_in : 0ull, jc + u,
+                          min(jc + u - t.jbase, (uint32_t)kT0Codes), t, acc);
+        if (2 * m + 1 < my) {
+          const bool yu = m + 1 < gy;
+          const float B = t0_xavg(lds_at(sgb, ga + kRow), lds_at(sgb, ga + kRow + 4), xav);
+          const float D = t0_xavg(lds_at(sgb, ga + kPl + kRow), lds_at(sgb, ga + kPl + kRow + 4), xav);
+          float p0 = avg2(A, B), p1 = avg2(Cc, D);
+          hold(p0);
+          hold(p1);
+          p0 = yu ? p0 : A;
+          p1 = yu ? p1 : Cc;
+          float pd = avg2(p0, p1);
+          hold(pd);
+          const float p2 = zu ? pd : p0;
+          t0_finish<KB, LL>(gq, iso, xs[2 * k + 1], p2, (zown && 2 * m + 1 < owny) ? lane_in : 0ull, jc + mx + u,
+                            min(jc + mx + u - t.jbase, (uint32_t)kT0Codes), t, acc);
+        }
+      }
+    }
+  }
+  // ---- column: the points u = 64 of the full rows (65-point rows only)
+  const uint32_t nB = my / 2, nF = nB + (has_odd ? my : 0u);
+  if (mx == 65) {
+    for (uint32_t c0 = wave * 64; c0 < nF; c0 += kWaves * 64) {
+      const uint32_t fr = c0 + (uint32_t)lane, f = min(fr, nF - 1);
+      const bool ev = f < nB;
+      const uint32_t w = ev ? we : we + 1, v = ev ? 2 * f + 1 : f - nB;
+      const float x = ldf(xbase, ((w * n1 + bp.o[1] + v) * n2 + bp.o[2] + 64u) * 4u);
+      const float p = t0_pred_any(sg, (w & 1u) && zu, v, 64u, gy, gx);
+      const uint32_t j = ev ? J0 + (v >> 1) * RP + rowE + 64u : J0 + s.Pe + v * mx + 64u;
+      t0_finish<KB, LL>(gq, iso, x, p, __ballot(fr < nF && w < ownz && v < owny && 64u < ownx), j,
+                        min(j - t.jbase, (uint32_t)kT0Codes), t, acc);
+    }
+  }
+  // ---- the tail of the last chunk (the next planes' first points; more
+  // than one pair when a pair holds fewer than 64 points), parents read from
+  // the level-1 grid in memory; not counted (the next pairs count them)
+  if (jend > J1 && t.jbase < jend && wave == kWaves - 1) {
+    const uint32_t j = min(J1 + (uint32_t)lane, jend - 1);
+    uint32_t w, v, uu;
+    sec_point24(s, rc, j, w, v, uu);
+    const float x = ldf(xbase, ((w * n1 + bp.o[1] + v) * n2 + bp.o[2] + uu) * 4u);
+    const float p = predict(P.G + P.g_off[1], h0, h1, h2, 0, bp.o[0] + w, bp.o[1] + v, bp.o[2] + uu);
+    t0_finish<KB, LL>(gq, iso, x, p, 0ull, j, min(j - t.jbase, (uint32_t)kT0Codes), t, acc);
+  }
+  __syncthreads();
+
+  // ---- pack the pair's chunks from LDS into their slots (exact values are
+  // already in the slots, at their lanes: count word 3 says so)
+  uint32_t *pk = pack[wave];
+  for (uint32_t c = cfirst + wave; c < cend; c += kWaves) {
+    const uint32_t j = c * 64 + (uint32_t)lane;
+    const uint32_t v16 = j < s.npts ? (uint32_t)sc[j - t.jbase] : 0u;
+    const bool E = v16 == kT0Exact;
+    const uint32_t zz = E ? 0u : v16;
+    const int64_t slot = slot0 + c;
+    // the chunk's width: bit length of the largest code, by a search over
+    // ballots (codes are below 2^16)
+    int wb = 0;
+    if (__ballot(zz != 0u)) {
+      uint32_t h = __ballot(zz >= 256u) ? 8u : 0u;
+      if (__ballot(zz >= (16u << h))) h += 4u;
+      if (__ballot(zz >= (4u << h))) h += 2u;
+      if (__ballot(zz >= (2u << h))) h += 1u;
+      wb = (int)h + 1;
+    }
+    const unsigned long long em = __ballot(E);
+    if (lane < 32) pk[lane] = 0u;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (zz) {
+      const uint32_t bit = mul24s((uint32_t)lane, (uint32_t)wb), wi = bit >> 5, off = bit & 31u;
+      __hip_atomic_fetch_or(&pk[wi], zz << off, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+      if (off + (uint32_t)wb > 32u)
+        __hip_atomic_fetch_or(&pk[wi + 1], zz >> (32u - off), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (lane < 2 * wb) P.pay[slot * 32 + lane] = pk[lane];
+    if (lane == 0) {
+      P.cnt[slot] = U4{(uint32_t)wb, em ? 1u : 0u, (uint32_t)__popcll(em), em ? 1u : 0u};
+      if (em) P.emask[slot] = em;
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  // the wave's counts join the lane records (once per wave)
+  if (lane == 0) {
+    acc.nO = t.nO;
+    acc.nC = t.nC;
+    acc.nonfinite = t.nf != 0 ? 1u : 0u;
+  }
+  part_store(acc, rec);
+}
+
 // Differentiated error control: block b is active when the input on its
 // closed extent crosses a candidate isovalue (min < k <= max).  Workgroup
 // (s, b) reduces planes s, s + kActSplit, ... of block b's extent (each
@@ -741,7 +1114,14 @@ __global__ __launch_bounds__(kBS) void k_pack(EncPlan P) {
     const int c = __builtin_ctzll(mx);
     mx &= mx - 1;
     const uint32_t nx = __shfl(cc.z, c, kWave), pxc = __shfl(px, c, kWave);
-    if ((uint32_t)lane < nx) xo[pxc + lane] = exv[(slot0 + c) * 64 + lane];
+    if (__shfl(cc.w, c, kWave)) {
+      // stored at their lanes: lane i's value is the popcount(mask below i)-th
+      const unsigned long long emc = ((unsigned long long)(uint32_t)__shfl((int)(uint32_t)(em >> 32), c, kWave) << 32) |
+                                     (uint32_t)__shfl((int)(uint32_t)em, c, kWave);
+      if ((emc >> lane) & 1ull) xo[pxc + lanes_below(emc)] = exv[(slot0 + c) * 64 + lane];
+    } else if ((uint32_t)lane < nx) {
+      xo[pxc + lane] = exv[(slot0 + c) * 64 + lane];
+    }
   }
 }
 
@@ -936,7 +1316,10 @@ __device__ void header_words(const EncPlan &P, uint64_t total, bool fits, uint32
 
 }  // namespace
 
-int64_t encode_fine_groups(const EncPlan &p) { return ceil_div(p.maxch[0], (int64_t)kWaves * p.cpw0); }
+int64_t encode_fine_groups(const EncPlan &p) {
+  return p.tile0 ? encode_tile0_groups(p) : ceil_div(p.maxch[0], (int64_t)kWaves * p.cpw0);
+}
+int64_t encode_tile0_groups(const EncPlan &p) { return (p.g.B + 2) / 2; }
 int64_t encode_l1_groups(const EncPlan &p) {
   return p.g.nL >= 2 ? ceil_div(p.maxch[1] > 0 ? p.maxch[1] : 1, (int64_t)kChunksPerWG) : 0;
 }
@@ -952,6 +1335,12 @@ static bool slab32(const Geo &g) {
 }
 
 bool encode_l2_fast(const EncPlan &p) { return p.g.nL >= 4 && slab32(p.g) && p.l0.small; }
+
+// Level 0 by plane pairs: 64-cell blocks below a coarser level, one
+// quantizer, no per-point outputs, 32-bit offsets within a block's slab.
+bool encode_tile0_ok(const EncPlan &p) {
+  return p.g.B == 64 && p.g.nL >= 2 && !p.g.diff && !p.codes && !p.flags && slab32(p.g) && p.l0.small;
+}
 
 void encode_pack_layout(EncPlan &p) {
   const int L = p.g.nL - 1;
@@ -996,7 +1385,10 @@ void launch_encode_levels(const EncPlan &p, hipStream_t s) {
   if (gx > 0) {
     prof_mark("k_encode_fine", s, 0);
     const dim3 grid0((unsigned)gx, (unsigned)g.nblocks);
-    if (L >= 1 && fast && !p.codes && !p.flags) {
+    if (p.tile0) {
+      if (g.lossless) k_encode_l0t<KB, true><<<grid0, dim3(kBS), 0, s>>>(p);
+      else k_encode_l0t<KB, false><<<grid0, dim3(kBS), 0, s>>>(p);
+    } else if (L >= 1 && fast && !p.codes && !p.flags) {
       if (p.cpw0 % 4 == 0) k_encode_l0<false, KB, 4, DIFF><<<grid0, dim3(kBS), 0, s>>>(p);
       else if (p.cpw0 % 2 == 0) k_encode_l0<false, KB, 2, DIFF><<<grid0, dim3(kBS), 0, s>>>(p);
       else k_encode_l0<false, KB, 1, DIFF><<<grid0, dim3(kBS), 0, s>>>(p);
