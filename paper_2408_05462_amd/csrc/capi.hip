@@ -340,6 +340,7 @@ int dec_prepare(const Geo &g, uint64_t payload_off, int level, const void *d_str
   D.g = g;
   make_l0geo(D.g, D.l0);
   D.cpw0 = cpw0;
+  D.tile0 = g_tune.tile0;
   D.lo = level;
   const int L = g.nL - 1;
   for (int l = 0; l < kMaxLevels; l++)

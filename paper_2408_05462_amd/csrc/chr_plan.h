@@ -64,6 +64,7 @@ struct DecPlan {
   Geo g;
   L0Geo l0;
   int cpw0;                      // level-0 chunks per wave: 8, 16, 32 or 64
+  int tile0;                     // level 0 of 64-cell blocks by plane pairs (results do not depend on it)
   int lo;
   int64_t gd[kMaxLevels][3];
   float *gp[kMaxLevels];         // compact grid of level l (gp[lo] = output when lo >= 1)

@@ -503,6 +503,358 @@ __device__ __forceinline__ void decode_fast(const DecPlan &D) {
   }
 }
 
+// ------------------------------------------------------- level 0 by plane pairs
+//
+// Reconstruction of level 0 of 64-cell blocks (at most 65 points per axis)
+// below a coarser level, one workgroup per (pair of z-planes, block) -- the
+// compression kernel's tiling.  The workgroup stages the two level-1 planes
+// that hold the pair's parents in LDS, reads the headers, exact masks and
+// exact-value offsets of the chunks that overlap the pair's part of the
+// section, unpacks their codes into LDS at their section positions (payload
+// words, masks and exact values are all loaded before any store), and then
+// writes the pair's field rows along x (lane = point): level-0 points from
+// their prediction and code, the even points of even rows of the even plane
+// from level 1.  Rows and points the block does not own are not written
+// (in a restricted reconstruction the whole closed extent is).
+
+constexpr int kD0Side = 33;                  // level-1 points per axis of a 64-cell block
+constexpr int kD0Plane = 1152;               // staged plane stride (floats; fits an LDS immediate offset)
+constexpr int kD0Codes = 7361;               // most section points of a pair
+constexpr int kD0Chunks = 118;               // chunks that overlap a pair's part of the section
+constexpr int kD0Xcap = 1024;                // exact values of a pair staged in LDS
+constexpr int kD0Group = 16;                 // chunks (unpack) whose loads a wave issues together
+constexpr int kD0Rows = 8;                   // rows a wave reconstructs before storing any
+constexpr uint16_t kD0Exact = 0xffffu;       // LDS code of a point stored exactly
+
+struct D0Ctx {
+  const uint16_t *sc;
+  const uint32_t *cxo;
+  const unsigned long long *cem;
+  const float *xl;
+  const uint8_t *xs;       // exact values of the section in the stream
+  uint32_t J0, c0, xo0;
+  float step;
+};
+
+// Value of a level-0 point predicted as p whose LDS code is zz (not an
+// exact point).
+__device__ __forceinline__ float d0_quant(const D0Ctx &t, uint32_t zz, float p) {
+  const int32_t q = (int32_t)(zz >> 1) ^ -(int32_t)(zz & 1u);
+  return __fadd_rn(p, __fmul_rn((float)q, t.step));
+}
+
+// The exact value of the level-0 point at section index j: the (rank within
+// its chunk)-th exact value of the chunk.
+__device__ __forceinline__ float d0_exact(const D0Ctx &t, uint32_t j) {
+  const uint32_t k = (j >> 6) - t.c0;
+  const unsigned long long em = t.cem[k];
+  const uint32_t ix = t.cxo[k] + (uint32_t)__popcll(em & ((1ull << (j & 63u)) - 1ull));
+  return ix - t.xo0 < (uint32_t)kD0Xcap ? t.xl[ix - t.xo0] : __uint_as_float(ld32(t.xs + 4 * (uint64_t)ix));
+}
+
+__device__ __forceinline__ float d0_xavg(float a0, float a1, bool xav) {
+  float m = avg2(a0, a1);
+  hold(m);
+  return xav ? m : a0;
+}
+
+__device__ __forceinline__ float d0_lds(const char *base, uint32_t off) {
+  return *reinterpret_cast<const float *>(base + off);
+}
+
+__global__ __launch_bounds__(kBS) void k_decode_l0t(DecPlan D) {
+  __shared__ float sg[2 * kD0Plane];
+  __shared__ uint16_t sc[kD0Codes + 1];
+  __shared__ uint32_t cwo[kD0Chunks], cxo[kD0Chunks], cwb[kD0Chunks];
+  __shared__ unsigned long long cem[kD0Chunks];
+  __shared__ float xl[kD0Xcap];
+  __shared__ uint32_t sbad[kWaves];
+  uint32_t w2, b;
+  xcd_remap(w2, b);
+  if (!block_needed(D, b)) return;
+  const Geo &g = D.g;
+  const BlockPos bp = block_pos(g, D.l0, b);
+  const Sec s = D.l0.sec[bp.cls];
+  const uint32_t PP = s.Pe + s.Po, J0 = w2 * PP;
+  if (J0 >= s.npts) return;
+  const uint32_t we = 2 * w2;
+  const bool all = D.prune != 0;
+  const uint32_t ownz = bp.own[0] - bp.o[0], owny = bp.own[1] - bp.o[1], ownx = bp.own[2] - bp.o[2];
+  if (!all && we >= ownz) return;              // neither plane of the pair is the block's
+  const bool has_odd = we + 1 < s.mz;
+  const uint32_t J1 = has_odd ? J0 + PP : J0 + s.Pe;
+  const uint32_t c0 = J0 >> 6, c1 = (J1 + 63) >> 6, ncw = c1 - c0;
+  const SecView v = open_section(D, b, 0, s.npts);
+  if (!v.ok) {
+    if (threadIdx.x == 0) set_status(D, -4);
+    return;
+  }
+  const uint32_t wave = wave_index();
+  const int lane = lane_id();
+  const uint32_t n1 = (uint32_t)g.n[1], n2 = (uint32_t)g.n[2];
+  const uint32_t mx = s.mx, my = s.my, rowE = s.rowE, RP = rowE + mx;
+  const uint32_t h0 = (uint32_t)D.gd[1][0], h1 = (uint32_t)D.gd[1][1], h2 = (uint32_t)D.gd[1][2];
+  const uint32_t zl0 = (bp.o[0] >> 1) + w2, oy1 = bp.o[1] >> 1, ox1 = bp.o[2] >> 1;
+  const uint32_t gy = (bp.hi[1] >> 1) - oy1 + 1, gx = (bp.hi[2] >> 1) - ox1 + 1;
+  const uint32_t np = zl0 + 1 < h0 ? 2u : 1u;
+  {
+    // the level-1 planes; lanes and rows past them load and store a copy of
+    // the last one
+    const float *__restrict__ G1 = D.gp[1];
+    const uint32_t nrows = np * gy, xl1 = min((uint32_t)lane, gx - 1);
+    // at most 2 * 33 rows: a wave's (at most 17) loads are all issued first
+    constexpr int kR = (2 * kD0Side + kWaves - 1) / kWaves;
+    float tv[kR];
+    uint32_t so[kR];
+#pragma unroll
+    for (int u = 0; u < kR; u++) {
+      const uint32_t r = min(wave + (uint32_t)u * kWaves, nrows - 1);
+      const uint32_t pz = r >= gy ? 1u : 0u, yy = r - pz * gy;
+      tv[u] = G1[((size_t)(zl0 + pz) * h1 + oy1 + yy) * h2 + ox1 + xl1];
+      so[u] = pz * kD0Plane + yy * kD0Side + xl1;
+    }
+#pragma unroll
+    for (int u = 0; u < kR; u++) sg[so[u]] = tv[u];
+  }
+  {
+    // chunk headers of the (at most three) 64-chunk tiles of the range:
+    // widths, payload offsets, exact masks and exact-value offsets, with the
+    // structural checks of every reader of a section
+    const uint32_t t = (c0 >> 6) + wave;
+    uint32_t bad = 0u;
+    if (t <= ((c1 - 1) >> 6)) {
+      const uint32_t c = t * 64 + (uint32_t)lane;
+      const uint8_t *tt = v.p + 16 + 12 * (uint64_t)t;
+      const uint32_t tw = ld32(tt), te = ld32(tt + 4), tx = ld32(tt + 8);
+      const uint32_t hb = c < v.nch ? v.p[v.A + c] : 0u;
+      const uint32_t w = hb & 31u, he = hb >> 7;
+      const uint32_t wo = tw + wave_excl_sum(w), eo = te + wave_excl_sum(he);
+      const bool badl = (w > (uint32_t)kMaxW) || (hb & 0x60u) || (wo + w > v.W) || (he && eo >= v.NE);
+      const unsigned long long em = (he && !badl) ? ld64(v.p + v.Moff + 8 * (uint64_t)eo) : 0ull;
+      const uint32_t pc = (uint32_t)__popcll(em);
+      const uint32_t xo = tx + wave_excl_sum(pc);
+      bad = __ballot(badl || xo + pc > v.NX) != 0ull ? 1u : 0u;
+      if (c >= c0 && c < c1) {
+        cwb[c - c0] = w;
+        cwo[c - c0] = wo;
+        cxo[c - c0] = xo;
+        cem[c - c0] = em;
+      }
+    }
+    if (lane == 0) sbad[wave] = bad;
+  }
+  __syncthreads();
+  if (sbad[0] | sbad[1] | sbad[2] | sbad[3]) {
+    if (threadIdx.x == 0) set_status(D, -4);
+    return;
+  }
+  const uint32_t xo0 = cxo[0];
+  const char *__restrict__ payb = reinterpret_cast<const char *>(v.p + v.Poff);
+  const char *__restrict__ exb = reinterpret_cast<const char *>(v.p + v.Xoff);
+  // ---- stage the range's exact values (one coalesced pass) and unpack the
+  // codes of the pair's points; each wave issues the payload loads of
+  // kD0Group chunks before using any
+  {
+    const uint32_t nx = min(cxo[ncw - 1] + (uint32_t)__popcll(cem[ncw - 1]) - xo0, (uint32_t)kD0Xcap);
+    for (uint32_t i = threadIdx.x; i < nx; i += kBS) xl[i] = __uint_as_float(ldu(exb, 4u * (xo0 + i)));
+  }
+  for (uint32_t k0 = wave; k0 < ncw; k0 += kD0Group * kWaves) {
+    uint32_t lo[kD0Group], hi[kD0Group];
+#pragma unroll
+    for (int u = 0; u < kD0Group; u++) {
+      const uint32_t k = min(k0 + (uint32_t)u * kWaves, ncw - 1);
+      const uint32_t w = __builtin_amdgcn_readfirstlane(cwb[k]);
+      const uint32_t wo = __builtin_amdgcn_readfirstlane(cwo[k]);
+      const uint32_t bit = mul24s((uint32_t)lane, w), wi = bit >> 5;
+      lo[u] = hi[u] = 0u;
+      if (w) {
+        lo[u] = ldu(payb, 8u * wo + 4u * wi);
+        hi[u] = ldu(payb, 8u * wo + 4u * min(wi + 1, 2 * w - 1));
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kD0Group; u++) {
+      const uint32_t k = k0 + (uint32_t)u * kWaves;
+      if (k >= ncw) break;
+      const uint32_t w = __builtin_amdgcn_readfirstlane(cwb[k]);
+      const uint32_t off = mul24s((uint32_t)lane, w) & 31u;
+      uint32_t zz = off + w > 32u ? (lo[u] >> off) | (hi[u] << (32u - off)) : lo[u] >> off;
+      zz = w ? zz & ((1u << w) - 1u) : 0u;
+      const bool E = (cem[k] >> lane) & 1ull;
+      const uint32_t j = (c0 + k) * 64 + (uint32_t)lane;
+      if (j >= J0 && j < J1) sc[j - J0] = E ? kD0Exact : (uint16_t)zz;
+    }
+  }
+  __syncthreads();
+
+  D0Ctx t;
+  t.sc = sc;
+  t.cxo = cxo;
+  t.cem = cem;
+  t.xl = xl;
+  t.xs = v.p + v.Xoff;
+  t.J0 = J0;
+  t.c0 = c0;
+  t.xo0 = xo0;
+  t.step = g.step;
+  const char *__restrict__ sgb = reinterpret_cast<const char *>(sg);
+  char *__restrict__ obase = reinterpret_cast<char *>(D.out + (size_t)bp.o[0] * n1 * n2);
+  const bool zu = np == 2;
+  const uint32_t rowB = n2 * 4u;
+  const uint32_t xe0 = ((we * n1 + bp.o[1]) * n2 + bp.o[2]) * 4u;     // even plane, row 0
+  const uint32_t xo0b = xe0 + n1 * n2 * 4u;                         // odd plane, row 0
+  const uint32_t u = min((uint32_t)lane, mx - 1);                   // lanes past the row copy its last point
+  const uint32_t lx0 = u >> 1;
+  const bool xav = (u & 1u) && lx0 + 1 < gx;
+  const uint32_t lg = lx0 * 4u, lx = u * 4u;
+  constexpr uint32_t kRow = kD0Side * 4u, kPl = kD0Plane * 4u;
+  const bool odd_u = (u & 1u) != 0;
+  const uint32_t rown = all ? my : min(my, owny);                   // rows written
+
+  // ---- even plane: rows v = 2a (odd u from codes, even u from level 1) and
+  // v = 2a + 1 (every u from codes).  A wave reads the parents and codes of
+  // kD0Rows rows, computes them, fixes any exact points, then stores.  Rows
+  // past the block and lanes past a row work on a point inside the pair's
+  // range (section indices clamped to [J0, J1)) and are not stored.
+  const uint32_t jlast = J1 - 1;
+  const uint32_t lxe = min(lx0, rowE > 0 ? rowE - 1 : 0u);   // an odd point of the row for even u
+  // LDS code byte offsets: per lane, plus a uniform row part, clamped to the
+  // pair's last point
+  const char *__restrict__ scb = reinterpret_cast<const char *>(sc);
+  const uint32_t cmax = 2 * (jlast - J0), ceb = 2 * lxe, cob = 2 * (rowE + u), cub = 2 * u;
+  for (uint32_t a0 = wave; 2 * a0 < rown; a0 += kWaves * (kD0Rows / 2)) {
+    float A0[kD0Rows / 2], A1[kD0Rows / 2], B0[kD0Rows / 2], B1[kD0Rows / 2];
+    uint32_t je[kD0Rows / 2], jo[kD0Rows / 2], ze[kD0Rows / 2], zo[kD0Rows / 2];
+#pragma unroll
+    for (int k = 0; k < kD0Rows / 2; k++) {
+      const uint32_t a = a0 + (uint32_t)k * kWaves;   // the row pair 2a, 2a + 1
+      const uint32_t ga = min(a, gy - 1) * kRow + lg;
+      A0[k] = d0_lds(sgb, ga);
+      A1[k] = d0_lds(sgb, ga + 4);
+      B0[k] = d0_lds(sgb, ga + kRow);
+      B1[k] = d0_lds(sgb, ga + kRow + 4);
+      je[k] = min(2 * a * RP + ceb, cmax);
+      jo[k] = min(2 * a * RP + cob, cmax);
+      ze[k] = *reinterpret_cast<const uint16_t *>(scb + je[k]);
+      zo[k] = *reinterpret_cast<const uint16_t *>(scb + jo[k]);
+    }
+    float rv[kD0Rows];
+    uint64_t anyE = 0;
+#pragma unroll
+    for (int k = 0; k < kD0Rows / 2; k++) {
+      const uint32_t a = a0 + (uint32_t)k * kWaves;
+      // v = 2a: a level-1 point (even u) or an x midpoint (odd u)
+      const float A = d0_xavg(A0[k], A1[k], xav);
+      rv[2 * k] = odd_u ? d0_quant(t, ze[k], A) : A0[k];
+      // v = 2a + 1: midpoints along y of the x-averaged rows a, a + 1
+      const float B = d0_xavg(B0[k], B1[k], xav);
+      float pb = avg2(A, B);
+      hold(pb);
+      rv[2 * k + 1] = d0_quant(t, zo[k], a + 1 < gy ? pb : A);
+      anyE |= __ballot((odd_u && ze[k] == kD0Exact) || zo[k] == kD0Exact);
+    }
+    if (anyE) {
+#pragma unroll
+      for (int k = 0; k < kD0Rows / 2; k++) {
+        if (odd_u && ze[k] == kD0Exact) rv[2 * k] = d0_exact(t, J0 + je[k] / 2);
+        if (zo[k] == kD0Exact) rv[2 * k + 1] = d0_exact(t, J0 + jo[k] / 2);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kD0Rows / 2; k++) {
+      const uint32_t a = a0 + (uint32_t)k * kWaves;
+      if (2 * a < rown) stf(obase, xe0 + 2 * a * rowB + lx, rv[2 * k]);
+      if (2 * a + 1 < rown) stf(obase, xe0 + (2 * a + 1) * rowB + lx, rv[2 * k + 1]);
+    }
+  }
+  // ---- odd plane: rows 2m (y even) and 2m + 1 (y odd), every u from codes
+  if (has_odd && (all || we + 1 < ownz)) {
+    for (uint32_t m0 = wave; 2 * m0 < rown; m0 += kWaves * (kD0Rows / 2)) {
+      float A0[kD0Rows / 2], A1[kD0Rows / 2], B0[kD0Rows / 2], B1[kD0Rows / 2];
+      float C0[kD0Rows / 2], C1[kD0Rows / 2], E0[kD0Rows / 2], E1[kD0Rows / 2];
+      uint32_t jc[kD0Rows / 2], jd[kD0Rows / 2], zc[kD0Rows / 2], zd[kD0Rows / 2];
+#pragma unroll
+      for (int k = 0; k < kD0Rows / 2; k++) {
+        const uint32_t m = m0 + (uint32_t)k * kWaves;
+        const uint32_t ga = min(m, gy - 1) * kRow + lg;
+        A0[k] = d0_lds(sgb, ga);
+        A1[k] = d0_lds(sgb, ga + 4);
+        C0[k] = d0_lds(sgb, ga + kPl);
+        C1[k] = d0_lds(sgb, ga + kPl + 4);
+        B0[k] = d0_lds(sgb, ga + kRow);
+        B1[k] = d0_lds(sgb, ga + kRow + 4);
+        E0[k] = d0_lds(sgb, ga + kPl + kRow);
+        E1[k] = d0_lds(sgb, ga + kPl + kRow + 4);
+        jc[k] = min(2 * (s.Pe + 2 * m * mx) + cub, cmax);
+        jd[k] = min(2 * (s.Pe + (2 * m + 1) * mx) + cub, cmax);
+        zc[k] = *reinterpret_cast<const uint16_t *>(scb + jc[k]);
+        zd[k] = *reinterpret_cast<const uint16_t *>(scb + jd[k]);
+      }
+      float rv[kD0Rows];
+      uint64_t anyE = 0;
+#pragma unroll
+      for (int k = 0; k < kD0Rows / 2; k++) {
+        const uint32_t m = m0 + (uint32_t)k * kWaves;
+        const float A = d0_xavg(A0[k], A1[k], xav), Cc = d0_xavg(C0[k], C1[k], xav);
+        float pc = avg2(A, Cc);
+        hold(pc);
+        rv[2 * k] = d0_quant(t, zc[k], zu ? pc : A);
+        const bool yu = m + 1 < gy;
+        const float B = d0_xavg(B0[k], B1[k], xav), Dd = d0_xavg(E0[k], E1[k], xav);
+        float p0 = avg2(A, B), p1 = avg2(Cc, Dd);
+        hold(p0);
+        hold(p1);
+        p0 = yu ? p0 : A;
+        p1 = yu ? p1 : Cc;
+        float pd = avg2(p0, p1);
+        hold(pd);
+        rv[2 * k + 1] = d0_quant(t, zd[k], zu ? pd : p0);
+        anyE |= __ballot(zc[k] == kD0Exact || zd[k] == kD0Exact);
+      }
+      if (anyE) {
+#pragma unroll
+        for (int k = 0; k < kD0Rows / 2; k++) {
+          if (zc[k] == kD0Exact) rv[2 * k] = d0_exact(t, J0 + jc[k] / 2);
+          if (zd[k] == kD0Exact) rv[2 * k + 1] = d0_exact(t, J0 + jd[k] / 2);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kD0Rows / 2; k++) {
+        const uint32_t m = m0 + (uint32_t)k * kWaves;
+        if (2 * m < rown) stf(obase, xo0b + 2 * m * rowB + lx, rv[2 * k]);
+        if (2 * m + 1 < rown) stf(obase, xo0b + (2 * m + 1) * rowB + lx, rv[2 * k + 1]);
+      }
+    }
+  }
+  // ---- the points u = 64 (65-point rows), one row per lane, when the block
+  // owns them (the last block along x) or writes its closed extent
+  if (mx == 65 && (all || 64u < ownx)) {
+    const uint32_t nrow = (has_odd && (all || we + 1 < ownz) ? 2u : 1u) * rown;
+    for (uint32_t r0 = wave * 64; r0 < nrow; r0 += kWaves * 64) {
+      const uint32_t rr = r0 + (uint32_t)lane;
+      const uint32_t rc = min(rr, nrow - 1);
+      const uint32_t w = rc >= rown ? 1u : 0u, vv = rc - w * rown;   // plane (0 even, 1 odd), row
+      const uint32_t yl = vv >> 1;
+      const bool yu = (vv & 1u) && yl + 1 < gy;
+      const uint32_t yb = yu ? yl + 1 : yl;
+      const float a0 = sg[yl * kD0Side + 32], b0 = sg[yb * kD0Side + 32];
+      const float c0v = sg[kD0Plane + yl * kD0Side + 32], d0v = sg[kD0Plane + yb * kD0Side + 32];
+      float r;
+      if (w == 0 && !(vv & 1u)) {
+        r = a0;  // a level-1 point
+      } else {
+        const float p0 = yu ? avg2(a0, b0) : a0;
+        const float p1 = yu ? avg2(c0v, d0v) : c0v;
+        const float p = (w == 1 && zu) ? avg2(p0, p1) : p0;
+        const uint32_t j = min(w == 0 ? J0 + (vv >> 1) * RP + rowE + 64u : J0 + s.Pe + vv * mx + 64u, jlast);
+        const uint32_t zz = sc[j - J0];
+        r = zz == kD0Exact ? d0_exact(t, j) : d0_quant(t, zz, p);
+      }
+      if (rr < nrow) stf(obase, (w == 0 ? xe0 : xo0b) + vv * rowB + 256u, r);
+    }
+  }
+}
+
 template <bool DIFF>
 __global__ __launch_bounds__(kBS) void k_decode_l0(DecPlan D) { decode_fast<0, DIFF>(D); }
 template <bool DIFF>
@@ -597,7 +949,9 @@ void launch_decode(const DecPlan &p, hipStream_t s) {
     const Sec s0 = sec_geom(o, hi, 0, L);
     const int64_t ntile = ceil_div(ceil_div(s0.npts, 64), 64);
     prof_mark("k_decode_fine", s, 0);
-    if (L >= 1 && slab32 && p.l0.small) {
+    if (p.tile0 && g.B == 64 && L >= 1 && slab32 && p.l0.small && !g.diff && !g.lossless) {
+      k_decode_l0t<<<dim3((unsigned)((g.B + 2) / 2), (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
+    } else if (L >= 1 && slab32 && p.l0.small) {
       const int64_t nch0 = ceil_div(s0.npts, 64);
       const int64_t gx0 = ceil_div(nch0 > 0 ? nch0 : 1, (int64_t)kWaves * p.cpw0);
       if (g.diff) k_decode_l0<true><<<dim3((unsigned)gx0, (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);

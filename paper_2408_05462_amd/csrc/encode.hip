@@ -683,19 +683,19 @@ __global__ __launch_bounds__(kBS) void k_encode_l0t(EncPlan P) {
     // lanes and rows past the planes load and store a copy of the last one
     const float *__restrict__ G1 = P.G + P.g_off[1];
     const uint32_t nrows = np * gy, xl = min((uint32_t)lane, gx - 1);
-    for (uint32_t r0 = wave; r0 < nrows; r0 += 4 * kWaves) {
-      float tv[4];
-      uint32_t so[4];
+    // at most 2 * 33 rows: a wave's (at most 17) loads are all issued first
+    constexpr int kR = (2 * kT0Side + kWaves - 1) / kWaves;
+    float tv[kR];
+    uint32_t so[kR];
 #pragma unroll
-      for (int u = 0; u < 4; u++) {
-        const uint32_t r = min(r0 + (uint32_t)u * kWaves, nrows - 1);
-        const uint32_t pz = r >= gy ? 1u : 0u, yy = r - pz * gy;
-        tv[u] = G1[((size_t)(zl0 + pz) * h1 + oy1 + yy) * h2 + ox1 + xl];
-        so[u] = pz * kT0Plane + yy * kT0Side + xl;
-      }
-#pragma unroll
-      for (int u = 0; u < 4; u++) sg[so[u]] = tv[u];
+    for (int u = 0; u < kR; u++) {
+      const uint32_t r = min(wave + (uint32_t)u * kWaves, nrows - 1);
+      const uint32_t pz = r >= gy ? 1u : 0u, yy = r - pz * gy;
+      tv[u] = G1[((size_t)(zl0 + pz) * h1 + oy1 + yy) * h2 + ox1 + xl];
+      so[u] = pz * kT0Plane + yy * kT0Side + xl;
     }
+#pragma unroll
+    for (int u = 0; u < kR; u++) sg[so[u]] = tv[u];
   }
   float iso[KB];
 #pragma unroll

@@ -3,7 +3,9 @@ the oracle, through the C ABI: stream bytes identical to the oracle's and to
 the one-wave-per-chunk kernels' on fields whose blocks are cut short on every
 axis (1, 2, ... points left), one block, one plane, a lossless stream (every
 point stored exactly), forced outliers (small qmax) and 16 candidates; the
-reconstruction from either stream is the oracle's bit for bit.
+level-0 reconstruction by either decoder is the oracle's bit for bit, also
+from the oracle's own stream; a reconstruction restricted to an isovalue
+range is the same by either decoder and keeps every cell's case.
 """
 import numpy as np
 import pytest
@@ -71,5 +73,21 @@ def test_plane_pair_kernels_match_oracle(case):
     assert ct.result == cc.result
     assert ct.result["n_outlier"] == int((ref["flags"] & 1).sum())
     assert ct.result["n_corrected"] == int((ref["flags"] >> 1).sum())
-    y = api.reconstruct(ct, 0).cpu().numpy()
-    assert np.array_equal(y.view(np.uint32), ref["xr"].view(np.uint32))
+    oc = api.Compressed(stream=torch.from_numpy(ref["stream"]).to(DEV),
+                        info=api.chr_stream_info(bytes(ref["stream"])), header=b"", result={})
+    try:
+        for on in (True, False):
+            api.chr_set_level0_tiles(on)
+            for c in (ct, oc):
+                y = api.reconstruct(c, 0).cpu().numpy()
+                assert np.array_equal(y.view(np.uint32), ref["xr"].view(np.uint32)), on
+        if isos:
+            k = float(isos[0])
+            rt = []
+            for on in (True, False):
+                api.chr_set_level0_tiles(on)
+                rt.append(api.reconstruct_range(ct, k, k))
+            assert torch.equal(rt[0].view(torch.int32), rt[1].view(torch.int32))
+            assert torch.equal(api.cases(rt[0], k), api.cases(x, k))
+    finally:
+        api.chr_set_level0_tiles(True)
