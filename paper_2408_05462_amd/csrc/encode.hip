@@ -603,10 +603,14 @@ __device__ __forceinline__ void t0_finish(const Geo &gq, const float (&iso)[KB],
   acc.rmin = min(acc.rmin, ro); acc.rmax = max(acc.rmax, ro);
   acc.xmin = min(acc.xmin, xo); acc.xmax = max(acc.xmax, xo);
   t.nf |= __ballot(!isfinite(x));
-  t.nO += (uint32_t)__popcll(mO & cmask);
-  t.nC += (uint32_t)__popcll(~mO & mr & cmask);
   t.sc[ci] = E ? kT0Exact : (uint16_t)zz;
-  if (E) t.exv[(size_t)j] = x;    // slot j / 64, lane j % 64
+  if (mE) {
+    // a row with exact points (rare): the counts, and the exact values into
+    // their slots (slot j / 64, lane j % 64)
+    t.nO += (uint32_t)__popcll(mO & cmask);
+    t.nC += (uint32_t)__popcll(~mO & mr & cmask);
+    if (E) t.exv[(size_t)j] = x;
+  }
 }
 
 // Average along x of parents a0, a1 (xav false: a0 alone), as a select.
@@ -708,121 +712,121 @@ __global__ __launch_bounds__(kBS) void k_encode_l0t(EncPlan P) {
   const uint32_t rowB = n2 * 4u;               // bytes between field rows
   const uint32_t xe0 = ((we * n1 + bp.o[1]) * n2 + bp.o[2]) * 4u;     // even plane, row 0
   const uint32_t xo0 = xe0 + n1 * n2 * 4u;                          // odd plane, row 0
-  __syncthreads();
-
-  // ---- A rows: even plane, v = 4a + 2*half, u = 2i + 1 (a row past the
-  // block or a lane past the row works on a copy of a point inside)
-  if (rowE > 0) {
-    const uint32_t half = (uint32_t)lane >> 5, ir = (uint32_t)lane & 31u;
-    const uint32_t i = min(ir, rowE - 1);
-    const uint32_t nA = ((my + 1) / 2 + 1) / 2;
-    const bool xav = i + 1 < gx;
-    const uint64_t lane_in = __ballot(ir < rowE && 2 * ir + 1 < ownx);
-    const uint32_t lx = (2 * i + 1) * 4u, lg = i * 4u;
-    for (uint32_t a0 = wave; a0 < nA; a0 += kT0Group * kWaves) {
-      float xs[kT0Group];
+  // codes past the section in its last chunk read as 0 when packing
+  if (cend > cfirst && cend * 64 > s.npts && threadIdx.x < cend * 64 - s.npts) sc[s.npts - t.jbase + threadIdx.x] = 0;
+  // Every x row a wave needs is loaded before the barrier (at most 5 A, 8 B
+  // and 9 C/D row pairs per wave for 65-point blocks): A rows v = 4a +
+  // 2*half (odd u = 2i + 1), B rows v = 2f + 1, C/D rows 2m and 2m + 1.  A
+  // row past the block or a lane past a row loads a copy of a point inside.
+  constexpr int kA = 5, kB = 8, kM = 9;
+  const uint32_t half = (uint32_t)lane >> 5, ir = (uint32_t)lane & 31u;
+  const uint32_t iA = min(ir, rowE > 0 ? rowE - 1 : 0u);
+  const uint32_t nA = rowE > 0 ? ((my + 1) / 2 + 1) / 2 : 0u, nB = my / 2, nM = has_odd ? (my + 1) / 2 : 0u;
+  const uint32_t u = min((uint32_t)lane, mx - 1);
+  const uint32_t lxA = (2 * iA + 1) * 4u, lx = u * 4u;
+  float xa[kA], xb[kB], xc[kM], xd[kM];
+  if (nA > 0) {
 #pragma unroll
-      for (int u = 0; u < kT0Group; u++) {
-        const uint32_t a = min(a0 + (uint32_t)u * kWaves, nA - 1);
-        const uint32_t vh = 4 * a + 2 * half < my ? 2 * half : 0u;
-        xs[u] = ldf(xbase, xe0 + (4 * a + vh) * rowB + lx);
-      }
-#pragma unroll
-      for (int u = 0; u < kT0Group; u++) {
-        const uint32_t a = a0 + (uint32_t)u * kWaves;
-        if (a >= nA) break;
-        const uint32_t v = 4 * a + 2 * half;
-        const uint32_t vc = v < my ? v : v - 2;
-        const uint32_t ga = (vc >> 1) * (kT0Side * 4u) + lg;
-        const float p = t0_xavg(lds_at(sgb, ga), lds_at(sgb, ga + 4), xav);
-        const uint32_t j = J0 + (vc >> 1) * RP + i;
-        const uint64_t h0 = (4 * a < my && 4 * a < owny) ? 0x00000000ffffffffull : 0ull;
-        const uint64_t h1 = (4 * a + 2 < my && 4 * a + 2 < owny) ? 0xffffffff00000000ull : 0ull;
-        t0_finish<KB, LL>(gq, iso, xs[u], p, we < ownz ? lane_in & (h0 | h1) : 0ull, j,
-                          min(j - t.jbase, (uint32_t)kT0Codes), t, acc);
-      }
+    for (int k = 0; k < kA; k++) {
+      const uint32_t a = min(wave + (uint32_t)k * kWaves, nA - 1);
+      const uint32_t vh = 4 * a + 2 * half < my ? 2 * half : 0u;
+      xa[k] = ldf(xbase, xe0 + (4 * a + vh) * rowB + lxA);
     }
   }
-  const uint32_t u = min((uint32_t)lane, mx - 1);
+  if (nB > 0) {
+#pragma unroll
+    for (int k = 0; k < kB; k++) {
+      const uint32_t f = min(wave + (uint32_t)k * kWaves, nB - 1);
+      xb[k] = ldf(xbase, xe0 + (2 * f + 1) * rowB + lx);
+    }
+  }
+  if (nM > 0) {
+#pragma unroll
+    for (int k = 0; k < kM; k++) {
+      const uint32_t m = min(wave + (uint32_t)k * kWaves, nM - 1);
+      xc[k] = ldf(xbase, xo0 + 2 * m * rowB + lx);
+      xd[k] = ldf(xbase, xo0 + min(2 * m + 1, my - 1) * rowB + lx);
+    }
+  }
+  __syncthreads();
+
+  // ---- A rows: even plane, v = 4a + 2*half, u = 2i + 1
+  if (nA > 0) {
+    const bool xav = iA + 1 < gx;
+    const uint64_t lane_in = __ballot(ir < rowE && 2 * ir + 1 < ownx);
+    const uint32_t lg = iA * 4u;
+#pragma unroll
+    for (int k = 0; k < kA; k++) {
+      const uint32_t a = wave + (uint32_t)k * kWaves;
+      if (a >= nA) break;
+      const uint32_t v = 4 * a + 2 * half;
+      const uint32_t vc = v < my ? v : v - 2;
+      const uint32_t ga = (vc >> 1) * (kT0Side * 4u) + lg;
+      const float p = t0_xavg(lds_at(sgb, ga), lds_at(sgb, ga + 4), xav);
+      const uint32_t j = J0 + (vc >> 1) * RP + iA;
+      const uint64_t h0 = (4 * a < my && 4 * a < owny) ? 0x00000000ffffffffull : 0ull;
+      const uint64_t h1 = (4 * a + 2 < my && 4 * a + 2 < owny) ? 0xffffffff00000000ull : 0ull;
+      t0_finish<KB, LL>(gq, iso, xa[k], p, we < ownz ? lane_in & (h0 | h1) : 0ull, j,
+                        min(j - t.jbase, (uint32_t)kT0Codes), t, acc);
+    }
+  }
   const uint32_t lx0 = u >> 1;
   const bool xav = (u & 1u) && lx0 + 1 < gx;
   const uint64_t lane_in = __ballot((uint32_t)lane < mx && (uint32_t)lane < ownx);
-  const uint32_t lg = lx0 * 4u, lx = u * 4u;
+  const uint32_t lg = lx0 * 4u;
   constexpr uint32_t kRow = kT0Side * 4u, kPl = kT0Plane * 4u;
   // ---- B rows: odd rows v = 2f + 1 of the even plane (z even, y odd)
-  {
-    const uint32_t nB = my / 2;
-    for (uint32_t f0 = wave; f0 < nB; f0 += kT0Group * kWaves) {
-      float xs[kT0Group];
 #pragma unroll
-      for (int k = 0; k < kT0Group; k++) {
-        const uint32_t f = min(f0 + (uint32_t)k * kWaves, nB - 1);
-        xs[k] = ldf(xbase, xe0 + (2 * f + 1) * rowB + lx);
-      }
-#pragma unroll
-      for (int k = 0; k < kT0Group; k++) {
-        const uint32_t f = f0 + (uint32_t)k * kWaves;
-        if (f >= nB) break;
-        const bool yu = f + 1 < gy;
-        const uint32_t ga = f * kRow + lg;
-        const float A = t0_xavg(lds_at(sgb, ga), lds_at(sgb, ga + 4), xav);
-        const float B = t0_xavg(lds_at(sgb, ga + kRow), lds_at(sgb, ga + kRow + 4), xav);
-        float pb = avg2(A, B);
-        hold(pb);
-        const float p = yu ? pb : A;
-        const uint32_t jr = J0 + f * RP + rowE;
-        t0_finish<KB, LL>(gq, iso, xs[k], p, (we < ownz && 2 * f + 1 < owny) ? lane_in : 0ull, jr + u,
-                          jr >= t.jbase ? jr - t.jbase + u : min(jr + u - t.jbase, (uint32_t)kT0Codes), t, acc);
-      }
-    }
+  for (int k = 0; k < kB; k++) {
+    const uint32_t f = wave + (uint32_t)k * kWaves;
+    if (f >= nB) break;
+    const bool yu = f + 1 < gy;
+    const uint32_t ga = f * kRow + lg;
+    const float A = t0_xavg(lds_at(sgb, ga), lds_at(sgb, ga + 4), xav);
+    const float B = t0_xavg(lds_at(sgb, ga + kRow), lds_at(sgb, ga + kRow + 4), xav);
+    float pb = avg2(A, B);
+    hold(pb);
+    const float p = yu ? pb : A;
+    const uint32_t jr = J0 + f * RP + rowE;
+    t0_finish<KB, LL>(gq, iso, xb[k], p, (we < ownz && 2 * f + 1 < owny) ? lane_in : 0ull, jr + u,
+                      min(jr + u - t.jbase, (uint32_t)kT0Codes), t, acc);
   }
   // ---- C and D rows: the odd plane's rows 2m (y even) and 2m + 1 (y odd)
-  if (has_odd) {
-    const uint32_t nM = (my + 1) / 2;
+  {
     const uint32_t jo = J0 + s.Pe;
     const bool zown = we + 1 < ownz;
-    for (uint32_t m0 = wave; m0 < nM; m0 += (kT0Group / 2) * kWaves) {
-      float xs[kT0Group];
 #pragma unroll
-      for (int k = 0; k < kT0Group / 2; k++) {
-        const uint32_t m = min(m0 + (uint32_t)k * kWaves, nM - 1);
-        const uint32_t vd = min(2 * m + 1, my - 1);
-        xs[2 * k] = ldf(xbase, xo0 + 2 * m * rowB + lx);
-        xs[2 * k + 1] = ldf(xbase, xo0 + vd * rowB + lx);
-      }
-#pragma unroll
-      for (int k = 0; k < kT0Group / 2; k++) {
-        const uint32_t m = m0 + (uint32_t)k * kWaves;
-        if (m >= nM) break;
-        const uint32_t ga = m * kRow + lg;
-        const float A = t0_xavg(lds_at(sgb, ga), lds_at(sgb, ga + 4), xav);
-        const float Cc = t0_xavg(lds_at(sgb, ga + kPl), lds_at(sgb, ga + kPl + 4), xav);
-        float pc = avg2(A, Cc);
-        hold(pc);
-        const float p = zu ? pc : A;
-        const uint32_t jc = jo + 2 * m * mx;
-        t0_finish<KB, LL>(gq, iso, xs[2 * k], p, (zown && 2 * m < owny) ? lane_in : 0ull, jc + u,
-                          min(jc + u - t.jbase, (uint32_t)kT0Codes), t, acc);
-        if (2 * m + 1 < my) {
-          const bool yu = m + 1 < gy;
-          const float B = t0_xavg(lds_at(sgb, ga + kRow), lds_at(sgb, ga + kRow + 4), xav);
-          const float D = t0_xavg(lds_at(sgb, ga + kPl + kRow), lds_at(sgb, ga + kPl + kRow + 4), xav);
-          float p0 = avg2(A, B), p1 = avg2(Cc, D);
-          hold(p0);
-          hold(p1);
-          p0 = yu ? p0 : A;
-          p1 = yu ? p1 : Cc;
-          float pd = avg2(p0, p1);
-          hold(pd);
-          const float p2 = zu ? pd : p0;
-          t0_finish<KB, LL>(gq, iso, xs[2 * k + 1], p2, (zown && 2 * m + 1 < owny) ? lane_in : 0ull, jc + mx + u,
-                            min(jc + mx + u - t.jbase, (uint32_t)kT0Codes), t, acc);
-        }
+    for (int k = 0; k < kM; k++) {
+      const uint32_t m = wave + (uint32_t)k * kWaves;
+      if (m >= nM) break;
+      const uint32_t ga = m * kRow + lg;
+      const float A = t0_xavg(lds_at(sgb, ga), lds_at(sgb, ga + 4), xav);
+      const float Cc = t0_xavg(lds_at(sgb, ga + kPl), lds_at(sgb, ga + kPl + 4), xav);
+      float pc = avg2(A, Cc);
+      hold(pc);
+      const float p = zu ? pc : A;
+      const uint32_t jc = jo + 2 * m * mx;
+      t0_finish<KB, LL>(gq, iso, xc[k], p, (zown && 2 * m < owny) ? lane_in : 0ull, jc + u,
+                        min(jc + u - t.jbase, (uint32_t)kT0Codes), t, acc);
+      if (2 * m + 1 < my) {
+        const bool yu = m + 1 < gy;
+        const float B = t0_xavg(lds_at(sgb, ga + kRow), lds_at(sgb, ga + kRow + 4), xav);
+        const float D = t0_xavg(lds_at(sgb, ga + kPl + kRow), lds_at(sgb, ga + kPl + kRow + 4), xav);
+        float p0 = avg2(A, B), p1 = avg2(Cc, D);
+        hold(p0);
+        hold(p1);
+        p0 = yu ? p0 : A;
+        p1 = yu ? p1 : Cc;
+        float pd = avg2(p0, p1);
+        hold(pd);
+        const float p2 = zu ? pd : p0;
+        t0_finish<KB, LL>(gq, iso, xd[k], p2, (zown && 2 * m + 1 < owny) ? lane_in : 0ull, jc + mx + u,
+                          min(jc + mx + u - t.jbase, (uint32_t)kT0Codes), t, acc);
       }
     }
   }
   // ---- column: the points u = 64 of the full rows (65-point rows only)
-  const uint32_t nB = my / 2, nF = nB + (has_odd ? my : 0u);
+  const uint32_t nF = nB + (has_odd ? my : 0u);
   if (mx == 65) {
     for (uint32_t c0 = wave * 64; c0 < nF; c0 += kWaves * 64) {
       const uint32_t fr = c0 + (uint32_t)lane, f = min(fr, nF - 1);
@@ -852,8 +856,7 @@ __global__ __launch_bounds__(kBS) void k_encode_l0t(EncPlan P) {
   // already in the slots, at their lanes: count word 3 says so)
   uint32_t *pk = pack[wave];
   for (uint32_t c = cfirst + wave; c < cend; c += kWaves) {
-    const uint32_t j = c * 64 + (uint32_t)lane;
-    const uint32_t v16 = j < s.npts ? (uint32_t)sc[j - t.jbase] : 0u;
+    const uint32_t v16 = sc[c * 64 - t.jbase + (uint32_t)lane];
     const bool E = v16 == kT0Exact;
     const uint32_t zz = E ? 0u : v16;
     const int64_t slot = slot0 + c;
