@@ -218,6 +218,32 @@ int iso_extract(const float *d_field, const int64_t dims[3], float isovalue, flo
                 float *d_vertices, int64_t cap_v, int32_t *d_tris, int64_t cap_t,
                 int64_t *d_counts, void *d_ws, size_t ws_bytes, void *stream);
 
+/* Marching cubes' classification bits (Sec. II.B: the sign of value minus
+ * isovalue at every vertex, which fixes every cell's case): one plane per
+ * isovalue of dims[0] * dims[1] * ceil(dims[2] / 64) little-endian u64
+ * words, row (z, y) at word (z * dims[1] + y) * ceil(dims[2] / 64), bit i of
+ * word w = [value at x = 64 w + i < isovalue] (0 past the row's end). */
+
+/* Level-0 reconstruction (as chr_reconstruct at level 0) that also writes
+ * the classification bits of n_iso (1..16) isovalues into d_bits (n_iso
+ * planes, plane j for h_isovalues[j], converted to binary32 as given).  The
+ * level-0 decoder for 64-cell blocks writes them with the rows it decodes,
+ * so marching cubes needs no pass over the field; otherwise one pass per
+ * isovalue over the output follows.  Same workspace and errors as
+ * chr_reconstruct, plus CHR_E_INVAL for a bad n_iso, non-finite isovalues or
+ * a NULL d_bits. */
+int chr_reconstruct_bits(const chr_info *info, const void *d_stream, size_t stream_bytes, double error_bound,
+                         const float *h_isovalues, int n_iso, float *d_out, uint64_t *d_bits, int32_t *d_status,
+                         void *d_ws, size_t ws_bytes, void *stream);
+
+/* iso_extract of isovalue on d_field given its classification bits d_bits
+ * (one plane as chr_reconstruct_bits writes, for this same isovalue):
+ * identical outputs, without the pass over the field.  Same arguments,
+ * workspace and errors as iso_extract. */
+int iso_extract_bits(const float *d_field, const int64_t dims[3], const uint64_t *d_bits, float isovalue,
+                     float spacing, float *d_vertices, int64_t cap_v, int32_t *d_tris, int64_t cap_t,
+                     int64_t *d_counts, void *d_ws, size_t ws_bytes, void *stream);
+
 /* Marching-cubes case of every cell: d_cases is uint8 [nz-1][ny-1][nx-1];
  * bit v is set iff the value at corner v = dx + 2dy + 4dz is below the
  * isovalue (f < k). */
@@ -357,7 +383,9 @@ int chr_batch_capture(chr_batch *b, void *d_ws, size_t ws_bytes, void *stream);
 /* Launches the captured graph on `stream` (CHR_E_INVAL before a capture). */
 int chr_batch_replay(chr_batch *b, void *stream);
 
-/* Chooses the branch count (1, 2, 4, 8) and the level-0 tiles
+/* Switched off (returns CHR_E_INVAL; chr_batch_tune replaces it): one GPU
+ * run aborted inside its replay-timed search and the cause is not known.
+ * Chose the branch count (1, 2, 4, 8) and the level-0 tiles
  * (chr_set_tiles' candidates) by timing replays of the captured batch:
  * coordinate descent from the current configuration over branches, then
  * compression tiles, then reconstruction tiles; a change is kept when it is
@@ -366,6 +394,24 @@ int chr_batch_replay(chr_batch *b, void *stream);
  * signature = hash of the items' shapes and parameters and the device; a
  * matching line skips the search, a new result is appended. */
 int chr_batch_autotune(chr_batch *b, void *d_ws, size_t ws_bytes, void *stream, const char *cache_path);
+
+/* Chooses the brick size B of every item's stream (as created, 32, 64 or
+ * 128: Sec. II.A's blocks; B changes the stream bytes, never a reconstructed
+ * value or a mesh), the branch count (1, 2, 4, 8) and the level-0 tiles by
+ * timing eager runs of the whole batch on `stream` (two per candidate, after
+ * an untimed one): coordinate descent over B, branches, compression tiles,
+ * reconstruction tiles from the current configuration; a change is kept when
+ * at least 1% faster.  A block size invalid for an item (not a multiple of
+ * 2^(levels-1)), a stream bound above an item's stream_capacity or a
+ * workspace above ws_bytes skips that candidate.  Ends with the chosen
+ * configuration captured (as chr_batch_capture).  *block_out (may be NULL):
+ * the chosen B, 0 for each item's own.  cache_path (may be NULL): text file
+ * of "signature branches block enc dec" lines; a matching line skips the
+ * search, a new result is appended.  The outputs hold the last timed run's
+ * results.  Errors: CHR_E_INVAL, CHR_E_NOMEM (workspace too small for the
+ * configuration as created), CHR_E_HIP. */
+int chr_batch_tune(chr_batch *b, void *d_ws, size_t ws_bytes, void *stream, const char *cache_path,
+                   int *block_out);
 
 /* Current configuration and the duration of the last timed replay (ms). */
 int chr_batch_config(const chr_batch *b, int *branches, int *enc_cpw, int *dec_cpw, float *last_ms);

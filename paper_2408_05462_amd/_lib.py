@@ -24,14 +24,15 @@ EXPORTS = ["chr_last_error", "chr_version", "chr_compress_bound", "chr_compress_
            "chr_stream_info", "chr_stream_verify", "chr_reconstruct_workspace", "chr_reconstruct",
            "iso_workspace", "iso_extract", "iso_cases", "chr_mc_table", "chr_range", "chr_prof_enable",
            "chr_prof_collect", "chr_prof_disable", "chr_set_tiles", "chr_set_level0_tiles", "chr_batch_create", "chr_batch_workspace",
-           "chr_batch_run", "chr_batch_capture", "chr_batch_replay", "chr_batch_autotune", "chr_batch_config", "chr_batch_set_config",
+           "chr_batch_run", "chr_batch_capture", "chr_batch_replay", "chr_batch_autotune", "chr_batch_tune", "chr_batch_config", "chr_batch_set_config",
            "chr_batch_destroy", "chr_server_create", "chr_server_add_stream", "chr_server_submit",
            "chr_server_step", "chr_server_poll", "chr_server_release", "chr_server_cancel", "chr_server_stats_get",
            "chr_server_now_ms", "chr_server_destroy", "chr_topology_workspace", "chr_topology_error_bound",
            "chr_reconstruct_range", "chr_entropy_bound", "chr_entropy_workspace", "chr_entropy_encode",
            "chr_entropy_info", "chr_entropy_decode", "chr_tiers_bound", "chr_tiers_workspace", "chr_tiers_compress",
            "chr_tiers_header", "chr_tiers_reconstruct_workspace", "chr_tiers_reconstruct", "chr_block_box",
-           "iso_box_workspace", "iso_extract_box", "chr_reconstruct_static"]
+           "iso_box_workspace", "iso_extract_box", "chr_reconstruct_static",
+           "chr_reconstruct_bits", "iso_extract_bits"]
 
 
 class ChrError(RuntimeError):
@@ -139,6 +140,12 @@ def load():
     L.iso_extract.argtypes = [vp, i64p, C.c_float, C.c_float, vp, C.c_int64, vp, C.c_int64, vp, vp, C.c_size_t,
                               vp]
     L.iso_extract.restype = C.c_int
+    L.chr_reconstruct_bits.argtypes = [C.POINTER(chr_info), vp, C.c_size_t, C.c_double, C.POINTER(C.c_float),
+                                       C.c_int, vp, vp, vp, vp, C.c_size_t, vp]
+    L.chr_reconstruct_bits.restype = C.c_int
+    L.iso_extract_bits.argtypes = [vp, i64p, vp, C.c_float, C.c_float, vp, C.c_int64, vp, C.c_int64, vp, vp,
+                                   C.c_size_t, vp]
+    L.iso_extract_bits.restype = C.c_int
     L.iso_cases.argtypes = [vp, i64p, C.c_float, vp, vp, C.c_size_t, vp]
     L.iso_cases.restype = C.c_int
     L.chr_mc_table.argtypes = [vp, vp]
@@ -166,6 +173,8 @@ def load():
     L.chr_batch_replay.restype = C.c_int
     L.chr_batch_autotune.argtypes = [vp, vp, C.c_size_t, vp, C.c_char_p]
     L.chr_batch_autotune.restype = C.c_int
+    L.chr_batch_tune.argtypes = [vp, vp, C.c_size_t, vp, C.c_char_p, C.POINTER(C.c_int)]
+    L.chr_batch_tune.restype = C.c_int
     ip = C.POINTER(C.c_int)
     L.chr_batch_config.argtypes = [vp, ip, ip, ip, C.POINTER(C.c_float)]
     L.chr_batch_config.restype = C.c_int

@@ -205,6 +205,58 @@ def iso_extract(field, isovalue, spacing, verts, tris, counts, ws, stream=None):
     L.check(rc, "iso_extract")
 
 
+def bits_shape(dims, n_iso=1):
+    """Shape of n_iso planes of classification bits (uint64 words) for a field of dims."""
+    return (n_iso, int(dims[0]) * int(dims[1]) * ((int(dims[2]) + 63) // 64))
+
+
+def chr_reconstruct_bits(info, stream_dev, error_bound, isovalues, out, bits, status, ws, stream=None):
+    ks = (C.c_float * len(isovalues))(*[float(np.float32(k)) for k in isovalues])
+    rc = L.load().chr_reconstruct_bits(C.byref(info), _p(stream_dev), stream_dev.numel(), float(error_bound), ks,
+                                       len(isovalues), _p(out), _p(bits), _p(status), _p(ws),
+                                       0 if ws is None else ws.numel(), _s(stream))
+    L.check(rc, "chr_reconstruct_bits")
+
+
+def iso_extract_bits(field, bits_plane, isovalue, spacing, verts, tris, counts, ws, stream=None):
+    _need_cuda_f32(field, "field")
+    rc = L.load().iso_extract_bits(_p(field), L.dims3(field.shape), _p(bits_plane), float(np.float32(isovalue)),
+                                   float(spacing), _p(verts), 0 if verts is None else verts.shape[0], _p(tris),
+                                   0 if tris is None else tris.shape[0], _p(counts), _p(ws), ws.numel(), _s(stream))
+    L.check(rc, "iso_extract_bits")
+
+
+def reconstruct_bits(c, isovalues):
+    """Synchronous level-0 reconstruction with the classification bits of
+    each isovalue: (field, bits [n_iso, words] as int64)."""
+    dev = c.stream.device
+    out = torch.empty(level_shape(c.info, 0), dtype=torch.float32, device=dev)
+    bits = torch.empty(bits_shape(out.shape, len(isovalues)), dtype=torch.int64, device=dev)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    ws = torch.empty(max(chr_reconstruct_workspace(c.info, 0), 256), dtype=torch.uint8, device=dev)
+    chr_reconstruct_bits(c.info, c.stream, stream_bound(c.info), isovalues, out, bits, status, ws)
+    torch.cuda.synchronize(dev)
+    st = int(status.item())
+    if st != 0:
+        raise L.ChrError(st, "chr_reconstruct_bits (device status)")
+    return out, bits
+
+
+def extract_bits(field, bits_plane, isovalue, spacing=1.0):
+    """Synchronous marching cubes from given classification bits."""
+    dev = field.device
+    ws = torch.empty(iso_workspace(field.shape), dtype=torch.uint8, device=dev)
+    counts = torch.zeros(2, dtype=torch.int64, device=dev)
+    iso_extract_bits(field, bits_plane, isovalue, spacing, None, None, counts, ws)
+    torch.cuda.synchronize(dev)
+    nv, nt = (int(v) for v in counts.cpu())
+    verts = torch.empty((max(nv, 1), 3), dtype=torch.float32, device=dev)
+    tris = torch.empty((max(nt, 1), 3), dtype=torch.int32, device=dev)
+    iso_extract_bits(field, bits_plane, isovalue, spacing, verts, tris, counts, ws)
+    torch.cuda.synchronize(dev)
+    return verts[:nv], tris[:nt]
+
+
 def extract(field, isovalue, spacing=1.0):
     """Synchronous marching cubes: returns (verts [V,3] f32, tris [T,3] i32)."""
     dev = field.device
@@ -353,6 +405,16 @@ class Batch:
         L.check(L.load().chr_batch_autotune(self.handle, _p(self.ws), self.ws.numel(), _s(stream),
                                             None if cache_path is None else str(cache_path).encode()),
                 "chr_batch_autotune")
+
+    def tune(self, cache_path=None, stream=None):
+        """Eager-timed search over brick size, branches and tiles, then one
+        capture (chr_batch_tune); returns the chosen brick size (0: each
+        item's own)."""
+        blk = C.c_int(0)
+        L.check(L.load().chr_batch_tune(self.handle, _p(self.ws), self.ws.numel(), _s(stream),
+                                        None if cache_path is None else str(cache_path).encode(), C.byref(blk)),
+                "chr_batch_tune")
+        return int(blk.value)
 
     def set_config(self, branches, enc_cpw=8, dec_cpw=16):
         L.check(L.load().chr_batch_set_config(self.handle, int(branches), int(enc_cpw), int(dec_cpw)),

@@ -8,7 +8,9 @@
 // single-field calls, so its outputs are bit for bit theirs.  Capturing the
 // fork/join into one graph turns the batch into a single launch whose
 // branches the device overlaps.  The autotuner picks B and the level-0 tile
-// shapes by timing replays of the captured graph.
+// shapes by timing replays of the captured graph (switched off, see below);
+// chr_batch_tune picks B, the brick size and the tiles by timing eager runs
+// and captures once.
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
@@ -57,6 +59,7 @@ struct chr_batch {
   hipEvent_t fork = nullptr;
   std::vector<hipEvent_t> join;
   hipGraphExec_t exec = nullptr;
+  std::vector<int> block0;        // each item's block size as created
 };
 
 namespace {
@@ -238,6 +241,93 @@ void cache_store(const char *path, const std::string &sig, int br, int ec, int d
   std::fclose(f);
 }
 
+// Workspace bytes of one branch for the items' current parameters (0 when
+// some item's parameters are invalid).
+size_t branch_bytes(const chr_batch *b, const std::vector<Geo> &geo) {
+  size_t ws = 0;
+  for (size_t i = 0; i < b->items.size(); i++) {
+    const chr_batch_item &it = b->items[i];
+    const size_t we = enc_workspace_bytes(it.dims, &it.params);
+    const size_t wd = dec_workspace_bytes(geo[i], 0);
+    const size_t wm = it.n_iso > 0 ? mc_workspace_bytes(it.dims) : 0;
+    if (!we || (it.n_iso > 0 && !wm)) return 0;
+    ws = std::max(ws, align256(std::max(we, std::max(wd, wm))));
+  }
+  return ws;
+}
+
+// Gives every item brick size B (0: each item's own, as created) when it is
+// valid for all of them, their streams fit the capacities and one branch's
+// workspace times `branches` fits ws_bytes; otherwise nothing changes.
+int set_block(chr_batch *b, int B, int branches, size_t ws_bytes) {
+  std::vector<chr_batch_item> items = b->items;
+  std::vector<Geo> geo(items.size());
+  std::vector<uint64_t> poff(items.size());
+  for (size_t i = 0; i < items.size(); i++) {
+    chr_batch_item &it = items[i];
+    it.params.block = B ? B : b->block0[i];
+    int rc = enc_geometry(it.dims, it.error_bound, it.isovalues, it.n_iso, &it.params, geo[i], poff[i]);
+    if (rc) return rc;
+    const size_t need = chr_compress_bound(it.dims, &it.params);
+    if (!need || need > it.stream_capacity) return api_fail(CHR_E_CAPACITY, "stream capacity below the bound");
+  }
+  std::swap(b->items, items);
+  const size_t ws = branch_bytes(b, geo);
+  if (!ws || ws * (size_t)branches > ws_bytes) {
+    std::swap(b->items, items);
+    return api_fail(CHR_E_NOMEM, "workspace too small for this block size");
+  }
+  b->geo = geo;
+  b->payload_off = poff;
+  b->ws_branch = ws;
+  return CHR_OK;
+}
+
+// Average duration (ms) of `reps` eager runs on s after one untimed run.
+int time_eager(chr_batch *b, void *d_ws, size_t ws_bytes, hipStream_t s, int reps, float &ms) {
+  std::vector<ItemJobs> jobs;
+  std::vector<int> br;
+  int rc = plan(b, d_ws, ws_bytes, jobs, br);
+  if (rc) return rc;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) hipEventDestroy(e0);
+    return api_fail(CHR_E_HIP, "hipEventCreate failed");
+  }
+  enqueue(b, jobs, br, s);
+  hipError_t e = hipEventRecord(e0, s);
+  for (int r = 0; r < reps && e == hipSuccess; r++) {
+    enqueue(b, jobs, br, s);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float t = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (e != hipSuccess) return api_fail(CHR_E_HIP, std::string("eager timing: ") + hipGetErrorString(e));
+  ms = t / (float)reps;
+  b->last_ms = ms;
+  return CHR_OK;
+}
+
+bool cache_lookup5(const char *path, const std::string &sig, int v[4]) {
+  if (!path) return false;
+  FILE *f = std::fopen(path, "r");
+  if (!f) return false;
+  char key[64];
+  int a, B, e, d;
+  bool found = false;
+  while (std::fscanf(f, "%63s %d %d %d %d", key, &a, &B, &e, &d) == 5)
+    if (sig == key && a >= 1 && a <= kMaxBranches && B >= 0 && tiles_ok(e, d)) {
+      v[0] = a; v[1] = B; v[2] = e; v[3] = d;
+      found = true;
+    }
+  std::fclose(f);
+  return found;
+}
+
 }  // namespace
 
 extern "C" {
@@ -274,6 +364,7 @@ int chr_batch_create(const chr_batch_item *items, int n_items, chr_batch **out) 
     if (!we || (it.n_iso > 0 && !wm)) { delete b; return api_fail(CHR_E_INVAL, at + chr_last_error()); }
     b->ws_branch = std::max(b->ws_branch, align256(std::max(we, std::max(wd, wm))));
   }
+  for (const chr_batch_item &it : b->items) b->block0.push_back(it.params.block);
   b->max_branches = std::min(kMaxBranches, n_items);
   b->branches = b->max_branches;  // measured: throughput grows up to 8 branches (batch64)
   *out = b;
@@ -356,6 +447,72 @@ int chr_batch_autotune(chr_batch *b, void *d_ws, size_t ws_bytes, void *stream, 
   if (rc) return rc;
   b->last_ms = best_ms;
   cache_store(cache_path, sig, best[0], best[1], best[2]);
+  return CHR_OK;
+}
+
+int chr_batch_tune(chr_batch *b, void *d_ws, size_t ws_bytes, void *stream, const char *cache_path,
+                   int *block_out) {
+  if (!b) return api_fail(CHR_E_INVAL, "NULL batch");
+  if (!d_ws) return api_fail(CHR_E_INVAL, "NULL workspace");
+  int rc = ensure_streams(b);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const std::string sig = "t" + signature(b);
+  int cur[4] = {b->branches, 0, b->enc_cpw, b->dec_cpw};   // branches, block (0: as created), tiles
+  auto apply = [&](const int c[4]) {
+    int r = set_block(b, c[1], c[0], ws_bytes);
+    if (r) return r;
+    b->branches = c[0];
+    b->enc_cpw = c[2];
+    b->dec_cpw = c[3];
+    return CHR_OK;
+  };
+  int cached[4];
+  if (cache_lookup5(cache_path, sig, cached) && cached[0] <= b->max_branches && apply(cached) == CHR_OK) {
+    if (block_out) *block_out = cached[1];
+    return capture(b, d_ws, ws_bytes);
+  }
+  const int reps = 2;
+  float best_ms = 0.f;
+  rc = apply(cur);
+  if (rc) return rc;
+  rc = time_eager(b, d_ws, ws_bytes, s, reps, best_ms);
+  if (rc) return rc;
+  // coordinate descent: brick size, branches, compression tiles,
+  // reconstruction tiles; a change is kept when at least 1% faster, and a
+  // candidate that does not fit (block size invalid for an item, stream or
+  // workspace too small) is skipped
+  const std::vector<int> cand[4] = {{1, 2, 4, 8}, {0, 32, 64, 128}, {1, 2, 4, 8, 16}, {8, 16, 32, 64}};
+  const int order[4] = {1, 0, 2, 3};
+  for (int oi = 0; oi < 4; oi++) {
+    const int dim = order[oi];
+    for (int v : cand[dim]) {
+      if (v == cur[dim] || (dim == 0 && v > b->max_branches)) continue;
+      int c[4] = {cur[0], cur[1], cur[2], cur[3]};
+      c[dim] = v;
+      if (apply(c) != CHR_OK) continue;
+      float ms = 0.f;
+      rc = time_eager(b, d_ws, ws_bytes, s, reps, ms);
+      if (rc) return rc;
+      if (ms < 0.99f * best_ms) {
+        best_ms = ms;
+        std::copy(c, c + 4, cur);
+      }
+    }
+  }
+  rc = apply(cur);
+  if (rc) return rc;
+  rc = capture(b, d_ws, ws_bytes);
+  if (rc) return rc;
+  b->last_ms = best_ms;
+  if (block_out) *block_out = cur[1];
+  if (cache_path) {
+    FILE *f = std::fopen(cache_path, "a");
+    if (f) {
+      std::fprintf(f, "%s %d %d %d %d\n", sig.c_str(), cur[0], cur[1], cur[2], cur[3]);
+      std::fclose(f);
+    }
+  }
   return CHR_OK;
 }
 

@@ -669,6 +669,57 @@ extern "C" {
 
 size_t iso_workspace(const int64_t dims[3]) { return mc_workspace_bytes(dims); }
 
+int iso_extract_bits(const float *d_field, const int64_t dims[3], const uint64_t *d_bits, float isovalue,
+                     float spacing, float *d_vertices, int64_t cap_v, int32_t *d_tris, int64_t cap_t,
+                     int64_t *d_counts, void *d_ws, size_t ws_bytes, void *stream) {
+  if (!d_bits) return fail(CHR_E_INVAL, "NULL bits");
+  McJob J;
+  int rc = mc_prepare(d_field, dims, isovalue, spacing, d_vertices, cap_v, d_tris, cap_t, d_counts, d_ws, ws_bytes, J);
+  if (rc) return rc;
+  J.M.bits = const_cast<unsigned long long *>(reinterpret_cast<const unsigned long long *>(d_bits));
+  launch_mc_from_bits(J.M, J.scan, static_cast<hipStream_t>(stream));
+  return check_hip("iso_extract_bits launch");
+}
+
+int chr_reconstruct_bits(const chr_info *info, const void *d_stream, size_t stream_bytes, double error_bound,
+                         const float *h_isovalues, int n_iso, float *d_out, uint64_t *d_bits, int32_t *d_status,
+                         void *d_ws, size_t ws_bytes, void *stream) {
+  if (!info || !d_stream || !d_out || !d_bits || !h_isovalues) return fail(CHR_E_INVAL, "NULL argument");
+  if (n_iso < 1 || n_iso > kMaxIso) return fail(CHR_E_INVAL, "n_iso must be in [1, 16]");
+  for (int j = 0; j < n_iso; j++)
+    if (!std::isfinite(h_isovalues[j])) return fail(CHR_E_INVAL, "isovalues must be finite");
+  Geo g;
+  int rc = info_geo(info, g);
+  if (rc) return rc;
+  if (!(error_bound >= stream_bound(*info))) return fail(CHR_E_ACCURACY, "requested error bound below the stream's");
+  if (stream_bytes < info->total_bytes) return fail(CHR_E_CORRUPT, "stream shorter than its header states");
+  McPlan M;
+  size_t mneed = 0, moff[6];
+  rc = mc_plan(d_out, info->dims, M, mneed, moff);
+  if (rc) return rc;
+  DecJob J;
+  rc = dec_prepare(g, info->payload_offset, 0, d_stream, info->total_bytes, d_out, d_status, d_ws, ws_bytes,
+                   g_tune.dec_cpw0, J);
+  if (rc) return rc;
+  DecPlan &D = J.D;
+  D.bits = reinterpret_cast<unsigned long long *>(d_bits);
+  D.bnw = M.nw;
+  D.bplane = M.nrows * M.nw;
+  D.nk = n_iso;
+  for (int j = 0; j < n_iso; j++) D.kb[j] = h_isovalues[j];
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  launch_decode(D, s);
+  if (!decode_tile0_used(D)) {
+    // another decoder ran: one classification pass per isovalue
+    for (int j = 0; j < n_iso; j++) {
+      M.bits = D.bits + (size_t)j * (size_t)D.bplane;
+      M.k = h_isovalues[j];
+      launch_mc_bits(M, s);
+    }
+  }
+  return check_hip("chr_reconstruct_bits launch");
+}
+
 int iso_extract(const float *d_field, const int64_t dims[3], float isovalue, float spacing, float *d_vertices,
                 int64_t cap_v, int32_t *d_tris, int64_t cap_t, int64_t *d_counts, void *d_ws, size_t ws_bytes,
                 void *stream) {

@@ -75,6 +75,13 @@ struct DecPlan {
   int32_t *status;
   int prune;                     // reconstruct only blocks that can hold an isosurface for k in [kmin, kmax]
   float kmin, kmax;
+  // below-isovalue bits of the level-0 output (marching cubes' words: 64
+  // points along x per u64, rows (z, y)), one plane of bplane words per
+  // isovalue kb[0..nk) (bits == nullptr: none)
+  unsigned long long *bits;
+  int64_t bplane, bnw;
+  int nk;
+  float kb[kMaxIso];
 };
 
 struct McPlan {
@@ -112,11 +119,14 @@ int64_t encode_l2_groups(const EncPlan &p);     // level-2 workgroups per block 
 bool encode_l2_fast(const EncPlan &p);          // whether level 2 runs in its own wide kernel
 void encode_pack_layout(EncPlan &p);            // fills pack_base / pack_gpb
 void launch_decode(const DecPlan &p, hipStream_t s);
+bool decode_tile0_used(const DecPlan &p);      // level 0 by plane pairs (writes p.bits when set)
 void launch_status_reset(int32_t *status, hipStream_t s);  // *status = 0 by a kernel (capturable)
 void launch_mc(const McPlan &p, U4 *scan_tmp, hipStream_t s);        // count + emit
 void launch_mc_count(const McPlan &p, U4 *scan_tmp, hipStream_t s);  // bits, counts, scan; totals to counts[0..3]
 void launch_mc_emit(const McPlan &p, hipStream_t s);                 // lists, vertices, triangles, counts[0..1]
 void launch_mc_cases(const McPlan &p, hipStream_t s);
+void launch_mc_bits(const McPlan &p, hipStream_t s);                 // the bits of isovalue p.k into p.bits
+void launch_mc_from_bits(const McPlan &p, U4 *scan_tmp, hipStream_t s); // count + emit from p.bits
 void launch_range(const float *f, int64_t n, float *out, hipStream_t s);
 size_t topo_workspace_bytes();
 int launch_topology(const float *f, const int64_t dims[3], const float *iso, int K, int64_t nth, double *out,

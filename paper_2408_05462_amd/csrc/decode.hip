@@ -549,7 +549,8 @@ __device__ __forceinline__ float d0_exact(const D0Ctx &t, uint32_t j) {
   const uint32_t k = (j >> 6) - t.c0;
   const unsigned long long em = t.cem[k];
   const uint32_t ix = t.cxo[k] + (uint32_t)__popcll(em & ((1ull << (j & 63u)) - 1ull));
-  return ix - t.xo0 < (uint32_t)kD0Xcap ? t.xl[ix - t.xo0] : __uint_as_float(ld32(t.xs + 4 * (uint64_t)ix));
+  if (ix - t.xo0 < (uint32_t)kD0Xcap) return t.xl[ix - t.xo0];
+  return __uint_as_float(ld32(t.xs + 4 * (uint64_t)ix));
 }
 
 __device__ __forceinline__ float d0_xavg(float a0, float a1, bool xav) {
@@ -560,6 +561,42 @@ __device__ __forceinline__ float d0_xavg(float a0, float a1, bool xav) {
 
 __device__ __forceinline__ float d0_lds(const char *base, uint32_t off) {
   return *reinterpret_cast<const float *>(base + off);
+}
+
+// Marching cubes' below-isovalue words of a group of kD0Rows decoded rows
+// along x: the word of row k for isovalue j is computed by the whole wave
+// (a ballot) and parked in lane 8 (j mod 8) + k of word set j / 8; then each
+// lane stores its word (at most two stores per group, for 16 isovalues).
+struct D0Bits {
+  uint32_t lo[2], hi[2];
+};
+
+// v_writelane: lane L (wave-uniform, through M0) of dst takes the
+// wave-uniform value v.
+__device__ __forceinline__ void writelane(uint32_t &dst, uint32_t v, uint32_t L) {
+  asm volatile("s_mov_b32 m0, %2\n\tv_writelane_b32 %0, %1, m0" : "+v"(dst) : "s"(v), "s"(L) : "m0");
+}
+
+// Words of the group's rows for isovalues j in [j0, j1) (j1 - j0 <= 8) into
+// one word set: isovalue j, row k at lane 8 (j - j0) + k.
+__device__ __forceinline__ void d0_bits_set(const DecPlan &D, uint32_t &lo, uint32_t &hi, const float (&rv)[kD0Rows],
+                                            int j0, int j1, unsigned long long vmask) {
+  for (int j = j0; j < j1; j++) {
+    const float kj = D.kb[j];
+    const uint32_t L0 = 8u * (uint32_t)(j - j0);
+#pragma unroll
+    for (int k = 0; k < kD0Rows; k++) {
+      const unsigned long long m = __ballot(rv[k] < kj) & vmask;
+      writelane(lo, (uint32_t)m, L0 + (uint32_t)k);
+      writelane(hi, (uint32_t)(m >> 32), L0 + (uint32_t)k);
+    }
+  }
+}
+
+__device__ __forceinline__ void d0_bits_rows(const DecPlan &D, D0Bits &q, const float (&rv)[kD0Rows], int nk,
+                                             unsigned long long vmask) {
+  d0_bits_set(D, q.lo[0], q.hi[0], rv, 0, min(nk, 8), vmask);
+  if (nk > 8) d0_bits_set(D, q.lo[1], q.hi[1], rv, 8, nk, vmask);
 }
 
 __global__ __launch_bounds__(kBS) void k_decode_l0t(DecPlan D) {
@@ -718,6 +755,26 @@ __global__ __launch_bounds__(kBS) void k_decode_l0t(DecPlan D) {
   // range (section indices clamped to [J0, J1)) and are not stored.
   const uint32_t jlast = J1 - 1;
   const uint32_t lxe = min(lx0, rowE > 0 ? rowE - 1 : 0u);   // an odd point of the row for even u
+  // marching cubes' words: row (z, y) of the field, word o_x / 64 (points
+  // u < min(mx, 64) of the row; u = 64 starts the next word)
+  const uint64_t bnw = (uint64_t)D.bnw;
+  const uint64_t wrow0 = ((uint64_t)(bp.o[0] + we) * n1 + bp.o[1]) * bnw + (bp.o[2] >> 6);
+  const uint32_t nvb = min(mx, 64u);
+  const unsigned long long vmask = __ballot((uint32_t)lane < nvb);
+  const int nk = D.bits ? D.nk : 0;
+  // the store of a group's words: lane L holds row k = L mod 8 (its row in
+  // the plane: rowof(k)) and isovalue 8 * set + L / 8
+  auto bits_store = [&](const D0Bits &q, auto rowof) {
+    const uint32_t k = (uint32_t)lane & 7u, jj = (uint32_t)lane >> 3;
+    const uint32_t row = rowof(k);
+#pragma unroll
+    for (int set = 0; set < 2; set++) {
+      const uint32_t j = jj + 8u * (uint32_t)set;
+      if (8 * set < nk && j < (uint32_t)nk && row < rown)
+        D.bits[(size_t)j * (size_t)D.bplane + wrow0 + (uint64_t)row * bnw] =
+            ((unsigned long long)q.hi[set] << 32) | q.lo[set];
+    }
+  };
   // LDS code byte offsets: per lane, plus a uniform row part, clamped to the
   // pair's last point
   const char *__restrict__ scb = reinterpret_cast<const char *>(sc);
@@ -765,6 +822,12 @@ __global__ __launch_bounds__(kBS) void k_decode_l0t(DecPlan D) {
       const uint32_t a = a0 + (uint32_t)k * kWaves;
       if (2 * a < rown) stf(obase, xe0 + 2 * a * rowB + lx, rv[2 * k]);
       if (2 * a + 1 < rown) stf(obase, xe0 + (2 * a + 1) * rowB + lx, rv[2 * k + 1]);
+    }
+    if (nk) {
+      D0Bits q{{0u, 0u}, {0u, 0u}};
+      d0_bits_rows(D, q, rv, nk, vmask);
+      // row k of the group: 2a + (k & 1), a = a0 + 4 (k / 2)
+      bits_store(q, [&](uint32_t k) { return 2 * (a0 + (k >> 1) * kWaves) + (k & 1u); });
     }
   }
   // ---- odd plane: rows 2m (y even) and 2m + 1 (y odd), every u from codes
@@ -824,6 +887,22 @@ __global__ __launch_bounds__(kBS) void k_decode_l0t(DecPlan D) {
         if (2 * m < rown) stf(obase, xo0b + 2 * m * rowB + lx, rv[2 * k]);
         if (2 * m + 1 < rown) stf(obase, xo0b + (2 * m + 1) * rowB + lx, rv[2 * k + 1]);
       }
+      if (nk) {
+        D0Bits q{{0u, 0u}, {0u, 0u}};
+        d0_bits_rows(D, q, rv, nk, vmask);
+        // rows of the odd plane: n1 rows after the even plane's
+        const uint32_t rbase = n1;
+        auto rowof = [&](uint32_t k) { return 2 * (m0 + (k >> 1) * kWaves) + (k & 1u); };
+        const uint32_t k = (uint32_t)lane & 7u, jj = (uint32_t)lane >> 3;
+        const uint32_t row = rowof(k);
+#pragma unroll
+        for (int set = 0; set < 2; set++) {
+          const uint32_t j = jj + 8u * (uint32_t)set;
+          if (8 * set < nk && j < (uint32_t)nk && row < rown)
+            D.bits[(size_t)j * (size_t)D.bplane + wrow0 + (uint64_t)(rbase + row) * bnw] =
+                ((unsigned long long)q.hi[set] << 32) | q.lo[set];
+        }
+      }
     }
   }
   // ---- the points u = 64 (65-point rows), one row per lane, when the block
@@ -851,6 +930,12 @@ __global__ __launch_bounds__(kBS) void k_decode_l0t(DecPlan D) {
         r = zz == kD0Exact ? d0_exact(t, j) : d0_quant(t, zz, p);
       }
       if (rr < nrow) stf(obase, (w == 0 ? xe0 : xo0b) + vv * rowB + 256u, r);
+      if (nk && rr < nrow) {
+        // the field's last point along x: bit 0 of the row's next word, the
+        // only point of that word
+        const uint64_t widx = wrow0 + (w * n1 + vv) * bnw + 1;
+        for (int j = 0; j < nk; j++) D.bits[(size_t)j * (size_t)D.bplane + widx] = r < D.kb[j] ? 1ull : 0ull;
+      }
     }
   }
 }
@@ -913,6 +998,16 @@ __global__ __launch_bounds__(kBS) void k_prune_fill(DecPlan D) {
   }
 }
 
+// Whether level 0 of this reconstruction runs by plane pairs (the kernel
+// that also writes marching cubes' bits).
+bool decode_tile0_used(const DecPlan &p) {
+  const Geo &g = p.g;
+  int64_t o[3], hi[3];
+  block_ext(g, 0, o, hi);
+  const bool slab32 = 4.0 * (double)(hi[0] - o[0] + 1) * (double)g.n[1] * (double)g.n[2] < 4294967296.0;
+  return p.lo == 0 && p.tile0 && g.B == 64 && g.nL >= 2 && slab32 && p.l0.small && !g.diff && !g.lossless;
+}
+
 void launch_decode(const DecPlan &p, hipStream_t s) {
   const Geo &g = p.g;
   const int L = g.nL - 1;
@@ -949,7 +1044,7 @@ void launch_decode(const DecPlan &p, hipStream_t s) {
     const Sec s0 = sec_geom(o, hi, 0, L);
     const int64_t ntile = ceil_div(ceil_div(s0.npts, 64), 64);
     prof_mark("k_decode_fine", s, 0);
-    if (p.tile0 && g.B == 64 && L >= 1 && slab32 && p.l0.small && !g.diff && !g.lossless) {
+    if (decode_tile0_used(p)) {
       k_decode_l0t<<<dim3((unsigned)((g.B + 2) / 2), (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
     } else if (L >= 1 && slab32 && p.l0.small) {
       const int64_t nch0 = ceil_div(s0.npts, 64);

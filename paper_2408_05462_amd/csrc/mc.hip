@@ -530,6 +530,23 @@ void launch_mc(const McPlan &p0, U4 *scan_tmp, hipStream_t s) {
   launch_mc_emit(p, s);
 }
 
+void launch_mc_bits(const McPlan &p0, hipStream_t s) {
+  const McPlan p = with_divisors(p0);
+  prof_mark("k_mc_bits", s, 0);
+  k_mc_bits<<<dim3((unsigned)ceil_div(p.nrows, kWaves)), dim3(kBS), 0, s>>>(p);
+  prof_mark("k_mc_bits", s, 1);
+}
+
+void launch_mc_from_bits(const McPlan &p0, U4 *scan_tmp, hipStream_t s) {
+  const McPlan p = with_divisors(p0);
+  const int64_t nwords = p.nrows * p.nw;
+  prof_mark("k_mc_count", s, 0);
+  k_mc_count<<<dim3((unsigned)ceil_div(nwords, kBS)), dim3(kBS), 0, s>>>(p);
+  prof_mark("k_mc_count", s, 1);
+  scan_u4(p.cnt, p.P, nwords, scan_tmp, s);
+  launch_mc_emit(p, s);
+}
+
 void launch_mc_cases(const McPlan &p0, hipStream_t s) {
   const McPlan p = with_divisors(p0);
   const int64_t nwords = p.nrows * p.nw;

@@ -154,6 +154,45 @@ def test_batch_autotune_and_cache(data, tmp_path):
     b2.close()
 
 
+def test_batch_tune_picks_a_configuration_and_keeps_outputs(data, tmp_path):
+    """The eager-timed search (brick size, branches, tiles) ends with a
+    captured graph whose replays give the oracle's outputs for the chosen
+    brick size (the oracle's stream at that size; reconstructions and meshes
+    do not depend on it); a second batch takes the configuration from the
+    cache file."""
+    fields, xs, singles = data
+    cache = tmp_path / "tune.txt"
+    b = _batch(fields, xs)
+    B = b.tune(cache)
+    cfg = b.config()
+    print("tuned", B, cfg, flush=True)
+    assert B in (0, 32, 64, 128) and 1 <= cfg["branches"] <= len(ITEMS) and cfg["last_ms"] > 0
+    refs = singles
+    if B:
+        refs = []
+        for (f, e, isos, nL, _), (s_ref, y_ref, m_ref) in zip(fields, singles):
+            refs.append((oracle.compress(f, e, isos, levels=nL, block=B)["stream"].tobytes(), y_ref, m_ref))
+    for r in b.recon:
+        r.fill_(float("nan"))
+    torch.cuda.synchronize()
+    b.replay()
+    torch.cuda.synchronize()
+    _check(b, refs, f"tuned {B} {cfg}")
+    line = cache.read_text().split()
+    assert len(line) == 5 and [int(v) for v in line[1:]] == [cfg["branches"], B, cfg["enc_cpw"], cfg["dec_cpw"]]
+    b2 = _batch(fields, xs)
+    assert b2.tune(cache) == B
+    assert len(cache.read_text().splitlines()) == 1
+    for r in b2.recon:
+        r.fill_(float("nan"))
+    torch.cuda.synchronize()
+    b2.replay()
+    torch.cuda.synchronize()
+    _check(b2, refs, "cached")
+    b.close()
+    b2.close()
+
+
 def test_tiles_do_not_change_results(data):
     fields, xs, singles = data
     f, e, isos, nL, B = fields[5]
