@@ -330,8 +330,10 @@ int chr_set_level0_tiles(int on);
  * once: timesteps or bricks of uneven sizes, each with its own isovalues.
  * Nothing in the arithmetic changes: every item runs the same kernels with
  * the same launch plans as chr_compress (no codes/flags output),
- * chr_reconstruct at level 0 and iso_extract, so each of its outputs is bit
- * for bit what those calls give. */
+ * chr_reconstruct_bits for its isovalues and iso_extract_bits, so each of its
+ * outputs is bit for bit what chr_compress, chr_reconstruct at level 0 and
+ * iso_extract give.  Its field is not read again for classification: the
+ * level-0 decoder writes every isovalue's bits as it reconstructs. */
 
 /* One field of a batch.  All pointers are caller-owned device buffers that
  * must stay valid while the batch (or its captured graph) is in use. */

@@ -39,6 +39,21 @@ struct ItemJobs {
   McJob mc[kMaxIso];
 };
 
+// Bytes of an item's classification bit planes (one per isovalue), which the
+// level-0 decoder writes and marching cubes reads; they sit at the start of
+// the branch's region, before the decode / extract scratch.
+size_t bits_bytes(const chr_batch_item &it) {
+  const size_t plane = (size_t)it.dims[0] * (size_t)it.dims[1] * (size_t)((it.dims[2] + 63) / 64);
+  return align256(8 * plane * (size_t)it.n_iso);
+}
+
+// One branch's bytes for an item: compression uses the whole region; then
+// the bit planes, followed by the reconstruction's or marching cubes'
+// scratch.
+size_t item_bytes(size_t we, size_t wd, size_t wm, size_t wb) {
+  return align256(std::max(we, wb + std::max(wd, wm)));
+}
+
 double item_weight(const chr_batch_item &it) {
   return (double)it.dims[0] * (double)it.dims[1] * (double)it.dims[2] * (2.0 + 0.3 * it.n_iso);
 }
@@ -114,13 +129,26 @@ int plan(const chr_batch *b, void *d_ws, size_t ws_bytes, std::vector<ItemJobs> 
     int rc = enc_prepare(it.d_field, it.dims, it.error_bound, it.isovalues, it.n_iso, &it.params, it.d_stream,
                          it.stream_capacity, it.d_result, nullptr, nullptr, ws, b->ws_branch, b->enc_cpw, jobs[i].enc);
     if (rc) return rc;
-    rc = dec_prepare(b->geo[i], b->payload_off[i], 0, it.d_stream, it.stream_capacity, it.d_recon, it.d_status, ws,
-                     b->ws_branch, b->dec_cpw, jobs[i].dec);
+    const size_t wb = it.n_iso > 0 ? bits_bytes(it) : 0;
+    unsigned long long *bits = reinterpret_cast<unsigned long long *>(ws);
+    rc = dec_prepare(b->geo[i], b->payload_off[i], 0, it.d_stream, it.stream_capacity, it.d_recon, it.d_status,
+                     ws + wb, b->ws_branch - wb, b->dec_cpw, jobs[i].dec);
     if (rc) return rc;
+    const int64_t plane = it.dims[0] * it.dims[1] * ((it.dims[2] + 63) / 64);
+    if (it.n_iso > 0) {
+      // the level-0 decoder writes the bits of every isovalue
+      DecPlan &D = jobs[i].dec.D;
+      D.bits = bits;
+      D.bnw = (it.dims[2] + 63) / 64;
+      D.bplane = plane;
+      D.nk = it.n_iso;
+      for (int j = 0; j < it.n_iso; j++) D.kb[j] = it.isovalues[j];
+    }
     for (int j = 0; j < it.n_iso; j++) {
       rc = mc_prepare(it.d_recon, it.dims, it.isovalues[j], it.spacing, it.d_vertices[j], it.cap_v[j], it.d_tris[j],
-                      it.cap_t[j], it.d_counts + 2 * j, ws, b->ws_branch, jobs[i].mc[j]);
+                      it.cap_t[j], it.d_counts + 2 * j, ws + wb, b->ws_branch - wb, jobs[i].mc[j]);
       if (rc) return rc;
+      jobs[i].mc[j].M.bits = bits + (size_t)j * (size_t)plane;
     }
   }
   return CHR_OK;
@@ -138,7 +166,9 @@ void enqueue(chr_batch *b, const std::vector<ItemJobs> &jobs, const std::vector<
     launch_encode(jobs[i].enc.P, 0, jobs[i].enc.scan, jobs[i].enc.scan64, bs);
     if (it.d_status) launch_status_reset(it.d_status, bs);
     launch_decode(jobs[i].dec.D, bs);
-    for (int k = 0; k < it.n_iso; k++) launch_mc(jobs[i].mc[k].M, jobs[i].mc[k].scan, bs);
+    if (it.n_iso > 0 && !decode_tile0_used(jobs[i].dec.D))
+      for (int k = 0; k < it.n_iso; k++) launch_mc_bits(jobs[i].mc[k].M, bs);   // another decoder ran
+    for (int k = 0; k < it.n_iso; k++) launch_mc_from_bits(jobs[i].mc[k].M, jobs[i].mc[k].scan, bs);
   }
   for (int j = 0; j < b->branches; j++) {
     hipEventRecord(b->join[j], b->streams[j]);
@@ -251,7 +281,7 @@ size_t branch_bytes(const chr_batch *b, const std::vector<Geo> &geo) {
     const size_t wd = dec_workspace_bytes(geo[i], 0);
     const size_t wm = it.n_iso > 0 ? mc_workspace_bytes(it.dims) : 0;
     if (!we || (it.n_iso > 0 && !wm)) return 0;
-    ws = std::max(ws, align256(std::max(we, std::max(wd, wm))));
+    ws = std::max(ws, item_bytes(we, wd, wm, it.n_iso > 0 ? bits_bytes(it) : 0));
   }
   return ws;
 }
@@ -362,7 +392,7 @@ int chr_batch_create(const chr_batch_item *items, int n_items, chr_batch **out) 
     const size_t wd = dec_workspace_bytes(b->geo[i], 0);
     const size_t wm = it.n_iso > 0 ? mc_workspace_bytes(it.dims) : 0;
     if (!we || (it.n_iso > 0 && !wm)) { delete b; return api_fail(CHR_E_INVAL, at + chr_last_error()); }
-    b->ws_branch = std::max(b->ws_branch, align256(std::max(we, std::max(wd, wm))));
+    b->ws_branch = std::max(b->ws_branch, item_bytes(we, wd, wm, it.n_iso > 0 ? bits_bytes(it) : 0));
   }
   for (const chr_batch_item &it : b->items) b->block0.push_back(it.params.block);
   b->max_branches = std::min(kMaxBranches, n_items);
