@@ -97,6 +97,15 @@ void set_quant(Geo &g, double e) {
     g.step = (float)(2.0 * e);
   }
   g.lossless = (!(e > 0) || g.step == 0.0f || !std::isfinite(g.step)) ? 1 : 0;
+  // fl(d) = d (1 + r) with |r| <= 2^-24, so |fl(d)| <= e (1 - 2^-23) gives
+  // |d| <= e (1 - 2^-23) / (1 - 2^-24) < e; rounded down to binary32
+  g.ein = 0.f;
+  if (e > 0) {
+    const double t = e * (1.0 - 0x1p-23);
+    float f = (float)t;
+    if ((double)f > t) f = std::nextafter(f, 0.0f);
+    g.ein = f;
+  }
 }
 
 // The far quantizer of differentiated error control (same rule as set_quant).

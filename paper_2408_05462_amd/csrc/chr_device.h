@@ -46,6 +46,9 @@ struct Geo {
   double e;
   float inv, step;
   int lossless;
+  // a binary32 bound below e by more than the rounding of one binary32
+  // subtraction: |fl(x' - x)| <= ein proves |x' - x| <= e exactly
+  float ein;
   float iso[kMaxIso];
   // differentiated error control: points of no block crossing a candidate
   // isovalue use the far quantizer (diff = 0: one quantizer everywhere)
@@ -328,6 +331,12 @@ __device__ inline float midpoint_rows(const float *__restrict__ r00, const float
 // Holds a value in a register at this point of the program: the arithmetic
 // that produces it stays above, instead of being moved into the branch that
 // uses it (so every load it reads is waited for before any later store).
+// v_writelane: lane L (wave-uniform, through M0) of dst takes the
+// wave-uniform value v.
+__device__ __forceinline__ void writelane(uint32_t &dst, uint32_t v, uint32_t L) {
+  asm volatile("s_mov_b32 m0, %2\n\tv_writelane_b32 %0, %1, m0" : "+v"(dst) : "s"(v), "s"(L) : "m0");
+}
+
 __device__ inline void hold(float &v) { asm volatile("" : "+v"(v)); }
 __device__ inline void hold(uint32_t &v) { asm volatile("" : "+v"(v)); }
 
@@ -341,6 +350,9 @@ __device__ inline uint32_t ldu(const char *__restrict__ base, uint32_t off) {
 }
 __device__ inline void stf(char *__restrict__ base, uint32_t off, float v) {
   *reinterpret_cast<float *>(base + off) = v;
+}
+__device__ inline void stu(char *__restrict__ base, uint32_t off, uint32_t v) {
+  *reinterpret_cast<uint32_t *>(base + off) = v;
 }
 
 // Level-0 section geometry of the (at most 8) block shapes -- interior or

@@ -571,12 +571,6 @@ struct D0Bits {
   uint32_t lo[2], hi[2];
 };
 
-// v_writelane: lane L (wave-uniform, through M0) of dst takes the
-// wave-uniform value v.
-__device__ __forceinline__ void writelane(uint32_t &dst, uint32_t v, uint32_t L) {
-  asm volatile("s_mov_b32 m0, %2\n\tv_writelane_b32 %0, %1, m0" : "+v"(dst) : "s"(v), "s"(L) : "m0");
-}
-
 // Words of the group's rows for isovalues j in [j0, j1) (j1 - j0 <= 8) into
 // one word set: isovalue j, row k at lane 8 (j - j0) + k.
 __device__ __forceinline__ void d0_bits_set(const DecPlan &D, uint32_t &lo, uint32_t &hi, const float (&rv)[kD0Rows],
@@ -635,23 +629,29 @@ __global__ __launch_bounds__(kBS) void k_decode_l0t(DecPlan D) {
   const uint32_t gy = (bp.hi[1] >> 1) - oy1 + 1, gx = (bp.hi[2] >> 1) - ox1 + 1;
   const uint32_t np = zl0 + 1 < h0 ? 2u : 1u;
   {
-    // the level-1 planes; lanes and rows past them load and store a copy of
-    // the last one
-    const float *__restrict__ G1 = D.gp[1];
-    const uint32_t nrows = np * gy, xl1 = min((uint32_t)lane, gx - 1);
-    // at most 2 * 33 rows: a wave's (at most 17) loads are all issued first
-    constexpr int kR = (2 * kD0Side + kWaves - 1) / kWaves;
-    float tv[kR];
-    uint32_t so[kR];
+    // the level-1 planes: rows past the block and lanes past a row load (and
+    // store) a copy of the last one; without an upper plane the second
+    // staged plane is a copy of the first and is never read.  32-bit offsets
+    // from the block's first parent, loads of both planes issued first.
+    const char *__restrict__ g1b =
+        reinterpret_cast<const char *>(D.gp[1] + ((size_t)zl0 * h1 + oy1) * h2 + ox1);
+    const uint32_t xl1 = min((uint32_t)lane, gx - 1), planeB = (np - 1) * h1 * h2 * 4u, rowB1 = h2 * 4u;
+    constexpr int kRP = (kD0Side + kWaves - 1) / kWaves;
+    float tv[2][kRP];
 #pragma unroll
-    for (int u = 0; u < kR; u++) {
-      const uint32_t r = min(wave + (uint32_t)u * kWaves, nrows - 1);
-      const uint32_t pz = r >= gy ? 1u : 0u, yy = r - pz * gy;
-      tv[u] = G1[((size_t)(zl0 + pz) * h1 + oy1 + yy) * h2 + ox1 + xl1];
-      so[u] = pz * kD0Plane + yy * kD0Side + xl1;
-    }
+    for (int pz = 0; pz < 2; pz++)
 #pragma unroll
-    for (int u = 0; u < kR; u++) sg[so[u]] = tv[u];
+      for (int u = 0; u < kRP; u++) {
+        const uint32_t yy = min(wave + (uint32_t)u * kWaves, gy - 1);
+        tv[pz][u] = ldf(g1b, (uint32_t)pz * planeB + yy * rowB1 + xl1 * 4u);
+      }
+#pragma unroll
+    for (int pz = 0; pz < 2; pz++)
+#pragma unroll
+      for (int u = 0; u < kRP; u++) {
+        const uint32_t yy = min(wave + (uint32_t)u * kWaves, gy - 1);
+        sg[pz * kD0Plane + yy * kD0Side + xl1] = tv[pz][u];
+      }
   }
   {
     // chunk headers of the (at most three) 64-chunk tiles of the range:

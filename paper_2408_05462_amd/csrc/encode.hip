@@ -549,17 +549,21 @@ constexpr int kT0Side = 33;                  // level-1 points per axis of a 64-
 constexpr int kT0Plane = 1152;               // staged plane stride (floats): 33 rows of 33, a byte offset that
                                              // fits an LDS instruction's immediate
 constexpr int kT0Codes = 7361 + 63;          // most section points of a pair, plus a chunk's tail
+constexpr int kT0Spare = 64;                 // LDS codes before the tile's first chunk (at most 63 used)
 constexpr int kT0Group = 8;                  // rows whose loads a wave issues together
 constexpr uint16_t kT0Exact = 0xffffu;       // LDS code of a point stored exactly (codes are < 2^16 - 1)
 
-// Per-tile state of the finishing steps: LDS codes, the slots' exact values
-// and the wave's counts (wave-uniform: outliers, corrections, non-finite lanes).
+// Per-tile state of the finishing steps: LDS codes (indexed by section
+// position: `sc` is offset so that the points of the previous pair's last
+// chunk, at most 63 before the tile's first chunk, land in a spare prefix),
+// the slots' exact values, the wave's counts (wave-uniform: outliers,
+// corrections) and the lane's running minima and maxima of the reconstructed
+// and the input values (IEEE minimum / maximum: -0 below +0, NaN kept).
 struct T0Ctx {
-  uint32_t jbase;
   uint16_t *sc;
   float *exv;          // exact values of the block's level-0 slots, by lane position
   uint32_t nO, nC;
-  uint64_t nf;
+  float rmin, rmax, xmin, xmax;
 };
 
 // Ordered key of a binary32 value (as ord_of), in two instructions.
@@ -572,13 +576,14 @@ __device__ __forceinline__ uint32_t t0_ord(float f) {
 // of one point predicted as p, without branches: lanes outside the row hold
 // a copy of a point inside it (same value, same code, same LDS slot), so only
 // the counts are masked (`cmask`: lanes holding a point of the pair that the
-// block owns).  The outlier / correction logic runs on lane masks.  `ci`:
-// the point's LDS code index (points of the previous pair's last chunk map
-// to the spare entry past the codes; their exact values are written by both
-// pairs, identically).  LL: the lossless quantizer.
+// block owns).  The outlier / correction logic runs on lane masks: a point
+// changes side of some candidate exactly when one candidate's comparison
+// differs between x and x', so the correction mask is an OR of ballot XORs.
+// LL: the lossless quantizer.
 template <int KB, bool LL>
 __device__ __forceinline__ void t0_finish(const Geo &gq, const float (&iso)[KB], float x, float p, uint64_t cmask,
-                                          uint32_t j, uint32_t ci, T0Ctx &t, Part &acc) {
+                                          uint32_t jr, uint32_t jl, T0Ctx &t) {
+  // the point's section index is jr + jl: jr the row's (wave-uniform), jl the lane's
   uint64_t mO;
   float xc;
   int32_t q;
@@ -591,25 +596,32 @@ __device__ __forceinline__ void t0_finish(const Geo &gq, const float (&iso)[KB],
     xc = __fadd_rn(p, __fmul_rn(qf, gq.step));
     q = (int32_t)qf;
     const uint64_t mq = __ballot(fabsf(qf) <= (float)gq.qmax);
-    const uint64_t mb = __ballot(fabs((double)xc - (double)x) <= gq.e);
+    // the bound in binary32 first; the exact check in double only for a row
+    // where some lane is not clearly inside
+    uint64_t mb = __ballot(fabsf(__fsub_rn(xc, x)) <= gq.ein);
+    if (mb != ~0ull) mb = __ballot(fabs((double)xc - (double)x) <= gq.e);
     mO = ~(mq & mb);
   }
-  const uint64_t mr = __ballot(rank_of<KB>(iso, gq.K, x) != rank_of<KB>(iso, gq.K, xc));
+  uint64_t mr = 0;
+#pragma unroll
+  for (int jj = 0; jj < KB; jj++)
+    if (jj < gq.K) mr |= __ballot(iso[jj] <= x) ^ __ballot(iso[jj] <= xc);
   const uint64_t mE = mO | mr;                 // outlier, or a correction (side change, not an outlier)
   const bool E = __builtin_amdgcn_inverse_ballot_w64(mE);
   const float xr = E ? x : xc;
   const uint32_t zz = ((uint32_t)q << 1) ^ (uint32_t)(q >> 31);
-  const uint32_t ro = t0_ord(xr), xo = t0_ord(x);
-  acc.rmin = min(acc.rmin, ro); acc.rmax = max(acc.rmax, ro);
-  acc.xmin = min(acc.xmin, xo); acc.xmax = max(acc.xmax, xo);
-  t.nf |= __ballot(!isfinite(x));
-  t.sc[ci] = E ? kT0Exact : (uint16_t)zz;
+  t.rmin = __builtin_elementwise_minimum(t.rmin, xr);
+  t.rmax = __builtin_elementwise_maximum(t.rmax, xr);
+  t.xmin = __builtin_elementwise_minimum(t.xmin, x);
+  t.xmax = __builtin_elementwise_maximum(t.xmax, x);
+  uint16_t *scr = t.sc + jr;
+  scr[jl] = E ? kT0Exact : (uint16_t)zz;
   if (mE) {
     // a row with exact points (rare): the counts, and the exact values into
     // their slots (slot j / 64, lane j % 64)
     t.nO += (uint32_t)__popcll(mO & cmask);
     t.nC += (uint32_t)__popcll(~mO & mr & cmask);
-    if (E) t.exv[(size_t)j] = x;
+    if (E) t.exv[(size_t)(jr + jl)] = x;
   }
 }
 
@@ -639,9 +651,17 @@ __device__ __forceinline__ float t0_pred_any(const float *sg, bool zu, uint32_t 
 
 template <int KB, bool LL>
 __global__ __launch_bounds__(kBS) void k_encode_l0t(EncPlan P) {
-  __shared__ float sg[2 * kT0Plane];
-  __shared__ uint16_t sc[kT0Codes + 1];
-  __shared__ uint32_t pack[kWaves][32];
+  // one LDS record with the parent planes first, so that they sit at LDS
+  // address 0 and a row's parent offsets fit the read instructions' fields
+  struct Lds {
+    float sg[2 * kT0Plane];
+    uint16_t sc[kT0Spare + kT0Codes];
+    uint32_t pack[kWaves][64];
+  };
+  __shared__ __align__(16) Lds lds;
+  float *sg = lds.sg;
+  uint16_t *sc = lds.sc;
+  uint32_t (*pack)[64] = lds.pack;
   uint32_t w2, b;
   xcd_remap(w2, b);
   const Geo &gq = P.g;
@@ -670,12 +690,13 @@ __global__ __launch_bounds__(kBS) void k_encode_l0t(EncPlan P) {
   const uint32_t J1 = has_odd ? J0 + PP : J0 + s.Pe;
   const uint32_t cfirst = (J0 + 63) / 64, cend = (J1 + 63) / 64;
   const uint32_t jend = min(cend * 64, s.npts);
+  const uint32_t jbase = cfirst * 64;          // section index of the tile's first code
   T0Ctx t;
-  t.jbase = cfirst * 64;
-  t.sc = sc;
+  t.sc = sc + kT0Spare - jbase;                // t.sc[j] for jbase - 63 <= j < jend
   t.exv = P.exv + slot0 * 64;
   t.nO = t.nC = 0;
-  t.nf = 0;
+  t.rmin = t.xmin = __builtin_inff();
+  t.rmax = t.xmax = -__builtin_inff();
   const uint32_t n1 = (uint32_t)gq.n[1], n2 = (uint32_t)gq.n[2];
   const uint32_t mx = s.mx, my = s.my, rowE = s.rowE, RP = rowE + mx;
   // the two level-1 planes (z = (o_z + we) / 2 and the next) of the block
@@ -684,22 +705,29 @@ __global__ __launch_bounds__(kBS) void k_encode_l0t(EncPlan P) {
   const uint32_t gy = (bp.hi[1] >> 1) - oy1 + 1, gx = (bp.hi[2] >> 1) - ox1 + 1;
   const uint32_t np = zl0 + 1 < h0 ? 2u : 1u;
   {
-    // lanes and rows past the planes load and store a copy of the last one
-    const float *__restrict__ G1 = P.G + P.g_off[1];
-    const uint32_t nrows = np * gy, xl = min((uint32_t)lane, gx - 1);
-    // at most 2 * 33 rows: a wave's (at most 17) loads are all issued first
-    constexpr int kR = (2 * kT0Side + kWaves - 1) / kWaves;
-    float tv[kR];
-    uint32_t so[kR];
+    // rows past the block and lanes past a row load (and store) a copy of
+    // the last one; without an upper plane the second staged plane is a
+    // copy of the first and is never read.  32-bit offsets from the block's
+    // first parent, loads of both planes issued before the stores.
+    const char *__restrict__ g1b =
+        reinterpret_cast<const char *>(P.G + P.g_off[1] + ((size_t)zl0 * h1 + oy1) * h2 + ox1);
+    const uint32_t xl = min((uint32_t)lane, gx - 1), planeB = (np - 1) * h1 * h2 * 4u, rowB1 = h2 * 4u;
+    constexpr int kRP = (kT0Side + kWaves - 1) / kWaves;
+    float tv[2][kRP];
 #pragma unroll
-    for (int u = 0; u < kR; u++) {
-      const uint32_t r = min(wave + (uint32_t)u * kWaves, nrows - 1);
-      const uint32_t pz = r >= gy ? 1u : 0u, yy = r - pz * gy;
-      tv[u] = G1[((size_t)(zl0 + pz) * h1 + oy1 + yy) * h2 + ox1 + xl];
-      so[u] = pz * kT0Plane + yy * kT0Side + xl;
-    }
+    for (int pz = 0; pz < 2; pz++)
 #pragma unroll
-    for (int u = 0; u < kR; u++) sg[so[u]] = tv[u];
+      for (int u = 0; u < kRP; u++) {
+        const uint32_t yy = min(wave + (uint32_t)u * kWaves, gy - 1);
+        tv[pz][u] = ldf(g1b, (uint32_t)pz * planeB + yy * rowB1 + xl * 4u);
+      }
+#pragma unroll
+    for (int pz = 0; pz < 2; pz++)
+#pragma unroll
+      for (int u = 0; u < kRP; u++) {
+        const uint32_t yy = min(wave + (uint32_t)u * kWaves, gy - 1);
+        sg[pz * kT0Plane + yy * kT0Side + xl] = tv[pz][u];
+      }
   }
   float iso[KB];
 #pragma unroll
@@ -713,7 +741,7 @@ __global__ __launch_bounds__(kBS) void k_encode_l0t(EncPlan P) {
   const uint32_t xe0 = ((we * n1 + bp.o[1]) * n2 + bp.o[2]) * 4u;     // even plane, row 0
   const uint32_t xo0 = xe0 + n1 * n2 * 4u;                          // odd plane, row 0
   // codes past the section in its last chunk read as 0 when packing
-  if (cend > cfirst && cend * 64 > s.npts && threadIdx.x < cend * 64 - s.npts) sc[s.npts - t.jbase + threadIdx.x] = 0;
+  if (cend > cfirst && cend * 64 > s.npts && threadIdx.x < cend * 64 - s.npts) t.sc[s.npts + threadIdx.x] = 0;
   // Every x row a wave needs is loaded before the barrier (at most 5 A, 8 B
   // and 9 C/D row pairs per wave for 65-point blocks): A rows v = 4a +
   // 2*half (odd u = 2i + 1), B rows v = 2f + 1, C/D rows 2m and 2m + 1.  A
@@ -763,11 +791,10 @@ __global__ __launch_bounds__(kBS) void k_encode_l0t(EncPlan P) {
       const uint32_t vc = v < my ? v : v - 2;
       const uint32_t ga = (vc >> 1) * (kT0Side * 4u) + lg;
       const float p = t0_xavg(lds_at(sgb, ga), lds_at(sgb, ga + 4), xav);
-      const uint32_t j = J0 + (vc >> 1) * RP + iA;
+      const uint32_t jA = J0 + (vc >> 1) * RP;
       const uint64_t h0 = (4 * a < my && 4 * a < owny) ? 0x00000000ffffffffull : 0ull;
       const uint64_t h1 = (4 * a + 2 < my && 4 * a + 2 < owny) ? 0xffffffff00000000ull : 0ull;
-      t0_finish<KB, LL>(gq, iso, xa[k], p, we < ownz ? lane_in & (h0 | h1) : 0ull, j,
-                        min(j - t.jbase, (uint32_t)kT0Codes), t, acc);
+      t0_finish<KB, LL>(gq, iso, xa[k], p, we < ownz ? lane_in & (h0 | h1) : 0ull, jA, iA, t);
     }
   }
   const uint32_t lx0 = u >> 1;
@@ -788,8 +815,7 @@ __global__ __launch_bounds__(kBS) void k_encode_l0t(EncPlan P) {
     hold(pb);
     const float p = yu ? pb : A;
     const uint32_t jr = J0 + f * RP + rowE;
-    t0_finish<KB, LL>(gq, iso, xb[k], p, (we < ownz && 2 * f + 1 < owny) ? lane_in : 0ull, jr + u,
-                      min(jr + u - t.jbase, (uint32_t)kT0Codes), t, acc);
+    t0_finish<KB, LL>(gq, iso, xb[k], p, (we < ownz && 2 * f + 1 < owny) ? lane_in : 0ull, jr, u, t);
   }
   // ---- C and D rows: the odd plane's rows 2m (y even) and 2m + 1 (y odd)
   {
@@ -806,8 +832,7 @@ __global__ __launch_bounds__(kBS) void k_encode_l0t(EncPlan P) {
       hold(pc);
       const float p = zu ? pc : A;
       const uint32_t jc = jo + 2 * m * mx;
-      t0_finish<KB, LL>(gq, iso, xc[k], p, (zown && 2 * m < owny) ? lane_in : 0ull, jc + u,
-                        min(jc + u - t.jbase, (uint32_t)kT0Codes), t, acc);
+      t0_finish<KB, LL>(gq, iso, xc[k], p, (zown && 2 * m < owny) ? lane_in : 0ull, jc, u, t);
       if (2 * m + 1 < my) {
         const bool yu = m + 1 < gy;
         const float B = t0_xavg(lds_at(sgb, ga + kRow), lds_at(sgb, ga + kRow + 4), xav);
@@ -820,8 +845,7 @@ __global__ __launch_bounds__(kBS) void k_encode_l0t(EncPlan P) {
         float pd = avg2(p0, p1);
         hold(pd);
         const float p2 = zu ? pd : p0;
-        t0_finish<KB, LL>(gq, iso, xd[k], p2, (zown && 2 * m + 1 < owny) ? lane_in : 0ull, jc + mx + u,
-                          min(jc + mx + u - t.jbase, (uint32_t)kT0Codes), t, acc);
+        t0_finish<KB, LL>(gq, iso, xd[k], p2, (zown && 2 * m + 1 < owny) ? lane_in : 0ull, jc + mx, u, t);
       }
     }
   }
@@ -835,65 +859,69 @@ __global__ __launch_bounds__(kBS) void k_encode_l0t(EncPlan P) {
       const float x = ldf(xbase, ((w * n1 + bp.o[1] + v) * n2 + bp.o[2] + 64u) * 4u);
       const float p = t0_pred_any(sg, (w & 1u) && zu, v, 64u, gy, gx);
       const uint32_t j = ev ? J0 + (v >> 1) * RP + rowE + 64u : J0 + s.Pe + v * mx + 64u;
-      t0_finish<KB, LL>(gq, iso, x, p, __ballot(fr < nF && w < ownz && v < owny && 64u < ownx), j,
-                        min(j - t.jbase, (uint32_t)kT0Codes), t, acc);
+      t0_finish<KB, LL>(gq, iso, x, p, __ballot(fr < nF && w < ownz && v < owny && 64u < ownx), 0u, j, t);
     }
   }
   // ---- the tail of the last chunk (the next planes' first points; more
   // than one pair when a pair holds fewer than 64 points), parents read from
   // the level-1 grid in memory; not counted (the next pairs count them)
-  if (jend > J1 && t.jbase < jend && wave == kWaves - 1) {
+  if (jend > J1 && jbase < jend && wave == kWaves - 1) {
     const uint32_t j = min(J1 + (uint32_t)lane, jend - 1);
     uint32_t w, v, uu;
     sec_point24(s, rc, j, w, v, uu);
     const float x = ldf(xbase, ((w * n1 + bp.o[1] + v) * n2 + bp.o[2] + uu) * 4u);
     const float p = predict(P.G + P.g_off[1], h0, h1, h2, 0, bp.o[0] + w, bp.o[1] + v, bp.o[2] + uu);
-    t0_finish<KB, LL>(gq, iso, x, p, 0ull, j, min(j - t.jbase, (uint32_t)kT0Codes), t, acc);
+    t0_finish<KB, LL>(gq, iso, x, p, 0ull, 0u, j, t);
   }
   __syncthreads();
 
   // ---- pack the pair's chunks from LDS into their slots (exact values are
-  // already in the slots, at their lanes: count word 3 says so)
-  uint32_t *pk = pack[wave];
-  for (uint32_t c = cfirst + wave; c < cend; c += kWaves) {
-    const uint32_t v16 = sc[c * 64 - t.jbase + (uint32_t)lane];
-    const bool E = v16 == kT0Exact;
-    const uint32_t zz = E ? 0u : v16;
-    const int64_t slot = slot0 + c;
-    // the chunk's width: bit length of the largest code, by a search over
-    // ballots (codes are below 2^16)
-    int wb = 0;
-    if (__ballot(zz != 0u)) {
-      uint32_t h = __ballot(zz >= 256u) ? 8u : 0u;
-      if (__ballot(zz >= (16u << h))) h += 4u;
-      if (__ballot(zz >= (4u << h))) h += 2u;
-      if (__ballot(zz >= (2u << h))) h += 1u;
-      wb = (int)h + 1;
-    }
-    const unsigned long long em = __ballot(E);
-    if (lane < 32) pk[lane] = 0u;
+  // already in the slots, at their lanes: count word 3 says so).  The wave
+  // packs chunks cfirst + wave + 4k; the counts of its chunk k wait in lane
+  // k of a register and are stored together after the loop.
+  uint32_t *pk = pack[wave];                   // 64 words, every lane clears its own
+  char *__restrict__ payw = reinterpret_cast<char *>(P.pay + slot0 * 32);
+  const uint32_t c0 = cfirst + wave;
+  const uint32_t nmine = cend > c0 ? (cend - c0 + kWaves - 1) / kWaves : 0u;
+  uint32_t cw = 0;                             // lane k: width | exact points << 8 | has exact << 16
+  for (uint32_t k = 0; k < nmine; k++) {
+    const uint32_t c = c0 + k * kWaves;
+    const uint32_t v16 = t.sc[c * 64 + (uint32_t)lane];
+    const uint64_t em = __ballot(v16 == kT0Exact);
+    const uint32_t zz = __builtin_amdgcn_inverse_ballot_w64(em) ? 0u : v16;
+    // the chunk's width: bit length of the OR of its codes
+    const uint32_t orv = wave_or_dpp(zz);
+    const uint32_t wb = orv ? 32u - (uint32_t)__clz((int)orv) : 0u;
+    pk[lane] = 0u;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     if (zz) {
-      const uint32_t bit = mul24s((uint32_t)lane, (uint32_t)wb), wi = bit >> 5, off = bit & 31u;
+      const uint32_t bit = mul24s((uint32_t)lane, wb), wi = bit >> 5, off = bit & 31u;
       __hip_atomic_fetch_or(&pk[wi], zz << off, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-      if (off + (uint32_t)wb > 32u)
+      if (off + wb > 32u)
         __hip_atomic_fetch_or(&pk[wi + 1], zz >> (32u - off), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    if (lane < 2 * wb) P.pay[slot * 32 + lane] = pk[lane];
-    if (lane == 0) {
-      P.cnt[slot] = U4{(uint32_t)wb, em ? 1u : 0u, (uint32_t)__popcll(em), em ? 1u : 0u};
-      if (em) P.emask[slot] = em;
-    }
+    if ((uint32_t)lane < 2 * wb) stu(payw, (c * 32 + (uint32_t)lane) * 4u, pk[lane]);
+    writelane(cw, wb | ((uint32_t)__popcll(em) << 8) | (em ? 0x10000u : 0u), k);
+    if (em && lane == 0) P.emask[slot0 + c] = em;
     __builtin_amdgcn_wave_barrier();
   }
-  // the wave's counts join the lane records (once per wave)
+  if ((uint32_t)lane < nmine) {
+    const uint32_t he = (cw >> 16) & 1u;
+    P.cnt[slot0 + c0 + (uint32_t)lane * kWaves] = U4{cw & 0xffu, he, (cw >> 8) & 0xffu, he};
+  }
+  // the lane's extremes as order-preserving keys (a lane that saw no point
+  // keeps +inf / -inf, which no finite value loses to); a non-finite input
+  // shows as an infinite extreme or a NaN; the wave's counts join the lane
+  // records once per wave
+  acc.rmin = t0_ord(t.rmin); acc.rmax = t0_ord(t.rmax);
+  acc.xmin = t0_ord(t.xmin); acc.xmax = t0_ord(t.xmax);
+  acc.nonfinite = (t.xmin > -__builtin_inff() && t.xmax < __builtin_inff()) ? 0u : 1u;
   if (lane == 0) {
     acc.nO = t.nO;
     acc.nC = t.nC;
-    acc.nonfinite = t.nf != 0 ? 1u : 0u;
   }
   part_store(acc, rec);
 }
