@@ -369,7 +369,7 @@ int dec_prepare(const Geo &g, uint64_t payload_off, int level, const void *d_str
   return CHR_OK;
 }
 
-static int mc_plan(const float *d_field, const int64_t dims[3], McPlan &M, size_t &need, size_t off[6]) {
+static int mc_plan(const float *d_field, const int64_t dims[3], McPlan &M, size_t &need, size_t off[7]) {
   std::memset(&M, 0, sizeof(M));
   if (!dims_ok(dims)) return fail(CHR_E_INVAL, "dims must be in [1, 2^30]");
   for (int a = 0; a < 3; a++) M.n[a] = dims[a];
@@ -387,14 +387,15 @@ static int mc_plan(const float *d_field, const int64_t dims[3], McPlan &M, size_
   off[2] = o; o = align256(o + sizeof(U4) * (size_t)(nwords + 1));
   off[3] = o; o = align256(o + sizeof(U4) * (size_t)scan_tmp_elems(nwords));
   off[4] = o; o = align256(o + sizeof(uint32_t) * (size_t)(nwords * 64));
-  off[5] = o; o = align256(o + sizeof(uint2) * (size_t)(nwords * 64));
+  off[5] = o; o = align256(o + sizeof(uint32_t) * (size_t)(nwords * 64));
+  off[6] = o; o = align256(o + sizeof(uint32_t) * (size_t)(nwords / 4 + 1));
   need = o;
   return CHR_OK;
 }
 
 size_t mc_workspace_bytes(const int64_t dims[3]) {
   McPlan M;
-  size_t need = 0, off[6];
+  size_t need = 0, off[7];
   if (mc_plan(nullptr, dims, M, need, off)) return 0;
   return need;
 }
@@ -406,7 +407,7 @@ int mc_prepare(const float *d_field, const int64_t dims[3], float isovalue, floa
   if (cap_v < 0 || cap_t < 0 || (cap_v && !d_vertices) || (cap_t && !d_tris)) return fail(CHR_E_INVAL, "bad capacity");
   if (!std::isfinite(isovalue) || !std::isfinite(spacing)) return fail(CHR_E_INVAL, "isovalue and spacing must be finite");
   McPlan &M = J.M;
-  size_t need = 0, off[6];
+  size_t need = 0, off[7];
   int rc = mc_plan(d_field, dims, M, need, off);
   if (rc) return rc;
   if (ws_bytes < need) return fail(CHR_E_NOMEM, "workspace too small: need " + std::to_string(need));
@@ -415,7 +416,8 @@ int mc_prepare(const float *d_field, const int64_t dims[3], float isovalue, floa
   M.cnt = reinterpret_cast<U4 *>(ws + off[1]);
   M.P = reinterpret_cast<U4 *>(ws + off[2]);
   M.vlist = reinterpret_cast<uint32_t *>(ws + off[4]);
-  M.clist = reinterpret_cast<uint2 *>(ws + off[5]);
+  M.clist = reinterpret_cast<uint32_t *>(ws + off[5]);
+  M.tb = reinterpret_cast<uint32_t *>(ws + off[6]);
   M.cap_pv = M.cap_ac = M.nrows * M.nw * 64;
   M.k = isovalue;
   M.spacing = spacing;
@@ -703,7 +705,7 @@ int chr_reconstruct_bits(const chr_info *info, const void *d_stream, size_t stre
   if (!(error_bound >= stream_bound(*info))) return fail(CHR_E_ACCURACY, "requested error bound below the stream's");
   if (stream_bytes < info->total_bytes) return fail(CHR_E_CORRUPT, "stream shorter than its header states");
   McPlan M;
-  size_t mneed = 0, moff[6];
+  size_t mneed = 0, moff[7];
   rc = mc_plan(d_out, info->dims, M, mneed, moff);
   if (rc) return rc;
   DecJob J;
@@ -803,7 +805,7 @@ int iso_cases(const float *d_field, const int64_t dims[3], float isovalue, uint8
               size_t ws_bytes, void *stream) {
   if (!d_field || !d_cases || !d_ws) return fail(CHR_E_INVAL, "NULL argument");
   McPlan M;
-  size_t need = 0, off[6];
+  size_t need = 0, off[7];
   int rc = mc_plan(d_field, dims, M, need, off);
   if (rc) return rc;
   if (ws_bytes < need) return fail(CHR_E_NOMEM, "workspace too small");

@@ -92,7 +92,8 @@ struct McPlan {
   unsigned long long *bits;      // nrows * nw below-isovalue bits
   U4 *cnt, *P;                   // per word {vertices, triangles, crossing points, active cells} and prefix
   uint32_t *vlist;               // crossing points (word*64 + bit), cap_pv entries
-  uint2 *clist;                  // active cells (word*64 + bit, first triangle id), cap_ac entries
+  uint32_t *clist;               // active cells (word*64 + bit), cap_ac entries
+  uint32_t *tb;                  // first triangle id of every 256th active cell, cap_ac / 256 + 1 entries
   int64_t cap_pv, cap_ac;
   float *verts;
   int32_t *tris;

@@ -6,14 +6,20 @@
 //  1. k_mc_bits:   coalesced streaming pass, a ballot per 64 points.
 //  2. k_mc_count:  one lane per word: its crossing +x/+y/+z edges (XORs of
 //     neighbouring words, popcount), the points carrying them, its active
-//     cells (corners disagree) and their triangles (generated table in LDS).
+//     cells (corners disagree) and their triangles, counted on the 64 cells
+//     at once from the crossed cell edges (E - 2 per single-loop cell, table
+//     corrections for the rare cells that may hold several loops).
 //  3. scan of the per-word {vertices, triangles, crossing points, active cells}.
-//  4. k_mc_expand: one lane per word writes compact lists of its crossing
-//     points and of its active cells (with each cell's first triangle id).
+//  4. k_mc_expand: compact lists of the crossing points and of the active
+//     cells, written word after word by the lanes of the word's set bits
+//     (consecutive entries, coalesced stores).
 //  5. k_mc_verts / k_mc_tris: one lane per list entry, so lanes stay dense
 //     however sparse the surface is.  The id of the vertex on an edge owned by
 //     point x' of word W is W's vertex base plus the popcount of W's crossing
-//     masks below x' -- no per-point id array.
+//     masks below x' -- no per-point id array.  A workgroup of k_mc_tris
+//     takes 256 consecutive active cells: its first triangle id from the
+//     word prefix and the cells before it in their word, the others by a
+//     workgroup scan of the cells' triangle counts.
 #include "chr_plan.h"
 #include "mc_table.h"
 
@@ -26,6 +32,9 @@ constexpr int kWordsPerWave = 8;
 
 constexpr mct::Table kTable = mct::make_table();
 __constant__ mct::Table c_table = kTable;
+static_assert(mct::loop_rule_holds(kTable), "a case outside multi_loop_possible has more than one loop");
+constexpr mct::LoopFix kFix = mct::make_loop_fix(kTable);
+__constant__ mct::LoopFix c_fix = kFix;
 
 constexpr int max_ntri(const mct::Table &t) {
   int m = 0;
@@ -175,9 +184,49 @@ __device__ inline u64 active_cells(const Corners &C, u64 validx) {
   return any & ~all & validx;
 }
 
+// Triangles of the active cells `act` of a word with corner masks C: the
+// crossed cell edges, minus two per active cell, plus the table's correction
+// of each cell whose case may hold several loops (any ambiguous face, or the
+// below or the above corners a lone body-diagonal pair; few cells).
+__device__ inline uint32_t word_tris(const Corners &C, u64 act, const int8_t *fix) {
+  uint32_t e = 0;
+#pragma unroll
+  for (int k = 0; k < 12; k++) {
+    const mct::Edge E = mct::edge_of(k);
+    e += (uint32_t)__popcll((C.m[E.lo] ^ C.m[E.hi]) & act);
+  }
+  u64 multi = 0;
+#pragma unroll
+  for (int f = 0; f < 6; f++) {
+    const u64 a = C.m[mct::kFaces[f][0]], b = C.m[mct::kFaces[f][1]];
+    const u64 c = C.m[mct::kFaces[f][2]], d = C.m[mct::kFaces[f][3]];
+    multi |= ~(a ^ c) & ~(b ^ d) & (a ^ b);
+  }
+  u64 por[4], pand[4];
+#pragma unroll
+  for (int p = 0; p < 4; p++) {
+    por[p] = C.m[mct::kBodyDiag[p][0]] | C.m[mct::kBodyDiag[p][1]];
+    pand[p] = C.m[mct::kBodyDiag[p][0]] & C.m[mct::kBodyDiag[p][1]];
+  }
+  const u64 o01 = por[0] | por[1], o23 = por[2] | por[3];
+  const u64 a01 = pand[0] & pand[1], a23 = pand[2] & pand[3];
+  const u64 orest[4] = {por[1] | o23, por[0] | o23, o01 | por[3], o01 | por[2]};
+  const u64 arest[4] = {pand[1] & a23, pand[0] & a23, a01 & pand[3], a01 & pand[2]};
+#pragma unroll
+  for (int p = 0; p < 4; p++) multi |= (pand[p] & ~orest[p]) | (~por[p] & arest[p]);
+  multi &= act;
+  int t = (int)e - 2 * __popcll(act);
+  while (multi) {
+    const int i = __ffsll((long long)multi) - 1;
+    multi &= multi - 1;
+    t += fix[case_at(C, i)];
+  }
+  return (uint32_t)t;
+}
+
 __global__ __launch_bounds__(kBS) void k_mc_count(McPlan M) {
-  __shared__ uint8_t ntri[256];
-  for (int i = threadIdx.x; i < 256; i += kBS) ntri[i] = c_table.ntri[i];
+  __shared__ int8_t fix[256];
+  for (int i = threadIdx.x; i < 256; i += kBS) fix[i] = c_fix.d[i];
   __syncthreads();
   const int64_t gw = (int64_t)blockIdx.x * kBS + threadIdx.x;
   if (gw >= M.nrows * M.nw) return;
@@ -188,13 +237,9 @@ __global__ __launch_bounds__(kBS) void k_mc_count(McPlan M) {
   uint32_t nt = 0, nac = 0;
   if (c.y + 1 < M.n[1] && c.z + 1 < M.n[0]) {
     const Corners C = corners_of(M, c.row, c.w);
-    u64 act = active_cells(C, c.validx);
+    const u64 act = active_cells(C, c.validx);
     nac = (uint32_t)__popcll(act);
-    while (act) {
-      const int i = __ffsll((long long)act) - 1;
-      act &= act - 1;
-      nt += ntri[case_at(C, i)];
-    }
+    if (act) nt = word_tris(C, act, fix);
   }
   M.cnt[gw] = U4{nv, nt, npv, nac};
 }
@@ -208,43 +253,97 @@ __device__ inline int popc3_below(const Cross &c, int x) {
   return __popcll(c.cx & bm) + __popcll(c.cy & bm) + __popcll(c.cz & bm);
 }
 
-// Lists the word's crossing points and active cells (each cell with the id
-// of its first triangle).  Entries are word*64 + bit.
+// Lists the crossing points and the active cells of the wave's 64 words
+// (entries word*64 + bit; a word's entries are written only if the whole
+// list up to it fits: lists are whole or unused).  Two ways: each lane walks
+// its own word's bits (as many steps as the fullest word, one scattered
+// store per step), or word after word the lanes of the word's set bits
+// write its entries at consecutive positions (one step per word with
+// entries, every store coalesced).  A wave takes the second where its
+// fullest words have more bits than it has words with entries (a dense
+// surface).
 __global__ __launch_bounds__(kBS) void k_mc_expand(McPlan M) {
-  __shared__ uint8_t ntri[256];
-  for (int i = threadIdx.x; i < 256; i += kBS) ntri[i] = c_table.ntri[i];
-  __syncthreads();
-  const int64_t gw = (int64_t)blockIdx.x * kBS + threadIdx.x;
-  if (gw >= M.nrows * M.nw) return;
-  const U4 p0 = M.P[gw], p1 = M.P[gw + 1];
-  if (p1.z != p0.z && (int64_t)p1.z <= M.cap_pv) {
-    const WordCtx c = word_ctx(M, gw);
-    const Cross x = cross_of(M, c.z, c.y, c.w);
-    u64 pts = x.cx | x.cy | x.cz;
-    uint32_t r = p0.z;
+  const uint32_t nwords = (uint32_t)(M.nrows * M.nw);
+  const uint32_t gw0 = blockIdx.x * kBS + wave_index() * kWave;   // the wave's first word
+  const int lane = lane_id();
+  const uint32_t gw = gw0 + (uint32_t)lane;
+  u64 pts = 0, act = 0;
+  uint32_t bz = 0, bw = 0;
+  if (gw < nwords) {
+    const U4 p0 = M.P[gw], p1 = M.P[gw + 1];
+    bz = p0.z;
+    bw = p0.w;
+    const bool okz = p1.z != p0.z && (int64_t)p1.z <= M.cap_pv;
+    const bool okw = p1.w != p0.w && (int64_t)p1.w <= M.cap_ac;
+    if (okz || okw) {
+      const WordCtx c = word_ctx(M, gw);
+      if (okz) {
+        const Cross x = cross_of(M, c.z, c.y, c.w);
+        pts = x.cx | x.cy | x.cz;
+      }
+      if (okw) act = active_cells(corners_of(M, c.row, c.w), c.validx);
+    }
+  }
+  u64 todo = __ballot(pts != 0ull || act != 0ull);
+  const uint32_t steps = wave_max_dpp((uint32_t)__popcll(pts)) + wave_max_dpp((uint32_t)__popcll(act));
+  if (steps < (uint32_t)__popcll(todo)) {
+    uint32_t r = bz;
     while (pts) {
       const int i = __ffsll((long long)pts) - 1;
       pts &= pts - 1;
-      M.vlist[r++] = (uint32_t)(gw * 64 + i);
+      M.vlist[r++] = gw * 64u + (uint32_t)i;
     }
-  }
-  if (p1.w != p0.w && (int64_t)p1.w <= M.cap_ac) {
-    const WordCtx c = word_ctx(M, gw);
-    const Corners C = corners_of(M, c.row, c.w);
-    u64 act = active_cells(C, c.validx);
-    uint32_t r = p0.w, t = p0.y;
+    r = bw;
     while (act) {
       const int i = __ffsll((long long)act) - 1;
       act &= act - 1;
-      M.clist[r++] = make_uint2((uint32_t)(gw * 64 + i), t);
-      t += ntri[case_at(C, i)];
+      M.clist[r++] = gw * 64u + (uint32_t)i;
     }
+    return;
+  }
+  while (todo) {
+    const int k = __ffsll((long long)todo) - 1;
+    todo &= todo - 1;
+    const u64 pk = ((u64)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(pts >> 32), k) << 32) |
+                   (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)pts, k);
+    const u64 ak = ((u64)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(act >> 32), k) << 32) |
+                   (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)act, k);
+    const uint32_t code = (gw0 + (uint32_t)k) * 64u + (uint32_t)lane;
+    if (__builtin_amdgcn_inverse_ballot_w64(pk))
+      M.vlist[(uint32_t)__builtin_amdgcn_readlane((int)bz, k) + lanes_below(pk)] = code;
+    if (__builtin_amdgcn_inverse_ballot_w64(ak))
+      M.clist[(uint32_t)__builtin_amdgcn_readlane((int)bw, k) + lanes_below(ak)] = code;
+  }
+}
+
+// First triangle id of every 256th active cell, where a k_mc_tris
+// workgroup's range starts: the triangle prefix of the cell's word plus the
+// triangles of the word's active cells before it (one wave per such cell,
+// one lane per cell of its word; run by the waves of k_mc_verts before
+// their vertices).
+__device__ inline void tile_bases(const McPlan &M, const uint8_t *ntri) {
+  const uint32_t nwords = (uint32_t)(M.nrows * M.nw);
+  const uint32_t n = (int64_t)M.P[nwords].w <= M.cap_ac ? M.P[nwords].w : 0u;
+  const uint32_t ntiles = (n + kBS - 1) / kBS;
+  const int lane = lane_id();
+  for (uint32_t t = blockIdx.x * kWaves + wave_index(); t < ntiles; t += gridDim.x * kWaves) {
+    const uint32_t ent = M.clist[t * kBS];
+    const WordCtx c = word_ctx(M, ent >> 6);
+    const Corners C = corners_of(M, (uint32_t)c.row, (uint32_t)c.w);
+    const u64 act = active_cells(C, c.validx);
+    const uint32_t mine = ((act >> lane) & 1ull) && (uint32_t)lane < (ent & 63u) ? (uint32_t)ntri[case_at(C, lane)] : 0u;
+    const uint32_t before = wave_sum_dpp(mine);
+    if (lane == 0) M.tb[t] = M.P[ent >> 6].y + before;
   }
 }
 
 // One lane per crossing point: its vertices in axis order x, y, z (a lane's
 // vertices are consecutive, and so are consecutive lanes').
 __global__ __launch_bounds__(kBS) void k_mc_verts(McPlan M) {
+  __shared__ uint8_t ntri[256];
+  for (int i = threadIdx.x; i < 256; i += kBS) ntri[i] = c_table.ntri[i];
+  __syncthreads();
+  tile_bases(M, ntri);
   const uint32_t nwords = (uint32_t)(M.nrows * M.nw);
   const uint32_t n = (int64_t)M.P[nwords].z <= M.cap_pv ? M.P[nwords].z : 0u;  // lists are whole or unused
   const uint32_t n1 = (uint32_t)M.n[1], n2 = (uint32_t)M.n[2];
@@ -301,13 +400,16 @@ struct Owner {
 
 // One lane per active cell: the ids of its 12 edge vertices go to LDS, then
 // its triangles in table order.  A workgroup takes 256 consecutive active
-// cells, whose triangles are one contiguous id range; they are staged in LDS
-// and written out coalesced.
+// cells, whose triangles are one contiguous id range starting at the id
+// k_mc_verts found; a cell's offset in the range is a workgroup scan of
+// the cells' triangle counts (at most 5: three ballots per wave).  The
+// triangles are staged in LDS and written out coalesced.
 __global__ __launch_bounds__(kBS) void k_mc_tris(McPlan M) {
   constexpr int kIdStride = 13;  // 12 edge ids per lane, odd stride against bank conflicts
   __shared__ mct::Table tab;
   __shared__ int32_t st[kBS * kMaxTri * 3];
   __shared__ int32_t sid[kBS * kIdStride];
+  __shared__ uint32_t wsum[kWaves];
   {
     const uint8_t *src = reinterpret_cast<const uint8_t *>(&c_table);
     uint8_t *dst = reinterpret_cast<uint8_t *>(&tab);
@@ -316,18 +418,18 @@ __global__ __launch_bounds__(kBS) void k_mc_tris(McPlan M) {
   __syncthreads();
   const uint32_t nwords = (uint32_t)(M.nrows * M.nw);
   const uint32_t n = (int64_t)M.P[nwords].w <= M.cap_ac ? M.P[nwords].w : 0u;
-  const uint32_t T = M.P[nwords].y;
   const uint32_t n1 = (uint32_t)M.n[1], nw = (uint32_t)M.nw;
+  const uint32_t wave = wave_index();
+  const int lane = lane_id();
   int32_t *my = sid + threadIdx.x * kIdStride;
   for (uint32_t e0 = blockIdx.x * kBS; e0 < n; e0 += gridDim.x * kBS) {
     const uint32_t e = e0 + threadIdx.x;
-    const uint32_t tbase = M.clist[e0].y;
-    const uint32_t e_end = min(e0 + (uint32_t)kBS, n);
-    const uint32_t tend = e_end < n ? M.clist[e_end].y : T;
+    const uint32_t tbase = M.tb[e0 / kBS];
+    uint32_t nt = 0, cs = 0;
     if (e < n) {
-      const uint2 ent = M.clist[e];
-      const uint32_t gw = ent.x >> 6;
-      const int i = ent.x & 63;
+      const uint32_t code = M.clist[e];
+      const uint32_t gw = code >> 6;
+      const int i = code & 63;
       const WordCtx32 c = word_ctx32(M, gw);
       // Every word this cell needs, loaded at once: point rows (z+dz, y+dy)
       // for dz, dy in 0..2 (not both 2), words w and w+1.  Rows and words
@@ -354,8 +456,8 @@ __global__ __launch_bounds__(kBS) void k_mc_tris(McPlan M) {
       C.m[2] = a1; C.m[3] = shr1(a1, nx1);
       C.m[4] = b0; C.m[5] = shr1(b0, nx2);
       C.m[6] = b1; C.m[7] = shr1(b1, nx3);
-      const uint32_t cs = case_at(C, i);
-      const int nt = tab.ntri[cs];
+      cs = case_at(C, i);
+      nt = tab.ntri[cs];
       // crossing masks of the four owner rows at word w
       const int64_t rem = (int64_t)n2 - (int64_t)c.w * 64;
       const u64 valid = rem >= 64 ? ~0ull : ((1ull << rem) - 1ull);
@@ -406,12 +508,22 @@ __global__ __launch_bounds__(kBS) void k_mc_tris(McPlan M) {
       my[9] = (int32_t)(a10.base + a10.bx + a10.by);
       my[10] = (int32_t)(b00.base + b00.bx + b00.by);
       my[11] = (int32_t)(b10.base + b10.bx + b10.by);
-      const uint32_t so = ent.y - tbase;
-      for (int t = 0; t < nt; t++)
-        for (int q = 0; q < 3; q++) st[3 * (so + t) + q] = my[tab.tri[cs][3 * t + q]];
     }
+    // the cell's offset in the workgroup's triangle range
+    const u64 t0 = __ballot(nt & 1u), t1 = __ballot(nt & 2u), t2 = __ballot(nt & 4u);
+    const uint32_t excl = lanes_below(t0) + 2 * lanes_below(t1) + 4 * lanes_below(t2);
+    if (lane == 0) wsum[wave] = (uint32_t)(__popcll(t0) + 2 * __popcll(t1) + 4 * __popcll(t2));
     __syncthreads();
-    const uint32_t nint = 3 * (tend - tbase);
+    uint32_t so = excl, total = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; w++) {
+      so += (uint32_t)w < wave ? wsum[w] : 0u;
+      total += wsum[w];
+    }
+    for (uint32_t t = 0; t < nt; t++)
+      for (int q = 0; q < 3; q++) st[3 * (so + t) + q] = my[tab.tri[cs][3 * t + q]];
+    __syncthreads();
+    const uint32_t nint = 3 * total;
     const uint64_t capi = 3 * (uint64_t)M.cap_t;
     for (uint32_t q = threadIdx.x; q < nint; q += kBS) {
       const uint64_t g = 3 * (uint64_t)tbase + q;

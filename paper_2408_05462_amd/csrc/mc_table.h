@@ -141,5 +141,67 @@ constexpr Table make_table() {
   return T;
 }
 
+// ---- triangle counts without the table
+//
+// A loop through k crossed edges is triangulated as a fan of k - 2
+// triangles, so a cell with E crossed edges and L loops has E - 2L
+// triangles.  On the cube's surface the loops separate the regions around
+// the below corners -- joined only along cube edges, since an ambiguous face
+// isolates each below corner -- from the regions around the above corners,
+// joined along every face they share; a sphere cut by L disjoint loops has
+// L + 1 regions.  Hence L > 1 needs two below corners with no path along
+// below-below edges or two above corners on no common face.  If no face is
+// ambiguous, two below corners sharing a face are joined through that
+// face's third or fourth corner, so the below corners can only split as one
+// body-diagonal pair with every other corner above; two above corners share
+// a face unless they are a body-diagonal pair, and a third above corner
+// shares a face with both.  A case that is none of these has one loop and
+// E - 2 triangles; the others are corrected from the table.
+
+constexpr int kFaces[6][4] = {{0, 2, 6, 4}, {1, 3, 7, 5}, {0, 1, 5, 4}, {2, 3, 7, 6}, {0, 1, 3, 2}, {4, 5, 7, 6}};
+constexpr int kBodyDiag[4][2] = {{0, 7}, {1, 6}, {2, 5}, {3, 4}};
+
+constexpr int crossed_edges(int cs) {
+  int n = 0;
+  for (int e = 0; e < 12; e++) {
+    Edge E = edge_of(e);
+    n += ((cs >> E.lo) & 1) != ((cs >> E.hi) & 1);
+  }
+  return n;
+}
+
+// The cases that may hold more than one loop (see above).
+constexpr bool multi_loop_possible(int cs) {
+  for (int f = 0; f < 6; f++) {
+    const int a = (cs >> kFaces[f][0]) & 1, b = (cs >> kFaces[f][1]) & 1;
+    const int c = (cs >> kFaces[f][2]) & 1, d = (cs >> kFaces[f][3]) & 1;
+    if (a == c && b == d && a != b) return true;   // ambiguous face
+  }
+  for (int p = 0; p < 4; p++) {
+    const int pair = (1 << kBodyDiag[p][0]) | (1 << kBodyDiag[p][1]);
+    if (cs == pair || cs == (255 ^ pair)) return true;
+  }
+  return false;
+}
+
+// Triangles of the case minus the single-loop count E - 2 (0 for inactive
+// cases and for every case outside multi_loop_possible).
+struct LoopFix {
+  int8_t d[256];
+};
+
+constexpr LoopFix make_loop_fix(const Table &T) {
+  LoopFix F{};
+  for (int cs = 1; cs < 255; cs++) F.d[cs] = (int8_t)((int)T.ntri[cs] - (crossed_edges(cs) - 2));
+  return F;
+}
+
+constexpr bool loop_rule_holds(const Table &T) {
+  if (T.ntri[0] != 0 || T.ntri[255] != 0) return false;
+  for (int cs = 1; cs < 255; cs++)
+    if (!multi_loop_possible(cs) && (int)T.ntri[cs] != crossed_edges(cs) - 2) return false;
+  return true;
+}
+
 }  // namespace mct
 }  // namespace chr

@@ -275,7 +275,9 @@ int launch_group(chr_server *s, int j) {
   return CHR_OK;
 }
 
-size_t list_bytes(const Req &r) { return align_up(4 * (size_t)r.npv) + align_up(8 * (size_t)r.nac); }
+size_t list_bytes(const Req &r) {
+  return align_up(4 * (size_t)r.npv) + align_up(4 * (size_t)r.nac) + align_up(4 * (size_t)(r.nac / 256 + 1));
+}
 size_t mesh_bytes(const Req &r) { return align_up(12 * (size_t)r.nv) + align_up(12 * (size_t)r.nt); }
 
 // Emitting half for the counted requests of slot j, in order, as far as the
@@ -299,7 +301,8 @@ int launch_emits(chr_server *s, int j) {
     McPlan &M = r.M;
     uint8_t *l = pool_ptr(s, r.lists.off);
     M.vlist = reinterpret_cast<uint32_t *>(l);
-    M.clist = reinterpret_cast<uint2 *>(l + align_up(4 * (size_t)r.npv));
+    M.clist = reinterpret_cast<uint32_t *>(l + align_up(4 * (size_t)r.npv));
+    M.tb = reinterpret_cast<uint32_t *>(l + align_up(4 * (size_t)r.npv) + align_up(4 * (size_t)r.nac));
     M.cap_pv = r.npv;
     M.cap_ac = r.nac;
     uint8_t *m = pool_ptr(s, r.mesh.off);
