@@ -345,6 +345,11 @@ __global__ __launch_bounds__(kBS) void k_mc_verts(McPlan M) {
   __syncthreads();
   tile_bases(M, ntri);
   const uint32_t nwords = (uint32_t)(M.nrows * M.nw);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    // the mesh sizes (required sizes, also when they exceed the capacities)
+    M.counts[0] = (int64_t)M.P[nwords].x;
+    M.counts[1] = (int64_t)M.P[nwords].y;
+  }
   const uint32_t n = (int64_t)M.P[nwords].z <= M.cap_pv ? M.P[nwords].z : 0u;  // lists are whole or unused
   const uint32_t n1 = (uint32_t)M.n[1], n2 = (uint32_t)M.n[2];
   const float *f = M.f;
@@ -626,7 +631,6 @@ void launch_mc_emit(const McPlan &p0, hipStream_t s) {
   prof_mark("k_mc_tris", s, 0);
   k_mc_tris<<<dim3(2048), dim3(kBS), 0, s>>>(p);
   prof_mark("k_mc_tris", s, 1);
-  k_mc_counts<<<dim3(1), dim3(64), 0, s>>>(p, 0);
 }
 
 void launch_mc(const McPlan &p0, U4 *scan_tmp, hipStream_t s) {
