@@ -520,6 +520,7 @@ __device__ __forceinline__ void decode_fast(const DecPlan &D) {
 constexpr int kD0Side = 33;                  // level-1 points per axis of a 64-cell block
 constexpr int kD0Plane = 1152;               // staged plane stride (floats; fits an LDS immediate offset)
 constexpr int kD0Codes = 7361;               // most section points of a pair
+constexpr int kD0Spare = 64;                 // LDS codes before the pair's first point (chunk heads)
 constexpr int kD0Chunks = 118;               // chunks that overlap a pair's part of the section
 constexpr int kD0Xcap = 1024;                // exact values of a pair staged in LDS
 constexpr int kD0Group = 16;                 // chunks (unpack) whose loads a wave issues together
@@ -595,7 +596,11 @@ __device__ __forceinline__ void d0_bits_rows(const DecPlan &D, D0Bits &q, const 
 
 __global__ __launch_bounds__(kBS) void k_decode_l0t(DecPlan D) {
   __shared__ float sg[2 * kD0Plane];
-  __shared__ uint16_t sc[kD0Codes + 1];
+  // codes by section index - J0, after a spare prefix: the pair's first and
+  // last chunks unpack whole, their points outside the pair landing in the
+  // spare entries (at most 63 before J0 and 63 after J1)
+  __shared__ uint16_t scs[kD0Spare + kD0Codes + 64];
+  uint16_t *const sc = scs + kD0Spare;
   __shared__ uint32_t cwo[kD0Chunks], cxo[kD0Chunks], cwb[kD0Chunks];
   __shared__ unsigned long long cem[kD0Chunks];
   __shared__ float xl[kD0Xcap];
@@ -696,13 +701,18 @@ __global__ __launch_bounds__(kBS) void k_decode_l0t(DecPlan D) {
     for (uint32_t i = threadIdx.x; i < nx; i += kBS) xl[i] = __uint_as_float(ldu(exb, 4u * (xo0 + i)));
   }
   for (uint32_t k0 = wave; k0 < ncw; k0 += kD0Group * kWaves) {
-    uint32_t lo[kD0Group], hi[kD0Group];
+    // the group's chunk headers, lane u holding chunk k0 + 4u's, taken by
+    // readlane (no LDS round trip per chunk)
+    const uint32_t kl = min(k0 + (uint32_t)lane * kWaves, ncw - 1);
+    const uint32_t lw = cwb[kl], lwo = cwo[kl];
+    const unsigned long long lem = cem[kl];
+    uint32_t wu[kD0Group], lo[kD0Group], hi[kD0Group];
 #pragma unroll
     for (int u = 0; u < kD0Group; u++) {
-      const uint32_t k = min(k0 + (uint32_t)u * kWaves, ncw - 1);
-      const uint32_t w = __builtin_amdgcn_readfirstlane(cwb[k]);
-      const uint32_t wo = __builtin_amdgcn_readfirstlane(cwo[k]);
+      const uint32_t w = (uint32_t)__builtin_amdgcn_readlane((int)lw, u);
+      const uint32_t wo = (uint32_t)__builtin_amdgcn_readlane((int)lwo, u);
       const uint32_t bit = mul24s((uint32_t)lane, w), wi = bit >> 5;
+      wu[u] = w;
       lo[u] = hi[u] = 0u;
       if (w) {
         lo[u] = ldu(payb, 8u * wo + 4u * wi);
@@ -713,13 +723,16 @@ __global__ __launch_bounds__(kBS) void k_decode_l0t(DecPlan D) {
     for (int u = 0; u < kD0Group; u++) {
       const uint32_t k = k0 + (uint32_t)u * kWaves;
       if (k >= ncw) break;
-      const uint32_t w = __builtin_amdgcn_readfirstlane(cwb[k]);
-      const uint32_t off = mul24s((uint32_t)lane, w) & 31u;
-      uint32_t zz = off + w > 32u ? (lo[u] >> off) | (hi[u] << (32u - off)) : lo[u] >> off;
-      zz = w ? zz & ((1u << w) - 1u) : 0u;
-      const bool E = (cem[k] >> lane) & 1ull;
-      const uint32_t j = (c0 + k) * 64 + (uint32_t)lane;
-      if (j >= J0 && j < J1) sc[j - J0] = E ? kD0Exact : (uint16_t)zz;
+      // the lane's code: w bits from bit lane * w of the chunk's payload
+      // (a funnel shift of the two words it can span, then a field extract;
+      // width 0 gives 0)
+      const uint32_t w = wu[u];
+      const uint32_t zz = __builtin_amdgcn_ubfe(__builtin_amdgcn_alignbit(hi[u], lo[u], mul24s((uint32_t)lane, w)), 0u, w);
+      const unsigned long long em =
+          ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(lem >> 32), u) << 32) |
+          (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)lem, u);
+      const bool E = __builtin_amdgcn_inverse_ballot_w64(em);
+      sc[(c0 + k) * 64 + (uint32_t)lane - J0] = E ? kD0Exact : (uint16_t)zz;
     }
   }
   __syncthreads();
