@@ -580,9 +580,10 @@ __device__ __forceinline__ uint32_t t0_ord(float f) {
 // changes side of some candidate exactly when one candidate's comparison
 // differs between x and x', so the correction mask is an OR of ballot XORs.
 // LL: the lossless quantizer.
-template <int KB, bool LL>
+template <int KB, bool LL, bool GW = false>
 __device__ __forceinline__ void t0_finish(const Geo &gq, const float (&iso)[KB], float x, float p, uint64_t cmask,
-                                          uint32_t jr, uint32_t jl, T0Ctx &t) {
+                                          uint32_t jr, uint32_t jl, T0Ctx &t, char *gl = nullptr,
+                                          uint32_t go = 0u) {
   // the point's section index is jr + jl: jr the row's (wave-uniform), jl the lane's
   uint64_t mO;
   float xc;
@@ -609,6 +610,7 @@ __device__ __forceinline__ void t0_finish(const Geo &gq, const float (&iso)[KB],
   const uint64_t mE = mO | mr;                 // outlier, or a correction (side change, not an outlier)
   const bool E = __builtin_amdgcn_inverse_ballot_w64(mE);
   const float xr = E ? x : xc;
+  if (GW) stf(gl, go, xr);                     // above level 0: the parent of the next finer level
   const uint32_t zz = ((uint32_t)q << 1) ^ (uint32_t)(q >> 31);
   t.rmin = __builtin_elementwise_minimum(t.rmin, xr);
   t.rmax = __builtin_elementwise_maximum(t.rmax, xr);
@@ -649,13 +651,33 @@ __device__ __forceinline__ float t0_pred_any(const float *sg, bool zu, uint32_t 
                    yu, xu);
 }
 
-template <int KB, bool LL>
-__global__ __launch_bounds__(kBS) void k_encode_l0t(EncPlan P) {
+// Level LV (0 or 1) of 64-cell blocks by pairs of planes of the level's
+// grid.  Level 1 is level 0's pattern on every other point of the field:
+// rows of at most 33 points (lanes past 33 idle), x loads at a stride of two,
+// parents from the level-2 grid; its reconstructed points, and the level-2
+// points of the pair's even plane that the level-1 grid carries over, are
+// written into the level-1 grid for level 0 to predict from.
+template <int LV>
+struct TileDims {
+  static constexpr int S = 1 << LV;                       // field points per level step
+  static constexpr int Side = (64 >> (LV + 1)) + 1;       // parent points per axis of a block
+  static constexpr int Plane = LV == 0 ? 1152 : 320;      // staged parent plane stride (floats)
+  static constexpr int Codes = LV == 0 ? 7361 + 63 : 1889 + 63;   // most section points of a pair + a chunk tail
+  static constexpr int A = LV == 0 ? 5 : 3;               // even-row pairs of the even plane per wave
+  static constexpr int B = LV == 0 ? 8 : 4;               // odd rows of the even plane per wave
+  static constexpr int M = LV == 0 ? 9 : 5;               // row pairs of the odd plane per wave
+};
+
+template <int KB, bool LL, int LV>
+__device__ __forceinline__ void encode_tile(const EncPlan &P) {
+  using TD = TileDims<LV>;
+  constexpr uint32_t S = TD::S;
+  constexpr bool GW = LV >= 1;
   // one LDS record with the parent planes first, so that they sit at LDS
   // address 0 and a row's parent offsets fit the read instructions' fields
   struct Lds {
-    float sg[2 * kT0Plane];
-    uint16_t sc[kT0Spare + kT0Codes];
+    float sg[2 * TD::Plane];
+    uint16_t sc[kT0Spare + TD::Codes];
     uint32_t pack[kWaves][64];
   };
   __shared__ __align__(16) Lds lds;
@@ -666,26 +688,26 @@ __global__ __launch_bounds__(kBS) void k_encode_l0t(EncPlan P) {
   xcd_remap(w2, b);
   const Geo &gq = P.g;
   const BlockPos bp = block_pos(gq, P.l0, b);
-  const Sec s = P.l0.sec[bp.cls];
-  const SecR rc = P.l0.rc[bp.cls];
+  const Sec s = LV == 0 ? P.l0.sec[bp.cls] : P.l0.sec1[bp.cls];
+  const SecR rc = LV == 0 ? P.l0.rc[bp.cls] : P.l0.rc1[bp.cls];
   const uint32_t wave = wave_index();
   const int lane = lane_id();
   Part acc;
   part_init(acc);
-  Part *rec = &P.part[(int64_t)b * P.part_per_block + w2];
+  Part *rec = &P.part[(int64_t)b * P.part_per_block + (LV == 0 ? 0 : P.part_l1) + w2];
   const uint32_t PP = s.Pe + s.Po;
   const uint32_t J0 = w2 * PP;
-  const int64_t slot0 = P.slot_base[0] + (int64_t)b * P.maxch[0];
+  const int64_t slot0 = P.slot_base[LV] + (int64_t)b * P.maxch[LV];
   const uint32_t nch = (s.npts + 63) / 64;
   if (w2 == 0) {
     // slots past this block's section (a shorter block than the first)
-    for (uint32_t c = nch + threadIdx.x; c < P.maxch[0]; c += kBS) P.cnt[slot0 + c] = U4{0, 0, 0, 0};
+    for (uint32_t c = nch + threadIdx.x; c < P.maxch[LV]; c += kBS) P.cnt[slot0 + c] = U4{0, 0, 0, 0};
   }
   if (J0 >= s.npts) {  // a pair past the block's planes
     part_store(acc, rec);
     return;
   }
-  const uint32_t we = 2 * w2;                  // the even plane (block-relative z)
+  const uint32_t we = 2 * w2;                  // the even plane (block-relative, level units)
   const bool has_odd = we + 1 < s.mz;
   const uint32_t J1 = has_odd ? J0 + PP : J0 + s.Pe;
   const uint32_t cfirst = (J0 + 63) / 64, cend = (J1 + 63) / 64;
@@ -699,10 +721,10 @@ __global__ __launch_bounds__(kBS) void k_encode_l0t(EncPlan P) {
   t.rmax = t.xmax = -__builtin_inff();
   const uint32_t n1 = (uint32_t)gq.n[1], n2 = (uint32_t)gq.n[2];
   const uint32_t mx = s.mx, my = s.my, rowE = s.rowE, RP = rowE + mx;
-  // the two level-1 planes (z = (o_z + we) / 2 and the next) of the block
-  const uint32_t h0 = (uint32_t)P.gd[1][0], h1 = (uint32_t)P.gd[1][1], h2 = (uint32_t)P.gd[1][2];
-  const uint32_t zl0 = (bp.o[0] >> 1) + w2, oy1 = bp.o[1] >> 1, ox1 = bp.o[2] >> 1;
-  const uint32_t gy = (bp.hi[1] >> 1) - oy1 + 1, gx = (bp.hi[2] >> 1) - ox1 + 1;
+  // the two parent planes (level LV + 1, z = (o_z / S + we) / 2 and the next)
+  const uint32_t h0 = (uint32_t)P.gd[LV + 1][0], h1 = (uint32_t)P.gd[LV + 1][1], h2 = (uint32_t)P.gd[LV + 1][2];
+  const uint32_t zl0 = (bp.o[0] >> (LV + 1)) + w2, oy1 = bp.o[1] >> (LV + 1), ox1 = bp.o[2] >> (LV + 1);
+  const uint32_t gy = (bp.hi[1] >> (LV + 1)) - oy1 + 1, gx = (bp.hi[2] >> (LV + 1)) - ox1 + 1;
   const uint32_t np = zl0 + 1 < h0 ? 2u : 1u;
   {
     // rows past the block and lanes past a row load (and store) a copy of
@@ -710,9 +732,9 @@ __global__ __launch_bounds__(kBS) void k_encode_l0t(EncPlan P) {
     // copy of the first and is never read.  32-bit offsets from the block's
     // first parent, loads of both planes issued before the stores.
     const char *__restrict__ g1b =
-        reinterpret_cast<const char *>(P.G + P.g_off[1] + ((size_t)zl0 * h1 + oy1) * h2 + ox1);
+        reinterpret_cast<const char *>(P.G + P.g_off[LV + 1] + ((size_t)zl0 * h1 + oy1) * h2 + ox1);
     const uint32_t xl = min((uint32_t)lane, gx - 1), planeB = (np - 1) * h1 * h2 * 4u, rowB1 = h2 * 4u;
-    constexpr int kRP = (kT0Side + kWaves - 1) / kWaves;
+    constexpr int kRP = (TD::Side + kWaves - 1) / kWaves;
     float tv[2][kRP];
 #pragma unroll
     for (int pz = 0; pz < 2; pz++)
@@ -726,7 +748,7 @@ __global__ __launch_bounds__(kBS) void k_encode_l0t(EncPlan P) {
 #pragma unroll
       for (int u = 0; u < kRP; u++) {
         const uint32_t yy = min(wave + (uint32_t)u * kWaves, gy - 1);
-        sg[pz * kT0Plane + yy * kT0Side + xl] = tv[pz][u];
+        sg[pz * TD::Plane + yy * TD::Side + xl] = tv[pz][u];
       }
   }
   float iso[KB];
@@ -737,21 +759,28 @@ __global__ __launch_bounds__(kBS) void k_encode_l0t(EncPlan P) {
   const char *__restrict__ sgb = reinterpret_cast<const char *>(sg);
   const uint32_t ownz = bp.own[0] - bp.o[0], owny = bp.own[1] - bp.o[1], ownx = bp.own[2] - bp.o[2];
   const bool zu = np == 2;                     // the odd plane has an upper parent plane
-  const uint32_t rowB = n2 * 4u;               // bytes between field rows
-  const uint32_t xe0 = ((we * n1 + bp.o[1]) * n2 + bp.o[2]) * 4u;     // even plane, row 0
-  const uint32_t xo0 = xe0 + n1 * n2 * 4u;                          // odd plane, row 0
+  const uint32_t rowB = n2 * 4u * S;           // bytes between the level's rows in the field
+  const uint32_t xe0 = ((we * S * n1 + bp.o[1]) * n2 + bp.o[2]) * 4u;  // even plane, row 0
+  const uint32_t xo0 = xe0 + n1 * n2 * 4u * S;                      // odd plane, row 0
+  // the level's grid (levels >= 1): its rows of the pair's two planes
+  const int64_t *gdl = P.gd[LV];
+  const uint32_t f1 = GW ? (uint32_t)gdl[1] : 0u, f2 = GW ? (uint32_t)gdl[2] : 0u;
+  char *__restrict__ glb =
+      GW ? reinterpret_cast<char *>(P.G + P.g_off[LV] +
+                                    (((size_t)(bp.o[0] / S) + we) * f1 + bp.o[1] / S) * f2 + bp.o[2] / S)
+         : nullptr;
+  const uint32_t grow = f2 * 4u, gplane = f1 * f2 * 4u;
   // codes past the section in its last chunk read as 0 when packing
   if (cend > cfirst && cend * 64 > s.npts && threadIdx.x < cend * 64 - s.npts) t.sc[s.npts + threadIdx.x] = 0;
-  // Every x row a wave needs is loaded before the barrier (at most 5 A, 8 B
-  // and 9 C/D row pairs per wave for 65-point blocks): A rows v = 4a +
+  // Every x row a wave needs is loaded before the barrier: A rows v = 4a +
   // 2*half (odd u = 2i + 1), B rows v = 2f + 1, C/D rows 2m and 2m + 1.  A
   // row past the block or a lane past a row loads a copy of a point inside.
-  constexpr int kA = 5, kB = 8, kM = 9;
+  constexpr int kA = TD::A, kB = TD::B, kM = TD::M;
   const uint32_t half = (uint32_t)lane >> 5, ir = (uint32_t)lane & 31u;
   const uint32_t iA = min(ir, rowE > 0 ? rowE - 1 : 0u);
   const uint32_t nA = rowE > 0 ? ((my + 1) / 2 + 1) / 2 : 0u, nB = my / 2, nM = has_odd ? (my + 1) / 2 : 0u;
   const uint32_t u = min((uint32_t)lane, mx - 1);
-  const uint32_t lxA = (2 * iA + 1) * 4u, lx = u * 4u;
+  const uint32_t lxA = (2 * iA + 1) * 4u * S, lx = u * 4u * S;
   float xa[kA], xb[kB], xc[kM], xd[kM];
   if (nA > 0) {
 #pragma unroll
@@ -778,10 +807,16 @@ __global__ __launch_bounds__(kBS) void k_encode_l0t(EncPlan P) {
   }
   __syncthreads();
 
+  if (GW) {
+    // the parents on the even plane's even rows and even points carry over
+    // into the level's grid unchanged
+    for (uint32_t r = wave; 2 * r < my; r += kWaves)
+      if (ir < gx && half == 0) stf(glb, 2 * r * grow + 2 * ir * 4u, sg[r * TD::Side + ir]);
+  }
   // ---- A rows: even plane, v = 4a + 2*half, u = 2i + 1
   if (nA > 0) {
     const bool xav = iA + 1 < gx;
-    const uint64_t lane_in = __ballot(ir < rowE && 2 * ir + 1 < ownx);
+    const uint64_t lane_in = __ballot(ir < rowE && (2 * ir + 1) * S < ownx);
     const uint32_t lg = iA * 4u;
 #pragma unroll
     for (int k = 0; k < kA; k++) {
@@ -789,19 +824,20 @@ __global__ __launch_bounds__(kBS) void k_encode_l0t(EncPlan P) {
       if (a >= nA) break;
       const uint32_t v = 4 * a + 2 * half;
       const uint32_t vc = v < my ? v : v - 2;
-      const uint32_t ga = (vc >> 1) * (kT0Side * 4u) + lg;
+      const uint32_t ga = (vc >> 1) * (TD::Side * 4u) + lg;
       const float p = t0_xavg(lds_at(sgb, ga), lds_at(sgb, ga + 4), xav);
       const uint32_t jA = J0 + (vc >> 1) * RP;
-      const uint64_t h0 = (4 * a < my && 4 * a < owny) ? 0x00000000ffffffffull : 0ull;
-      const uint64_t h1 = (4 * a + 2 < my && 4 * a + 2 < owny) ? 0xffffffff00000000ull : 0ull;
-      t0_finish<KB, LL>(gq, iso, xa[k], p, we < ownz ? lane_in & (h0 | h1) : 0ull, jA, iA, t);
+      const uint64_t hm0 = (4 * a < my && 4 * a * S < owny) ? 0x00000000ffffffffull : 0ull;
+      const uint64_t hm1 = (4 * a + 2 < my && (4 * a + 2) * S < owny) ? 0xffffffff00000000ull : 0ull;
+      t0_finish<KB, LL, GW>(gq, iso, xa[k], p, we * S < ownz ? lane_in & (hm0 | hm1) : 0ull, jA, iA, t, glb,
+                            vc * grow + (2 * iA + 1) * 4u);
     }
   }
   const uint32_t lx0 = u >> 1;
   const bool xav = (u & 1u) && lx0 + 1 < gx;
-  const uint64_t lane_in = __ballot((uint32_t)lane < mx && (uint32_t)lane < ownx);
+  const uint64_t lane_in = __ballot((uint32_t)lane < mx && (uint32_t)lane * S < ownx);
   const uint32_t lg = lx0 * 4u;
-  constexpr uint32_t kRow = kT0Side * 4u, kPl = kT0Plane * 4u;
+  constexpr uint32_t kRow = TD::Side * 4u, kPl = TD::Plane * 4u;
   // ---- B rows: odd rows v = 2f + 1 of the even plane (z even, y odd)
 #pragma unroll
   for (int k = 0; k < kB; k++) {
@@ -815,12 +851,13 @@ __global__ __launch_bounds__(kBS) void k_encode_l0t(EncPlan P) {
     hold(pb);
     const float p = yu ? pb : A;
     const uint32_t jr = J0 + f * RP + rowE;
-    t0_finish<KB, LL>(gq, iso, xb[k], p, (we < ownz && 2 * f + 1 < owny) ? lane_in : 0ull, jr, u, t);
+    t0_finish<KB, LL, GW>(gq, iso, xb[k], p, (we * S < ownz && (2 * f + 1) * S < owny) ? lane_in : 0ull, jr, u, t,
+                          glb, (2 * f + 1) * grow + u * 4u);
   }
   // ---- C and D rows: the odd plane's rows 2m (y even) and 2m + 1 (y odd)
   {
     const uint32_t jo = J0 + s.Pe;
-    const bool zown = we + 1 < ownz;
+    const bool zown = (we + 1) * S < ownz;
 #pragma unroll
     for (int k = 0; k < kM; k++) {
       const uint32_t m = wave + (uint32_t)k * kWaves;
@@ -832,7 +869,8 @@ __global__ __launch_bounds__(kBS) void k_encode_l0t(EncPlan P) {
       hold(pc);
       const float p = zu ? pc : A;
       const uint32_t jc = jo + 2 * m * mx;
-      t0_finish<KB, LL>(gq, iso, xc[k], p, (zown && 2 * m < owny) ? lane_in : 0ull, jc, u, t);
+      t0_finish<KB, LL, GW>(gq, iso, xc[k], p, (zown && 2 * m * S < owny) ? lane_in : 0ull, jc, u, t, glb,
+                            gplane + 2 * m * grow + u * 4u);
       if (2 * m + 1 < my) {
         const bool yu = m + 1 < gy;
         const float B = t0_xavg(lds_at(sgb, ga + kRow), lds_at(sgb, ga + kRow + 4), xav);
@@ -845,13 +883,14 @@ __global__ __launch_bounds__(kBS) void k_encode_l0t(EncPlan P) {
         float pd = avg2(p0, p1);
         hold(pd);
         const float p2 = zu ? pd : p0;
-        t0_finish<KB, LL>(gq, iso, xd[k], p2, (zown && 2 * m + 1 < owny) ? lane_in : 0ull, jc + mx, u, t);
+        t0_finish<KB, LL, GW>(gq, iso, xd[k], p2, (zown && (2 * m + 1) * S < owny) ? lane_in : 0ull, jc + mx, u, t,
+                              glb, gplane + (2 * m + 1) * grow + u * 4u);
       }
     }
   }
-  // ---- column: the points u = 64 of the full rows (65-point rows only)
+  // ---- column: the points u = 64 of the full rows (65-point rows, level 0)
   const uint32_t nF = nB + (has_odd ? my : 0u);
-  if (mx == 65) {
+  if (LV == 0 && mx == 65) {
     for (uint32_t c0 = wave * 64; c0 < nF; c0 += kWaves * 64) {
       const uint32_t fr = c0 + (uint32_t)lane, f = min(fr, nF - 1);
       const bool ev = f < nB;
@@ -864,13 +903,15 @@ __global__ __launch_bounds__(kBS) void k_encode_l0t(EncPlan P) {
   }
   // ---- the tail of the last chunk (the next planes' first points; more
   // than one pair when a pair holds fewer than 64 points), parents read from
-  // the level-1 grid in memory; not counted (the next pairs count them)
+  // the parent grid in memory; not counted and not written to the level's
+  // grid (the next pairs count and write them)
   if (jend > J1 && jbase < jend && wave == kWaves - 1) {
     const uint32_t j = min(J1 + (uint32_t)lane, jend - 1);
     uint32_t w, v, uu;
     sec_point24(s, rc, j, w, v, uu);
-    const float x = ldf(xbase, ((w * n1 + bp.o[1] + v) * n2 + bp.o[2] + uu) * 4u);
-    const float p = predict(P.G + P.g_off[1], h0, h1, h2, 0, bp.o[0] + w, bp.o[1] + v, bp.o[2] + uu);
+    const float x = ldf(xbase, ((w * S * n1 + bp.o[1] + v * S) * n2 + bp.o[2] + uu * S) * 4u);
+    const float p = predict(P.G + P.g_off[LV + 1], h0, h1, h2, LV, bp.o[0] + w * S, bp.o[1] + v * S,
+                            bp.o[2] + uu * S);
     t0_finish<KB, LL>(gq, iso, x, p, 0ull, 0u, j, t);
   }
   __syncthreads();
@@ -924,6 +965,16 @@ __global__ __launch_bounds__(kBS) void k_encode_l0t(EncPlan P) {
     acc.nC = t.nC;
   }
   part_store(acc, rec);
+}
+
+template <int KB, bool LL>
+__global__ __launch_bounds__(kBS) void k_encode_l0t(EncPlan P) {
+  encode_tile<KB, LL, 0>(P);
+}
+
+template <int KB, bool LL>
+__global__ __launch_bounds__(kBS) void k_encode_l1t(EncPlan P) {
+  encode_tile<KB, LL, 1>(P);
 }
 
 // Differentiated error control: block b is active when the input on its
@@ -1352,6 +1403,7 @@ int64_t encode_fine_groups(const EncPlan &p) {
 }
 int64_t encode_tile0_groups(const EncPlan &p) { return (p.g.B + 2) / 2; }
 int64_t encode_l1_groups(const EncPlan &p) {
+  if (p.tile1) return (p.g.B / 2 + 2) / 2;     // pairs of level-1 planes of a 64-cell block
   return p.g.nL >= 2 ? ceil_div(p.maxch[1] > 0 ? p.maxch[1] : 1, (int64_t)kChunksPerWG) : 0;
 }
 int64_t encode_l2_groups(const EncPlan &p) {
@@ -1372,6 +1424,9 @@ bool encode_l2_fast(const EncPlan &p) { return p.g.nL >= 4 && slab32(p.g) && p.l
 bool encode_tile0_ok(const EncPlan &p) {
   return p.g.B == 64 && p.g.nL >= 2 && !p.g.diff && !p.codes && !p.flags && slab32(p.g) && p.l0.small;
 }
+
+// Level 1 by plane pairs likewise, below a coarser level (level 2 exists).
+bool encode_tile1_ok(const EncPlan &p) { return encode_tile0_ok(p) && p.g.nL >= 3; }
 
 void encode_pack_layout(EncPlan &p) {
   const int L = p.g.nL - 1;
@@ -1405,7 +1460,10 @@ void launch_encode_levels(const EncPlan &p, hipStream_t s) {
   if (L >= 1) {
     const dim3 grid1((unsigned)encode_l1_groups(p), (unsigned)g.nblocks);
     prof_mark("k_encode_l1", s, 0);
-    if (L >= 2 && fast && !p.codes && !p.flags)
+    if (p.tile1) {
+      if (g.lossless) k_encode_l1t<KB, true><<<grid1, dim3(kBS), 0, s>>>(p);
+      else k_encode_l1t<KB, false><<<grid1, dim3(kBS), 0, s>>>(p);
+    } else if (L >= 2 && fast && !p.codes && !p.flags)
       k_encode_l1s<false, KB, 4, DIFF><<<grid1, dim3(kBS), 0, s>>>(p);
     else if (L >= 2 && fast)
       k_encode_l1s<true, KB, 1, DIFF><<<grid1, dim3(kBS), 0, s>>>(p);
