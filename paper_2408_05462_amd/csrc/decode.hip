@@ -594,15 +594,30 @@ __device__ __forceinline__ void d0_bits_rows(const DecPlan &D, D0Bits &q, const 
   if (nk > 8) d0_bits_set(D, q.lo[1], q.hi[1], rv, 8, nk, vmask);
 }
 
-__global__ __launch_bounds__(kBS) void k_decode_l0t(DecPlan D) {
-  __shared__ float sg[2 * kD0Plane];
+// Level LV (0 or 1) of 64-cell blocks by pairs of planes of the level's
+// grid: at level 1 the rows have at most 33 points (lanes past 33 idle), the
+// parents come from the level-2 grid and the rows go to the level-1 grid (the
+// even points of the even plane's even rows from level 2); no bit planes.
+template <int LV>
+struct DTileDims {
+  static constexpr int Side = (64 >> (LV + 1)) + 1;       // parent points per axis of a block
+  static constexpr int Plane = LV == 0 ? kD0Plane : 320;  // staged parent plane stride (floats)
+  static constexpr int Codes = LV == 0 ? kD0Codes : 1889; // most section points of a pair
+  static constexpr int Chunks = LV == 0 ? kD0Chunks : 32; // chunks that overlap a pair's part of the section
+};
+
+template <int LV>
+__device__ __forceinline__ void decode_tile(const DecPlan &D) {
+  using TD = DTileDims<LV>;
+  constexpr uint32_t S = 1u << LV;             // field points per level step
+  __shared__ float sg[2 * TD::Plane];
   // codes by section index - J0, after a spare prefix: the pair's first and
   // last chunks unpack whole, their points outside the pair landing in the
   // spare entries (at most 63 before J0 and 63 after J1)
-  __shared__ uint16_t scs[kD0Spare + kD0Codes + 64];
+  __shared__ uint16_t scs[kD0Spare + TD::Codes + 64];
   uint16_t *const sc = scs + kD0Spare;
-  __shared__ uint32_t cwo[kD0Chunks], cxo[kD0Chunks], cwb[kD0Chunks];
-  __shared__ unsigned long long cem[kD0Chunks];
+  __shared__ uint32_t cwo[TD::Chunks], cxo[TD::Chunks], cwb[TD::Chunks];
+  __shared__ unsigned long long cem[TD::Chunks];
   __shared__ float xl[kD0Xcap];
   __shared__ uint32_t sbad[kWaves];
   uint32_t w2, b;
@@ -610,17 +625,17 @@ __global__ __launch_bounds__(kBS) void k_decode_l0t(DecPlan D) {
   if (!block_needed(D, b)) return;
   const Geo &g = D.g;
   const BlockPos bp = block_pos(g, D.l0, b);
-  const Sec s = D.l0.sec[bp.cls];
+  const Sec s = LV == 0 ? D.l0.sec[bp.cls] : D.l0.sec1[bp.cls];
   const uint32_t PP = s.Pe + s.Po, J0 = w2 * PP;
   if (J0 >= s.npts) return;
   const uint32_t we = 2 * w2;
   const bool all = D.prune != 0;
   const uint32_t ownz = bp.own[0] - bp.o[0], owny = bp.own[1] - bp.o[1], ownx = bp.own[2] - bp.o[2];
-  if (!all && we >= ownz) return;              // neither plane of the pair is the block's
+  if (!all && we * S >= ownz) return;          // neither plane of the pair is the block's
   const bool has_odd = we + 1 < s.mz;
   const uint32_t J1 = has_odd ? J0 + PP : J0 + s.Pe;
   const uint32_t c0 = J0 >> 6, c1 = (J1 + 63) >> 6, ncw = c1 - c0;
-  const SecView v = open_section(D, b, 0, s.npts);
+  const SecView v = open_section(D, b, LV, s.npts);
   if (!v.ok) {
     if (threadIdx.x == 0) set_status(D, -4);
     return;
@@ -629,19 +644,19 @@ __global__ __launch_bounds__(kBS) void k_decode_l0t(DecPlan D) {
   const int lane = lane_id();
   const uint32_t n1 = (uint32_t)g.n[1], n2 = (uint32_t)g.n[2];
   const uint32_t mx = s.mx, my = s.my, rowE = s.rowE, RP = rowE + mx;
-  const uint32_t h0 = (uint32_t)D.gd[1][0], h1 = (uint32_t)D.gd[1][1], h2 = (uint32_t)D.gd[1][2];
-  const uint32_t zl0 = (bp.o[0] >> 1) + w2, oy1 = bp.o[1] >> 1, ox1 = bp.o[2] >> 1;
-  const uint32_t gy = (bp.hi[1] >> 1) - oy1 + 1, gx = (bp.hi[2] >> 1) - ox1 + 1;
+  const uint32_t h0 = (uint32_t)D.gd[LV + 1][0], h1 = (uint32_t)D.gd[LV + 1][1], h2 = (uint32_t)D.gd[LV + 1][2];
+  const uint32_t zl0 = (bp.o[0] >> (LV + 1)) + w2, oy1 = bp.o[1] >> (LV + 1), ox1 = bp.o[2] >> (LV + 1);
+  const uint32_t gy = (bp.hi[1] >> (LV + 1)) - oy1 + 1, gx = (bp.hi[2] >> (LV + 1)) - ox1 + 1;
   const uint32_t np = zl0 + 1 < h0 ? 2u : 1u;
   {
-    // the level-1 planes: rows past the block and lanes past a row load (and
+    // the parent planes: rows past the block and lanes past a row load (and
     // store) a copy of the last one; without an upper plane the second
     // staged plane is a copy of the first and is never read.  32-bit offsets
     // from the block's first parent, loads of both planes issued first.
     const char *__restrict__ g1b =
-        reinterpret_cast<const char *>(D.gp[1] + ((size_t)zl0 * h1 + oy1) * h2 + ox1);
+        reinterpret_cast<const char *>(D.gp[LV + 1] + ((size_t)zl0 * h1 + oy1) * h2 + ox1);
     const uint32_t xl1 = min((uint32_t)lane, gx - 1), planeB = (np - 1) * h1 * h2 * 4u, rowB1 = h2 * 4u;
-    constexpr int kRP = (kD0Side + kWaves - 1) / kWaves;
+    constexpr int kRP = (TD::Side + kWaves - 1) / kWaves;
     float tv[2][kRP];
 #pragma unroll
     for (int pz = 0; pz < 2; pz++)
@@ -655,7 +670,7 @@ __global__ __launch_bounds__(kBS) void k_decode_l0t(DecPlan D) {
 #pragma unroll
       for (int u = 0; u < kRP; u++) {
         const uint32_t yy = min(wave + (uint32_t)u * kWaves, gy - 1);
-        sg[pz * kD0Plane + yy * kD0Side + xl1] = tv[pz][u];
+        sg[pz * TD::Plane + yy * TD::Side + xl1] = tv[pz][u];
       }
   }
   {
@@ -748,18 +763,20 @@ __global__ __launch_bounds__(kBS) void k_decode_l0t(DecPlan D) {
   t.xo0 = xo0;
   t.step = g.step;
   const char *__restrict__ sgb = reinterpret_cast<const char *>(sg);
-  char *__restrict__ obase = reinterpret_cast<char *>(D.out + (size_t)bp.o[0] * n1 * n2);
+  // output: the field (level 0) or the level's grid, from the block's first plane
+  const uint32_t f1 = LV == 0 ? n1 : (uint32_t)D.gd[LV][1], f2 = LV == 0 ? n2 : (uint32_t)D.gd[LV][2];
+  char *__restrict__ obase = reinterpret_cast<char *>((LV == 0 ? D.out : D.gp[LV]) + (size_t)(bp.o[0] / S) * f1 * f2);
   const bool zu = np == 2;
-  const uint32_t rowB = n2 * 4u;
-  const uint32_t xe0 = ((we * n1 + bp.o[1]) * n2 + bp.o[2]) * 4u;     // even plane, row 0
-  const uint32_t xo0b = xe0 + n1 * n2 * 4u;                         // odd plane, row 0
+  const uint32_t rowB = f2 * 4u;
+  const uint32_t xe0 = ((we * f1 + bp.o[1] / S) * f2 + bp.o[2] / S) * 4u;  // even plane, row 0
+  const uint32_t xo0b = xe0 + f1 * f2 * 4u;                               // odd plane, row 0
   const uint32_t u = min((uint32_t)lane, mx - 1);                   // lanes past the row copy its last point
   const uint32_t lx0 = u >> 1;
   const bool xav = (u & 1u) && lx0 + 1 < gx;
   const uint32_t lg = lx0 * 4u, lx = u * 4u;
-  constexpr uint32_t kRow = kD0Side * 4u, kPl = kD0Plane * 4u;
+  constexpr uint32_t kRow = TD::Side * 4u, kPl = TD::Plane * 4u;
   const bool odd_u = (u & 1u) != 0;
-  const uint32_t rown = all ? my : min(my, owny);                   // rows written
+  const uint32_t rown = all ? my : min(my, (owny + S - 1) / S);     // rows written
 
   // ---- even plane: rows v = 2a (odd u from codes, even u from level 1) and
   // v = 2a + 1 (every u from codes).  A wave reads the parents and codes of
@@ -774,7 +791,7 @@ __global__ __launch_bounds__(kBS) void k_decode_l0t(DecPlan D) {
   const uint64_t wrow0 = ((uint64_t)(bp.o[0] + we) * n1 + bp.o[1]) * bnw + (bp.o[2] >> 6);
   const uint32_t nvb = min(mx, 64u);
   const unsigned long long vmask = __ballot((uint32_t)lane < nvb);
-  const int nk = D.bits ? D.nk : 0;
+  const int nk = (LV == 0 && D.bits) ? D.nk : 0;
   // the store of a group's words: lane L holds row k = L mod 8 (its row in
   // the plane: rowof(k)) and isovalue 8 * set + L / 8
   auto bits_store = [&](const D0Bits &q, auto rowof) {
@@ -844,7 +861,7 @@ __global__ __launch_bounds__(kBS) void k_decode_l0t(DecPlan D) {
     }
   }
   // ---- odd plane: rows 2m (y even) and 2m + 1 (y odd), every u from codes
-  if (has_odd && (all || we + 1 < ownz)) {
+  if (has_odd && (all || (we + 1) * S < ownz)) {
     for (uint32_t m0 = wave; 2 * m0 < rown; m0 += kWaves * (kD0Rows / 2)) {
       float A0[kD0Rows / 2], A1[kD0Rows / 2], B0[kD0Rows / 2], B1[kD0Rows / 2];
       float C0[kD0Rows / 2], C1[kD0Rows / 2], E0[kD0Rows / 2], E1[kD0Rows / 2];
@@ -920,7 +937,7 @@ __global__ __launch_bounds__(kBS) void k_decode_l0t(DecPlan D) {
   }
   // ---- the points u = 64 (65-point rows), one row per lane, when the block
   // owns them (the last block along x) or writes its closed extent
-  if (mx == 65 && (all || 64u < ownx)) {
+  if constexpr (LV == 0) if (mx == 65 && (all || 64u < ownx)) {
     const uint32_t nrow = (has_odd && (all || we + 1 < ownz) ? 2u : 1u) * rown;
     for (uint32_t r0 = wave * 64; r0 < nrow; r0 += kWaves * 64) {
       const uint32_t rr = r0 + (uint32_t)lane;
@@ -952,6 +969,9 @@ __global__ __launch_bounds__(kBS) void k_decode_l0t(DecPlan D) {
     }
   }
 }
+
+__global__ __launch_bounds__(kBS) void k_decode_l0t(DecPlan D) { decode_tile<0>(D); }
+__global__ __launch_bounds__(kBS) void k_decode_l1t(DecPlan D) { decode_tile<1>(D); }
 
 template <bool DIFF>
 __global__ __launch_bounds__(kBS) void k_decode_l0(DecPlan D) { decode_fast<0, DIFF>(D); }
@@ -1021,6 +1041,15 @@ bool decode_tile0_used(const DecPlan &p) {
   return p.lo == 0 && p.tile0 && g.B == 64 && g.nL >= 2 && slab32 && p.l0.small && !g.diff && !g.lossless;
 }
 
+// Level 1 likewise (as the output or on the way to level 0), below level 2.
+static bool decode_tile1_used(const DecPlan &p) {
+  const Geo &g = p.g;
+  int64_t o[3], hi[3];
+  block_ext(g, 0, o, hi);
+  const bool slab32 = 4.0 * (double)(hi[0] - o[0] + 1) * (double)g.n[1] * (double)g.n[2] < 4294967296.0;
+  return p.lo <= 1 && p.tile0 && g.B == 64 && g.nL >= 3 && slab32 && p.l0.small && !g.diff && !g.lossless;
+}
+
 void launch_decode(const DecPlan &p, hipStream_t s) {
   const Geo &g = p.g;
   const int L = g.nL - 1;
@@ -1040,7 +1069,9 @@ void launch_decode(const DecPlan &p, hipStream_t s) {
       const int64_t ntl = ceil_div(ceil_div(sl.npts, 64), 64);
       const dim3 grid((unsigned)(ntl > 0 ? ntl : 1), (unsigned)g.nblocks);
       prof_mark(l == 1 ? "k_decode_l1" : "k_decode_l2", s, 0);
-      if (l == 1 && L >= 2 && slab32 && p.l0.small) {
+      if (l == 1 && decode_tile1_used(p)) {
+        k_decode_l1t<<<dim3((unsigned)((g.B / 2 + 2) / 2), (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
+      } else if (l == 1 && L >= 2 && slab32 && p.l0.small) {
         // one tile per workgroup: 16 chunks per wave
         if (g.diff) k_decode_l1<true><<<grid, dim3(kBS), 0, s>>>(p);
         else k_decode_l1<false><<<grid, dim3(kBS), 0, s>>>(p);
