@@ -388,7 +388,7 @@ static int mc_plan(const float *d_field, const int64_t dims[3], McPlan &M, size_
   size_t o = 0;
   off[0] = o; o = align256(o + 8 * (size_t)(M.nrows * M.nw));
   const int64_t nwords = M.nrows * M.nw;
-  off[1] = o; o = align256(o + sizeof(U4) * (size_t)nwords);
+  off[1] = o; o = align256(o + sizeof(uint32_t) * (size_t)nwords);
   off[2] = o; o = align256(o + sizeof(U4) * (size_t)(nwords + 1));
   off[3] = o; o = align256(o + sizeof(U4) * (size_t)scan_tmp_elems(nwords));
   off[4] = o; o = align256(o + sizeof(uint32_t) * (size_t)(nwords * 64));
@@ -418,7 +418,7 @@ int mc_prepare(const float *d_field, const int64_t dims[3], float isovalue, floa
   if (ws_bytes < need) return fail(CHR_E_NOMEM, "workspace too small: need " + std::to_string(need));
   uint8_t *ws = static_cast<uint8_t *>(d_ws);
   M.bits = reinterpret_cast<unsigned long long *>(ws + off[0]);
-  M.cnt = reinterpret_cast<U4 *>(ws + off[1]);
+  M.cnt = reinterpret_cast<uint32_t *>(ws + off[1]);
   M.P = reinterpret_cast<U4 *>(ws + off[2]);
   M.vlist = reinterpret_cast<uint32_t *>(ws + off[4]);
   M.clist = reinterpret_cast<uint32_t *>(ws + off[5]);

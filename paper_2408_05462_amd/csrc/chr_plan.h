@@ -91,7 +91,8 @@ struct McPlan {
   float k, spacing;
   const float *f;
   unsigned long long *bits;      // nrows * nw below-isovalue bits
-  U4 *cnt, *P;                   // per word {vertices, triangles, crossing points, active cells} and prefix
+  uint32_t *cnt;                 // per word {vertices, triangles, crossing points, active cells}, packed (scan.h)
+  U4 *P;                         // their exclusive prefix
   uint32_t *vlist;               // crossing points (word*64 + bit), cap_pv entries
   uint32_t *clist;               // active cells (word*64 + bit), cap_ac entries
   uint32_t *tb;                  // first triangle id of every 256th active cell, cap_ac / 256 + 1 entries

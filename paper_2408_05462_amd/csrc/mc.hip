@@ -241,7 +241,7 @@ __global__ __launch_bounds__(kBS) void k_mc_count(McPlan M) {
     nac = (uint32_t)__popcll(act);
     if (act) nt = word_tris(C, act, fix);
   }
-  M.cnt[gw] = U4{nv, nt, npv, nac};
+  M.cnt[gw] = nv | (nt << 8) | (npv << 17) | (nac << 24);   // the packed record scan_u4_packed reads
 }
 
 __device__ inline float interp(float fa, float fb, float k) {
@@ -614,7 +614,7 @@ void launch_mc_count(const McPlan &p0, U4 *scan_tmp, hipStream_t s) {
   prof_mark("k_mc_count", s, 0);
   k_mc_count<<<dim3((unsigned)ceil_div(nwords, kBS)), dim3(kBS), 0, s>>>(p);
   prof_mark("k_mc_count", s, 1);
-  scan_u4(p.cnt, p.P, nwords, scan_tmp, s);
+  scan_u4_packed(p.cnt, p.P, nwords, scan_tmp, s);
   k_mc_counts<<<dim3(1), dim3(64), 0, s>>>(p, 1);
 }
 
@@ -642,7 +642,7 @@ void launch_mc(const McPlan &p0, U4 *scan_tmp, hipStream_t s) {
   prof_mark("k_mc_count", s, 0);
   k_mc_count<<<dim3((unsigned)ceil_div(nwords, kBS)), dim3(kBS), 0, s>>>(p);
   prof_mark("k_mc_count", s, 1);
-  scan_u4(p.cnt, p.P, nwords, scan_tmp, s);
+  scan_u4_packed(p.cnt, p.P, nwords, scan_tmp, s);
   launch_mc_emit(p, s);
 }
 
@@ -659,7 +659,7 @@ void launch_mc_from_bits(const McPlan &p0, U4 *scan_tmp, hipStream_t s) {
   prof_mark("k_mc_count", s, 0);
   k_mc_count<<<dim3((unsigned)ceil_div(nwords, kBS)), dim3(kBS), 0, s>>>(p);
   prof_mark("k_mc_count", s, 1);
-  scan_u4(p.cnt, p.P, nwords, scan_tmp, s);
+  scan_u4_packed(p.cnt, p.P, nwords, scan_tmp, s);
   launch_mc_emit(p, s);
 }
 

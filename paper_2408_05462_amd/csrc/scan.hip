@@ -1,10 +1,14 @@
 // scan.hip -- device-wide exclusive prefix sums for gfx950.
 //
-// Three launches: per-tile totals (coalesced striped loads), one workgroup
-// scanning the tile totals, and a downsweep that scans each tile as eight
-// 256-element rows with wave-level shuffles and adds the tile's prefix.
-// Small inputs take one launch.
+// Three launches: per-tile totals (coalesced loads, all in flight together),
+// one workgroup scanning the tile totals, and a downsweep.  For the 4 x u32
+// records (the chunk and word counts) a wave scans its 512 consecutive
+// elements as 8 rows of 64 with DPP (row shifts, then row broadcasts), so a
+// tile needs one workgroup barrier; the 64-bit scans (short: section sizes)
+// keep the shuffle-based block scan.  Small inputs take one launch.
 #include "scan.h"
+
+#include <type_traits>
 
 #include "chr_device.h"
 
@@ -51,6 +55,94 @@ __device__ T block_excl_scan(T v, T *total, T *lds) {
   __syncthreads();
   *total = tot;
   return add(pre, sub(x, v));
+}
+
+// Inclusive sum over the 64 lanes through DPP: shifts by 1, 2, 4 and 8
+// within each 16-lane row, then the broadcasts of lanes 15 and 31 into the
+// rows after them (a lane without a source adds 0).
+__device__ inline uint32_t wave_incl_u32(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);   // row_shr:1
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);   // row_shr:2
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);   // row_shr:4
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);   // row_shr:8
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);   // row_bcast:15
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);   // row_bcast:31
+  return v;
+}
+__device__ inline U4 wave_incl(U4 v) {
+  return U4{wave_incl_u32(v.x), wave_incl_u32(v.y), wave_incl_u32(v.z), wave_incl_u32(v.w)};
+}
+__device__ inline U4 lane63(U4 v) {
+  return U4{(uint32_t)__builtin_amdgcn_readlane((int)v.x, 63), (uint32_t)__builtin_amdgcn_readlane((int)v.y, 63),
+            (uint32_t)__builtin_amdgcn_readlane((int)v.z, 63), (uint32_t)__builtin_amdgcn_readlane((int)v.w, 63)};
+}
+
+// Records as scanned: 4 x u32 as stored, or unpacked from the 32-bit form
+// of marching cubes' word counts (see scan.h).
+__device__ inline U4 rec(const U4 *in, int64_t k) { return in[k]; }
+__device__ inline U4 rec(const uint32_t *in, int64_t k) {
+  const uint32_t c = in[k];
+  return U4{c & 0xffu, (c >> 8) & 0x1ffu, (c >> 17) & 0x7fu, (c >> 24) & 0x7fu};
+}
+
+// Tile totals of 4 x u32 records: eight loads a lane, a DPP sum per wave.
+template <class In>
+__global__ __launch_bounds__(kBS) void k_scan_reduce_u4(const In *__restrict__ in, U4 *__restrict__ part, int64_t n) {
+  __shared__ U4 lds[kBS / kWave];
+  const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)(threadIdx.x / kWave) * (kTile / (kBS / kWave));
+  const int lane = (int)(threadIdx.x & (kWave - 1));
+  U4 v[kIPT];
+#pragma unroll
+  for (int r = 0; r < kIPT; r++) {
+    const int64_t k = base + r * kWave + lane;
+    v[r] = k < n ? rec(in, k) : U4{0, 0, 0, 0};
+  }
+  U4 t = U4{0, 0, 0, 0};
+#pragma unroll
+  for (int r = 0; r < kIPT; r++) t = add(t, v[r]);
+  t = lane63(wave_incl(t));
+  if (lane == 0) lds[threadIdx.x / kWave] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    U4 tot = lds[0];
+#pragma unroll
+    for (int w = 1; w < kBS / kWave; w++) tot = add(tot, lds[w]);
+    part[blockIdx.x] = tot;
+  }
+}
+
+// Downsweep of 4 x u32 records: a wave's 512 consecutive elements as 8 rows
+// of 64 (DPP scans with a running carry), the waves' totals through LDS
+// (one barrier), the tile's prefix from the partials.
+template <class In>
+__global__ __launch_bounds__(kBS) void k_scan_down_u4(const In *__restrict__ in, U4 *__restrict__ out,
+                                                      const U4 *__restrict__ part, int64_t n) {
+  __shared__ U4 lds[kBS / kWave];
+  const uint32_t wave = threadIdx.x / kWave;
+  const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)wave * (kTile / (kBS / kWave));
+  const int lane = (int)(threadIdx.x & (kWave - 1));
+  U4 v[kIPT];
+#pragma unroll
+  for (int r = 0; r < kIPT; r++) {
+    const int64_t k = base + r * kWave + lane;
+    v[r] = k < n ? rec(in, k) : U4{0, 0, 0, 0};
+  }
+  U4 carry = U4{0, 0, 0, 0};
+#pragma unroll
+  for (int r = 0; r < kIPT; r++) {
+    const U4 inc = add(wave_incl(v[r]), carry);
+    carry = lane63(inc);
+    v[r] = sub(inc, v[r]);                     // exclusive within the wave's run
+  }
+  if (lane == 0) lds[wave] = carry;
+  __syncthreads();
+  U4 pre = part[blockIdx.x];
+  for (uint32_t w = 0; w < wave; w++) pre = add(pre, lds[w]);
+#pragma unroll
+  for (int r = 0; r < kIPT; r++) {
+    const int64_t k = base + r * kWave + lane;
+    if (k < n) out[k] = add(pre, v[r]);
+  }
 }
 
 template <class T>
@@ -105,15 +197,21 @@ __global__ __launch_bounds__(kBS) void k_scan_down(const T *__restrict__ in, T *
 template <class T>
 constexpr int64_t single_max() { return 32768 / (int64_t)sizeof(T); }  // 32 KiB of LDS
 
-template <class T>
-__global__ __launch_bounds__(kBS) void k_scan_single(const T *__restrict__ in, T *__restrict__ out, int64_t n) {
+template <class T, class In>
+__device__ inline T rec_any(const In *in, int64_t k) {
+  if constexpr (std::is_same<T, U4>::value) return rec(in, k);
+  else return in[k];
+}
+
+template <class T, class In = T>
+__global__ __launch_bounds__(kBS) void k_scan_single(const In *__restrict__ in, T *__restrict__ out, int64_t n) {
   constexpr int64_t kMax = single_max<T>();
   __shared__ T buf[kMax];
   __shared__ T lds[kBS / kWave];
 #pragma unroll
   for (int64_t i = 0; i < kMax / kBS; i++) {
     const int64_t k = i * kBS + threadIdx.x;
-    if (k < n) buf[k] = in[k];
+    if (k < n) buf[k] = rec_any<T>(in, k);
   }
   __syncthreads();
   constexpr int64_t per = kMax / kBS;
@@ -145,7 +243,22 @@ void scan_impl(const T *in, T *out, int64_t n, T *tmp, hipStream_t s) {
 
 int64_t scan_tmp_elems(int64_t n) { return ceil_div(n > 0 ? n : 1, kTile) + 1; }
 
-void scan_u4(const U4 *in, U4 *out, int64_t n, U4 *tmp, hipStream_t s) { scan_impl<U4>(in, out, n, tmp, s); }
+template <class In>
+static void scan_records(const In *in, U4 *out, int64_t n, U4 *tmp, hipStream_t s) {
+  if (n <= single_max<U4>()) {
+    k_scan_single<U4, In><<<dim3(1), dim3(kBS), 0, s>>>(in, out, n);
+    return;
+  }
+  const int64_t ntiles = ceil_div(n, kTile);
+  k_scan_reduce_u4<In><<<dim3((unsigned)ntiles), dim3(kBS), 0, s>>>(in, tmp, n);
+  k_scan_part<U4><<<dim3(1), dim3(kBS), 0, s>>>(tmp, ntiles, out + n);
+  k_scan_down_u4<In><<<dim3((unsigned)ntiles), dim3(kBS), 0, s>>>(in, out, tmp, n);
+}
+
+void scan_u4(const U4 *in, U4 *out, int64_t n, U4 *tmp, hipStream_t s) { scan_records<U4>(in, out, n, tmp, s); }
+void scan_u4_packed(const uint32_t *in, U4 *out, int64_t n, U4 *tmp, hipStream_t s) {
+  scan_records<uint32_t>(in, out, n, tmp, s);
+}
 void scan_u64(const uint64_t *in, uint64_t *out, int64_t n, uint64_t *tmp, hipStream_t s) {
   scan_impl<uint64_t>(in, out, n, tmp, s);
 }

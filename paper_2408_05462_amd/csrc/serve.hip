@@ -94,7 +94,7 @@ McSizes mc_sizes(const int64_t n[3]) {
   z.nw = ceil_div(n[2], 64);
   z.nwords = z.nrows * z.nw;
   z.bits = align_up(8 * (size_t)z.nwords);
-  z.cnt = align_up(sizeof(U4) * (size_t)z.nwords);
+  z.cnt = align_up(sizeof(uint32_t) * (size_t)z.nwords);
   z.P = align_up(sizeof(U4) * (size_t)(z.nwords + 1));
   z.scan = align_up(sizeof(U4) * (size_t)scan_tmp_elems(z.nwords));
   z.counts = align_up(4 * sizeof(int64_t));
@@ -262,7 +262,7 @@ int launch_group(chr_server *s, int j) {
     M.k = r.k;
     M.spacing = (float)(1 << r.level);
     M.bits = reinterpret_cast<unsigned long long *>(c);
-    M.cnt = reinterpret_cast<U4 *>(c + z.bits);
+    M.cnt = reinterpret_cast<uint32_t *>(c + z.bits);
     M.P = reinterpret_cast<U4 *>(c + z.bits + z.cnt);
     r.scan = reinterpret_cast<U4 *>(c + z.bits + z.cnt + z.P);
     M.counts = reinterpret_cast<int64_t *>(c + z.bits + z.cnt + z.P + z.scan);
