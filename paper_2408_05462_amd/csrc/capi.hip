@@ -178,6 +178,7 @@ EncLayout enc_layout(EncPlan &P) {
     const int64_t ppb1_chunks = encode_l1_groups(q);
     q.tile1 = 1;
     const int64_t ppb1 = std::max<int64_t>(ppb1_chunks, encode_l1_groups(q));
+    q.top = 0;
     const int64_t ppb_max = ppb0 + ppb1 + encode_l2_groups(q) + 1;
     Lo.part_records = (size_t)(g.nblocks * ppb_max);
   }
@@ -300,6 +301,7 @@ int enc_prepare(const float *d_field, const int64_t dims[3], double error_bound,
   P.flags = d_flags;
   P.tile0 = (g_tune.tile0 && encode_tile0_ok(P)) ? 1 : 0;
   P.tile1 = (g_tune.tile0 && encode_tile1_ok(P)) ? 1 : 0;
+  P.top = (g_tune.tile0 && encode_top_ok(P)) ? 1 : 0;
   EncLayout Lo = enc_layout(P);
   if (ws_bytes < Lo.total) return fail(CHR_E_NOMEM, "workspace too small: need " + std::to_string(Lo.total));
   if (capacity < P.payload_off) return fail(CHR_E_CAPACITY, "capacity below the header and tables");

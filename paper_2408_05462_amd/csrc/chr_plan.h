@@ -30,6 +30,7 @@ struct EncPlan {
   int cpw0;                      // level-0 chunks per wave (tile shape; results do not depend on it)
   int tile0;                     // level 0 by plane pairs (64-cell blocks; results do not depend on it)
   int tile1;                     // level 1 likewise
+  int top;                       // levels L .. 2 of a 64-cell block in one workgroup, in LDS
   int64_t slot_base[kMaxLevels];
   uint32_t maxch[kMaxLevels];
   int64_t nslots;
@@ -117,6 +118,7 @@ void launch_encode(const EncPlan &p, int64_t scan_tmp_elems_u4, U4 *scan_tmp, ui
 int64_t encode_fine_groups(const EncPlan &p);   // level-0 workgroups per block
 bool encode_tile0_ok(const EncPlan &p);         // level 0 can run by plane pairs
 bool encode_tile1_ok(const EncPlan &p);         // level 1 can run by plane pairs
+bool encode_top_ok(const EncPlan &p);           // levels L .. 2 can run in one workgroup per block
 int64_t encode_tile0_groups(const EncPlan &p);  // plane pairs per block
 int64_t encode_l1_groups(const EncPlan &p);     // level-1 workgroups per block
 int64_t encode_l2_groups(const EncPlan &p);     // level-2 workgroups per block (records reserved)

@@ -977,6 +977,230 @@ __global__ __launch_bounds__(kBS) void k_encode_l1t(EncPlan P) {
   encode_tile<KB, LL, 1>(P);
 }
 
+// ------------------------------------------------ levels L .. 2 in one pass
+//
+// The levels of a 64-cell block from the anchors down to level 2 hold at
+// most 17^3 points (the block's points of the 4-grid).  One workgroup per
+// block: each thread owns fixed 4-grid points (coordinates by constant
+// divisions, a point's level from its coordinates' trailing zeros), reads
+// their input once and keeps it in registers.  Level by level, coarsest
+// first, a thread's points of that level predict from the reconstructed
+// coarser points in LDS, quantize and check as everywhere else, leave their
+// reconstruction in LDS and their code at their section index (in closed
+// form from the coordinates) in an LDS code array.  Then the chunks of every
+// level are packed into their slots and the reconstructed 4-grid is written
+// to the level-2 grid, where level 1 predicts from it.
+
+constexpr int kTopSide = 17;                             // 4-grid points per axis of a 64-cell block
+constexpr int kTopPts = kTopSide * kTopSide * kTopSide;  // 4913
+constexpr int kTopCodes = kTopPts + 6 * 64;              // codes of every level (at most 5), each 64-aligned
+constexpr int kTopBS = 1024;                             // threads per block
+constexpr int kTopWaves = kTopBS / kWave;
+constexpr int kTopPer = (kTopPts + kTopBS - 1) / kTopBS; // 4-grid points per thread
+
+__device__ inline uint32_t top_idx(uint32_t z, uint32_t y, uint32_t x) { return (z * kTopSide + y) * kTopSide + x; }
+
+// The section sizes of level l of a block (as sec_geom, without divisors).
+struct SecDims {
+  uint32_t mx, my, mz, rowE, Pe, Po, npts;
+};
+__device__ inline SecDims sec_dims(const BlockPos &bp, int l, int L) {
+  SecDims d;
+  d.mz = ((bp.hi[0] - bp.o[0]) >> l) + 1;
+  d.my = ((bp.hi[1] - bp.o[1]) >> l) + 1;
+  d.mx = ((bp.hi[2] - bp.o[2]) >> l) + 1;
+  if (l == L) {
+    d.rowE = 0; d.Pe = 0; d.Po = d.mx * d.my;
+    d.npts = d.mx * d.my * d.mz;
+  } else {
+    const uint32_t cx = (d.mx + 1) / 2, cy = (d.my + 1) / 2, cz = (d.mz + 1) / 2;
+    d.rowE = d.mx - cx;
+    d.Pe = d.my * d.mx - cy * cx;
+    d.Po = d.my * d.mx;
+    d.npts = d.mz * d.my * d.mx - cz * cy * cx;
+  }
+  return d;
+}
+
+// Section index of the level-l point (w, v, u) (level-l units): lexicographic
+// over the level's points (the anchors' level: every point).
+__device__ inline uint32_t sec_index(const SecDims &d, bool top, uint32_t w, uint32_t v, uint32_t u) {
+  if (top) return (w * d.my + v) * d.mx + u;
+  const uint32_t base = (w >> 1) * (d.Pe + d.Po);
+  if (w & 1u) return base + d.Pe + v * d.mx + u;
+  const uint32_t row = (v >> 1) * (d.rowE + d.mx);
+  return (v & 1u) ? base + row + d.rowE + u : base + row + (u >> 1);
+}
+
+template <int KB>
+__global__ __launch_bounds__(kTopBS) void k_encode_top(EncPlan P) {
+  __shared__ float R[kTopPts];                 // the reconstruction at the block's 4-grid points
+  __shared__ uint16_t sc[kTopCodes];
+  __shared__ uint32_t pack[kTopWaves][64];
+  __shared__ Part red[kTopWaves];
+  __shared__ uint32_t base[kMaxLevels], npt[kMaxLevels];   // each level's first code and points
+  const uint32_t b = blockIdx.x;
+  const Geo &gq = P.g;
+  const int L = gq.nL - 1;
+  const BlockPos bp = block_pos(gq, P.l0, b);
+  const uint32_t wave = wave_index();
+  const int lane = lane_id();
+  const uint32_t n1 = (uint32_t)gq.n[1], n2 = (uint32_t)gq.n[2];
+  const uint32_t d0 = ((bp.hi[0] - bp.o[0]) >> 2) + 1, d1 = ((bp.hi[1] - bp.o[1]) >> 2) + 1;
+  const uint32_t d2 = ((bp.hi[2] - bp.o[2]) >> 2) + 1;
+  // the thread's points: coordinates and level packed in one word (x, y, z
+  // in bits 0-4, 5-9, 10-14, level + 1 from bit 15, 0 for no point), input
+  // (all loads in flight)
+  uint32_t pc[kTopPer];
+  float xv[kTopPer];
+  {
+    const char *__restrict__ xbase = reinterpret_cast<const char *>(P.x + (size_t)bp.o[0] * n1 * n2);
+#pragma unroll
+    for (int k = 0; k < kTopPer; k++) {
+      const uint32_t i = threadIdx.x + (uint32_t)k * kTopBS;
+      const uint32_t z = i / (kTopSide * kTopSide), y = (i / kTopSide) % kTopSide, x = i % kTopSide;
+      const bool in = i < (uint32_t)kTopPts && z < d0 && y < d1 && x < d2;
+      int lv = L;
+      if (z) lv = min(lv, 2 + __builtin_ctz(z));
+      if (y) lv = min(lv, 2 + __builtin_ctz(y));
+      if (x) lv = min(lv, 2 + __builtin_ctz(x));
+      const uint32_t zc = min(z, d0 - 1), yc = min(y, d1 - 1), xc = min(x, d2 - 1);
+      pc[k] = xc | (yc << 5) | (zc << 10) | (in ? (uint32_t)(lv + 1) << 15 : 0u);
+      xv[k] = ldf(xbase, ((4 * zc * n1 + bp.o[1] + 4 * yc) * n2 + bp.o[2] + 4 * xc) * 4u);
+    }
+  }
+  if (threadIdx.x == 0) {
+    uint32_t off = 0;
+    for (int l = L; l >= 2; l--) {
+      const uint32_t n = sec_dims(bp, l, L).npts;
+      base[l] = off;
+      npt[l] = n;
+      off += (n + 63) & ~63u;
+    }
+  }
+  float iso[KB];
+#pragma unroll
+  for (int jj = 0; jj < KB; jj++) iso[jj] = gq.iso[jj];
+  Part acc;
+  part_init(acc);
+  uint32_t nO = 0, nC = 0;
+  __syncthreads();
+  // ---- the levels, coarsest first
+  for (int l = L; l >= 2; l--) {
+    const SecDims sd = sec_dims(bp, l, L);
+    const uint32_t sh = (uint32_t)(l - 2), st = 1u << sh;     // the level's step on the 4-grid
+    const int64_t slot0 = P.slot_base[l] + (int64_t)b * P.maxch[l];
+    const uint32_t bl = base[l];
+#pragma unroll
+    for (int k = 0; k < kTopPer; k++) {
+      if ((pc[k] >> 15) != (uint32_t)(l + 1)) continue;
+      const uint32_t x = pc[k] & 31u, y = (pc[k] >> 5) & 31u, z = (pc[k] >> 10) & 31u;
+      const uint32_t w = z >> sh, v = y >> sh, u = x >> sh;
+      float p = 0.0f;
+      if (l < L) {
+        // parents at -st and +st along the odd axes, the lower alone where
+        // the upper is outside the domain
+        const uint32_t oz = w & 1u, oy = v & 1u, ox = u & 1u;
+        const uint32_t zl = z - oz * st, yl = y - oy * st, xl = x - ox * st;
+        const bool zu = oz && z + st < d0, yu = oy && y + st < d1, xu = ox && x + st < d2;
+        const uint32_t zb = zu ? z + st : zl, yb = yu ? y + st : yl, xb = xu ? x + st : xl;
+        p = midpoint8(R[top_idx(zl, yl, xl)], R[top_idx(zl, yl, xb)], R[top_idx(zl, yb, xl)], R[top_idx(zl, yb, xb)],
+                      R[top_idx(zb, yl, xl)], R[top_idx(zb, yl, xb)], R[top_idx(zb, yb, xl)], R[top_idx(zb, yb, xb)],
+                      zu, yu, xu);
+      }
+      int32_t q;
+      int O, C = 0;
+      float xr;
+      quantize(gq, xv[k], p, q, O, xr);
+      if (!O && gq.K > 0) C = rank_of<KB>(iso, gq.K, xv[k]) != rank_of<KB>(iso, gq.K, xr);
+      const bool E = O || C;
+      if (E) { xr = xv[k]; q = 0; }
+      R[top_idx(z, y, x)] = xr;
+      const uint32_t j = sec_index(sd, l == L, w, v, u);
+      sc[bl + j] = E ? kT0Exact : (uint16_t)(((uint32_t)q << 1) ^ (uint32_t)(q >> 31));
+      if (E) P.exv[slot0 * 64 + j] = xv[k];   // slot j / 64, lane j % 64
+      const uint32_t ro = ord_of(xr), xo = ord_of(xv[k]);
+      acc.rmin = min(acc.rmin, ro); acc.rmax = max(acc.rmax, ro);
+      acc.xmin = min(acc.xmin, xo); acc.xmax = max(acc.xmax, xo);
+      acc.nonfinite |= !isfinite(xv[k]);
+      if (bp.o[0] + 4 * z < bp.own[0] && bp.o[1] + 4 * y < bp.own[1] && bp.o[2] + 4 * x < bp.own[2]) {
+        nO += (uint32_t)O;
+        nC += (uint32_t)C;
+      }
+    }
+    // codes past the section in its last chunk read as 0 when packing
+    const uint32_t pad = ((sd.npts + 63) & ~63u) - sd.npts;
+    if (threadIdx.x < pad) sc[bl + sd.npts + threadIdx.x] = 0;
+    __syncthreads();
+  }
+  // ---- pack every level's chunks into their slots (exact values are already
+  // in the slots, at their lanes: count word 3 says so); slots past a
+  // section (a shorter block than the first) get zero counts
+  uint32_t *pk = pack[wave];
+  for (int l = L; l >= 2; l--) {
+    const uint32_t nch = (npt[l] + 63) / 64, bl = base[l];
+    const int64_t slot0 = P.slot_base[l] + (int64_t)b * P.maxch[l];
+    for (uint32_t c = nch + threadIdx.x; c < P.maxch[l]; c += kTopBS) P.cnt[slot0 + c] = U4{0, 0, 0, 0};
+    char *__restrict__ payw = reinterpret_cast<char *>(P.pay + slot0 * 32);
+    for (uint32_t c = wave; c < nch; c += kTopWaves) {
+      const uint32_t v16 = sc[bl + c * 64 + (uint32_t)lane];
+      const uint64_t em = __ballot(v16 == kT0Exact);
+      const uint32_t zz = __builtin_amdgcn_inverse_ballot_w64(em) ? 0u : v16;
+      const uint32_t orv = wave_or_dpp(zz);
+      const uint32_t wb = orv ? 32u - (uint32_t)__clz((int)orv) : 0u;
+      pk[lane] = 0u;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      if (zz) {
+        const uint32_t bit = mul24s((uint32_t)lane, wb), wi = bit >> 5, off = bit & 31u;
+        __hip_atomic_fetch_or(&pk[wi], zz << off, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        if (off + wb > 32u)
+          __hip_atomic_fetch_or(&pk[wi + 1], zz >> (32u - off), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      if ((uint32_t)lane < 2 * wb) stu(payw, (c * 32 + (uint32_t)lane) * 4u, pk[lane]);
+      if (lane == 0) {
+        const uint32_t he = em ? 1u : 0u;
+        P.cnt[slot0 + c] = U4{wb, he, (uint32_t)__popcll(em), he};
+        if (em) P.emask[slot0 + c] = em;
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  // ---- the reconstructed 4-grid into the level-2 grid (every point of the
+  // closed extent; neighbours write their shared faces with the same values)
+  {
+    const int64_t *g2 = P.gd[2];
+    const uint32_t e1 = (uint32_t)g2[1], e2 = (uint32_t)g2[2];
+    char *__restrict__ gb =
+        reinterpret_cast<char *>(P.G + P.g_off[2] + (((size_t)(bp.o[0] >> 2)) * e1 + (bp.o[1] >> 2)) * e2 + (bp.o[2] >> 2));
+#pragma unroll
+    for (int k = 0; k < kTopPer; k++)
+      if (pc[k] >> 15) {
+        const uint32_t x = pc[k] & 31u, y = (pc[k] >> 5) & 31u, z = (pc[k] >> 10) & 31u;
+        stf(gb, ((z * e1 + y) * e2 + x) * 4u, R[top_idx(z, y, x)]);
+      }
+  }
+  // the block's record: lanes, then waves, then one thread
+  Part r;
+  r.rmin = wave_min_dpp(acc.rmin); r.rmax = wave_max_dpp(acc.rmax);
+  r.xmin = wave_min_dpp(acc.xmin); r.xmax = wave_max_dpp(acc.xmax);
+  r.nonfinite = wave_or_dpp(acc.nonfinite); r.nO = wave_sum_dpp(nO); r.nC = wave_sum_dpp(nC);
+  r.pad = 0;
+  if (lane == 0) red[wave] = r;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Part t = red[0];
+    for (int i = 1; i < kTopWaves; i++) {
+      t.rmin = min(t.rmin, red[i].rmin); t.rmax = max(t.rmax, red[i].rmax);
+      t.xmin = min(t.xmin, red[i].xmin); t.xmax = max(t.xmax, red[i].xmax);
+      t.nonfinite |= red[i].nonfinite; t.nO += red[i].nO; t.nC += red[i].nC;
+    }
+    P.part[(int64_t)b * P.part_per_block + (P.part_per_block - 1)] = t;
+  }
+}
+
 // Differentiated error control: block b is active when the input on its
 // closed extent crosses a candidate isovalue (min < k <= max).  Workgroup
 // (s, b) reduces planes s, s + kActSplit, ... of block b's extent (each
@@ -1407,6 +1631,7 @@ int64_t encode_l1_groups(const EncPlan &p) {
   return p.g.nL >= 2 ? ceil_div(p.maxch[1] > 0 ? p.maxch[1] : 1, (int64_t)kChunksPerWG) : 0;
 }
 int64_t encode_l2_groups(const EncPlan &p) {
+  if (p.top) return 0;                         // levels L .. 2 in one workgroup per block
   return p.g.nL >= 4 ? ceil_div(p.maxch[2] > 0 ? p.maxch[2] : 1, (int64_t)kChunksPerWG) : 0;
 }
 
@@ -1417,7 +1642,7 @@ static bool slab32(const Geo &g) {
   return 4.0 * (double)(hi[0] - o[0] + 1) * (double)g.n[1] * (double)g.n[2] < 4294967296.0;
 }
 
-bool encode_l2_fast(const EncPlan &p) { return p.g.nL >= 4 && slab32(p.g) && p.l0.small; }
+bool encode_l2_fast(const EncPlan &p) { return !p.top && p.g.nL >= 4 && slab32(p.g) && p.l0.small; }
 
 // Level 0 by plane pairs: 64-cell blocks below a coarser level, one
 // quantizer, no per-point outputs, 32-bit offsets within a block's slab.
@@ -1427,6 +1652,9 @@ bool encode_tile0_ok(const EncPlan &p) {
 
 // Level 1 by plane pairs likewise, below a coarser level (level 2 exists).
 bool encode_tile1_ok(const EncPlan &p) { return encode_tile0_ok(p) && p.g.nL >= 3; }
+
+// Levels L .. 2 of a 64-cell block in one workgroup (level 2 exists).
+bool encode_top_ok(const EncPlan &p) { return encode_tile1_ok(p); }
 
 void encode_pack_layout(EncPlan &p) {
   const int L = p.g.nL - 1;
@@ -1444,7 +1672,11 @@ void launch_encode_levels(const EncPlan &p, hipStream_t s) {
   const Geo &g = p.g;
   const int L = g.nL - 1;
   const int64_t gx = encode_fine_groups(p);
-  if (L >= 2) {
+  if (L >= 2 && p.top) {
+    prof_mark("k_encode_coarse", s, 0);
+    k_encode_top<KB><<<dim3((unsigned)g.nblocks), dim3(kTopBS), 0, s>>>(p);
+    prof_mark("k_encode_coarse", s, 1);
+  } else if (L >= 2) {
     prof_mark("k_encode_coarse", s, 0);
     k_encode_coarse<KB><<<dim3((unsigned)g.nblocks), dim3(kBS), 0, s>>>(p, p.l2fast ? 3 : 2);
     if (p.l2fast) {
