@@ -72,6 +72,12 @@ def lib():
                                    C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
                                    C.POINTER(C.c_size_t)]
         L.orc_compress.restype = C.c_int
+        L.orc_compress_merged.argtypes = [C.c_void_p, i64p, C.c_double, C.c_double, C.c_void_p, C.c_int, C.c_int,
+                                          C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                          C.c_size_t, C.POINTER(C.c_size_t)]
+        L.orc_compress_merged.restype = C.c_int
+        L.orc_compress_bound_merged.argtypes = [i64p, C.c_int, C.c_int, C.c_int]
+        L.orc_compress_bound_merged.restype = C.c_size_t
         L.orc_stream_verify.argtypes = [C.c_void_p, C.c_size_t]
         L.orc_stream_codes.argtypes = [C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]
         L.orc_decompress.argtypes = [C.c_void_p, C.c_size_t, C.c_int, C.c_double, C.c_void_p]
@@ -135,22 +141,23 @@ def compress_bound(shape, nL, block):
     return lib().orc_compress_bound(_dims(shape), nL, block)
 
 
-def compress(x, error_bound, isovalues=(), levels=3, block=64, qmax=32767, error_bound_far=0.0):
+def compress(x, error_bound, isovalues=(), levels=3, block=64, qmax=32767, error_bound_far=0.0, merge=0):
     """Returns dict(stream=bytes(np.uint8), q, flags, xr).  error_bound_far > 0
     selects differentiated error control (the far bound away from blocks that
-    cross a candidate isovalue)."""
+    cross a candidate isovalue); merge > 1 merges blocks of equal index
+    signature into units of at most `merge` blocks per axis before
+    compression."""
     x, px = _f32(x)
     iso = np.ascontiguousarray(np.asarray(isovalues, np.float32).reshape(-1))
-    cap = compress_bound(x.shape, levels, block)
+    cap = lib().orc_compress_bound_merged(_dims(x.shape), levels, block, int(merge))
     stream = np.zeros(cap, np.uint8)
     q = np.zeros(x.shape, np.int32)
     fl = np.zeros(x.shape, np.uint8)
     xr = np.zeros(x.shape, np.float32)
     nbytes = C.c_size_t()
-    rc = lib().orc_compress(px, _dims(x.shape), float(error_bound), float(error_bound_far), iso.ctypes.data,
-                            len(iso), levels,
-                            block, qmax, q.ctypes.data, fl.ctypes.data, xr.ctypes.data,
-                            stream.ctypes.data, cap, C.byref(nbytes))
+    rc = lib().orc_compress_merged(px, _dims(x.shape), float(error_bound), float(error_bound_far), iso.ctypes.data,
+                                   len(iso), levels, block, qmax, int(merge), q.ctypes.data, fl.ctypes.data,
+                                   xr.ctypes.data, stream.ctypes.data, cap, C.byref(nbytes))
     if rc != OK:
         raise OracleError(rc, "orc_compress")
     return dict(stream=stream[: nbytes.value].copy(), q=q, flags=fl, xr=xr)
@@ -162,7 +169,8 @@ class Info(C.Structure):
                 ("iso", C.c_float * 16), ("vmin", C.c_float), ("vmax", C.c_float), ("nblocks", C.c_int64),
                 ("nb", C.c_int * 3), ("flags", C.c_uint32), ("total_bytes", C.c_uint64),
                 ("n_outlier", C.c_uint64), ("n_corrected", C.c_uint64), ("payload_offset", C.c_uint64),
-                ("error_bound_far", C.c_double), ("inv_far", C.c_float), ("step_far", C.c_float)]
+                ("error_bound_far", C.c_double), ("inv_far", C.c_float), ("step_far", C.c_float),
+                ("merge", C.c_int), ("mb", C.c_int * 3)]
 
 
 def stream_info(stream):

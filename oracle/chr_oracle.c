@@ -297,6 +297,92 @@ static int point_near(const uint8_t *act, const int64_t nb[3], int64_t B, int64_
 }
 
 /* ------------------------------------------------------------------------ */
+/* block merging before compression (Sec. II.A, third step; reading R22)    */
+/* ------------------------------------------------------------------------ */
+
+/* Index signature of every block: bit j set when the input on the block's
+ * closed extent crosses candidate j (min < k_j <= max).  Blocks with equal
+ * signatures answer every query for a candidate isovalue alike. */
+static void block_signatures(const float *x, const int64_t d[3], int64_t B, const int64_t nb[3],
+                             const float *iso, int K, uint32_t *sig) {
+  int64_t nblocks = nb[0] * nb[1] * nb[2];
+  for (int64_t b = 0; b < nblocks; b++) {
+    int64_t bi[3] = {b / (nb[1] * nb[2]), (b / nb[2]) % nb[1], b % nb[2]}, o[3], hi[3];
+    block_extent(d, B, bi, o, hi);
+    float mn = x[idx3(d, o[0], o[1], o[2])], mx = mn;
+    for (int64_t z = o[0]; z <= hi[0]; z++)
+      for (int64_t y = o[1]; y <= hi[1]; y++)
+        for (int64_t xx = o[2]; xx <= hi[2]; xx++) {
+          float v = x[idx3(d, z, y, xx)];
+          if (v < mn) mn = v;
+          if (v > mx) mx = v;
+        }
+    sig[b] = 0;
+    for (int j = 0; j < K; j++)
+      if (mn < iso[j] && iso[j] <= mx) sig[b] |= 1u << j;
+  }
+}
+
+/* Greedy merging into rectangular units of at most M blocks per axis: the
+ * blocks are visited in lexicographic (z, y, x) order; an unassigned block
+ * starts a unit, which grows along x while the next block is unassigned and
+ * has the same signature, then along y while the whole next row of the unit
+ * qualifies, then along z while the whole next plane does.  Units are
+ * numbered in the order they start.  box[8u .. 8u+5] = first block and one
+ * past the last block of unit u along z, y, x (box[8u+6..7] = 0).  Returns
+ * the number of units; M = 1 gives one unit per block. */
+static int64_t merge_units(const uint32_t *sig, const int64_t nb[3], int M, uint32_t *box, int64_t *owner) {
+  int64_t nblocks = nb[0] * nb[1] * nb[2], U = 0;
+  for (int64_t b = 0; b < nblocks; b++) owner[b] = -1;
+#define BLK(z, y, x) (((z) * nb[1] + (y)) * nb[2] + (x))
+  for (int64_t z0 = 0; z0 < nb[0]; z0++)
+    for (int64_t y0 = 0; y0 < nb[1]; y0++)
+      for (int64_t x0 = 0; x0 < nb[2]; x0++) {
+        if (owner[BLK(z0, y0, x0)] >= 0) continue;
+        uint32_t g = sig[BLK(z0, y0, x0)];
+        int64_t ex = 1, ey = 1, ez = 1;
+        while (ex < M && x0 + ex < nb[2] && owner[BLK(z0, y0, x0 + ex)] < 0 && sig[BLK(z0, y0, x0 + ex)] == g) ex++;
+        for (;;) {
+          if (ey >= M || y0 + ey >= nb[1]) break;
+          int ok = 1;
+          for (int64_t x = x0; x < x0 + ex && ok; x++)
+            ok = owner[BLK(z0, y0 + ey, x)] < 0 && sig[BLK(z0, y0 + ey, x)] == g;
+          if (!ok) break;
+          ey++;
+        }
+        for (;;) {
+          if (ez >= M || z0 + ez >= nb[0]) break;
+          int ok = 1;
+          for (int64_t y = y0; y < y0 + ey && ok; y++)
+            for (int64_t x = x0; x < x0 + ex && ok; x++)
+              ok = owner[BLK(z0 + ez, y, x)] < 0 && sig[BLK(z0 + ez, y, x)] == g;
+          if (!ok) break;
+          ez++;
+        }
+        for (int64_t z = z0; z < z0 + ez; z++)
+          for (int64_t y = y0; y < y0 + ey; y++)
+            for (int64_t x = x0; x < x0 + ex; x++) owner[BLK(z, y, x)] = U;
+        uint32_t *e = box + 8 * U;
+        e[0] = (uint32_t)z0; e[1] = (uint32_t)y0; e[2] = (uint32_t)x0;
+        e[3] = (uint32_t)(z0 + ez); e[4] = (uint32_t)(y0 + ey); e[5] = (uint32_t)(x0 + ex);
+        e[6] = e[7] = 0;
+        U++;
+      }
+#undef BLK
+  return U;
+}
+
+/* Closed extent of a unit of blocks b0 .. b1 - 1 per axis (z, y, x): points
+ * [b0 B, min(b1 B, n - 1)]. */
+static void unit_extent_of(const int64_t dims[3], int64_t B, const uint32_t *e, int64_t o[3], int64_t hi[3]) {
+  for (int a = 0; a < 3; a++) {
+    o[a] = (int64_t)e[a] * B;
+    hi[a] = (int64_t)e[3 + a] * B;
+    if (hi[a] > dims[a] - 1) hi[a] = dims[a] - 1;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
 /* section encoding                                                         */
 /* ------------------------------------------------------------------------ */
 
@@ -401,6 +487,17 @@ static int prepare_iso(const float *iso, int n_iso, float out[16]) {
   return k;
 }
 
+size_t orc_compress_bound_merged(const int64_t dims[3], int nL, int block, int merge) {
+  /* a unit's sections are no larger than its blocks' together (fewer points,
+   * fewer section overheads); each unit adds a 32-byte box entry */
+  size_t t = orc_compress_bound(dims, nL, block);
+  if (merge > 1) {
+    int64_t nblocks = nblk_axis(dims[0], block) * nblk_axis(dims[1], block) * nblk_axis(dims[2], block);
+    t += 32 * (size_t)nblocks;
+  }
+  return t;
+}
+
 size_t orc_compress_bound(const int64_t dims[3], int nL, int block) {
   int64_t nb[3];
   for (int a = 0; a < 3; a++) nb[a] = nblk_axis(dims[a], block);
@@ -430,11 +527,36 @@ static int check_params(const int64_t dims[3], int nL, int block, int qmax) {
   return 0;
 }
 
+/* Largest unit extent (in points) of merged blocks must stay below 2^31
+ * points, as a block's closed extent does. */
+static int merge_ok(const int64_t dims[3], int block, int merge) {
+  if (merge < 0 || merge > 16) return 0;
+  if (merge <= 1) return 1;
+  double pts = 1;
+  for (int a = 0; a < 3; a++) {
+    int64_t e = (int64_t)merge * block;
+    if (e > dims[a] - 1) e = dims[a] - 1;
+    pts *= (double)(e + 1);
+  }
+  return pts < 2147483648.0;
+}
+
 int orc_compress(const float *x, const int64_t dims[3], double error_bound, double error_bound_far,
                  const float *iso_in, int n_iso_in, int nL, int block, int qmax,
                  int32_t *q_out, uint8_t *flags_out, float *xr_out,
                  uint8_t *stream, size_t cap, size_t *stream_bytes) {
+  return orc_compress_merged(x, dims, error_bound, error_bound_far, iso_in, n_iso_in, nL, block, qmax, 1, q_out,
+                             flags_out, xr_out, stream, cap, stream_bytes);
+}
+
+int orc_compress_merged(const float *x, const int64_t dims[3], double error_bound, double error_bound_far,
+                        const float *iso_in, int n_iso_in, int nL, int block, int qmax, int merge,
+                        int32_t *q_out, uint8_t *flags_out, float *xr_out,
+                        uint8_t *stream, size_t cap, size_t *stream_bytes) {
   if (check_params(dims, nL, block, qmax)) return ORC_E_INVAL;
+  if (!merge_ok(dims, block, merge)) return ORC_E_INVAL;
+  /* merging is not combined with differentiated error control */
+  if (merge > 1 && error_bound_far != 0) return ORC_E_INVAL;
   if (!(error_bound >= 0) || !isfinite(error_bound)) return ORC_E_INVAL;
   /* far bound: 0 for one bound everywhere, else finite and >= error_bound */
   if (error_bound_far != 0 && !(error_bound_far >= error_bound && isfinite(error_bound_far))) return ORC_E_INVAL;
@@ -456,8 +578,24 @@ int orc_compress(const float *x, const int64_t dims[3], double error_bound, doub
   int32_t *q = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
   uint8_t *fl = (uint8_t *)malloc((size_t)N);
   uint8_t *act = (uint8_t *)calloc((size_t)nblocks, 1);
-  if (!xr || !q || !fl || !act) { free(xr); free(q); free(fl); free(act); return ORC_E_NOMEM; }
+  uint32_t *sig = (uint32_t *)calloc((size_t)nblocks, sizeof(uint32_t));
+  uint32_t *box = (uint32_t *)malloc(sizeof(uint32_t) * 8 * (size_t)nblocks);
+  int64_t *owner = (int64_t *)malloc(sizeof(int64_t) * (size_t)nblocks);
+  if (!xr || !q || !fl || !act || !sig || !box || !owner) {
+    free(xr); free(q); free(fl); free(act); free(sig); free(box); free(owner);
+    return ORC_E_NOMEM;
+  }
   if (diff) block_activity(x, dims, block, nb, iso, K, act);
+  /* storage units: the blocks themselves, or merged rectangles of blocks
+   * with equal index signatures (reading R22) */
+  const int merged = merge > 1;
+  if (merged) block_signatures(x, dims, block, nb, iso, K, sig);
+  const int64_t U = merge_units(sig, nb, merged ? merge : 1, box, owner);
+  free(sig); free(owner);
+  uint32_t mb[3] = {0, 0, 0};
+  for (int64_t u = 0; u < U; u++)
+    for (int a = 0; a < 3; a++)
+      if (box[8 * u + 3 + a] - box[8 * u + a] > mb[a]) mb[a] = box[8 * u + 3 + a] - box[8 * u + a];
 
   /* Levels from the coarsest; the points of one level depend only on
    * reconstructed values of coarser levels, so their order is immaterial. */
@@ -491,16 +629,18 @@ int orc_compress(const float *x, const int64_t dims[3], double error_bound, doub
         }
   }
 
-  /* stream (reading R9) */
-  size_t tab = HEADER_BYTES, btab = tab + 16 * (size_t)nblocks * (size_t)nL;
-  size_t payload = btab + 16 * (size_t)nblocks;
+  /* stream (reading R9): tables per unit; a merged stream adds the box
+   * table of its units after the unit (block) table */
+  size_t tab = HEADER_BYTES, btab = tab + 16 * (size_t)U * (size_t)nL;
+  size_t xtab = btab + 16 * (size_t)U;
+  size_t payload = xtab + (merged ? 32 * (size_t)U : 0);
 
   /* pass 1: sizes; pass 2: write */
   size_t total = payload;
   int64_t maxn = 0;
-  for (int64_t b = 0; b < nblocks; b++) {
-    int64_t bi[3] = {b / (nb[1] * nb[2]), (b / nb[2]) % nb[1], b % nb[2]}, o[3], hi[3];
-    block_extent(dims, block, bi, o, hi);
+  for (int64_t b = 0; b < U; b++) {
+    int64_t o[3], hi[3];
+    unit_extent_of(dims, block, box + 8 * b, o, hi);
     for (int l = nL - 1; l >= 0; l--) {
       int64_t n = section_points(o, hi, l, nL, NULL);
       if (n > maxn) maxn = n;
@@ -511,14 +651,14 @@ int orc_compress(const float *x, const int64_t dims[3], double error_bound, doub
   uint8_t *se = (uint8_t *)malloc((size_t)(maxn ? maxn : 1));
   float *sx = (float *)malloc(sizeof(float) * (size_t)(maxn ? maxn : 1));
   if (!pts || !sq || !se || !sx) {
-    free(pts); free(sq); free(se); free(sx); free(xr); free(q); free(fl); free(act);
+    free(pts); free(sq); free(se); free(sx); free(xr); free(q); free(fl); free(act); free(box);
     return ORC_E_NOMEM;
   }
   for (int pass = 0; pass < 2; pass++) {
     size_t off = payload;
-    for (int64_t b = 0; b < nblocks; b++) {
-      int64_t bi[3] = {b / (nb[1] * nb[2]), (b / nb[2]) % nb[1], b % nb[2]}, o[3], hi[3];
-      block_extent(dims, block, bi, o, hi);
+    for (int64_t b = 0; b < U; b++) {
+      int64_t o[3], hi[3];
+      unit_extent_of(dims, block, box + 8 * b, o, hi);
       size_t bstart = off;
       float bmin = INFINITY, bmax = -INFINITY;
       for (int l = nL - 1; l >= 0; l--) {
@@ -546,19 +686,21 @@ int orc_compress(const float *x, const int64_t dims[3], double error_bound, doub
         putf(be + 4, bmax);
         put32(be + 8, checksum(stream + bstart, off - bstart));
         put32(be + 12, diff ? (uint32_t)act[b] : 0u);  /* bit 0: active block (R19) */
+        if (merged)
+          for (int k = 0; k < 8; k++) put32(stream + xtab + 32 * (size_t)b + 4 * (size_t)k, box[8 * b + k]);
       }
     }
     total = off;
     if (pass == 0) {
       if (stream_bytes) *stream_bytes = total;
       if (!stream || cap < total) {
-        free(pts); free(sq); free(se); free(sx); free(xr); free(q); free(fl); free(act);
+        free(pts); free(sq); free(se); free(sx); free(xr); free(q); free(fl); free(act); free(box);
         return ORC_E_CAPACITY;
       }
       memset(stream, 0, total);
     }
   }
-  free(pts); free(sq); free(se); free(sx);
+  free(pts); free(sq); free(se); free(sx); free(box);
 
   /* header */
   float vmin = INFINITY, vmax = -INFINITY;
@@ -580,9 +722,9 @@ int orc_compress(const float *x, const int64_t dims[3], double error_bound, doub
   for (int j = 0; j < 16; j++) putf(H + 64 + 4 * j, iso[j]);
   putf(H + 128, vmin);
   putf(H + 132, vmax);
-  put64(H + 136, (uint64_t)nblocks);
+  put64(H + 136, (uint64_t)U);
   for (int a = 0; a < 3; a++) put32(H + 144 + 4 * a, (uint32_t)nb[a]);
-  put32(H + 156, (Q.lossless ? 1u : 0u) | (diff ? 2u : 0u) | (diff && Qf.lossless ? 4u : 0u));
+  put32(H + 156, (Q.lossless ? 1u : 0u) | (diff ? 2u : 0u) | (diff && Qf.lossless ? 4u : 0u) | (merged ? 8u : 0u));
   put64(H + 160, total);
   put64(H + 168, nO);
   put64(H + 176, nC);
@@ -591,6 +733,10 @@ int orc_compress(const float *x, const int64_t dims[3], double error_bound, doub
     putd(H + 192, error_bound_far);
     putf(H + 200, Qf.inv);
     putf(H + 204, Qf.step);
+  }
+  if (merged) {
+    put32(H + 208, (uint32_t)merge);
+    for (int a = 0; a < 3; a++) put32(H + 212 + 4 * a, mb[a]);
   }
   put32(H + 248, checksum(stream + HEADER_BYTES, payload - HEADER_BYTES));
   put32(H + 252, checksum(H, 252));
@@ -632,15 +778,67 @@ int orc_stream_info(const uint8_t *s, size_t n, orc_info *I) {
   I->error_bound_far = getd(s + 192);
   I->inv_far = getf(s + 200);
   I->step_far = getf(s + 204);
+  const int merged = (I->flags & 8u) != 0;
+  I->merge = merged ? (int)get32(s + 208) : 1;
+  for (int a = 0; a < 3; a++) I->mb[a] = merged ? (int)get32(s + 212 + 4 * a) : 1;
+  if (I->flags & ~15u) return ORC_E_CORRUPT;
   if ((I->flags & 2u) && !(I->error_bound_far >= I->error_bound && isfinite(I->error_bound_far))) return ORC_E_CORRUPT;
+  if (merged && (I->flags & 2u)) return ORC_E_CORRUPT;
   if (check_params(I->dims, I->levels, I->block, I->qmax)) return ORC_E_CORRUPT;
+  if (merged && (I->merge < 2 || !merge_ok(I->dims, I->block, I->merge))) return ORC_E_CORRUPT;
+  for (int a = 0; a < 3; a++)
+    if (I->mb[a] < 1 || I->mb[a] > I->merge || I->nb[a] != nblk_axis(I->dims[a], I->block)) return ORC_E_CORRUPT;
+  const int64_t nbt = (int64_t)I->nb[0] * I->nb[1] * I->nb[2];
+  if (I->nblocks < 1 || I->nblocks > nbt || (!merged && I->nblocks != nbt)) return ORC_E_CORRUPT;
   if (I->n_iso < 0 || I->n_iso > 16) return ORC_E_CORRUPT;
   if (I->total_bytes > n) return ORC_E_CORRUPT;
-  if (I->payload_offset != HEADER_BYTES + 16 * (uint64_t)I->nblocks * (uint64_t)I->levels + 16 * (uint64_t)I->nblocks)
+  if (I->payload_offset != HEADER_BYTES + 16 * (uint64_t)I->nblocks * (uint64_t)I->levels + 16 * (uint64_t)I->nblocks +
+                               (merged ? 32 * (uint64_t)I->nblocks : 0))
     return ORC_E_CORRUPT;
   if (I->payload_offset > I->total_bytes) return ORC_E_CORRUPT;
   if (checksum(s + HEADER_BYTES, I->payload_offset - HEADER_BYTES) != get32(s + 248)) return ORC_E_CORRUPT;
+  if (merged) {
+    /* the units tile the block grid: every block in exactly one unit, none
+     * wider than the stored largest extent */
+    uint8_t *seen = (uint8_t *)calloc((size_t)nbt, 1);
+    if (!seen) return ORC_E_NOMEM;
+    const uint8_t *xt = s + HEADER_BYTES + 16 * (size_t)I->nblocks * (size_t)I->levels + 16 * (size_t)I->nblocks;
+    int bad = 0;
+    for (int64_t u = 0; u < I->nblocks && !bad; u++) {
+      uint32_t e[8];
+      for (int k = 0; k < 8; k++) e[k] = get32(xt + 32 * (size_t)u + 4 * (size_t)k);
+      for (int a = 0; a < 3; a++)
+        if (e[a] >= e[3 + a] || e[3 + a] > (uint32_t)I->nb[a] || e[3 + a] - e[a] > (uint32_t)I->mb[a]) bad = 1;
+      if (e[6] || e[7]) bad = 1;
+      for (uint32_t z = e[0]; z < e[3] && !bad; z++)
+        for (uint32_t y = e[1]; y < e[4] && !bad; y++)
+          for (uint32_t x = e[2]; x < e[5] && !bad; x++) {
+            uint8_t *f = seen + ((int64_t)z * I->nb[1] + y) * I->nb[2] + x;
+            if (*f) bad = 1;
+            *f = 1;
+          }
+    }
+    for (int64_t b = 0; b < nbt && !bad; b++)
+      if (!seen[b]) bad = 1;
+    free(seen);
+    if (bad) return ORC_E_CORRUPT;
+  }
   return ORC_OK;
+}
+
+/* Closed extent of storage unit u of a stream (a block, or a merged box). */
+static void unit_extent(const uint8_t *s, const orc_info *I, int64_t u, int64_t o[3], int64_t hi[3]) {
+  uint32_t e[8];
+  if (I->flags & 8u) {
+    const uint8_t *xt = s + HEADER_BYTES + 16 * (size_t)I->nblocks * (size_t)I->levels + 16 * (size_t)I->nblocks;
+    for (int k = 0; k < 6; k++) e[k] = get32(xt + 32 * (size_t)u + 4 * (size_t)k);
+  } else {
+    e[0] = (uint32_t)(u / ((int64_t)I->nb[1] * I->nb[2]));
+    e[1] = (uint32_t)((u / I->nb[2]) % I->nb[1]);
+    e[2] = (uint32_t)(u % I->nb[2]);
+    for (int a = 0; a < 3; a++) e[3 + a] = e[a] + 1;
+  }
+  unit_extent_of(I->dims, I->block, e, o, hi);
 }
 
 int orc_stream_verify(const uint8_t *s, size_t n) {
@@ -724,8 +922,8 @@ int orc_stream_codes(const uint8_t *s, size_t n, int32_t *q_out, uint8_t *e_out)
   int nL = I.levels;
   int64_t maxn = 0;
   for (int64_t b = 0; b < I.nblocks; b++) {
-    int64_t bi[3] = {b / ((int64_t)I.nb[1] * I.nb[2]), (b / I.nb[2]) % I.nb[1], b % I.nb[2]}, o[3], hi[3];
-    block_extent(I.dims, I.block, bi, o, hi);
+    int64_t o[3], hi[3];
+    unit_extent(s, &I, b, o, hi);
     for (int l = nL - 1; l >= 0; l--) {
       int64_t m = section_points(o, hi, l, nL, NULL);
       if (m > maxn) maxn = m;
@@ -739,8 +937,8 @@ int orc_stream_codes(const uint8_t *s, size_t n, int32_t *q_out, uint8_t *e_out)
   if (!pts || !sq || !se || !sx) { free(pts); free(sq); free(se); free(sx); return ORC_E_NOMEM; }
   rc = ORC_OK;
   for (int64_t b = 0; b < I.nblocks && rc == ORC_OK; b++) {
-    int64_t bi[3] = {b / ((int64_t)I.nb[1] * I.nb[2]), (b / I.nb[2]) % I.nb[1], b % I.nb[2]}, o[3], hi[3];
-    block_extent(I.dims, I.block, bi, o, hi);
+    int64_t o[3], hi[3];
+    unit_extent(s, &I, b, o, hi);
     for (int l = nL - 1; l >= 0 && rc == ORC_OK; l--) {
       int64_t m = section_points(o, hi, l, nL, pts);
       size_t avail;
@@ -787,8 +985,11 @@ int orc_decompress(const uint8_t *s, size_t n, int level, double eb, float *out)
   int64_t od[3];
   for (int a = 0; a < 3; a++) od[a] = ((I.dims[a] - 1) >> level) + 1;
   int64_t B = I.block;
-  size_t le = 1;
-  for (int a = 0; a < 3; a++) le *= (size_t)((B < I.dims[a] - 1 ? B : I.dims[a] - 1) + 1);
+  size_t le = 1;  /* points of the largest unit */
+  for (int a = 0; a < 3; a++) {
+    int64_t e = (int64_t)I.mb[a] * B;
+    le *= (size_t)((e < I.dims[a] - 1 ? e : I.dims[a] - 1) + 1);
+  }
   float *loc = (float *)malloc(sizeof(float) * le);
   int64_t *pts = (int64_t *)malloc(sizeof(int64_t) * 3 * le);
   int32_t *sq = (int32_t *)malloc(sizeof(int32_t) * le);
@@ -797,8 +998,8 @@ int orc_decompress(const uint8_t *s, size_t n, int level, double eb, float *out)
   if (!loc || !pts || !sq || !se || !sx) { free(loc); free(pts); free(sq); free(se); free(sx); free(act); return ORC_E_NOMEM; }
   rc = ORC_OK;
   for (int64_t b = 0; b < I.nblocks && rc == ORC_OK; b++) {
-    int64_t bi[3] = {b / ((int64_t)I.nb[1] * I.nb[2]), (b / I.nb[2]) % I.nb[1], b % I.nb[2]}, o[3], hi[3];
-    block_extent(I.dims, B, bi, o, hi);
+    int64_t o[3], hi[3];
+    unit_extent(s, &I, b, o, hi);
     int64_t le3[3] = {hi[0] - o[0] + 1, hi[1] - o[1] + 1, hi[2] - o[2] + 1};
     for (int l = nL - 1; l >= level && rc == ORC_OK; l--) {
       int64_t m = section_points(o, hi, l, nL, pts);
@@ -1074,8 +1275,8 @@ int orc_block_box(const uint8_t *s, size_t n, float kmin, float kmax, int64_t lo
   for (int64_t b = 0; b < I.nblocks; b++) {
     const float mn = getf(s + btab + 16 * (size_t)b), mx = getf(s + btab + 16 * (size_t)b + 4);
     if (!(mn < mx && mn < kmax && kmin <= mx)) continue;
-    int64_t bi[3] = {b / ((int64_t)I.nb[1] * I.nb[2]), (b / I.nb[2]) % I.nb[1], b % I.nb[2]}, o[3], h[3];
-    block_extent(I.dims, I.block, bi, o, h);
+    int64_t o[3], h[3];
+    unit_extent(s, &I, b, o, h);
     for (int a = 0; a < 3; a++) {
       if (o[a] < lo[a]) lo[a] = o[a];
       if (h[a] > hi[a]) hi[a] = h[a];

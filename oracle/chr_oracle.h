@@ -78,7 +78,23 @@ int orc_compress(const float *x, const int64_t dims[3], double error_bound, doub
                  int32_t *q_out, uint8_t *flags_out, float *xr_out,
                  uint8_t *stream, size_t cap, size_t *stream_bytes);
 
-/* Header fields of a stream (after checksum validation). */
+/* Compression with block merging before compression (Sec. II.A, third
+ * step; reading R22): merge = the largest number of blocks per axis of a
+ * merged unit (0 or 1: no merging, the stream of orc_compress).  Blocks
+ * with equal index signatures (the set of candidate isovalues their input
+ * range crosses) are merged greedily into rectangular units, each stored as
+ * one closed extent; codes and reconstruction are those of orc_compress.
+ * Not combined with error_bound_far (ORC_E_INVAL). */
+int orc_compress_merged(const float *x, const int64_t dims[3], double error_bound, double error_bound_far,
+                        const float *iso, int n_iso, int nL, int block, int qmax, int merge,
+                        int32_t *q_out, uint8_t *flags_out, float *xr_out,
+                        uint8_t *stream, size_t cap, size_t *stream_bytes);
+
+/* Stream size bound with merging (adds the box table). */
+size_t orc_compress_bound_merged(const int64_t dims[3], int nL, int block, int merge);
+
+/* Header fields of a stream (after checksum validation).  nblocks counts the
+ * storage units (blocks, or merged units when flags bit 3 is set). */
 typedef struct {
   int64_t dims[3];
   int levels, block, qmax, n_iso;
@@ -92,6 +108,8 @@ typedef struct {
   uint64_t total_bytes, n_outlier, n_corrected, payload_offset;
   double error_bound_far;  /* flags bit 1: differentiated error control */
   float inv_far, step_far;
+  int merge;               /* flags bit 3: largest blocks per axis of a unit (1: no merging) */
+  int mb[3];               /* largest unit extent in blocks along z, y, x */
 } orc_info;
 
 int orc_stream_info(const uint8_t *stream, size_t n, orc_info *out);

@@ -82,13 +82,27 @@ class Stream:
         self.e_far = struct.unpack_from("<d", s, 192)[0]
         self.far_inv, self.far_step = f32(200), f32(204)
         self.tab_sum, self.hdr_sum = u32(248), u32(252)
+        # flags bit 3: storage units are merged rectangles of blocks, listed
+        # in a box table after the unit records
+        self.merged = bool(self.flags & 8)
+        self.merge = u32(208) if self.merged else 1
+        self.mb = tuple(u32(212 + 4 * a) for a in range(3)) if self.merged else (1, 1, 1)
         self.u32, self.u64, self.f32 = u32, u64, f32
 
-    def extent(self, b):
+    def box(self, b):
+        """First block and one past the last block of unit b (z, y, x)."""
+        if self.merged:
+            e = struct.unpack_from("<8I", self.s, 256 + 16 * self.nblocks * self.nL + 16 * self.nblocks + 32 * b)
+            assert e[6] == 0 and e[7] == 0
+            return e[:3], e[3:6]
         nby, nbx = self.nb[1], self.nb[2]
         bi = (b // (nby * nbx), (b // nbx) % nby, b % nbx)
-        lo = [self.B * bi[a] for a in range(3)]
-        hi = [min(lo[a] + self.B, self.dims[a] - 1) for a in range(3)]
+        return bi, tuple(v + 1 for v in bi)
+
+    def extent(self, b):
+        b0, b1 = self.box(b)
+        lo = [self.B * b0[a] for a in range(3)]
+        hi = [min(self.B * b1[a], self.dims[a] - 1) for a in range(3)]
         return lo, hi
 
     def points(self, b, l):
@@ -188,13 +202,17 @@ class Stream:
 
 
 CASES = [
-    # (field, shape, levels, block, relative bound, isovalues, qmax, far bound factor)
+    # (field, shape, levels, block, relative bound, isovalues, qmax, far bound factor[, merge])
     ("normal", (19, 23, 21), 3, 8, 3e-2, 3, 32767, 0),
     ("normal", (9, 12, 17), 2, 4, 0.0, 1, 32767, 0),        # lossless: every point exact
     ("normal", (17, 9, 13), 3, 8, 2e-3, 2, 4, 0),           # most points outliers
     ("grf", (40, 40, 40), 2, 32, 1e-3, 2, 32767, 0),        # sections of 8 tiles
     ("smooth", (24, 24, 24), 4, 16, 1e-3, 2, 32767, 10),    # differentiated bounds
     ("normal", (1, 5, 70), 2, 8, 1e-2, 1, 32767, 0),        # one plane
+    ("normal", (19, 23, 21), 3, 8, 3e-2, 3, 32767, 0, 2),   # merged units of up to 2 blocks per axis
+    ("smooth", (40, 40, 40), 3, 8, 1e-3, 2, 32767, 0, 3),   # merged, mixed signatures
+    ("grf", (40, 40, 40), 2, 8, 1e-3, 0, 32767, 0, 4),      # merged, no candidates: one signature
+    ("normal", (1, 5, 70), 2, 8, 1e-2, 1, 32767, 0, 3),     # merged along x only
 ]
 
 
@@ -208,14 +226,22 @@ def _field(kind, shape, seed=3):
     raise KeyError(kind)
 
 
-@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}-{'x'.join(map(str, c[1]))}-L{c[2]}-B{c[3]}")
+def _signature(f, lo, hi, u):
+    blk = f[lo[0]: hi[0] + 1, lo[1]: hi[1] + 1, lo[2]: hi[2] + 1]
+    return tuple(bool(blk.min() < k <= blk.max()) for k in u)
+
+
+@pytest.mark.parametrize("case", CASES,
+                         ids=lambda c: f"{c[0]}-{'x'.join(map(str, c[1]))}-L{c[2]}-B{c[3]}" + (
+                             f"-M{c[8]}" if len(c) > 8 else ""))
 def test_independent_reader_recovers_the_oracle(case):
-    kind, shape, nL, B, rel, nk, qmax, far = case
+    kind, shape, nL, B, rel, nk, qmax, far = case[:8]
+    merge = case[8] if len(case) > 8 else 0
     f = _field(kind, shape)
     e = inputs.abs_error_bound(rel, f)
     isos = list(np.quantile(f, np.linspace(0.25, 0.75, nk)).astype(np.float32))
     isos = isos + isos[:1]                        # a duplicate, dropped in the header
-    r = oracle.compress(f, e, isos, levels=nL, block=B, qmax=qmax, error_bound_far=far * e)
+    r = oracle.compress(f, e, isos, levels=nL, block=B, qmax=qmax, error_bound_far=far * e, merge=merge)
     S = Stream(r["stream"])
 
     # header
@@ -225,8 +251,32 @@ def test_independent_reader_recovers_the_oracle(case):
     assert S.K == len(u) and S.iso[: S.K] == u and not any(S.iso[S.K:])
     assert S.e == e and S.vmin == f.min() and S.vmax == f.max()
     nb = tuple(max(1, -(-(n - 1) // B)) for n in f.shape)
-    assert S.nb == nb and S.nblocks == nb[0] * nb[1] * nb[2]
-    assert S.payload == 256 + 16 * S.nblocks * nL + 16 * S.nblocks
+    assert S.nb == nb
+    assert S.merged == (merge > 1)
+    if S.merged:
+        # the units tile the block grid, each a rectangle of at most `merge`
+        # blocks per axis whose blocks share one index signature
+        owner = np.full(nb, -1)
+        for b in range(S.nblocks):
+            b0, b1 = S.box(b)
+            assert all(0 <= b0[a] < b1[a] <= nb[a] and b1[a] - b0[a] <= S.mb[a] <= merge for a in range(3))
+            assert (owner[b0[0]: b1[0], b0[1]: b1[1], b0[2]: b1[2]] == -1).all()
+            owner[b0[0]: b1[0], b0[1]: b1[1], b0[2]: b1[2]] = b
+            sigs = set()
+            for z in range(b0[0], b1[0]):
+                for y in range(b0[1], b1[1]):
+                    for x in range(b0[2], b1[2]):
+                        lo = [B * z, B * y, B * x]
+                        hi = [min(lo[a] + B, f.shape[a] - 1) for a in range(3)]
+                        sigs.add(_signature(f, lo, hi, sorted(set(float(k) for k in isos))))
+            assert len(sigs) == 1, b
+        assert (owner >= 0).all()
+        assert S.merge == merge
+        assert S.mb == tuple(max(S.box(b)[1][a] - S.box(b)[0][a] for b in range(S.nblocks)) for a in range(3))
+        assert S.payload == 256 + 16 * S.nblocks * nL + 16 * S.nblocks + 32 * S.nblocks
+    else:
+        assert S.nblocks == nb[0] * nb[1] * nb[2]
+        assert S.payload == 256 + 16 * S.nblocks * nL + 16 * S.nblocks
     assert S.flags & 1 == (e == 0)
     assert (S.flags >> 1) & 1 == (far > 0)
     if far:
