@@ -72,6 +72,21 @@ typedef struct chr_params {
    * meshes of the candidate isovalues equal those of a stream compressed
    * with error_bound everywhere. */
   double error_bound_far;
+  /* Block merging before compression (Sec. II.A, third step of CHR
+   * generation: blocks merged into larger rectangular grids so that they are
+   * compressed and visualized more efficiently).  0 or 1: none.  2..16: the
+   * most blocks per axis of a merged unit.  A block's index signature is
+   * the set of candidate isovalues its input crosses (min < k <= max over
+   * its closed extent); blocks of equal signature are merged greedily in
+   * lexicographic block order into rectangular units (grown along x, then y,
+   * then z), each stored as one closed extent, so faces between merged
+   * blocks are stored once.  Codes and reconstruction equal the unmerged
+   * stream's; the block table then holds one record per unit and a box table
+   * lists the units.  A unit's closed extent must hold fewer than 2^31
+   * points; not combined with error_bound_far, batches or tier containers
+   * (CHR_E_INVAL).  chr_compress with merging waits once for its stream
+   * (the units are laid out on the host from the blocks' signatures). */
+  int merge;
 } chr_params;
 
 /* Device-side result of chr_compress (caller-allocated device memory). */
@@ -94,10 +109,13 @@ typedef struct chr_info {
   float vmin, vmax;
   int64_t nblocks;
   int nb[3];
-  uint32_t flags;        /* bit 0: lossless mode; bit 1: differentiated error control; bit 2: far quantizer lossless */
+  uint32_t flags;        /* bit 0: lossless mode; bit 1: differentiated error control; bit 2: far quantizer
+                            lossless; bit 3: merged units (nblocks then counts units) */
   uint64_t total_bytes, n_outlier, n_corrected, payload_offset;
   double error_bound_far;      /* flags bit 1: bound of points outside every active block (header bytes 192..199) */
   float inv_far, step_far;     /* its 1/(2e) and 2e (bytes 200..207) */
+  int merge;                   /* flags bit 3: most blocks per axis of a unit (bytes 208..211); else 1 */
+  int mb[3];                   /* largest unit extent in blocks along z, y, x (bytes 212..223); else 1 */
 } chr_info;
 
 const char *chr_last_error(void);

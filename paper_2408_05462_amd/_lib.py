@@ -42,7 +42,8 @@ class ChrError(RuntimeError):
 
 
 class chr_params(C.Structure):
-    _fields_ = [("levels", C.c_int), ("block", C.c_int), ("qmax", C.c_int), ("error_bound_far", C.c_double)]
+    _fields_ = [("levels", C.c_int), ("block", C.c_int), ("qmax", C.c_int), ("error_bound_far", C.c_double),
+                ("merge", C.c_int)]
 
 
 class chr_result(C.Structure):
@@ -57,7 +58,7 @@ class chr_info(C.Structure):
                 ("nblocks", C.c_int64), ("nb", C.c_int * 3), ("flags", C.c_uint32),
                 ("total_bytes", C.c_uint64), ("n_outlier", C.c_uint64), ("n_corrected", C.c_uint64),
                 ("payload_offset", C.c_uint64), ("error_bound_far", C.c_double), ("inv_far", C.c_float),
-                ("step_far", C.c_float)]
+                ("step_far", C.c_float), ("merge", C.c_int), ("mb", C.c_int * 3)]
 
 
 class chr_batch_item(C.Structure):

@@ -31,9 +31,11 @@ def _need_cuda_f32(t, name):
         raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
 
 
-def params(levels=3, block=64, qmax=32767, error_bound_far=0.0):
-    """error_bound_far > 0: differentiated error control (include/chr.h)."""
-    return L.chr_params(levels, block, qmax, float(error_bound_far))
+def params(levels=3, block=64, qmax=32767, error_bound_far=0.0, merge=0):
+    """error_bound_far > 0: differentiated error control; merge > 1: block
+    merging before compression, at most `merge` blocks per axis of a unit
+    (include/chr.h)."""
+    return L.chr_params(levels, block, qmax, float(error_bound_far), int(merge))
 
 
 # ------------------------------------------------------------------ compress
@@ -78,9 +80,9 @@ class Compressed:
 
 
 def compress(field, error_bound, isovalues=(), levels=3, block=64, qmax=32767, codes=None, flags=None,
-             error_bound_far=0.0):
+             error_bound_far=0.0, merge=0):
     """Synchronous compression; raises ChrError on any device-side status."""
-    p = params(levels, block, qmax, error_bound_far)
+    p = params(levels, block, qmax, error_bound_far, merge)
     dev = field.device
     cap = chr_compress_bound(field.shape, p)
     out = torch.empty(cap, dtype=torch.uint8, device=dev)

@@ -73,6 +73,15 @@ bool params_ok(const int64_t dims[3], const chr_params *p, std::string &why) {
   int64_t e[3];
   for (int a = 0; a < 3; a++) e[a] = std::min<int64_t>(p->block, dims[a] - 1) + 1;
   if ((double)e[0] * (double)e[1] * (double)e[2] >= 2147483647.0) { why = "block too large for this field"; return false; }
+  if (p->merge < 0 || p->merge > 16) { why = "merge must be in [0, 16]"; return false; }
+  if (p->merge > 1) {
+    for (int a = 0; a < 3; a++) e[a] = std::min<int64_t>((int64_t)p->merge * p->block, dims[a] - 1) + 1;
+    if ((double)e[0] * (double)e[1] * (double)e[2] >= 2147483647.0) {
+      why = "merged units too large for this field";
+      return false;
+    }
+    if (p->error_bound_far != 0) { why = "merging is not combined with differentiated error control"; return false; }
+  }
   return true;
 }
 
@@ -119,6 +128,12 @@ void set_quant_far(Geo &g, double e2) {
   g.lossless2 = t.lossless;
 }
 
+// Merging parameter of a geometry (0 and 1: none).
+void set_merge(Geo &g, int merge) {
+  g.merge = merge > 1 ? merge : 1;
+  for (int a = 0; a < 3; a++) g.mb[a] = g.merge;
+}
+
 // max chunks of a level-l section (the first block is the largest)
 uint32_t max_chunks(const Geo &g, int l) {
   int64_t o[3], hi[3];
@@ -129,7 +144,7 @@ uint32_t max_chunks(const Geo &g, int l) {
 
 struct EncLayout {
   size_t off_G, off_cnt, off_P, off_scan, off_pay, off_emask, off_exv, off_part, off_bst, off_csum, off_secsz, off_secoff,
-      off_scan64, off_act, total, part_records;
+      off_scan64, off_act, off_units, off_ubase, total, part_records;
 };
 
 EncLayout enc_layout(EncPlan &P) {
@@ -142,6 +157,15 @@ EncLayout enc_layout(EncPlan &P) {
     base += g.nblocks * (int64_t)P.maxch[l];
   }
   P.nslots = base;
+  if (g.merge > 1) {
+    // merged units: no more points than their blocks, at most one partial
+    // chunk per unit and level beyond them; workgroups per unit sized for
+    // the largest possible unit (merge blocks per axis)
+    P.nslots += g.nblocks * g.nL;
+    int64_t o[3], hi[3];
+    largest_ext(g, o, hi);
+    for (int l = L; l >= 0; l--) P.maxch[l] = (uint32_t)((sec_geom(o, hi, l, L).npts + 63) / 64);
+  }
   int64_t goff = 0;
   for (int l = 0; l < kMaxLevels; l++) {
     for (int a = 0; a < 3; a++) P.gd[l][a] = (l <= L) ? lvl_dim(g.n[a], l) : 0;
@@ -189,8 +213,14 @@ EncLayout enc_layout(EncPlan &P) {
   Lo.off_secsz = o; o = align256(o + sizeof(uint64_t) * (size_t)nsec);
   Lo.off_secoff = o; o = align256(o + sizeof(uint64_t) * (size_t)(nsec + 1));
   Lo.off_scan64 = o; o = align256(o + sizeof(uint64_t) * (size_t)scan_tmp_elems(nsec));
-  // activity flags, then 16 partial (min, max) key pairs per block
+  // activity flags (or index signatures), then 16 partial (min, max) key
+  // pairs per block
   Lo.off_act = o; o = align256(o + sizeof(uint32_t) * (size_t)g.nblocks * (1 + 2 * kActSplit));
+  if (g.merge > 1) {
+    // merged units: their boxes and first slots
+    Lo.off_units = o; o = align256(o + sizeof(uint32_t) * 8 * (size_t)g.nblocks);
+    Lo.off_ubase = o; o = align256(o + sizeof(int64_t) * (size_t)nsec);
+  }
   Lo.total = o;
   return Lo;
 }
@@ -265,6 +295,7 @@ size_t enc_workspace_bytes(const int64_t dims[3], const chr_params *p) {
   std::memset(&P, 0, sizeof(P));
   P.cpw0 = 4;
   fill_geo(P.g, dims, p->levels, p->block, p->qmax);
+  set_merge(P.g, p->merge);
   return enc_layout(P).total;
 }
 
@@ -287,8 +318,9 @@ int enc_geometry(const int64_t dims[3], double error_bound, const float *h_iso, 
 
 int enc_prepare(const float *d_field, const int64_t dims[3], double error_bound, const float *h_iso, int n_iso,
                 const chr_params *p, void *d_stream, size_t capacity, chr_result *d_result, int32_t *d_codes,
-                uint8_t *d_flags, void *d_ws, size_t ws_bytes, int cpw0, EncJob &J) {
+                uint8_t *d_flags, void *d_ws, size_t ws_bytes, int cpw0, EncJob &J, bool merging) {
   if (!d_field || !d_stream || !d_result || !d_ws) return fail(CHR_E_INVAL, "NULL device pointer");
+  if (p && p->merge > 1 && !merging) return fail(CHR_E_INVAL, "block merging is available through chr_compress only");
   if (reinterpret_cast<uintptr_t>(d_stream) & 7) return fail(CHR_E_INVAL, "stream buffer must be 8-byte aligned");
   EncPlan &P = J.P;
   std::memset(&P, 0, sizeof(P));
@@ -297,6 +329,8 @@ int enc_prepare(const float *d_field, const int64_t dims[3], double error_bound,
   if (rc) return rc;
   P.cpw0 = cpw0;
   make_l0geo(P.g, P.l0);
+  set_merge(P.g, p->merge);
+  if (P.g.merge > 1) P.l0.small = 0;   // units of varying shapes: the general kernels
   P.codes = d_codes;
   P.flags = d_flags;
   P.tile0 = (g_tune.tile0 && encode_tile0_ok(P)) ? 1 : 0;
@@ -326,6 +360,95 @@ int enc_prepare(const float *d_field, const int64_t dims[3], double error_bound,
   P.act = reinterpret_cast<uint32_t *>(ws + Lo.off_act);
   J.scan = reinterpret_cast<U4 *>(ws + Lo.off_scan);
   J.scan64 = reinterpret_cast<uint64_t *>(ws + Lo.off_scan64);
+  if (P.g.merge > 1) {
+    J.units = reinterpret_cast<uint32_t *>(ws + Lo.off_units);
+    J.ubase = reinterpret_cast<int64_t *>(ws + Lo.off_ubase);
+  }
+  return CHR_OK;
+}
+
+// Block merging before compression: the blocks' index signatures computed
+// on the device, the units laid out here (greedy, lexicographic block order:
+// a unit grows along x while the next block is free and has its signature,
+// then along y by whole rows, then along z by whole planes, up to `merge`
+// blocks per axis), and the plan switched from blocks to units.  Waits for
+// the stream once.
+int enc_merge_units(EncJob &J, hipStream_t s) {
+  EncPlan &P = J.P;
+  const Geo gb = P.g;
+  const int64_t nb0 = gb.nb[0], nb1 = gb.nb[1], nb2 = gb.nb[2], nblk = gb.nblocks;
+  const int M = gb.merge, L = gb.nL - 1;
+  launch_block_signatures(P, s);
+  std::vector<uint32_t> sig((size_t)nblk);
+  if (hipMemcpyAsync(sig.data(), P.act, sizeof(uint32_t) * (size_t)nblk, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(CHR_E_HIP, "block signatures: copy to the host failed");
+  std::vector<int32_t> unit((size_t)nblk, -1);
+  std::vector<uint32_t> box;
+  auto at = [&](int64_t z, int64_t y, int64_t x) { return (size_t)((z * nb1 + y) * nb2 + x); };
+  auto free_same = [&](int64_t z, int64_t y, int64_t x, uint32_t g) { return unit[at(z, y, x)] < 0 && sig[at(z, y, x)] == g; };
+  for (int64_t z = 0; z < nb0; z++)
+    for (int64_t y = 0; y < nb1; y++)
+      for (int64_t x = 0; x < nb2; x++) {
+        if (unit[at(z, y, x)] >= 0) continue;
+        const uint32_t g = sig[at(z, y, x)];
+        int64_t wx = 1, wy = 1, wz = 1;
+        while (wx < M && x + wx < nb2 && free_same(z, y, x + wx, g)) wx++;
+        for (bool grow = true; grow && wy < M && y + wy < nb1;) {
+          for (int64_t i = 0; i < wx && grow; i++) grow = free_same(z, y + wy, x + i, g);
+          if (grow) wy++;
+        }
+        for (bool grow = true; grow && wz < M && z + wz < nb0;) {
+          for (int64_t j = 0; j < wy && grow; j++)
+            for (int64_t i = 0; i < wx && grow; i++) grow = free_same(z + wz, y + j, x + i, g);
+          if (grow) wz++;
+        }
+        const int32_t id = (int32_t)(box.size() / 8);
+        for (int64_t k = 0; k < wz; k++)
+          for (int64_t j = 0; j < wy; j++)
+            for (int64_t i = 0; i < wx; i++) unit[at(z + k, y + j, x + i)] = id;
+        const uint32_t e[8] = {(uint32_t)z, (uint32_t)y, (uint32_t)x, (uint32_t)(z + wz), (uint32_t)(y + wy),
+                               (uint32_t)(x + wx), 0u, 0u};
+        box.insert(box.end(), e, e + 8);
+      }
+  const int64_t U = (int64_t)(box.size() / 8);
+  // slots of every (unit, level) in order, the largest unit
+  std::vector<int64_t> ubase((size_t)(U * gb.nL));
+  uint32_t maxch[kMaxLevels] = {};
+  int mb[3] = {1, 1, 1};
+  int64_t base = 0;
+  for (int64_t u = 0; u < U; u++) {
+    int64_t o[3], hi[3];
+    for (int a = 0; a < 3; a++) {
+      o[a] = (int64_t)box[8 * u + a] * gb.B;
+      hi[a] = std::min<int64_t>((int64_t)box[8 * u + 3 + a] * gb.B, gb.n[a] - 1);
+      mb[a] = std::max<int>(mb[a], (int)(box[8 * u + 3 + a] - box[8 * u + a]));
+    }
+    for (int l = L; l >= 0; l--) {
+      const uint32_t nch = (uint32_t)((sec_geom(o, hi, l, L).npts + 63) / 64);
+      ubase[(size_t)(u * gb.nL + (L - l))] = base;
+      base += nch;
+      maxch[l] = std::max(maxch[l], nch);
+    }
+  }
+  if (hipMemcpyAsync(J.units, box.data(), sizeof(uint32_t) * box.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(J.ubase, ubase.data(), sizeof(int64_t) * ubase.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(CHR_E_HIP, "merged units: copy to the device failed");
+  // the plan over units (every size here is within the workspace layout's
+  // bounds for merged units)
+  P.g.units = J.units;
+  P.g.nblocks = U;
+  for (int a = 0; a < 3; a++) P.g.mb[a] = mb[a];
+  P.ubase = J.ubase;
+  P.nslots = base;
+  for (int l = 0; l < kMaxLevels; l++) P.maxch[l] = l <= L ? maxch[l] : 0;
+  P.part_l1 = encode_fine_groups(P);
+  P.part_l2 = P.part_l1 + encode_l1_groups(P);
+  P.part_per_block = P.part_l2 + encode_l2_groups(P) + 1;
+  encode_pack_layout(P);
+  P.payload_off = kHeaderBytes + (uint64_t)U * (16 * (uint64_t)gb.nL + 16 + 32);
+  if (P.cap < P.payload_off) return fail(CHR_E_CAPACITY, "capacity below the header and tables");
   return CHR_OK;
 }
 
@@ -355,6 +478,12 @@ int dec_prepare(const Geo &g, uint64_t payload_off, int level, const void *d_str
   if (ws_bytes < need || (need && !d_ws)) return fail(CHR_E_NOMEM, "workspace too small: need " + std::to_string(need));
   D.g = g;
   make_l0geo(D.g, D.l0);
+  if (g.merge > 1) {
+    // merged units: their boxes from the stream's box table, general kernels
+    D.g.units = reinterpret_cast<const uint32_t *>(static_cast<const uint8_t *>(d_stream) + payload_off -
+                                                  32 * (uint64_t)g.nblocks);
+    D.l0.small = 0;
+  }
   D.cpw0 = cpw0;
   D.tile0 = g_tune.tile0;
   D.lo = level;
@@ -439,10 +568,21 @@ int mc_prepare(const float *d_field, const int64_t dims[3], float isovalue, floa
 
 // Geometry of a stream from its parsed header, checked for consistency.
 int info_geo(const chr_info *I, Geo &g) {
-  chr_params p{I->levels, I->block, I->qmax};
+  const bool merged = (I->flags & 8u) != 0;
+  chr_params p{I->levels, I->block, I->qmax, 0.0, merged ? I->merge : 0};
   std::string why;
   if (!params_ok(I->dims, &p, why)) return fail(CHR_E_CORRUPT, why);
   fill_geo(g, I->dims, I->levels, I->block, I->qmax);
+  if (merged) {
+    // storage units: the merged units (their boxes are read on the device)
+    if (I->merge < 2 || I->nblocks < 1 || I->nblocks > g.nblocks) return fail(CHR_E_CORRUPT, "bad merged units");
+    set_merge(g, I->merge);
+    g.nblocks = I->nblocks;
+    for (int a = 0; a < 3; a++) {
+      if (I->mb[a] < 1 || I->mb[a] > I->merge) return fail(CHR_E_CORRUPT, "bad largest unit");
+      g.mb[a] = I->mb[a];
+    }
+  }
   set_quant(g, I->error_bound);
   if (std::memcmp(&g.inv, &I->inv, 4) || std::memcmp(&g.step, &I->step, 4))
     return fail(CHR_E_CORRUPT, "quantizer constants do not match the error bound");
@@ -531,6 +671,8 @@ size_t chr_compress_bound(const int64_t dims[3], const chr_params *p) {
   fill_geo(g, dims, p->levels, p->block, p->qmax);
   const int L = g.nL - 1;
   size_t total = kHeaderBytes + 16 * (size_t)g.nblocks * g.nL + 16 * (size_t)g.nblocks;
+  // merged units: no larger than their blocks' sections, plus a box entry each
+  if (p->merge > 1) total += 32 * (size_t)g.nblocks;
   AxisClass ac[3];
   for (int a = 0; a < 3; a++) ac[a] = axis_classes(dims[a], p->block);
   for (int iz = 0; iz < ac[0].n; iz++)
@@ -554,8 +696,12 @@ int chr_compress(const float *d_field, const int64_t dims[3], double error_bound
                  int32_t *d_codes, uint8_t *d_flags, void *d_ws, size_t ws_bytes, void *stream) {
   EncJob J;
   int rc = enc_prepare(d_field, dims, error_bound, h_isovalues, n_iso, p, d_stream, capacity, d_result, d_codes,
-                       d_flags, d_ws, ws_bytes, g_tune.enc_cpw0, J);
+                       d_flags, d_ws, ws_bytes, g_tune.enc_cpw0, J, true);
   if (rc) return rc;
+  if (J.P.g.merge > 1) {
+    rc = enc_merge_units(J, static_cast<hipStream_t>(stream));
+    if (rc) return rc;
+  }
   launch_encode(J.P, 0, J.scan, J.scan64, static_cast<hipStream_t>(stream));
   return check_hip("chr_compress launch");
 }
@@ -588,20 +734,53 @@ int chr_stream_info(const void *h_stream, size_t n, chr_info *I) {
   I->error_bound_far = rd<double>(s + 192);
   I->inv_far = rd<float>(s + 200);
   I->step_far = rd<float>(s + 204);
-  chr_params p{I->levels, I->block, I->qmax, 0.0};
+  const bool merged = (I->flags & 8u) != 0;
+  I->merge = merged ? rd<int32_t>(s + 208) : 1;
+  for (int a = 0; a < 3; a++) I->mb[a] = merged ? rd<int32_t>(s + 212 + 4 * a) : 1;
+  if (I->flags & ~15u) return fail(CHR_E_CORRUPT, "unknown flags");
+  if (merged && (I->flags & 2u)) return fail(CHR_E_CORRUPT, "merged units with differentiated bounds");
+  chr_params p{I->levels, I->block, I->qmax, 0.0, merged ? I->merge : 0};
   std::string why;
   if (!params_ok(I->dims, &p, why)) return fail(CHR_E_CORRUPT, "header parameters invalid: " + why);
+  if (merged && I->merge < 2) return fail(CHR_E_CORRUPT, "bad merge");
   if (I->n_iso < 0 || I->n_iso > kMaxIso) return fail(CHR_E_CORRUPT, "bad isovalue count");
   Geo g;
   fill_geo(g, I->dims, I->levels, I->block, I->qmax);
-  if (g.nblocks != I->nblocks || g.nb[0] != I->nb[0] || g.nb[1] != I->nb[1] || g.nb[2] != I->nb[2])
-    return fail(CHR_E_CORRUPT, "block grid mismatch");
-  if (I->payload_offset != kHeaderBytes + 16 * (uint64_t)I->nblocks * I->levels + 16 * (uint64_t)I->nblocks)
+  if (g.nb[0] != I->nb[0] || g.nb[1] != I->nb[1] || g.nb[2] != I->nb[2]) return fail(CHR_E_CORRUPT, "block grid mismatch");
+  if (merged ? (I->nblocks < 1 || I->nblocks > g.nblocks) : g.nblocks != I->nblocks)
+    return fail(CHR_E_CORRUPT, "unit count mismatch");
+  for (int a = 0; a < 3; a++)
+    if (I->mb[a] < 1 || I->mb[a] > I->merge) return fail(CHR_E_CORRUPT, "bad largest unit");
+  if (I->payload_offset != kHeaderBytes + 16 * (uint64_t)I->nblocks * I->levels + 16 * (uint64_t)I->nblocks +
+                               (merged ? 32 * (uint64_t)I->nblocks : 0))
     return fail(CHR_E_CORRUPT, "payload offset mismatch");
   if (I->payload_offset > I->total_bytes) return fail(CHR_E_CORRUPT, "total size below the tables");
-  if (n >= I->payload_offset &&
-      host_checksum(s + kHeaderBytes, I->payload_offset - kHeaderBytes) != rd<uint32_t>(s + 248))
-    return fail(CHR_E_CORRUPT, "table checksum mismatch");
+  if (n >= I->payload_offset) {
+    if (host_checksum(s + kHeaderBytes, I->payload_offset - kHeaderBytes) != rd<uint32_t>(s + 248))
+      return fail(CHR_E_CORRUPT, "table checksum mismatch");
+    if (merged) {
+      // the units tile the block grid, none wider than the largest stated
+      std::vector<uint8_t> seen((size_t)g.nblocks, 0);
+      const uint8_t *xt = s + I->payload_offset - 32 * (size_t)I->nblocks;
+      for (int64_t u = 0; u < I->nblocks; u++) {
+        uint32_t e[8];
+        std::memcpy(e, xt + 32 * (size_t)u, 32);
+        if (e[6] || e[7]) return fail(CHR_E_CORRUPT, "bad box entry");
+        for (int a = 0; a < 3; a++)
+          if (e[a] >= e[3 + a] || e[3 + a] > (uint32_t)g.nb[a] || e[3 + a] - e[a] > (uint32_t)I->mb[a])
+            return fail(CHR_E_CORRUPT, "bad box entry");
+        for (uint32_t z = e[0]; z < e[3]; z++)
+          for (uint32_t y = e[1]; y < e[4]; y++)
+            for (uint32_t x = e[2]; x < e[5]; x++) {
+              uint8_t &f = seen[(size_t)(((int64_t)z * g.nb[1] + y) * g.nb[2] + x)];
+              if (f) return fail(CHR_E_CORRUPT, "overlapping units");
+              f = 1;
+            }
+      }
+      for (uint8_t f : seen)
+        if (!f) return fail(CHR_E_CORRUPT, "units leave a block out");
+    }
+  }
   return CHR_OK;
 }
 
@@ -768,7 +947,16 @@ int chr_block_box(const void *h_head, size_t head_bytes, float kmin, float kmax,
     const float mn = rd<float>(s + btab + 16 * (size_t)b), mx = rd<float>(s + btab + 16 * (size_t)b + 4);
     if (!(mn < mx && mn < kmax && kmin <= mx)) continue;
     int64_t o[3], h[3];
-    block_ext(g, b, o, h);
+    if (g.merge > 1) {
+      uint32_t e[8];
+      std::memcpy(e, s + I.payload_offset - 32 * (size_t)I.nblocks + 32 * (size_t)b, 32);
+      for (int a = 0; a < 3; a++) {
+        o[a] = (int64_t)e[a] * g.B;
+        h[a] = std::min<int64_t>((int64_t)e[3 + a] * g.B, g.n[a] - 1);
+      }
+    } else {
+      block_ext(g, b, o, h);
+    }
     for (int a = 0; a < 3; a++) {
       blo[a] = std::min(blo[a], o[a]);
       bhi[a] = std::max(bhi[a], h[a]);

@@ -24,6 +24,8 @@ struct EncJob {
   EncPlan P;
   U4 *scan;
   uint64_t *scan64;
+  uint32_t *units;   // merged units: box table and first slots (workspace)
+  int64_t *ubase;
 };
 
 struct DecJob {
@@ -36,9 +38,13 @@ struct McJob {
 };
 
 size_t enc_workspace_bytes(const int64_t dims[3], const chr_params *p);
+// merging: whether the caller runs enc_merge_units (block merging, p->merge > 1)
 int enc_prepare(const float *d_field, const int64_t dims[3], double error_bound, const float *h_iso, int n_iso,
                 const chr_params *p, void *d_stream, size_t capacity, chr_result *d_result, int32_t *d_codes,
-                uint8_t *d_flags, void *d_ws, size_t ws_bytes, int cpw0, EncJob &J);
+                uint8_t *d_flags, void *d_ws, size_t ws_bytes, int cpw0, EncJob &J, bool merging = false);
+// Block merging before compression: units from the blocks' signatures
+// (waits for stream s once); the plan then covers units.
+int enc_merge_units(EncJob &J, hipStream_t s);
 
 // Reconstruction plan from the compression geometry (quantizer constants and
 // isovalues already set), for streams whose header is not on the host.

@@ -5,13 +5,21 @@
 //     0 u32 magic "CHR1"   4 u32 version=1   8 i64 nz  16 i64 ny  24 i64 nx
 //     32 i32 levels  36 i32 block  40 i32 qmax  44 i32 n_iso  48 f64 e
 //     56 f32 1/(2e)  60 f32 2e  64 f32 iso[16]  128 f32 vmin  132 f32 vmax
-//     136 i64 nblocks  144 i32 nbz,nby,nbx  156 u32 flags (bit0 lossless)
-//     160 u64 total bytes  168 u64 #outliers  176 u64 #corrections
-//     184 u64 payload offset  248 u32 table checksum  252 u32 header checksum
-//   section table at 256: per block (bz,by,bx lexicographic), per level from
-//     the coarsest: {u64 offset, u64 bytes}
-//   block table: per block {f32 min, f32 max, u32 checksum, u32 0}
-//   payload: blocks in order, each the concatenation of its sections.
+//     136 i64 nblocks (storage units)  144 i32 nbz,nby,nbx (block grid)
+//     156 u32 flags (bit0 lossless, bit1 differentiated bounds, bit2 far
+//     bound lossless, bit3 merged units)  160 u64 total bytes
+//     168 u64 #outliers  176 u64 #corrections  184 u64 payload offset
+//     192 f64 far bound  200 f32 1/(2 e_far)  204 f32 2 e_far
+//     208 u32 merge (largest blocks per axis of a unit)  212 u32 largest unit
+//     extent in blocks along z, y, x  248 u32 table checksum
+//     252 u32 header checksum
+//   section table at 256: per unit (blocks bz,by,bx lexicographic, or the
+//     merged units in order), per level from the coarsest: {u64 offset,
+//     u64 bytes}
+//   block table: per unit {f32 min, f32 max, u32 checksum, u32 activity}
+//   box table (merged streams only): per unit {u32 first block z, y, x,
+//     u32 one past the last block z, y, x, u32 0, u32 0}
+//   payload: units in order, each the concatenation of its sections.
 //   section (the points of one level in one closed block, lexicographic z,y,x):
 //     u32 npts, u32 W, u32 NE, u32 NX
 //     tile table: per 64 chunks {u32 W, u32 NE, u32 NX before the tile}, pad 8
@@ -55,6 +63,14 @@ struct Geo {
   double e2;
   float inv2, step2;
   int lossless2, diff;
+  // block merging before compression: storage units are rectangles of
+  // blocks, units[8u .. 8u+5] = first block and one past the last block of
+  // unit u along z, y, x (device memory); nullptr: one unit per block, and
+  // nblocks counts blocks.  merge: largest blocks per axis of a unit (1
+  // without merging); mb: the largest unit extent in blocks.
+  const uint32_t *units;
+  int merge;
+  int mb[3];
 };
 
 // The quantizer constants of one point.
@@ -80,6 +96,37 @@ __host__ __device__ inline int64_t blocks_along(int64_t n, int64_t B) {
 }
 
 // Closed extent [o, hi] of block b (lexicographic bz, by, bx).
+__host__ __device__ inline void block_ext(const Geo &g, int64_t b, int64_t o[3], int64_t hi[3]);
+
+// Closed extent of storage unit b: block b, or merged unit b (its box read
+// from the unit table, clamped to the block grid so that a corrupt table
+// cannot reach outside the field).
+__device__ inline void unit_ext(const Geo &g, int64_t b, int64_t o[3], int64_t hi[3]) {
+  if (!g.units) {
+    block_ext(g, b, o, hi);
+    return;
+  }
+  const uint32_t *e = g.units + 8 * b;
+  for (int a = 0; a < 3; a++) {
+    int64_t b1 = (int64_t)e[3 + a];
+    b1 = b1 < 1 ? 1 : (b1 > g.nb[a] ? g.nb[a] : b1);
+    const int64_t b0 = (int64_t)e[a] < b1 - 1 ? (int64_t)e[a] : b1 - 1;
+    const int64_t h = b1 * (int64_t)g.B;
+    o[a] = b0 * g.B;
+    hi[a] = h < g.n[a] - 1 ? h : g.n[a] - 1;
+  }
+}
+
+// The extent of the largest storage unit (its origin at 0): block 0, or a
+// unit of mb blocks per axis.  Host code sizes launches with it.
+__host__ __device__ inline void largest_ext(const Geo &g, int64_t o[3], int64_t hi[3]) {
+  for (int a = 0; a < 3; a++) {
+    const int64_t e = (int64_t)(g.merge > 1 ? g.mb[a] : 1) * g.B;
+    o[a] = 0;
+    hi[a] = e < g.n[a] - 1 ? e : g.n[a] - 1;
+  }
+}
+
 __host__ __device__ inline void block_ext(const Geo &g, int64_t b, int64_t o[3], int64_t hi[3]) {
   int64_t bi[3];
   bi[2] = b % g.nb[2];

@@ -19,7 +19,8 @@ struct Part {
 
 // Compression: per-level chunk slots hold one 64-point chunk each before the
 // stream is assembled (width/exact counts, packed codes, exact mask, exact
-// values); slots of level l for block b start at slot_base[l] + b*maxch[l].
+// values); slots of level l for block b start at slot_base[l] + b*maxch[l],
+// or, for merged units (their sizes differ), at ubase[b*nL + nL-1-l].
 // Workgroups per block of the block-activity pass (differentiated error
 // control); the workspace holds 2 partial keys per block and workgroup.
 constexpr int kActSplit = 16;
@@ -59,7 +60,14 @@ struct EncPlan {
   int32_t *codes;
   uint8_t *flags;
   uint32_t *act;                 // per block: 1 = active (differentiated error control only)
+  const int64_t *ubase;          // merged units: first slot of every (unit, level), levels from the coarsest
 };
+
+// First chunk slot of level l of storage unit b.
+__device__ inline int64_t slot_of(const EncPlan &P, int l, int64_t b) {
+  if (P.ubase) return P.ubase[b * P.g.nL + (P.g.nL - 1 - l)];
+  return P.slot_base[l] + b * (int64_t)P.maxch[l];
+}
 
 // Reconstruction of levels L..lo.
 struct DecPlan {
@@ -113,6 +121,8 @@ struct McPlan {
 void prof_mark(const char *kernel, hipStream_t s, int end);
 
 // launchers (encode.hip, decode.hip, mc.hip)
+// Index signature of every block into p.act[0 .. nblocks) (block merging).
+void launch_block_signatures(const EncPlan &p, hipStream_t s);
 void launch_encode(const EncPlan &p, int64_t scan_tmp_elems_u4, U4 *scan_tmp, uint64_t *scan_tmp64,
                    hipStream_t s);
 int64_t encode_fine_groups(const EncPlan &p);   // level-0 workgroups per block

@@ -184,7 +184,7 @@ __global__ __launch_bounds__(kBS) void k_decode_coarse(DecPlan D) {
   const int wave = threadIdx.x / kWave;
   const int lmin = D.lo > 3 ? D.lo : 3;  // levels 2 and 1 have wide kernels of their own
   int64_t o[3], hi[3];
-  block_ext(g, b, o, hi);
+  unit_ext(g, b, o, hi);
   const NearSel ns = g.diff ? dec_near(D, b, o, hi) : NearSel{};
   for (int l = L; l >= lmin; l--) {
     float *dst = D.gp[l];
@@ -227,7 +227,7 @@ __global__ __launch_bounds__(kBS) void k_decode_fine(DecPlan D) {
   if (!block_needed(D, b)) return;
   const uint32_t t = blockIdx.x * kWaves + threadIdx.x / kWave;
   int64_t o[3], hi[3];
-  block_ext(g, b, o, hi);
+  unit_ext(g, b, o, hi);
   const Sec s = sec_geom(o, hi, 0, L);
   const uint32_t nch = (s.npts + 63) / 64;
   if (t >= (nch + 63) / 64) return;
@@ -237,9 +237,9 @@ __global__ __launch_bounds__(kBS) void k_decode_fine(DecPlan D) {
     return;
   }
   const int64_t n1 = g.n[1], n2 = g.n[2];
-  const int64_t ez = (o[0] + g.B < g.n[0] - 1) ? o[0] + g.B : g.n[0];  // first z not owned
-  const int64_t ey = (o[1] + g.B < g.n[1] - 1) ? o[1] + g.B : g.n[1];
-  const int64_t ex = (o[2] + g.B < g.n[2] - 1) ? o[2] + g.B : g.n[2];
+  const int64_t ez = (hi[0] < g.n[0] - 1) ? hi[0] : g.n[0];  // first z not owned
+  const int64_t ey = (hi[1] < g.n[1] - 1) ? hi[1] : g.n[1];
+  const int64_t ex = (hi[2] < g.n[2] - 1) ? hi[2] : g.n[2];
   const float *G1 = (L >= 1) ? D.gp[1] : nullptr;
   const int64_t *gd1 = D.gd[1];
   float *out = D.out;
@@ -274,8 +274,15 @@ __global__ __launch_bounds__(kBS) void k_decode_level(DecPlan D, int l) {
   xcd_remap(t, b);
   if (!block_needed(D, b)) return;
   const int wave = threadIdx.x / kWave;
-  const BlockPos bp = block_pos(g, D.l0, b);
-  const int64_t o[3] = {bp.o[0], bp.o[1], bp.o[2]}, hi[3] = {bp.hi[0], bp.hi[1], bp.hi[2]};
+  int64_t o[3], hi[3];
+  int cls = 0;
+  if (g.units) {
+    unit_ext(g, b, o, hi);
+  } else {
+    const BlockPos bp = block_pos(g, D.l0, b);
+    for (int a = 0; a < 3; a++) { o[a] = bp.o[a]; hi[a] = bp.hi[a]; }
+    cls = bp.cls;
+  }
   float *dst = D.gp[l];
   const int64_t *gd = D.gd[l];
   if (l < L) {
@@ -294,7 +301,7 @@ __global__ __launch_bounds__(kBS) void k_decode_level(DecPlan D, int l) {
       for (uint32_t u = lane_id(); u < c2; u += kWave) dst[drow + 2 * u] = src[srow + u];
     }
   }
-  const Sec s = (l == 1) ? D.l0.sec1[bp.cls] : sec_geom(o, hi, l, L);
+  const Sec s = (l == 1 && !g.units) ? D.l0.sec1[cls] : sec_geom(o, hi, l, L);
   const uint32_t nch = (s.npts + 63) / 64;
   if (t >= (nch + 63) / 64) return;
   const SecView v = open_section(D, b, l, s.npts);
@@ -987,7 +994,7 @@ __global__ __launch_bounds__(kBS) void k_decode_thin(DecPlan D) {
   const int64_t b = blockIdx.x;
   if (!block_needed(D, b)) return;
   int64_t o[3], hi[3];
-  block_ext(g, b, o, hi);
+  unit_ext(g, b, o, hi);
   if (hi[2] != o[2]) return;
   const int64_t cz = ((hi[0] - o[0]) >> 1) + 1, cy = ((hi[1] - o[1]) >> 1) + 1;
   for (int64_t i = threadIdx.x; i < cz * cy; i += kBS) {
@@ -1012,7 +1019,7 @@ __global__ __launch_bounds__(kBS) void k_prune_fill(DecPlan D) {
   block_range(D, b, mn, mx);
   const float c = (mn >= D.kmax || mn == mx) ? mn : mx;
   int64_t o[3], hi[3];
-  block_ext(g, b, o, hi);
+  unit_ext(g, b, o, hi);
   const int lo = D.lo;
   uint32_t lo3[3], hi3[3], dim[3];
   for (int a = 0; a < 3; a++) {
@@ -1036,7 +1043,7 @@ __global__ __launch_bounds__(kBS) void k_prune_fill(DecPlan D) {
 bool decode_tile0_used(const DecPlan &p) {
   const Geo &g = p.g;
   int64_t o[3], hi[3];
-  block_ext(g, 0, o, hi);
+  largest_ext(g, o, hi);
   const bool slab32 = 4.0 * (double)(hi[0] - o[0] + 1) * (double)g.n[1] * (double)g.n[2] < 4294967296.0;
   return p.lo == 0 && p.tile0 && g.B == 64 && g.nL >= 2 && slab32 && p.l0.small && !g.diff && !g.lossless;
 }
@@ -1045,7 +1052,7 @@ bool decode_tile0_used(const DecPlan &p) {
 static bool decode_tile1_used(const DecPlan &p) {
   const Geo &g = p.g;
   int64_t o[3], hi[3];
-  block_ext(g, 0, o, hi);
+  largest_ext(g, o, hi);
   const bool slab32 = 4.0 * (double)(hi[0] - o[0] + 1) * (double)g.n[1] * (double)g.n[2] < 4294967296.0;
   return p.lo <= 1 && p.tile0 && g.B == 64 && g.nL >= 3 && slab32 && p.l0.small && !g.diff && !g.lossless;
 }
@@ -1054,7 +1061,7 @@ void launch_decode(const DecPlan &p, hipStream_t s) {
   const Geo &g = p.g;
   const int L = g.nL - 1;
   int64_t o[3], hi[3];
-  block_ext(g, 0, o, hi);  // the first block is the largest
+  largest_ext(g, o, hi);
   if (p.prune) k_prune_fill<<<dim3(8, (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
   if (L >= 3 && p.lo <= L) {
     prof_mark("k_decode_coarse", s, 0);

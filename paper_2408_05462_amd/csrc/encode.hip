@@ -175,7 +175,7 @@ __device__ void enc_chunk(const EncPlan &P, int l, int64_t b, const int64_t o[3]
   const uint32_t orv = wave_or_dpp(zz);
   const int wb = orv ? 32 - __clz((int)orv) : 0;
   const unsigned long long em = __ballot(E);
-  const int64_t slot = P.slot_base[l] + b * (int64_t)P.maxch[l] + c;
+  const int64_t slot = slot_of(P, l, b) + c;
 
   // pack the codes at bit lane*wb through LDS
   if (lane < 32) pack[lane] = 0u;
@@ -198,14 +198,17 @@ __device__ void enc_chunk(const EncPlan &P, int l, int64_t b, const int64_t o[3]
   __builtin_amdgcn_wave_barrier();
 }
 
+// Zero counts for a slot past the section (the uniform layout's padding;
+// merged units have no padding slots).
 __device__ inline void zero_slot(const EncPlan &P, int l, int64_t b, uint32_t c) {
-  if (lane_id() == 0) P.cnt[P.slot_base[l] + b * (int64_t)P.maxch[l] + c] = U4{0, 0, 0, 0};
+  if (P.ubase) return;
+  if (lane_id() == 0) P.cnt[slot_of(P, l, b) + c] = U4{0, 0, 0, 0};
 }
 
-// First coordinate past the points block b owns along each axis: the upper
-// face belongs to the next block unless it is the domain's last plane.
-__device__ inline void owned_end(const Geo &g, const int64_t o[3], int64_t own[3]) {
-  for (int a = 0; a < 3; a++) own[a] = (o[a] + g.B < g.n[a] - 1) ? o[a] + g.B : g.n[a];
+// First coordinate past the points a unit owns along each axis: the upper
+// face belongs to the next unit unless it is the domain's last plane.
+__device__ inline void owned_end(const Geo &g, const int64_t hi[3], int64_t own[3]) {
+  for (int a = 0; a < 3; a++) own[a] = (hi[a] < g.n[a] - 1) ? hi[a] : g.n[a];
 }
 
 // Levels nL-1 .. 2 of one block per workgroup.
@@ -217,8 +220,8 @@ __global__ __launch_bounds__(kBS) void k_encode_coarse(EncPlan P, int lmin) {
   const int64_t b = blockIdx.x;
   const int wave = threadIdx.x / kWave;
   int64_t o[3], hi[3], own[3];
-  block_ext(g, b, o, hi);
-  owned_end(g, o, own);
+  unit_ext(g, b, o, hi);
+  owned_end(g, hi, own);
   const NearSel ns = g.diff ? near_sel(g, P.act, 1u, b, o, hi) : NearSel{};
   Part acc;
   part_init(acc);
@@ -251,8 +254,8 @@ __global__ __launch_bounds__(kBS) void k_encode_l1(EncPlan P) {
   const int64_t b = by;
   const int wave = threadIdx.x / kWave;
   int64_t o[3], hi[3], own[3];
-  block_ext(g, b, o, hi);
-  owned_end(g, o, own);
+  unit_ext(g, b, o, hi);
+  owned_end(g, hi, own);
   const NearSel ns = g.diff ? near_sel(g, P.act, 1u, b, o, hi) : NearSel{};
   if (L >= 2) {
     copy_coarse(P.G + P.g_off[2], P.gd[2], P.G + P.g_off[1], P.gd[1], o, hi, 2, bx * kWaves + wave,
@@ -280,8 +283,8 @@ __global__ __launch_bounds__(kBS) void k_encode_fine(EncPlan P) {
   const int64_t b = blockIdx.y;
   const int wave = threadIdx.x / kWave;
   int64_t o[3], hi[3], own[3];
-  block_ext(g, b, o, hi);
-  owned_end(g, o, own);
+  unit_ext(g, b, o, hi);
+  owned_end(g, hi, own);
   const NearSel ns = g.diff ? near_sel(g, P.act, 1u, b, o, hi) : NearSel{};
   const Sec s = sec_geom(o, hi, 0, L);
   const uint32_t nch = (s.npts + 63) / 64;
@@ -1264,6 +1267,25 @@ __global__ __launch_bounds__(kBS) void k_block_active_final(EncPlan P) {
   P.act[b] = a;
 }
 
+// Block merging before compression: the index signature of every block, bit
+// j set when the input on its closed extent crosses candidate j
+// (min < k_j <= max), from k_block_minmax's partial keys.
+__global__ __launch_bounds__(kBS) void k_block_sig(EncPlan P) {
+  const Geo &g = P.g;
+  const int64_t b = (int64_t)blockIdx.x * kBS + threadIdx.x;
+  if (b >= g.nblocks) return;
+  uint32_t mn = 0xffffffffu, mx = 0u;
+  for (int s2 = 0; s2 < kActSplit; s2++) {
+    const uint32_t *part = P.act + g.nblocks + 2 * (b * kActSplit + s2);
+    mn = min(mn, part[0]);
+    mx = max(mx, part[1]);
+  }
+  const float vmn = of_ord(mn), vmx = of_ord(mx);
+  uint32_t sig = 0;
+  for (int j = 0; j < g.K; j++) sig |= (vmn < g.iso[j] && g.iso[j] <= vmx) ? 1u << j : 0u;
+  P.act[b] = sig;
+}
+
 // Byte size of every section from the scanned chunk sizes.
 __global__ __launch_bounds__(kBS) void k_sections(EncPlan P) {
   const Geo &g = P.g;
@@ -1274,10 +1296,10 @@ __global__ __launch_bounds__(kBS) void k_sections(EncPlan P) {
   const int64_t b = sec / g.nL;
   const int l = L - (int)(sec % g.nL);
   int64_t o[3], hi[3];
-  block_ext(g, b, o, hi);
+  unit_ext(g, b, o, hi);
   const Sec s = sec_geom(o, hi, l, L);
   const uint32_t nch = (s.npts + 63) / 64;
-  const int64_t s0 = P.slot_base[l] + b * (int64_t)P.maxch[l];
+  const int64_t s0 = slot_of(P, l, b);
   const U4 a = P.P[s0], e = P.P[s0 + nch];
   P.secsz[sec] = sec_bytes(s.npts, e.x - a.x, e.y - a.y, e.z - a.z);
 }
@@ -1296,6 +1318,14 @@ __device__ inline void put64(const EncPlan &P, uint64_t off, uint64_t v) {
   }
 }
 
+// Box table of a merged stream: the unit table, after the block table.
+__global__ __launch_bounds__(kBS) void k_box_table(EncPlan P) {
+  const Geo &g = P.g;
+  const int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x;
+  if (i >= 8 * g.nblocks) return;
+  put32(P, P.payload_off - 32 * (uint64_t)g.nblocks + 4 * (uint64_t)i, g.units[i]);
+}
+
 // Section table entries, section headers and padding bytes.
 __global__ __launch_bounds__(kBS) void k_sec_table(EncPlan P) {
   const Geo &g = P.g;
@@ -1306,10 +1336,10 @@ __global__ __launch_bounds__(kBS) void k_sec_table(EncPlan P) {
   const int64_t b = sec / g.nL;
   const int l = L - (int)(sec % g.nL);
   int64_t o[3], hi[3];
-  block_ext(g, b, o, hi);
+  unit_ext(g, b, o, hi);
   const Sec s = sec_geom(o, hi, l, L);
   const uint32_t nch = (s.npts + 63) / 64, ntile = (nch + 63) / 64;
-  const int64_t s0 = P.slot_base[l] + b * (int64_t)P.maxch[l];
+  const int64_t s0 = slot_of(P, l, b);
   const U4 a = P.P[s0], e = P.P[s0 + nch];
   const uint32_t W = e.x - a.x, NE = e.y - a.y, NX = e.z - a.z;
   const uint64_t so = P.payload_off + P.secoff[sec];
@@ -1354,13 +1384,13 @@ __global__ __launch_bounds__(kBS) void k_pack(EncPlan P) {
   const int64_t b = rel / P.pack_gpb[l];
   const uint32_t tile = (uint32_t)(rel - b * P.pack_gpb[l]);
   Sec s;
-  if (l == 0) {
+  if (l == 0 && !g.units) {
     s = P.l0.sec[block_pos(g, P.l0, (uint32_t)b).cls];
-  } else if (l == 1) {
+  } else if (l == 1 && !g.units) {
     s = P.l0.sec1[block_pos(g, P.l0, (uint32_t)b).cls];
   } else {
     int64_t o[3], hi[3];
-    block_ext(g, b, o, hi);
+    unit_ext(g, b, o, hi);
     s = sec_geom(o, hi, l, L);
   }
   const uint32_t nch = (s.npts + 63) / 64;
@@ -1369,7 +1399,7 @@ __global__ __launch_bounds__(kBS) void k_pack(EncPlan P) {
   const int64_t sec = b * g.nL + (L - l);
   const uint64_t so = P.payload_off + P.secoff[sec];
   if (so + P.secsz[sec] > P.cap) return;
-  const int64_t s0 = P.slot_base[l] + b * (int64_t)P.maxch[l];
+  const int64_t s0 = slot_of(P, l, b);
   const U4 a = P.P[s0], e = P.P[s0 + nch];
   const uint32_t W = e.x - a.x, NE = e.y - a.y;
   const uint64_t A = 16 + pad8(12 * (uint64_t)ntile), Poff = A + pad8(nch);
@@ -1593,7 +1623,8 @@ __device__ void header_words(const EncPlan &P, uint64_t total, bool fits, uint32
     h[132 / 4] = __float_as_uint(vmax);
     h64(136, (uint64_t)g.nblocks);
     for (int a = 0; a < 3; a++) h[(144 + 4 * a) / 4] = (uint32_t)g.nb[a];
-    h[156 / 4] = (g.lossless ? 1u : 0u) | (g.diff ? 2u : 0u) | (g.diff && g.lossless2 ? 4u : 0u);
+    h[156 / 4] = (g.lossless ? 1u : 0u) | (g.diff ? 2u : 0u) | (g.diff && g.lossless2 ? 4u : 0u) |
+                 (g.units ? 8u : 0u);
     h64(160, total);
     h64(168, redc[0][0]);
     h64(176, redc[0][1]);
@@ -1604,6 +1635,10 @@ __device__ void header_words(const EncPlan &P, uint64_t total, bool fits, uint32
       h64(192, e2);
       h[200 / 4] = __float_as_uint(g.inv2);
       h[204 / 4] = __float_as_uint(g.step2);
+    }
+    if (g.units) {
+      h[208 / 4] = (uint32_t)g.merge;
+      for (int a = 0; a < 3; a++) h[(212 + 4 * a) / 4] = (uint32_t)g.mb[a];
     }
     h[248 / 4] = sum;
     uint32_t hs = 0;
@@ -1638,7 +1673,7 @@ int64_t encode_l2_groups(const EncPlan &p) {
 // A block's slab of planes spans < 4 GiB (the specialized kernels' 32-bit offsets).
 static bool slab32(const Geo &g) {
   int64_t o[3], hi[3];
-  block_ext(g, 0, o, hi);
+  largest_ext(g, o, hi);
   return 4.0 * (double)(hi[0] - o[0] + 1) * (double)g.n[1] * (double)g.n[2] < 4294967296.0;
 }
 
@@ -1722,6 +1757,15 @@ void launch_encode_levels(const EncPlan &p, hipStream_t s) {
   }
 }
 
+// Index signatures of the blocks (block merging before compression): the
+// input's min and max per closed block extent, then one signature word per
+// block in p.act[0 .. nblocks).
+void launch_block_signatures(const EncPlan &p, hipStream_t s) {
+  const Geo &g = p.g;
+  k_block_minmax<<<dim3((unsigned)kActSplit, (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
+  k_block_sig<<<dim3((unsigned)ceil_div(g.nblocks, kBS)), dim3(kBS), 0, s>>>(p);
+}
+
 void launch_encode(const EncPlan &p, int64_t, U4 *scan_tmp, uint64_t *scan_tmp64, hipStream_t s) {
   const Geo &g = p.g;
   const int64_t nsec = g.nblocks * g.nL;
@@ -1756,6 +1800,7 @@ void launch_encode(const EncPlan &p, int64_t, U4 *scan_tmp, uint64_t *scan_tmp64
   prof_mark("k_block_table", s, 0);
   k_block_sum<<<dim3((unsigned)(g.nblocks * kSumSegs)), dim3(kBS), 0, s>>>(p);
   k_block_table<<<dim3((unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
+  if (g.units) k_box_table<<<dim3((unsigned)ceil_div(8 * g.nblocks, kBS)), dim3(kBS), 0, s>>>(p);
   k_table_sum<<<dim3((unsigned)kSumSegs), dim3(kBS), 0, s>>>(p);
   prof_mark("k_block_table", s, 1);
   prof_mark("k_header", s, 0);

@@ -416,3 +416,56 @@ def test_block_box_matches_oracle_on_the_host():
         api.chr_block_box(head, 1.0, 0.5)
     with pytest.raises(L.ChrError):
         api.chr_block_box(head[:300], 0.5, 0.5)
+
+
+def test_merged_stream_info_bound_and_rejections():
+    """Merged streams (block merging before compression) from the oracle:
+    the library's header parser reads the units and checks their tiling; the
+    bound and the argument checks of merging."""
+    import struct
+
+    f = np.random.default_rng(8).standard_normal((21, 19, 23)).astype(np.float32)
+    r = oracle.compress(f, 0.05, [], levels=2, block=4, merge=3)
+    s = bytes(r["stream"])
+    info = api.chr_stream_info(s)
+    oinfo = oracle.stream_info(r["stream"])
+    assert info.flags == 8 and info.merge == 3 and tuple(info.mb) == tuple(oinfo.mb)
+    assert info.nblocks == oinfo.nblocks < 6 * 5 * 6
+    assert info.payload_offset == oinfo.payload_offset
+    assert api.chr_stream_verify(s) == L.CHR_OK
+    # a box entry moved onto another unit: caught once the tables' checksum
+    # is made consistent again
+    t = bytearray(s)
+    xt = info.payload_offset - 32 * info.nblocks
+    t[xt + 32: xt + 44] = t[xt: xt + 12]
+    words = np.frombuffer(bytes(t[256: info.payload_offset]), "<u4").astype(np.uint64)
+    j = (np.arange(len(words), dtype=np.uint64) * np.uint64(0x9E3779B9)) & np.uint64(0xFFFFFFFF)
+    h = words ^ j
+    for sh, mul in ((16, 0x85EBCA6B), (13, 0xC2B2AE35)):
+        h = ((h ^ (h >> np.uint64(sh))) * np.uint64(mul)) & np.uint64(0xFFFFFFFF)
+    h ^= h >> np.uint64(16)
+    t[248:252] = struct.pack("<I", int(h.sum() & np.uint64(0xFFFFFFFF)))
+    hw = np.frombuffer(bytes(t[:252]), "<u4").astype(np.uint64)
+    j = (np.arange(63, dtype=np.uint64) * np.uint64(0x9E3779B9)) & np.uint64(0xFFFFFFFF)
+    h = hw ^ j
+    for sh, mul in ((16, 0x85EBCA6B), (13, 0xC2B2AE35)):
+        h = ((h ^ (h >> np.uint64(sh))) * np.uint64(mul)) & np.uint64(0xFFFFFFFF)
+    h ^= h >> np.uint64(16)
+    t[252:256] = struct.pack("<I", int(h.sum() & np.uint64(0xFFFFFFFF)))
+    with pytest.raises(L.ChrError):
+        api.chr_stream_info(bytes(t))
+    api.chr_stream_info(bytes(t[:256]))     # the header alone does not hold the units
+    # bound: the plain bound plus a box entry per block
+    shape = (65, 70, 129)
+    nb = 2 * 3 * 4
+    assert (api.chr_compress_bound(shape, api.params(3, 32, merge=2))
+            == api.chr_compress_bound(shape, api.params(3, 32)) + 32 * nb
+            == oracle.compress_bound(shape, 3, 32) + 32 * nb)
+    for dims, bad in (((40, 40, 40), api.params(3, 8, merge=17)), ((40, 40, 40), api.params(3, 8, merge=-1)),
+                      ((40, 40, 40), api.params(3, 8, error_bound_far=1.0, merge=2)),
+                      ((2049, 2049, 2049), api.params(1, 1024, merge=2))):   # units of 2049^3 points
+        with pytest.raises(L.ChrError):
+            api.chr_compress_bound(dims, bad)
+    api.chr_compress_bound((2049, 2049, 2049), api.params(1, 1024))
+    assert api.chr_compress_workspace((64, 64, 64), api.params(3, 16, merge=2)) > \
+        api.chr_compress_workspace((64, 64, 64), api.params(3, 16))
