@@ -64,6 +64,7 @@ def parse_args():
     ap.add_argument("--no-entropy", action="store_true", help="skip the entropy stage of the default run")
     ap.add_argument("--no-diff", action="store_true", help="skip differentiated error control in the default run")
     ap.add_argument("--no-tiers", action="store_true", help="skip the multi-tier container in the default run")
+    ap.add_argument("--no-merge", action="store_true", help="skip block merging before compression in the default run")
     ap.add_argument("--serve-requests", type=int, default=200, help="requests of the default run's served part")
     ap.add_argument("--batch-items", type=int, default=64, help="batch64: number of timesteps")
     ap.add_argument("--branches", type=int, default=0, help="batch64: parallel branches of the graph (default: 4)")
@@ -765,6 +766,51 @@ def run_field(args):
         tiers = {"container_bytes": tsize, "compress_ms": round(comp_ms, 4), "tiers": per}
         del tout, tws, trec, rws2
 
+    # block merging before compression: blocks of equal index signature
+    # merged into units of at most M blocks per axis; the stream shrinks by
+    # the faces stored once, codes and reconstruction stay those of the plain
+    # stream.  The merged compress waits once on the host (the units are laid
+    # out there), so it is timed by the wall clock around synchronised calls.
+    mrg = None
+    if not args.no_merge:
+        mrg = []
+        for M in (2, 4):
+            pm = api.params(w["levels"], w["block"], merge=M)
+            mcap = api.chr_compress_bound(shape, pm)
+            mbuf = torch.empty(mcap, dtype=torch.uint8, device=dev)
+            mws = torch.empty(api.chr_compress_workspace(shape, pm), dtype=torch.uint8, device=dev)
+            api.chr_compress(x, e, isos, pm, mbuf, res, mws)
+            torch.cuda.synchronize()
+            rm = api.read_result(res)
+            assert rm["status"] == 0
+            mbytes = rm["stream_bytes"]
+            minfo, _ = api.chr_stream_info_dev(mbuf[:mbytes])
+            rep = 5
+            t0 = time.perf_counter()
+            for _ in range(rep):
+                api.chr_compress(x, e, isos, pm, mbuf, res, mws)
+            torch.cuda.synchronize()
+            comp_ms = (time.perf_counter() - t0) * 1e3 / rep
+            mrec = torch.empty(shape, dtype=torch.float32, device=dev)
+            mrws = torch.empty(max(api.chr_reconstruct_workspace(minfo, 0), 256), dtype=torch.uint8, device=dev)
+            api.chr_reconstruct(minfo, mbuf[:mbytes], 0, e, mrec, st, mrws)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(rep):
+                api.chr_reconstruct(minfo, mbuf[:mbytes], 0, e, mrec, st, mrws)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            same = int(st.item()) == 0 and bool(torch.equal(mrec.view(torch.int32), recon.view(torch.int32)))
+            assert same, "merged stream: reconstruction differs from the plain stream's"
+            mrg.append({"merge": M, "units": int(minfo.nblocks), "blocks": int(np.prod(list(minfo.nb))),
+                        "largest_unit_blocks": list(minfo.mb), "stream_bytes": mbytes,
+                        "compression_ratio": round(4.0 * N / mbytes, 3),
+                        "bytes_vs_plain": round(mbytes / nbytes, 4),
+                        "compress_ms_wall": round(comp_ms, 4),
+                        "reconstruct_ms": round(e0.elapsed_time(e1) / rep, 4),
+                        "reconstruction_equal_plain": same})
+            del mbuf, mws, mrec, mrws
+
     # block merging for extraction: the blocks that can hold the isosurface
     # merged into one box; marching cubes over the box vs over the field
     boxm = None
@@ -852,7 +898,7 @@ def run_field(args):
         "wall_s_timed": round(wall, 3), "parity": parity, "topology_error_bound": topo or None, "roofline": roofline,
         "cpu_baseline": cpu,
         "workflow_model": workflow_model(4.0 * N, cr, stage_ms), "entropy_stage": ent,
-        "differentiated_error_control": dif, "tiers": tiers, "merged_box_extraction": boxm,
+        "differentiated_error_control": dif, "tiers": tiers, "merged_box_extraction": boxm, "merged_compression": mrg,
     }
     return out
 
