@@ -569,6 +569,29 @@ struct T0Ctx {
   float rmin, rmax, xmin, xmax;
 };
 
+// The quantizer's constants as the tile kernels use them, read once per
+// workgroup into scalar registers (readfirstlane: kept in registers rather
+// than reloaded from the kernel arguments before every row, where each
+// reload's wait would also wait for the row's LDS reads).
+struct T0Quant {
+  float inv, step, ein, qmaxf;
+  double e;
+};
+
+__device__ __forceinline__ float sreg(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+
+__device__ __forceinline__ T0Quant t0_quant(const Geo &gq) {
+  T0Quant c;
+  c.inv = sreg(gq.inv);
+  c.step = sreg(gq.step);
+  c.ein = sreg(gq.ein);
+  c.qmaxf = sreg((float)gq.qmax);
+  const uint64_t eb = __double_as_longlong(gq.e);
+  c.e = __longlong_as_double((long long)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)eb)) |
+                                         ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(eb >> 32)) << 32)));
+  return c;
+}
+
 // Ordered key of a binary32 value (as ord_of), in two instructions.
 __device__ __forceinline__ uint32_t t0_ord(float f) {
   const uint32_t u = __float_as_uint(f);
@@ -583,8 +606,9 @@ __device__ __forceinline__ uint32_t t0_ord(float f) {
 // changes side of some candidate exactly when one candidate's comparison
 // differs between x and x', so the correction mask is an OR of ballot XORs.
 // LL: the lossless quantizer.
+// Candidates past K are +inf in `iso` (no finite value reaches them).
 template <int KB, bool LL, bool GW = false>
-__device__ __forceinline__ void t0_finish(const Geo &gq, const float (&iso)[KB], float x, float p, uint64_t cmask,
+__device__ __forceinline__ void t0_finish(const T0Quant &gq, const float (&iso)[KB], float x, float p, uint64_t cmask,
                                           uint32_t jr, uint32_t jl, T0Ctx &t, char *gl = nullptr,
                                           uint32_t go = 0u) {
   // the point's section index is jr + jl: jr the row's (wave-uniform), jl the lane's
@@ -599,7 +623,7 @@ __device__ __forceinline__ void t0_finish(const Geo &gq, const float (&iso)[KB],
     const float qf = rintf(__fmul_rn(__fsub_rn(x, p), gq.inv));
     xc = __fadd_rn(p, __fmul_rn(qf, gq.step));
     q = (int32_t)qf;
-    const uint64_t mq = __ballot(fabsf(qf) <= (float)gq.qmax);
+    const uint64_t mq = __ballot(fabsf(qf) <= gq.qmaxf);
     // the bound in binary32 first; the exact check in double only for a row
     // where some lane is not clearly inside
     uint64_t mb = __ballot(fabsf(__fsub_rn(xc, x)) <= gq.ein);
@@ -608,8 +632,7 @@ __device__ __forceinline__ void t0_finish(const Geo &gq, const float (&iso)[KB],
   }
   uint64_t mr = 0;
 #pragma unroll
-  for (int jj = 0; jj < KB; jj++)
-    if (jj < gq.K) mr |= __ballot(iso[jj] <= x) ^ __ballot(iso[jj] <= xc);
+  for (int jj = 0; jj < KB; jj++) mr |= __ballot(iso[jj] <= x) ^ __ballot(iso[jj] <= xc);
   const uint64_t mE = mO | mr;                 // outlier, or a correction (side change, not an outlier)
   const bool E = __builtin_amdgcn_inverse_ballot_w64(mE);
   const float xr = E ? x : xc;
@@ -756,7 +779,8 @@ __device__ __forceinline__ void encode_tile(const EncPlan &P) {
   }
   float iso[KB];
 #pragma unroll
-  for (int jj = 0; jj < KB; jj++) iso[jj] = gq.iso[jj];
+  for (int jj = 0; jj < KB; jj++) iso[jj] = sreg(jj < gq.K ? gq.iso[jj] : __builtin_inff());
+  const T0Quant tq = t0_quant(gq);
   // the block's slab of the field; the launcher guarantees it spans < 4 GiB
   const char *__restrict__ xbase = reinterpret_cast<const char *>(P.x + (size_t)bp.o[0] * n1 * n2);
   const char *__restrict__ sgb = reinterpret_cast<const char *>(sg);
@@ -832,7 +856,7 @@ __device__ __forceinline__ void encode_tile(const EncPlan &P) {
       const uint32_t jA = J0 + (vc >> 1) * RP;
       const uint64_t hm0 = (4 * a < my && 4 * a * S < owny) ? 0x00000000ffffffffull : 0ull;
       const uint64_t hm1 = (4 * a + 2 < my && (4 * a + 2) * S < owny) ? 0xffffffff00000000ull : 0ull;
-      t0_finish<KB, LL, GW>(gq, iso, xa[k], p, we * S < ownz ? lane_in & (hm0 | hm1) : 0ull, jA, iA, t, glb,
+      t0_finish<KB, LL, GW>(tq, iso, xa[k], p, we * S < ownz ? lane_in & (hm0 | hm1) : 0ull, jA, iA, t, glb,
                             vc * grow + (2 * iA + 1) * 4u);
     }
   }
@@ -848,13 +872,16 @@ __device__ __forceinline__ void encode_tile(const EncPlan &P) {
     if (f >= nB) break;
     const bool yu = f + 1 < gy;
     const uint32_t ga = f * kRow + lg;
-    const float A = t0_xavg(lds_at(sgb, ga), lds_at(sgb, ga + 4), xav);
-    const float B = t0_xavg(lds_at(sgb, ga + kRow), lds_at(sgb, ga + kRow + 4), xav);
+    // the row's parents read together, before any value is used
+    const float a0 = lds_at(sgb, ga), a1 = lds_at(sgb, ga + 4);
+    const float b0 = lds_at(sgb, ga + kRow), b1 = lds_at(sgb, ga + kRow + 4);
+    const float A = t0_xavg(a0, a1, xav);
+    const float B = t0_xavg(b0, b1, xav);
     float pb = avg2(A, B);
     hold(pb);
     const float p = yu ? pb : A;
     const uint32_t jr = J0 + f * RP + rowE;
-    t0_finish<KB, LL, GW>(gq, iso, xb[k], p, (we * S < ownz && (2 * f + 1) * S < owny) ? lane_in : 0ull, jr, u, t,
+    t0_finish<KB, LL, GW>(tq, iso, xb[k], p, (we * S < ownz && (2 * f + 1) * S < owny) ? lane_in : 0ull, jr, u, t,
                           glb, (2 * f + 1) * grow + u * 4u);
   }
   // ---- C and D rows: the odd plane's rows 2m (y even) and 2m + 1 (y odd)
@@ -866,18 +893,24 @@ __device__ __forceinline__ void encode_tile(const EncPlan &P) {
       const uint32_t m = wave + (uint32_t)k * kWaves;
       if (m >= nM) break;
       const uint32_t ga = m * kRow + lg;
-      const float A = t0_xavg(lds_at(sgb, ga), lds_at(sgb, ga + 4), xav);
-      const float Cc = t0_xavg(lds_at(sgb, ga + kPl), lds_at(sgb, ga + kPl + 4), xav);
+      // the parents of both rows read together, before any value is used
+      // (rows m + 1 past the plane read the staging's spare floats, unused)
+      const float a0 = lds_at(sgb, ga), a1 = lds_at(sgb, ga + 4);
+      const float c0 = lds_at(sgb, ga + kPl), c1 = lds_at(sgb, ga + kPl + 4);
+      const float b0 = lds_at(sgb, ga + kRow), b1 = lds_at(sgb, ga + kRow + 4);
+      const float d0 = lds_at(sgb, ga + kPl + kRow), d1 = lds_at(sgb, ga + kPl + kRow + 4);
+      const float A = t0_xavg(a0, a1, xav);
+      const float Cc = t0_xavg(c0, c1, xav);
       float pc = avg2(A, Cc);
       hold(pc);
       const float p = zu ? pc : A;
       const uint32_t jc = jo + 2 * m * mx;
-      t0_finish<KB, LL, GW>(gq, iso, xc[k], p, (zown && 2 * m * S < owny) ? lane_in : 0ull, jc, u, t, glb,
+      t0_finish<KB, LL, GW>(tq, iso, xc[k], p, (zown && 2 * m * S < owny) ? lane_in : 0ull, jc, u, t, glb,
                             gplane + 2 * m * grow + u * 4u);
       if (2 * m + 1 < my) {
         const bool yu = m + 1 < gy;
-        const float B = t0_xavg(lds_at(sgb, ga + kRow), lds_at(sgb, ga + kRow + 4), xav);
-        const float D = t0_xavg(lds_at(sgb, ga + kPl + kRow), lds_at(sgb, ga + kPl + kRow + 4), xav);
+        const float B = t0_xavg(b0, b1, xav);
+        const float D = t0_xavg(d0, d1, xav);
         float p0 = avg2(A, B), p1 = avg2(Cc, D);
         hold(p0);
         hold(p1);
@@ -886,7 +919,7 @@ __device__ __forceinline__ void encode_tile(const EncPlan &P) {
         float pd = avg2(p0, p1);
         hold(pd);
         const float p2 = zu ? pd : p0;
-        t0_finish<KB, LL, GW>(gq, iso, xd[k], p2, (zown && (2 * m + 1) * S < owny) ? lane_in : 0ull, jc + mx, u, t,
+        t0_finish<KB, LL, GW>(tq, iso, xd[k], p2, (zown && (2 * m + 1) * S < owny) ? lane_in : 0ull, jc + mx, u, t,
                               glb, gplane + (2 * m + 1) * grow + u * 4u);
       }
     }
@@ -901,7 +934,7 @@ __device__ __forceinline__ void encode_tile(const EncPlan &P) {
       const float x = ldf(xbase, ((w * n1 + bp.o[1] + v) * n2 + bp.o[2] + 64u) * 4u);
       const float p = t0_pred_any(sg, (w & 1u) && zu, v, 64u, gy, gx);
       const uint32_t j = ev ? J0 + (v >> 1) * RP + rowE + 64u : J0 + s.Pe + v * mx + 64u;
-      t0_finish<KB, LL>(gq, iso, x, p, __ballot(fr < nF && w < ownz && v < owny && 64u < ownx), 0u, j, t);
+      t0_finish<KB, LL>(tq, iso, x, p, __ballot(fr < nF && w < ownz && v < owny && 64u < ownx), 0u, j, t);
     }
   }
   // ---- the tail of the last chunk (the next planes' first points; more
@@ -915,7 +948,7 @@ __device__ __forceinline__ void encode_tile(const EncPlan &P) {
     const float x = ldf(xbase, ((w * S * n1 + bp.o[1] + v * S) * n2 + bp.o[2] + uu * S) * 4u);
     const float p = predict(P.G + P.g_off[LV + 1], h0, h1, h2, LV, bp.o[0] + w * S, bp.o[1] + v * S,
                             bp.o[2] + uu * S);
-    t0_finish<KB, LL>(gq, iso, x, p, 0ull, 0u, j, t);
+    t0_finish<KB, LL>(tq, iso, x, p, 0ull, 0u, j, t);
   }
   __syncthreads();
 
