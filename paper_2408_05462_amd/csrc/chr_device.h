@@ -468,6 +468,66 @@ __device__ inline BlockPos block_pos(const Geo &g, const L0Geo &G, uint32_t b) {
   return p;
 }
 
+// Levels L .. 2 of a 64-cell block (its points of the 4-grid, at most 17^3)
+// in one 1024-thread workgroup, compression and reconstruction alike: each
+// thread owns fixed 4-grid points, whose section indices follow in closed
+// form from their coordinates.
+constexpr int kTopSide = 17;                             // 4-grid points per axis of a 64-cell block
+constexpr int kTopPts = kTopSide * kTopSide * kTopSide;  // 4913
+constexpr int kTopCodes = kTopPts + 6 * 64;              // codes of every level (at most 5), each 64-aligned
+constexpr int kTopBS = 1024;                             // threads per block
+constexpr int kTopWaves = kTopBS / kWave;
+constexpr int kTopPer = (kTopPts + kTopBS - 1) / kTopBS; // 4-grid points per thread
+
+__device__ inline uint32_t top_idx(uint32_t z, uint32_t y, uint32_t x) { return (z * kTopSide + y) * kTopSide + x; }
+
+// The section sizes of level l of a block (as sec_geom, without divisors).
+struct SecDims {
+  uint32_t mx, my, mz, rowE, Pe, Po, npts;
+};
+__device__ inline SecDims sec_dims(const BlockPos &bp, int l, int L) {
+  SecDims d;
+  d.mz = ((bp.hi[0] - bp.o[0]) >> l) + 1;
+  d.my = ((bp.hi[1] - bp.o[1]) >> l) + 1;
+  d.mx = ((bp.hi[2] - bp.o[2]) >> l) + 1;
+  if (l == L) {
+    d.rowE = 0; d.Pe = 0; d.Po = d.mx * d.my;
+    d.npts = d.mx * d.my * d.mz;
+  } else {
+    const uint32_t cx = (d.mx + 1) / 2, cy = (d.my + 1) / 2, cz = (d.mz + 1) / 2;
+    d.rowE = d.mx - cx;
+    d.Pe = d.my * d.mx - cy * cx;
+    d.Po = d.my * d.mx;
+    d.npts = d.mz * d.my * d.mx - cz * cy * cx;
+  }
+  return d;
+}
+
+// Point i of a block's 4-grid (dims d0 x d1 x d2 <= 17^3) packed in one word:
+// x, y, z (clamped into the block) in bits 0-4, 5-9, 10-14, and from bit 15
+// the point's level + 1 (the fewest trailing zeros of its non-zero
+// coordinates, plus 2, at most L), 0 for no point.
+__device__ inline uint32_t top_point(uint32_t i, uint32_t d0, uint32_t d1, uint32_t d2, int L) {
+  const uint32_t z = i / (kTopSide * kTopSide), y = (i / kTopSide) % kTopSide, x = i % kTopSide;
+  const bool in = i < (uint32_t)kTopPts && z < d0 && y < d1 && x < d2;
+  int lv = L;
+  if (z) lv = min(lv, 2 + __builtin_ctz(z));
+  if (y) lv = min(lv, 2 + __builtin_ctz(y));
+  if (x) lv = min(lv, 2 + __builtin_ctz(x));
+  const uint32_t zc = min(z, d0 - 1), yc = min(y, d1 - 1), xc = min(x, d2 - 1);
+  return xc | (yc << 5) | (zc << 10) | (in ? (uint32_t)(lv + 1) << 15 : 0u);
+}
+
+// Section index of the level-l point (w, v, u) (level-l units): lexicographic
+// over the level's points (the anchors' level: every point).
+__device__ inline uint32_t sec_index(const SecDims &d, bool top, uint32_t w, uint32_t v, uint32_t u) {
+  if (top) return (w * d.my + v) * d.mx + u;
+  const uint32_t base = (w >> 1) * (d.Pe + d.Po);
+  if (w & 1u) return base + d.Pe + v * d.mx + u;
+  const uint32_t row = (v >> 1) * (d.rowE + d.mx);
+  return (v & 1u) ? base + row + d.rowE + u : base + row + (u >> 1);
+}
+
 // Workgroups are dispatched to the 8 XCDs round-robin by linear id.  This
 // maps linear id i of a 2D grid to logical work so that each XCD receives a
 // contiguous eighth of the work (its L2 then sees neighbouring data).

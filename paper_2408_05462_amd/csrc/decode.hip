@@ -987,6 +987,160 @@ __global__ __launch_bounds__(kBS) void k_decode_l1(DecPlan D) { decode_fast<1, D
 template <bool DIFF>
 __global__ __launch_bounds__(kBS) void k_decode_l2(DecPlan D) { decode_fast<2, DIFF>(D); }
 
+// Levels L .. 2 of a 64-cell block in one 1024-thread workgroup (the
+// reconstruction half of k_encode_top).  The chunk headers of the levels'
+// sections are read and checked (two waves per level, a tile each), every
+// code is unpacked into LDS, then the threads' fixed 4-grid points are
+// reconstructed level by level, coarsest first, predicting from the
+// reconstruction in LDS, and the block's 4-grid is written to the level-2
+// grid (every point of the closed extent; a neighbour writes the shared
+// faces with the same values).
+constexpr int kTopChunks = kTopCodes / 64;   // chunks of every level, each level 64-aligned
+
+__global__ __launch_bounds__(kTopBS) void k_decode_top(DecPlan D) {
+  __shared__ float R[kTopPts];
+  __shared__ uint16_t sc[kTopCodes];
+  __shared__ uint32_t cwb[kTopChunks], cwo[kTopChunks], cxo[kTopChunks];
+  __shared__ unsigned long long cem[kTopChunks];
+  __shared__ uint32_t base[kMaxLevels], npt[kMaxLevels];   // each level's first code and points
+  __shared__ uint64_t spay[kMaxLevels], sxv[kMaxLevels];   // its payload and exact values (stream offsets)
+  __shared__ uint32_t sbad;
+  const uint32_t b = blockIdx.x;
+  if (!block_needed(D, b)) return;
+  const Geo &g = D.g;
+  const int L = g.nL - 1;
+  const BlockPos bp = block_pos(g, D.l0, b);
+  const uint32_t wave = wave_index();
+  const int lane = lane_id();
+  const uint32_t d0 = ((bp.hi[0] - bp.o[0]) >> 2) + 1, d1 = ((bp.hi[1] - bp.o[1]) >> 2) + 1;
+  const uint32_t d2 = ((bp.hi[2] - bp.o[2]) >> 2) + 1;
+  uint32_t pc[kTopPer];
+#pragma unroll
+  for (int k = 0; k < kTopPer; k++) pc[k] = top_point(threadIdx.x + (uint32_t)k * kTopBS, d0, d1, d2, L);
+  if (threadIdx.x == 0) {
+    uint32_t off = 0;
+    for (int l = L; l >= 2; l--) {
+      const uint32_t n = sec_dims(bp, l, L).npts;
+      base[l] = off;
+      npt[l] = n;
+      off += (n + 63) & ~63u;
+    }
+    sbad = 0u;
+  }
+  __syncthreads();
+  // ---- chunk headers: wave 2 (L - l) + t reads tile t of level l's section
+  {
+    const int l = L - (int)(wave >> 1);
+    const uint32_t t = wave & 1u;
+    if (l >= 2) {
+      const uint32_t nch = (npt[l] + 63) / 64;
+      if (t * 64 < nch) {
+        const SecView v = open_section(D, b, l, npt[l]);
+        bool bad = !v.ok;
+        if (v.ok) {
+          if (t == 0 && lane == 0) {
+            spay[l] = (uint64_t)(v.p - D.s) + v.Poff;
+            sxv[l] = (uint64_t)(v.p - D.s) + v.Xoff;
+          }
+          const uint32_t c = t * 64 + (uint32_t)lane;
+          const uint8_t *tt = v.p + 16 + 12 * (uint64_t)t;
+          const uint32_t tw = ld32(tt), te = ld32(tt + 4), tx = ld32(tt + 8);
+          const uint32_t hb = c < v.nch ? v.p[v.A + c] : 0u;
+          const uint32_t w = hb & 31u, he = hb >> 7;
+          const uint32_t wo = tw + wave_excl_sum(w), eo = te + wave_excl_sum(he);
+          const bool badl = (w > (uint32_t)kMaxW) || (hb & 0x60u) || (wo + w > v.W) || (he && eo >= v.NE);
+          const unsigned long long em = (he && !badl) ? ld64(v.p + v.Moff + 8 * (uint64_t)eo) : 0ull;
+          const uint32_t pcnt = (uint32_t)__popcll(em);
+          const uint32_t xo = tx + wave_excl_sum(pcnt);
+          bad = __ballot(badl || xo + pcnt > v.NX) != 0ull;
+          if (c < nch) {
+            const uint32_t gi = base[l] / 64 + c;
+            cwb[gi] = w;
+            cwo[gi] = wo;
+            cxo[gi] = xo;
+            cem[gi] = em;
+          }
+        }
+        if (bad && lane == 0) sbad = 1u;
+      }
+    }
+  }
+  __syncthreads();
+  if (sbad) {
+    if (threadIdx.x == 0) set_status(D, -4);
+    return;
+  }
+  // ---- every code into LDS: wave w unpacks chunks w, w + 16, ... (its
+  // level found from the levels' first chunks)
+  {
+    const uint32_t nct = base[2] / 64 + (npt[2] + 63) / 64;
+    for (uint32_t gi = wave; gi < nct; gi += kTopWaves) {
+      int l = L;
+      while (l > 2 && gi >= base[l - 1] / 64) l--;
+      const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane(cwb[gi]);
+      const uint32_t wo = (uint32_t)__builtin_amdgcn_readfirstlane(cwo[gi]);
+      uint32_t zz = 0u;
+      if (w) {
+        const char *__restrict__ pay = reinterpret_cast<const char *>(D.s + spay[l]);
+        const uint32_t bit = mul24s((uint32_t)lane, w), wi = bit >> 5;
+        const uint32_t lo = ldu(pay, 8u * wo + 4u * wi), hi = ldu(pay, 8u * wo + 4u * min(wi + 1, 2 * w - 1));
+        zz = __builtin_amdgcn_ubfe(__builtin_amdgcn_alignbit(hi, lo, bit), 0u, w);
+      }
+      sc[gi * 64 + (uint32_t)lane] = (uint16_t)zz;
+    }
+  }
+  __syncthreads();
+  // ---- the levels, coarsest first
+  const float step = g.step;
+  const bool lossless = g.lossless != 0;
+  for (int l = L; l >= 2; l--) {
+    const SecDims sd = sec_dims(bp, l, L);
+    const uint32_t sh = (uint32_t)(l - 2), st = 1u << sh;     // the level's step on the 4-grid
+    const uint32_t bl = base[l];
+#pragma unroll
+    for (int k = 0; k < kTopPer; k++) {
+      if ((pc[k] >> 15) != (uint32_t)(l + 1)) continue;
+      const uint32_t x = pc[k] & 31u, y = (pc[k] >> 5) & 31u, z = (pc[k] >> 10) & 31u;
+      const uint32_t w = z >> sh, v = y >> sh, u = x >> sh;
+      const uint32_t j = bl + sec_index(sd, l == L, w, v, u);
+      const unsigned long long em = cem[j >> 6];
+      float r;
+      if ((em >> (j & 63u)) & 1ull) {
+        const uint32_t xi = cxo[j >> 6] + (uint32_t)__popcll(em & ((1ull << (j & 63u)) - 1ull));
+        r = __uint_as_float(ld32(D.s + sxv[l] + 4 * (uint64_t)xi));
+      } else {
+        float p = 0.0f;
+        if (l < L) {
+          // parents at -st and +st along the odd axes, the lower alone where
+          // the upper is outside the domain
+          const uint32_t oz = w & 1u, oy = v & 1u, ox = u & 1u;
+          const uint32_t zl = z - oz * st, yl = y - oy * st, xl = x - ox * st;
+          const bool zu = oz && z + st < d0, yu = oy && y + st < d1, xu = ox && x + st < d2;
+          const uint32_t zb = zu ? z + st : zl, yb = yu ? y + st : yl, xb = xu ? x + st : xl;
+          p = midpoint8(R[top_idx(zl, yl, xl)], R[top_idx(zl, yl, xb)], R[top_idx(zl, yb, xl)], R[top_idx(zl, yb, xb)],
+                        R[top_idx(zb, yl, xl)], R[top_idx(zb, yl, xb)], R[top_idx(zb, yb, xl)], R[top_idx(zb, yb, xb)],
+                        zu, yu, xu);
+        }
+        const uint32_t zc = sc[j];
+        const int32_t q = (int32_t)(zc >> 1) ^ -(int32_t)(zc & 1u);
+        r = lossless ? p : __fadd_rn(p, __fmul_rn((float)q, step));
+      }
+      R[top_idx(z, y, x)] = r;
+    }
+    __syncthreads();
+  }
+  // ---- the reconstructed 4-grid into the level-2 grid
+  const uint32_t e1 = (uint32_t)D.gd[2][1], e2 = (uint32_t)D.gd[2][2];
+  char *__restrict__ gb = reinterpret_cast<char *>(D.gp[2] + (((size_t)(bp.o[0] >> 2)) * e1 + (bp.o[1] >> 2)) * e2 +
+                                                   (bp.o[2] >> 2));
+#pragma unroll
+  for (int k = 0; k < kTopPer; k++)
+    if (pc[k] >> 15) {
+      const uint32_t x = pc[k] & 31u, y = (pc[k] >> 5) & 31u, z = (pc[k] >> 10) & 31u;
+      stf(gb, ((z * e1 + y) * e2 + x) * 4u, R[top_idx(z, y, x)]);
+    }
+}
+
 // Even points of even rows in blocks one point wide along x (no level-0
 // point in those rows writes them).
 __global__ __launch_bounds__(kBS) void k_decode_thin(DecPlan D) {
@@ -1048,6 +1202,16 @@ bool decode_tile0_used(const DecPlan &p) {
   return p.lo == 0 && p.tile0 && g.B == 64 && g.nL >= 2 && slab32 && p.l0.small && !g.diff && !g.lossless;
 }
 
+// Levels L .. 2 of 64-cell blocks in one workgroup per block (the output
+// level 2 or finer).
+static bool decode_top_used(const DecPlan &p) {
+  const Geo &g = p.g;
+  int64_t o[3], hi[3];
+  largest_ext(g, o, hi);
+  const bool slab32 = 4.0 * (double)(hi[0] - o[0] + 1) * (double)g.n[1] * (double)g.n[2] < 4294967296.0;
+  return p.lo <= 2 && p.tile0 && g.B == 64 && g.nL >= 3 && slab32 && p.l0.small && !g.diff && !g.lossless;
+}
+
 // Level 1 likewise (as the output or on the way to level 0), below level 2.
 static bool decode_tile1_used(const DecPlan &p) {
   const Geo &g = p.g;
@@ -1063,7 +1227,12 @@ void launch_decode(const DecPlan &p, hipStream_t s) {
   int64_t o[3], hi[3];
   largest_ext(g, o, hi);
   if (p.prune) k_prune_fill<<<dim3(8, (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
-  if (L >= 3 && p.lo <= L) {
+  const bool top = decode_top_used(p);
+  if (top) {
+    prof_mark("k_decode_coarse", s, 0);
+    k_decode_top<<<dim3((unsigned)g.nblocks), dim3(kTopBS), 0, s>>>(p);
+    prof_mark("k_decode_coarse", s, 1);
+  } else if (L >= 3 && p.lo <= L) {
     prof_mark("k_decode_coarse", s, 0);
     k_decode_coarse<<<dim3((unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
     prof_mark("k_decode_coarse", s, 1);
@@ -1071,6 +1240,7 @@ void launch_decode(const DecPlan &p, hipStream_t s) {
   // the specialized kernels address a block's slab with 32-bit offsets
   const bool slab32 = 4.0 * (double)(hi[0] - o[0] + 1) * (double)g.n[1] * (double)g.n[2] < 4294967296.0;
   for (int l = 2; l >= 1; l--) {
+    if (l == 2 && top) continue;               // level 2 came with the coarser levels
     if (L >= l && p.lo <= l) {
       const Sec sl = sec_geom(o, hi, l, L);
       const int64_t ntl = ceil_div(ceil_div(sl.npts, 64), 64);

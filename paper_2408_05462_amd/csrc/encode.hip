@@ -1027,47 +1027,6 @@ __global__ __launch_bounds__(kBS) void k_encode_l1t(EncPlan P) {
 // level are packed into their slots and the reconstructed 4-grid is written
 // to the level-2 grid, where level 1 predicts from it.
 
-constexpr int kTopSide = 17;                             // 4-grid points per axis of a 64-cell block
-constexpr int kTopPts = kTopSide * kTopSide * kTopSide;  // 4913
-constexpr int kTopCodes = kTopPts + 6 * 64;              // codes of every level (at most 5), each 64-aligned
-constexpr int kTopBS = 1024;                             // threads per block
-constexpr int kTopWaves = kTopBS / kWave;
-constexpr int kTopPer = (kTopPts + kTopBS - 1) / kTopBS; // 4-grid points per thread
-
-__device__ inline uint32_t top_idx(uint32_t z, uint32_t y, uint32_t x) { return (z * kTopSide + y) * kTopSide + x; }
-
-// The section sizes of level l of a block (as sec_geom, without divisors).
-struct SecDims {
-  uint32_t mx, my, mz, rowE, Pe, Po, npts;
-};
-__device__ inline SecDims sec_dims(const BlockPos &bp, int l, int L) {
-  SecDims d;
-  d.mz = ((bp.hi[0] - bp.o[0]) >> l) + 1;
-  d.my = ((bp.hi[1] - bp.o[1]) >> l) + 1;
-  d.mx = ((bp.hi[2] - bp.o[2]) >> l) + 1;
-  if (l == L) {
-    d.rowE = 0; d.Pe = 0; d.Po = d.mx * d.my;
-    d.npts = d.mx * d.my * d.mz;
-  } else {
-    const uint32_t cx = (d.mx + 1) / 2, cy = (d.my + 1) / 2, cz = (d.mz + 1) / 2;
-    d.rowE = d.mx - cx;
-    d.Pe = d.my * d.mx - cy * cx;
-    d.Po = d.my * d.mx;
-    d.npts = d.mz * d.my * d.mx - cz * cy * cx;
-  }
-  return d;
-}
-
-// Section index of the level-l point (w, v, u) (level-l units): lexicographic
-// over the level's points (the anchors' level: every point).
-__device__ inline uint32_t sec_index(const SecDims &d, bool top, uint32_t w, uint32_t v, uint32_t u) {
-  if (top) return (w * d.my + v) * d.mx + u;
-  const uint32_t base = (w >> 1) * (d.Pe + d.Po);
-  if (w & 1u) return base + d.Pe + v * d.mx + u;
-  const uint32_t row = (v >> 1) * (d.rowE + d.mx);
-  return (v & 1u) ? base + row + d.rowE + u : base + row + (u >> 1);
-}
-
 template <int KB>
 __global__ __launch_bounds__(kTopBS) void k_encode_top(EncPlan P) {
   __shared__ float R[kTopPts];                 // the reconstruction at the block's 4-grid points
@@ -1093,15 +1052,8 @@ __global__ __launch_bounds__(kTopBS) void k_encode_top(EncPlan P) {
     const char *__restrict__ xbase = reinterpret_cast<const char *>(P.x + (size_t)bp.o[0] * n1 * n2);
 #pragma unroll
     for (int k = 0; k < kTopPer; k++) {
-      const uint32_t i = threadIdx.x + (uint32_t)k * kTopBS;
-      const uint32_t z = i / (kTopSide * kTopSide), y = (i / kTopSide) % kTopSide, x = i % kTopSide;
-      const bool in = i < (uint32_t)kTopPts && z < d0 && y < d1 && x < d2;
-      int lv = L;
-      if (z) lv = min(lv, 2 + __builtin_ctz(z));
-      if (y) lv = min(lv, 2 + __builtin_ctz(y));
-      if (x) lv = min(lv, 2 + __builtin_ctz(x));
-      const uint32_t zc = min(z, d0 - 1), yc = min(y, d1 - 1), xc = min(x, d2 - 1);
-      pc[k] = xc | (yc << 5) | (zc << 10) | (in ? (uint32_t)(lv + 1) << 15 : 0u);
+      pc[k] = top_point(threadIdx.x + (uint32_t)k * kTopBS, d0, d1, d2, L);
+      const uint32_t xc = pc[k] & 31u, yc = (pc[k] >> 5) & 31u, zc = (pc[k] >> 10) & 31u;
       xv[k] = ldf(xbase, ((4 * zc * n1 + bp.o[1] + 4 * yc) * n2 + bp.o[2] + 4 * xc) * 4u);
     }
   }
