@@ -529,7 +529,7 @@ constexpr int kD0Plane = 1152;               // staged plane stride (floats; fit
 constexpr int kD0Codes = 7361;               // most section points of a pair
 constexpr int kD0Spare = 64;                 // LDS codes before the pair's first point (chunk heads)
 constexpr int kD0Chunks = 118;               // chunks that overlap a pair's part of the section
-constexpr int kD0Xcap = 1024;                // exact values of a pair staged in LDS
+constexpr int kD0Xcap = 128;                 // exact values of a pair staged in LDS (more are read from the stream)
 constexpr int kD0Group = 16;                 // chunks (unpack) whose loads a wave issues together
 constexpr int kD0Rows = 8;                   // rows a wave reconstructs before storing any
 constexpr uint16_t kD0Exact = 0xffffu;       // LDS code of a point stored exactly
