@@ -966,21 +966,26 @@ __device__ __forceinline__ void encode_tile(const EncPlan &P) {
     const uint32_t v16 = t.sc[c * 64 + (uint32_t)lane];
     const uint64_t em = __ballot(v16 == kT0Exact);
     const uint32_t zz = __builtin_amdgcn_inverse_ballot_w64(em) ? 0u : v16;
-    // the chunk's width: bit length of the OR of its codes
-    const uint32_t orv = wave_or_dpp(zz);
-    const uint32_t wb = orv ? 32u - (uint32_t)__clz((int)orv) : 0u;
-    pk[lane] = 0u;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    if (zz) {
-      const uint32_t bit = mul24s((uint32_t)lane, wb), wi = bit >> 5, off = bit & 31u;
-      __hip_atomic_fetch_or(&pk[wi], zz << off, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-      if (off + wb > 32u)
-        __hip_atomic_fetch_or(&pk[wi + 1], zz >> (32u - off), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    uint32_t wb = 0u;
+    if (__ballot(zz != 0u)) {
+      // the chunk's width: bit length of the OR of its codes (a chunk of
+      // zero codes, common, has width 0 and no payload)
+      const uint32_t orv = wave_or_dpp(zz);
+      wb = 32u - (uint32_t)__clz((int)orv);
+      pk[lane] = 0u;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      if (zz) {
+        const uint32_t bit = mul24s((uint32_t)lane, wb), wi = bit >> 5, off = bit & 31u;
+        __hip_atomic_fetch_or(&pk[wi], zz << off, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        if (off + wb > 32u)
+          __hip_atomic_fetch_or(&pk[wi + 1], zz >> (32u - off), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      if ((uint32_t)lane < 2 * wb) stu(payw, (c * 32 + (uint32_t)lane) * 4u, pk[lane]);
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    if ((uint32_t)lane < 2 * wb) stu(payw, (c * 32 + (uint32_t)lane) * 4u, pk[lane]);
+    wb = (uint32_t)__builtin_amdgcn_readfirstlane(wb);
     writelane(cw, wb | ((uint32_t)__popcll(em) << 8) | (em ? 0x10000u : 0u), k);
     if (em && lane == 0) P.emask[slot0 + c] = em;
     __builtin_amdgcn_wave_barrier();
