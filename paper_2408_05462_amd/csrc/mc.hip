@@ -491,12 +491,25 @@ __global__ __launch_bounds__(kBS) void k_mc_tris(McPlan M) {
         }
         return o;
       };
+      // the owner at i + 1 of the same row: the owner at i plus point i's
+      // crossings (no second count of the row below it)
+      auto next = [&](const Cross &k, const Owner &o, uint32_t vbn, uint32_t bxn, uint32_t byn) {
+        Owner r;
+        if (i + 1 < 64) {
+          r.base = o.base + o.bx + o.by + (uint32_t)((k.cz >> i) & 1ull);
+          r.bx = (uint32_t)((k.cx >> (i + 1)) & 1ull);
+          r.by = (uint32_t)((k.cy >> (i + 1)) & 1ull);
+        } else {
+          r.base = vbn; r.bx = bxn; r.by = byn;
+        }
+        return r;
+      };
       const Owner a00 = own(k0, v0, v0n, a0x, a0y, i);          // (dx,dy,dz) = (0,0,0)
-      const Owner a10 = own(k0, v0, v0n, a0x, a0y, i + 1);      // (1,0,0)
+      const Owner a10 = next(k0, a00, v0n, a0x, a0y);           // (1,0,0)
       const Owner b00 = own(k1, v1, v1n, a1x, a1y, i);          // (0,1,0)
-      const Owner b10 = own(k1, v1, v1n, a1x, a1y, i + 1);      // (1,1,0)
+      const Owner b10 = next(k1, b00, v1n, a1x, a1y);           // (1,1,0)
       const Owner d00 = own(k2, v2, v2n, b0x, 0u, i);           // (0,0,1)
-      const Owner d10 = own(k2, v2, v2n, b0x, 0u, i + 1);       // (1,0,1)
+      const Owner d10 = next(k2, d00, v2n, b0x, 0u);            // (1,0,1)
       const Owner e00 = own(k3, v3, v3, 0u, 0u, i);             // (0,1,1)
       // x edges 0..3 at (dy,dz) = (0,0), (1,0), (0,1), (1,1)
       my[0] = (int32_t)a00.base;
