@@ -526,14 +526,19 @@ def run_field(args):
     bits = torch.empty(api.bits_shape(shape, len(isos)), dtype=torch.int64, device=dev)
     fused = not args.unfused_mc
 
-    def step():
+    def step(split=False):
+        # split: events between the stages (the warm-up steps measure the
+        # stage split; each event costs the stream a few microseconds, so the
+        # timed steps record none)
         api.chr_compress(x, e, isos, p, sbuf, res, cws)
-        ev[1].record(stream)
+        if split:
+            ev[1].record(stream)
         if fused:
             api.chr_reconstruct_bits(info, sdev, e, isos, recon, bits, st, rws)
         else:
             api.chr_reconstruct(info, sdev, 0, e, recon, st, rws)
-        ev[2].record(stream)
+        if split:
+            ev[2].record(stream)
         for j, k in enumerate(isos):
             if fused:
                 api.iso_extract_bits(recon, bits[j], k, 1.0, verts, tris, counts[j], mws)
@@ -548,16 +553,22 @@ def run_field(args):
 
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     for _ in range(args.warmup):
-        ev[0].record(stream)
         step()
-        ev[3].record(stream)
     torch.cuda.synchronize()
+    # the stage split, from three more untimed steps
+    stage = np.zeros(3)
+    for _ in range(3):
+        ev[0].record(stream)
+        step(split=True)
+        ev[3].record(stream)
+        torch.cuda.synchronize()
+        stage += [ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]), ev[2].elapsed_time(ev[3])]
+    stage_ms = stage / 3
 
     # per-kernel timing with HIP events on the launch stream, inside the timed region
     kern = args.kernel or "k_encode_fine"
     L.check(lib.chr_prof_enable(kern.encode(), max(args.steps, 1)), "chr_prof_enable")
 
-    stage = np.zeros(3)
     total_ev = 0.0
     torch.cuda.synchronize()
     t_start = time.perf_counter()
@@ -566,7 +577,6 @@ def run_field(args):
         step()
         ev[3].record(stream)
         torch.cuda.synchronize()
-        stage += [ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]), ev[2].elapsed_time(ev[3])]
         total_ev += ev[0].elapsed_time(ev[3])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
@@ -584,7 +594,6 @@ def run_field(args):
 
     ms_step = total_ev / args.steps
     gbs = 4.0 * N / (ms_step * 1e-3) / 1e9
-    stage_ms = stage / args.steps
     cr = 4.0 * N / nbytes
 
     # algorithmic bytes of the timed kernel per launch

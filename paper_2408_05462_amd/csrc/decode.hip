@@ -1276,7 +1276,7 @@ void launch_decode(const DecPlan &p, hipStream_t s) {
       k_decode_fine<<<dim3((unsigned)ceil_div(ntile > 0 ? ntile : 1, kWaves), (unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
     }
     prof_mark("k_decode_fine", s, 1);
-    if (L >= 1) {
+    if (L >= 1 && g.n[2] == 1) {   // only a field one point wide along x has blocks that wide
       prof_mark("k_decode_thin", s, 0);
       k_decode_thin<<<dim3((unsigned)g.nblocks), dim3(kBS), 0, s>>>(p);
       prof_mark("k_decode_thin", s, 1);
