@@ -18,6 +18,7 @@ namespace {
 constexpr int kBS = 256;
 constexpr int kIPT = 8;
 constexpr int kTile = kBS * kIPT;
+constexpr int64_t kFuseTiles = 2048;  // 4 x u32 scans of at most this many tiles skip the tile-total scan
 
 template <class T> __device__ inline T zero();
 template <> __device__ inline U4 zero<U4>() { return U4{0, 0, 0, 0}; }
@@ -114,10 +115,16 @@ __global__ __launch_bounds__(kBS) void k_scan_reduce_u4(const In *__restrict__ i
 // Downsweep of 4 x u32 records: a wave's 512 consecutive elements as 8 rows
 // of 64 (DPP scans with a running carry), the waves' totals through LDS
 // (one barrier), the tile's prefix from the partials.
-template <class In>
+// FROM_TOTALS: the tile's prefix is summed here from the tile totals before
+// it (each thread a strided share, reduced with the waves' run totals
+// through the same barrier), instead of read from a scanned array; the last
+// tile writes the grand total to out[n].  For up to kFuseTiles tiles, where
+// that costs less than a separate launch.
+template <class In, bool FROM_TOTALS = false>
 __global__ __launch_bounds__(kBS) void k_scan_down_u4(const In *__restrict__ in, U4 *__restrict__ out,
                                                       const U4 *__restrict__ part, int64_t n) {
   __shared__ U4 lds[kBS / kWave];
+  __shared__ U4 ldp[kBS / kWave];
   const uint32_t wave = threadIdx.x / kWave;
   const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)wave * (kTile / (kBS / kWave));
   const int lane = (int)(threadIdx.x & (kWave - 1));
@@ -134,9 +141,24 @@ __global__ __launch_bounds__(kBS) void k_scan_down_u4(const In *__restrict__ in,
     carry = lane63(inc);
     v[r] = sub(inc, v[r]);                     // exclusive within the wave's run
   }
-  if (lane == 0) lds[wave] = carry;
-  __syncthreads();
-  U4 pre = part[blockIdx.x];
+  U4 pre;
+  if (FROM_TOTALS) {
+    U4 t = U4{0, 0, 0, 0};
+    for (uint32_t i = threadIdx.x; i < blockIdx.x; i += kBS) t = add(t, part[i]);
+    t = lane63(wave_incl(t));
+    if (lane == 0) {
+      lds[wave] = carry;
+      ldp[wave] = t;
+    }
+    __syncthreads();
+    pre = add(add(ldp[0], ldp[1]), add(ldp[2], ldp[3]));
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0)
+      out[n] = add(pre, add(add(lds[0], lds[1]), add(lds[2], lds[3])));
+  } else {
+    if (lane == 0) lds[wave] = carry;
+    __syncthreads();
+    pre = part[blockIdx.x];
+  }
   for (uint32_t w = 0; w < wave; w++) pre = add(pre, lds[w]);
 #pragma unroll
   for (int r = 0; r < kIPT; r++) {
@@ -251,6 +273,10 @@ static void scan_records(const In *in, U4 *out, int64_t n, U4 *tmp, hipStream_t 
   }
   const int64_t ntiles = ceil_div(n, kTile);
   k_scan_reduce_u4<In><<<dim3((unsigned)ntiles), dim3(kBS), 0, s>>>(in, tmp, n);
+  if (ntiles <= kFuseTiles) {
+    k_scan_down_u4<In, true><<<dim3((unsigned)ntiles), dim3(kBS), 0, s>>>(in, out, tmp, n);
+    return;
+  }
   k_scan_part<U4><<<dim3(1), dim3(kBS), 0, s>>>(tmp, ntiles, out + n);
   k_scan_down_u4<In><<<dim3((unsigned)ntiles), dim3(kBS), 0, s>>>(in, out, tmp, n);
 }
