@@ -787,8 +787,8 @@ def run_field(args):
             pm = api.params(w["levels"], w["block"], merge=M)
             mcap = api.chr_compress_bound(shape, pm)
             mbuf = torch.empty(mcap, dtype=torch.uint8, device=dev)
-            mws = torch.empty(api.chr_compress_workspace(shape, pm), dtype=torch.uint8, device=dev)
-            api.chr_compress(x, e, isos, pm, mbuf, res, mws)
+            mcws = torch.empty(api.chr_compress_workspace(shape, pm), dtype=torch.uint8, device=dev)
+            api.chr_compress(x, e, isos, pm, mbuf, res, mcws)
             torch.cuda.synchronize()
             rm = api.read_result(res)
             assert rm["status"] == 0
@@ -797,7 +797,7 @@ def run_field(args):
             rep = 5
             t0 = time.perf_counter()
             for _ in range(rep):
-                api.chr_compress(x, e, isos, pm, mbuf, res, mws)
+                api.chr_compress(x, e, isos, pm, mbuf, res, mcws)
             torch.cuda.synchronize()
             comp_ms = (time.perf_counter() - t0) * 1e3 / rep
             mrec = torch.empty(shape, dtype=torch.float32, device=dev)
@@ -818,7 +818,7 @@ def run_field(args):
                         "compress_ms_wall": round(comp_ms, 4),
                         "reconstruct_ms": round(e0.elapsed_time(e1) / rep, 4),
                         "reconstruction_equal_plain": same})
-            del mbuf, mws, mrec, mrws
+            del mbuf, mcws, mrec, mrws
 
     # block merging for extraction: the blocks that can hold the isosurface
     # merged into one box; marching cubes over the box vs over the field
