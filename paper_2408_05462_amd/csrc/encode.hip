@@ -598,6 +598,19 @@ __device__ __forceinline__ uint32_t t0_ord(float f) {
   return u ^ ((uint32_t)((int32_t)u >> 31) | 0x80000000u);
 }
 
+// OR of v over lanes 0-31 (a) and over lanes 32-63 (b), as wave-uniform
+// values: within each 16-lane row (xor 1, xor 2, half mirror, mirror), then
+// row 0's result into row 1 and row 2's into row 3 (broadcast of lane 15).
+__device__ __forceinline__ void half_or(uint32_t v, uint32_t &a, uint32_t &b) {
+  v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xb1, 0xf, 0xf, false);   // quad_perm 1,0,3,2
+  v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4e, 0xf, 0xf, false);   // quad_perm 2,3,0,1
+  v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xf, 0xf, false);  // row_half_mirror
+  v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xf, 0xf, false);  // row_mirror
+  v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  a = (uint32_t)__builtin_amdgcn_readlane((int)v, 31);
+  b = (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
 // Quantization, the bound and topology checks, the statistics and the code
 // of one point predicted as p, without branches: lanes outside the row hold
 // a copy of a point inside it (same value, same code, same LDS slot), so only
@@ -703,13 +716,13 @@ __device__ __forceinline__ void encode_tile(const EncPlan &P) {
   // address 0 and a row's parent offsets fit the read instructions' fields
   struct Lds {
     float sg[2 * TD::Plane];
-    uint16_t sc[kT0Spare + TD::Codes];
-    uint32_t pack[kWaves][64];
+    uint16_t sc[kT0Spare + TD::Codes + 64];   // + the second chunk of a pair read past the last
+    uint32_t pack[kWaves][65];                // + a spare word past the last half
   };
   __shared__ __align__(16) Lds lds;
   float *sg = lds.sg;
   uint16_t *sc = lds.sc;
-  uint32_t (*pack)[64] = lds.pack;
+  uint32_t (*pack)[65] = lds.pack;
   uint32_t w2, b;
   xcd_remap(w2, b);
   const Geo &gq = P.g;
@@ -799,6 +812,9 @@ __device__ __forceinline__ void encode_tile(const EncPlan &P) {
   const uint32_t grow = f2 * 4u, gplane = f1 * f2 * 4u;
   // codes past the section in its last chunk read as 0 when packing
   if (cend > cfirst && cend * 64 > s.npts && threadIdx.x < cend * 64 - s.npts) t.sc[s.npts + threadIdx.x] = 0;
+  // and the chunk after the tile's last, which the packing of an odd
+  // count of chunks reads as the second of a pair
+  if (threadIdx.x < 64) t.sc[cend * 64 + threadIdx.x] = 0;
   // Every x row a wave needs is loaded before the barrier: A rows v = 4a +
   // 2*half (odd u = 2i + 1), B rows v = 2f + 1, C/D rows 2m and 2m + 1.  A
   // row past the block or a lane past a row loads a copy of a point inside.
@@ -953,46 +969,79 @@ __device__ __forceinline__ void encode_tile(const EncPlan &P) {
   __syncthreads();
 
   // ---- pack the pair's chunks from LDS into their slots (exact values are
-  // already in the slots, at their lanes: count word 3 says so).  The wave
-  // packs chunks cfirst + wave + 4k; the counts of its chunk k wait in lane
-  // k of a register and are stored together after the loop.
+  // already in the slots, at their lanes: count word 3 says so), two chunks
+  // at a time: lane i reads the codes 2i and 2i + 1 of chunks c, c + 1 (c
+  // even from cfirst) as one word, so lanes 0-31 hold chunk c and lanes
+  // 32-63 chunk c + 1; one OR reduction gives both widths, and each chunk
+  // packs into its own half of the wave's LDS row (at most 2 * 16 words:
+  // codes are below 2^16 - 1).  The wave takes the chunk pairs
+  // cfirst + 2 (wave + 4k); the counts of its pair k wait in lane k of a
+  // register (chunk c in the low half-word, c + 1 in the high one) and are
+  // stored together after the loop.
   uint32_t *pk = pack[wave];                   // 64 words, every lane clears its own
   char *__restrict__ payw = reinterpret_cast<char *>(P.pay + slot0 * 32);
-  const uint32_t c0 = cfirst + wave;
-  const uint32_t nmine = cend > c0 ? (cend - c0 + kWaves - 1) / kWaves : 0u;
-  uint32_t cw = 0;                             // lane k: width | exact points << 8 | has exact << 16
+  const uint32_t nchk = cend > cfirst ? cend - cfirst : 0u;
+  const uint32_t npair = (nchk + 1) / 2;
+  const uint32_t nmine = npair > wave ? (npair - wave + kWaves - 1) / kWaves : 0u;
+  const uint32_t lh = (uint32_t)lane & 31u;    // the lane's place in its chunk's half
+  uint32_t *pkh = pk + (half << 5);
+  uint32_t cw = 0;                             // lane k: width | exact points << 5, per chunk of pair k
   for (uint32_t k = 0; k < nmine; k++) {
-    const uint32_t c = c0 + k * kWaves;
-    const uint32_t v16 = t.sc[c * 64 + (uint32_t)lane];
-    const uint64_t em = __ballot(v16 == kT0Exact);
-    const uint32_t zz = __builtin_amdgcn_inverse_ballot_w64(em) ? 0u : v16;
-    uint32_t wb = 0u;
-    if (__ballot(zz != 0u)) {
-      // the chunk's width: bit length of the OR of its codes (a chunk of
-      // zero codes, common, has width 0 and no payload)
-      const uint32_t orv = wave_or_dpp(zz);
-      wb = 32u - (uint32_t)__clz((int)orv);
+    const uint32_t c = cfirst + 2 * (wave + k * kWaves);
+    // chunk c + 1 past the tile's last reads zeros
+    const uint32_t v2 = *reinterpret_cast<const uint32_t *>(t.sc + c * 64 + 2 * (uint32_t)lane);
+    uint32_t lo = v2 & 0xffffu, hi = v2 >> 16;
+    uint32_t wA = 0u, wB = 0u;
+    uint64_t emA = 0ull, emB = 0ull;
+    if (__ballot(v2 != 0u)) {
+      // the chunks' widths: bit lengths of the OR of each half's codes (a
+      // chunk of zero codes, common, has width 0 and no payload); an exact
+      // point's marker sets bit 15, so only then are the exact points
+      // looked for (their masks in code order) and taken out of the widths
+      uint32_t oA, oB;
+      half_or(lo | hi, oA, oB);
+      if ((oA | oB) & 0x8000u) {
+        emA = __ballot(t.sc[c * 64 + (uint32_t)lane] == kT0Exact);
+        emB = __ballot(t.sc[c * 64 + 64 + (uint32_t)lane] == kT0Exact);
+        lo = lo == kT0Exact ? 0u : lo;
+        hi = hi == kT0Exact ? 0u : hi;
+        half_or(lo | hi, oA, oB);
+      }
+      wA = oA ? 32u - (uint32_t)__clz((int)oA) : 0u;
+      wB = oB ? 32u - (uint32_t)__clz((int)oB) : 0u;
+      const uint32_t wl = half ? wB : wA;
       pk[lane] = 0u;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
-      if (zz) {
-        const uint32_t bit = mul24s((uint32_t)lane, wb), wi = bit >> 5, off = bit & 31u;
-        __hip_atomic_fetch_or(&pk[wi], zz << off, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-        if (off + wb > 32u)
-          __hip_atomic_fetch_or(&pk[wi + 1], zz >> (32u - off), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-      }
+      // the lane's two codes (2 wl bits) at bit 2 lh wl of its half: the
+      // word holding the start, and the next one (its top `bit mod 32`
+      // bits, an extract of width 0 when the start is word-aligned; the
+      // word past a half is the next half's first or the row's spare, and
+      // only zeros reach it)
+      const uint32_t pv = lo | (hi << wl);
+      const uint32_t bit = mul24v(2 * lh, wl);
+      uint32_t *dst = pkh + (bit >> 5);
+      __hip_atomic_fetch_or(dst, pv << (bit & 31u), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+      __hip_atomic_fetch_or(dst + 1, __builtin_amdgcn_ubfe(pv, 0u - bit, bit), __ATOMIC_RELAXED,
+                            __HIP_MEMORY_SCOPE_WAVEFRONT);
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       __builtin_amdgcn_wave_barrier();
-      if ((uint32_t)lane < 2 * wb) stu(payw, (c * 32 + (uint32_t)lane) * 4u, pk[lane]);
+      if ((lh >> 1) < wl) stu(payw, (c * 32 + (uint32_t)lane) * 4u, pk[lane]);
     }
-    wb = (uint32_t)__builtin_amdgcn_readfirstlane(wb);
-    writelane(cw, wb | ((uint32_t)__popcll(em) << 8) | (em ? 0x10000u : 0u), k);
-    if (em && lane == 0) P.emask[slot0 + c] = em;
+    wA = (uint32_t)__builtin_amdgcn_readfirstlane(wA);
+    wB = (uint32_t)__builtin_amdgcn_readfirstlane(wB);
+    writelane(cw, wA | ((uint32_t)__popcll(emA) << 5) | ((wB | ((uint32_t)__popcll(emB) << 5)) << 16), k);
+    if (emA && lane == 0) P.emask[slot0 + c] = emA;
+    if (emB && lane == 0) P.emask[slot0 + c + 1] = emB;
     __builtin_amdgcn_wave_barrier();
   }
-  if ((uint32_t)lane < nmine) {
-    const uint32_t he = (cw >> 16) & 1u;
-    P.cnt[slot0 + c0 + (uint32_t)lane * kWaves] = U4{cw & 0xffu, he, (cw >> 8) & 0xffu, he};
+  {
+    const uint32_t i = (uint32_t)lane, c = cfirst + 2 * (wave + (i >> 1) * kWaves) + (i & 1u);
+    const uint32_t w = (uint32_t)__shfl((int)cw, (int)(i >> 1), kWave) >> (16 * (i & 1u));
+    if (i < 2 * nmine && c < cend) {
+      const uint32_t ne = (w >> 5) & 0x7fu, he = ne ? 1u : 0u;
+      P.cnt[slot0 + c] = U4{w & 31u, he, ne, he};
+    }
   }
   // the lane's extremes as order-preserving keys (a lane that saw no point
   // keeps +inf / -inf, which no finite value loses to); a non-finite input
