@@ -527,15 +527,14 @@ __device__ __forceinline__ void decode_fast(const DecPlan &D) {
 constexpr int kD0Side = 33;                  // level-1 points per axis of a 64-cell block
 constexpr int kD0Plane = 1152;               // staged plane stride (floats; fits an LDS immediate offset)
 constexpr int kD0Codes = 7361;               // most section points of a pair
-constexpr int kD0Spare = 64;                 // LDS codes before the pair's first point (chunk heads)
 constexpr int kD0Chunks = 118;               // chunks that overlap a pair's part of the section
 constexpr int kD0Xcap = 128;                 // exact values of a pair staged in LDS (more are read from the stream)
-constexpr int kD0Group = 16;                 // chunks (unpack) whose loads a wave issues together
+constexpr int kD0Group = 8;                  // pairs of chunks (unpack) whose loads a wave issues together
 constexpr int kD0Rows = 8;                   // rows a wave reconstructs before storing any
-constexpr uint16_t kD0Exact = 0xffffu;       // LDS code of a point stored exactly
+constexpr int32_t kD0ExactQ = -32768;        // LDS code of a point stored exactly (codes are within +-32767)
 
 struct D0Ctx {
-  const uint16_t *sc;
+  const int16_t *sc;
   const uint32_t *cxo;
   const unsigned long long *cem;
   const float *xl;
@@ -544,10 +543,9 @@ struct D0Ctx {
   float step;
 };
 
-// Value of a level-0 point predicted as p whose LDS code is zz (not an
-// exact point).
-__device__ __forceinline__ float d0_quant(const D0Ctx &t, uint32_t zz, float p) {
-  const int32_t q = (int32_t)(zz >> 1) ^ -(int32_t)(zz & 1u);
+// Value of a level-0 point predicted as p whose (signed) LDS code is q (not
+// an exact point).
+__device__ __forceinline__ float d0_quant(const D0Ctx &t, int32_t q, float p) {
   return __fadd_rn(p, __fmul_rn((float)q, t.step));
 }
 
@@ -618,13 +616,13 @@ __device__ __forceinline__ void decode_tile(const DecPlan &D) {
   using TD = DTileDims<LV>;
   constexpr uint32_t S = 1u << LV;             // field points per level step
   __shared__ float sg[2 * TD::Plane];
-  // codes by section index - J0, after a spare prefix: the pair's first and
-  // last chunks unpack whole, their points outside the pair landing in the
-  // spare entries (at most 63 before J0 and 63 after J1)
-  __shared__ uint16_t scs[kD0Spare + TD::Codes + 64];
-  uint16_t *const sc = scs + kD0Spare;
-  __shared__ uint32_t cwo[TD::Chunks], cxo[TD::Chunks], cwb[TD::Chunks];
-  __shared__ unsigned long long cem[TD::Chunks];
+  // signed codes by section index - 64 c0 (c0 the pair's first chunk): the
+  // pair's first and last chunks unpack whole (at most 63 points before J0
+  // and 63 after J1), and a last pair of chunks may end one chunk past them
+  __shared__ __align__(4) int16_t scs[TD::Codes + 192];
+  // chunk headers, plus a zero-width entry for the chunk past the range
+  __shared__ uint32_t cwo[TD::Chunks + 1], cxo[TD::Chunks + 1], cwb[TD::Chunks + 1];
+  __shared__ unsigned long long cem[TD::Chunks + 1];
   __shared__ float xl[kD0Xcap];
   __shared__ uint32_t sbad[kWaves];
   uint32_t w2, b;
@@ -698,7 +696,9 @@ __device__ __forceinline__ void decode_tile(const DecPlan &D) {
       const uint32_t pc = (uint32_t)__popcll(em);
       const uint32_t xo = tx + wave_excl_sum(pc);
       bad = __ballot(badl || xo + pc > v.NX) != 0ull ? 1u : 0u;
-      if (c >= c0 && c < c1) {
+      const bool in = c >= c0 && c < c1;
+      bad |= __ballot(in && em != 0ull) != 0ull ? 2u : 0u;
+      if (in) {
         cwb[c - c0] = w;
         cwo[c - c0] = wo;
         cxo[c - c0] = xo;
@@ -706,58 +706,82 @@ __device__ __forceinline__ void decode_tile(const DecPlan &D) {
       }
     }
     if (lane == 0) sbad[wave] = bad;
+    if (threadIdx.x == 0) {
+      cwb[ncw] = 0u;
+      cwo[ncw] = 0u;
+      cem[ncw] = 0ull;
+    }
   }
   __syncthreads();
-  if (sbad[0] | sbad[1] | sbad[2] | sbad[3]) {
+  const uint32_t hflags = sbad[0] | sbad[1] | sbad[2] | sbad[3];
+  if (hflags & 1u) {
     if (threadIdx.x == 0) set_status(D, -4);
     return;
   }
+  const bool tileE = (hflags & 2u) != 0;       // some chunk of the range has exact points
   const uint32_t xo0 = cxo[0];
   const char *__restrict__ payb = reinterpret_cast<const char *>(v.p + v.Poff);
   const char *__restrict__ exb = reinterpret_cast<const char *>(v.p + v.Xoff);
   // ---- stage the range's exact values (one coalesced pass) and unpack the
-  // codes of the pair's points; each wave issues the payload loads of
-  // kD0Group chunks before using any
+  // codes of the pair's points two chunks at a time: for the pair of chunks
+  // k = 2i, 2i + 1 of the range, lane l < 32 takes codes 2l, 2l + 1 of chunk
+  // k and lane 32 + l those of chunk k + 1 (2 w bits from bit 2 l w of the
+  // chunk's payload), decodes both from zigzag form in one word and stores
+  // them as one word; each wave issues the payload loads of kD0Group pairs
+  // before using any
   {
     const uint32_t nx = min(cxo[ncw - 1] + (uint32_t)__popcll(cem[ncw - 1]) - xo0, (uint32_t)kD0Xcap);
     for (uint32_t i = threadIdx.x; i < nx; i += kBS) xl[i] = __uint_as_float(ldu(exb, 4u * (xo0 + i)));
   }
-  for (uint32_t k0 = wave; k0 < ncw; k0 += kD0Group * kWaves) {
-    // the group's chunk headers, lane u holding chunk k0 + 4u's, taken by
-    // readlane (no LDS round trip per chunk)
-    const uint32_t kl = min(k0 + (uint32_t)lane * kWaves, ncw - 1);
-    const uint32_t lw = cwb[kl], lwo = cwo[kl];
-    const unsigned long long lem = cem[kl];
-    uint32_t wu[kD0Group], lo[kD0Group], hi[kD0Group];
+  {
+    const uint32_t lh = (uint32_t)lane & 31u, hf = (uint32_t)lane >> 5;
+    const uint32_t npair = (ncw + 1) / 2;
+    // the payload and the byte offset of its last word (a section without
+    // payload: its own first word, read and not used)
+    const char *__restrict__ pldb = v.W ? payb : reinterpret_cast<const char *>(v.p);
+    const uint32_t plast = v.W ? 8u * v.W - 4u : 0u;
+    for (uint32_t i0 = wave; i0 < npair; i0 += kD0Group * kWaves) {
+      uint32_t wu[kD0Group], bu[kD0Group], lo[kD0Group], hi[kD0Group];
 #pragma unroll
-    for (int u = 0; u < kD0Group; u++) {
-      const uint32_t w = (uint32_t)__builtin_amdgcn_readlane((int)lw, u);
-      const uint32_t wo = (uint32_t)__builtin_amdgcn_readlane((int)lwo, u);
-      const uint32_t bit = mul24s((uint32_t)lane, w), wi = bit >> 5;
-      wu[u] = w;
-      lo[u] = hi[u] = 0u;
-      if (w) {
-        lo[u] = ldu(payb, 8u * wo + 4u * wi);
-        hi[u] = ldu(payb, 8u * wo + 4u * min(wi + 1, 2 * w - 1));
+      for (int u = 0; u < kD0Group; u++) {
+        // the lane's chunk (past the range the zero-width entry), and the
+        // two payload words its codes can span, loaded without a branch: at
+        // offsets clamped to the payload's last word, which changes no word
+        // a code uses (a zero-width chunk, or a second word its codes do not
+        // reach, reads a word of the payload that is then not used)
+        const uint32_t kc = min(2 * (i0 + (uint32_t)u * kWaves) + hf, ncw);
+        const uint32_t w = cwb[kc], wo = cwo[kc];
+        const uint32_t bit = mul24v(2 * lh, w);
+        const uint32_t o0 = min(8u * wo + 4u * (bit >> 5), plast);
+        wu[u] = w;
+        bu[u] = bit;
+        lo[u] = ldu(pldb, o0);
+        hi[u] = ldu(pldb, min(o0 + 4u, plast));
       }
-    }
 #pragma unroll
-    for (int u = 0; u < kD0Group; u++) {
-      const uint32_t k = k0 + (uint32_t)u * kWaves;
-      if (k >= ncw) break;
-      // the lane's code: w bits from bit lane * w of the chunk's payload
-      // (a funnel shift of the two words it can span, then a field extract;
-      // width 0 gives 0)
-      const uint32_t w = wu[u];
-      const uint32_t zz = __builtin_amdgcn_ubfe(__builtin_amdgcn_alignbit(hi[u], lo[u], mul24s((uint32_t)lane, w)), 0u, w);
-      const unsigned long long em =
-          ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(lem >> 32), u) << 32) |
-          (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)lem, u);
-      const bool E = __builtin_amdgcn_inverse_ballot_w64(em);
-      sc[(c0 + k) * 64 + (uint32_t)lane - J0] = E ? kD0Exact : (uint16_t)zz;
+      for (int u = 0; u < kD0Group; u++) {
+        const uint32_t i = i0 + (uint32_t)u * kWaves;
+        if (i >= npair) break;
+        // a funnel shift of the two words the codes can span, then the two
+        // fields (width 0 gives 0), then zigzag decoding of both halves
+        const uint32_t w = wu[u];
+        const uint32_t x = __builtin_amdgcn_alignbit(hi[u], lo[u], bu[u]);
+        const uint32_t z = __builtin_amdgcn_ubfe(x, 0u, w) | (__builtin_amdgcn_ubfe(x, w, w) << 16);
+        uint32_t q = ((z >> 1) & 0x7fff7fffu) ^ ((z & 0x00010001u) * 0xffffu);
+        if (tileE) {
+          // exact points take the marker in their half
+          const uint32_t kc = min(2 * i + hf, ncw);
+          const uint32_t e2 = (uint32_t)(cem[kc] >> (2 * lh)) & 3u;
+          const uint32_t m = (e2 & 1u) * 0xffffu + (e2 & 2u) * 0x7fff8000u;
+          q = (q & ~m) | (0x80008000u & m);
+        }
+        *reinterpret_cast<uint32_t *>(scs + 128 * i + 2 * (uint32_t)lane) = q;
+      }
     }
   }
   __syncthreads();
+  // codes by section index - J0
+  const int16_t *const sc = scs + (J0 & 63u);
 
   D0Ctx t;
   t.sc = sc;
@@ -818,7 +842,8 @@ __device__ __forceinline__ void decode_tile(const DecPlan &D) {
   const uint32_t cmax = 2 * (jlast - J0), ceb = 2 * lxe, cob = 2 * (rowE + u), cub = 2 * u;
   for (uint32_t a0 = wave; 2 * a0 < rown; a0 += kWaves * (kD0Rows / 2)) {
     float A0[kD0Rows / 2], A1[kD0Rows / 2], B0[kD0Rows / 2], B1[kD0Rows / 2];
-    uint32_t je[kD0Rows / 2], jo[kD0Rows / 2], ze[kD0Rows / 2], zo[kD0Rows / 2];
+    uint32_t je[kD0Rows / 2], jo[kD0Rows / 2];
+    int32_t ze[kD0Rows / 2], zo[kD0Rows / 2];
 #pragma unroll
     for (int k = 0; k < kD0Rows / 2; k++) {
       const uint32_t a = a0 + (uint32_t)k * kWaves;   // the row pair 2a, 2a + 1
@@ -829,11 +854,10 @@ __device__ __forceinline__ void decode_tile(const DecPlan &D) {
       B1[k] = d0_lds(sgb, ga + kRow + 4);
       je[k] = min(2 * a * RP + ceb, cmax);
       jo[k] = min(2 * a * RP + cob, cmax);
-      ze[k] = *reinterpret_cast<const uint16_t *>(scb + je[k]);
-      zo[k] = *reinterpret_cast<const uint16_t *>(scb + jo[k]);
+      ze[k] = *reinterpret_cast<const int16_t *>(scb + je[k]);
+      zo[k] = *reinterpret_cast<const int16_t *>(scb + jo[k]);
     }
     float rv[kD0Rows];
-    uint64_t anyE = 0;
 #pragma unroll
     for (int k = 0; k < kD0Rows / 2; k++) {
       const uint32_t a = a0 + (uint32_t)k * kWaves;
@@ -845,13 +869,17 @@ __device__ __forceinline__ void decode_tile(const DecPlan &D) {
       float pb = avg2(A, B);
       hold(pb);
       rv[2 * k + 1] = d0_quant(t, zo[k], a + 1 < gy ? pb : A);
-      anyE |= __ballot((odd_u && ze[k] == kD0Exact) || zo[k] == kD0Exact);
     }
-    if (anyE) {
+    if (tileE) {
+      uint64_t anyE = 0;
 #pragma unroll
-      for (int k = 0; k < kD0Rows / 2; k++) {
-        if (odd_u && ze[k] == kD0Exact) rv[2 * k] = d0_exact(t, J0 + je[k] / 2);
-        if (zo[k] == kD0Exact) rv[2 * k + 1] = d0_exact(t, J0 + jo[k] / 2);
+      for (int k = 0; k < kD0Rows / 2; k++) anyE |= __ballot((odd_u && ze[k] == kD0ExactQ) || zo[k] == kD0ExactQ);
+      if (anyE) {
+#pragma unroll
+        for (int k = 0; k < kD0Rows / 2; k++) {
+          if (odd_u && ze[k] == kD0ExactQ) rv[2 * k] = d0_exact(t, J0 + je[k] / 2);
+          if (zo[k] == kD0ExactQ) rv[2 * k + 1] = d0_exact(t, J0 + jo[k] / 2);
+        }
       }
     }
 #pragma unroll
@@ -872,7 +900,8 @@ __device__ __forceinline__ void decode_tile(const DecPlan &D) {
     for (uint32_t m0 = wave; 2 * m0 < rown; m0 += kWaves * (kD0Rows / 2)) {
       float A0[kD0Rows / 2], A1[kD0Rows / 2], B0[kD0Rows / 2], B1[kD0Rows / 2];
       float C0[kD0Rows / 2], C1[kD0Rows / 2], E0[kD0Rows / 2], E1[kD0Rows / 2];
-      uint32_t jc[kD0Rows / 2], jd[kD0Rows / 2], zc[kD0Rows / 2], zd[kD0Rows / 2];
+      uint32_t jc[kD0Rows / 2], jd[kD0Rows / 2];
+      int32_t zc[kD0Rows / 2], zd[kD0Rows / 2];
 #pragma unroll
       for (int k = 0; k < kD0Rows / 2; k++) {
         const uint32_t m = m0 + (uint32_t)k * kWaves;
@@ -887,11 +916,10 @@ __device__ __forceinline__ void decode_tile(const DecPlan &D) {
         E1[k] = d0_lds(sgb, ga + kPl + kRow + 4);
         jc[k] = min(2 * (s.Pe + 2 * m * mx) + cub, cmax);
         jd[k] = min(2 * (s.Pe + (2 * m + 1) * mx) + cub, cmax);
-        zc[k] = *reinterpret_cast<const uint16_t *>(scb + jc[k]);
-        zd[k] = *reinterpret_cast<const uint16_t *>(scb + jd[k]);
+        zc[k] = *reinterpret_cast<const int16_t *>(scb + jc[k]);
+        zd[k] = *reinterpret_cast<const int16_t *>(scb + jd[k]);
       }
       float rv[kD0Rows];
-      uint64_t anyE = 0;
 #pragma unroll
       for (int k = 0; k < kD0Rows / 2; k++) {
         const uint32_t m = m0 + (uint32_t)k * kWaves;
@@ -909,13 +937,17 @@ __device__ __forceinline__ void decode_tile(const DecPlan &D) {
         float pd = avg2(p0, p1);
         hold(pd);
         rv[2 * k + 1] = d0_quant(t, zd[k], zu ? pd : p0);
-        anyE |= __ballot(zc[k] == kD0Exact || zd[k] == kD0Exact);
       }
-      if (anyE) {
+      if (tileE) {
+        uint64_t anyE = 0;
 #pragma unroll
-        for (int k = 0; k < kD0Rows / 2; k++) {
-          if (zc[k] == kD0Exact) rv[2 * k] = d0_exact(t, J0 + jc[k] / 2);
-          if (zd[k] == kD0Exact) rv[2 * k + 1] = d0_exact(t, J0 + jd[k] / 2);
+        for (int k = 0; k < kD0Rows / 2; k++) anyE |= __ballot(zc[k] == kD0ExactQ || zd[k] == kD0ExactQ);
+        if (anyE) {
+#pragma unroll
+          for (int k = 0; k < kD0Rows / 2; k++) {
+            if (zc[k] == kD0ExactQ) rv[2 * k] = d0_exact(t, J0 + jc[k] / 2);
+            if (zd[k] == kD0ExactQ) rv[2 * k + 1] = d0_exact(t, J0 + jd[k] / 2);
+          }
         }
       }
 #pragma unroll
@@ -963,8 +995,8 @@ __device__ __forceinline__ void decode_tile(const DecPlan &D) {
         const float p1 = yu ? avg2(c0v, d0v) : c0v;
         const float p = (w == 1 && zu) ? avg2(p0, p1) : p0;
         const uint32_t j = min(w == 0 ? J0 + (vv >> 1) * RP + rowE + 64u : J0 + s.Pe + vv * mx + 64u, jlast);
-        const uint32_t zz = sc[j - J0];
-        r = zz == kD0Exact ? d0_exact(t, j) : d0_quant(t, zz, p);
+        const int32_t q = sc[j - J0];
+        r = q == kD0ExactQ ? d0_exact(t, j) : d0_quant(t, q, p);
       }
       if (rr < nrow) stf(obase, (w == 0 ? xe0 : xo0b) + vv * rowB + 256u, r);
       if (nk && rr < nrow) {
