@@ -52,7 +52,7 @@ __device__ inline uint64_t rl64(uint64_t v, int k) {
 struct SecView {
   const uint8_t *p;
   uint32_t npts, W, NE, NX, nch, ntile;
-  uint64_t A, Poff, Moff, Xoff;
+  uint64_t A, Poff, Moff, Xoff, sz;
   bool ok;
 };
 
@@ -81,6 +81,51 @@ __device__ inline SecView open_section(const DecPlan &D, int64_t b, int l, uint3
   v.Xoff = v.Moff + 8 * (uint64_t)v.NE;
   v.ok = true;
   return v;
+}
+
+// A zero the compiler cannot see through, in a vector register: a uniform
+// load at an address offset by it goes through the vector memory path, whose
+// wait counter it does not share with the kernel's scalar loads (of its
+// arguments, say), so a later scalar load's wait does not wait for it.
+__device__ inline uint32_t vzero() {
+  uint32_t z = 0u;
+  asm volatile("" : "+v"(z));
+  return z;
+}
+
+// Section (b, l) located from its table entry alone, for a reader that
+// issues its tile-table and chunk-header loads before the section's own
+// header arrives: the layout up to the payload comes from the expected point
+// count (checked to fit in the section), `ok` covers the entry and that fit,
+// and the header's fields (loaded here through the vector path, not yet
+// used) are checked by sec_fields_ok; Moff and Xoff are left to the caller.
+__device__ inline SecView open_section_early(const DecPlan &D, int64_t b, int l, uint32_t expect_npts) {
+  SecView v;
+  v.ok = false;
+  const int L = D.g.nL - 1;
+  const uint64_t ent = kHeaderBytes + 16 * ((uint64_t)b * D.g.nL + (uint64_t)(L - l));
+  if (ent + 16 > D.sbytes) return v;
+  const uint64_t off = ld64(D.s + ent), sz = ld64(D.s + ent + 8);
+  if (off < D.payload_off || (off & 7) || sz < 16 || off + sz > D.sbytes) return v;
+  v.p = D.s + off;
+  v.sz = sz;
+  v.nch = (expect_npts + 63) / 64;
+  v.ntile = (v.nch + 63) / 64;
+  v.A = 16 + pad8(12 * (uint64_t)v.ntile);
+  v.Poff = v.A + pad8(v.nch);
+  if (v.Poff > sz) return v;
+  const uint8_t *hp = v.p + vzero();
+  v.npts = ld32(hp);
+  v.W = ld32(hp + 4);
+  v.NE = ld32(hp + 8);
+  v.NX = ld32(hp + 12);
+  v.ok = true;
+  return v;
+}
+
+// The checks open_section makes on a section's header fields.
+__device__ inline bool sec_fields_ok(const SecView &v, uint32_t expect_npts) {
+  return v.npts == expect_npts && sec_bytes(v.npts, v.W, v.NE, v.NX) == v.sz;
 }
 
 // Block activity flags of a differentiated stream: bit 0 of the spare word
@@ -640,11 +685,6 @@ __device__ __forceinline__ void decode_tile(const DecPlan &D) {
   const bool has_odd = we + 1 < s.mz;
   const uint32_t J1 = has_odd ? J0 + PP : J0 + s.Pe;
   const uint32_t c0 = J0 >> 6, c1 = (J1 + 63) >> 6, ncw = c1 - c0;
-  const SecView v = open_section(D, b, LV, s.npts);
-  if (!v.ok) {
-    if (threadIdx.x == 0) set_status(D, -4);
-    return;
-  }
   const uint32_t wave = wave_index();
   const int lane = lane_id();
   const uint32_t n1 = (uint32_t)g.n[1], n2 = (uint32_t)g.n[2];
@@ -653,16 +693,19 @@ __device__ __forceinline__ void decode_tile(const DecPlan &D) {
   const uint32_t zl0 = (bp.o[0] >> (LV + 1)) + w2, oy1 = bp.o[1] >> (LV + 1), ox1 = bp.o[2] >> (LV + 1);
   const uint32_t gy = (bp.hi[1] >> (LV + 1)) - oy1 + 1, gx = (bp.hi[2] >> (LV + 1)) - ox1 + 1;
   const uint32_t np = zl0 + 1 < h0 ? 2u : 1u;
+  // The loads overlap: the parent planes first (rows past the block and
+  // lanes past a row load, and later store, a copy of the last one; without
+  // an upper plane the second staged plane is a copy of the first and is
+  // never read), then the section's table entry, then together the section's
+  // header, its tile table and the chunk headers of the range (offsets from
+  // the block's geometry), then the exact masks; the parents reach LDS last.
+  const uint32_t xl1 = min((uint32_t)lane, gx - 1);
+  constexpr int kRP = (TD::Side + kWaves - 1) / kWaves;
+  float tv[2][kRP];
   {
-    // the parent planes: rows past the block and lanes past a row load (and
-    // store) a copy of the last one; without an upper plane the second
-    // staged plane is a copy of the first and is never read.  32-bit offsets
-    // from the block's first parent, loads of both planes issued first.
     const char *__restrict__ g1b =
         reinterpret_cast<const char *>(D.gp[LV + 1] + ((size_t)zl0 * h1 + oy1) * h2 + ox1);
-    const uint32_t xl1 = min((uint32_t)lane, gx - 1), planeB = (np - 1) * h1 * h2 * 4u, rowB1 = h2 * 4u;
-    constexpr int kRP = (TD::Side + kWaves - 1) / kWaves;
-    float tv[2][kRP];
+    const uint32_t planeB = (np - 1) * h1 * h2 * 4u, rowB1 = h2 * 4u;
 #pragma unroll
     for (int pz = 0; pz < 2; pz++)
 #pragma unroll
@@ -670,13 +713,11 @@ __device__ __forceinline__ void decode_tile(const DecPlan &D) {
         const uint32_t yy = min(wave + (uint32_t)u * kWaves, gy - 1);
         tv[pz][u] = ldf(g1b, (uint32_t)pz * planeB + yy * rowB1 + xl1 * 4u);
       }
-#pragma unroll
-    for (int pz = 0; pz < 2; pz++)
-#pragma unroll
-      for (int u = 0; u < kRP; u++) {
-        const uint32_t yy = min(wave + (uint32_t)u * kWaves, gy - 1);
-        sg[pz * TD::Plane + yy * TD::Side + xl1] = tv[pz][u];
-      }
+  }
+  const SecView v = open_section_early(D, b, LV, s.npts);
+  if (!v.ok) {
+    if (threadIdx.x == 0) set_status(D, -4);
+    return;
   }
   {
     // chunk headers of the (at most three) 64-chunk tiles of the range:
@@ -686,13 +727,15 @@ __device__ __forceinline__ void decode_tile(const DecPlan &D) {
     uint32_t bad = 0u;
     if (t <= ((c1 - 1) >> 6)) {
       const uint32_t c = t * 64 + (uint32_t)lane;
-      const uint8_t *tt = v.p + 16 + 12 * (uint64_t)t;
+      const uint8_t *tt = v.p + 16 + 12 * (uint64_t)t + vzero();
       const uint32_t tw = ld32(tt), te = ld32(tt + 4), tx = ld32(tt + 8);
       const uint32_t hb = c < v.nch ? v.p[v.A + c] : 0u;
+      const bool fok = sec_fields_ok(v, s.npts);
+      const uint64_t Moff = v.Poff + 8 * (uint64_t)v.W;
       const uint32_t w = hb & 31u, he = hb >> 7;
       const uint32_t wo = tw + wave_excl_sum(w), eo = te + wave_excl_sum(he);
-      const bool badl = (w > (uint32_t)kMaxW) || (hb & 0x60u) || (wo + w > v.W) || (he && eo >= v.NE);
-      const unsigned long long em = (he && !badl) ? ld64(v.p + v.Moff + 8 * (uint64_t)eo) : 0ull;
+      const bool badl = !fok || (w > (uint32_t)kMaxW) || (hb & 0x60u) || (wo + w > v.W) || (he && eo >= v.NE);
+      const unsigned long long em = (he && !badl) ? ld64(v.p + Moff + 8 * (uint64_t)eo) : 0ull;
       const uint32_t pc = (uint32_t)__popcll(em);
       const uint32_t xo = tx + wave_excl_sum(pc);
       bad = __ballot(badl || xo + pc > v.NX) != 0ull ? 1u : 0u;
@@ -712,6 +755,13 @@ __device__ __forceinline__ void decode_tile(const DecPlan &D) {
       cem[ncw] = 0ull;
     }
   }
+#pragma unroll
+  for (int pz = 0; pz < 2; pz++)
+#pragma unroll
+    for (int u = 0; u < kRP; u++) {
+      const uint32_t yy = min(wave + (uint32_t)u * kWaves, gy - 1);
+      sg[pz * TD::Plane + yy * TD::Side + xl1] = tv[pz][u];
+    }
   __syncthreads();
   const uint32_t hflags = sbad[0] | sbad[1] | sbad[2] | sbad[3];
   if (hflags & 1u) {
@@ -721,7 +771,11 @@ __device__ __forceinline__ void decode_tile(const DecPlan &D) {
   const bool tileE = (hflags & 2u) != 0;       // some chunk of the range has exact points
   const uint32_t xo0 = cxo[0];
   const char *__restrict__ payb = reinterpret_cast<const char *>(v.p + v.Poff);
-  const char *__restrict__ exb = reinterpret_cast<const char *>(v.p + v.Xoff);
+  // the header's fields as uniform values (they arrived before the barrier)
+  const uint32_t Wu = (uint32_t)__builtin_amdgcn_readfirstlane((int)v.W);
+  const uint32_t NEu = (uint32_t)__builtin_amdgcn_readfirstlane((int)v.NE);
+  const uint64_t Xoff = v.Poff + 8 * ((uint64_t)Wu + NEu);
+  const char *__restrict__ exb = reinterpret_cast<const char *>(v.p + Xoff);
   // ---- stage the range's exact values (one coalesced pass) and unpack the
   // codes of the pair's points two chunks at a time: for the pair of chunks
   // k = 2i, 2i + 1 of the range, lane l < 32 takes codes 2l, 2l + 1 of chunk
@@ -738,8 +792,8 @@ __device__ __forceinline__ void decode_tile(const DecPlan &D) {
     const uint32_t npair = (ncw + 1) / 2;
     // the payload and the byte offset of its last word (a section without
     // payload: its own first word, read and not used)
-    const char *__restrict__ pldb = v.W ? payb : reinterpret_cast<const char *>(v.p);
-    const uint32_t plast = v.W ? 8u * v.W - 4u : 0u;
+    const char *__restrict__ pldb = Wu ? payb : reinterpret_cast<const char *>(v.p);
+    const uint32_t plast = Wu ? 8u * Wu - 4u : 0u;
     for (uint32_t i0 = wave; i0 < npair; i0 += kD0Group * kWaves) {
       uint32_t wu[kD0Group], bu[kD0Group], lo[kD0Group], hi[kD0Group];
 #pragma unroll
@@ -788,7 +842,7 @@ __device__ __forceinline__ void decode_tile(const DecPlan &D) {
   t.cxo = cxo;
   t.cem = cem;
   t.xl = xl;
-  t.xs = v.p + v.Xoff;
+  t.xs = v.p + Xoff;
   t.J0 = J0;
   t.c0 = c0;
   t.xo0 = xo0;
