@@ -677,34 +677,41 @@ __device__ __forceinline__ float lds_at(const char *base, uint32_t off) {
   return *reinterpret_cast<const float *>(base + off);
 }
 
-// Multilinear midpoint of a point of the tile from the staged level-1
-// planes, any parity (used for the few C points).
+// Multilinear midpoint of a point of the tile from the staged parent
+// planes (rows of Side, planes of Plane floats), any parity (used for the
+// few column points).
+template <int Side, int Plane>
 __device__ __forceinline__ float t0_pred_any(const float *sg, bool zu, uint32_t v, uint32_t u, uint32_t gy,
                                              uint32_t gx) {
   const uint32_t yl = v >> 1, xl = u >> 1;
   const bool yu = (v & 1u) && yl + 1 < gy, xu = (u & 1u) && xl + 1 < gx;
   const uint32_t yb = yu ? yl + 1 : yl, xb = xu ? xl + 1 : xl;
-  const float *p1 = zu ? sg + kT0Plane : sg;
-  return midpoint8(sg[yl * kT0Side + xl], sg[yl * kT0Side + xb], sg[yb * kT0Side + xl], sg[yb * kT0Side + xb],
-                   p1[yl * kT0Side + xl], p1[yl * kT0Side + xb], p1[yb * kT0Side + xl], p1[yb * kT0Side + xb], zu,
-                   yu, xu);
+  const float *p1 = zu ? sg + Plane : sg;
+  return midpoint8(sg[yl * Side + xl], sg[yl * Side + xb], sg[yb * Side + xl], sg[yb * Side + xb],
+                   p1[yl * Side + xl], p1[yl * Side + xb], p1[yb * Side + xl], p1[yb * Side + xb], zu, yu, xu);
 }
 
 // Level LV (0 or 1) of 64-cell blocks by pairs of planes of the level's
-// grid.  Level 1 is level 0's pattern on every other point of the field:
-// rows of at most 33 points (lanes past 33 idle), x loads at a stride of two,
-// parents from the level-2 grid; its reconstructed points, and the level-2
-// points of the pair's even plane that the level-1 grid carries over, are
-// written into the level-1 grid for level 0 to predict from.
+// grid.  Level 1 is level 0's pattern on every other point of the field,
+// x loads at a stride of two, parents from the level-2 grid; its rows hold
+// at most 33 points, so a wave instruction takes two rows (lanes 0-31 and
+// 32-63, the points u < 32; the points u = 32 go one row per lane, as level
+// 0's u = 64) and four of the rows of odd points only.  Its reconstructed
+// points, and the level-2 points of the pair's even plane that the level-1
+// grid carries over, are written into the level-1 grid for level 0 to
+// predict from.
 template <int LV>
 struct TileDims {
   static constexpr int S = 1 << LV;                       // field points per level step
   static constexpr int Side = (64 >> (LV + 1)) + 1;       // parent points per axis of a block
   static constexpr int Plane = LV == 0 ? 1152 : 320;      // staged parent plane stride (floats)
   static constexpr int Codes = LV == 0 ? 7361 + 63 : 1889 + 63;   // most section points of a pair + a chunk tail
-  static constexpr int A = LV == 0 ? 5 : 3;               // even-row pairs of the even plane per wave
-  static constexpr int B = LV == 0 ? 8 : 4;               // odd rows of the even plane per wave
-  static constexpr int M = LV == 0 ? 9 : 5;               // row pairs of the odd plane per wave
+  static constexpr int R = LV == 0 ? 1 : 2;               // full rows per wave instruction
+  static constexpr int LW = 64 / R;                       // lanes (points u < LW) of a full row
+  static constexpr int QA = 2 * R;                        // rows of odd points (A rows) per wave instruction
+  static constexpr int A = LV == 0 ? 5 : 2;               // A-row groups of the even plane per wave
+  static constexpr int B = LV == 0 ? 8 : 2;               // odd-row groups of the even plane per wave
+  static constexpr int M = LV == 0 ? 9 : 3;               // row-pair groups of the odd plane per wave
 };
 
 template <int KB, bool LL, int LV>
@@ -815,35 +822,49 @@ __device__ __forceinline__ void encode_tile(const EncPlan &P) {
   // and the chunk after the tile's last, which the packing of an odd
   // count of chunks reads as the second of a pair
   if (threadIdx.x < 64) t.sc[cend * 64 + threadIdx.x] = 0;
-  // Every x row a wave needs is loaded before the barrier: A rows v = 4a +
-  // 2*half (odd u = 2i + 1), B rows v = 2f + 1, C/D rows 2m and 2m + 1.  A
-  // row past the block or a lane past a row loads a copy of a point inside.
+  // Every x row a wave needs is loaded before the barrier.  Lanes: an A
+  // group holds QA rows of odd points (v = 2 (QA a + qa), u = 2 i + 1, lane
+  // LA qa + i); a B or C/D group holds R full rows (row R g + hr, u < LW,
+  // lane LW hr + uu).  A row past the block or a lane past a row loads (and
+  // codes) a copy of a point inside, whose counts are masked.
   constexpr int kA = TD::A, kB = TD::B, kM = TD::M;
+  constexpr uint32_t R = TD::R, LW = TD::LW, QA = TD::QA, LA = 64 / QA;
   const uint32_t half = (uint32_t)lane >> 5, ir = (uint32_t)lane & 31u;
-  const uint32_t iA = min(ir, rowE > 0 ? rowE - 1 : 0u);
-  const uint32_t nA = rowE > 0 ? ((my + 1) / 2 + 1) / 2 : 0u, nB = my / 2, nM = has_odd ? (my + 1) / 2 : 0u;
-  const uint32_t u = min((uint32_t)lane, mx - 1);
+  const uint32_t qa = (uint32_t)lane / LA, ia = (uint32_t)lane % LA;
+  const uint32_t hr = R == 1 ? 0u : (uint32_t)lane / LW, uu = R == 1 ? (uint32_t)lane : (uint32_t)lane % LW;
+  const uint32_t iA = min(ia, rowE > 0 ? rowE - 1 : 0u);
+  const uint32_t nEv = (my + 1) / 2;           // even rows of the even plane
+  const uint32_t nA = rowE > 0 ? (nEv + QA - 1) / QA : 0u, nB = my / 2, nM = has_odd ? (my + 1) / 2 : 0u;
+  const uint32_t u = min(uu, mx - 1);
   const uint32_t lxA = (2 * iA + 1) * 4u * S, lx = u * 4u * S;
+  // the row of A group a for this lane (a sub-row past the plane: the group's first)
+  auto a_row = [&](uint32_t a) {
+    const uint32_t v = 2 * (QA * a + qa);
+    return v < my ? v : 2 * QA * a;
+  };
+  // lanes of sub-row h of a group of n sub-rows (wave-uniform masks)
+  auto sub_lanes = [](uint32_t h, uint32_t n) -> uint64_t {
+    return n == 1 ? ~0ull : (((1ull << (64 / n)) - 1ull) << (h * (64 / n)));
+  };
   float xa[kA], xb[kB], xc[kM], xd[kM];
   if (nA > 0) {
 #pragma unroll
     for (int k = 0; k < kA; k++) {
       const uint32_t a = min(wave + (uint32_t)k * kWaves, nA - 1);
-      const uint32_t vh = 4 * a + 2 * half < my ? 2 * half : 0u;
-      xa[k] = ldf(xbase, xe0 + (4 * a + vh) * rowB + lxA);
+      xa[k] = ldf(xbase, xe0 + a_row(a) * rowB + lxA);
     }
   }
   if (nB > 0) {
 #pragma unroll
     for (int k = 0; k < kB; k++) {
-      const uint32_t f = min(wave + (uint32_t)k * kWaves, nB - 1);
+      const uint32_t f = min(R * (wave + (uint32_t)k * kWaves) + hr, nB - 1);
       xb[k] = ldf(xbase, xe0 + (2 * f + 1) * rowB + lx);
     }
   }
   if (nM > 0) {
 #pragma unroll
     for (int k = 0; k < kM; k++) {
-      const uint32_t m = min(wave + (uint32_t)k * kWaves, nM - 1);
+      const uint32_t m = min(R * (wave + (uint32_t)k * kWaves) + hr, nM - 1);
       xc[k] = ldf(xbase, xo0 + 2 * m * rowB + lx);
       xd[k] = ldf(xbase, xo0 + min(2 * m + 1, my - 1) * rowB + lx);
     }
@@ -856,36 +877,40 @@ __device__ __forceinline__ void encode_tile(const EncPlan &P) {
     for (uint32_t r = wave; 2 * r < my; r += kWaves)
       if (ir < gx && half == 0) stf(glb, 2 * r * grow + 2 * ir * 4u, sg[r * TD::Side + ir]);
   }
-  // ---- A rows: even plane, v = 4a + 2*half, u = 2i + 1
+  // ---- A rows: even plane, even rows v, odd u = 2i + 1
   if (nA > 0) {
     const bool xav = iA + 1 < gx;
-    const uint64_t lane_in = __ballot(ir < rowE && (2 * ir + 1) * S < ownx);
+    const uint64_t lane_inA = __ballot(ia < rowE && (2 * ia + 1) * S < ownx);
     const uint32_t lg = iA * 4u;
 #pragma unroll
     for (int k = 0; k < kA; k++) {
       const uint32_t a = wave + (uint32_t)k * kWaves;
       if (a >= nA) break;
-      const uint32_t v = 4 * a + 2 * half;
-      const uint32_t vc = v < my ? v : v - 2;
+      const uint32_t vc = a_row(a);
       const uint32_t ga = (vc >> 1) * (TD::Side * 4u) + lg;
       const float p = t0_xavg(lds_at(sgb, ga), lds_at(sgb, ga + 4), xav);
       const uint32_t jA = J0 + (vc >> 1) * RP;
-      const uint64_t hm0 = (4 * a < my && 4 * a * S < owny) ? 0x00000000ffffffffull : 0ull;
-      const uint64_t hm1 = (4 * a + 2 < my && (4 * a + 2) * S < owny) ? 0xffffffff00000000ull : 0ull;
-      t0_finish<KB, LL, GW>(tq, iso, xa[k], p, we * S < ownz ? lane_in & (hm0 | hm1) : 0ull, jA, iA, t, glb,
-                            vc * grow + (2 * iA + 1) * 4u);
+      uint64_t rows = 0;
+#pragma unroll
+      for (uint32_t h = 0; h < QA; h++) {
+        const uint32_t vh = 2 * (QA * a + h);
+        if (vh < my && vh * S < owny) rows |= sub_lanes(h, QA);
+      }
+      const uint64_t cm = we * S < ownz ? lane_inA & rows : 0ull;
+      t0_finish<KB, LL, GW>(tq, iso, xa[k], p, cm, jA, iA, t, glb, vc * grow + (2 * iA + 1) * 4u);
     }
   }
   const uint32_t lx0 = u >> 1;
   const bool xav = (u & 1u) && lx0 + 1 < gx;
-  const uint64_t lane_in = __ballot((uint32_t)lane < mx && (uint32_t)lane * S < ownx);
+  const uint64_t lane_in = __ballot(uu < mx && uu * S < ownx);
   const uint32_t lg = lx0 * 4u;
   constexpr uint32_t kRow = TD::Side * 4u, kPl = TD::Plane * 4u;
   // ---- B rows: odd rows v = 2f + 1 of the even plane (z even, y odd)
 #pragma unroll
   for (int k = 0; k < kB; k++) {
-    const uint32_t f = wave + (uint32_t)k * kWaves;
-    if (f >= nB) break;
+    const uint32_t f0 = R * (wave + (uint32_t)k * kWaves);
+    if (f0 >= nB) break;
+    const uint32_t f = R == 1 ? f0 : min(f0 + hr, nB - 1);
     const bool yu = f + 1 < gy;
     const uint32_t ga = f * kRow + lg;
     // the row's parents read together, before any value is used
@@ -897,8 +922,12 @@ __device__ __forceinline__ void encode_tile(const EncPlan &P) {
     hold(pb);
     const float p = yu ? pb : A;
     const uint32_t jr = J0 + f * RP + rowE;
-    t0_finish<KB, LL, GW>(tq, iso, xb[k], p, (we * S < ownz && (2 * f + 1) * S < owny) ? lane_in : 0ull, jr, u, t,
-                          glb, (2 * f + 1) * grow + u * 4u);
+    uint64_t rows = 0;
+#pragma unroll
+    for (uint32_t h = 0; h < R; h++)
+      if (f0 + h < nB && (2 * (f0 + h) + 1) * S < owny) rows |= sub_lanes(h, R);
+    const uint64_t cm = we * S < ownz ? lane_in & rows : 0ull;
+    t0_finish<KB, LL, GW>(tq, iso, xb[k], p, cm, jr, u, t, glb, (2 * f + 1) * grow + u * 4u);
   }
   // ---- C and D rows: the odd plane's rows 2m (y even) and 2m + 1 (y odd)
   {
@@ -906,8 +935,16 @@ __device__ __forceinline__ void encode_tile(const EncPlan &P) {
     const bool zown = (we + 1) * S < ownz;
 #pragma unroll
     for (int k = 0; k < kM; k++) {
-      const uint32_t m = wave + (uint32_t)k * kWaves;
-      if (m >= nM) break;
+      const uint32_t m0 = R * (wave + (uint32_t)k * kWaves);
+      if (m0 >= nM) break;
+      const uint32_t m = R == 1 ? m0 : min(m0 + hr, nM - 1);
+      uint64_t rowsC = 0, rowsD = 0;
+#pragma unroll
+      for (uint32_t h = 0; h < R; h++) {
+        const uint32_t mh = m0 + h;
+        if (mh < nM && 2 * mh * S < owny) rowsC |= sub_lanes(h, R);
+        if (mh < nM && 2 * mh + 1 < my && (2 * mh + 1) * S < owny) rowsD |= sub_lanes(h, R);
+      }
       const uint32_t ga = m * kRow + lg;
       // the parents of both rows read together, before any value is used
       // (rows m + 1 past the plane read the staging's spare floats, unused)
@@ -921,9 +958,9 @@ __device__ __forceinline__ void encode_tile(const EncPlan &P) {
       hold(pc);
       const float p = zu ? pc : A;
       const uint32_t jc = jo + 2 * m * mx;
-      t0_finish<KB, LL, GW>(tq, iso, xc[k], p, (zown && 2 * m * S < owny) ? lane_in : 0ull, jc, u, t, glb,
+      t0_finish<KB, LL, GW>(tq, iso, xc[k], p, zown ? lane_in & rowsC : 0ull, jc, u, t, glb,
                             gplane + 2 * m * grow + u * 4u);
-      if (2 * m + 1 < my) {
+      if (R == 1 ? 2 * m + 1 < my : 2 * m0 + 1 < my) {
         const bool yu = m + 1 < gy;
         const float B = t0_xavg(b0, b1, xav);
         const float D = t0_xavg(d0, d1, xav);
@@ -934,23 +971,33 @@ __device__ __forceinline__ void encode_tile(const EncPlan &P) {
         p1 = yu ? p1 : Cc;
         float pd = avg2(p0, p1);
         hold(pd);
-        const float p2 = zu ? pd : p0;
-        t0_finish<KB, LL, GW>(tq, iso, xd[k], p2, (zown && (2 * m + 1) * S < owny) ? lane_in : 0ull, jc + mx, u, t,
-                              glb, gplane + (2 * m + 1) * grow + u * 4u);
+        float p2 = zu ? pd : p0;
+        uint32_t jd = jc + mx, gd = gplane + (2 * m + 1) * grow + u * 4u;
+        if (R > 1) {
+          // a lane whose row 2m + 1 is past the plane codes its row 2m again
+          // (its x loads are row 2m's): same code into the same slot, not
+          // counted
+          const bool dok = 2 * m + 1 < my;
+          p2 = dok ? p2 : p;
+          jd = dok ? jd : jc;
+          gd = dok ? gd : gplane + 2 * m * grow + u * 4u;
+        }
+        t0_finish<KB, LL, GW>(tq, iso, xd[k], p2, zown ? lane_in & rowsD : 0ull, jd, u, t, glb, gd);
       }
     }
   }
-  // ---- column: the points u = 64 of the full rows (65-point rows, level 0)
+  // ---- column: the points u = LW of the full rows (rows of LW + 1 points)
   const uint32_t nF = nB + (has_odd ? my : 0u);
-  if (LV == 0 && mx == 65) {
+  if (mx == LW + 1) {
     for (uint32_t c0 = wave * 64; c0 < nF; c0 += kWaves * 64) {
       const uint32_t fr = c0 + (uint32_t)lane, f = min(fr, nF - 1);
       const bool ev = f < nB;
       const uint32_t w = ev ? we : we + 1, v = ev ? 2 * f + 1 : f - nB;
-      const float x = ldf(xbase, ((w * n1 + bp.o[1] + v) * n2 + bp.o[2] + 64u) * 4u);
-      const float p = t0_pred_any(sg, (w & 1u) && zu, v, 64u, gy, gx);
-      const uint32_t j = ev ? J0 + (v >> 1) * RP + rowE + 64u : J0 + s.Pe + v * mx + 64u;
-      t0_finish<KB, LL>(tq, iso, x, p, __ballot(fr < nF && w < ownz && v < owny && 64u < ownx), 0u, j, t);
+      const float x = ldf(xbase, ((w * S * n1 + bp.o[1] + v * S) * n2 + bp.o[2] + LW * S) * 4u);
+      const float p = t0_pred_any<TD::Side, TD::Plane>(sg, (w & 1u) && zu, v, LW, gy, gx);
+      const uint32_t j = ev ? J0 + (v >> 1) * RP + rowE + LW : J0 + s.Pe + v * mx + LW;
+      t0_finish<KB, LL, GW>(tq, iso, x, p, __ballot(fr < nF && w * S < ownz && v * S < owny && LW * S < ownx), 0u, j,
+                            t, glb, (ev ? 0u : gplane) + v * grow + LW * 4u);
     }
   }
   // ---- the tail of the last chunk (the next planes' first points; more
@@ -959,11 +1006,11 @@ __device__ __forceinline__ void encode_tile(const EncPlan &P) {
   // grid (the next pairs count and write them)
   if (jend > J1 && jbase < jend && wave == kWaves - 1) {
     const uint32_t j = min(J1 + (uint32_t)lane, jend - 1);
-    uint32_t w, v, uu;
-    sec_point24(s, rc, j, w, v, uu);
-    const float x = ldf(xbase, ((w * S * n1 + bp.o[1] + v * S) * n2 + bp.o[2] + uu * S) * 4u);
+    uint32_t w, v, uu2;
+    sec_point24(s, rc, j, w, v, uu2);
+    const float x = ldf(xbase, ((w * S * n1 + bp.o[1] + v * S) * n2 + bp.o[2] + uu2 * S) * 4u);
     const float p = predict(P.G + P.g_off[LV + 1], h0, h1, h2, LV, bp.o[0] + w * S, bp.o[1] + v * S,
-                            bp.o[2] + uu * S);
+                            bp.o[2] + uu2 * S);
     t0_finish<KB, LL>(tq, iso, x, p, 0ull, 0u, j, t);
   }
   __syncthreads();
