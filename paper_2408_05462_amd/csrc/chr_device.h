@@ -622,6 +622,21 @@ struct OpMin { __device__ uint32_t operator()(uint32_t a, uint32_t b) const { re
 struct OpMax { __device__ uint32_t operator()(uint32_t a, uint32_t b) const { return a > b ? a : b; } };
 struct OpAdd { __device__ uint32_t operator()(uint32_t a, uint32_t b) const { return a + b; } };
 __device__ inline uint32_t wave_or_dpp(uint32_t v) { return wave_reduce_dpp(v, OpOr(), 0u); }
+// Exclusive prefix sum over the lanes of a wave through DPP: an inclusive
+// scan within each 16-lane row (shifts by 1, 2, 4, 8; lanes shifted in from
+// before the row read 0), then row 0's total into row 1 and row 2's into row
+// 3 (broadcast of lane 15), then the first half's total into the second
+// (broadcast of lane 31); no LDS round trip.
+__device__ inline uint32_t wave_excl_sum_dpp(uint32_t v) {
+  uint32_t x = v;
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);  // row_shr:1
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);  // row_shr:2
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);  // row_shr:4
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);  // row_shr:8
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return x - v;
+}
 __device__ inline uint32_t wave_min_dpp(uint32_t v) { return wave_reduce_dpp(v, OpMin(), 0xffffffffu); }
 __device__ inline uint32_t wave_max_dpp(uint32_t v) { return wave_reduce_dpp(v, OpMax(), 0u); }
 __device__ inline uint32_t wave_sum_dpp(uint32_t v) { return wave_reduce_dpp(v, OpAdd(), 0u); }

@@ -173,7 +173,7 @@ __device__ void dec_tile(const DecPlan &D, const SecView &v, int l, const int64_
   const uint32_t tw = ld32(tt), te = ld32(tt + 4), tx = ld32(tt + 8);
   const uint32_t hb = c < v.nch ? v.p[v.A + c] : 0u;
   const uint32_t w = hb & 31u, he = hb >> 7;
-  const uint32_t wo = tw + wave_excl_sum(w), eo = te + wave_excl_sum(he);
+  const uint32_t wo = tw + wave_excl_sum_dpp(w), eo = te + wave_excl_sum_dpp(he);
   // structural checks: widths, exact masks and values stay inside the section
   const uint32_t bad_l = (w > (uint32_t)kMaxW) || (hb & 0x60u) || (wo + w > v.W) || (he && eo >= v.NE);
   if (__ballot(bad_l)) {
@@ -182,7 +182,7 @@ __device__ void dec_tile(const DecPlan &D, const SecView &v, int l, const int64_
   }
   const uint64_t em = he ? ld64(v.p + v.Moff + 8 * (uint64_t)eo) : 0ull;
   const uint32_t pc = (uint32_t)__popcll(em);
-  const uint32_t xo = tx + wave_excl_sum(pc);
+  const uint32_t xo = tx + wave_excl_sum_dpp(pc);
   if (__ballot(xo + pc > v.NX)) {
     set_status(D, -4);
     return;
@@ -440,7 +440,7 @@ __device__ __forceinline__ void decode_fast(const DecPlan &D) {
   const uint32_t tw = ld32(tt), te = ld32(tt + 4), tx = ld32(tt + 8);
   const uint32_t hb = c < v.nch ? v.p[v.A + c] : 0u;
   const uint32_t w = hb & 31u, he = hb >> 7;
-  const uint32_t wo = tw + wave_excl_sum(w), eo = te + wave_excl_sum(he);
+  const uint32_t wo = tw + wave_excl_sum_dpp(w), eo = te + wave_excl_sum_dpp(he);
   const uint32_t bad_l = (w > (uint32_t)kMaxW) || (hb & 0x60u) || (wo + w > v.W) || (he && eo >= v.NE);
   if (__ballot(bad_l)) {
     set_status(D, -4);
@@ -448,7 +448,7 @@ __device__ __forceinline__ void decode_fast(const DecPlan &D) {
   }
   const uint64_t em = he ? ld64(v.p + v.Moff + 8 * (uint64_t)eo) : 0ull;
   const uint32_t pc = (uint32_t)__popcll(em);
-  const uint32_t xo = tx + wave_excl_sum(pc);
+  const uint32_t xo = tx + wave_excl_sum_dpp(pc);
   if (__ballot(xo + pc > v.NX)) {
     set_status(D, -4);
     return;
@@ -665,8 +665,10 @@ __device__ __forceinline__ void decode_tile(const DecPlan &D) {
   // pair's first and last chunks unpack whole (at most 63 points before J0
   // and 63 after J1), and a last pair of chunks may end one chunk past them
   __shared__ __align__(4) int16_t scs[TD::Codes + 192];
-  // chunk headers, plus a zero-width entry for the chunk past the range
-  __shared__ uint32_t cwo[TD::Chunks + 1], cxo[TD::Chunks + 1], cwb[TD::Chunks + 1];
+  // chunk headers: width | payload byte offset << 5 (zero-width entries for
+  // the 64 chunks past the range, which the unpacking's last pairs read),
+  // exact-value offsets and exact masks (a zero entry past the range)
+  __shared__ uint32_t cwh[TD::Chunks + 64], cxo[TD::Chunks + 1];
   __shared__ unsigned long long cem[TD::Chunks + 1];
   __shared__ float xl[kD0Xcap];
   __shared__ uint32_t sbad[kWaves];
@@ -733,27 +735,23 @@ __device__ __forceinline__ void decode_tile(const DecPlan &D) {
       const bool fok = sec_fields_ok(v, s.npts);
       const uint64_t Moff = v.Poff + 8 * (uint64_t)v.W;
       const uint32_t w = hb & 31u, he = hb >> 7;
-      const uint32_t wo = tw + wave_excl_sum(w), eo = te + wave_excl_sum(he);
+      const uint32_t wo = tw + wave_excl_sum_dpp(w), eo = te + wave_excl_sum_dpp(he);
       const bool badl = !fok || (w > (uint32_t)kMaxW) || (hb & 0x60u) || (wo + w > v.W) || (he && eo >= v.NE);
       const unsigned long long em = (he && !badl) ? ld64(v.p + Moff + 8 * (uint64_t)eo) : 0ull;
       const uint32_t pc = (uint32_t)__popcll(em);
-      const uint32_t xo = tx + wave_excl_sum(pc);
+      const uint32_t xo = tx + wave_excl_sum_dpp(pc);
       bad = __ballot(badl || xo + pc > v.NX) != 0ull ? 1u : 0u;
       const bool in = c >= c0 && c < c1;
       bad |= __ballot(in && em != 0ull) != 0ull ? 2u : 0u;
       if (in) {
-        cwb[c - c0] = w;
-        cwo[c - c0] = wo;
+        cwh[c - c0] = w | (8u * wo) << 5;
         cxo[c - c0] = xo;
         cem[c - c0] = em;
       }
     }
     if (lane == 0) sbad[wave] = bad;
-    if (threadIdx.x == 0) {
-      cwb[ncw] = 0u;
-      cwo[ncw] = 0u;
-      cem[ncw] = 0ull;
-    }
+    if (threadIdx.x < 64) cwh[ncw + threadIdx.x] = 0u;
+    if (threadIdx.x == 0) cem[ncw] = 0ull;
   }
 #pragma unroll
   for (int pz = 0; pz < 2; pz++)
@@ -798,15 +796,15 @@ __device__ __forceinline__ void decode_tile(const DecPlan &D) {
       uint32_t wu[kD0Group], bu[kD0Group], lo[kD0Group], hi[kD0Group];
 #pragma unroll
       for (int u = 0; u < kD0Group; u++) {
-        // the lane's chunk (past the range the zero-width entry), and the
-        // two payload words its codes can span, loaded without a branch: at
+        // the lane's chunk (past the range a zero-width entry), and the two
+        // payload words its codes can span, loaded without a branch: at
         // offsets clamped to the payload's last word, which changes no word
         // a code uses (a zero-width chunk, or a second word its codes do not
         // reach, reads a word of the payload that is then not used)
-        const uint32_t kc = min(2 * (i0 + (uint32_t)u * kWaves) + hf, ncw);
-        const uint32_t w = cwb[kc], wo = cwo[kc];
+        const uint32_t hw = cwh[2 * (i0 + (uint32_t)u * kWaves) + hf];
+        const uint32_t w = hw & 31u;
         const uint32_t bit = mul24v(2 * lh, w);
-        const uint32_t o0 = min(8u * wo + 4u * (bit >> 5), plast);
+        const uint32_t o0 = min((hw >> 5) + ((bit >> 3) & ~3u), plast);
         wu[u] = w;
         bu[u] = bit;
         lo[u] = ldu(pldb, o0);
@@ -1133,11 +1131,11 @@ __global__ __launch_bounds__(kTopBS) void k_decode_top(DecPlan D) {
           const uint32_t tw = ld32(tt), te = ld32(tt + 4), tx = ld32(tt + 8);
           const uint32_t hb = c < v.nch ? v.p[v.A + c] : 0u;
           const uint32_t w = hb & 31u, he = hb >> 7;
-          const uint32_t wo = tw + wave_excl_sum(w), eo = te + wave_excl_sum(he);
+          const uint32_t wo = tw + wave_excl_sum_dpp(w), eo = te + wave_excl_sum_dpp(he);
           const bool badl = (w > (uint32_t)kMaxW) || (hb & 0x60u) || (wo + w > v.W) || (he && eo >= v.NE);
           const unsigned long long em = (he && !badl) ? ld64(v.p + v.Moff + 8 * (uint64_t)eo) : 0ull;
           const uint32_t pcnt = (uint32_t)__popcll(em);
-          const uint32_t xo = tx + wave_excl_sum(pcnt);
+          const uint32_t xo = tx + wave_excl_sum_dpp(pcnt);
           bad = __ballot(badl || xo + pcnt > v.NX) != 0ull;
           if (c < nch) {
             const uint32_t gi = base[l] / 64 + c;
