@@ -1452,14 +1452,14 @@ __global__ __launch_bounds__(kBS) void k_sec_table(EncPlan P) {
 // (first workgroups) to level 0.  A section that does not fit the capacity is
 // not written (the result then reports the required size).
 __global__ __launch_bounds__(kBS) void k_pack(EncPlan P) {
-  __shared__ uint16_t s_own_all[kWaves][64 * kMaxW];  // chunk (within the tile) of each payload word
-  __shared__ uint32_t s_pw_all[kWaves][64];
+  // source of each payload word of the tile: its chunk (within the tile)
+  // times 16 plus its place in the chunk's slot
+  __shared__ uint16_t s_src_all[kWaves][64 * kMaxW];
   const Geo &g = P.g;
   const int L = g.nL - 1;
   const int lane = lane_id();
   const uint32_t wave = wave_index();
-  uint16_t *s_own = s_own_all[wave];
-  uint32_t *s_pw = s_pw_all[wave];
+  uint16_t *s_src = s_src_all[wave];
   // one wave per tile of 64 chunks (tiles of every section in level-major order)
   const int64_t wg = (int64_t)blockIdx.x * kWaves + wave;
   if (wg >= P.pack_base[0] + g.nblocks * P.pack_gpb[0]) return;
@@ -1512,10 +1512,9 @@ __global__ __launch_bounds__(kBS) void k_pack(EncPlan P) {
       m[0] = (uint32_t)em;
       m[1] = (uint32_t)(em >> 32);
     }
-    for (uint32_t k = 0; k < cc.x; k++) s_own[pw + k] = (uint16_t)lane;
+    for (uint32_t k = 0; k < cc.x; k++) s_src[pw + k] = (uint16_t)(lane * 16 + k);
   }
-  s_pw[lane] = pw;
-  const uint32_t tot = __shfl(pw + cc.x, (int)tn - 1, kWave);  // payload words of the tile
+  const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)(pw + cc.x), (int)tn - 1);  // payload words of the tile
   const uint32_t base = cur.x - a.x;                            // (lane 0's) before the tile
   const uint32_t base0 = __builtin_amdgcn_readfirstlane(base);
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -1523,10 +1522,8 @@ __global__ __launch_bounds__(kBS) void k_pack(EncPlan P) {
   // payload: 8-byte words of the tile in stream order
   const unsigned long long *__restrict__ pay = reinterpret_cast<const unsigned long long *>(P.pay);
   unsigned long long *__restrict__ dst = reinterpret_cast<unsigned long long *>(out + Poff) + base0;
-  for (uint32_t u = (uint32_t)lane; u < tot; u += kWave) {
-    const uint32_t c = s_own[u];
-    dst[u] = pay[(slot0 + c) * 16 + (u - s_pw[c])];
-  }
+  const unsigned long long *__restrict__ pays = pay + slot0 * 16;
+  for (uint32_t u = (uint32_t)lane; u < tot; u += kWave) dst[u] = pays[s_src[u]];
   // exact values of the chunks that have any, one chunk at a time
   const uint32_t *__restrict__ exv = reinterpret_cast<const uint32_t *>(P.exv);
   uint32_t *xo = reinterpret_cast<uint32_t *>(out + Xoff);
@@ -1535,11 +1532,13 @@ __global__ __launch_bounds__(kBS) void k_pack(EncPlan P) {
   while (mx) {
     const int c = __builtin_ctzll(mx);
     mx &= mx - 1;
-    const uint32_t nx = __shfl(cc.z, c, kWave), pxc = __shfl(px, c, kWave);
-    if (__shfl(cc.w, c, kWave)) {
+    const uint32_t nx = (uint32_t)__builtin_amdgcn_readlane((int)cc.z, c);
+    const uint32_t pxc = (uint32_t)__builtin_amdgcn_readlane((int)px, c);
+    if (__builtin_amdgcn_readlane((int)cc.w, c)) {
       // stored at their lanes: lane i's value is the popcount(mask below i)-th
-      const unsigned long long emc = ((unsigned long long)(uint32_t)__shfl((int)(uint32_t)(em >> 32), c, kWave) << 32) |
-                                     (uint32_t)__shfl((int)(uint32_t)em, c, kWave);
+      const unsigned long long emc =
+          ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(em >> 32), c) << 32) |
+          (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)em, c);
       if ((emc >> lane) & 1ull) xo[pxc + lanes_below(emc)] = exv[(slot0 + c) * 64 + lane];
     } else if ((uint32_t)lane < nx) {
       xo[pxc + lane] = exv[(slot0 + c) * 64 + lane];
