@@ -182,3 +182,50 @@ def test_serve_cancel_and_corrupt_stream(world):
         s.release(rid)
     assert s.stats()["pool_used"] == 0
     s.close()
+
+
+def test_serve_64cell_blocks_matches_oracle():
+    """Streams of 64-cell blocks, which the server reconstructs with the
+    plane-pair kernels (level 0) restricted to the blocks a group's isovalues
+    need, the skipped blocks filled; ragged last blocks on every axis, random
+    isovalues, so that most groups skip blocks next to reconstructed ones,
+    level-0 and level-1 requests, groups of up to four.  Every mesh against
+    the oracle's, bit for bit."""
+    f = np.ascontiguousarray(inputs.grf(193, 0.35)[:97, :130, :193])
+    rng = np.random.default_rng(17)
+    isos = [float(v) for v in np.quantile(f, [0.3, 0.7]).astype(np.float32)]
+    x = torch.from_numpy(f).to(DEV)
+    streams, ostreams = [], []
+    for rel in (1e-2, 1e-3):
+        e = inputs.abs_error_bound(rel, f)
+        c = api.compress(x, e, isos, levels=4, block=64)
+        ref = oracle.compress(f, e, isos, levels=4, block=64)
+        assert np.array_equal(c.stream.cpu().numpy(), ref["stream"]), rel
+        streams.append((e, c))
+        ostreams.append(ref["stream"])
+    reqs = []
+    for i in range(16):
+        k = float(np.float32(rng.uniform(np.quantile(f, 0.05), np.quantile(f, 0.95))))
+        t = int(rng.integers(0, 2))
+        level = 0 if i % 4 else 1
+        reqs.append((0, k, streams[t][0], level, t))
+    recon, refs = {}, []
+    for ds, k, acc, level, t in reqs:
+        if (t, level) not in recon:
+            recon[(t, level)] = oracle.decompress(ostreams[t], level)
+        v, tr, _, _ = oracle.mc(recon[(t, level)], k, spacing=float(1 << level))
+        refs.append((v, tr))
+    pool = torch.empty(1 << 30, dtype=torch.uint8, device=DEV)
+    s = api.Server(pool, slots=2, max_group=4)
+    for e, c in streams:
+        s.add_stream(0, c.info, c.stream)
+    print("64-cell blocks:", len(reqs), "requests", flush=True)
+    ids = [s.submit(ds, k, acc, level) for ds, k, acc, level, t in reqs]
+    s.drain(ids)
+    _check(s, ids, reqs, refs, "64-cell")
+    st = s.stats()
+    print("64-cell stats", st, flush=True)
+    assert st["groups"] < len(reqs)
+    for rid in ids:
+        s.release(rid)
+    s.close()
