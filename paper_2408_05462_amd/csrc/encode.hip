@@ -772,29 +772,25 @@ __device__ __forceinline__ void encode_tile(const EncPlan &P) {
   const uint32_t zl0 = (bp.o[0] >> (LV + 1)) + w2, oy1 = bp.o[1] >> (LV + 1), ox1 = bp.o[2] >> (LV + 1);
   const uint32_t gy = (bp.hi[1] >> (LV + 1)) - oy1 + 1, gx = (bp.hi[2] >> (LV + 1)) - ox1 + 1;
   const uint32_t np = zl0 + 1 < h0 ? 2u : 1u;
+  // The two parent planes: rows past the block and lanes past a row load
+  // (and store) a copy of the last one; without an upper plane the second
+  // staged plane is a copy of the first and is never read.  32-bit offsets
+  // from the block's first parent.  They are stored into LDS only after the
+  // x rows below are loaded, so that both sets of loads are in flight
+  // together.
+  const uint32_t pxl = min((uint32_t)lane, gx - 1);
+  constexpr int kRP = (TD::Side + kWaves - 1) / kWaves;
+  float tv[2][kRP];
   {
-    // rows past the block and lanes past a row load (and store) a copy of
-    // the last one; without an upper plane the second staged plane is a
-    // copy of the first and is never read.  32-bit offsets from the block's
-    // first parent, loads of both planes issued before the stores.
     const char *__restrict__ g1b =
         reinterpret_cast<const char *>(P.G + P.g_off[LV + 1] + ((size_t)zl0 * h1 + oy1) * h2 + ox1);
-    const uint32_t xl = min((uint32_t)lane, gx - 1), planeB = (np - 1) * h1 * h2 * 4u, rowB1 = h2 * 4u;
-    constexpr int kRP = (TD::Side + kWaves - 1) / kWaves;
-    float tv[2][kRP];
+    const uint32_t planeB = (np - 1) * h1 * h2 * 4u, rowB1 = h2 * 4u;
 #pragma unroll
     for (int pz = 0; pz < 2; pz++)
 #pragma unroll
       for (int u = 0; u < kRP; u++) {
         const uint32_t yy = min(wave + (uint32_t)u * kWaves, gy - 1);
-        tv[pz][u] = ldf(g1b, (uint32_t)pz * planeB + yy * rowB1 + xl * 4u);
-      }
-#pragma unroll
-    for (int pz = 0; pz < 2; pz++)
-#pragma unroll
-      for (int u = 0; u < kRP; u++) {
-        const uint32_t yy = min(wave + (uint32_t)u * kWaves, gy - 1);
-        sg[pz * TD::Plane + yy * TD::Side + xl] = tv[pz][u];
+        tv[pz][u] = ldf(g1b, (uint32_t)pz * planeB + yy * rowB1 + pxl * 4u);
       }
   }
   float iso[KB];
@@ -869,6 +865,13 @@ __device__ __forceinline__ void encode_tile(const EncPlan &P) {
       xd[k] = ldf(xbase, xo0 + min(2 * m + 1, my - 1) * rowB + lx);
     }
   }
+#pragma unroll
+  for (int pz = 0; pz < 2; pz++)
+#pragma unroll
+    for (int u = 0; u < kRP; u++) {
+      const uint32_t yy = min(wave + (uint32_t)u * kWaves, gy - 1);
+      sg[pz * TD::Plane + yy * TD::Side + pxl] = tv[pz][u];
+    }
   __syncthreads();
 
   if (GW) {
