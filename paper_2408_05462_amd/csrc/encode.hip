@@ -1454,6 +1454,8 @@ __global__ __launch_bounds__(kBS) void k_sec_table(EncPlan P) {
 // workgroup per (level, block, tile); levels are laid out from the coarsest
 // (first workgroups) to level 0.  A section that does not fit the capacity is
 // not written (the result then reports the required size).
+constexpr int kPackUnroll = 8;
+
 __global__ __launch_bounds__(kBS) void k_pack(EncPlan P) {
   // source of each payload word of the tile: its chunk (within the tile)
   // times 16 plus its place in the chunk's slot
@@ -1526,7 +1528,16 @@ __global__ __launch_bounds__(kBS) void k_pack(EncPlan P) {
   const unsigned long long *__restrict__ pay = reinterpret_cast<const unsigned long long *>(P.pay);
   unsigned long long *__restrict__ dst = reinterpret_cast<unsigned long long *>(out + Poff) + base0;
   const unsigned long long *__restrict__ pays = pay + slot0 * 16;
-  for (uint32_t u = (uint32_t)lane; u < tot; u += kWave) dst[u] = pays[s_src[u]];
+  // (kPackUnroll words per lane in flight: every lane loads a clamped index
+  // and only the words inside the tile are stored)
+  for (uint32_t u0 = (uint32_t)lane; u0 < tot; u0 += kPackUnroll * kWave) {
+    unsigned long long v[kPackUnroll];
+#pragma unroll
+    for (int j = 0; j < kPackUnroll; j++) v[j] = pays[s_src[min(u0 + (uint32_t)j * kWave, tot - 1)]];
+#pragma unroll
+    for (int j = 0; j < kPackUnroll; j++)
+      if (u0 + (uint32_t)j * kWave < tot) dst[u0 + (uint32_t)j * kWave] = v[j];
+  }
   // exact values of the chunks that have any, one chunk at a time
   const uint32_t *__restrict__ exv = reinterpret_cast<const uint32_t *>(P.exv);
   uint32_t *xo = reinterpret_cast<uint32_t *>(out + Xoff);
