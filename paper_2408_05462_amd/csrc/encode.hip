@@ -1589,9 +1589,18 @@ __device__ uint32_t range_sum(const EncPlan &P, uint64_t start, uint64_t end, ui
   const uint32_t per = (npair + kSumSegs - 1) / kSumSegs;
   const uint32_t lo = min(npair, seg * per), hi = min(npair, lo + per);
   const uint2 *__restrict__ src = reinterpret_cast<const uint2 *>(P.out + start);
-  for (uint32_t i = lo + threadIdx.x; i < hi; i += kBS) {
-    const uint2 v = src[i];
-    sum += fmix32(v.x ^ (2u * i) * 0x9E3779B9u) + fmix32(v.y ^ (2u * i + 1u) * 0x9E3779B9u);
+  // four words per thread in flight (clamped loads; the sum wraps, so the
+  // order of the terms does not change it)
+  for (uint32_t i0 = lo + threadIdx.x; i0 < hi; i0 += 4 * kBS) {
+    uint2 v[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) v[j] = src[min(i0 + (uint32_t)j * kBS, hi - 1)];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const uint32_t i = i0 + (uint32_t)j * kBS;
+      const uint32_t h = fmix32(v[j].x ^ (2u * i) * 0x9E3779B9u) + fmix32(v[j].y ^ (2u * i + 1u) * 0x9E3779B9u);
+      sum += i < hi ? h : 0u;
+    }
   }
   return block_sum<kBS>(sum);
 }

@@ -86,6 +86,27 @@ __device__ inline U4 rec(const uint32_t *in, int64_t k) {
   return U4{c & 0xffu, (c >> 8) & 0x1ffu, (c >> 17) & 0x7fu, (c >> 24) & 0x7fu};
 }
 
+// The lane's kIPT records of a wave's run (zeros past n; n >= 1 here), all
+// loads in flight together: each load is clamped and its record masked by
+// an opaque mask, as with a select the compiler moves every load into a
+// branch and waits for it there.
+template <class In>
+__device__ __forceinline__ void load_recs(const In *__restrict__ in, int64_t base, int lane, int64_t n,
+                                          U4 (&v)[kIPT]) {
+  uint32_t m[kIPT];
+#pragma unroll
+  for (int r = 0; r < kIPT; r++) {
+    m[r] = base + r * kWave + lane < n ? ~0u : 0u;
+    asm volatile("" : "+v"(m[r]));
+  }
+#pragma unroll
+  for (int r = 0; r < kIPT; r++) {
+    const int64_t k = base + r * kWave + lane;
+    const U4 x = rec(in, k < n ? k : n - 1);
+    v[r] = U4{x.x & m[r], x.y & m[r], x.z & m[r], x.w & m[r]};
+  }
+}
+
 // Tile totals of 4 x u32 records: eight loads a lane, a DPP sum per wave.
 template <class In>
 __global__ __launch_bounds__(kBS) void k_scan_reduce_u4(const In *__restrict__ in, U4 *__restrict__ part, int64_t n) {
@@ -93,11 +114,7 @@ __global__ __launch_bounds__(kBS) void k_scan_reduce_u4(const In *__restrict__ i
   const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)(threadIdx.x / kWave) * (kTile / (kBS / kWave));
   const int lane = (int)(threadIdx.x & (kWave - 1));
   U4 v[kIPT];
-#pragma unroll
-  for (int r = 0; r < kIPT; r++) {
-    const int64_t k = base + r * kWave + lane;
-    v[r] = k < n ? rec(in, k) : U4{0, 0, 0, 0};
-  }
+  load_recs(in, base, lane, n, v);
   U4 t = U4{0, 0, 0, 0};
 #pragma unroll
   for (int r = 0; r < kIPT; r++) t = add(t, v[r]);
@@ -129,11 +146,7 @@ __global__ __launch_bounds__(kBS) void k_scan_down_u4(const In *__restrict__ in,
   const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)wave * (kTile / (kBS / kWave));
   const int lane = (int)(threadIdx.x & (kWave - 1));
   U4 v[kIPT];
-#pragma unroll
-  for (int r = 0; r < kIPT; r++) {
-    const int64_t k = base + r * kWave + lane;
-    v[r] = k < n ? rec(in, k) : U4{0, 0, 0, 0};
-  }
+  load_recs(in, base, lane, n, v);
   U4 carry = U4{0, 0, 0, 0};
 #pragma unroll
   for (int r = 0; r < kIPT; r++) {
@@ -144,7 +157,15 @@ __global__ __launch_bounds__(kBS) void k_scan_down_u4(const In *__restrict__ in,
   U4 pre;
   if (FROM_TOTALS) {
     U4 t = U4{0, 0, 0, 0};
-    for (uint32_t i = threadIdx.x; i < blockIdx.x; i += kBS) t = add(t, part[i]);
+    // four totals per thread in flight (clamped loads, masked adds)
+    for (uint32_t i0 = threadIdx.x; i0 < blockIdx.x; i0 += 4 * kBS) {
+      U4 q[4];
+#pragma unroll
+      for (int j = 0; j < 4; j++) q[j] = part[min(i0 + (uint32_t)j * kBS, blockIdx.x - 1)];
+#pragma unroll
+      for (int j = 0; j < 4; j++)
+        if (i0 + (uint32_t)j * kBS < blockIdx.x) t = add(t, q[j]);
+    }
     t = lane63(wave_incl(t));
     if (lane == 0) {
       lds[wave] = carry;
